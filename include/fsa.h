@@ -1,0 +1,178 @@
+/*
+ * fsa.h -- C ABI of the MI355X (gfx950) full-scale-approximation library.
+ *
+ * Method: Gyger, Furrer & Sigrist, "Iterative Methods for Full-Scale
+ * Gaussian Process Approximations for Large Spatial Data" (arXiv 2405.14492).
+ *
+ * The library computes, on one GPU, the negative log-likelihood of a
+ * zero-mean Gaussian process under the full-scale approximation (FSA)
+ *
+ *   Sigma~_dagger = Sigma_mn^T Sigma_m^{-1} Sigma_mn            (Section 2.1)
+ *                 + (Sigma - Sigma_mn^T Sigma_m^{-1} Sigma_mn) o T(gamma)
+ *                 + sigma^2 I,
+ *
+ * its gradient in (sigma1^2, rho, sigma^2) (eq. NEGLLDNEGLLFSA), and the
+ * FSA predictive variances (eq. MuPredFSA), all by preconditioned conjugate
+ * gradients with the FITC preconditioner P = D_s + Sigma_mn^T Sigma_m^{-1}
+ * Sigma_mn (eq. eqfitcp) applied through the Woodbury identity (App. F),
+ * stochastic Lanczos quadrature for log det (Section 3.3), stochastic trace
+ * estimation for the gradient (Section 3.3) and the simulation-based
+ * variance estimator of Algorithm 1 (Section 3.2).
+ *
+ * Conventions for every entry point:
+ *  - Every function returns fsa_status; no C++ exception crosses the ABI.
+ *    On failure fsa_last_error() returns a message (thread-local).
+ *  - Host pointers are read during the call only; the library keeps no
+ *    caller pointer after returning.  Outputs go to caller buffers.
+ *  - Locations are row-major n x d float64 arrays with d == 2.
+ *  - A context is used by one host thread at a time.  Distinct contexts may
+ *    run concurrently on distinct streams.
+ *  - Device-pointer variants (suffix _dev) take device buffers that must stay
+ *    valid for the duration of the call only.
+ */
+#ifndef FSA_H
+#define FSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsa_ctx fsa_ctx; /* opaque; owned by the library until fsa_destroy */
+
+typedef enum {
+  FSA_OK = 0,
+  FSA_ERR_INVALID_ARG = 1, /* bad size, non-finite input, parameter out of range */
+  FSA_ERR_OOM = 2,         /* device allocation failed */
+  FSA_ERR_NOT_SPD = 3,     /* Cholesky of Sigma_m or of the FITC capacitance failed */
+  FSA_ERR_NOT_CONVERGED = 4, /* max_iter reached; outputs are still written */
+  FSA_ERR_BREAKDOWN = 5,   /* CG breakdown: h^T Sigma~ h <= 0 or non-finite */
+  FSA_ERR_DEVICE = 6       /* HIP runtime error */
+} fsa_status;
+
+/* Covariance function c(s_i, s_j) (Section 2), d = Euclidean distance:
+ *   EXPONENTIAL: sigma1^2 exp(-d / rho)                      (Matérn 1/2)
+ *   MATERN32:    sigma1^2 (1 + sqrt3 d/rho) exp(-sqrt3 d/rho) (Matérn 3/2) */
+typedef enum { FSA_COV_EXPONENTIAL = 0, FSA_COV_MATERN32 = 1 } fsa_cov;
+
+/* Arithmetic of the PCG loop.
+ *   FP64: everything in float64.
+ *   MIXED_FP32: covariance blocks, sparse values, low-rank factor and the
+ *     PCG block vectors in float32; Cholesky factors, inner products, the
+ *     CG coefficients, the solution accumulator and the tridiagonal
+ *     eigensolve in float64; the residual is recomputed with the float64
+ *     operator every rr_period iterations. */
+typedef enum { FSA_FP64 = 0, FSA_MIXED_FP32 = 1 } fsa_precision;
+
+typedef struct {
+  int32_t cov;      /* fsa_cov */
+  double sigma1_sq; /* marginal variance sigma1^2 > 0 */
+  double rho;       /* range rho > 0 */
+  double sigma_sq;  /* nugget sigma^2 > 0 (Theorems 1-2 assume it) */
+} fsa_theta;
+
+typedef struct {
+  int32_t num_probes;    /* number of probe vectors ell >= 1 (Section 3.1) */
+  uint64_t seed;         /* key of the counter-based Rademacher generator */
+  double cg_rel_tol;     /* per column ||r||_2 / ||b||_2 < tol stops the column */
+  int32_t max_iter;      /* iteration cap; reaching it gives FSA_ERR_NOT_CONVERGED */
+  int32_t fixed_iter;    /* > 0: every column runs exactly this many iterations */
+  int32_t precision;     /* fsa_precision */
+  int32_t rr_period;     /* mixed precision: float64 residual replacement period (0 = never) */
+  int32_t slq_weight_n;  /* 0: SLQ weight z^T P^{-1} z; 1: the weight n of Section 3.1 */
+  double sigma_m_jitter; /* adds jitter * sigma1^2 to the diagonal of Sigma_m (default 0) */
+  void* hip_stream;      /* hipStream_t to run on, or NULL for the default stream */
+} fsa_options;
+
+typedef struct {
+  int32_t iters_min, iters_max; /* PCG iterations over the right-hand-side columns */
+  int64_t probe_iters;          /* sum over columns of iterations executed */
+  double rel_res_max;           /* largest final relative residual */
+  double logdet;                /* SLQ estimate of log det Sigma~_dagger */
+  double logdet_P;              /* log det of the FITC preconditioner (Sylvester) */
+  double quad;                  /* y^T Sigma~_dagger^{-1} y */
+  double ms_build, ms_pcg, ms_backward, ms_total;
+  int64_t nnz;                  /* nonzeros of the tapered residual */
+} fsa_stats;
+
+/* Default options: 50 probes, seed 0, tol 1e-8, max_iter 1000, FP64. */
+void fsa_default_options(fsa_options* opt);
+
+/* Build a context: taper pattern by uniform-grid neighbour search (Section
+ * 2.1: T(gamma) is zero for d >= gamma; a pair is kept iff
+ * dx*dx + dy*dy < gamma*gamma in float64), Sigma_m and its Cholesky factor,
+ * the whitened low-rank factor L_m^{-1} Sigma_mn, the residual values, D_s,
+ * and the FITC capacitance with its Cholesky factor (App. F).
+ *   locs      host, n x d row-major; n >= 2 (Assumption 1)
+ *   y         host, n responses (zero mean assumed: no fixed effects)
+ *   theta     covariance parameters
+ *   inducing  host, m x d row-major; 1 <= m <= min(n, 1024), distinct
+ *   taper_range gamma > 0
+ *   opt       options (copied); NULL = defaults
+ *   out       receives the new context
+ * Errors: INVALID_ARG, OOM, NOT_SPD (Sigma_m or capacitance), DEVICE. */
+fsa_status fsa_build(const double* locs, int64_t n, int32_t d, const double* y, const fsa_theta* theta,
+                     const double* inducing, int32_t m, double taper_range, const fsa_options* opt,
+                     fsa_ctx** out);
+/* Same with device-resident locs, y and inducing (pointers as above, but on
+ * the GPU the context will run on). */
+fsa_status fsa_build_dev(const double* locs_dev, int64_t n, int32_t d, const double* y_dev,
+                         const fsa_theta* theta, const double* inducing_dev, int32_t m, double taper_range,
+                         const fsa_options* opt, fsa_ctx** out);
+
+/* Negative log-likelihood (eq. NEGLLDNEGLLFSA) by preconditioned SLQ and,
+ * if grad != NULL, its gradient by stochastic trace estimation with
+ * z ~ (0, P) (Section 3.3).
+ *   theta  NULL = the parameters of the build; else the context is revalued
+ *          on the same taper pattern with these parameters (gamma fixed)
+ *   nll    host scalar out
+ *   grad   host [3] out, order (sigma1^2, rho, sigma^2), or NULL
+ *   st     optional statistics out
+ * Errors: INVALID_ARG, NOT_SPD, BREAKDOWN, NOT_CONVERGED (outputs written),
+ * DEVICE. */
+fsa_status fsa_nll_grad(fsa_ctx* ctx, const fsa_theta* theta, double* nll, double* grad, fsa_stats* st);
+
+/* Predictive variances diag(Sigma^p_dagger) (eq. MuPredFSA, nugget
+ * included) by Algorithm 1 with num_samples Rademacher vectors; Sigma~_s
+ * solves by CG preconditioned with D_s (Section 3.3).  If mean_out is not
+ * NULL, also the predictive mean Sigma^dagger_{n n_p}^T Sigma~^{-1} y
+ * (Section 2.3), which needs a preceding fsa_nll_grad on this context.
+ *   pred_locs host, n_p x d row-major; n_p >= 1
+ *   var_out   host, n_p out; mean_out host, n_p out or NULL
+ * Errors: INVALID_ARG, NOT_SPD, BREAKDOWN, NOT_CONVERGED, DEVICE. */
+fsa_status fsa_predict_var(fsa_ctx* ctx, const double* pred_locs, int64_t n_p, int32_t num_samples,
+                           double* var_out, double* mean_out, fsa_stats* st);
+
+void fsa_destroy(fsa_ctx* ctx);
+const char* fsa_last_error(void);
+
+/* ---- inspection hooks (tests) ---- */
+int64_t fsa_nnz(const fsa_ctx* ctx);
+/* Taper pattern in the caller's point order: row_ptr host int64 (n+1),
+ * col_idx host int32 (nnz), columns ascending per row; vals host float64
+ * (nnz) or NULL gives the values of Sigma~_s. */
+fsa_status fsa_export_csr(fsa_ctx* ctx, int64_t* row_ptr, int32_t* col_idx, double* vals);
+/* D_s (host, n) and log det P. */
+fsa_status fsa_export_diag(fsa_ctx* ctx, double* D, double* logdet_P);
+
+enum {
+  FSA_OP_SIGMA_DAGGER = 0, /* Sigma~_dagger X */
+  FSA_OP_SIGMA_S = 1,      /* Sigma~_s X */
+  FSA_OP_P_INV = 2,        /* P^{-1} X (Woodbury, App. F) */
+  FSA_OP_D_SIGMA1 = 3,     /* dSigma~_dagger / dsigma1^2 X */
+  FSA_OP_D_RHO = 4,        /* dSigma~_dagger / drho X */
+  FSA_OP_PROBES = 5        /* ignores X; Y = the probe block z_1..z_ncols */
+};
+/* Apply an operator in float64 to ncols columns: X, Y host, n x ncols
+ * row-major, in the caller's point order. */
+fsa_status fsa_apply(fsa_ctx* ctx, int32_t which, const double* X, double* Y, int32_t ncols);
+
+/* Release every cached device block of the process-wide pool. */
+void fsa_pool_trim(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSA_H */

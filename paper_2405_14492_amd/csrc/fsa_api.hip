@@ -1,0 +1,768 @@
+// C ABI of the FSA library: context lifetime, build and revaluation, the
+// PCG/SLQ likelihood with its stochastic gradient, predictive variances and
+// inspection hooks.  All arithmetic runs in the kernels of geom/dense/ops;
+// this file orders launches and moves scalars.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "ops.hpp"
+
+namespace fsa {
+
+// ---------------------------------------------------------------- errors
+static thread_local char g_err[1024] = "";
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+const char* get_error() { return g_err; }
+
+// ---------------------------------------------------------------- pool
+namespace {
+std::mutex g_pool_mu;
+std::multimap<size_t, void*> g_free;   // rounded size -> block
+std::map<void*, size_t> g_live;        // block -> rounded size
+size_t pool_round(size_t b) {
+  const size_t g = b < (1u << 20) ? 4096 : (size_t(2) << 20);
+  return (b + g - 1) / g * g;
+}
+}  // namespace
+
+void* pool_alloc(size_t bytes) {
+  size_t r = pool_round(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_free.find(r);
+    if (it != g_free.end()) {
+      void* p = it->second;
+      g_free.erase(it);
+      g_live[p] = r;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, r) != hipSuccess) {
+    (void)hipGetLastError();
+    // release cached blocks and retry once
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (auto& kv : g_free) (void)hipFree(kv.second);
+    g_free.clear();
+    if (hipMalloc(&p, r) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_live[p] = r;
+  return p;
+}
+
+void pool_free(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) return;
+  g_free.emplace(it->second, p);
+  g_live.erase(it);
+}
+
+void pool_trim() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (auto& kv : g_free) (void)hipFree(kv.second);
+  g_free.clear();
+}
+
+// ---------------------------------------------------------------- small kernels
+__global__ __launch_bounds__(1024) void k_sum_log(const double* __restrict__ D, int64_t n, double* out, int* bad) {
+  __shared__ double s[1024];
+  double a = 0.0;
+  int b = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = D[i];
+    if (!(v > 0.0) || !isfinite(v)) b = 1;
+    a += log(v);
+  }
+  s[threadIdx.x] = a;
+  if (b) atomicOr(bad, 1);
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+__global__ void k_count_bad(const double* __restrict__ v, int64_t cnt, int* bad) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < cnt && !isfinite(v[i])) atomicOr(bad, 1);
+}
+
+__global__ void k_pad_inducing(const double* __restrict__ in, int m, int mp, double* __restrict__ out) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= mp) return;
+  out[2 * k] = k < m ? in[2 * k] : 0.0;
+  out[2 * k + 1] = k < m ? in[2 * k + 1] : 0.0;
+}
+
+// results[0] = log det, [1] = quad, [2] = nll
+__global__ void k_finalize_nll(const double* __restrict__ slq, int ncols, const double* __restrict__ logdet_parts,
+                               const double* __restrict__ quad, int64_t n, double* out) {
+  double s = 0.0;
+  for (int c = 1; c < ncols; ++c) s += slq[c];
+  double logdet = s / (double)(ncols - 1) + logdet_parts[0] + logdet_parts[1];
+  out[0] = logdet;
+  out[1] = quad[0];
+  out[2] = 0.5 * (double)n * 1.8378770664093453 + 0.5 * logdet + 0.5 * quad[0];
+}
+
+// grad from column dots: uSX = U.(Sigma X), uX = U.X, uDX = U.(dSigma/drho X)
+__global__ void k_finalize_grad(int ncols, const double* __restrict__ uSX, const double* __restrict__ uX,
+                                const double* __restrict__ uDX, double s1, double s2, double* out) {
+  double tr[3] = {0, 0, 0};
+  for (int c = 1; c < ncols; ++c) {
+    tr[0] += (uSX[c] - s2 * uX[c]) / s1;
+    tr[1] += uDX[c];
+    tr[2] += uX[c];
+  }
+  double t = (double)(ncols - 1);
+  double qd[3] = {(uSX[0] - s2 * uX[0]) / s1, uDX[0], uX[0]};
+  for (int k = 0; k < 3; ++k) {
+    out[k] = 0.5 * tr[k] / t - 0.5 * qd[k];
+    out[3 + k] = tr[k] / t;
+    out[6 + k] = qd[k];
+  }
+}
+
+__global__ void k_grad_block(int64_t n, int ncols, int64_t ld, const double* __restrict__ U, const void* Q0, int q0_f32,
+                             double* __restrict__ X) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / ncols;
+  int c = (int)(e % ncols);
+  if (p >= n) return;
+  int64_t o = p * ld + c;
+  if (c == 0) X[o] = U[o];
+  else X[o] = q0_f32 ? (double)((const float*)Q0)[o] : ((const double*)Q0)[o];
+}
+
+__global__ void k_fill_weight_n(double* w, int ncols, double n) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncols) w[c] = n;
+}
+
+}  // namespace fsa
+
+using namespace fsa;
+
+struct fsa_ctx {
+  int64_t n = 0;
+  int m = 0, mp = 0;
+  int t = 0, tp = 0, ld = 0, ldw = 0;
+  Theta th{};
+  double gamma = 0;
+  fsa_options opt{};
+  hipStream_t st = nullptr;
+  Grid grid;
+  Csr csr;
+  Buf<double> ind, y;
+  Buf<double> Sm, Lm, Lminv, LminvT, C, LCinv, Cinv;
+  Buf<double> A, vals, D;
+  Buf<float> Af, valsf;
+  Buf<double> logdet_parts;  // [0] = 2 sum log diag L_C, [1] = sum log D
+  Buf<int> info;
+  // PCG / SLQ
+  Buf<double> B, U, Emat;
+  Buf<char> blockmem;
+  Buf<double> colbuf;   // per-column scalars
+  Buf<int> colint;
+  Buf<double> hist;
+  Buf<double> slq_scratch, results;
+  // gradient
+  Buf<double> F, dvals, Xb, SX, DX, tmp, G2, dSm, Ework;
+  Scratch scr;
+  bool solved = false;
+  double last_logdet_P = 0;
+  // last statistics
+  fsa_stats stats{};
+};
+
+static hipStream_t as_stream(void* p) { return reinterpret_cast<hipStream_t>(p); }
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static fsa_status check_theta(const fsa_theta* th) {
+  if (!th) return FSA_OK;
+  if (th->cov != FSA_COV_EXPONENTIAL && th->cov != FSA_COV_MATERN32) {
+    set_error("unknown covariance %d", th->cov);
+    return FSA_ERR_INVALID_ARG;
+  }
+  if (!(th->sigma1_sq > 0) || !(th->rho > 0) || !(th->sigma_sq > 0) || !std::isfinite(th->sigma1_sq) ||
+      !std::isfinite(th->rho) || !std::isfinite(th->sigma_sq)) {
+    set_error("covariance parameters must be finite and > 0");
+    return FSA_ERR_INVALID_ARG;
+  }
+  return FSA_OK;
+}
+
+// Sigma_m, L_m, whitened factor, residual values, D_s, FITC capacitance.
+static fsa_status build_values(fsa_ctx* c) {
+  hipStream_t st = c->st;
+  const int mp = c->mp;
+  FSA_TRY(dense_sigma_m(c->ind.p, c->m, mp, c->th, c->opt.sigma_m_jitter, false, c->Sm.p, st));
+  FSA_HIP(hipMemcpyAsync(c->Lm.p, c->Sm.p, (size_t)mp * mp * sizeof(double), hipMemcpyDeviceToDevice, st));
+  FSA_TRY(dense_cholesky(c->Lm.p, mp, c->info.p, st));
+  int info = 0;
+  FSA_HIP(hipMemcpyAsync(&info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (info) {
+    set_error("Cholesky of Sigma_m failed at column %d (duplicate inducing points?)", info - 1);
+    return FSA_ERR_NOT_SPD;
+  }
+  FSA_TRY(dense_tri_inverse(c->Lm.p, c->Lminv.p, mp, st));
+  FSA_TRY(transpose_scale(c->Lminv.p, c->LminvT.p, mp, 1.0, st));
+  FSA_TRY(whiten(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->LminvT.p, 0, c->A.p, st));
+  FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, true, false,
+                          c->vals.p, c->D.p, st));
+  FSA_TRY(capacitance(c->A.p, c->D.p, c->n, mp, c->C.p, c->scr, st));
+  // C -> L_C (in place), L_C^{-1}, C^{-1} = L_C^{-T} L_C^{-1}
+  FSA_TRY(dense_cholesky(c->C.p, mp, c->info.p, st));
+  FSA_HIP(hipMemcpyAsync(&info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipMemsetAsync(c->info.p + 1, 0, sizeof(int), st));
+  FSA_TRY(dense_logdet_chol(c->C.p, mp, c->logdet_parts.p, st));
+  hipLaunchKernelGGL(k_sum_log, dim3(1), dim3(1024), 0, st, c->D.p, c->n, c->logdet_parts.p + 1, c->info.p + 1);
+  FSA_TRY(dense_tri_inverse(c->C.p, c->LCinv.p, mp, st));
+  FSA_TRY(dense_gemm(c->LCinv.p, true, c->LCinv.p, false, c->Cinv.p, mp, 1.0, st));
+  int bad = 0;
+  FSA_HIP(hipMemcpyAsync(&bad, c->info.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  double ld2[2];
+  FSA_HIP(hipMemcpyAsync(ld2, c->logdet_parts.p, sizeof(ld2), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (info) {
+    set_error("Cholesky of the FITC capacitance failed at column %d", info - 1);
+    return FSA_ERR_NOT_SPD;
+  }
+  if (bad) {
+    set_error("residual diagonal D_s has a non-positive or non-finite entry");
+    return FSA_ERR_NOT_SPD;
+  }
+  c->last_logdet_P = ld2[0] + ld2[1];
+  if (c->opt.precision == FSA_MIXED_FP32) {
+    FSA_TRY(to_float(c->A.p, c->Af.p, c->n * (int64_t)mp, st));
+    FSA_TRY(to_float(c->vals.p, c->valsf.p, c->csr.nnz, st));
+  }
+  c->solved = false;
+  return FSA_OK;
+}
+
+static fsa_status build_core(fsa_ctx* c, const double* locs, const double* y, const double* inducing) {
+  hipStream_t st = c->st;
+  const int64_t n = c->n;
+  const int mp = c->mp;
+  // input checks on the device
+  FSA_TRY(c->info.alloc(4));
+  FSA_HIP(hipMemsetAsync(c->info.p, 0, 4 * sizeof(int), st));
+  hipLaunchKernelGGL(k_count_bad, dim3(ceil_div(2 * n, 256)), dim3(256), 0, st, locs, 2 * n, c->info.p + 2);
+  hipLaunchKernelGGL(k_count_bad, dim3(ceil_div(n, 256)), dim3(256), 0, st, y, n, c->info.p + 2);
+  hipLaunchKernelGGL(k_count_bad, dim3(ceil_div(2 * c->m, 256)), dim3(256), 0, st, inducing, (int64_t)2 * c->m,
+                     c->info.p + 2);
+  int bad = 0;
+  FSA_HIP(hipMemcpyAsync(&bad, c->info.p + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (bad) {
+    set_error("non-finite value in locations, responses or inducing points");
+    return FSA_ERR_INVALID_ARG;
+  }
+  FSA_TRY(build_grid(c->grid, locs, n, c->gamma, st, nullptr, nullptr));
+  FSA_TRY(build_pattern(c->grid, c->grid, c->csr, st));
+  FSA_TRY(c->y.alloc(n));
+  FSA_TRY(permute_rows(y, 1, c->y.p, 1, c->grid.perm.p, n, 1, st));
+  FSA_TRY(c->ind.alloc(2 * (size_t)mp));
+  hipLaunchKernelGGL(k_pad_inducing, dim3(ceil_div(mp, 256)), dim3(256), 0, st, inducing, c->m, mp, c->ind.p);
+  size_t mm = (size_t)mp * mp;
+  FSA_TRY(c->Sm.alloc(mm));
+  FSA_TRY(c->Lm.alloc(mm));
+  FSA_TRY(c->Lminv.alloc(mm));
+  FSA_TRY(c->LminvT.alloc(mm));
+  FSA_TRY(c->C.alloc(mm));
+  FSA_TRY(c->LCinv.alloc(mm));
+  FSA_TRY(c->Cinv.alloc(mm));
+  FSA_TRY(c->A.alloc((size_t)n * mp));
+  FSA_TRY(c->vals.alloc(c->csr.nnz));
+  FSA_TRY(c->D.alloc(n));
+  FSA_TRY(c->logdet_parts.alloc(2));
+  if (c->opt.precision == FSA_MIXED_FP32) {
+    FSA_TRY(c->Af.alloc((size_t)n * mp));
+    FSA_TRY(c->valsf.alloc(c->csr.nnz));
+  }
+  return build_values(c);
+}
+
+static fsa_status validate_build(int64_t n, int32_t d, const fsa_theta* theta, int32_t m, double gamma,
+                                 const fsa_options* opt) {
+  if (n < 2) { set_error("n must be >= 2 (got %lld)", (long long)n); return FSA_ERR_INVALID_ARG; }
+  if (n > (int64_t)INT32_MAX / 2) { set_error("n too large"); return FSA_ERR_INVALID_ARG; }
+  if (d != 2) { set_error("only d == 2 is supported (got %d)", d); return FSA_ERR_INVALID_ARG; }
+  if (!theta) { set_error("theta is required"); return FSA_ERR_INVALID_ARG; }
+  FSA_TRY(check_theta(theta));
+  if (m < 1 || m > n || m > 512) { set_error("need 1 <= m <= min(n, 512) (got m=%d)", m); return FSA_ERR_INVALID_ARG; }
+  if (!(gamma > 0) || !std::isfinite(gamma)) { set_error("taper range must be finite and > 0"); return FSA_ERR_INVALID_ARG; }
+  if (opt) {
+    if (opt->num_probes < 1 || opt->num_probes > 4096) { set_error("num_probes must be in [1, 4096]"); return FSA_ERR_INVALID_ARG; }
+    if (opt->max_iter < 1 && opt->fixed_iter < 1) { set_error("max_iter must be >= 1"); return FSA_ERR_INVALID_ARG; }
+    if (!(opt->cg_rel_tol >= 0)) { set_error("cg_rel_tol must be >= 0"); return FSA_ERR_INVALID_ARG; }
+    if (opt->precision != FSA_FP64 && opt->precision != FSA_MIXED_FP32) { set_error("unknown precision"); return FSA_ERR_INVALID_ARG; }
+    if (!(opt->sigma_m_jitter >= 0)) { set_error("sigma_m_jitter must be >= 0"); return FSA_ERR_INVALID_ARG; }
+  }
+  return FSA_OK;
+}
+
+static fsa_status new_ctx(int64_t n, int32_t m, const fsa_theta* theta, double gamma, const fsa_options* opt,
+                          fsa_ctx** out) {
+  fsa_ctx* c = new fsa_ctx();
+  c->n = n;
+  c->m = m;
+  c->mp = (int)round_up(m, 64);
+  if (opt) c->opt = *opt;
+  else fsa_default_options(&c->opt);
+  if (c->opt.max_iter < 1) c->opt.max_iter = c->opt.fixed_iter;
+  c->t = c->opt.num_probes;
+  c->tp = c->t + 1;
+  c->ld = (int)round_up(c->tp, 4);
+  c->ldw = (int)round_up(c->tp, 64);
+  c->th = Theta{theta->cov, theta->sigma1_sq, theta->rho, theta->sigma_sq};
+  c->gamma = gamma;
+  c->st = as_stream(c->opt.hip_stream);
+  *out = c;
+  return FSA_OK;
+}
+
+extern "C" {
+
+void fsa_default_options(fsa_options* o) {
+  memset(o, 0, sizeof(*o));
+  o->num_probes = 50;
+  o->seed = 0;
+  o->cg_rel_tol = 1e-8;
+  o->max_iter = 1000;
+  o->fixed_iter = 0;
+  o->precision = FSA_FP64;
+  o->rr_period = 10;
+  o->slq_weight_n = 0;
+  o->sigma_m_jitter = 0.0;
+  o->hip_stream = nullptr;
+}
+
+const char* fsa_last_error(void) { return get_error(); }
+
+void fsa_pool_trim(void) { pool_trim(); }
+
+fsa_status fsa_build_dev(const double* locs, int64_t n, int32_t d, const double* y, const fsa_theta* theta,
+                         const double* inducing, int32_t m, double gamma, const fsa_options* opt, fsa_ctx** out) {
+  if (!out || !locs || !y || !inducing) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  *out = nullptr;
+  FSA_TRY(validate_build(n, d, theta, m, gamma, opt));
+  fsa_ctx* c = nullptr;
+  FSA_TRY(new_ctx(n, m, theta, gamma, opt, &c));
+  fsa_status s = build_core(c, locs, y, inducing);
+  if (s != FSA_OK) {
+    fsa_destroy(c);
+    return s;
+  }
+  *out = c;
+  return FSA_OK;
+}
+
+fsa_status fsa_build(const double* locs, int64_t n, int32_t d, const double* y, const fsa_theta* theta,
+                     const double* inducing, int32_t m, double gamma, const fsa_options* opt, fsa_ctx** out) {
+  if (!out || !locs || !y || !inducing) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  *out = nullptr;
+  FSA_TRY(validate_build(n, d, theta, m, gamma, opt));
+  hipStream_t st = opt ? as_stream(opt->hip_stream) : nullptr;
+  Buf<double> dl, dy, di;
+  FSA_TRY(dl.alloc(2 * (size_t)n));
+  FSA_TRY(dy.alloc(n));
+  FSA_TRY(di.alloc(2 * (size_t)m));
+  FSA_HIP(hipMemcpyAsync(dl.p, locs, 2 * n * sizeof(double), hipMemcpyHostToDevice, st));
+  FSA_HIP(hipMemcpyAsync(dy.p, y, n * sizeof(double), hipMemcpyHostToDevice, st));
+  FSA_HIP(hipMemcpyAsync(di.p, inducing, 2 * (size_t)m * sizeof(double), hipMemcpyHostToDevice, st));
+  fsa_status s = fsa_build_dev(dl.p, n, d, dy.p, theta, di.p, m, gamma, opt, out);
+  (void)hipStreamSynchronize(st);
+  return s;
+}
+
+void fsa_destroy(fsa_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  delete c;  // Buf members return their blocks to the pool
+}
+
+int64_t fsa_nnz(const fsa_ctx* c) { return c ? c->csr.nnz : -1; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- PCG driver
+template <typename T>
+static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
+  hipStream_t st = c->st;
+  const int64_t n = c->n;
+  const int tp = c->tp, ld = c->ld, ldw = c->ldw, mp = c->mp;
+  const int max_iter = c->opt.fixed_iter > 0 ? c->opt.fixed_iter : c->opt.max_iter;
+  size_t blk = (size_t)n * ld;
+  FSA_TRY(c->blockmem.alloc(6 * blk * sizeof(T)));
+  T* base = reinterpret_cast<T*>(c->blockmem.p);
+  PcgBlock<T> b;
+  b.n = n;
+  b.ncols = tp;
+  b.ld = ld;
+  b.ldw = ldw;
+  b.max_iter = max_iter;
+  b.R = base;
+  b.H = base + blk;
+  b.V = base + 2 * blk;
+  b.P = base + 3 * blk;
+  b.Tt = base + 4 * blk;
+  b.Q0 = base + 5 * blk;
+  FSA_TRY(c->U.alloc(blk));
+  b.U = c->U.p;
+  FSA_TRY(c->colbuf.alloc(8 * (size_t)ldw));
+  b.rz = c->colbuf.p;
+  b.rz0 = b.rz + ldw;
+  b.alpha = b.rz + 2 * ldw;
+  b.beta = b.rz + 3 * ldw;
+  b.rr = b.rz + 4 * ldw;
+  b.bn2 = b.rz + 5 * ldw;
+  FSA_TRY(c->colint.alloc(2 * (size_t)ldw + 4));
+  b.active = c->colint.p;
+  b.iters = c->colint.p + ldw;
+  b.flags = c->colint.p + 2 * ldw;
+  FSA_TRY(c->hist.alloc(2 * (size_t)max_iter * tp));
+  b.alpha_hist = c->hist.p;
+  b.beta_hist = c->hist.p + (size_t)max_iter * tp;
+  FSA_TRY(c->scr.w.alloc((size_t)mp * ldw * 2));
+  Buf<T> gbuf;
+  FSA_TRY(gbuf.alloc((size_t)mp * ldw));
+  b.g = gbuf.p;
+  OpDesc<T> op;
+  op.S = &c->csr;
+  op.D = c->D.p;
+  op.kdim = mp;
+  op.Cinv = c->Cinv.p;
+  OpDesc<double> op64;
+  op64.S = &c->csr;
+  op64.val = c->vals.p;
+  op64.D = c->D.p;
+  op64.A = c->A.p;
+  op64.kdim = mp;
+  op64.Cinv = c->Cinv.p;
+  if constexpr (sizeof(T) == 8) {
+    op.val = reinterpret_cast<const T*>(c->vals.p);
+    op.A = reinterpret_cast<const T*>(c->A.p);
+  } else {
+    op.val = reinterpret_cast<const T*>(c->valsf.p);
+    op.A = reinterpret_cast<const T*>(c->Af.p);
+  }
+  const double tol = c->opt.cg_rel_tol;
+  const int fixed = c->opt.fixed_iter > 0 ? 1 : 0;
+  double t0 = now_ms();
+  FSA_TRY(pcg_init<T>(b, op, c->B.p, tol, c->scr, st));
+  int flags[2] = {0, 0};
+  int it = 0;
+  const int check = 4;
+  for (it = 0; it < max_iter; ++it) {
+    FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
+    if constexpr (sizeof(T) == 4) {
+      if (c->opt.rr_period > 0 && (it + 1) % c->opt.rr_period == 0 && it + 1 < max_iter)
+        FSA_TRY(pcg_replace_residual_f32(reinterpret_cast<PcgBlock<float>&>(b), op64,
+                                         reinterpret_cast<const OpDesc<float>&>(op), c->B.p, c->scr, st));
+    }
+    if (!fixed && ((it + 1) % check == 0 || it + 1 == max_iter)) {
+      FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      FSA_HIP(hipStreamSynchronize(st));
+      if (flags[1]) break;
+      if (flags[0] == 0) {
+        ++it;
+        break;
+      }
+    }
+  }
+  FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  *ms_pcg = now_ms() - t0;
+  // iteration statistics
+  std::vector<int> iters(tp);
+  FSA_HIP(hipMemcpy(iters.data(), b.iters, tp * sizeof(int), hipMemcpyDeviceToHost));
+  int imin = 1 << 30, imax = 0;
+  int64_t tot = 0;
+  for (int k = 0; k < tp; ++k) {
+    imin = std::min(imin, iters[k]);
+    imax = std::max(imax, iters[k]);
+    tot += iters[k];
+  }
+  c->stats.iters_min = imin;
+  c->stats.iters_max = imax;
+  c->stats.probe_iters = tot;
+  if (flags[1]) {
+    set_error("CG breakdown (h^T Sigma h <= 0 or non-finite)");
+    return FSA_ERR_BREAKDOWN;
+  }
+  // SLQ terms for probe columns
+  FSA_TRY(c->slq_scratch.alloc((size_t)tp * 3 * max_iter));
+  FSA_TRY(c->results.alloc(4 * (size_t)ldw + 16));
+  double* slq = c->results.p;
+  double* quad = c->results.p + ldw;
+  double* fin = c->results.p + 2 * ldw;
+  const double* weight = b.rz0;
+  if (c->opt.slq_weight_n) {
+    hipLaunchKernelGGL(k_fill_weight_n, dim3(ceil_div(tp, 64)), dim3(64), 0, st, b.rr, tp, (double)n);
+    weight = b.rr;
+  }
+  FSA_TRY(slq_terms(b.alpha_hist, b.beta_hist, b.iters, tp, 1, weight, slq, c->slq_scratch.p, max_iter, st));
+  FSA_TRY((coldot<double, double>(c->B.p, c->U.p, n, ld, 1, quad, c->scr, st)));
+  hipLaunchKernelGGL(k_finalize_nll, dim3(1), dim3(1), 0, st, slq, tp, c->logdet_parts.p, quad, n, fin);
+  FSA_HIP(hipGetLastError());
+  // keep Q0 (P^{-1} z) for the gradient in float64
+  FSA_TRY(c->Xb.alloc(blk));
+  hipLaunchKernelGGL(k_grad_block, dim3(ceil_div((int64_t)n * tp, 256)), dim3(256), 0, st, n, tp, (int64_t)ld, c->U.p,
+                     (const void*)b.Q0, sizeof(T) == 4 ? 1 : 0, c->Xb.p);
+  FSA_HIP(hipGetLastError());
+  FSA_HIP(hipStreamSynchronize(st));
+  c->solved = true;
+  if (!fixed && flags[0] > 0) {
+    set_error("PCG did not converge in %d iterations (%d columns active)", max_iter, flags[0]);
+    return FSA_ERR_NOT_CONVERGED;
+  }
+  return FSA_OK;
+}
+
+// Y = Sigma~_dagger X (float64), X/Y n x ld blocks in sorted order.
+static fsa_status apply_sigma(fsa_ctx* c, const double* X, double* Y, int ncols, int ldx) {
+  hipStream_t st = c->st;
+  int ldw = (int)round_up(ncols, 64);
+  FSA_TRY(c->scr.w.alloc((size_t)c->mp * ldw * 2));
+  FSA_TRY(c->tmp.alloc((size_t)c->n * ldx));
+  FSA_TRY(spmm<double>(c->csr, c->vals.p, X, ldx, ncols, Y, ldx, false, st));
+  FSA_TRY(lowrank_reduce<double>(c->A.p, c->n, c->mp, X, ldx, ncols, nullptr, c->scr, c->scr.w.p, ldw, st));
+  FSA_TRY(lowrank_expand<double>(c->A.p, nullptr, c->n, c->mp, c->scr.w.p, ldw, ncols, c->tmp.p, ldx, st));
+  FSA_TRY(axpy_block(c->tmp.p, 1.0, Y, ldx, c->n, ncols, st));
+  return FSA_OK;
+}
+
+// F = dA - E A / 2 (whitened rho-derivative factor) and the derivative values.
+static fsa_status build_derivative(fsa_ctx* c) {
+  hipStream_t st = c->st;
+  const int mp = c->mp;
+  size_t mm = (size_t)mp * mp;
+  FSA_TRY(c->dSm.alloc(mm));
+  FSA_TRY(c->Ework.alloc(2 * mm));
+  FSA_TRY(c->G2.alloc(2 * mm));
+  FSA_TRY(dense_sigma_m(c->ind.p, c->m, mp, c->th, 0.0, true, c->dSm.p, st));
+  double* T1 = c->Ework.p;
+  double* E = c->Ework.p + mm;
+  FSA_TRY(dense_gemm(c->Lminv.p, false, c->dSm.p, false, T1, mp, 1.0, st));   // L^{-1} dSm
+  FSA_TRY(dense_gemm(T1, false, c->Lminv.p, true, E, mp, 1.0, st));           // E = L^{-1} dSm L^{-T}
+  FSA_TRY(dense_gemm(E, false, c->Lminv.p, false, T1, mp, 1.0, st));          // E L^{-1}
+  FSA_HIP(hipMemcpyAsync(c->G2.p, c->LminvT.p, mm * sizeof(double), hipMemcpyDeviceToDevice, st));
+  FSA_TRY(transpose_scale(T1, c->G2.p + mm, mp, -0.5, st));                 // -(E L^{-1})^T / 2
+  FSA_TRY(c->F.alloc((size_t)c->n * mp));
+  FSA_TRY(whiten(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->G2.p, 1, c->F.p, st));
+  FSA_TRY(c->dvals.alloc(c->csr.nnz));
+  FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, c->F.p, c->F.p, mp, c->th, c->gamma, true, true,
+                          c->dvals.p, nullptr, st));
+  return FSA_OK;
+}
+
+// Y = dSigma~/drho X = dS X + F^T (A X) + A^T (F X)
+static fsa_status apply_drho(fsa_ctx* c, const double* X, double* Y, int ncols, int ldx) {
+  hipStream_t st = c->st;
+  const int mp = c->mp;
+  int ldw = (int)round_up(ncols, 64);
+  FSA_TRY(c->scr.w.alloc((size_t)mp * ldw * 2));
+  FSA_TRY(c->tmp.alloc((size_t)c->n * ldx));
+  FSA_TRY(spmm<double>(c->csr, c->dvals.p, X, ldx, ncols, Y, ldx, false, st));
+  FSA_TRY(lowrank_reduce<double>(c->A.p, c->n, mp, X, ldx, ncols, nullptr, c->scr, c->scr.w.p, ldw, st));
+  FSA_TRY(lowrank_reduce<double>(c->F.p, c->n, mp, X, ldx, ncols, nullptr, c->scr, c->scr.w.p + (size_t)mp * ldw, ldw,
+                                 st));
+  FSA_TRY(lowrank_expand<double>(c->F.p, c->A.p, c->n, 2 * mp, c->scr.w.p, ldw, ncols, c->tmp.p, ldx, st));
+  FSA_TRY(axpy_block(c->tmp.p, 1.0, Y, ldx, c->n, ncols, st));
+  return FSA_OK;
+}
+
+static fsa_status run_gradient(fsa_ctx* c, double* grad) {
+  hipStream_t st = c->st;
+  const int64_t n = c->n;
+  const int tp = c->tp, ld = c->ld;
+  size_t blk = (size_t)n * ld;
+  FSA_TRY(build_derivative(c));
+  FSA_TRY(c->SX.alloc(blk));
+  FSA_TRY(c->DX.alloc(blk));
+  FSA_TRY(apply_sigma(c, c->Xb.p, c->SX.p, tp, ld));
+  FSA_TRY(apply_drho(c, c->Xb.p, c->DX.p, tp, ld));
+  double* dots = c->results.p + 3 * c->ldw;  // 3 x tp (fits: results has 4 ldw + 16)
+  Buf<double> dd;
+  FSA_TRY(dd.alloc(3 * (size_t)tp + 9));
+  FSA_TRY((coldot<double, double>(c->U.p, c->SX.p, n, ld, tp, dd.p, c->scr, st)));
+  FSA_TRY((coldot<double, double>(c->U.p, c->Xb.p, n, ld, tp, dd.p + tp, c->scr, st)));
+  FSA_TRY((coldot<double, double>(c->U.p, c->DX.p, n, ld, tp, dd.p + 2 * tp, c->scr, st)));
+  hipLaunchKernelGGL(k_finalize_grad, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, c->th.s1, c->th.s2,
+                     dd.p + 3 * tp);
+  FSA_HIP(hipGetLastError());
+  double g9[9];
+  FSA_HIP(hipMemcpyAsync(g9, dd.p + 3 * tp, sizeof(g9), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  (void)dots;
+  for (int k = 0; k < 3; ++k) grad[k] = g9[k];
+  return FSA_OK;
+}
+
+extern "C" {
+
+fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double* grad, fsa_stats* st_out) {
+  if (!c || !nll) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  double t0 = now_ms();
+  hipStream_t st = c->st;
+  memset(&c->stats, 0, sizeof(c->stats));
+  if (theta) {
+    FSA_TRY(check_theta(theta));
+    Theta nt{theta->cov, theta->sigma1_sq, theta->rho, theta->sigma_sq};
+    if (nt.kind != c->th.kind || nt.s1 != c->th.s1 || nt.rho != c->th.rho || nt.s2 != c->th.s2) {
+      c->th = nt;
+      FSA_TRY(build_values(c));
+    }
+  }
+  double t_build = now_ms();
+  // probe block [y, z_1 .. z_t]
+  FSA_TRY(c->B.alloc((size_t)c->n * c->ld));
+  FSA_TRY(c->Emat.alloc((size_t)c->mp * c->ldw));
+  FSA_TRY(make_probes(c->A.p, c->n, c->m, c->mp, c->D.p, c->y.p, c->grid.perm.p, c->opt.seed, c->t, c->B.p, c->ld,
+                      c->Emat.p, st));
+  double ms_pcg = 0;
+  fsa_status s;
+  if (c->opt.precision == FSA_MIXED_FP32) s = run_pcg<float>(c, &ms_pcg);
+  else s = run_pcg<double>(c, &ms_pcg);
+  if (s != FSA_OK && s != FSA_ERR_NOT_CONVERGED) {
+    *nll = INFINITY;
+    return s;
+  }
+  double fin[3];
+  FSA_HIP(hipMemcpyAsync(fin, c->results.p + 2 * c->ldw, sizeof(fin), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  *nll = fin[2];
+  double t_b0 = now_ms();
+  if (grad) {
+    fsa_status gs = run_gradient(c, grad);
+    if (gs != FSA_OK) return gs;
+  }
+  double t1 = now_ms();
+  c->stats.logdet = fin[0];
+  c->stats.quad = fin[1];
+  c->stats.logdet_P = c->last_logdet_P;
+  c->stats.ms_build = t_build - t0;
+  c->stats.ms_pcg = ms_pcg;
+  c->stats.ms_backward = grad ? t1 - t_b0 : 0.0;
+  c->stats.ms_total = t1 - t0;
+  c->stats.nnz = c->csr.nnz;
+  if (st_out) *st_out = c->stats;
+  return s;
+}
+
+fsa_status fsa_export_csr(fsa_ctx* c, int64_t* row_ptr, int32_t* col_idx, double* vals) {
+  if (!c || !row_ptr || !col_idx) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  return export_csr(c->csr, c->grid, c->grid, c->vals.p, row_ptr, col_idx, vals, c->st);
+}
+
+fsa_status fsa_export_diag(fsa_ctx* c, double* D, double* logdet_P) {
+  if (!c) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (D) {
+    Buf<double> tmp;
+    FSA_TRY(tmp.alloc(c->n));
+    FSA_TRY(permute_rows(c->D.p, 1, tmp.p, 1, c->grid.iperm.p, c->n, 1, c->st));
+    FSA_HIP(hipMemcpyAsync(D, tmp.p, c->n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    FSA_HIP(hipStreamSynchronize(c->st));
+  }
+  if (logdet_P) *logdet_P = c->last_logdet_P;
+  return FSA_OK;
+}
+
+fsa_status fsa_apply(fsa_ctx* c, int32_t which, const double* X, double* Y, int32_t ncols) {
+  if (!c || !Y || ncols < 1 || (which != FSA_OP_PROBES && !X)) { set_error("bad argument"); return FSA_ERR_INVALID_ARG; }
+  hipStream_t st = c->st;
+  const int64_t n = c->n;
+  int ld = (int)round_up(ncols, 4);
+  Buf<double> xh, xs, ys;
+  FSA_TRY(xh.alloc((size_t)n * ncols));
+  FSA_TRY(xs.alloc((size_t)n * ld));
+  FSA_TRY(ys.alloc((size_t)n * ld));
+  if (which != FSA_OP_PROBES) {
+    FSA_HIP(hipMemcpyAsync(xh.p, X, (size_t)n * ncols * sizeof(double), hipMemcpyHostToDevice, st));
+    FSA_TRY(permute_rows(xh.p, ncols, xs.p, ld, c->grid.perm.p, n, ncols, st));
+  }
+  int ldw = (int)round_up(ncols + 1, 64);
+  switch (which) {
+    case FSA_OP_SIGMA_S:
+      FSA_TRY(spmm<double>(c->csr, c->vals.p, xs.p, ld, ncols, ys.p, ld, false, st));
+      break;
+    case FSA_OP_SIGMA_DAGGER:
+      FSA_TRY(apply_sigma(c, xs.p, ys.p, ncols, ld));
+      break;
+    case FSA_OP_D_SIGMA1:
+      FSA_TRY(apply_sigma(c, xs.p, ys.p, ncols, ld));
+      FSA_TRY(axpy_block(xs.p, -c->th.s2, ys.p, ld, n, ncols, st));
+      FSA_TRY(scal_block(ys.p, ld, n, ncols, 1.0 / c->th.s1, st));
+      break;
+    case FSA_OP_D_RHO:
+      FSA_TRY(build_derivative(c));
+      FSA_TRY(apply_drho(c, xs.p, ys.p, ncols, ld));
+      break;
+    case FSA_OP_P_INV: {
+      int ldw2 = (int)round_up(ncols, 64);
+      FSA_TRY(c->scr.w.alloc((size_t)c->mp * ldw2 * 2));
+      Buf<double> g, tt;
+      FSA_TRY(g.alloc((size_t)c->mp * ldw2));
+      FSA_TRY(tt.alloc((size_t)n * ld));
+      FSA_TRY(lowrank_reduce<double>(c->A.p, n, c->mp, xs.p, ld, ncols, c->D.p, c->scr, c->scr.w.p, ldw2, st));
+      FSA_TRY(mspace_apply<double>(c->Cinv.p, c->scr.w.p, ldw2, c->mp, ncols, g.p, ldw2, st));
+      FSA_TRY(lowrank_expand<double>(c->A.p, nullptr, n, c->mp, g.p, ldw2, ncols, tt.p, ld, st));
+      FSA_TRY((copy_block<double, double>(xs.p, ld, ys.p, ld, n, ncols, st)));
+      FSA_TRY(axpy_block(tt.p, -1.0, ys.p, ld, n, ncols, st));
+      FSA_TRY(scale_rows(ys.p, ld, c->D.p, n, ncols, 1, st));
+      FSA_HIP(hipStreamSynchronize(st));
+      break;
+    }
+    case FSA_OP_PROBES: {
+      int ldb = (int)round_up(ncols + 1, 4);
+      Buf<double> Bp, Em;
+      FSA_TRY(Bp.alloc((size_t)n * ldb));
+      FSA_TRY(Em.alloc((size_t)c->mp * ldw));
+      FSA_TRY(make_probes(c->A.p, n, c->m, c->mp, c->D.p, c->y.p, c->grid.perm.p, c->opt.seed, ncols, Bp.p, ldb, Em.p,
+                          st));
+      FSA_TRY((copy_block<double, double>(Bp.p + 1, ldb, ys.p, ld, n, ncols, st)));
+      FSA_HIP(hipStreamSynchronize(st));
+      break;
+    }
+    default:
+      set_error("unknown operator %d", which);
+      return FSA_ERR_INVALID_ARG;
+  }
+  FSA_TRY(permute_rows(ys.p, ld, xh.p, ncols, c->grid.iperm.p, n, ncols, st));
+  FSA_HIP(hipMemcpyAsync(Y, xh.p, (size_t)n * ncols * sizeof(double), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  return FSA_OK;
+}
+
+fsa_status fsa_predict_var(fsa_ctx* c, const double* pred_locs, int64_t n_p, int32_t num_samples, double* var_out,
+                           double* mean_out, fsa_stats* st) {
+  (void)c; (void)pred_locs; (void)n_p; (void)num_samples; (void)var_out; (void)mean_out; (void)st;
+  set_error("fsa_predict_var: not built yet");
+  return FSA_ERR_INVALID_ARG;
+}
+
+}  // extern "C"

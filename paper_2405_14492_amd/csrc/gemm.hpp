@@ -1,0 +1,297 @@
+// MFMA (16x16x4, f64 or f32) kernels for the three dense contractions of the
+// FSA path.  All point-indexed matrices are stored point-major: row i holds
+// the kdim (multiple of 64) values of point i contiguously.
+//
+//  k_rows_gemm   OUT(i, c) = sum_k Aop(i, k) G[k][c]          (n x K) (K x 64)
+//                e.g. A^T g (the low-rank half of the operator / Woodbury
+//                solve), the whitening L_m^{-1} Sigma_mn, the probe block.
+//  k_reduce_gemm W[k][c]   = sum_i Acol(i, k) X(i, c)          (K x n) (n x 64)
+//                split over point chunks; deterministic second-stage sum.
+//                e.g. A D^{-1} r, the capacitance A D^{-1} A^T.
+//  k_sddmm       V(p, q)   = fn(d_pq, Xrow(p) . Yrow(q)) for the taper
+//                pattern, by dense 16x16 blocks between a grid cell's points
+//                and the points of its 3x3 neighbourhood.
+//
+// K-permutation: inside every block of 16 consecutive k, lane group
+// q = lane/16 owns k = 4q..4q+3 and feeds element j to MFMA number j, so each
+// lane fetches its four values with one vector load.  Any order of the k
+// terms is a valid contraction order.
+#pragma once
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fsa {
+
+constexpr int GS_LD = 80;  // LDS row stride of the G tile (bank spread)
+constexpr int XS_LD = 68;  // LDS row stride of the X chunk
+
+// ------------------------------------------------------------------ operand loaders
+template <typename T>
+struct RowsOp {  // row i of a point-major matrix
+  const T* a;
+  int64_t lda;
+  __device__ __forceinline__ V4<T> operator()(int64_t i, int k) const { return load4(a + i * lda + k); }
+};
+
+template <typename T>
+struct Rows2Op {  // row i of [a1 | a2] (two point-major matrices, kseg each)
+  const T* a1;
+  const T* a2;
+  int64_t lda;
+  int kseg;
+  __device__ __forceinline__ V4<T> operator()(int64_t i, int k) const {
+    return k < kseg ? load4(a1 + i * lda + k) : load4(a2 + i * lda + (k - kseg));
+  }
+};
+
+// ------------------------------------------------------------------ rows GEMM
+// grid: (ceil(nrows / (64*RT)), ceil(ncols / 64)); block 256 (4 waves).
+// Wave w handles rows [blk*64RT + w*16RT, +16RT) x 64 columns.
+template <typename T, int RT, bool DOT, class AOp, class Epi>
+__global__ __launch_bounds__(256) void k_rows_gemm(int64_t nrows, int kdim, const T* __restrict__ G, int ldg, int ncols,
+                                                   int upper_g, AOp aop, Epi epi, double* __restrict__ dot_part,
+                                                   int ld_dot) {
+  __shared__ __attribute__((aligned(16))) T Gs[64 * GS_LD];
+  __shared__ double red[4][64];
+  typedef typename Mfma<T>::acc acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.y * 64;
+  const int64_t row0 = (int64_t)blockIdx.x * (64 * RT) + w * 16 * RT;
+  acc_t acc[RT][4];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  const int kend = upper_g ? min(kdim, c0 + 64) : kdim;
+  for (int kc = 0; kc < kend; kc += 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      int rr = e >> 6, cc = e & 63;
+      int gc = c0 + cc;
+      Gs[rr * GS_LD + cc] = (gc < ncols) ? G[(int64_t)(kc + rr) * ldg + gc] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 64; ks += 16) {
+      V4<T> av[RT];
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        int64_t i = row0 + a * 16 + r16;
+        if (i < nrows) av[a] = aop(i, kc + ks + 4 * q);
+        else av[a] = V4<T>{{T(0), T(0), T(0), T(0)}};
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        T bv[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = Gs[(ks + 4 * q + j) * GS_LD + b * 16 + r16];
+#pragma unroll
+        for (int a = 0; a < RT; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::op(av[a].v[j], bv[b], acc[a][b]);
+      }
+    }
+  }
+  double dsum[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int64_t i = row0 + a * 16 + 4 * q + r;
+        int c = c0 + b * 16 + r16;
+        if (i < nrows && c < ncols) dsum[b] += epi(i, c, acc[a][b][r]);
+      }
+  if constexpr (DOT) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double v = dsum[b];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (q == 0) red[w][b * 16 + r16] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      double s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + threadIdx.x] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ reduce GEMM
+// grid: (nchunks, ncb = ceil(ncols/64), ceil(kdim / 512)); block 64*NW.
+// Partial tile layout: part[((chunk*ncb + cb)*nmb + mb)*4096 + (tile*4 + r)*64 + lane]
+// with tile = tau*4 + ct, k = mb*64 + 16*(lane/16) + 4r + tau, c = cb*64 + 4*(lane%16) + ct.
+template <typename T, bool DOT, class AOp, class Pro>
+__global__ __launch_bounds__(512) void k_reduce_gemm(int64_t npts, int pts_per_chunk, int kdim, int ncols, AOp acol,
+                                                     Pro pro, T* __restrict__ part, double* __restrict__ dot_part,
+                                                     int ld_dot) {
+  __shared__ __attribute__((aligned(16))) T Xs[64 * XS_LD];
+  __shared__ double red[512];
+  typedef typename Mfma<T>::acc acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.y * 64;
+  const int ncb = gridDim.y;
+  const int nmb = kdim / 64;
+  const int mb = blockIdx.z * 8 + w;
+  const bool mactive = mb < nmb;
+  const int kb = mb * 64;
+  const int64_t pbeg = (int64_t)blockIdx.x * pts_per_chunk;
+  const int64_t pend = min(npts, pbeg + pts_per_chunk);
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  // prologue thread mapping: column tc, points tp0 + k*(nthreads/64)
+  const int tc = threadIdx.x & 63;
+  const int tp0 = threadIdx.x >> 6;
+  double dacc = 0.0;
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 64) {
+    __syncthreads();
+    for (int pp = tp0; pp < 64; pp += nw) {
+      int64_t p = p0 + pp;
+      int c = c0 + tc;
+      T xv = T(0);
+      if (p < pend && c < ncols) xv = pro(p, c, dacc);
+      Xs[pp * XS_LD + tc] = xv;
+    }
+    __syncthreads();
+    if (mactive) {
+#pragma unroll 4
+      for (int kk = 0; kk < 64; kk += 4) {
+        int64_t i = p0 + kk + q;
+        V4<T> av;
+        if (i < pend) av = acol(i, kb + 4 * r16);
+        else av = V4<T>{{T(0), T(0), T(0), T(0)}};
+        V4<T> xv = load4(&Xs[(kk + q) * XS_LD + 4 * r16]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::op(av.v[a], xv.v[b], acc[a][b]);
+      }
+    }
+  }
+  if (mactive) {
+    T* dst = part + (((int64_t)blockIdx.x * ncb + blockIdx.y) * nmb + mb) * 4096;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[((a * 4 + b) * 4 + r) * 64 + lane] = acc[a][b][r];
+  }
+  if constexpr (DOT) {
+    red[threadIdx.x] = dacc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      double s = 0.0;
+      for (int k = 0; k < nw; ++k) s += red[k * 64 + threadIdx.x];
+      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + threadIdx.x] = s;
+    }
+  }
+}
+
+// Sum the per-chunk partial tiles (fixed order) into W (float64, row-major
+// kdim x ldw); optionally add the identity.
+template <typename T>
+__global__ void k_reduce_parts(const T* __restrict__ part, int nchunks, int ncb, int nmb, double* __restrict__ W,
+                               int ldw, int add_identity) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t per = (int64_t)ncb * nmb * 4096;
+  if (e >= per) return;
+  double s = 0.0;
+  for (int ch = 0; ch < nchunks; ++ch) s += (double)part[(int64_t)ch * per + e];
+  int lane = (int)(e & 63);
+  int r = (int)((e >> 6) & 3);
+  int tile = (int)((e >> 8) & 15);
+  int64_t blk = e >> 12;
+  int mb = (int)(blk % nmb);
+  int cb = (int)(blk / nmb);
+  int tau = tile >> 2, ct = tile & 3;
+  int k = mb * 64 + 16 * (lane >> 4) + 4 * r + tau;
+  int c = cb * 64 + 4 * (lane & 15) + ct;
+  if (add_identity && k == c) s += 1.0;
+  W[(int64_t)k * ldw + c] = s;
+}
+
+// ------------------------------------------------------------------ SDDMM
+// One workgroup per row cell; rows are the row set's points in that cell,
+// candidate columns the column set's points in the 3x3 block of cells.
+template <typename T, class XOp, class YOp, class Fn>
+__global__ __launch_bounds__(256) void k_sddmm(const int64_t* __restrict__ rcs, const double* __restrict__ rxs,
+                                               const int64_t* __restrict__ ccs, const double* __restrict__ cxs,
+                                               GridDesc gd, const int64_t* __restrict__ row_ptr,
+                                               const int* __restrict__ col, int kdim, XOp xop, YOp yop, Fn fn,
+                                               double* __restrict__ vals) {
+#pragma clang fp contract(off)
+  typedef typename Mfma<T>::acc acc_t;
+  const int64_t cell = blockIdx.x;
+  const int64_t rb = rcs[cell], re = rcs[cell + 1];
+  if (rb >= re) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int64_t cx = cell % gd.gx, cy = cell / gd.gx;
+  int64_t qb[3], qe[3], nt[3];
+  int64_t ntot = 0;
+  for (int t = 0; t < 3; ++t) {
+    int64_t yy = cy - 1 + t;
+    qb[t] = qe[t] = 0;
+    if (yy >= 0 && yy < gd.gy) {
+      int64_t xlo = cx - 1 < 0 ? 0 : cx - 1;
+      int64_t xhi = cx + 1 >= gd.gx ? gd.gx - 1 : cx + 1;
+      qb[t] = ccs[yy * gd.gx + xlo];
+      qe[t] = ccs[yy * gd.gx + xhi + 1];
+    }
+    nt[t] = (qe[t] - qb[t] + 15) / 16;
+    ntot += nt[t];
+  }
+  const int64_t nrt = (re - rb + 15) / 16;
+  const int64_t items = nrt * ntot;
+  const double g2 = gd.gamma * gd.gamma;
+  for (int64_t it = w; it < items; it += 4) {
+    int64_t rt = it / ntot, ti = it % ntot;
+    int t = 0;
+    while (ti >= nt[t]) { ti -= nt[t]; ++t; }
+    const int64_t p0 = rb + rt * 16;
+    const int64_t q0 = qb[t] + ti * 16;
+    const int64_t qend = qe[t];
+    const int64_t pa = min(p0 + r16, re - 1);
+    const int64_t qa = min(q0 + r16, qend - 1);
+    acc_t acc = acc_t{0, 0, 0, 0};
+    for (int ks = 0; ks < kdim; ks += 16) {
+      V4<T> a = xop(pa, ks + 4 * q);
+      V4<T> b = yop(qa, ks + 4 * q);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc = Mfma<T>::op(a.v[j], b.v[j], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int64_t p = p0 + 4 * q + r;
+      int64_t qq = q0 + r16;
+      if (p < re && qq < qend) {
+        double dx = rxs[2 * p] - cxs[2 * qq];
+        double dy = rxs[2 * p + 1] - cxs[2 * qq + 1];
+        double dx2 = dx * dx;
+        double dy2 = dy * dy;
+        double d2 = dx2 + dy2;
+        if (d2 < g2) {
+          int64_t lo = row_ptr[p], hi = row_ptr[p + 1] - 1;
+          while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (col[mid] < qq) lo = mid + 1;
+            else hi = mid;
+          }
+          if (lo <= hi && col[lo] == qq) vals[lo] = fn(p, qq, sqrt(d2), (double)acc[r]);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace fsa

@@ -1,0 +1,917 @@
+// FSA operations: covariance generation + whitening, residual values,
+// capacitance, sparse and low-rank block products, the fused PCG steps of
+// Algorithm 2, and the Lanczos-quadrature eigensolve.
+#include "gemm.hpp"
+#include "ops.hpp"
+
+namespace fsa {
+
+constexpr int RT_ROWS = 2;  // row tiles per wave in k_rows_gemm
+
+static int64_t rows_grid(int64_t n) { return ceil_div(n, 64 * RT_ROWS); }
+
+// ================================================================ functors
+struct CovRowsOp {
+  const double* xs;
+  const double* ind;
+  int m, mp, mode;
+  Theta th;
+  __device__ __forceinline__ V4<double> operator()(int64_t i, int k) const {
+    V4<double> r;
+    const double px = xs[2 * i], py = xs[2 * i + 1];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int kk = k + j;
+      bool der = false;
+      if (mode == 1) {
+        if (kk < mp) der = true;
+        else kk -= mp;
+      }
+      double v = 0.0;
+      if (kk < m) {
+        double dx = px - ind[2 * kk], dy = py - ind[2 * kk + 1];
+        double d = sqrt(dx * dx + dy * dy);
+        v = der ? dcov_drho(d, th) : cov_d(d, th);
+      }
+      r.v[j] = v;
+    }
+    return r;
+  }
+};
+
+template <typename T>
+struct StoreEpi {
+  T* out;
+  int64_t ld;
+  int accumulate;
+  __device__ __forceinline__ double operator()(int64_t i, int c, T v) const {
+    if (accumulate) out[i * ld + c] += v;
+    else out[i * ld + c] = v;
+    return 0.0;
+  }
+};
+
+struct ProbeEpi {
+  double* B;
+  int64_t ld;
+  const double* y;
+  const double* D;
+  const int* perm;
+  uint64_t seed;
+  __device__ __forceinline__ double operator()(int64_t i, int c, double v) const {
+    if (c == 0) B[i * ld] = y[i];
+    else B[i * ld + c] = sqrt(D[i]) * rademacher(seed, STREAM_RHO, (uint64_t)(c - 1), (uint64_t)perm[i]) + v;
+    return 0.0;
+  }
+};
+
+struct ValFn {
+  Theta th;
+  double gamma;
+  int self;
+  double* D;
+  __device__ __forceinline__ double operator()(int64_t p, int64_t q, double d, double dot) const {
+    double v = (cov_d(d, th) - dot) * taper(d, gamma);
+    if (self && p == q) {
+      v += th.s2;
+      D[p] = v;
+    }
+    return v;
+  }
+};
+
+struct DValFn {
+  Theta th;
+  double gamma;
+  __device__ __forceinline__ double operator()(int64_t, int64_t, double d, double dot) const {
+    return (dcov_drho(d, th) - dot) * taper(d, gamma);
+  }
+};
+
+// X(p, c) = S[p][c] / D[p]
+template <typename T>
+struct DivDPro {
+  const T* S;
+  int64_t ld;
+  const double* D;
+  __device__ __forceinline__ T operator()(int64_t p, int c, double&) const { return (T)((double)S[p * ld + c] / D[p]); }
+};
+// X(p, c) = S[p][c]
+template <typename T, typename TS>
+struct PlainPro {
+  const TS* S;
+  int64_t ld;
+  __device__ __forceinline__ T operator()(int64_t p, int c, double&) const { return (T)S[p * ld + c]; }
+};
+
+// ================================================================ build-time
+fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th, const double* G,
+                  int mode, double* A_out, hipStream_t st) {
+  CovRowsOp op{xs, ind, m, mp, mode, th};
+  StoreEpi<double> epi{A_out, mp, 0};
+  int kdim = mode == 1 ? 2 * mp : mp;
+  dim3 grid(rows_grid(n), mp / 64);
+  hipLaunchKernelGGL((k_rows_gemm<double, RT_ROWS, false, CovRowsOp, StoreEpi<double>>), grid, dim3(256), 0, st, n,
+                     kdim, G, mp, mp, mode == 0 ? 1 : 0, op, epi, (double*)nullptr, 0);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const double* Xr, const double* Yc,
+                           const double* Fr, const double* Fc, int mp, const Theta& th, double gamma, bool self,
+                           bool deriv, double* vals, double* D, hipStream_t st) {
+  if (rg.ncell == 0) return FSA_OK;
+  GridDesc gd = cg.desc;
+  gd.gamma = gamma;
+  if (!deriv) {
+    RowsOp<double> xo{Xr, mp}, yo{Yc, mp};
+    ValFn fn{th, gamma, self ? 1 : 0, D};
+    hipLaunchKernelGGL((k_sddmm<double, RowsOp<double>, RowsOp<double>, ValFn>), dim3(rg.ncell), dim3(256), 0, st,
+                       rg.cstart.p, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, mp, xo, yo, fn,
+                       vals);
+  } else {
+    Rows2Op<double> xo{Fr, Xr, mp, mp}, yo{Yc, Fc, mp, mp};
+    DValFn fn{th, gamma};
+    hipLaunchKernelGGL((k_sddmm<double, Rows2Op<double>, Rows2Op<double>, DValFn>), dim3(rg.ncell), dim3(256), 0, st,
+                       rg.cstart.p, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, 2 * mp, xo, yo, fn,
+                       vals);
+  }
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+struct ReduceShape {
+  int nchunks, ppc, ncb, nmb, zb, threads;
+};
+static ReduceShape reduce_shape(int64_t n, int kdim, int ncols) {
+  ReduceShape r;
+  r.ncb = (int)ceil_div(ncols, 64);
+  r.nmb = kdim / 64;
+  r.zb = (int)ceil_div(r.nmb, 8);
+  r.threads = 64 * (r.nmb < 8 ? r.nmb : 8);
+  int64_t target = 512 / (r.ncb * r.zb);
+  if (target < 16) target = 16;
+  int64_t nch = ceil_div(n, 1024);
+  if (nch > target) nch = target;
+  if (nch < 1) nch = 1;
+  r.ppc = (int)round_up(ceil_div(n, nch), 64);
+  r.nchunks = (int)ceil_div(n, r.ppc);
+  if (r.nchunks < 1) r.nchunks = 1;
+  return r;
+}
+
+template <typename T>
+static fsa_status ensure_part(Scratch& s, const ReduceShape& r) {
+  size_t need = (size_t)r.nchunks * r.ncb * r.nmb * 4096 * sizeof(T);
+  if (s.part.count < need) FSA_TRY(s.part.alloc(need));
+  size_t needd = (size_t)r.nchunks * r.ncb * 64;
+  if (s.dot.count < needd) FSA_TRY(s.dot.alloc(needd));
+  if (s.dot2.count < needd) FSA_TRY(s.dot2.alloc(needd));
+  return FSA_OK;
+}
+
+template <typename T>
+static fsa_status reduce_finish(Scratch& s, const ReduceShape& r, double* W, int ldw, int add_id, hipStream_t st) {
+  int64_t per = (int64_t)r.ncb * r.nmb * 4096;
+  hipLaunchKernelGGL(k_reduce_parts<T>, dim3(ceil_div(per, 256)), dim3(256), 0, st, (const T*)s.part.p, r.nchunks,
+                     r.ncb, r.nmb, W, ldw, add_id);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+fsa_status capacitance(const double* A, const double* D, int64_t n, int mp, double* C, Scratch& s, hipStream_t st) {
+  ReduceShape r = reduce_shape(n, mp, mp);
+  FSA_TRY(ensure_part<double>(s, r));
+  DivDPro<double> pro{A, mp, D};
+  RowsOp<double> acol{A, mp};
+  hipLaunchKernelGGL((k_reduce_gemm<double, false, RowsOp<double>, DivDPro<double>>), dim3(r.nchunks, r.ncb, r.zb),
+                     dim3(r.threads), 0, st, n, r.ppc, mp, mp, acol, pro, (double*)s.part.p, (double*)nullptr, 0);
+  FSA_HIP(hipGetLastError());
+  return reduce_finish<double>(s, r, C, mp, 1, st);
+}
+
+// ================================================================ block products
+template <typename T>
+fsa_status lowrank_reduce(const T* A, int64_t n, int kdim, const T* X, int ldx, int ncols, const double* Dinv_src,
+                          Scratch& s, double* W, int ldw, hipStream_t st) {
+  ReduceShape r = reduce_shape(n, kdim, ncols);
+  FSA_TRY(ensure_part<T>(s, r));
+  RowsOp<T> acol{A, kdim};
+  if (Dinv_src) {
+    DivDPro<T> pro{X, ldx, Dinv_src};
+    hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, DivDPro<T>>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads),
+                       0, st, n, r.ppc, kdim, ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0);
+  } else {
+    PlainPro<T, T> pro{X, ldx};
+    hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, PlainPro<T, T>>), dim3(r.nchunks, r.ncb, r.zb),
+                       dim3(r.threads), 0, st, n, r.ppc, kdim, ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0);
+  }
+  FSA_HIP(hipGetLastError());
+  return reduce_finish<T>(s, r, W, ldw, 0, st);
+}
+
+template <typename T>
+fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T* G, int ldg, int ncols, T* OUT,
+                          int ldo, hipStream_t st) {
+  StoreEpi<T> epi{OUT, ldo, 0};
+  dim3 grid(rows_grid(n), ceil_div(ncols, 64));
+  if (A2) {
+    Rows2Op<T> op{A, A2, kdim / 2, kdim / 2};
+    hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, false, Rows2Op<T>, StoreEpi<T>>), grid, dim3(256), 0, st, n, kdim, G,
+                       ldg, ncols, 0, op, epi, (double*)nullptr, 0);
+  } else {
+    RowsOp<T> op{A, kdim};
+    hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, false, RowsOp<T>, StoreEpi<T>>), grid, dim3(256), 0, st, n, kdim, G,
+                       ldg, ncols, 0, op, epi, (double*)nullptr, 0);
+  }
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// ---------------------------------------------------------------- SpMM
+// One wave per row and 64-column block; lanes are columns.
+template <typename T, bool DOT, class Epi>
+__global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int64_t* __restrict__ rp, const int* __restrict__ col,
+                                              const T* __restrict__ val, const T* __restrict__ X, int ldx, int ncols,
+                                              Epi epi, double* __restrict__ dot_part, int ld_dot) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + lane;
+  const bool cok = c < ncols;
+  double dacc = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + w; row < nrows; row += (int64_t)gridDim.x * 4) {
+    const int64_t rowu = row;
+    int64_t e = rp[rowu];
+    const int64_t ee = rp[rowu + 1];
+    T acc0 = T(0), acc1 = T(0);
+    for (; e + 2 <= ee; e += 2) {
+      const T v0 = val[e], v1 = val[e + 1];
+      const int j0 = col[e], j1 = col[e + 1];
+      T x0 = cok ? X[(int64_t)j0 * ldx + c] : T(0);
+      T x1 = cok ? X[(int64_t)j1 * ldx + c] : T(0);
+      acc0 += v0 * x0;
+      acc1 += v1 * x1;
+    }
+    if (e < ee) {
+      const T v0 = val[e];
+      const int j0 = col[e];
+      acc0 += v0 * (cok ? X[(int64_t)j0 * ldx + c] : T(0));
+    }
+    if (cok) dacc += epi(rowu, c, acc0 + acc1);
+  }
+  if constexpr (DOT) {
+    red[w][lane] = dacc;
+    __syncthreads();
+    if (threadIdx.x < 64)
+      dot_part[(int64_t)blockIdx.x * ld_dot + blockIdx.y * 64 + threadIdx.x] =
+          red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+  }
+}
+
+static int64_t spmm_grid(int64_t n) {
+  int64_t g = ceil_div(n, 4 * 8);
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return g;
+}
+
+template <typename T>
+fsa_status spmm(const Csr& S, const T* val, const T* X, int ldx, int ncols, T* Y, int ldy, bool accumulate,
+                hipStream_t st) {
+  StoreEpi<T> epi{Y, ldy, accumulate ? 1 : 0};
+  dim3 grid(spmm_grid(S.nrows), ceil_div(ncols, 64));
+  hipLaunchKernelGGL((k_spmm<T, false, StoreEpi<T>>), grid, dim3(256), 0, st, S.nrows, S.row_ptr.p, S.col.p, val, X,
+                     ldx, ncols, epi, (double*)nullptr, 0);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// ---------------------------------------------------------------- column dots
+template <typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_coldot(const TX* __restrict__ X, const TY* __restrict__ Y, int64_t n, int ld,
+                                                int ncols, double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + lane;
+  double a = 0.0;
+  if (c < ncols)
+    for (int64_t p = (int64_t)blockIdx.x * 4 + w; p < n; p += (int64_t)gridDim.x * 4)
+      a += (double)X[p * ld + c] * (double)Y[p * ld + c];
+  red[w][lane] = a;
+  __syncthreads();
+  if (threadIdx.x < 64)
+    part[(int64_t)blockIdx.x * (gridDim.y * 64) + blockIdx.y * 64 + threadIdx.x] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int nparts, int ldp, int ncols, double* __restrict__ out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  double s = 0.0;
+  for (int k = 0; k < nparts; ++k) s += part[(int64_t)k * ldp + c];
+  out[c] = s;
+}
+
+template <typename TX, typename TY>
+fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double* out, Scratch& s, hipStream_t st) {
+  int ncb = (int)ceil_div(ncols, 64);
+  int64_t g = ceil_div(n, 64);
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  size_t need = (size_t)g * ncb * 64;
+  if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
+  hipLaunchKernelGGL((k_coldot<TX, TY>), dim3(g, ncb), dim3(256), 0, st, X, Y, n, ld, ncols, s.dot.p);
+  hipLaunchKernelGGL(k_sum_parts, dim3(ceil_div(ncols, 256)), dim3(256), 0, st, s.dot.p, (int)g, ncb * 64, ncols, out);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// ---------------------------------------------------------------- m-space
+template <typename T>
+__global__ void k_mspace(const double* __restrict__ M, const double* __restrict__ W, int ldw, int kdim, int ncols,
+                         T* __restrict__ G, int ldg) {
+  int c = blockIdx.x * 64 + threadIdx.x % 64;
+  int k = blockIdx.y * (blockDim.x / 64) + threadIdx.x / 64;
+  if (k >= kdim) return;
+  double s = 0.0;
+  if (c < ncols) {
+    const double* mr = M + (int64_t)k * kdim;
+    for (int j = 0; j < kdim; ++j) s += mr[j] * W[(int64_t)j * ldw + c];
+  }
+  if (c < ldg) G[(int64_t)k * ldg + c] = (T)s;
+}
+
+template <typename T>
+fsa_status mspace_apply(const double* M, const double* W, int ldw, int kdim, int ncols, T* G, int ldg,
+                        hipStream_t st) {
+  dim3 grid(ceil_div(ldg, 64), ceil_div(kdim, 4));
+  hipLaunchKernelGGL(k_mspace<T>, grid, dim3(256), 0, st, M, W, ldw, kdim, ncols, G, ldg);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// ================================================================ PCG (Algorithm 2)
+// Pass-1 prologue of an iteration: u += alpha h, r -= alpha v, |r|^2, X = r / D.
+template <typename T>
+struct PcgPass1Pro {
+  double* U;
+  const T* H;
+  T* R;
+  const T* V;
+  const double* D;
+  const double* alpha;
+  int64_t ld;
+  int update;
+  __device__ __forceinline__ T operator()(int64_t p, int c, double& dot) const {
+    int64_t o = p * ld + c;
+    double r;
+    if (update) {
+      double a = alpha[c];
+      U[o] += a * (double)H[o];
+      r = (double)R[o] - a * (double)V[o];
+      R[o] = (T)r;
+      r = (double)R[o];
+    } else {
+      r = (double)R[o];
+    }
+    dot += r * r;
+    return (T)(r / D[p]);
+  }
+};
+
+// Pass-2 epilogue: t = (A^T g)_i, q = (r - t)/D; on init h = q, p = t, q0 = q.
+template <typename T>
+struct PcgPass2Epi {
+  T* Tt;
+  const T* R;
+  const double* D;
+  T* H;
+  T* P;
+  T* Q0;
+  int64_t ld;
+  int init;
+  __device__ __forceinline__ double operator()(int64_t i, int c, T v) const {
+    int64_t o = i * ld + c;
+    double r = (double)R[o];
+    double qv = (r - (double)v) / D[i];
+    if (init) {
+      H[o] = (T)qv;
+      P[o] = v;
+      Q0[o] = (T)qv;
+    } else {
+      Tt[o] = v;
+    }
+    return r * qv;
+  }
+};
+
+// SpMM epilogue: v = (S h)_i + p_i; accumulates h . v
+template <typename T>
+struct PcgSpmmEpi {
+  const T* H;
+  const T* P;
+  T* V;
+  int64_t ld;
+  int has_p;
+  __device__ __forceinline__ double operator()(int64_t i, int c, T acc) const {
+    int64_t o = i * ld + c;
+    double v = (double)acc + (has_p ? (double)P[o] : 0.0);
+    V[o] = (T)v;
+    return (double)H[o] * (double)V[o];
+  }
+};
+
+// Sparse-only variants (no low-rank part): elementwise
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_sparse_update(int64_t n, int ncols, int64_t ld, double* U, const T* H, T* R,
+                                                           const T* V, const double* D, const double* alpha, int update,
+                                                           int init, T* Hout, T* Q0, double* rr_part,
+                                                           double* rq_part, int ld_dot) {
+  __shared__ double red1[4][64], red2[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + lane;
+  double a1 = 0.0, a2 = 0.0;
+  if (c < ncols) {
+    for (int64_t p = (int64_t)blockIdx.x * 4 + w; p < n; p += (int64_t)gridDim.x * 4) {
+      int64_t o = p * ld + c;
+      double r;
+      if (update) {
+        double a = alpha[c];
+        U[o] += a * (double)H[o];
+        r = (double)R[o] - a * (double)V[o];
+        R[o] = (T)r;
+        r = (double)R[o];
+      } else {
+        r = (double)R[o];
+      }
+      double qv = r / D[p];
+      if (init) {
+        Hout[o] = (T)qv;
+        Q0[o] = (T)qv;
+      }
+      a1 += r * r;
+      a2 += r * qv;
+    }
+  }
+  red1[w][lane] = a1;
+  red2[w][lane] = a2;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    int64_t o = (int64_t)blockIdx.x * ld_dot + blockIdx.y * 64 + threadIdx.x;
+    rr_part[o] = red1[0][threadIdx.x] + red1[1][threadIdx.x] + red1[2][threadIdx.x] + red1[3][threadIdx.x];
+    rq_part[o] = red2[0][threadIdx.x] + red2[1][threadIdx.x] + red2[2][threadIdx.x] + red2[3][threadIdx.x];
+  }
+}
+
+// h = q + beta h with q = (r - t)/D (t = 0 when no low-rank part); p = t + beta p.
+template <typename T>
+__global__ void k_pcg_hupdate(int64_t n, int ncols, int64_t ld, const T* __restrict__ R, const T* __restrict__ Tt,
+                              const double* __restrict__ D, const double* __restrict__ beta, T* __restrict__ H,
+                              T* __restrict__ P, int has_lr) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / ncols;
+  int c = (int)(e % ncols);
+  if (p >= n) return;
+  int64_t o = p * ld + c;
+  double b = beta[c];
+  double t = has_lr ? (double)Tt[o] : 0.0;
+  double q = ((double)R[o] - t) / D[p];
+  H[o] = (T)(q + b * (double)H[o]);
+  if (has_lr) P[o] = (T)(t + b * (double)P[o]);
+}
+
+__global__ void k_pcg_setup(int ncols, const double* __restrict__ bn2_part, int nb, int ldb, const double* __restrict__ rq_part,
+                            int nr, int ldr, double* bn2, double* rz, double* rz0, int* active, int* iters, int* flags) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    double b = 0.0, r = 0.0;
+    for (int k = 0; k < nb; ++k) b += bn2_part[(int64_t)k * ldb + c];
+    for (int k = 0; k < nr; ++k) r += rq_part[(int64_t)k * ldr + c];
+    bn2[c] = b;
+    rz[c] = r;
+    rz0[c] = r;
+    iters[c] = 0;
+    int a = b > 0.0 ? 1 : 0;
+    active[c] = a;
+    if (a) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    flags[0] = cnt;
+    flags[1] = 0;
+  }
+}
+
+__global__ void k_pcg_alpha(int ncols, const double* __restrict__ hv_part, int np, int ldp, const double* __restrict__ rz,
+                            const int* __restrict__ active, double* __restrict__ alpha, int* flags) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  double hv = 0.0;
+  for (int k = 0; k < np; ++k) hv += hv_part[(int64_t)k * ldp + c];
+  double a = 0.0;
+  if (active[c]) {
+    if (!(hv > 0.0) || !isfinite(hv)) {
+      atomicOr(&flags[1], 1);
+    } else {
+      a = rz[c] / hv;
+    }
+  }
+  alpha[c] = a;
+}
+
+__global__ void k_pcg_beta(int ncols, const double* __restrict__ rq_part, int nq, int ldq, const double* __restrict__ rr_part,
+                           int nr, int ldr, double* rz, const double* __restrict__ alpha, double* beta, int* active,
+                           int* iters, double* ah, double* bh, const double* __restrict__ bn2, double tol2, int fixed,
+                           int max_iter, int* flags) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    double b = 0.0;
+    if (active[c]) {
+      double rq = 0.0, rr = 0.0;
+      for (int k = 0; k < nq; ++k) rq += rq_part[(int64_t)k * ldq + c];
+      for (int k = 0; k < nr; ++k) rr += rr_part[(int64_t)k * ldr + c];
+      b = rq / rz[c];
+      int it = iters[c];
+      if (it < max_iter) {
+        ah[(int64_t)it * ncols + c] = alpha[c];
+        bh[(int64_t)it * ncols + c] = b;
+      }
+      iters[c] = it + 1;
+      rz[c] = rq;
+      if (!isfinite(rq)) atomicOr(&flags[1], 1);
+      if (!fixed && rr < tol2 * bn2[c]) active[c] = 0;
+    }
+    beta[c] = b;
+    if (active[c]) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) flags[0] = cnt;
+}
+
+template <typename T>
+static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int init, Scratch& s, int& nparts_rq,
+                                       hipStream_t st) {
+  // m-space: g = Cinv (A D^{-1} r), then q = (r - A^T g)/D
+  FSA_TRY(mspace_apply<T>(op.Cinv, s.w.p, b.ldw, op.kdim, b.ncols, b.g, b.ldw, st));
+  PcgPass2Epi<T> epi{b.Tt, b.R, op.D, b.H, b.P, b.Q0, b.ld, init};
+  RowsOp<T> aop{op.A, op.kdim};
+  int64_t gx = rows_grid(b.n);
+  int ncb = (int)ceil_div(b.ncols, 64);
+  size_t need = (size_t)gx * ncb * 64;
+  if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
+  hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, true, RowsOp<T>, PcgPass2Epi<T>>), dim3(gx, ncb), dim3(256), 0, st, b.n,
+                     op.kdim, b.g, b.ldw, b.ncols, 0, aop, epi, s.dot.p, ncb * 64);
+  FSA_HIP(hipGetLastError());
+  nparts_rq = (int)gx;
+  return FSA_OK;
+}
+
+template <typename T>
+fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double tol, Scratch& s, hipStream_t st) {
+  (void)tol;
+  FSA_TRY((copy_block<double, T>(B, b.ld, b.R, b.ld, b.n, b.ncols, st)));
+  FSA_HIP(hipMemsetAsync(b.U, 0, (size_t)b.n * b.ld * sizeof(double), st));
+  int ncb = (int)ceil_div(b.ncols, 64);
+  int nparts_rq = 0, nparts_rr = 0;
+  if (op.kdim > 0) {
+    ReduceShape r = reduce_shape(b.n, op.kdim, b.ncols);
+    FSA_TRY(ensure_part<T>(s, r));
+    DivDPro<T> pro{b.R, b.ld, op.D};
+    RowsOp<T> acol{op.A, op.kdim};
+    hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, DivDPro<T>>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads),
+                       0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0);
+    FSA_HIP(hipGetLastError());
+    FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
+    FSA_TRY(pcg_precond_and_dots<T>(b, op, 1, s, nparts_rq, st));
+    // |b|^2 partials
+    int64_t g = ceil_div(b.n, 64);
+    if (g > 1024) g = 1024;
+    size_t need = (size_t)g * ncb * 64;
+    if (s.dot2.count < need) FSA_TRY(s.dot2.alloc(need));
+    hipLaunchKernelGGL((k_coldot<double, double>), dim3(g, ncb), dim3(256), 0, st, B, B, b.n, b.ld, b.ncols, s.dot2.p);
+    nparts_rr = (int)g;
+    FSA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_pcg_setup, dim3(1), dim3(256), 0, st, b.ncols, s.dot2.p, nparts_rr, ncb * 64, s.dot.p,
+                       nparts_rq, ncb * 64, b.bn2, b.rz, b.rz0, b.active, b.iters, b.flags);
+  } else {
+    int64_t g = spmm_grid(b.n);
+    size_t need = (size_t)g * ncb * 64;
+    if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
+    if (s.dot2.count < need) FSA_TRY(s.dot2.alloc(need));
+    hipLaunchKernelGGL((k_pcg_sparse_update<T>), dim3(g, ncb), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, b.U,
+                       (const T*)b.H, b.R, (const T*)b.V, op.D, b.alpha, 0, 1, b.H, b.Q0, s.dot2.p, s.dot.p, ncb * 64);
+    FSA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_pcg_setup, dim3(1), dim3(256), 0, st, b.ncols, s.dot2.p, (int)g, ncb * 64, s.dot.p, (int)g,
+                       ncb * 64, b.bn2, b.rz, b.rz0, b.active, b.iters, b.flags);
+  }
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+template <typename T>
+fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, Scratch& s, hipStream_t st) {
+  const int ncb = (int)ceil_div(b.ncols, 64);
+  const int ldd = ncb * 64;
+  const bool lr = op.kdim > 0;
+  // 1. V = S H + P, h^T v
+  {
+    PcgSpmmEpi<T> epi{b.H, b.P, b.V, b.ld, lr ? 1 : 0};
+    int64_t g = spmm_grid(b.n);
+    size_t need = (size_t)g * ldd;
+    if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
+    hipLaunchKernelGGL((k_spmm<T, true, PcgSpmmEpi<T>>), dim3(g, ncb), dim3(256), 0, st, b.n, op.S->row_ptr.p,
+                       op.S->col.p, op.val, b.H, b.ld, b.ncols, epi, s.dot.p, ldd);
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(ceil_div(b.ncols, 64)), dim3(64), 0, st, b.ncols, s.dot.p, (int)g, ldd, b.rz,
+                       b.active, b.alpha, b.flags);
+    FSA_HIP(hipGetLastError());
+  }
+  int nparts_rq = 0, nparts_rr = 0;
+  if (lr) {
+    // 2. u += alpha h, r -= alpha v, |r|^2, W = A D^{-1} r
+    ReduceShape r = reduce_shape(b.n, op.kdim, b.ncols);
+    FSA_TRY(ensure_part<T>(s, r));
+    PcgPass1Pro<T> pro{b.U, b.H, b.R, b.V, op.D, b.alpha, b.ld, 1};
+    RowsOp<T> acol{op.A, op.kdim};
+    hipLaunchKernelGGL((k_reduce_gemm<T, true, RowsOp<T>, PcgPass1Pro<T>>), dim3(r.nchunks, r.ncb, r.zb),
+                       dim3(r.threads), 0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, s.dot2.p, ldd);
+    FSA_HIP(hipGetLastError());
+    nparts_rr = r.nchunks;
+    FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
+    // 3. g = Cinv W; t = A^T g; q = (r - t)/D; r^T q
+    FSA_TRY(pcg_precond_and_dots<T>(b, op, 0, s, nparts_rq, st));
+  } else {
+    int64_t g = spmm_grid(b.n);
+    hipLaunchKernelGGL((k_pcg_sparse_update<T>), dim3(g, ncb), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, b.U,
+                       (const T*)b.H, b.R, (const T*)b.V, op.D, b.alpha, 1, 0, b.H, b.Q0, s.dot2.p, s.dot.p, ldd);
+    FSA_HIP(hipGetLastError());
+    nparts_rq = nparts_rr = (int)g;
+  }
+  // 4. beta, Lanczos entries, convergence
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, st, b.ncols, s.dot.p, nparts_rq, ldd, s.dot2.p, nparts_rr, ldd,
+                     b.rz, b.alpha, b.beta, b.active, b.iters, b.alpha_hist, b.beta_hist, b.bn2, tol * tol, fixed,
+                     b.max_iter, b.flags);
+  // 5. h = q + beta h, p = t + beta p
+  int64_t tot = b.n * b.ncols;
+  hipLaunchKernelGGL(k_pcg_hupdate<T>, dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld,
+                     (const T*)b.R, (const T*)b.Tt, op.D, b.beta, b.H, b.P, lr ? 1 : 0);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// R = B - (S U + A^T (A U)) in float64, then rounded to float.
+__global__ void k_residual_f32(int64_t n, int ncols, int64_t ld, const double* __restrict__ B, const double* __restrict__ SU,
+                               const double* __restrict__ LU, float* __restrict__ R) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / ncols;
+  int c = (int)(e % ncols);
+  if (p >= n) return;
+  int64_t o = p * ld + c;
+  R[o] = (float)(B[o] - SU[o] - LU[o]);
+}
+
+fsa_status pcg_replace_residual_f32(PcgBlock<float>& b, const OpDesc<double>& op64, const OpDesc<float>& op32,
+                                    const double* B, Scratch& s, hipStream_t st) {
+  (void)op32;
+  Buf<double> SU, LU, G;
+  FSA_TRY(SU.alloc((size_t)b.n * b.ld));
+  FSA_TRY(LU.alloc((size_t)b.n * b.ld));
+  FSA_TRY(spmm<double>(*op64.S, op64.val, b.U, b.ld, b.ncols, SU.p, b.ld, false, st));
+  FSA_TRY(lowrank_reduce<double>(op64.A, b.n, op64.kdim, b.U, b.ld, b.ncols, nullptr, s, s.w.p, b.ldw, st));
+  FSA_TRY(lowrank_expand<double>(op64.A, nullptr, b.n, op64.kdim, s.w.p, b.ldw, b.ncols, LU.p, b.ld, st));
+  int64_t tot = b.n * b.ncols;
+  hipLaunchKernelGGL(k_residual_f32, dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, B, SU.p,
+                     LU.p, b.R);
+  FSA_HIP(hipGetLastError());
+  FSA_HIP(hipStreamSynchronize(st));
+  return FSA_OK;
+}
+
+// ================================================================ SLQ
+// e_1^T log(T) e_1 of the Lanczos tridiagonal built from the CG
+// coefficients: T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_{j,j+1} =
+// sqrt(beta_j)/alpha_j (Algorithm 2).  Eigenvalues by the implicit QL
+// iteration with Wilkinson-type shifts (Bowdler, Martin, Reinsch &
+// Wilkinson 1968), tracking only the first row of the eigenvector matrix.
+__global__ void k_slq(const double* __restrict__ ah, const double* __restrict__ bh, const int* __restrict__ iters,
+                      int ncols, int c_first, const double* __restrict__ weight, double* __restrict__ out,
+                      double* __restrict__ scratch, int max_iter) {
+  int c = c_first + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  int k = iters[c];
+  if (k > max_iter) k = max_iter;
+  double* d = scratch + (int64_t)c * 3 * max_iter;
+  double* e = d + max_iter;
+  double* z = e + max_iter;
+  for (int j = 0; j < k; ++j) {
+    double a = ah[(int64_t)j * ncols + c];
+    d[j] = 1.0 / a + (j > 0 ? bh[(int64_t)(j - 1) * ncols + c] / ah[(int64_t)(j - 1) * ncols + c] : 0.0);
+    e[j] = (j < k - 1) ? sqrt(bh[(int64_t)j * ncols + c]) / a : 0.0;
+    z[j] = (j == 0) ? 1.0 : 0.0;
+  }
+  bool ok = k > 0;
+  for (int l = 0; l < k && ok; ++l) {
+    int iter = 0;
+    int mm;
+    do {
+      for (mm = l; mm < k - 1; ++mm) {
+        double dd = fabs(d[mm]) + fabs(d[mm + 1]);
+        if (fabs(e[mm]) <= 2.220446049250313e-16 * dd) break;
+      }
+      if (mm != l) {
+        if (iter++ == 200) { ok = false; break; }
+        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+        double r = hypot(g, 1.0);
+        g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
+        double s = 1.0, cc = 1.0, p = 0.0;
+        int i;
+        bool deflated = false;
+        for (i = mm - 1; i >= l; --i) {
+          double f = s * e[i], bb = cc * e[i];
+          r = hypot(f, g);
+          e[i + 1] = r;
+          if (r == 0.0) {
+            d[i + 1] -= p;
+            e[mm] = 0.0;
+            deflated = true;
+            break;
+          }
+          s = f / r;
+          cc = g / r;
+          g = d[i + 1] - p;
+          r = (d[i] - g) * s + 2.0 * cc * bb;
+          p = s * r;
+          d[i + 1] = g + p;
+          g = cc * r - bb;
+          double zf = z[i + 1];
+          z[i + 1] = s * z[i] + cc * zf;
+          z[i] = cc * z[i] - s * zf;
+        }
+        if (deflated) continue;
+        d[l] -= p;
+        e[l] = g;
+        e[mm] = 0.0;
+      }
+    } while (mm != l);
+  }
+  double v = 0.0;
+  if (ok) {
+    for (int j = 0; j < k; ++j) {
+      if (!(d[j] > 0.0)) { ok = false; break; }
+      v += z[j] * z[j] * log(d[j]);
+    }
+  }
+  out[c] = ok ? weight[c] * v : NAN;
+}
+
+fsa_status slq_terms(const double* alpha_hist, const double* beta_hist, const int* iters, int ncols, int c_first,
+                     const double* weight, double* out, double* scratch, int max_iter, hipStream_t st) {
+  int cnt = ncols - c_first;
+  if (cnt <= 0) return FSA_OK;
+  hipLaunchKernelGGL(k_slq, dim3(ceil_div(cnt, 64)), dim3(64), 0, st, alpha_hist, beta_hist, iters, ncols, c_first,
+                     weight, out, scratch, max_iter);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// ================================================================ probes
+__global__ void k_probe_e(int m, int mp, int nprobe, uint64_t seed, double* E, int ldb) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)mp * ldb) return;
+  int k = (int)(e / ldb), c = (int)(e % ldb);
+  double v = 0.0;
+  if (k < m && c >= 1 && c <= nprobe) v = rademacher(seed, STREAM_E, (uint64_t)(c - 1), (uint64_t)k);
+  E[e] = v;
+}
+
+fsa_status make_probes(const double* A, int64_t n, int m, int mp, const double* D, const double* y, const int* perm,
+                       uint64_t seed, int nprobe, double* B, int ldb, double* Emat, hipStream_t st) {
+  int ncols = nprobe + 1;
+  int ldE = (int)round_up(ncols, 64);
+  hipLaunchKernelGGL(k_probe_e, dim3(ceil_div((int64_t)mp * ldE, 256)), dim3(256), 0, st, m, mp, nprobe, seed, Emat,
+                     ldE);
+  ProbeEpi epi{B, ldb, y, D, perm, seed};
+  RowsOp<double> op{A, mp};
+  dim3 grid(rows_grid(n), ceil_div(ncols, 64));
+  hipLaunchKernelGGL((k_rows_gemm<double, RT_ROWS, false, RowsOp<double>, ProbeEpi>), grid, dim3(256), 0, st, n, mp,
+                     Emat, ldE, ncols, 0, op, epi, (double*)nullptr, 0);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// ================================================================ elementwise
+template <typename TI, typename TO>
+__global__ void k_copy_block(const TI* __restrict__ in, int ldi, TO* __restrict__ out, int ldo, int64_t n, int ncols) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / ncols;
+  int c = (int)(e % ncols);
+  if (p >= n) return;
+  out[p * ldo + c] = (TO)in[p * ldi + c];
+}
+
+template <typename TI, typename TO>
+fsa_status copy_block(const TI* in, int ldi, TO* out, int ldo, int64_t n, int ncols, hipStream_t st) {
+  int64_t tot = n * ncols;
+  if (tot == 0) return FSA_OK;
+  hipLaunchKernelGGL((k_copy_block<TI, TO>), dim3(ceil_div(tot, 256)), dim3(256), 0, st, in, ldi, out, ldo, n, ncols);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+__global__ void k_permute_rows(const double* __restrict__ in, int ldi, double* __restrict__ out, int ldo,
+                               const int* __restrict__ idx, int64_t n, int ncols) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / ncols;
+  int c = (int)(e % ncols);
+  if (p >= n) return;
+  out[p * ldo + c] = in[(int64_t)idx[p] * ldi + c];
+}
+
+fsa_status permute_rows(const double* in, int ldi, double* out, int ldo, const int* idx, int64_t n, int ncols,
+                        hipStream_t st) {
+  int64_t tot = n * ncols;
+  if (tot == 0) return FSA_OK;
+  hipLaunchKernelGGL(k_permute_rows, dim3(ceil_div(tot, 256)), dim3(256), 0, st, in, ldi, out, ldo, idx, n, ncols);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+__global__ void k_scale_rows(double* X, int ld, const double* __restrict__ D, int64_t n, int ncols, int invert) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / ncols;
+  int c = (int)(e % ncols);
+  if (p >= n) return;
+  X[p * ld + c] = invert ? X[p * ld + c] / D[p] : X[p * ld + c] * D[p];
+}
+
+fsa_status scale_rows(double* X, int ld, const double* D, int64_t n, int ncols, int invert, hipStream_t st) {
+  int64_t tot = n * ncols;
+  if (tot == 0) return FSA_OK;
+  hipLaunchKernelGGL(k_scale_rows, dim3(ceil_div(tot, 256)), dim3(256), 0, st, X, ld, D, n, ncols, invert);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+__global__ void k_axpy_block(const double* __restrict__ X, double a, double* __restrict__ Y, int ld, int64_t n, int ncols) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / ncols;
+  int c = (int)(e % ncols);
+  if (p >= n) return;
+  Y[p * ld + c] += a * X[p * ld + c];
+}
+
+fsa_status axpy_block(const double* X, double a, double* Y, int ld, int64_t n, int ncols, hipStream_t st) {
+  int64_t tot = n * ncols;
+  if (tot == 0) return FSA_OK;
+  hipLaunchKernelGGL(k_axpy_block, dim3(ceil_div(tot, 256)), dim3(256), 0, st, X, a, Y, ld, n, ncols);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+__global__ void k_scal_block(double* X, int ld, int64_t n, int ncols, double a) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / ncols;
+  int c = (int)(e % ncols);
+  if (p >= n) return;
+  X[p * ld + c] *= a;
+}
+
+fsa_status scal_block(double* X, int ld, int64_t n, int ncols, double a, hipStream_t st) {
+  int64_t tot = n * ncols;
+  if (tot == 0) return FSA_OK;
+  hipLaunchKernelGGL(k_scal_block, dim3(ceil_div(tot, 256)), dim3(256), 0, st, X, ld, n, ncols, a);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// ================================================================ instantiations
+template fsa_status lowrank_reduce<double>(const double*, int64_t, int, const double*, int, int, const double*, Scratch&,
+                                           double*, int, hipStream_t);
+template fsa_status lowrank_reduce<float>(const float*, int64_t, int, const float*, int, int, const double*, Scratch&,
+                                          double*, int, hipStream_t);
+template fsa_status lowrank_expand<double>(const double*, const double*, int64_t, int, const double*, int, int, double*,
+                                           int, hipStream_t);
+template fsa_status lowrank_expand<float>(const float*, const float*, int64_t, int, const float*, int, int, float*, int,
+                                          hipStream_t);
+template fsa_status spmm<double>(const Csr&, const double*, const double*, int, int, double*, int, bool, hipStream_t);
+template fsa_status spmm<float>(const Csr&, const float*, const float*, int, int, float*, int, bool, hipStream_t);
+template fsa_status coldot<double, double>(const double*, const double*, int64_t, int, int, double*, Scratch&,
+                                           hipStream_t);
+template fsa_status coldot<double, float>(const double*, const float*, int64_t, int, int, double*, Scratch&,
+                                          hipStream_t);
+template fsa_status mspace_apply<double>(const double*, const double*, int, int, int, double*, int, hipStream_t);
+template fsa_status mspace_apply<float>(const double*, const double*, int, int, int, float*, int, hipStream_t);
+template fsa_status pcg_init<double>(PcgBlock<double>&, const OpDesc<double>&, const double*, double, Scratch&,
+                                     hipStream_t);
+template fsa_status pcg_init<float>(PcgBlock<float>&, const OpDesc<float>&, const double*, double, Scratch&,
+                                    hipStream_t);
+template fsa_status pcg_iter<double>(PcgBlock<double>&, const OpDesc<double>&, double, int, Scratch&, hipStream_t);
+template fsa_status pcg_iter<float>(PcgBlock<float>&, const OpDesc<float>&, double, int, Scratch&, hipStream_t);
+template fsa_status copy_block<double, double>(const double*, int, double*, int, int64_t, int, hipStream_t);
+template fsa_status copy_block<double, float>(const double*, int, float*, int, int64_t, int, hipStream_t);
+template fsa_status copy_block<float, double>(const float*, int, double*, int, int64_t, int, hipStream_t);
+
+}  // namespace fsa

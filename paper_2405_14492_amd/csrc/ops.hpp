@@ -1,0 +1,110 @@
+// Launchers of the FSA operations (float64 or float32 element type T).
+#pragma once
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fsa {
+
+// Scratch for split reductions, grown on demand.
+struct Scratch {
+  Buf<double> dot;   // per-workgroup column partials
+  Buf<double> dot2;
+  Buf<char> part;    // reduce-GEMM partial tiles
+  Buf<double> w;     // reduced m-space block (kdim x ldw)
+};
+
+// ---- build-time contractions (float64) ----
+// A_out[i][k] = sum_j G[j][k] c(x_i, ind_j)   (G = L_m^{-T}: whitening)
+// mode 1: K = 2 mp, row = [dc/drho(x_i, ind_j) | c(x_i, ind_j)] (derivative factor F)
+fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th, const double* G,
+                  int mode, double* A_out, hipStream_t st);
+// Residual values of a taper pattern (rows of grid rg, columns of grid cg):
+// v = (c(d) - Xr_p . Yc_q) W(d/gamma) (+ s2 on the self diagonal, D[p] = v_pp).
+// deriv: v = (dc/drho(d) - [F|A]_p . [A|F]_q) W(d/gamma).
+fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const double* Xr, const double* Yc,
+                           const double* Fr, const double* Fc, int mp, const Theta& th, double gamma, bool self,
+                           bool deriv, double* vals, double* D, hipStream_t st);
+// C = I + A D^{-1} A^T (mp x mp float64)
+fsa_status capacitance(const double* A, const double* D, int64_t n, int mp, double* C, Scratch& s, hipStream_t st);
+
+// ---- block operations on n x ld point-major blocks ----
+// W (float64, kdim x ldw) = A^T-side reduction sum_i A_i^T X_i with X = src / D (scale_by_dinv)
+template <typename T>
+fsa_status lowrank_reduce(const T* A, int64_t n, int kdim, const T* X, int ldx, int ncols, const double* Dinv_src,
+                          Scratch& s, double* W, int ldw, hipStream_t st);
+// OUT = A G (+ beta_out * OUT_prev handled by caller), G row-major kdim x ldg (type T)
+template <typename T>
+fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T* G, int ldg, int ncols, T* OUT,
+                          int ldo, hipStream_t st);
+// Y = S X (+ Y if accumulate) ; S in CSR with values val
+template <typename T>
+fsa_status spmm(const Csr& S, const T* val, const T* X, int ldx, int ncols, T* Y, int ldy, bool accumulate,
+                hipStream_t st);
+// out[c] = sum_p X[p][c] Y[p][c] (float64 result, c < ncols)
+template <typename TX, typename TY>
+fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double* out, Scratch& s, hipStream_t st);
+// G (type T, kdim x ldg) = M (kdim x kdim f64) * W (kdim x ldw f64), columns < ncols
+template <typename T>
+fsa_status mspace_apply(const double* M, const double* W, int ldw, int kdim, int ncols, T* G, int ldg,
+                        hipStream_t st);
+
+// ---- PCG (Algorithm 2) on a block of columns ----
+template <typename T>
+struct PcgBlock {
+  int64_t n = 0;
+  int ncols = 0, ld = 0, ldw = 0;
+  int max_iter = 0;
+  // block vectors (n x ld)
+  T *R = nullptr, *H = nullptr, *V = nullptr, *P = nullptr, *Tt = nullptr, *Q0 = nullptr;
+  double* U = nullptr;  // solution accumulator (float64)
+  // per column
+  double *rz = nullptr, *rz0 = nullptr, *alpha = nullptr, *beta = nullptr, *rr = nullptr, *bn2 = nullptr;
+  int *active = nullptr, *iters = nullptr, *flags = nullptr;  // flags[0] = #active, flags[1] = breakdown
+  double *alpha_hist = nullptr, *beta_hist = nullptr;
+  T* g = nullptr;  // m-space block in T (kdim x ldw)
+};
+
+// Operator description: sparse part (CSR values valT, diagonal D) plus an
+// optional low-rank part A (point-major n x kdim) with Woodbury capacitance
+// inverse Cinv (kdim x kdim f64); kdim == 0 gives the sparse operator with
+// the diagonal preconditioner.
+template <typename T>
+struct OpDesc {
+  const Csr* S = nullptr;
+  const T* val = nullptr;
+  const double* D = nullptr;
+  const T* A = nullptr;
+  int kdim = 0;
+  const double* Cinv = nullptr;
+};
+
+// Initialise: R = B, U = 0, Q0 = H = P^{-1} R, P = A^T A H, rz = r^T q.
+template <typename T>
+fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double tol, Scratch& s, hipStream_t st);
+// One iteration on all active columns; the Lanczos coefficients of the
+// iteration are appended to alpha_hist/beta_hist.
+template <typename T>
+fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, Scratch& s, hipStream_t st);
+// Replace R by B - A_op U with the float64 operator (mixed precision).
+fsa_status pcg_replace_residual_f32(PcgBlock<float>& b, const OpDesc<double>& op64, const OpDesc<float>& op32,
+                                    const double* B, Scratch& s, hipStream_t st);
+
+// out[c] = w_c e_1^T log(T_c) e_1 for c in [c_first, ncols) (tridiagonal QL)
+fsa_status slq_terms(const double* alpha_hist, const double* beta_hist, const int* iters, int ncols, int c_first,
+                     const double* weight, double* out, double* scratch, int max_iter, hipStream_t st);
+
+// B[:,0] = y, B[:,1+i] = sqrt(D) rho_i + A^T e_i  (probe block, Section 3.3 / App. F)
+fsa_status make_probes(const double* A, int64_t n, int m, int mp, const double* D, const double* y, const int* perm,
+                       uint64_t seed, int nprobe, double* B, int ldb, double* Emat, hipStream_t st);
+
+// elementwise helpers
+template <typename TI, typename TO>
+fsa_status copy_block(const TI* in, int ldi, TO* out, int ldo, int64_t n, int ncols, hipStream_t st);
+fsa_status permute_rows(const double* in, int ldi, double* out, int ldo, const int* idx, int64_t n, int ncols,
+                        hipStream_t st);  // out[p] = in[idx[p]]
+fsa_status scale_rows(double* X, int ld, const double* D, int64_t n, int ncols, int invert, hipStream_t st);
+fsa_status scal_block(double* X, int ld, int64_t n, int ncols, double a, hipStream_t st);
+fsa_status axpy_block(const double* X, double a, double* Y, int ld, int64_t n, int ncols, hipStream_t st);
+
+}  // namespace fsa

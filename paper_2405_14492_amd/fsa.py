@@ -1,0 +1,289 @@
+"""Thin ctypes binding of libfsa.so (the C ABI declared in include/fsa.h).
+
+Only argument marshalling lives here: every numerical step runs in the HIP
+kernels of the library.  The library must have been built
+(`python -m paper_2405_14492_amd.build`); importing this module without it
+raises ImportError -- there is no CPU fallback.
+
+Covariance parameters are passed as a tuple (cov, sigma1_sq, rho, sigma_sq)
+with cov = EXPONENTIAL (0) or MATERN32 (1).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+EXPONENTIAL = 0
+MATERN32 = 1
+FP64 = 0
+MIXED_FP32 = 1
+
+OP_SIGMA_DAGGER, OP_SIGMA_S, OP_P_INV, OP_D_SIGMA1, OP_D_RHO, OP_PROBES = range(6)
+
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "NOT_SPD", 4: "NOT_CONVERGED", 5: "BREAKDOWN", 6: "DEVICE"}
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfsa.so")
+
+EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad", "fsa_predict_var", "fsa_destroy",
+            "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_apply", "fsa_pool_trim"]
+
+
+class FsaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class NotConverged(FsaError):
+    pass
+
+
+class fsa_theta(C.Structure):
+    _fields_ = [("cov", C.c_int32), ("sigma1_sq", C.c_double), ("rho", C.c_double), ("sigma_sq", C.c_double)]
+
+
+class fsa_options(C.Structure):
+    _fields_ = [("num_probes", C.c_int32), ("seed", C.c_uint64), ("cg_rel_tol", C.c_double),
+                ("max_iter", C.c_int32), ("fixed_iter", C.c_int32), ("precision", C.c_int32),
+                ("rr_period", C.c_int32), ("slq_weight_n", C.c_int32), ("sigma_m_jitter", C.c_double),
+                ("hip_stream", C.c_void_p)]
+
+
+class fsa_stats(C.Structure):
+    _fields_ = [("iters_min", C.c_int32), ("iters_max", C.c_int32), ("probe_iters", C.c_int64),
+                ("rel_res_max", C.c_double), ("logdet", C.c_double), ("logdet_P", C.c_double),
+                ("quad", C.c_double), ("ms_build", C.c_double), ("ms_pcg", C.c_double),
+                ("ms_backward", C.c_double), ("ms_total", C.c_double), ("nnz", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2405_14492_amd.build`")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    dp = P(C.c_double)
+    vp = C.c_void_p
+    lib.fsa_default_options.argtypes = [P(fsa_options)]
+    lib.fsa_default_options.restype = None
+    for name in ("fsa_build", "fsa_build_dev"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, C.c_int64, C.c_int32, vp, P(fsa_theta), vp, C.c_int32, C.c_double, P(fsa_options),
+                      P(vp)]
+        f.restype = C.c_int
+    lib.fsa_nll_grad.argtypes = [vp, P(fsa_theta), dp, dp, P(fsa_stats)]
+    lib.fsa_nll_grad.restype = C.c_int
+    lib.fsa_predict_var.argtypes = [vp, dp, C.c_int64, C.c_int32, dp, dp, P(fsa_stats)]
+    lib.fsa_predict_var.restype = C.c_int
+    lib.fsa_destroy.argtypes = [vp]
+    lib.fsa_destroy.restype = None
+    lib.fsa_last_error.argtypes = []
+    lib.fsa_last_error.restype = C.c_char_p
+    lib.fsa_nnz.argtypes = [vp]
+    lib.fsa_nnz.restype = C.c_int64
+    lib.fsa_export_csr.argtypes = [vp, P(C.c_int64), P(C.c_int32), dp]
+    lib.fsa_export_csr.restype = C.c_int
+    lib.fsa_export_diag.argtypes = [vp, dp, dp]
+    lib.fsa_export_diag.restype = C.c_int
+    lib.fsa_apply.argtypes = [vp, C.c_int32, dp, dp, C.c_int32]
+    lib.fsa_apply.restype = C.c_int
+    lib.fsa_pool_trim.argtypes = []
+    lib.fsa_pool_trim.restype = None
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _check(status: int, allow_not_converged: bool = False):
+    if status == 0:
+        return
+    msg = lib().fsa_last_error().decode()
+    if status == 4:
+        if allow_not_converged:
+            return
+        raise NotConverged(status, msg)
+    raise FsaError(status, msg)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_theta(theta) -> fsa_theta:
+    cov, s1, rho, s2 = theta
+    return fsa_theta(int(cov), float(s1), float(rho), float(s2))
+
+
+def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, precision=FP64, rr_period=10,
+                 slq_weight_n=False, jitter=0.0, stream=None) -> fsa_options:
+    o = fsa_options()
+    lib().fsa_default_options(C.byref(o))
+    o.num_probes = int(num_probes)
+    o.seed = int(seed)
+    o.cg_rel_tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.fixed_iter = int(fixed_iter)
+    o.precision = int(precision)
+    o.rr_period = int(rr_period)
+    o.slq_weight_n = int(bool(slq_weight_n))
+    o.sigma_m_jitter = float(jitter)
+    o.hip_stream = stream
+    return o
+
+
+# ---------------------------------------------------------------- C names
+def fsa_build(locs, y, theta, inducing, taper_range, opt: fsa_options | None = None) -> C.c_void_p:
+    """Host arrays in; returns the context handle."""
+    locs, y, ind = _f64(locs), _f64(y), _f64(inducing)
+    ctx = C.c_void_p()
+    th = make_theta(theta)
+    _check(lib().fsa_build(locs.ctypes.data, locs.shape[0], locs.shape[1], y.ctypes.data, C.byref(th),
+                           ind.ctypes.data, ind.shape[0], float(taper_range), C.byref(opt) if opt else None,
+                           C.byref(ctx)))
+    return ctx
+
+
+def fsa_build_dev(locs, y, theta, inducing, taper_range, opt: fsa_options | None = None) -> C.c_void_p:
+    """Device tensors (torch, float64, contiguous, on the GPU) in."""
+    ctx = C.c_void_p()
+    th = make_theta(theta)
+    _check(lib().fsa_build_dev(locs.data_ptr(), locs.shape[0], locs.shape[1], y.data_ptr(), C.byref(th),
+                               inducing.data_ptr(), inducing.shape[0], float(taper_range),
+                               C.byref(opt) if opt else None, C.byref(ctx)))
+    return ctx
+
+
+def fsa_nll_grad(ctx, theta=None, with_grad=True, allow_not_converged=False):
+    nll = C.c_double()
+    g = np.zeros(3)
+    st = fsa_stats()
+    th = make_theta(theta) if theta is not None else None
+    s = lib().fsa_nll_grad(ctx, C.byref(th) if th is not None else None, C.byref(nll),
+                           _dptr(g) if with_grad else None, C.byref(st))
+    _check(s, allow_not_converged)
+    return nll.value, (g if with_grad else None), st.as_dict()
+
+
+def fsa_predict_var(ctx, pred_locs, num_samples, with_mean=False, allow_not_converged=False):
+    P = _f64(pred_locs)
+    var = np.zeros(P.shape[0])
+    mean = np.zeros(P.shape[0]) if with_mean else None
+    st = fsa_stats()
+    s = lib().fsa_predict_var(ctx, _dptr(P), P.shape[0], int(num_samples), _dptr(var),
+                              _dptr(mean) if with_mean else None, C.byref(st))
+    _check(s, allow_not_converged)
+    return var, mean, st.as_dict()
+
+
+def fsa_destroy(ctx):
+    if ctx:
+        lib().fsa_destroy(ctx)
+
+
+def fsa_nnz(ctx) -> int:
+    return int(lib().fsa_nnz(ctx))
+
+
+def fsa_export_csr(ctx, n, with_values=False):
+    nnz = fsa_nnz(ctx)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(nnz, dtype=np.int32)
+    vals = np.zeros(nnz) if with_values else None
+    _check(lib().fsa_export_csr(ctx, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                col.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(vals) if with_values else None))
+    return rp, col, vals
+
+
+def fsa_export_diag(ctx, n):
+    D = np.zeros(n)
+    ld = C.c_double()
+    _check(lib().fsa_export_diag(ctx, _dptr(D), C.byref(ld)))
+    return D, ld.value
+
+
+def fsa_apply(ctx, which, X, ncols=None):
+    if which == OP_PROBES:
+        n = int(X)
+        Y = np.zeros((n, ncols))
+        _check(lib().fsa_apply(ctx, which, None, _dptr(Y), ncols))
+        return Y
+    X = _f64(X)
+    if X.ndim == 1:
+        X = X[:, None]
+    Y = np.zeros_like(X)
+    _check(lib().fsa_apply(ctx, which, _dptr(X), _dptr(Y), X.shape[1]))
+    return Y
+
+
+def fsa_pool_trim():
+    lib().fsa_pool_trim()
+
+
+# ---------------------------------------------------------------- convenience
+class FSA:
+    """Owns one context.  Host numpy inputs (or torch GPU tensors with device=True)."""
+
+    def __init__(self, locs, y, theta, inducing, taper_range, num_probes=50, seed=0, tol=1e-8, max_iter=1000,
+                 fixed_iter=0, precision=FP64, rr_period=10, slq_weight_n=False, jitter=0.0, stream=None,
+                 device=False):
+        self.opt = make_options(num_probes, seed, tol, max_iter, fixed_iter, precision, rr_period, slq_weight_n,
+                                jitter, stream)
+        self.n = int(locs.shape[0])
+        self.theta = tuple(theta)
+        build = fsa_build_dev if device else fsa_build
+        self.ctx = build(locs, y, theta, inducing, taper_range, self.opt)
+
+    def nll_grad(self, theta=None, with_grad=True, allow_not_converged=False):
+        out = fsa_nll_grad(self.ctx, theta, with_grad, allow_not_converged)
+        if theta is not None:
+            self.theta = tuple(theta)
+        return out
+
+    def predict_var(self, pred_locs, num_samples, with_mean=False, allow_not_converged=False):
+        return fsa_predict_var(self.ctx, pred_locs, num_samples, with_mean, allow_not_converged)
+
+    def export_csr(self, with_values=False):
+        return fsa_export_csr(self.ctx, self.n, with_values)
+
+    def export_diag(self):
+        return fsa_export_diag(self.ctx, self.n)
+
+    def apply(self, which, X, ncols=None):
+        return fsa_apply(self.ctx, which, X if which != OP_PROBES else self.n, ncols)
+
+    @property
+    def nnz(self):
+        return fsa_nnz(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            fsa_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,80 @@
+"""The C-ABI library builds, loads and exports every declared symbol; host-side
+argument validation rejects bad inputs before any device work (no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2405_14492_amd import fsa
+    if not os.path.exists(fsa.LIB_PATH):
+        from paper_2405_14492_amd import build
+        build.build(verbose=False)
+    return fsa.load_library()
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fsa.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:fsa_status|void|int64_t|const char\*)\s*(fsa_\w+)\s*\(", src, re.M)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_symbols()
+    assert len(names) >= 12
+    for nm in names:
+        assert hasattr(L, nm), nm
+    from paper_2405_14492_amd import fsa
+    assert set(fsa.EXPORTED) == set(names)
+
+
+def test_struct_layouts(L):
+    from paper_2405_14492_amd import fsa
+    # fsa_options: int32, (pad) uint64, double, 5 x int32, (pad) double, void*
+    assert ctypes.sizeof(fsa.fsa_options) == 64
+    assert ctypes.sizeof(fsa.fsa_theta) == 32
+    o = fsa.fsa_options()
+    L.fsa_default_options(ctypes.byref(o))
+    assert o.num_probes == 50 and o.cg_rel_tol == 1e-8 and o.max_iter == 1000 and o.precision == 0
+
+
+@pytest.mark.parametrize("case", ["n1", "d3", "m0", "m_gt_n", "gamma0", "sigma2_0", "rho_neg", "cov_bad", "probes0"])
+def test_invalid_arguments_rejected_on_host(L, case):
+    from paper_2405_14492_amd import fsa
+    n, d, m, gamma = 10, 2, 3, 0.1
+    theta = [0, 1.0, 0.1, 0.1]
+    opt = fsa.make_options()
+    if case == "n1":
+        n = 1
+        m = 1
+    elif case == "d3":
+        d = 3
+    elif case == "m0":
+        m = 0
+    elif case == "m_gt_n":
+        m = 11
+    elif case == "gamma0":
+        gamma = 0.0
+    elif case == "sigma2_0":
+        theta[3] = 0.0
+    elif case == "rho_neg":
+        theta[2] = -1.0
+    elif case == "cov_bad":
+        theta[0] = 7
+    elif case == "probes0":
+        opt.num_probes = 0
+    locs = np.zeros((max(n, 1), d))
+    y = np.zeros(max(n, 1))
+    ind = np.zeros((max(m, 1), d))
+    th = fsa.make_theta(theta)
+    ctx = ctypes.c_void_p()
+    s = L.fsa_build(locs.ctypes.data, n, d, y.ctypes.data, ctypes.byref(th), ind.ctypes.data, m, gamma,
+                    ctypes.byref(opt), ctypes.byref(ctx))
+    assert s == 1
+    assert not ctx.value
+    assert len(L.fsa_last_error()) > 0

@@ -1,0 +1,152 @@
+"""GPU path vs the CPU oracle on identical seeded inputs (MI355X only).
+
+Bars: the taper pattern is bit-exact; float64 operators and values agree to
+1e-11 relative; float64 NLL / gradient to 1e-9 relative (identical probes,
+fixed iteration count, or both converged to a tight tolerance)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fsa_oracle as O
+from workloads import configs
+from workloads import generators as G
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2405_14492_amd import fsa
+    fsa.lib()
+    return fsa
+
+
+def case(n=700, m=40, kind=O.EXPONENTIAL, rho=0.1, s1=1.0, s2=0.05, n_gamma=25, seed=0, clustered=False):
+    locs = G.clustered_locations(n, 100 + seed) if clustered else G.uniform_locations(n, 100 + seed)
+    ind = G.random_subset_inducing(locs, m, 200 + seed)
+    gamma = G.taper_range_by_count(locs, n_gamma, sample=min(n, 5000)) if clustered else \
+        G.taper_range_for_uniform(n, n_gamma)
+    y = G.rff_response(locs, kind, s1, rho, s2, 300, 300 + seed)
+    return locs, y, (kind, s1, rho, s2), ind, gamma
+
+
+CASES = {
+    "exp_n700_m40": dict(),
+    "m32_n1500_m100": dict(n=1500, m=100, kind=O.MATERN32, rho=0.05, s2=0.1, n_gamma=40, seed=1),
+    "exp_clustered_n2000_m70": dict(n=2000, m=70, rho=0.2, s1=2.0, s2=0.01, n_gamma=30, seed=2, clustered=True),
+    "ragged_n333_m7": dict(n=333, m=7, kind=O.MATERN32, rho=0.15, n_gamma=12, seed=3),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pattern_bit_exact(F, name):
+    say("case", name)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=2) as f:
+        rp, col, vals = f.export_csr(with_values=True)
+    orp, ocol = O.taper_pattern(locs, locs, gamma)
+    assert np.array_equal(rp, orp)
+    assert np.array_equal(col, ocol)
+
+
+def test_pattern_ties_bit_exact(F):
+    g = np.arange(40) / 64.0
+    locs = np.array([(a, b) for a in g for b in g])
+    gamma = 2.0 / 64.0
+    y = np.ones(locs.shape[0])
+    ind = locs[::97].copy()
+    with F.FSA(locs, y, (O.EXPONENTIAL, 1.0, 0.1, 0.1), ind, gamma, num_probes=2) as f:
+        rp, col, _ = f.export_csr()
+    orp, ocol = O.taper_pattern(locs, locs, gamma)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_values_and_fitc_match_oracle(F, name):
+    say("case", name)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    mdl = O.FSA(locs, ind, theta, gamma)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=2) as f:
+        _, _, vals = f.export_csr(with_values=True)
+        D, logdet_P = f.export_diag()
+    scale = np.abs(mdl.vals).max()
+    np.testing.assert_allclose(vals, mdl.vals, rtol=0, atol=1e-11 * scale)
+    np.testing.assert_allclose(D, mdl.D, rtol=1e-11)
+    assert abs(logdet_P - mdl.logdet_P) <= 1e-11 * abs(mdl.logdet_P) + 1e-9
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_operators_match_oracle(F, name):
+    say("case", name)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    mdl = O.FSA(locs, ind, theta, gamma)
+    X = np.random.default_rng(5).standard_normal((locs.shape[0], 5))
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=3, seed=11) as f:
+        got = {
+            "sigma": f.apply(F.OP_SIGMA_DAGGER, X),
+            "sparse": f.apply(F.OP_SIGMA_S, X),
+            "pinv": f.apply(F.OP_P_INV, X),
+            "dsigma1": f.apply(F.OP_D_SIGMA1, X),
+            "drho": f.apply(F.OP_D_RHO, X),
+            "probes": f.apply(F.OP_PROBES, None, ncols=3),
+        }
+    ref = {
+        "sigma": mdl.matvec(X),
+        "sparse": mdl.sparse_matvec(X),
+        "pinv": mdl.precond_solve(X),
+        "dsigma1": mdl.dmatvec(0, X),
+        "drho": mdl.dmatvec(1, X),
+        "probes": O.probes(mdl, 3, 11),
+    }
+    for k in ref:
+        err = np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max()
+        say(k, err)
+        assert err < 1e-10, (k, err)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_nll_grad_fixed_iterations_match_oracle(F, name):
+    say("case", name)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    mdl = O.FSA(locs, ind, theta, gamma)
+    t, k = 6, 15
+    ref = O.nll_grad(mdl, y, t, 77, fixed_iter=k)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=t, seed=77, fixed_iter=k) as f:
+        nll, grad, st = f.nll_grad()
+    say("nll", nll, ref["nll"], "grad", grad, ref["grad"])
+    assert abs(nll - ref["nll"]) <= 1e-9 * abs(ref["nll"])
+    gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
+    assert np.all(np.abs(grad - ref["grad"]) <= 1e-9 * gscale + 1e-12), (grad, ref["grad"])
+    assert st["iters_min"] == k and st["iters_max"] == k
+
+
+@pytest.mark.parametrize("name", ["exp_n700_m40", "m32_n1500_m100"])
+def test_nll_converged_matches_oracle(F, name):
+    say("case", name)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    mdl = O.FSA(locs, ind, theta, gamma)
+    ref = O.nll_grad(mdl, y, 8, 5, tol=1e-11, max_iter=2000)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=8, seed=5, tol=1e-11, max_iter=2000) as f:
+        nll, grad, st = f.nll_grad()
+    say("iters", st["iters_min"], st["iters_max"], ref["iters"].min(), ref["iters"].max())
+    assert abs(nll - ref["nll"]) <= 1e-9 * abs(ref["nll"])
+    assert abs(st["iters_max"] - ref["iters"].max()) <= 1
+
+
+def test_revalue_same_pattern(F):
+    locs, y, theta, ind, gamma = case(**CASES["exp_n700_m40"])
+    th2 = (theta[0], 1.3, 0.07, 0.2)
+    ref = O.nll_grad(O.FSA(locs, ind, th2, gamma), y, 4, 3, fixed_iter=10)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=4, seed=3, fixed_iter=10) as f:
+        f.nll_grad()
+        nll, grad, _ = f.nll_grad(theta=th2)
+    assert abs(nll - ref["nll"]) <= 1e-9 * abs(ref["nll"])
+    np.testing.assert_allclose(grad, ref["grad"], rtol=1e-8)
