@@ -20,17 +20,20 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------- MFMA 16x16x4
-// Lane l supplies A[l%16][l/16] and B[l/16][l%16]; it receives
-// D[4*(l/16)+r][l%16], r = 0..3.
+// Lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register r of
+// lane l holds D[orow(l/16, r)][l%16] with orow = 4q + r for f32 and
+// q + 4r for f64 (checked on gfx950).
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
   typedef d4 acc;
+  static __device__ __forceinline__ int orow(int q, int r) { return q + 4 * r; }
   static __device__ __forceinline__ acc op(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
 template <> struct Mfma<float> {
   typedef f4 acc;
+  static __device__ __forceinline__ int orow(int q, int r) { return 4 * q + r; }
   static __device__ __forceinline__ acc op(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t nrows, int kdim, cons
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int64_t i = row0 + a * 16 + 4 * q + r;
+        int64_t i = row0 + a * 16 + Mfma<T>::orow(q, r);
         int c = c0 + b * 16 + r16;
         if (i < nrows && c < ncols) dsum[b] += epi(i, c, acc[a][b][r]);
       }
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t nrows, int kdim, cons
 // ------------------------------------------------------------------ reduce GEMM
 // grid: (nchunks, ncb = ceil(ncols/64), ceil(kdim / 512)); block 64*NW.
 // Partial tile layout: part[((chunk*ncb + cb)*nmb + mb)*4096 + (tile*4 + r)*64 + lane]
-// with tile = tau*4 + ct, k = mb*64 + 16*(lane/16) + 4r + tau, c = cb*64 + 4*(lane%16) + ct.
+// with tile = tau*4 + ct, k = mb*64 + 4*orow(lane/16, r) + tau, c = cb*64 + 4*(lane%16) + ct.
 template <typename T, bool DOT, class AOp, class Pro>
 __global__ __launch_bounds__(512) void k_reduce_gemm(int64_t npts, int pts_per_chunk, int kdim, int ncols, AOp acol,
                                                      Pro pro, T* __restrict__ part, double* __restrict__ dot_part,
@@ -214,7 +214,7 @@ __global__ void k_reduce_parts(const T* __restrict__ part, int nchunks, int ncb,
   int mb = (int)(blk % nmb);
   int cb = (int)(blk / nmb);
   int tau = tile >> 2, ct = tile & 3;
-  int k = mb * 64 + 16 * (lane >> 4) + 4 * r + tau;
+  int k = mb * 64 + 4 * Mfma<T>::orow(lane >> 4, r) + tau;
   int c = cb * 64 + 4 * (lane & 15) + ct;
   if (add_identity && k == c) s += 1.0;
   W[(int64_t)k * ldw + c] = s;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_sddmm(const int64_t* __restrict__ rcs, 
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int64_t p = p0 + 4 * q + r;
+      int64_t p = p0 + Mfma<T>::orow(q, r);
       int64_t qq = q0 + r16;
       if (p < re && qq < qend) {
         double dx = rxs[2 * p] - cxs[2 * qq];
