@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the FSA likelihood + gradient step on one MI355X.
+
+Workload (synthetic, seeded): n = 500,000 locations uniform on [0,1]^2,
+Matérn-3/2 (sigma1^2 = 1, rho = 0.05, sigma^2 = 0.1), m = 500 inducing points
+by kmeans++ on a 20k subsample, Wendland taper with ~80 nonzeros per row,
+y from 2,000 random Fourier features plus noise, t = 50 Rademacher probes.
+
+One step = the whole hot path from device-resident inputs: grid binning and
+taper pattern, covariance generation and whitening, residual values,
+FITC capacitance and its Cholesky factor, probes, block PCG with Lanczos
+coefficients, SLQ log-determinant, and the stochastic gradient.
+`value` = PCG probe-iterations executed per second of step time in the
+mixed-precision mode (float32 blocks, float64 inner products, float64
+residual replacement); the float64 run is reported beside it.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+KERNELS = ["sparse_product", "update_and_reduce", "woodbury_expand", "direction_update", "small"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_work(k, n, m, tp, nnz, b):
+    """Algorithmic (bytes, flops) per launch of kernel class k with element
+    size b (block vectors, sparse values and low-rank factor); the solution
+    accumulator is float64 in both modes."""
+    blk = n * tp
+    if k == 0:   # V = S H + P (CSR values+cols, row_ptr, H gathered once, P in, V out)
+        return nnz * (b + 4) + 8 * (n + 1) + 3 * blk * b, 2.0 * nnz * tp
+    if k == 1:   # u += a h, r -= a v (U f64 r/w, H, R r/w, V), D, then A (n x m) reduction
+        return n * m * b + blk * (16 + 4 * b) + 8 * n, 2.0 * n * m * tp
+    if k == 2:   # t = A g, q = (r - t)/D: A, R in, T out, D
+        return n * m * b + 2 * blk * b + 8 * n, 2.0 * n * m * tp
+    if k == 3:   # h = (r - t)/D + beta h, p = t + beta p
+        return 6 * blk * b + 8 * n, 4.0 * blk
+    return 0, 0
+
+
+def run_mode(F, dev, w, precision, steps, warmup, tol, torch):
+    opt = F.make_options(num_probes=w.num_probes, seed=w.seed, tol=tol, max_iter=1000, precision=precision,
+                         rr_period=10, profile=True)
+    theta = w.theta
+
+    def step():
+        ctx = F.fsa_build_dev(dev["locs"], dev["y"], theta, dev["ind"], w.gamma, opt)
+        try:
+            nll, grad, st = F.fsa_nll_grad(ctx, None, True)
+        finally:
+            F.fsa_destroy(ctx)
+        return nll, grad, st
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    probe_iters = sum(o[2]["probe_iters"] for o in outs)
+    kms = np.sum([o[2]["kernel_ms"] for o in outs], axis=0)
+    kcnt = np.sum([o[2]["kernel_launches"] for o in outs], axis=0)
+    pcg_ms = sum(o[2]["ms_pcg"] for o in outs)
+    return {
+        "value": probe_iters / dt,
+        "ms_per_step": 1000.0 * dt / steps,
+        "pcg_only_probe_iters_per_s": probe_iters / (pcg_ms / 1000.0),
+        "probe_iters_per_step": probe_iters / steps,
+        "iters": [outs[-1][2]["iters_min"], outs[-1][2]["iters_max"]],
+        "nll": outs[-1][0],
+        "grad": [float(g) for g in outs[-1][1]],
+        "ms_build": float(np.mean([o[2]["ms_build"] for o in outs])),
+        "ms_pcg": pcg_ms / steps,
+        "ms_backward": float(np.mean([o[2]["ms_backward"] for o in outs])),
+        "nnz": outs[-1][2]["nnz"],
+        "kernel_ms": kms.tolist(),
+        "kernel_launches": kcnt.tolist(),
+    }
+
+
+def roofline(res, n, m, tp, precision):
+    b = 4 if precision == "f32" else 8
+    avg = [res["kernel_ms"][k] / max(res["kernel_launches"][k], 1) for k in range(5)]
+    dom = int(np.argmax(res["kernel_ms"][:4]))
+    byt, flop = kernel_work(dom, n, m, tp, res["nnz"], b)
+    t_s = avg[dom] / 1000.0
+    gbs = byt / t_s / 1e9
+    tfl = flop / t_s / 1e12
+    peak_t = PEAK_TFLOPS[precision]
+    t_hbm = byt / (HBM_PEAK_GBS * 1e9)
+    t_cmp = flop / (peak_t * 1e12)
+    if t_cmp > t_hbm:
+        r = {"bound": "mfma", "achieved": tfl, "peak": peak_t, "unit": "TFLOP/s", "frac": tfl / peak_t}
+    else:
+        r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    r.update({"kernel": KERNELS[dom], "avg_launch_ms": avg[dom], "algorithmic_bytes": byt,
+              "algorithmic_flops": flop, "achieved_GBps": gbs, "achieved_TFLOPs": tfl, "traffic": None,
+              "per_kernel_avg_ms": dict(zip(KERNELS, avg))})
+    return r
+
+
+def cpu_baseline(w, sample_n, iters):
+    """The oracle on a spatial window of the same workload (same density,
+    taper range, covariance and all m inducing points), `iters` PCG
+    iterations on t+1 columns; the rate is scaled by sample_n / n to the
+    full size (per-iteration cost is linear in n at fixed m and n_gamma)."""
+    from oracle import fsa_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        blas_threads = os.cpu_count() or 1
+    a = math.sqrt(sample_n / w.n)
+    sel = (w.locs[:, 0] < a) & (w.locs[:, 1] < a)
+    locs = w.locs[sel]
+    y = w.y[sel]
+    ns = locs.shape[0]
+    t0 = time.perf_counter()
+    mdl = O.FSA(locs, w.inducing, w.theta, w.gamma)
+    t1 = time.perf_counter()
+    Z = O.probes(mdl, w.num_probes, w.seed)
+    B = np.column_stack([y, Z])
+    t2 = time.perf_counter()
+    O.pcg_lanczos(mdl.matvec, mdl.precond_solve, B, 0.0, iters, fixed_iter=iters)
+    t3 = time.perf_counter()
+    rate = B.shape[1] * iters / (t3 - t2)
+    return {"value": rate * ns / w.n, "unit": "probe-iters/s", "cores": int(blas_threads), "kind": "oracle",
+            "sample": (f"oracle PCG, {iters} iterations x {B.shape[1]} columns on the {ns}-point window "
+                       f"[0,{a:.4f}]^2 of the same workload (all {w.m} inducing points, same gamma); rate "
+                       f"{rate:.2f} probe-iters/s at n={ns} scaled by {ns}/{w.n}; oracle build "
+                       f"{t1 - t0:.1f} s not included"),
+            "host_cores_visible": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=500_000)
+    ap.add_argument("--m", type=int, default=500)
+    ap.add_argument("--probes", type=int, default=50)
+    ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--cpu-sample-n", type=int, default=40_000)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for hardware-counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path does not shard "
+              f"across GPUs in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2405_14492_amd import fsa as F
+    from workloads import configs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    F.lib()
+    log(f"generating inputs n={args.n} m={args.m} t={args.probes}")
+    t0 = time.perf_counter()
+    w = configs.large_matern(n=args.n, m=args.m, t=args.probes)
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s; gamma={w.gamma:.6g}")
+    dev = {"locs": torch.from_numpy(w.locs).cuda(), "y": torch.from_numpy(w.y).cuda(),
+           "ind": torch.from_numpy(w.inducing).cuda()}
+    torch.cuda.synchronize()
+    if args.copy_calibration_mib:
+        src = torch.empty(args.copy_calibration_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
+    results = {}
+    for mode in args.modes.split(","):
+        prec = F.MIXED_FP32 if mode == "mixed" else F.FP64
+        tol = 1e-6 if mode == "mixed" else 1e-8
+        log(f"mode {mode}: warmup {args.warmup}, steps {args.steps}")
+        results[mode] = run_mode(F, dev, w, prec, args.steps, args.warmup, tol, torch)
+        log(f"mode {mode}: {results[mode]['value']:.1f} probe-iters/s, {results[mode]['ms_per_step']:.2f} ms/step, "
+            f"iters {results[mode]['iters']}, kernel ms/launch "
+            f"{[round(a / max(b, 1), 4) for a, b in zip(results[mode]['kernel_ms'], results[mode]['kernel_launches'])]}")
+    main_mode = "mixed" if "mixed" in results else list(results)[0]
+    r = results[main_mode]
+    dtype = "f32" if main_mode == "mixed" else "f64"
+    out = {
+        "metric": "PCG probe-iters/s at n=500k,m=500,t=50 (mixed precision; fp64 beside it)",
+        "value": r["value"],
+        "unit": "probe-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"fsa_nll_grad n={args.n} m={args.m} t={args.probes} matern32 "
+                               f"rho=0.05 sigma2=0.1 n_gamma=80 tol={'1e-6' if main_mode == 'mixed' else '1e-8'}",
+                   "n": args.n, "m": args.m, "t": args.probes, "gamma": w.gamma, "nnz": r["nnz"]},
+        "roofline": roofline(r, args.n, args.m, args.probes + 1, dtype),
+        "pcg_only_probe_iters_per_s": r["pcg_only_probe_iters_per_s"],
+        "modes": results,
+    }
+    if "fp64" in results and "mixed" in results:
+        out["mixed_over_fp64"] = results["mixed"]["value"] / results["fp64"]["value"]
+        out["mixed_vs_fp64_rel_nll"] = abs(results["mixed"]["nll"] - results["fp64"]["nll"]) / abs(results["fp64"]["nll"])
+        out["roofline_fp64"] = roofline(results["fp64"], args.n, args.m, args.probes + 1, "f64")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_n, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

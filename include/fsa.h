@@ -82,6 +82,7 @@ typedef struct {
   int32_t precision;     /* fsa_precision */
   int32_t rr_period;     /* mixed precision: float64 residual replacement period (0 = never) */
   int32_t slq_weight_n;  /* 0: SLQ weight z^T P^{-1} z; 1: the weight n of Section 3.1 */
+  int32_t profile;       /* 1: time every PCG kernel launch with HIP events (fsa_stats.kernel_ms) */
   double sigma_m_jitter; /* adds jitter * sigma1^2 to the diagonal of Sigma_m (default 0) */
   void* hip_stream;      /* hipStream_t to run on, or NULL for the default stream */
 } fsa_options;
@@ -95,6 +96,12 @@ typedef struct {
   double quad;                  /* y^T Sigma~_dagger^{-1} y */
   double ms_build, ms_pcg, ms_backward, ms_total;
   int64_t nnz;                  /* nonzeros of the tapered residual */
+  /* with options.profile: summed device time and launch count of the PCG
+   * kernels: [0] sparse product Sigma~_s H, [1] fused update + A D^{-1} r
+   * reduction, [2] Woodbury expansion A^T g, [3] search-direction update,
+   * [4] small reductions and m-space products */
+  double kernel_ms[5];
+  int32_t kernel_launches[5];
 } fsa_stats;
 
 /* Default options: 50 probes, seed 0, tol 1e-8, max_iter 1000, FP64. */

@@ -187,6 +187,7 @@ struct fsa_ctx {
   // gradient
   Buf<double> F, dvals, Xb, SX, DX, tmp, G2, dSm, Ework;
   Scratch scr;
+  KernelTimer timer;
   bool solved = false;
   double last_logdet_P = 0;
   // last statistics
@@ -472,6 +473,9 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   }
   const double tol = c->opt.cg_rel_tol;
   const int fixed = c->opt.fixed_iter > 0 ? 1 : 0;
+  c->timer.on = c->opt.profile != 0;
+  c->timer.reset();
+  b.timer = c->timer.on ? &c->timer : nullptr;
   double t0 = now_ms();
   FSA_TRY(pcg_init<T>(b, op, c->B.p, tol, c->scr, st));
   int flags[2] = {0, 0};
@@ -497,6 +501,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   *ms_pcg = now_ms() - t0;
+  if (c->timer.on) c->timer.collect(c->stats.kernel_ms, c->stats.kernel_launches);
   // iteration statistics
   std::vector<int> iters(tp);
   FSA_HIP(hipMemcpy(iters.data(), b.iters, tp * sizeof(int), hipMemcpyDeviceToHost));

@@ -351,6 +351,10 @@ fsa_status mspace_apply(const double* M, const double* W, int ldw, int kdim, int
 }
 
 // ================================================================ PCG (Algorithm 2)
+#define KT_BEGIN(b) int _kt = (b).timer ? (b).timer->start(st) : -1
+#define KT_END(b, cls) \
+  if ((b).timer) (b).timer->stop((cls), _kt, st)
+
 // Pass-1 prologue of an iteration: u += alpha h, r -= alpha v, |r|^2, X = r / D.
 template <typename T>
 struct PcgPass1Pro {
@@ -556,15 +560,21 @@ template <typename T>
 static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int init, Scratch& s, int& nparts_rq,
                                        hipStream_t st) {
   // m-space: g = Cinv (A D^{-1} r), then q = (r - A^T g)/D
-  FSA_TRY(mspace_apply<T>(op.Cinv, s.w.p, b.ldw, op.kdim, b.ncols, b.g, b.ldw, st));
+  {
+    KT_BEGIN(b);
+    FSA_TRY(mspace_apply<T>(op.Cinv, s.w.p, b.ldw, op.kdim, b.ncols, b.g, b.ldw, st));
+    KT_END(b, KT_SMALL);
+  }
   PcgPass2Epi<T> epi{b.Tt, b.R, op.D, b.H, b.P, b.Q0, b.ld, init};
   RowsOp<T> aop{op.A, op.kdim};
   int64_t gx = rows_grid(b.n);
   int ncb = (int)ceil_div(b.ncols, 64);
   size_t need = (size_t)gx * ncb * 64;
   if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
+  KT_BEGIN(b);
   hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, true, RowsOp<T>, PcgPass2Epi<T>>), dim3(gx, ncb), dim3(256), 0, st, b.n,
                      op.kdim, b.g, b.ldw, b.ncols, 0, aop, epi, s.dot.p, ncb * 64);
+  KT_END(b, KT_PASS2);
   FSA_HIP(hipGetLastError());
   nparts_rq = (int)gx;
   return FSA_OK;
@@ -623,10 +633,16 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     int64_t g = spmm_grid(b.n);
     size_t need = (size_t)g * ldd;
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
-    hipLaunchKernelGGL((k_spmm<T, true, PcgSpmmEpi<T>>), dim3(g, ncb), dim3(256), 0, st, b.n, op.S->row_ptr.p,
-                       op.S->col.p, op.val, b.H, b.ld, b.ncols, epi, s.dot.p, ldd);
+    {
+      KT_BEGIN(b);
+      hipLaunchKernelGGL((k_spmm<T, true, PcgSpmmEpi<T>>), dim3(g, ncb), dim3(256), 0, st, b.n, op.S->row_ptr.p,
+                         op.S->col.p, op.val, b.H, b.ld, b.ncols, epi, s.dot.p, ldd);
+      KT_END(b, KT_SPMM);
+    }
+    KT_BEGIN(b);
     hipLaunchKernelGGL(k_pcg_alpha, dim3(ceil_div(b.ncols, 64)), dim3(64), 0, st, b.ncols, s.dot.p, (int)g, ldd, b.rz,
                        b.active, b.alpha, b.flags);
+    KT_END(b, KT_SMALL);
     FSA_HIP(hipGetLastError());
   }
   int nparts_rq = 0, nparts_rr = 0;
@@ -636,11 +652,19 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     FSA_TRY(ensure_part<T>(s, r));
     PcgPass1Pro<T> pro{b.U, b.H, b.R, b.V, op.D, b.alpha, b.ld, 1};
     RowsOp<T> acol{op.A, op.kdim};
-    hipLaunchKernelGGL((k_reduce_gemm<T, true, RowsOp<T>, PcgPass1Pro<T>>), dim3(r.nchunks, r.ncb, r.zb),
-                       dim3(r.threads), 0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, s.dot2.p, ldd);
+    {
+      KT_BEGIN(b);
+      hipLaunchKernelGGL((k_reduce_gemm<T, true, RowsOp<T>, PcgPass1Pro<T>>), dim3(r.nchunks, r.ncb, r.zb),
+                         dim3(r.threads), 0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, s.dot2.p, ldd);
+      KT_END(b, KT_PASS1);
+    }
     FSA_HIP(hipGetLastError());
     nparts_rr = r.nchunks;
-    FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
+    {
+      KT_BEGIN(b);
+      FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
+      KT_END(b, KT_SMALL);
+    }
     // 3. g = Cinv W; t = A^T g; q = (r - t)/D; r^T q
     FSA_TRY(pcg_precond_and_dots<T>(b, op, 0, s, nparts_rq, st));
   } else {
@@ -651,13 +675,19 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     nparts_rq = nparts_rr = (int)g;
   }
   // 4. beta, Lanczos entries, convergence
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, st, b.ncols, s.dot.p, nparts_rq, ldd, s.dot2.p, nparts_rr, ldd,
-                     b.rz, b.alpha, b.beta, b.active, b.iters, b.alpha_hist, b.beta_hist, b.bn2, tol * tol, fixed,
-                     b.max_iter, b.flags);
+  {
+    KT_BEGIN(b);
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, st, b.ncols, s.dot.p, nparts_rq, ldd, s.dot2.p, nparts_rr,
+                       ldd, b.rz, b.alpha, b.beta, b.active, b.iters, b.alpha_hist, b.beta_hist, b.bn2, tol * tol,
+                       fixed, b.max_iter, b.flags);
+    KT_END(b, KT_SMALL);
+  }
   // 5. h = q + beta h, p = t + beta p
   int64_t tot = b.n * b.ncols;
+  KT_BEGIN(b);
   hipLaunchKernelGGL(k_pcg_hupdate<T>, dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld,
                      (const T*)b.R, (const T*)b.Tt, op.D, b.beta, b.H, b.P, lr ? 1 : 0);
+  KT_END(b, KT_UPDATE);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }

@@ -14,6 +14,52 @@ struct Scratch {
   Buf<double> w;     // reduced m-space block (kdim x ldw)
 };
 
+// HIP-event timing of kernel classes on one stream (enabled per context).
+struct KernelTimer {
+  static constexpr int NCLS = 5;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<int> cls;
+  void reset() { used = 0; cls.clear(); }
+  int start(hipStream_t st) {
+    if (!on) return -1;
+    if (used + 2 > pool.size()) {
+      for (int k = 0; k < 256; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        pool.push_back(e);
+      }
+    }
+    int i = (int)used;
+    used += 2;
+    (void)hipEventRecord(pool[i], st);
+    return i;
+  }
+  void stop(int k, int i, hipStream_t st) {
+    if (i < 0) return;
+    (void)hipEventRecord(pool[i + 1], st);
+    if ((int)cls.size() <= i / 2) cls.resize(i / 2 + 1, -1);
+    cls[i / 2] = k;
+  }
+  // after the stream has drained
+  void collect(double* ms, int* cnt) {
+    for (size_t j = 0; j < cls.size(); ++j) {
+      if (cls[j] < 0) continue;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pool[2 * j], pool[2 * j + 1]) == hipSuccess) {
+        ms[cls[j]] += t;
+        cnt[cls[j]] += 1;
+      }
+    }
+    reset();
+  }
+  ~KernelTimer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+enum { KT_SPMM = 0, KT_PASS1 = 1, KT_PASS2 = 2, KT_UPDATE = 3, KT_SMALL = 4 };
+
 // ---- build-time contractions (float64) ----
 // A_out[i][k] = sum_j G[j][k] c(x_i, ind_j)   (G = L_m^{-T}: whitening)
 // mode 1: K = 2 mp, row = [dc/drho(x_i, ind_j) | c(x_i, ind_j)] (derivative factor F)
@@ -63,6 +109,7 @@ struct PcgBlock {
   int *active = nullptr, *iters = nullptr, *flags = nullptr;  // flags[0] = #active, flags[1] = breakdown
   double *alpha_hist = nullptr, *beta_hist = nullptr;
   T* g = nullptr;  // m-space block in T (kdim x ldw)
+  KernelTimer* timer = nullptr;
 };
 
 // Operator description: sparse part (CSR values valT, diagonal D) plus an

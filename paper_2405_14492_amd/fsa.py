@@ -47,7 +47,8 @@ class fsa_theta(C.Structure):
 class fsa_options(C.Structure):
     _fields_ = [("num_probes", C.c_int32), ("seed", C.c_uint64), ("cg_rel_tol", C.c_double),
                 ("max_iter", C.c_int32), ("fixed_iter", C.c_int32), ("precision", C.c_int32),
-                ("rr_period", C.c_int32), ("slq_weight_n", C.c_int32), ("sigma_m_jitter", C.c_double),
+                ("rr_period", C.c_int32), ("slq_weight_n", C.c_int32), ("profile", C.c_int32),
+                ("sigma_m_jitter", C.c_double),
                 ("hip_stream", C.c_void_p)]
 
 
@@ -55,10 +56,14 @@ class fsa_stats(C.Structure):
     _fields_ = [("iters_min", C.c_int32), ("iters_max", C.c_int32), ("probe_iters", C.c_int64),
                 ("rel_res_max", C.c_double), ("logdet", C.c_double), ("logdet_P", C.c_double),
                 ("quad", C.c_double), ("ms_build", C.c_double), ("ms_pcg", C.c_double),
-                ("ms_backward", C.c_double), ("ms_total", C.c_double), ("nnz", C.c_int64)]
+                ("ms_backward", C.c_double), ("ms_total", C.c_double), ("nnz", C.c_int64),
+                ("kernel_ms", C.c_double * 5), ("kernel_launches", C.c_int32 * 5)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["kernel_ms"] = list(self.kernel_ms)
+        d["kernel_launches"] = list(self.kernel_launches)
+        return d
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -131,7 +136,7 @@ def make_theta(theta) -> fsa_theta:
 
 
 def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, precision=FP64, rr_period=10,
-                 slq_weight_n=False, jitter=0.0, stream=None) -> fsa_options:
+                 slq_weight_n=False, jitter=0.0, stream=None, profile=False) -> fsa_options:
     o = fsa_options()
     lib().fsa_default_options(C.byref(o))
     o.num_probes = int(num_probes)
@@ -144,6 +149,7 @@ def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, p
     o.slq_weight_n = int(bool(slq_weight_n))
     o.sigma_m_jitter = float(jitter)
     o.hip_stream = stream
+    o.profile = int(bool(profile))
     return o
 
 
@@ -241,9 +247,9 @@ class FSA:
 
     def __init__(self, locs, y, theta, inducing, taper_range, num_probes=50, seed=0, tol=1e-8, max_iter=1000,
                  fixed_iter=0, precision=FP64, rr_period=10, slq_weight_n=False, jitter=0.0, stream=None,
-                 device=False):
+                 device=False, profile=False):
         self.opt = make_options(num_probes, seed, tol, max_iter, fixed_iter, precision, rr_period, slq_weight_n,
-                                jitter, stream)
+                                jitter, stream, profile)
         self.n = int(locs.shape[0])
         self.theta = tuple(theta)
         build = fsa_build_dev if device else fsa_build

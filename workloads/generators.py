@@ -10,6 +10,7 @@ number of nonzeros per row).
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 
@@ -68,21 +69,23 @@ def kmeanspp_inducing(locs: np.ndarray, m: int, seed: int, subsample: int = 2000
         d2 = np.minimum(d2, np.sum((pts - centres[c]) ** 2, axis=1))
     assign = None
     for _ in range(lloyd_iters):
-        dist = ((pts[:, None, :] - centres[None, :, :]) ** 2).sum(-1) if k * m <= 4_000_000 else None
-        if dist is None:
-            new = np.empty(k, dtype=np.int64)
-            for s in range(0, k, 2000):
-                blk = pts[s:s + 2000]
-                new[s:s + 2000] = ((blk[:, None, :] - centres[None, :, :]) ** 2).sum(-1).argmin(1)
-        else:
-            new = dist.argmin(1)
+        new = np.empty(k, dtype=np.int64)
+
+        def nearest(s):
+            blk = pts[s:s + 2048]
+            d2 = (blk[:, 0:1] - centres[None, :, 0]) ** 2 + (blk[:, 1:2] - centres[None, :, 1]) ** 2
+            new[s:s + 2048] = d2.argmin(1)
+
+        _parallel(nearest, range(0, k, 2048))
         if assign is not None and np.array_equal(new, assign):
             break
         assign = new
-        for c in range(m):
-            sel = pts[assign == c]
-            if sel.shape[0]:
-                centres[c] = sel.mean(0)
+        cnt = np.bincount(assign, minlength=m)
+        sx = np.bincount(assign, weights=pts[:, 0], minlength=m)
+        sy = np.bincount(assign, weights=pts[:, 1], minlength=m)
+        nz = cnt > 0
+        centres[nz, 0] = sx[nz] / cnt[nz]
+        centres[nz, 1] = sy[nz] / cnt[nz]
     return np.ascontiguousarray(centres)
 
 
@@ -102,11 +105,24 @@ def rff_response(locs: np.ndarray, kind: int, sigma1_sq: float, rho: float, sigm
     w = g * (np.sqrt(2 * nu / u) / rho)[:, None]
     b = rng.uniform(0, 2 * np.pi, n_features)
     y = np.empty(locs.shape[0])
-    for s in range(0, locs.shape[0], 50000):
-        blk = locs[s:s + 50000]
-        y[s:s + 50000] = math.sqrt(2 * sigma1_sq / n_features) * np.cos(blk @ w.T + b).sum(1)
+    amp = math.sqrt(2 * sigma1_sq / n_features)
+
+    def chunk(s):
+        blk = locs[s:s + 8192]
+        y[s:s + 8192] = amp * np.cos(blk @ w.T + b).sum(1)
+
+    _parallel(chunk, range(0, locs.shape[0], 8192))
     y += math.sqrt(sigma_sq) * rng.standard_normal(locs.shape[0])
     return y
+
+
+def _parallel(fn, items):
+    """Run fn over items on a thread pool (numpy releases the GIL); the
+    result does not depend on the number of threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    nt = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(fn, items))
 
 
 def mean_neighbours_uniform(n: int, gamma: float) -> float:
