@@ -36,72 +36,155 @@ fsa_status dense_sigma_m(const double* ind, int m, int mp, const Theta& th, doub
   return FSA_OK;
 }
 
-// Right-looking Cholesky in one workgroup.  The matrix (<= 1024^2 doubles)
-// lives in global memory and stays in L2; a 64-column panel of the current
-// trailing matrix is factored with the pivot column cached in LDS.
+// Blocked right-looking Cholesky in one workgroup (n <= 512, n % 32 == 0).
+// Per 32-column block: factor the diagonal block in LDS, solve the panel
+// below it (one thread per row, panel kept in LDS), then update the trailing
+// lower triangle in 4x4 register tiles.  The matrix stays in L2.
+constexpr int CH_NB = 32;
 __global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int n, int* __restrict__ info) {
-  __shared__ double colk[1024];
+  __shared__ double Dk[CH_NB][CH_NB + 1];
+  __shared__ double P[512 - CH_NB][CH_NB + 1];
   __shared__ int fail;
-  if (threadIdx.x == 0) fail = 0;
+  const int tid = threadIdx.x;
+  if (tid == 0) fail = 0;
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      double a = A[(int64_t)k * n + k];
-      if (!(a > 0.0) || !isfinite(a)) {
-        fail = k + 1;
-        a = 1.0;
+  for (int kb = 0; kb < n; kb += CH_NB) {
+    // 1. diagonal block
+    for (int e = tid; e < CH_NB * CH_NB; e += 1024) {
+      int i = e / CH_NB, j = e % CH_NB;
+      Dk[i][j] = A[(int64_t)(kb + i) * n + kb + j];
+    }
+    __syncthreads();
+    for (int j = 0; j < CH_NB; ++j) {
+      if (tid == 0) {
+        double a = Dk[j][j];
+        if (!(a > 0.0) || !isfinite(a)) {
+          if (!fail) fail = kb + j + 1;
+          a = 1.0;
+        }
+        Dk[j][j] = sqrt(a);
       }
-      A[(int64_t)k * n + k] = sqrt(a);
+      __syncthreads();
+      if (tid > j && tid < CH_NB) Dk[tid][j] /= Dk[j][j];
+      __syncthreads();
+      {
+        int i = tid / CH_NB, k = tid % CH_NB;
+        if (i > j && k > j && k <= i) Dk[i][k] -= Dk[i][j] * Dk[k][j];
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (fail) break;
-    double dkk = A[(int64_t)k * n + k];
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) {
-      double v = A[(int64_t)i * n + k] / dkk;
-      A[(int64_t)i * n + k] = v;
-      colk[i] = v;
+    for (int e = tid; e < CH_NB * CH_NB; e += 1024) {
+      int i = e / CH_NB, j = e % CH_NB;
+      A[(int64_t)(kb + i) * n + kb + j] = j <= i ? Dk[i][j] : 0.0;
+    }
+    // 2. panel rows below: x Dk^T = a  (forward substitution per row)
+    const int r0 = kb + CH_NB;
+    const int rem = n - r0;
+    if (tid < rem) {
+      int i = r0 + tid;
+      double x[CH_NB];
+#pragma unroll
+      for (int j = 0; j < CH_NB; ++j) {
+        double v = A[(int64_t)i * n + kb + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= x[k] * Dk[j][k];
+        x[j] = v / Dk[j][j];
+      }
+#pragma unroll
+      for (int j = 0; j < CH_NB; ++j) {
+        P[tid][j] = x[j];
+        A[(int64_t)i * n + kb + j] = x[j];
+      }
     }
     __syncthreads();
-    // trailing update of the lower triangle: A[i][j] -= l_i l_j, k < j <= i
-    int rem = n - k - 1;
-    int64_t tot = (int64_t)rem * rem;
-    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
-      int i = k + 1 + (int)(e / rem);
-      int j = k + 1 + (int)(e % rem);
-      if (j <= i) A[(int64_t)i * n + j] -= colk[i] * colk[j];
+    // 3. trailing update of the lower triangle, 4x4 tiles
+    const int tb = (rem + 3) / 4;
+    const int ntile = tb * (tb + 1) / 2;
+    for (int t = tid; t < ntile; t += 1024) {
+      // t -> (bi, bj), bj <= bi
+      int bi = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while (bi * (bi + 1) / 2 > t) --bi;
+      while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+      int bj = t - bi * (bi + 1) / 2;
+      double acc[4][4] = {};
+#pragma unroll 4
+      for (int k = 0; k < CH_NB; ++k) {
+        double pi[4], pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          int ii = 4 * bi + u, jj = 4 * bj + u;
+          pi[u] = ii < rem ? P[ii][k] : 0.0;
+          pj[u] = jj < rem ? P[jj][k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += pi[u] * pj[v];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int ii = 4 * bi + u, jj = 4 * bj + v;
+          if (ii < rem && jj <= ii) A[(int64_t)(r0 + ii) * n + r0 + jj] -= acc[u][v];
+        }
     }
     __syncthreads();
   }
-  // zero the strict upper triangle
   __syncthreads();
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
+  // zero the strict upper triangle
+  for (int64_t e = tid; e < (int64_t)n * n; e += 1024) {
     int i = (int)(e / n), j = (int)(e % n);
     if (j > i) A[e] = 0.0;
   }
-  if (threadIdx.x == 0) *info = fail;
+  if (tid == 0) *info = fail;
 }
 
 fsa_status dense_cholesky(double* A, int mp, int* info_dev, hipStream_t st) {
+  if (mp > 512 || mp % CH_NB) {
+    set_error("cholesky: unsupported order %d", mp);
+    return FSA_ERR_INVALID_ARG;
+  }
   hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, A, mp, info_dev);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
 
-// Column j of L^{-1}: forward substitution L x = e_j, one thread per column.
-__global__ void k_tri_inverse(const double* __restrict__ L, double* __restrict__ X, int n) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  for (int i = 0; i < j; ++i) X[(int64_t)i * n + j] = 0.0;
-  X[(int64_t)j * n + j] = 1.0 / L[(int64_t)j * n + j];
-  for (int i = j + 1; i < n; ++i) {
+// L^{-1} for lower-triangular L: one workgroup per block of 32 columns.
+// Rows are solved in order; row i of the block is
+// x_i = (e_i - sum_{k<i} L_ik x_k) / L_ii with the sum split over 8 lanes
+// per column; the block lives in LDS.
+__global__ __launch_bounds__(256) void k_tri_inverse(const double* __restrict__ L, double* __restrict__ X, int n) {
+  __shared__ double Xs[512][33];
+  const int j0 = blockIdx.x * 32;
+  const int c = threadIdx.x >> 3;   // column within the block
+  const int g = threadIdx.x & 7;    // summation lane
+  for (int i = 0; i < n; ++i) {
     double s = 0.0;
-    for (int k = j; k < i; ++k) s += L[(int64_t)i * n + k] * X[(int64_t)k * n + j];
-    X[(int64_t)i * n + j] = -s / L[(int64_t)i * n + i];
+    if (i >= j0) {
+      const double* Li = L + (int64_t)i * n;
+      for (int k = j0 + g; k < i; k += 8) s += Li[k] * Xs[k][c];
+    }
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    double x = 0.0;
+    if (i >= j0) x = ((i == j0 + c ? 1.0 : 0.0) - s) / L[(int64_t)i * n + i];
+    if (g == 0) {
+      Xs[i][c] = x;
+      X[(int64_t)i * n + j0 + c] = x;
+    }
+    __syncthreads();
   }
 }
 
 fsa_status dense_tri_inverse(const double* L, double* Linv, int mp, hipStream_t st) {
-  hipLaunchKernelGGL(k_tri_inverse, dim3(ceil_div(mp, 64)), dim3(64), 0, st, L, Linv, mp);
+  if (mp > 512 || mp % 32) {
+    set_error("triangular inverse: unsupported order %d", mp);
+    return FSA_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_tri_inverse, dim3(mp / 32), dim3(256), 0, st, L, Linv, mp);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }

@@ -453,11 +453,13 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   FSA_TRY(gbuf.alloc((size_t)mp * ldw));
   b.g = gbuf.p;
   OpDesc<T> op;
+  op.grid = &c->grid;
   op.S = &c->csr;
   op.D = c->D.p;
   op.kdim = mp;
   op.Cinv = c->Cinv.p;
   OpDesc<double> op64;
+  op64.grid = &c->grid;
   op64.S = &c->csr;
   op64.val = c->vals.p;
   op64.D = c->D.p;
@@ -554,7 +556,7 @@ static fsa_status apply_sigma(fsa_ctx* c, const double* X, double* Y, int ncols,
   int ldw = (int)round_up(ncols, 64);
   FSA_TRY(c->scr.w.alloc((size_t)c->mp * ldw * 2));
   FSA_TRY(c->tmp.alloc((size_t)c->n * ldx));
-  FSA_TRY(spmm<double>(c->csr, c->vals.p, X, ldx, ncols, Y, ldx, false, st));
+  FSA_TRY(spmm<double>(c->csr, c->grid, c->grid, c->vals.p, X, ldx, ncols, Y, ldx, false, st));
   FSA_TRY(lowrank_reduce<double>(c->A.p, c->n, c->mp, X, ldx, ncols, nullptr, c->scr, c->scr.w.p, ldw, st));
   FSA_TRY(lowrank_expand<double>(c->A.p, nullptr, c->n, c->mp, c->scr.w.p, ldw, ncols, c->tmp.p, ldx, st));
   FSA_TRY(axpy_block(c->tmp.p, 1.0, Y, ldx, c->n, ncols, st));
@@ -592,7 +594,7 @@ static fsa_status apply_drho(fsa_ctx* c, const double* X, double* Y, int ncols, 
   int ldw = (int)round_up(ncols, 64);
   FSA_TRY(c->scr.w.alloc((size_t)mp * ldw * 2));
   FSA_TRY(c->tmp.alloc((size_t)c->n * ldx));
-  FSA_TRY(spmm<double>(c->csr, c->dvals.p, X, ldx, ncols, Y, ldx, false, st));
+  FSA_TRY(spmm<double>(c->csr, c->grid, c->grid, c->dvals.p, X, ldx, ncols, Y, ldx, false, st));
   FSA_TRY(lowrank_reduce<double>(c->A.p, c->n, mp, X, ldx, ncols, nullptr, c->scr, c->scr.w.p, ldw, st));
   FSA_TRY(lowrank_reduce<double>(c->F.p, c->n, mp, X, ldx, ncols, nullptr, c->scr, c->scr.w.p + (size_t)mp * ldw, ldw,
                                  st));
@@ -713,7 +715,7 @@ fsa_status fsa_apply(fsa_ctx* c, int32_t which, const double* X, double* Y, int3
   int ldw = (int)round_up(ncols + 1, 64);
   switch (which) {
     case FSA_OP_SIGMA_S:
-      FSA_TRY(spmm<double>(c->csr, c->vals.p, xs.p, ld, ncols, ys.p, ld, false, st));
+      FSA_TRY(spmm<double>(c->csr, c->grid, c->grid, c->vals.p, xs.p, ld, ncols, ys.p, ld, false, st));
       break;
     case FSA_OP_SIGMA_DAGGER:
       FSA_TRY(apply_sigma(c, xs.p, ys.p, ncols, ld));

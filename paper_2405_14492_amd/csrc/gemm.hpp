@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t nrows, int kdim, cons
 template <typename T, bool DOT, class AOp, class Pro>
 __global__ __launch_bounds__(512) void k_reduce_gemm(int64_t npts, int pts_per_chunk, int kdim, int ncols, AOp acol,
                                                      Pro pro, T* __restrict__ part, double* __restrict__ dot_part,
-                                                     int ld_dot) {
+                                                     int ld_dot, int lower_only) {
   __shared__ __attribute__((aligned(16))) T Xs[64 * XS_LD];
   __shared__ double red[512];
   typedef typename Mfma<T>::acc acc_t;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(512) void k_reduce_gemm(int64_t npts, int pts_per_c
   const int ncb = gridDim.y;
   const int nmb = kdim / 64;
   const int mb = blockIdx.z * 8 + w;
-  const bool mactive = mb < nmb;
+  const bool mactive = mb < nmb && (!lower_only || mb >= (int)blockIdx.y);
   const int kb = mb * 64;
   const int64_t pbeg = (int64_t)blockIdx.x * pts_per_chunk;
   const int64_t pend = min(npts, pbeg + pts_per_chunk);
@@ -197,16 +197,23 @@ __global__ __launch_bounds__(512) void k_reduce_gemm(int64_t npts, int pts_per_c
   }
 }
 
-// Sum the per-chunk partial tiles (fixed order) into W (float64, row-major
-// kdim x ldw); optionally add the identity.
+// Sum the per-chunk partial tiles (fixed order, eight interleaved partial
+// sums) into W (float64, row-major kdim x ldw); optionally add the identity.
 template <typename T>
 __global__ void k_reduce_parts(const T* __restrict__ part, int nchunks, int ncb, int nmb, double* __restrict__ W,
-                               int ldw, int add_identity) {
+                               int ldw, int add_identity, int lower_only) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t per = (int64_t)ncb * nmb * 4096;
   if (e >= per) return;
-  double s = 0.0;
-  for (int ch = 0; ch < nchunks; ++ch) s += (double)part[(int64_t)ch * per + e];
+  if (lower_only && (int)((e >> 12) % nmb) < (int)((e >> 12) / nmb)) return;
+  double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int ch = 0;
+  for (; ch + 8 <= nchunks; ch += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s8[u] += (double)part[(int64_t)(ch + u) * per + e];
+  }
+  for (int u = 0; ch < nchunks; ++ch, ++u) s8[u] += (double)part[(int64_t)ch * per + e];
+  double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
   int lane = (int)(e & 63);
   int r = (int)((e >> 6) & 3);
   int tile = (int)((e >> 8) & 15);
@@ -218,6 +225,121 @@ __global__ void k_reduce_parts(const T* __restrict__ part, int nchunks, int ncb,
   int c = cb * 64 + 4 * (lane & 15) + ct;
   if (add_identity && k == c) s += 1.0;
   W[(int64_t)k * ldw + c] = s;
+}
+
+// Column sums of per-workgroup partials: out[c] = sum_k part[k*ldp + c],
+// one workgroup per column, fixed order.
+__global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ part, int nparts, int ldp,
+                                                double* __restrict__ out);
+
+// ------------------------------------------------------------------ SpMM
+// Y(p, c) = sum_q S_pq X(q, c) for the rows of one grid cell per workgroup.
+// The candidate columns are the points of the 3x3 block of cells (three
+// contiguous ranges); their block rows are staged in LDS in chunks of CH
+// rows, and every row reads its neighbours from LDS.  Waves own rows; lanes
+// own columns (64-column block per grid.y).
+__device__ __forceinline__ int64_t spmm_v_of_q(int64_t q, const int64_t* qb, const int64_t* off) {
+  return q >= qb[2] ? q - qb[2] + off[2] : (q >= qb[1] ? q - qb[1] + off[1] : q - qb[0] + off[0]);
+}
+__device__ __forceinline__ double readlane_t(double v, int j) {
+  int64_t b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)b, j);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ float readlane_t(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
+template <typename T, bool DOT, int R, class Epi>
+__global__ __launch_bounds__(256) void k_spmm_cell(const int64_t* __restrict__ rcs, const int64_t* __restrict__ ccs,
+                                                   GridDesc gd, const int64_t* __restrict__ rp,
+                                                   const int* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ X, int ldx, int ncols, int CH, Epi epi,
+                                                   double* __restrict__ dot_part, int ld_dot) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char spmm_smem[];
+  T* Xs = reinterpret_cast<T*>(spmm_smem);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t cell = blockIdx.x;
+  const int c0 = blockIdx.y * 64;
+  const int c = c0 + lane;
+  const int64_t rb = rcs[cell], re = rcs[cell + 1];
+  double dacc = 0.0;
+  if (rb < re) {
+    const int64_t cx = cell % gd.gx, cy = cell / gd.gx;
+    int64_t qb[3], qe[3], off[3];
+    int64_t V = 0;
+    for (int t = 0; t < 3; ++t) {
+      int64_t yy = cy - 1 + t;
+      qb[t] = qe[t] = 0;
+      if (yy >= 0 && yy < gd.gy) {
+        int64_t xlo = cx - 1 < 0 ? 0 : cx - 1;
+        int64_t xhi = cx + 1 >= gd.gx ? gd.gx - 1 : cx + 1;
+        qb[t] = ccs[yy * gd.gx + xlo];
+        qe[t] = ccs[yy * gd.gx + xhi + 1];
+      }
+      off[t] = V;
+      V += qe[t] - qb[t];
+    }
+    for (int64_t g0 = rb; g0 < re; g0 += 4 * R) {
+      T acc[R];
+      int64_t cur[R], end[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        acc[r] = T(0);
+        int64_t p = g0 + w + 4 * r;
+        cur[r] = p < re ? rp[p] : 0;
+        end[r] = p < re ? rp[p + 1] : 0;
+      }
+      for (int64_t vb = 0; vb < V; vb += CH) {
+        __syncthreads();
+        const int64_t vn = min((int64_t)CH, V - vb);
+        for (int e = threadIdx.x; e < vn * 64; e += 256) {
+          int vr = e >> 6, cc = e & 63;
+          int64_t v = vb + vr;
+          int64_t q = v >= off[2] ? v - off[2] + qb[2] : (v >= off[1] ? v - off[1] + qb[1] : v - off[0] + qb[0]);
+          Xs[vr * 64 + cc] = (c0 + cc < ncols) ? X[q * ldx + c0 + cc] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int64_t e = cur[r];
+          const int64_t ee = end[r];
+          while (e < ee) {
+            const int ne = (int)min((int64_t)64, ee - e);
+            int qv = lane < ne ? col[e + lane] : 0;
+            T vv = lane < ne ? val[e + lane] : T(0);
+            int vq = (int)(spmm_v_of_q(qv, qb, off) - vb);
+            uint64_t mask = __ballot(lane < ne && vq < (int)vn);
+            int cnt = __popcll(mask);
+            for (int j = 0; j < cnt; ++j) {
+              int vj = __builtin_amdgcn_readlane(vq, j);
+              T wj = readlane_t(vv, j);
+              acc[r] += wj * Xs[vj * 64 + lane];
+            }
+            e += cnt;
+            if (cnt < ne) break;
+          }
+          cur[r] = e;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int64_t p = g0 + w + 4 * r;
+        if (p < re && c < ncols) dacc += epi(p, c, acc[r]);
+      }
+    }
+  }
+  if constexpr (DOT) {
+    __shared__ double red[4][64];
+    __syncthreads();
+    red[w][lane] = dacc;
+    __syncthreads();
+    if (threadIdx.x < 64)
+      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + threadIdx.x] =
+          red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+  }
 }
 
 // ------------------------------------------------------------------ SDDMM

@@ -105,14 +105,99 @@ struct PlainPro {
 };
 
 // ================================================================ build-time
+// OUT[i][c] = sum_k Gen(i, k) G[k][c] for all c < mp, 64 points per
+// workgroup (8 waves, wave w owns columns [64w, 64w+64)).  Gen is the
+// covariance row c(x_i, s*_k) (mode 0, K = mp) or [dc/drho | c] (mode 1,
+// K = 2 mp), generated once per (i, k) into LDS.  With upper != 0, G is upper
+// triangular and wave w stops at k = 64 (w+1).
+__global__ __launch_bounds__(512) void k_whiten(const double* __restrict__ xs, int64_t n,
+                                                const double* __restrict__ ind, int m, int mp, Theta th,
+                                                const double* __restrict__ G, int mode, int upper,
+                                                double* __restrict__ out) {
+  __shared__ double As[64][20];
+  __shared__ double Bs[16][520];
+  typedef Mfma<double>::acc acc_t;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int K = mode ? 2 * mp : mp;
+  const int nw = mp / 64;
+  const int kend = upper ? min(K, 64 * (w + 1)) : K;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  // generator mapping: thread -> (row gr, two consecutive k)
+  const int gr = threadIdx.x >> 3;
+  const int gk = (threadIdx.x & 7) * 2;
+  const int64_t gi = row0 + gr;
+  double px = 0.0, py = 0.0;
+  if (gi < n) {
+    px = xs[2 * gi];
+    py = xs[2 * gi + 1];
+  }
+  const int kmax_wg = upper ? min(K, 64 * nw) : K;
+  for (int k0 = 0; k0 < kmax_wg; k0 += 16) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int kk = k0 + gk + u;
+      bool der = false;
+      if (mode == 1) {
+        if (kk < mp) der = true;
+        else kk -= mp;
+      }
+      double v = 0.0;
+      if (gi < n && kk < m) {
+        double dx = px - ind[2 * kk], dy = py - ind[2 * kk + 1];
+        double d = sqrt(dx * dx + dy * dy);
+        v = der ? dcov_drho(d, th) : cov_d(d, th);
+      }
+      As[gr][gk + u] = v;
+    }
+    for (int e = threadIdx.x; e < 16 * mp; e += 512) {
+      int rr = e / mp, cc = e - rr * mp;
+      Bs[rr][cc] = G[(int64_t)(k0 + rr) * mp + cc];
+    }
+    __syncthreads();
+    if (w < nw && k0 < kend) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = As[a * 16 + r16][4 * q + j];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = Bs[4 * q + j][64 * w + 16 * b + r16];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<double>::op(av[a], bv[b], acc[a][b]);
+      }
+    }
+  }
+  if (w < nw) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int64_t i = row0 + a * 16 + Mfma<double>::orow(q, r);
+          if (i < n) out[i * mp + 64 * w + 16 * b + r16] = acc[a][b][r];
+        }
+  }
+}
+
 fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th, const double* G,
                   int mode, double* A_out, hipStream_t st) {
-  CovRowsOp op{xs, ind, m, mp, mode, th};
-  StoreEpi<double> epi{A_out, mp, 0};
-  int kdim = mode == 1 ? 2 * mp : mp;
-  dim3 grid(rows_grid(n), mp / 64);
-  hipLaunchKernelGGL((k_rows_gemm<double, RT_ROWS, false, CovRowsOp, StoreEpi<double>>), grid, dim3(256), 0, st, n,
-                     kdim, G, mp, mp, mode == 0 ? 1 : 0, op, epi, (double*)nullptr, 0);
+  if (mp > 512) {
+    set_error("whiten: m too large");
+    return FSA_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_whiten, dim3(ceil_div(n, 64)), dim3(512), 0, st, xs, n, ind, m, mp, th, G, mode,
+                     mode == 0 ? 1 : 0, A_out);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -149,7 +234,7 @@ static ReduceShape reduce_shape(int64_t n, int kdim, int ncols) {
   r.nmb = kdim / 64;
   r.zb = (int)ceil_div(r.nmb, 8);
   r.threads = 64 * (r.nmb < 8 ? r.nmb : 8);
-  int64_t target = 512 / (r.ncb * r.zb);
+  int64_t target = 256 / (r.ncb * r.zb);
   if (target < 16) target = 16;
   int64_t nch = ceil_div(n, 1024);
   if (nch > target) nch = target;
@@ -171,10 +256,11 @@ static fsa_status ensure_part(Scratch& s, const ReduceShape& r) {
 }
 
 template <typename T>
-static fsa_status reduce_finish(Scratch& s, const ReduceShape& r, double* W, int ldw, int add_id, hipStream_t st) {
+static fsa_status reduce_finish(Scratch& s, const ReduceShape& r, double* W, int ldw, int add_id, hipStream_t st,
+                                int lower_only = 0) {
   int64_t per = (int64_t)r.ncb * r.nmb * 4096;
   hipLaunchKernelGGL(k_reduce_parts<T>, dim3(ceil_div(per, 256)), dim3(256), 0, st, (const T*)s.part.p, r.nchunks,
-                     r.ncb, r.nmb, W, ldw, add_id);
+                     r.ncb, r.nmb, W, ldw, add_id, lower_only);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -185,9 +271,9 @@ fsa_status capacitance(const double* A, const double* D, int64_t n, int mp, doub
   DivDPro<double> pro{A, mp, D};
   RowsOp<double> acol{A, mp};
   hipLaunchKernelGGL((k_reduce_gemm<double, false, RowsOp<double>, DivDPro<double>>), dim3(r.nchunks, r.ncb, r.zb),
-                     dim3(r.threads), 0, st, n, r.ppc, mp, mp, acol, pro, (double*)s.part.p, (double*)nullptr, 0);
+                     dim3(r.threads), 0, st, n, r.ppc, mp, mp, acol, pro, (double*)s.part.p, (double*)nullptr, 0, 1);
   FSA_HIP(hipGetLastError());
-  return reduce_finish<double>(s, r, C, mp, 1, st);
+  return reduce_finish<double>(s, r, C, mp, 1, st, 1);
 }
 
 // ================================================================ block products
@@ -200,11 +286,11 @@ fsa_status lowrank_reduce(const T* A, int64_t n, int kdim, const T* X, int ldx, 
   if (Dinv_src) {
     DivDPro<T> pro{X, ldx, Dinv_src};
     hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, DivDPro<T>>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads),
-                       0, st, n, r.ppc, kdim, ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0);
+                       0, st, n, r.ppc, kdim, ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0, 0);
   } else {
     PlainPro<T, T> pro{X, ldx};
     hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, PlainPro<T, T>>), dim3(r.nchunks, r.ncb, r.zb),
-                       dim3(r.threads), 0, st, n, r.ppc, kdim, ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0);
+                       dim3(r.threads), 0, st, n, r.ppc, kdim, ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0, 0);
   }
   FSA_HIP(hipGetLastError());
   return reduce_finish<T>(s, r, W, ldw, 0, st);
@@ -229,61 +315,65 @@ fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T*
 }
 
 // ---------------------------------------------------------------- SpMM
-// One wave per row and 64-column block; lanes are columns.
-template <typename T, bool DOT, class Epi>
-__global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int64_t* __restrict__ rp, const int* __restrict__ col,
-                                              const T* __restrict__ val, const T* __restrict__ X, int ldx, int ncols,
-                                              Epi epi, double* __restrict__ dot_part, int ld_dot) {
-  __shared__ double red[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = blockIdx.y * 64 + lane;
-  const bool cok = c < ncols;
-  double dacc = 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * 4 + w; row < nrows; row += (int64_t)gridDim.x * 4) {
-    const int64_t rowu = row;
-    int64_t e = rp[rowu];
-    const int64_t ee = rp[rowu + 1];
-    T acc0 = T(0), acc1 = T(0);
-    for (; e + 2 <= ee; e += 2) {
-      const T v0 = val[e], v1 = val[e + 1];
-      const int j0 = col[e], j1 = col[e + 1];
-      T x0 = cok ? X[(int64_t)j0 * ldx + c] : T(0);
-      T x1 = cok ? X[(int64_t)j1 * ldx + c] : T(0);
-      acc0 += v0 * x0;
-      acc1 += v1 * x1;
-    }
-    if (e < ee) {
-      const T v0 = val[e];
-      const int j0 = col[e];
-      acc0 += v0 * (cok ? X[(int64_t)j0 * ldx + c] : T(0));
-    }
-    if (cok) dacc += epi(rowu, c, acc0 + acc1);
-  }
-  if constexpr (DOT) {
-    red[w][lane] = dacc;
-    __syncthreads();
-    if (threadIdx.x < 64)
-      dot_part[(int64_t)blockIdx.x * ld_dot + blockIdx.y * 64 + threadIdx.x] =
-          red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-  }
-}
-
 static int64_t spmm_grid(int64_t n) {
   int64_t g = ceil_div(n, 4 * 8);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   return g;
 }
+constexpr int SPMM_R = 8;
+static int spmm_ch(size_t elem) { return elem == 8 ? 64 : 128; }
 
-template <typename T>
-fsa_status spmm(const Csr& S, const T* val, const T* X, int ldx, int ncols, T* Y, int ldy, bool accumulate,
-                hipStream_t st) {
-  StoreEpi<T> epi{Y, ldy, accumulate ? 1 : 0};
-  dim3 grid(spmm_grid(S.nrows), ceil_div(ncols, 64));
-  hipLaunchKernelGGL((k_spmm<T, false, StoreEpi<T>>), grid, dim3(256), 0, st, S.nrows, S.row_ptr.p, S.col.p, val, X,
-                     ldx, ncols, epi, (double*)nullptr, 0);
+template <typename T, bool DOT, class Epi>
+static fsa_status launch_spmm_cell(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx,
+                                   int ncols, const Epi& epi, double* dot_part, int ld_dot, hipStream_t st) {
+  if (rg.ncell == 0) return FSA_OK;
+  int CH = spmm_ch(sizeof(T));
+  size_t smem = (size_t)CH * 64 * sizeof(T);
+  dim3 grid(rg.ncell, ceil_div(ncols, 64));
+  GridDesc gd = cg.desc;
+  hipLaunchKernelGGL((k_spmm_cell<T, DOT, SPMM_R, Epi>), grid, dim3(256), smem, st, rg.cstart.p, cg.cstart.p, gd,
+                     S.row_ptr.p, S.col.p, val, X, ldx, ncols, CH, epi, dot_part, ld_dot);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
+}
+
+template <typename T>
+fsa_status spmm(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx, int ncols, T* Y,
+                int ldy, bool accumulate, hipStream_t st) {
+  StoreEpi<T> epi{Y, ldy, accumulate ? 1 : 0};
+  return launch_spmm_cell<T, false, StoreEpi<T>>(S, rg, cg, val, X, ldx, ncols, epi, nullptr, 0, st);
+}
+
+__global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ part, int nparts, int ldp,
+                                                double* __restrict__ out) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 256) s += part[(int64_t)k * ldp + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// block-wide fixed-order sum of nparts partials of column c (256 threads)
+__device__ __forceinline__ double block_colsum(const double* __restrict__ part, int nparts, int ldp, int c,
+                                               double* red) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 256) s += part[(int64_t)k * ldp + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
 }
 
 // ---------------------------------------------------------------- column dots
@@ -304,14 +394,6 @@ __global__ __launch_bounds__(256) void k_coldot(const TX* __restrict__ X, const 
         red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
-__global__ void k_sum_parts(const double* __restrict__ part, int nparts, int ldp, int ncols, double* __restrict__ out) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  double s = 0.0;
-  for (int k = 0; k < nparts; ++k) s += part[(int64_t)k * ldp + c];
-  out[c] = s;
-}
-
 template <typename TX, typename TY>
 fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double* out, Scratch& s, hipStream_t st) {
   int ncb = (int)ceil_div(ncols, 64);
@@ -321,30 +403,48 @@ fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double
   size_t need = (size_t)g * ncb * 64;
   if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
   hipLaunchKernelGGL((k_coldot<TX, TY>), dim3(g, ncb), dim3(256), 0, st, X, Y, n, ld, ncols, s.dot.p);
-  hipLaunchKernelGGL(k_sum_parts, dim3(ceil_div(ncols, 256)), dim3(256), 0, st, s.dot.p, (int)g, ncb * 64, ncols, out);
+  hipLaunchKernelGGL(k_colsum, dim3(ncols), dim3(256), 0, st, s.dot.p, (int)g, ncb * 64, out);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
 
 // ---------------------------------------------------------------- m-space
+// G (kdim x ldg, type T) = M (kdim x kdim) W (kdim x ldw, columns < ncols),
+// 32 x 32 output tiles through LDS, float64 accumulation.
 template <typename T>
-__global__ void k_mspace(const double* __restrict__ M, const double* __restrict__ W, int ldw, int kdim, int ncols,
-                         T* __restrict__ G, int ldg) {
-  int c = blockIdx.x * 64 + threadIdx.x % 64;
-  int k = blockIdx.y * (blockDim.x / 64) + threadIdx.x / 64;
-  if (k >= kdim) return;
-  double s = 0.0;
-  if (c < ncols) {
-    const double* mr = M + (int64_t)k * kdim;
-    for (int j = 0; j < kdim; ++j) s += mr[j] * W[(int64_t)j * ldw + c];
+__global__ __launch_bounds__(256) void k_mspace(const double* __restrict__ M, const double* __restrict__ W, int ldw,
+                                                int kdim, int ncols, T* __restrict__ G, int ldg) {
+  __shared__ double Ms[32][33], Ws[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // ty 0..7
+  const int k0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  double acc[4] = {0, 0, 0, 0};
+  for (int j0 = 0; j0 < kdim; j0 += 32) {
+    for (int r = ty; r < 32; r += 8) {
+      int k = k0 + r, j = j0 + tx, cc = c0 + tx;
+      Ms[r][tx] = (k < kdim && j < kdim) ? M[(int64_t)k * kdim + j] : 0.0;
+      int jj = j0 + r;
+      Ws[r][tx] = (jj < kdim && cc < ncols) ? W[(int64_t)jj * ldw + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int j = 0; j < 32; ++j) {
+      double wv = Ws[j][tx];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += Ms[ty + 8 * u][j] * wv;
+    }
+    __syncthreads();
   }
-  if (c < ldg) G[(int64_t)k * ldg + c] = (T)s;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int k = k0 + ty + 8 * u, cc = c0 + tx;
+    if (k < kdim && cc < ldg) G[(int64_t)k * ldg + cc] = (T)(cc < ncols ? acc[u] : 0.0);
+  }
 }
 
 template <typename T>
 fsa_status mspace_apply(const double* M, const double* W, int ldw, int kdim, int ncols, T* G, int ldg,
                         hipStream_t st) {
-  dim3 grid(ceil_div(ldg, 64), ceil_div(kdim, 4));
+  dim3 grid(ceil_div(ldg, 32), ceil_div(kdim, 32));
   hipLaunchKernelGGL(k_mspace<T>, grid, dim3(256), 0, st, M, W, ldw, kdim, ncols, G, ldg);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -508,36 +608,44 @@ __global__ void k_pcg_setup(int ncols, const double* __restrict__ bn2_part, int 
   }
 }
 
-__global__ void k_pcg_alpha(int ncols, const double* __restrict__ hv_part, int np, int ldp, const double* __restrict__ rz,
-                            const int* __restrict__ active, double* __restrict__ alpha, int* flags) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  double hv = 0.0;
-  for (int k = 0; k < np; ++k) hv += hv_part[(int64_t)k * ldp + c];
-  double a = 0.0;
-  if (active[c]) {
-    if (!(hv > 0.0) || !isfinite(hv)) {
-      atomicOr(&flags[1], 1);
-    } else {
-      a = rz[c] / hv;
+// One workgroup per column: alpha = r^T q / h^T v for active columns.
+__global__ __launch_bounds__(256) void k_pcg_alpha(int ncols, const double* __restrict__ hv_part, int np, int ldp,
+                                                   const double* __restrict__ rz, const int* __restrict__ active,
+                                                   double* __restrict__ alpha, int* flags) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  double hv = block_colsum(hv_part, np, ldp, c, red);
+  if (threadIdx.x == 0) {
+    if (c == 0) flags[0] = 0;
+    double a = 0.0;
+    if (active[c]) {
+      if (!(hv > 0.0) || !isfinite(hv)) atomicOr(&flags[1], 1);
+      else a = rz[c] / hv;
     }
+    alpha[c] = a;
   }
-  alpha[c] = a;
 }
 
-__global__ void k_pcg_beta(int ncols, const double* __restrict__ rq_part, int nq, int ldq, const double* __restrict__ rr_part,
-                           int nr, int ldr, double* rz, const double* __restrict__ alpha, double* beta, int* active,
-                           int* iters, double* ah, double* bh, const double* __restrict__ bn2, double tol2, int fixed,
-                           int max_iter, int* flags) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+// One workgroup per column: beta = r'^T q' / r^T q, Lanczos coefficients of
+// the iteration, convergence test on |r'|^2 / |b|^2; flags[0] counts the
+// columns still active afterwards.
+__global__ __launch_bounds__(256) void k_pcg_beta(int ncols, const double* __restrict__ rq_part, int nq, int ldq,
+                                                  const double* __restrict__ rr_part, int nr, int ldr, double* rz,
+                                                  const double* __restrict__ alpha, double* beta, int* active,
+                                                  int* iters, double* ah, double* bh, const double* __restrict__ bn2,
+                                                  double tol2, int fixed, int max_iter, int* flags) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  const bool act = active[c] != 0;
+  double rq = 0.0, rr = 0.0;
+  if (act) {
+    rq = block_colsum(rq_part, nq, ldq, c, red);
+    rr = block_colsum(rr_part, nr, ldr, c, red);
+  }
+  if (threadIdx.x == 0) {
     double b = 0.0;
-    if (active[c]) {
-      double rq = 0.0, rr = 0.0;
-      for (int k = 0; k < nq; ++k) rq += rq_part[(int64_t)k * ldq + c];
-      for (int k = 0; k < nr; ++k) rr += rr_part[(int64_t)k * ldr + c];
+    int still = 0;
+    if (act) {
       b = rq / rz[c];
       int it = iters[c];
       if (it < max_iter) {
@@ -547,13 +655,12 @@ __global__ void k_pcg_beta(int ncols, const double* __restrict__ rq_part, int nq
       iters[c] = it + 1;
       rz[c] = rq;
       if (!isfinite(rq)) atomicOr(&flags[1], 1);
-      if (!fixed && rr < tol2 * bn2[c]) active[c] = 0;
+      still = (fixed || !(rr < tol2 * bn2[c])) ? 1 : 0;
+      active[c] = still;
     }
     beta[c] = b;
-    if (active[c]) atomicAdd(&cnt, 1);
+    if (still) atomicAdd(&flags[0], 1);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) flags[0] = cnt;
 }
 
 template <typename T>
@@ -593,7 +700,7 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
     DivDPro<T> pro{b.R, b.ld, op.D};
     RowsOp<T> acol{op.A, op.kdim};
     hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, DivDPro<T>>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads),
-                       0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0);
+                       0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0, 0);
     FSA_HIP(hipGetLastError());
     FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
     FSA_TRY(pcg_precond_and_dots<T>(b, op, 1, s, nparts_rq, st));
@@ -630,18 +737,18 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
   // 1. V = S H + P, h^T v
   {
     PcgSpmmEpi<T> epi{b.H, b.P, b.V, b.ld, lr ? 1 : 0};
-    int64_t g = spmm_grid(b.n);
+    int64_t g = op.grid->ncell;
     size_t need = (size_t)g * ldd;
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
     {
       KT_BEGIN(b);
-      hipLaunchKernelGGL((k_spmm<T, true, PcgSpmmEpi<T>>), dim3(g, ncb), dim3(256), 0, st, b.n, op.S->row_ptr.p,
-                         op.S->col.p, op.val, b.H, b.ld, b.ncols, epi, s.dot.p, ldd);
+      FSA_TRY((launch_spmm_cell<T, true, PcgSpmmEpi<T>>(*op.S, *op.grid, *op.grid, op.val, b.H, b.ld, b.ncols, epi,
+                                                          s.dot.p, ldd, st)));
       KT_END(b, KT_SPMM);
     }
     KT_BEGIN(b);
-    hipLaunchKernelGGL(k_pcg_alpha, dim3(ceil_div(b.ncols, 64)), dim3(64), 0, st, b.ncols, s.dot.p, (int)g, ldd, b.rz,
-                       b.active, b.alpha, b.flags);
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(b.ncols), dim3(256), 0, st, b.ncols, s.dot.p, (int)g, ldd, b.rz, b.active,
+                       b.alpha, b.flags);
     KT_END(b, KT_SMALL);
     FSA_HIP(hipGetLastError());
   }
@@ -655,7 +762,7 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     {
       KT_BEGIN(b);
       hipLaunchKernelGGL((k_reduce_gemm<T, true, RowsOp<T>, PcgPass1Pro<T>>), dim3(r.nchunks, r.ncb, r.zb),
-                         dim3(r.threads), 0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, s.dot2.p, ldd);
+                         dim3(r.threads), 0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, s.dot2.p, ldd, 0);
       KT_END(b, KT_PASS1);
     }
     FSA_HIP(hipGetLastError());
@@ -677,7 +784,7 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
   // 4. beta, Lanczos entries, convergence
   {
     KT_BEGIN(b);
-    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, st, b.ncols, s.dot.p, nparts_rq, ldd, s.dot2.p, nparts_rr,
+    hipLaunchKernelGGL(k_pcg_beta, dim3(b.ncols), dim3(256), 0, st, b.ncols, s.dot.p, nparts_rq, ldd, s.dot2.p, nparts_rr,
                        ldd, b.rz, b.alpha, b.beta, b.active, b.iters, b.alpha_hist, b.beta_hist, b.bn2, tol * tol,
                        fixed, b.max_iter, b.flags);
     KT_END(b, KT_SMALL);
@@ -709,7 +816,7 @@ fsa_status pcg_replace_residual_f32(PcgBlock<float>& b, const OpDesc<double>& op
   Buf<double> SU, LU, G;
   FSA_TRY(SU.alloc((size_t)b.n * b.ld));
   FSA_TRY(LU.alloc((size_t)b.n * b.ld));
-  FSA_TRY(spmm<double>(*op64.S, op64.val, b.U, b.ld, b.ncols, SU.p, b.ld, false, st));
+  FSA_TRY(spmm<double>(*op64.S, *op64.grid, *op64.grid, op64.val, b.U, b.ld, b.ncols, SU.p, b.ld, false, st));
   FSA_TRY(lowrank_reduce<double>(op64.A, b.n, op64.kdim, b.U, b.ld, b.ncols, nullptr, s, s.w.p, b.ldw, st));
   FSA_TRY(lowrank_expand<double>(op64.A, nullptr, b.n, op64.kdim, s.w.p, b.ldw, b.ncols, LU.p, b.ld, st));
   int64_t tot = b.n * b.ncols;
@@ -726,83 +833,98 @@ fsa_status pcg_replace_residual_f32(PcgBlock<float>& b, const OpDesc<double>& op
 // sqrt(beta_j)/alpha_j (Algorithm 2).  Eigenvalues by the implicit QL
 // iteration with Wilkinson-type shifts (Bowdler, Martin, Reinsch &
 // Wilkinson 1968), tracking only the first row of the eigenvector matrix.
-__global__ void k_slq(const double* __restrict__ ah, const double* __restrict__ bh, const int* __restrict__ iters,
-                      int ncols, int c_first, const double* __restrict__ weight, double* __restrict__ out,
-                      double* __restrict__ scratch, int max_iter) {
-  int c = c_first + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
+__global__ __launch_bounds__(64) void k_slq(const double* __restrict__ ah, const double* __restrict__ bh,
+                                            const int* __restrict__ iters, int ncols, int c_first,
+                                            const double* __restrict__ weight, double* __restrict__ out,
+                                            int max_iter) {
+  extern __shared__ double slq_smem[];
+  const int c = c_first + blockIdx.x;
   int k = iters[c];
   if (k > max_iter) k = max_iter;
-  double* d = scratch + (int64_t)c * 3 * max_iter;
+  double* d = slq_smem;
   double* e = d + max_iter;
   double* z = e + max_iter;
-  for (int j = 0; j < k; ++j) {
+  for (int j = threadIdx.x; j < k; j += 64) {
     double a = ah[(int64_t)j * ncols + c];
     d[j] = 1.0 / a + (j > 0 ? bh[(int64_t)(j - 1) * ncols + c] / ah[(int64_t)(j - 1) * ncols + c] : 0.0);
     e[j] = (j < k - 1) ? sqrt(bh[(int64_t)j * ncols + c]) / a : 0.0;
     z[j] = (j == 0) ? 1.0 : 0.0;
   }
-  bool ok = k > 0;
-  for (int l = 0; l < k && ok; ++l) {
-    int iter = 0;
-    int mm;
-    do {
-      for (mm = l; mm < k - 1; ++mm) {
-        double dd = fabs(d[mm]) + fabs(d[mm + 1]);
-        if (fabs(e[mm]) <= 2.220446049250313e-16 * dd) break;
-      }
-      if (mm != l) {
-        if (iter++ == 200) { ok = false; break; }
-        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-        double r = hypot(g, 1.0);
-        g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
-        double s = 1.0, cc = 1.0, p = 0.0;
-        int i;
-        bool deflated = false;
-        for (i = mm - 1; i >= l; --i) {
-          double f = s * e[i], bb = cc * e[i];
-          r = hypot(f, g);
-          e[i + 1] = r;
-          if (r == 0.0) {
-            d[i + 1] -= p;
-            e[mm] = 0.0;
-            deflated = true;
-            break;
-          }
-          s = f / r;
-          cc = g / r;
-          g = d[i + 1] - p;
-          r = (d[i] - g) * s + 2.0 * cc * bb;
-          p = s * r;
-          d[i + 1] = g + p;
-          g = cc * r - bb;
-          double zf = z[i + 1];
-          z[i + 1] = s * z[i] + cc * zf;
-          z[i] = cc * z[i] - s * zf;
+  __syncthreads();
+  __shared__ int ok_s;
+  if (threadIdx.x == 0) {
+    bool ok = k > 0;
+    for (int l = 0; l < k && ok; ++l) {
+      int iter = 0;
+      int mm;
+      do {
+        for (mm = l; mm < k - 1; ++mm) {
+          double dd = fabs(d[mm]) + fabs(d[mm + 1]);
+          if (fabs(e[mm]) <= 2.220446049250313e-16 * dd) break;
         }
-        if (deflated) continue;
-        d[l] -= p;
-        e[l] = g;
-        e[mm] = 0.0;
-      }
-    } while (mm != l);
+        if (mm != l) {
+          if (iter++ == 200) { ok = false; break; }
+          double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+          double r = hypot(g, 1.0);
+          g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
+          double s = 1.0, cc = 1.0, p = 0.0;
+          bool deflated = false;
+          for (int i = mm - 1; i >= l; --i) {
+            double f = s * e[i], bb = cc * e[i];
+            r = hypot(f, g);
+            e[i + 1] = r;
+            if (r == 0.0) {
+              d[i + 1] -= p;
+              e[mm] = 0.0;
+              deflated = true;
+              break;
+            }
+            s = f / r;
+            cc = g / r;
+            g = d[i + 1] - p;
+            r = (d[i] - g) * s + 2.0 * cc * bb;
+            p = s * r;
+            d[i + 1] = g + p;
+            g = cc * r - bb;
+            double zf = z[i + 1];
+            z[i + 1] = s * z[i] + cc * zf;
+            z[i] = cc * z[i] - s * zf;
+          }
+          if (deflated) continue;
+          d[l] -= p;
+          e[l] = g;
+          e[mm] = 0.0;
+        }
+      } while (mm != l);
+    }
+    ok_s = ok ? 1 : 0;
   }
+  __syncthreads();
   double v = 0.0;
-  if (ok) {
-    for (int j = 0; j < k; ++j) {
-      if (!(d[j] > 0.0)) { ok = false; break; }
-      v += z[j] * z[j] * log(d[j]);
+  int bad = 0;
+  if (ok_s) {
+    for (int j = threadIdx.x; j < k; j += 64) {
+      if (!(d[j] > 0.0)) bad = 1;
+      else v += z[j] * z[j] * log(d[j]);
     }
   }
-  out[c] = ok ? weight[c] * v : NAN;
+  v = wave_sum(v);
+  bad = __any(bad);
+  if (threadIdx.x == 0) out[c] = (ok_s && !bad) ? weight[c] * v : NAN;
 }
 
 fsa_status slq_terms(const double* alpha_hist, const double* beta_hist, const int* iters, int ncols, int c_first,
                      const double* weight, double* out, double* scratch, int max_iter, hipStream_t st) {
   int cnt = ncols - c_first;
   if (cnt <= 0) return FSA_OK;
-  hipLaunchKernelGGL(k_slq, dim3(ceil_div(cnt, 64)), dim3(64), 0, st, alpha_hist, beta_hist, iters, ncols, c_first,
-                     weight, out, scratch, max_iter);
+  (void)scratch;
+  size_t smem = (size_t)3 * max_iter * sizeof(double);
+  if (smem > 150 * 1024) {
+    set_error("slq: max_iter too large for the on-chip eigensolve");
+    return FSA_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_slq, dim3(cnt), dim3(64), smem, st, alpha_hist, beta_hist, iters, ncols, c_first, weight, out,
+                     max_iter);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -926,8 +1048,10 @@ template fsa_status lowrank_expand<double>(const double*, const double*, int64_t
                                            int, hipStream_t);
 template fsa_status lowrank_expand<float>(const float*, const float*, int64_t, int, const float*, int, int, float*, int,
                                           hipStream_t);
-template fsa_status spmm<double>(const Csr&, const double*, const double*, int, int, double*, int, bool, hipStream_t);
-template fsa_status spmm<float>(const Csr&, const float*, const float*, int, int, float*, int, bool, hipStream_t);
+template fsa_status spmm<double>(const Csr&, const Grid&, const Grid&, const double*, const double*, int, int, double*,
+                                 int, bool, hipStream_t);
+template fsa_status spmm<float>(const Csr&, const Grid&, const Grid&, const float*, const float*, int, int, float*, int,
+                                bool, hipStream_t);
 template fsa_status coldot<double, double>(const double*, const double*, int64_t, int, int, double*, Scratch&,
                                            hipStream_t);
 template fsa_status coldot<double, float>(const double*, const float*, int64_t, int, int, double*, Scratch&,

@@ -83,10 +83,11 @@ fsa_status lowrank_reduce(const T* A, int64_t n, int kdim, const T* X, int ldx, 
 template <typename T>
 fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T* G, int ldg, int ncols, T* OUT,
                           int ldo, hipStream_t st);
-// Y = S X (+ Y if accumulate) ; S in CSR with values val
+// Y = S X (+ Y if accumulate) ; S in CSR with values val, rows of grid rg,
+// columns of grid cg (cell-aligned grids)
 template <typename T>
-fsa_status spmm(const Csr& S, const T* val, const T* X, int ldx, int ncols, T* Y, int ldy, bool accumulate,
-                hipStream_t st);
+fsa_status spmm(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx, int ncols, T* Y,
+                int ldy, bool accumulate, hipStream_t st);
 // out[c] = sum_p X[p][c] Y[p][c] (float64 result, c < ncols)
 template <typename TX, typename TY>
 fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double* out, Scratch& s, hipStream_t st);
@@ -118,6 +119,7 @@ struct PcgBlock {
 // the diagonal preconditioner.
 template <typename T>
 struct OpDesc {
+  const Grid* grid = nullptr;  // row = column grid of S
   const Csr* S = nullptr;
   const T* val = nullptr;
   const double* D = nullptr;
