@@ -238,8 +238,12 @@ __global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ part,
 // contiguous ranges); their block rows are staged in LDS in chunks of CH
 // rows, and every row reads its neighbours from LDS.  Waves own rows; lanes
 // own columns (64-column block per grid.y).
-__device__ __forceinline__ int64_t spmm_v_of_q(int64_t q, const int64_t* qb, const int64_t* off) {
-  return q >= qb[2] ? q - qb[2] + off[2] : (q >= qb[1] ? q - qb[1] + off[1] : q - qb[0] + off[0]);
+// Position of column q in the concatenation of the three neighbour ranges
+// (empty ranges never match).
+__device__ __forceinline__ int64_t spmm_v_of_q(int64_t q, const int64_t* qb, const int64_t* qe, const int64_t* off) {
+  if (q >= qb[2] && q < qe[2]) return q - qb[2] + off[2];
+  if (q >= qb[1] && q < qe[1]) return q - qb[1] + off[1];
+  return q - qb[0] + off[0];
 }
 __device__ __forceinline__ double readlane_t(double v, int j) {
   int64_t b = __double_as_longlong(v);
@@ -283,18 +287,32 @@ __global__ __launch_bounds__(256) void k_spmm_cell(const int64_t* __restrict__ r
       V += qe[t] - qb[t];
     }
     for (int64_t g0 = rb; g0 < re; g0 += 4 * R) {
+      // prefetch up to 128 entries of each of this wave's R rows: slot index
+      // in the neighbourhood and value, two per lane
       T acc[R];
-      int64_t cur[R], end[R];
+      int vq0[R], vq1[R];
+      T vv0[R], vv1[R];
+      int nent[R];
+      int64_t ebeg[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         acc[r] = T(0);
         int64_t p = g0 + w + 4 * r;
-        cur[r] = p < re ? rp[p] : 0;
-        end[r] = p < re ? rp[p + 1] : 0;
+        int64_t e0 = p < re ? rp[p] : 0;
+        int64_t e1 = p < re ? rp[p + 1] : 0;
+        ebeg[r] = e0;
+        nent[r] = (int)(e1 - e0);
+        int ne = nent[r];
+        int qa = lane < ne ? col[e0 + lane] : 0;
+        int qc = lane + 64 < ne ? col[e0 + 64 + lane] : 0;
+        vv0[r] = lane < ne ? val[e0 + lane] : T(0);
+        vv1[r] = lane + 64 < ne ? val[e0 + 64 + lane] : T(0);
+        vq0[r] = lane < ne ? (int)spmm_v_of_q(qa, qb, qe, off) : 0x7fffffff;
+        vq1[r] = lane + 64 < ne ? (int)spmm_v_of_q(qc, qb, qe, off) : 0x7fffffff;
       }
       for (int64_t vb = 0; vb < V; vb += CH) {
         __syncthreads();
-        const int64_t vn = min((int64_t)CH, V - vb);
+        const int vn = (int)min((int64_t)CH, V - vb);
         for (int e = threadIdx.x; e < vn * 64; e += 256) {
           int vr = e >> 6, cc = e & 63;
           int64_t v = vb + vr;
@@ -302,26 +320,53 @@ __global__ __launch_bounds__(256) void k_spmm_cell(const int64_t* __restrict__ r
           Xs[vr * 64 + cc] = (c0 + cc < ncols) ? X[q * ldx + c0 + cc] : T(0);
         }
         __syncthreads();
+        const int lo = (int)vb, hi = (int)vb + vn;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          int64_t e = cur[r];
-          const int64_t ee = end[r];
-          while (e < ee) {
-            const int ne = (int)min((int64_t)64, ee - e);
-            int qv = lane < ne ? col[e + lane] : 0;
-            T vv = lane < ne ? val[e + lane] : T(0);
-            int vq = (int)(spmm_v_of_q(qv, qb, off) - vb);
-            uint64_t mask = __ballot(lane < ne && vq < (int)vn);
-            int cnt = __popcll(mask);
-            for (int j = 0; j < cnt; ++j) {
-              int vj = __builtin_amdgcn_readlane(vq, j);
-              T wj = readlane_t(vv, j);
-              acc[r] += wj * Xs[vj * 64 + lane];
+          if (nent[r] == 0) continue;
+          // entries are sorted, so the ones in [lo, hi) are a contiguous run
+          uint64_t m0 = __ballot(vq0[r] >= lo && vq0[r] < hi);
+          uint64_t m1 = __ballot(vq1[r] >= lo && vq1[r] < hi);
+          int j = m0 ? __ffsll((unsigned long long)m0) - 1 : 64;
+          int jn = 64 - __clzll((unsigned long long)m0);
+          if (!m0) jn = 64;
+          T a0 = T(0), a1 = T(0);
+          if (m0) {
+            for (; j + 2 <= jn; j += 2) {
+              int v0 = __builtin_amdgcn_readlane(vq0[r], j) - lo;
+              int v1 = __builtin_amdgcn_readlane(vq0[r], j + 1) - lo;
+              T w0 = readlane_t(vv0[r], j), w1 = readlane_t(vv0[r], j + 1);
+              a0 += w0 * Xs[v0 * 64 + lane];
+              a1 += w1 * Xs[v1 * 64 + lane];
             }
-            e += cnt;
-            if (cnt < ne) break;
+            if (j < jn) {
+              int v0 = __builtin_amdgcn_readlane(vq0[r], j) - lo;
+              a0 += readlane_t(vv0[r], j) * Xs[v0 * 64 + lane];
+            }
           }
-          cur[r] = e;
+          if (m1) {
+            j = __ffsll((unsigned long long)m1) - 1;
+            jn = 64 - __clzll((unsigned long long)m1);
+            for (; j + 2 <= jn; j += 2) {
+              int v0 = __builtin_amdgcn_readlane(vq1[r], j) - lo;
+              int v1 = __builtin_amdgcn_readlane(vq1[r], j + 1) - lo;
+              T w0 = readlane_t(vv1[r], j), w1 = readlane_t(vv1[r], j + 1);
+              a0 += w0 * Xs[v0 * 64 + lane];
+              a1 += w1 * Xs[v1 * 64 + lane];
+            }
+            if (j < jn) {
+              int v0 = __builtin_amdgcn_readlane(vq1[r], j) - lo;
+              a0 += readlane_t(vv1[r], j) * Xs[v0 * 64 + lane];
+            }
+          }
+          // rows with more than 128 entries: the rest straight from memory
+          if (nent[r] > 128) {
+            for (int64_t e = ebeg[r] + 128; e < ebeg[r] + nent[r]; ++e) {
+              int v0 = (int)spmm_v_of_q(col[e], qb, qe, off);
+              if (v0 >= lo && v0 < hi) a0 += val[e] * Xs[(v0 - lo) * 64 + lane];
+            }
+          }
+          acc[r] += a0 + a1;
         }
       }
 #pragma unroll

@@ -589,10 +589,11 @@ __global__ void k_pcg_setup(int ncols, const double* __restrict__ bn2_part, int 
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
-  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-    double b = 0.0, r = 0.0;
-    for (int k = 0; k < nb; ++k) b += bn2_part[(int64_t)k * ldb + c];
-    for (int k = 0; k < nr; ++k) r += rq_part[(int64_t)k * ldr + c];
+  __shared__ double red[256];
+  for (int c = 0; c < ncols; ++c) {
+    double b = block_colsum(bn2_part, nb, ldb, c, red);
+    double r = block_colsum(rq_part, nr, ldr, c, red);
+    if (threadIdx.x != 0) continue;
     bn2[c] = b;
     rz[c] = r;
     rz0[c] = r;
