@@ -96,15 +96,25 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t nrows, int kdim, cons
   }
   double dsum[4] = {0, 0, 0, 0};
 #pragma unroll
-  for (int a = 0; a < RT; ++a)
+  for (int a = 0; a < RT; ++a) {
+    typename Epi::In in[4][4];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int64_t i = row0 + a * 16 + Mfma<T>::orow(q, r);
         int c = c0 + b * 16 + r16;
-        if (i < nrows && c < ncols) dsum[b] += epi(i, c, acc[a][b][r]);
+        if (i < nrows && c < ncols) in[b][r] = epi.load(i, c);
       }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int64_t i = row0 + a * 16 + Mfma<T>::orow(q, r);
+        int c = c0 + b * 16 + r16;
+        if (i < nrows && c < ncols) dsum[b] += epi.apply(i, c, acc[a][b][r], in[b][r]);
+      }
+  }
   if constexpr (DOT) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -154,12 +164,25 @@ __global__ __launch_bounds__(512) void k_reduce_gemm(int64_t npts, int pts_per_c
   double dacc = 0.0;
   for (int64_t p0 = pbeg; p0 < pend; p0 += 64) {
     __syncthreads();
-    for (int pp = tp0; pp < 64; pp += nw) {
-      int64_t p = p0 + pp;
-      int c = c0 + tc;
-      T xv = T(0);
-      if (p < pend && c < ncols) xv = pro(p, c, dacc);
-      Xs[pp * XS_LD + tc] = xv;
+    for (int pb = tp0; pb < 64; pb += 8 * nw) {
+      typename Pro::In in[8];
+      const int c = c0 + tc;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int pp = pb + u * nw;
+        int64_t p = p0 + pp;
+        if (pp < 64 && p < pend && c < ncols) in[u] = pro.load(p, c);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int pp = pb + u * nw;
+        if (pp < 64) {
+          int64_t p = p0 + pp;
+          T xv = T(0);
+          if (p < pend && c < ncols) xv = pro.apply(p, c, in[u], dacc);
+          Xs[pp * XS_LD + tc] = xv;
+        }
+      }
     }
     __syncthreads();
     if (mactive) {
@@ -313,11 +336,29 @@ __global__ __launch_bounds__(256) void k_spmm_cell(const int64_t* __restrict__ r
       for (int64_t vb = 0; vb < V; vb += CH) {
         __syncthreads();
         const int vn = (int)min((int64_t)CH, V - vb);
-        for (int e = threadIdx.x; e < vn * 64; e += 256) {
-          int vr = e >> 6, cc = e & 63;
-          int64_t v = vb + vr;
-          int64_t q = v >= off[2] ? v - off[2] + qb[2] : (v >= off[1] ? v - off[1] + qb[1] : v - off[0] + qb[0]);
-          Xs[vr * 64 + cc] = (c0 + cc < ncols) ? X[q * ldx + c0 + cc] : T(0);
+        // 16 four-element vectors per staged row; batches of 8 loads in flight
+        for (int u0 = threadIdx.x; u0 < vn * 16; u0 += 256 * 8) {
+          V4<T> tmp[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            int u = u0 + 256 * k;
+            tmp[k] = V4<T>{{T(0), T(0), T(0), T(0)}};
+            if (u < vn * 16) {
+              int vr = u >> 4, c4 = (u & 15) * 4;
+              int64_t v = vb + vr;
+              int64_t q = v >= off[2] ? v - off[2] + qb[2] : (v >= off[1] ? v - off[1] + qb[1] : v - off[0] + qb[0]);
+              if (c0 + c4 < ncols) tmp[k] = load4(X + q * ldx + c0 + c4);
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            int u = u0 + 256 * k;
+            if (u < vn * 16) {
+              int vr = u >> 4, c4 = (u & 15) * 4;
+#pragma unroll
+              for (int z = 0; z < 4; ++z) Xs[vr * 64 + c4 + z] = (c0 + c4 + z < ncols) ? tmp[k].v[z] : T(0);
+            }
+          }
         }
         __syncthreads();
         const int lo = (int)vb, hi = (int)vb + vn;
@@ -369,10 +410,16 @@ __global__ __launch_bounds__(256) void k_spmm_cell(const int64_t* __restrict__ r
           acc[r] += a0 + a1;
         }
       }
+      typename Epi::In in[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         int64_t p = g0 + w + 4 * r;
-        if (p < re && c < ncols) dacc += epi(p, c, acc[r]);
+        if (p < re && c < ncols) in[r] = epi.load(p, c);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int64_t p = g0 + w + 4 * r;
+        if (p < re && c < ncols) dacc += epi.apply(p, c, acc[r], in[r]);
       }
     }
   }

@@ -39,14 +39,18 @@ struct CovRowsOp {
   }
 };
 
+// Epilogues / prologues are split into load() (all global reads of an
+// element) and apply() (arithmetic and stores), so that a thread issues the
+// loads of a whole batch before its first store.
 template <typename T>
 struct StoreEpi {
   T* out;
   int64_t ld;
   int accumulate;
-  __device__ __forceinline__ double operator()(int64_t i, int c, T v) const {
-    if (accumulate) out[i * ld + c] += v;
-    else out[i * ld + c] = v;
+  struct In { T prev; };
+  __device__ __forceinline__ In load(int64_t i, int c) const { return In{accumulate ? out[i * ld + c] : T(0)}; }
+  __device__ __forceinline__ double apply(int64_t i, int c, T v, const In& x) const {
+    out[i * ld + c] = accumulate ? x.prev + v : v;
     return 0.0;
   }
 };
@@ -58,9 +62,13 @@ struct ProbeEpi {
   const double* D;
   const int* perm;
   uint64_t seed;
-  __device__ __forceinline__ double operator()(int64_t i, int c, double v) const {
-    if (c == 0) B[i * ld] = y[i];
-    else B[i * ld + c] = sqrt(D[i]) * rademacher(seed, STREAM_RHO, (uint64_t)(c - 1), (uint64_t)perm[i]) + v;
+  struct In { double a; int pi; };
+  __device__ __forceinline__ In load(int64_t i, int c) const {
+    return c == 0 ? In{y[i], 0} : In{D[i], perm[i]};
+  }
+  __device__ __forceinline__ double apply(int64_t i, int c, double v, const In& x) const {
+    if (c == 0) B[i * ld] = x.a;
+    else B[i * ld + c] = sqrt(x.a) * rademacher(seed, STREAM_RHO, (uint64_t)(c - 1), (uint64_t)x.pi) + v;
     return 0.0;
   }
 };
@@ -94,14 +102,18 @@ struct DivDPro {
   const T* S;
   int64_t ld;
   const double* D;
-  __device__ __forceinline__ T operator()(int64_t p, int c, double&) const { return (T)((double)S[p * ld + c] / D[p]); }
+  struct In { T s; double d; };
+  __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c], D[p]}; }
+  __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)((double)x.s / x.d); }
 };
 // X(p, c) = S[p][c]
 template <typename T, typename TS>
 struct PlainPro {
   const TS* S;
   int64_t ld;
-  __device__ __forceinline__ T operator()(int64_t p, int c, double&) const { return (T)S[p * ld + c]; }
+  struct In { TS s; };
+  __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c]}; }
+  __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)x.s; }
 };
 
 // ================================================================ build-time
@@ -466,20 +478,25 @@ struct PcgPass1Pro {
   const double* alpha;
   int64_t ld;
   int update;
-  __device__ __forceinline__ T operator()(int64_t p, int c, double& dot) const {
+  struct In { double u; T h, r, v; double d, a; };
+  __device__ __forceinline__ In load(int64_t p, int c) const {
+    int64_t o = p * ld + c;
+    if (update) return In{U[o], H[o], R[o], V[o], D[p], alpha[c]};
+    return In{0.0, T(0), R[o], T(0), D[p], 0.0};
+  }
+  __device__ __forceinline__ T apply(int64_t p, int c, const In& x, double& dot) const {
     int64_t o = p * ld + c;
     double r;
     if (update) {
-      double a = alpha[c];
-      U[o] += a * (double)H[o];
-      r = (double)R[o] - a * (double)V[o];
-      R[o] = (T)r;
-      r = (double)R[o];
+      U[o] = x.u + x.a * (double)x.h;
+      T rt = (T)((double)x.r - x.a * (double)x.v);
+      R[o] = rt;
+      r = (double)rt;
     } else {
-      r = (double)R[o];
+      r = (double)x.r;
     }
     dot += r * r;
-    return (T)(r / D[p]);
+    return (T)(r / x.d);
   }
 };
 
@@ -494,10 +511,12 @@ struct PcgPass2Epi {
   T* Q0;
   int64_t ld;
   int init;
-  __device__ __forceinline__ double operator()(int64_t i, int c, T v) const {
+  struct In { T r; double d; };
+  __device__ __forceinline__ In load(int64_t i, int c) const { return In{R[i * ld + c], D[i]}; }
+  __device__ __forceinline__ double apply(int64_t i, int c, T v, const In& x) const {
     int64_t o = i * ld + c;
-    double r = (double)R[o];
-    double qv = (r - (double)v) / D[i];
+    double r = (double)x.r;
+    double qv = (r - (double)v) / x.d;
     if (init) {
       H[o] = (T)qv;
       P[o] = v;
@@ -517,11 +536,15 @@ struct PcgSpmmEpi {
   T* V;
   int64_t ld;
   int has_p;
-  __device__ __forceinline__ double operator()(int64_t i, int c, T acc) const {
+  struct In { T h, p; };
+  __device__ __forceinline__ In load(int64_t i, int c) const {
     int64_t o = i * ld + c;
-    double v = (double)acc + (has_p ? (double)P[o] : 0.0);
-    V[o] = (T)v;
-    return (double)H[o] * (double)V[o];
+    return In{H[o], has_p ? P[o] : T(0)};
+  }
+  __device__ __forceinline__ double apply(int64_t i, int c, T acc, const In& x) const {
+    T v = (T)((double)acc + (double)x.p);
+    V[i * ld + c] = v;
+    return (double)x.h * (double)v;
   }
 };
 
