@@ -630,6 +630,216 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad) {
   return FSA_OK;
 }
 
+// ---------------------------------------------------------------- sparse block PCG
+// Sigma~_s W = B with the diagonal preconditioner D_s (Section 3.3), every
+// column independent; W (float64, n x ld) receives the solutions.
+template <typename T>
+static fsa_status run_sparse_pcg(fsa_ctx* c, const double* B, int ncols, int ld, double* W, int* iters_max) {
+  hipStream_t st = c->st;
+  const int64_t n = c->n;
+  const int max_iter = c->opt.fixed_iter > 0 ? c->opt.fixed_iter : c->opt.max_iter;
+  const int ldw = (int)round_up(ncols, 64);
+  size_t blk = (size_t)n * ld;
+  Buf<T> mem;
+  FSA_TRY(mem.alloc(6 * blk));
+  PcgBlock<T> b;
+  b.n = n;
+  b.ncols = ncols;
+  b.ld = ld;
+  b.ldw = ldw;
+  b.max_iter = max_iter;
+  b.R = mem.p;
+  b.H = mem.p + blk;
+  b.V = mem.p + 2 * blk;
+  b.P = mem.p + 3 * blk;
+  b.Tt = mem.p + 4 * blk;
+  b.Q0 = mem.p + 5 * blk;
+  b.U = W;
+  Buf<double> colb, hist;
+  Buf<int> coli;
+  FSA_TRY(colb.alloc(8 * (size_t)ldw));
+  FSA_TRY(coli.alloc(2 * (size_t)ldw + 4));
+  FSA_TRY(hist.alloc(2 * (size_t)max_iter * ncols));
+  b.rz = colb.p;
+  b.rz0 = colb.p + ldw;
+  b.alpha = colb.p + 2 * ldw;
+  b.beta = colb.p + 3 * ldw;
+  b.rr = colb.p + 4 * ldw;
+  b.bn2 = colb.p + 5 * ldw;
+  b.active = coli.p;
+  b.iters = coli.p + ldw;
+  b.flags = coli.p + 2 * ldw;
+  b.alpha_hist = hist.p;
+  b.beta_hist = hist.p + (size_t)max_iter * ncols;
+  OpDesc<T> op;
+  op.grid = &c->grid;
+  op.S = &c->csr;
+  op.D = c->D.p;
+  op.kdim = 0;
+  if constexpr (sizeof(T) == 8) op.val = reinterpret_cast<const T*>(c->vals.p);
+  else op.val = reinterpret_cast<const T*>(c->valsf.p);
+  OpDesc<double> op64;
+  op64.grid = &c->grid;
+  op64.S = &c->csr;
+  op64.val = c->vals.p;
+  op64.D = c->D.p;
+  op64.kdim = 0;
+  const double tol = c->opt.cg_rel_tol;
+  const int fixed = c->opt.fixed_iter > 0 ? 1 : 0;
+  FSA_TRY(pcg_init<T>(b, op, B, tol, c->scr, st));
+  int flags[2] = {0, 0};
+  for (int it = 0; it < max_iter; ++it) {
+    FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
+    if constexpr (sizeof(T) == 4) {
+      if (c->opt.rr_period > 0 && (it + 1) % c->opt.rr_period == 0 && it + 1 < max_iter)
+        FSA_TRY(pcg_replace_residual_f32(reinterpret_cast<PcgBlock<float>&>(b), op64,
+                                         reinterpret_cast<const OpDesc<float>&>(op), B, c->scr, st));
+    }
+    if (!fixed && ((it + 1) % 4 == 0 || it + 1 == max_iter)) {
+      FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      FSA_HIP(hipStreamSynchronize(st));
+      if (flags[1] || flags[0] == 0) break;
+    }
+  }
+  FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  std::vector<int> its(ncols);
+  FSA_HIP(hipMemcpyAsync(its.data(), b.iters, ncols * sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  int mx = 0;
+  for (int k = 0; k < ncols; ++k) mx = std::max(mx, its[k]);
+  if (iters_max) *iters_max = mx;
+  if (flags[1]) {
+    set_error("CG breakdown in a Sigma~_s solve");
+    return FSA_ERR_BREAKDOWN;
+  }
+  if (!fixed && flags[0] > 0) {
+    set_error("Sigma~_s PCG did not converge in %d iterations (%d columns active)", max_iter, flags[0]);
+    return FSA_ERR_NOT_CONVERGED;
+  }
+  return FSA_OK;
+}
+
+// Algorithm 1 with the whitened factors: A = L_m^{-1} Sigma_mn (training),
+// A_p = L_m^{-1} Sigma_{m n_p}, V~ = Sigma~_s^{-1} A^T and
+// M~ = I + A V~ (= L_m^{-1} M L_m^{-T}), so that
+//   D1 = diag(A_p^T A_p) - diag(A_p^T M~^{-1} A_p),
+//   D2 = diag(S_p^T V~ M~^{-1} A_p),  D3 = diag(S_p^T V~ M~^{-1} V~^T S_p),
+// S_p = Sigma^s_{n n_p}; D_l by simulation with Rademacher z (Algorithm 1).
+static fsa_status predict_core(fsa_ctx* c, const double* pred_locs_h, int64_t n_p, int s, double* var_out,
+                               double* mean_out, fsa_stats* st_out, double* parts_out) {
+  double t0 = now_ms();
+  hipStream_t st = c->st;
+  const int64_t n = c->n;
+  const int mp = c->mp;
+  Buf<double> pl;
+  FSA_TRY(pl.alloc(2 * (size_t)n_p));
+  FSA_HIP(hipMemcpyAsync(pl.p, pred_locs_h, 2 * n_p * sizeof(double), hipMemcpyHostToDevice, st));
+  Buf<int> bad;
+  FSA_TRY(bad.alloc(1));
+  FSA_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_count_bad, dim3(ceil_div(2 * n_p, 256)), dim3(256), 0, st, pl.p, 2 * n_p, bad.p);
+  int hbad = 0;
+  FSA_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (hbad) { set_error("non-finite prediction location"); return FSA_ERR_INVALID_ARG; }
+  Grid pg;
+  FSA_TRY(build_grid(pg, pl.p, n_p, c->gamma, st, nullptr, &c->grid));
+  Csr cPT, cTP;
+  FSA_TRY(build_pattern(pg, c->grid, cPT, st));
+  FSA_TRY(build_pattern(c->grid, pg, cTP, st));
+  // whitened prediction factor and the cross residual values
+  Buf<double> Ap, vPT, vTP;
+  FSA_TRY(Ap.alloc((size_t)n_p * mp));
+  FSA_TRY(vPT.alloc(cPT.nnz));
+  FSA_TRY(vTP.alloc(cTP.nnz));
+  FSA_TRY(whiten(pg.xs.p, n_p, c->ind.p, c->m, mp, c->th, c->LminvT.p, 0, Ap.p, st));
+  FSA_TRY(residual_values(pg, c->grid, cPT, Ap.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, false, false, vPT.p,
+                          nullptr, st));
+  FSA_TRY(residual_values(c->grid, pg, cTP, c->A.p, Ap.p, nullptr, nullptr, mp, c->th, c->gamma, false, false, vTP.p,
+                          nullptr, st));
+  // right-hand sides [A^T | S_p z^(1)]
+  const int ncols = mp + s;
+  const int ld = (int)round_up(ncols, 4);
+  const int lds = (int)round_up(s, 4);
+  Buf<double> B, W, Z1;
+  FSA_TRY(B.alloc((size_t)n * ld));
+  FSA_TRY(W.alloc((size_t)n * ld));
+  FSA_TRY(Z1.alloc((size_t)n_p * lds));
+  FSA_HIP(hipMemsetAsync(Z1.p, 0, (size_t)n_p * lds * sizeof(double), st));
+  FSA_TRY((copy_block<double, double>(c->A.p, mp, B.p, ld, n, mp, st)));
+  FSA_TRY(pred_rademacher(pg.perm.p, n_p, s, c->opt.seed, Z1.p, lds, st));
+  FSA_TRY(spmm<double>(cTP, c->grid, pg, vTP.p, Z1.p, lds, s, B.p + mp, ld, false, st));
+  int its = 0;
+  double t1 = now_ms();
+  fsa_status ps = c->opt.precision == FSA_MIXED_FP32 ? run_sparse_pcg<float>(c, B.p, ncols, ld, W.p, &its)
+                                                      : run_sparse_pcg<double>(c, B.p, ncols, ld, W.p, &its);
+  if (ps != FSA_OK && ps != FSA_ERR_NOT_CONVERGED) return ps;
+  double t2 = now_ms();
+  // M~ = I + A V~ and its Cholesky factor
+  size_t mm = (size_t)mp * mp;
+  Buf<double> Mt, LMi, G;
+  FSA_TRY(Mt.alloc(mm));
+  FSA_TRY(LMi.alloc(mm));
+  FSA_TRY(G.alloc(mm));
+  FSA_TRY(c->scr.w.alloc(mm));
+  FSA_TRY(lowrank_reduce<double>(c->A.p, n, mp, W.p, ld, mp, nullptr, c->scr, Mt.p, mp, st));
+  FSA_TRY(add_identity(Mt.p, mp, st));
+  FSA_TRY(symmetrize(Mt.p, mp, st));
+  FSA_TRY(dense_cholesky(Mt.p, mp, c->info.p, st));
+  int info = 0;
+  FSA_HIP(hipMemcpyAsync(&info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (info) { set_error("Cholesky of I + A Sigma~_s^{-1} A^T failed at column %d", info - 1); return FSA_ERR_NOT_SPD; }
+  FSA_TRY(dense_tri_inverse(Mt.p, LMi.p, mp, st));
+  FSA_TRY(transpose_scale(LMi.p, G.p, mp, 1.0, st));
+  // Y = A_p L_M^{-T}, Z2 = (S_p^T V~) L_M^{-T}, Z_l = S_p^T W_l
+  Buf<double> Y, Y2, Z2, Zl;
+  FSA_TRY(Y.alloc((size_t)n_p * mp));
+  FSA_TRY(Y2.alloc((size_t)n_p * mp));
+  FSA_TRY(Z2.alloc((size_t)n_p * mp));
+  FSA_TRY(Zl.alloc((size_t)n_p * lds));
+  FSA_HIP(hipMemsetAsync(Zl.p, 0, (size_t)n_p * lds * sizeof(double), st));
+  FSA_TRY(lowrank_expand<double>(Ap.p, nullptr, n_p, mp, G.p, mp, mp, Y.p, mp, st));
+  FSA_TRY(spmm<double>(cPT, pg, c->grid, vPT.p, W.p, ld, mp, Y2.p, mp, false, st));
+  FSA_TRY(lowrank_expand<double>(Y2.p, nullptr, n_p, mp, G.p, mp, mp, Z2.p, mp, st));
+  FSA_TRY(spmm<double>(cPT, pg, c->grid, vPT.p, W.p + mp, ld, s, Zl.p, lds, false, st));
+  Buf<double> vdev;
+  FSA_TRY(vdev.alloc(n_p));
+  Buf<double> pdev;
+  if (parts_out) FSA_TRY(pdev.alloc(4 * (size_t)n_p));
+  FSA_TRY(pred_combine(n_p, mp, Ap.p, Y.p, Z2.p, Z1.p, Zl.p, lds, s, c->th.s1, c->th.s2, pg.perm.p, vdev.p,
+                       parts_out ? pdev.p : nullptr, st));
+  FSA_HIP(hipMemcpyAsync(var_out, vdev.p, n_p * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (parts_out) FSA_HIP(hipMemcpyAsync(parts_out, pdev.p, 4 * n_p * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (mean_out) {
+    // mu = A_p (A u) + S_p^T u, u = Sigma~_dagger^{-1} y from the last likelihood solve
+    Buf<double> wu, su, mdev;
+    FSA_TRY(wu.alloc((size_t)mp * 64));
+    FSA_TRY(su.alloc((size_t)n_p * 4));
+    FSA_TRY(mdev.alloc(n_p));
+    FSA_TRY(lowrank_reduce<double>(c->A.p, n, mp, c->U.p, c->ld, 1, nullptr, c->scr, wu.p, 64, st));
+    FSA_TRY(spmm<double>(cPT, pg, c->grid, vPT.p, c->U.p, c->ld, 1, su.p, 1, false, st));
+    Buf<double> wcol;
+    FSA_TRY(wcol.alloc(mp));
+    FSA_TRY((copy_block<double, double>(wu.p, 64, wcol.p, 1, mp, 1, st)));
+    FSA_TRY(pred_mean(n_p, mp, Ap.p, wcol.p, su.p, pg.perm.p, mdev.p, st));
+    FSA_HIP(hipMemcpyAsync(mean_out, mdev.p, n_p * sizeof(double), hipMemcpyDeviceToHost, st));
+    FSA_HIP(hipStreamSynchronize(st));
+  }
+  FSA_HIP(hipStreamSynchronize(st));
+  double t3 = now_ms();
+  if (st_out) {
+    memset(st_out, 0, sizeof(*st_out));
+    st_out->iters_max = its;
+    st_out->ms_build = t1 - t0;
+    st_out->ms_pcg = t2 - t1;
+    st_out->ms_backward = t3 - t2;
+    st_out->ms_total = t3 - t0;
+    st_out->nnz = cPT.nnz;
+  }
+  return ps;
+}
+
 extern "C" {
 
 fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double* grad, fsa_stats* st_out) {
@@ -766,10 +976,12 @@ fsa_status fsa_apply(fsa_ctx* c, int32_t which, const double* X, double* Y, int3
 }
 
 fsa_status fsa_predict_var(fsa_ctx* c, const double* pred_locs, int64_t n_p, int32_t num_samples, double* var_out,
-                           double* mean_out, fsa_stats* st) {
-  (void)c; (void)pred_locs; (void)n_p; (void)num_samples; (void)var_out; (void)mean_out; (void)st;
-  set_error("fsa_predict_var: not built yet");
-  return FSA_ERR_INVALID_ARG;
+                           double* mean_out, fsa_stats* st_out) {
+  if (!c || !pred_locs || !var_out) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (n_p < 1 || n_p > (int64_t)INT32_MAX / 2) { set_error("n_p out of range"); return FSA_ERR_INVALID_ARG; }
+  if (num_samples < 1 || num_samples > 4096) { set_error("num_samples must be in [1, 4096]"); return FSA_ERR_INVALID_ARG; }
+  if (mean_out && !c->solved) { set_error("the predictive mean needs a preceding fsa_nll_grad"); return FSA_ERR_INVALID_ARG; }
+  return predict_core(c, pred_locs, n_p, num_samples, var_out, mean_out, st_out, nullptr);
 }
 
 }  // extern "C"

@@ -340,6 +340,10 @@ template <typename T, bool DOT, class Epi>
 static fsa_status launch_spmm_cell(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx,
                                    int ncols, const Epi& epi, double* dot_part, int ld_dot, hipStream_t st) {
   if (rg.ncell == 0) return FSA_OK;
+  if ((ldx & 3) || (reinterpret_cast<uintptr_t>(X) & 15)) {
+    set_error("spmm: block rows must be 16-byte aligned (ld multiple of 4)");
+    return FSA_ERR_INVALID_ARG;
+  }
   int CH = spmm_ch(sizeof(T));
   size_t smem = (size_t)CH * 64 * sizeof(T);
   dim3 grid(rg.ncell, ceil_div(ncols, 64));
@@ -837,17 +841,20 @@ __global__ void k_residual_f32(int64_t n, int ncols, int64_t ld, const double* _
 fsa_status pcg_replace_residual_f32(PcgBlock<float>& b, const OpDesc<double>& op64, const OpDesc<float>& op32,
                                     const double* B, Scratch& s, hipStream_t st) {
   (void)op32;
-  Buf<double> SU, LU, G;
+  Buf<double> SU, LU;
   FSA_TRY(SU.alloc((size_t)b.n * b.ld));
   FSA_TRY(LU.alloc((size_t)b.n * b.ld));
   FSA_TRY(spmm<double>(*op64.S, *op64.grid, *op64.grid, op64.val, b.U, b.ld, b.ncols, SU.p, b.ld, false, st));
-  FSA_TRY(lowrank_reduce<double>(op64.A, b.n, op64.kdim, b.U, b.ld, b.ncols, nullptr, s, s.w.p, b.ldw, st));
-  FSA_TRY(lowrank_expand<double>(op64.A, nullptr, b.n, op64.kdim, s.w.p, b.ldw, b.ncols, LU.p, b.ld, st));
+  if (op64.kdim > 0) {
+    FSA_TRY(lowrank_reduce<double>(op64.A, b.n, op64.kdim, b.U, b.ld, b.ncols, nullptr, s, s.w.p, b.ldw, st));
+    FSA_TRY(lowrank_expand<double>(op64.A, nullptr, b.n, op64.kdim, s.w.p, b.ldw, b.ncols, LU.p, b.ld, st));
+  } else {
+    FSA_HIP(hipMemsetAsync(LU.p, 0, (size_t)b.n * b.ld * sizeof(double), st));
+  }
   int64_t tot = b.n * b.ncols;
   hipLaunchKernelGGL(k_residual_f32, dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, B, SU.p,
                      LU.p, b.R);
   FSA_HIP(hipGetLastError());
-  FSA_HIP(hipStreamSynchronize(st));
   return FSA_OK;
 }
 
@@ -1059,6 +1066,107 @@ fsa_status scal_block(double* X, int ld, int64_t n, int ncols, double a, hipStre
   int64_t tot = n * ncols;
   if (tot == 0) return FSA_OK;
   hipLaunchKernelGGL(k_scal_block, dim3(ceil_div(tot, 256)), dim3(256), 0, st, X, ld, n, ncols, a);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// ================================================================ predictive variances
+// Z[p][c] = Rademacher(seed, stream 2, column c, original index perm[p]) (Algorithm 1 z^(1))
+__global__ void k_pred_rademacher(const int* __restrict__ perm, int64_t np, int s, uint64_t seed, double* __restrict__ Z,
+                                  int ldz) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / s;
+  int c = (int)(e % s);
+  if (p >= np) return;
+  Z[p * ldz + c] = rademacher(seed, STREAM_PRED, (uint64_t)c, (uint64_t)perm[p]);
+}
+
+fsa_status pred_rademacher(const int* perm, int64_t np, int s, uint64_t seed, double* Z, int ldz, hipStream_t st) {
+  int64_t tot = np * s;
+  if (tot == 0) return FSA_OK;
+  hipLaunchKernelGGL(k_pred_rademacher, dim3(ceil_div(tot, 256)), dim3(256), 0, st, perm, np, s, seed, Z, ldz);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// One wave per prediction point (sorted slot p):
+// D1 = |a|^2 - |y|^2, D2 = z . y, D3 = |z|^2 with a = A_p row, y = L_M^{-1} a,
+// z = L_M^{-1} (S_p^T V~) row; D_l = mean_c z1_c (S_p^T W_l)_c; the variance
+// sigma1^2 + sigma^2 - D1 - 2 D2 + D3 - D_l goes to the caller's slot perm[p].
+__global__ __launch_bounds__(256) void k_pred_combine(int64_t np, int mp, const double* __restrict__ Ap,
+                                                      const double* __restrict__ Y, const double* __restrict__ Z2,
+                                                      const double* __restrict__ Z1, const double* __restrict__ Zl,
+                                                      int ldl, int s, double s1, double s2, const int* __restrict__ perm,
+                                                      double* __restrict__ var_out, double* __restrict__ parts) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= np) return;
+  double aa = 0, yy = 0, zy = 0, zz = 0, dl = 0;
+  for (int k = lane; k < mp; k += 64) {
+    double a = Ap[p * mp + k], y = Y[p * mp + k], z = Z2[p * mp + k];
+    aa += a * a;
+    yy += y * y;
+    zy += z * y;
+    zz += z * z;
+  }
+  for (int c = lane; c < s; c += 64) dl += Z1[p * ldl + c] * Zl[p * ldl + c];
+  aa = wave_sum(aa);
+  yy = wave_sum(yy);
+  zy = wave_sum(zy);
+  zz = wave_sum(zz);
+  dl = wave_sum(dl);
+  if (lane == 0) {
+    double D1 = aa - yy, D2 = zy, D3 = zz, Dl = s > 0 ? dl / s : 0.0;
+    int o = perm[p];
+    var_out[o] = s1 + s2 - D1 - 2.0 * D2 + D3 - Dl;
+    if (parts) {
+      parts[4 * (int64_t)o + 0] = D1;
+      parts[4 * (int64_t)o + 1] = D2;
+      parts[4 * (int64_t)o + 2] = D3;
+      parts[4 * (int64_t)o + 3] = Dl;
+    }
+  }
+}
+
+fsa_status pred_combine(int64_t np, int mp, const double* Ap, const double* Y, const double* Z2, const double* Z1,
+                        const double* Zl, int ldl, int s, double s1, double s2, const int* perm, double* var_out,
+                        double* parts, hipStream_t st) {
+  hipLaunchKernelGGL(k_pred_combine, dim3(ceil_div(np, 4)), dim3(256), 0, st, np, mp, Ap, Y, Z2, Z1, Zl, ldl, s, s1, s2,
+                     perm, var_out, parts);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// mean[perm[p]] = A_p row . w + (S_p^T u)_p
+__global__ void k_pred_mean(int64_t np, int mp, const double* __restrict__ Ap, const double* __restrict__ w,
+                            const double* __restrict__ su, const int* __restrict__ perm, double* __restrict__ out) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  double v = su[p];
+  for (int k = 0; k < mp; ++k) v += Ap[p * mp + k] * w[k];
+  out[perm[p]] = v;
+}
+
+fsa_status pred_mean(int64_t np, int mp, const double* Ap, const double* w, const double* su, const int* perm,
+                     double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pred_mean, dim3(ceil_div(np, 256)), dim3(256), 0, st, np, mp, Ap, w, su, perm, out);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+__global__ void k_symmetrize(double* A, int n) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  int i = (int)(e / n), j = (int)(e % n);
+  if (j < i) {
+    double v = 0.5 * (A[(int64_t)i * n + j] + A[(int64_t)j * n + i]);
+    A[(int64_t)i * n + j] = v;
+    A[(int64_t)j * n + i] = v;
+  }
+}
+
+fsa_status symmetrize(double* A, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(ceil_div((int64_t)n * n, 256)), dim3(256), 0, st, A, n);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }

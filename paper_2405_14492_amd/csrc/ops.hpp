@@ -147,6 +147,15 @@ fsa_status slq_terms(const double* alpha_hist, const double* beta_hist, const in
 fsa_status make_probes(const double* A, int64_t n, int m, int mp, const double* D, const double* y, const int* perm,
                        uint64_t seed, int nprobe, double* B, int ldb, double* Emat, hipStream_t st);
 
+// predictive variances (Algorithm 1)
+fsa_status pred_rademacher(const int* perm, int64_t np, int s, uint64_t seed, double* Z, int ldz, hipStream_t st);
+fsa_status pred_combine(int64_t np, int mp, const double* Ap, const double* Y, const double* Z2, const double* Z1,
+                        const double* Zl, int ldl, int s, double s1, double s2, const int* perm, double* var_out,
+                        double* parts, hipStream_t st);
+fsa_status pred_mean(int64_t np, int mp, const double* Ap, const double* w, const double* su, const int* perm,
+                     double* out, hipStream_t st);
+fsa_status symmetrize(double* A, int n, hipStream_t st);
+
 // elementwise helpers
 template <typename TI, typename TO>
 fsa_status copy_block(const TI* in, int ldi, TO* out, int ldo, int64_t n, int ncols, hipStream_t st);

@@ -168,3 +168,37 @@ def test_mixed_precision_matches_oracle(F, name):
     assert abs(nll - ref["nll"]) <= 1e-4 * abs(ref["nll"])
     gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
     assert np.all(np.abs(grad - ref["grad"]) <= 1e-4 * gscale), (grad, ref["grad"])
+
+
+@pytest.mark.parametrize("name", ["exp_n700_m40", "m32_n1500_m100", "exp_clustered_n2000_m70", "ragged_n333_m7"])
+def test_predictive_variances_match_oracle(F, name):
+    """Algorithm 1 (float64, tight tolerance, identical Rademacher draws) and
+    the predictive mean; includes prediction points outside the training
+    region and far from every training point."""
+    say("case", name)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    pred = np.vstack([G.uniform_locations(257, 900), [[1.3, 0.5], [-0.2, -0.2], [0.5, 0.5], [5.0, 5.0]]])
+    mdl = O.FSA(locs, ind, theta, gamma)
+    u = O.pcg_lanczos(mdl.matvec, mdl.precond_solve, y[:, None], 1e-13, 3000).U[:, 0]
+    ref_var, det = O.predict_var(mdl, pred, 16, 21, tol=1e-12, max_iter=3000, u=u)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=2, seed=21, tol=1e-12, max_iter=3000) as f:
+        f.nll_grad(with_grad=False)
+        var, mean, st = f.predict_var(pred, 16, with_mean=True)
+    err = np.abs(var - ref_var).max() / np.abs(ref_var).max()
+    merr = np.abs(mean - det["mean"]).max() / np.abs(det["mean"]).max()
+    say("var err", err, "mean err", merr, "iters", st["iters_max"])
+    assert err < 1e-9
+    assert merr < 1e-9
+
+
+def test_predictive_variances_mixed_precision(F):
+    locs, y, theta, ind, gamma = case(**CASES["m32_n1500_m100"])
+    pred = G.uniform_locations(300, 901)
+    mdl = O.FSA(locs, ind, theta, gamma)
+    ref_var, _ = O.predict_var(mdl, pred, 16, 22, tol=1e-12, max_iter=3000)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=2, seed=22, tol=1e-7, max_iter=3000,
+               precision=F.MIXED_FP32) as f:
+        var, _, _ = f.predict_var(pred, 16)
+    err = np.abs(var - ref_var) / np.abs(ref_var)
+    say("mixed var rel err max", err.max())
+    assert err.max() < 1e-4
