@@ -102,6 +102,10 @@ typedef struct {
    * [4] small reductions and m-space products */
   double kernel_ms[5];
   int32_t kernel_launches[5];
+  /* gradient parts: trace estimate (1/t) sum_i (Sigma~^{-1} z_i)^T dSigma~ P^{-1} z_i
+   * and quadratic term u^T dSigma~ u (u = Sigma~^{-1} y), order (sigma1^2, rho, sigma^2) */
+  double grad_trace[3];
+  double grad_quad[3];
 } fsa_stats;
 
 /* Default options: 50 probes, seed 0, tol 1e-8, max_iter 1000, FP64. */
@@ -140,6 +144,13 @@ fsa_status fsa_build_dev(const double* locs_dev, int64_t n, int32_t d, const dou
  * Errors: INVALID_ARG, NOT_SPD, BREAKDOWN, NOT_CONVERGED (outputs written),
  * DEVICE. */
 fsa_status fsa_nll_grad(fsa_ctx* ctx, const fsa_theta* theta, double* nll, double* grad, fsa_stats* st);
+
+/* Gradient of the NLL of the preceding fsa_nll_grad call on this context
+ * (eq. NEGLLDNEGLLFSA, trace by stochastic estimation with P^{-1} z,
+ * Section 3.3), from the solves that call retained: the backward pass of the
+ * likelihood.  grad: host [3] out, order (sigma1^2, rho, sigma^2).
+ * Errors: INVALID_ARG (no preceding solve), DEVICE. */
+fsa_status fsa_grad(fsa_ctx* ctx, double* grad, fsa_stats* st);
 
 /* Predictive variances diag(Sigma^p_dagger) (eq. MuPredFSA, nugget
  * included) by Algorithm 1 with num_samples Rademacher vectors; Sigma~_s

@@ -603,7 +603,7 @@ static fsa_status apply_drho(fsa_ctx* c, const double* X, double* Y, int ncols, 
   return FSA_OK;
 }
 
-static fsa_status run_gradient(fsa_ctx* c, double* grad) {
+static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   hipStream_t st = c->st;
   const int64_t n = c->n;
   const int tp = c->tp, ld = c->ld;
@@ -627,6 +627,8 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad) {
   FSA_HIP(hipStreamSynchronize(st));
   (void)dots;
   for (int k = 0; k < 3; ++k) grad[k] = g9[k];
+  if (parts6)
+    for (int k = 0; k < 6; ++k) parts6[k] = g9[3 + k];
   return FSA_OK;
 }
 
@@ -875,8 +877,13 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
   *nll = fin[2];
   double t_b0 = now_ms();
   if (grad) {
-    fsa_status gs = run_gradient(c, grad);
+    double parts6[6];
+    fsa_status gs = run_gradient(c, grad, parts6);
     if (gs != FSA_OK) return gs;
+    for (int k = 0; k < 3; ++k) {
+      c->stats.grad_trace[k] = parts6[k];
+      c->stats.grad_quad[k] = parts6[3 + k];
+    }
   }
   double t1 = now_ms();
   c->stats.logdet = fin[0];
@@ -889,6 +896,21 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
   c->stats.nnz = c->csr.nnz;
   if (st_out) *st_out = c->stats;
   return s;
+}
+
+fsa_status fsa_grad(fsa_ctx* c, double* grad, fsa_stats* st_out) {
+  if (!c || !grad) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (!c->solved) { set_error("fsa_grad needs a preceding fsa_nll_grad on this context"); return FSA_ERR_INVALID_ARG; }
+  double t0 = now_ms();
+  double parts6[6];
+  FSA_TRY(run_gradient(c, grad, parts6));
+  for (int k = 0; k < 3; ++k) {
+    c->stats.grad_trace[k] = parts6[k];
+    c->stats.grad_quad[k] = parts6[3 + k];
+  }
+  c->stats.ms_backward = now_ms() - t0;
+  if (st_out) *st_out = c->stats;
+  return FSA_OK;
 }
 
 fsa_status fsa_export_csr(fsa_ctx* c, int64_t* row_ptr, int32_t* col_idx, double* vals) {

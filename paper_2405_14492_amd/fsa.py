@@ -26,7 +26,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "NOT_SPD", 4: "NOT_CONVERGED",
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfsa.so")
 
-EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad", "fsa_predict_var", "fsa_destroy",
+EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad", "fsa_grad", "fsa_predict_var",
+            "fsa_destroy",
             "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_apply", "fsa_pool_trim"]
 
 
@@ -57,12 +58,13 @@ class fsa_stats(C.Structure):
                 ("rel_res_max", C.c_double), ("logdet", C.c_double), ("logdet_P", C.c_double),
                 ("quad", C.c_double), ("ms_build", C.c_double), ("ms_pcg", C.c_double),
                 ("ms_backward", C.c_double), ("ms_total", C.c_double), ("nnz", C.c_int64),
-                ("kernel_ms", C.c_double * 5), ("kernel_launches", C.c_int32 * 5)]
+                ("kernel_ms", C.c_double * 5), ("kernel_launches", C.c_int32 * 5),
+                ("grad_trace", C.c_double * 3), ("grad_quad", C.c_double * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        d["kernel_ms"] = list(self.kernel_ms)
-        d["kernel_launches"] = list(self.kernel_launches)
+        for k in ("kernel_ms", "kernel_launches", "grad_trace", "grad_quad"):
+            d[k] = list(getattr(self, k))
         return d
 
 
@@ -82,6 +84,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         f.restype = C.c_int
     lib.fsa_nll_grad.argtypes = [vp, P(fsa_theta), dp, dp, P(fsa_stats)]
     lib.fsa_nll_grad.restype = C.c_int
+    lib.fsa_grad.argtypes = [vp, dp, P(fsa_stats)]
+    lib.fsa_grad.restype = C.c_int
     lib.fsa_predict_var.argtypes = [vp, dp, C.c_int64, C.c_int32, dp, dp, P(fsa_stats)]
     lib.fsa_predict_var.restype = C.c_int
     lib.fsa_destroy.argtypes = [vp]
@@ -186,6 +190,13 @@ def fsa_nll_grad(ctx, theta=None, with_grad=True, allow_not_converged=False):
     return nll.value, (g if with_grad else None), st.as_dict()
 
 
+def fsa_grad(ctx):
+    g = np.zeros(3)
+    st = fsa_stats()
+    _check(lib().fsa_grad(ctx, _dptr(g), C.byref(st)))
+    return g, st.as_dict()
+
+
 def fsa_predict_var(ctx, pred_locs, num_samples, with_mean=False, allow_not_converged=False):
     P = _f64(pred_locs)
     var = np.zeros(P.shape[0])
@@ -260,6 +271,9 @@ class FSA:
         if theta is not None:
             self.theta = tuple(theta)
         return out
+
+    def grad(self):
+        return fsa_grad(self.ctx)
 
     def predict_var(self, pred_locs, num_samples, with_mean=False, allow_not_converged=False):
         return fsa_predict_var(self.ctx, pred_locs, num_samples, with_mean, allow_not_converged)
