@@ -42,10 +42,18 @@ def fit_lbfgs(model: "F.FSA", theta0, cov: int, steps: int = 20, lr: float = 1.0
 
     def closure():
         opt.zero_grad()
-        val = fsa_nll(phi.exp(), model, cov)
-        val.backward()
-        trace.append((float(val), phi.detach().exp().tolist()))
-        return val
+        th = phi.exp()
+        try:
+            val = fsa_nll(th, model, cov)
+            val.backward()
+        except F.FsaError as e:
+            # an infeasible trial point (e.g. breakdown at an extreme step):
+            # report +inf so the line search backs off
+            trace.append((float("inf"), th.detach().tolist(), str(e)))
+            phi.grad = torch.zeros_like(phi)
+            return phi.new_tensor(float("inf"))
+        trace.append((float(val), th.detach().tolist()))
+        return val.detach()
 
     for _ in range(steps):
         opt.step(closure)
