@@ -173,7 +173,7 @@ struct fsa_ctx {
   Csr csr;
   Buf<double> ind, y;
   Buf<double> Sm, Lm, Lminv, LminvT, C, LCinv, Cinv;
-  Buf<double> A, vals, D;
+  Buf<double> A, vals, D, Dinv;
   Buf<float> Af, valsf;
   Buf<double> logdet_parts;  // [0] = 2 sum log diag L_C, [1] = sum log D
   Buf<int> info;
@@ -233,6 +233,7 @@ static fsa_status build_values(fsa_ctx* c) {
   FSA_TRY(whiten(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->LminvT.p, 0, c->A.p, st));
   FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, true, false,
                           c->vals.p, c->D.p, st));
+  FSA_TRY(reciprocal(c->D.p, c->Dinv.p, c->n, st));
   FSA_TRY(capacitance(c->A.p, c->D.p, c->n, mp, c->C.p, c->scr, st));
   // C -> L_C (in place), L_C^{-1}, C^{-1} = L_C^{-T} L_C^{-1}
   FSA_TRY(dense_cholesky(c->C.p, mp, c->info.p, st));
@@ -299,6 +300,7 @@ static fsa_status build_core(fsa_ctx* c, const double* locs, const double* y, co
   FSA_TRY(c->A.alloc((size_t)n * mp));
   FSA_TRY(c->vals.alloc(c->csr.nnz));
   FSA_TRY(c->D.alloc(n));
+  FSA_TRY(c->Dinv.alloc(n));
   FSA_TRY(c->logdet_parts.alloc(2));
   if (c->opt.precision == FSA_MIXED_FP32) {
     FSA_TRY(c->Af.alloc((size_t)n * mp));
@@ -456,6 +458,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   op.grid = &c->grid;
   op.S = &c->csr;
   op.D = c->D.p;
+  op.Dinv = c->Dinv.p;
   op.kdim = mp;
   op.Cinv = c->Cinv.p;
   OpDesc<double> op64;
@@ -463,6 +466,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   op64.S = &c->csr;
   op64.val = c->vals.p;
   op64.D = c->D.p;
+  op64.Dinv = c->Dinv.p;
   op64.A = c->A.p;
   op64.kdim = mp;
   op64.Cinv = c->Cinv.p;
@@ -677,6 +681,7 @@ static fsa_status run_sparse_pcg(fsa_ctx* c, const double* B, int ncols, int ld,
   op.grid = &c->grid;
   op.S = &c->csr;
   op.D = c->D.p;
+  op.Dinv = c->Dinv.p;
   op.kdim = 0;
   if constexpr (sizeof(T) == 8) op.val = reinterpret_cast<const T*>(c->vals.p);
   else op.val = reinterpret_cast<const T*>(c->valsf.p);
@@ -685,6 +690,7 @@ static fsa_status run_sparse_pcg(fsa_ctx* c, const double* B, int ncols, int ld,
   op64.S = &c->csr;
   op64.val = c->vals.p;
   op64.D = c->D.p;
+  op64.Dinv = c->Dinv.p;
   op64.kdim = 0;
   const double tol = c->opt.cg_rel_tol;
   const int fixed = c->opt.fixed_iter > 0 ? 1 : 0;

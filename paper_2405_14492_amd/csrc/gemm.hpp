@@ -131,6 +131,101 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t nrows, int kdim, cons
   }
 }
 
+// ------------------------------------------------------------------ rows GEMM, float32, resident G
+// OUT(i, c) = sum_k A[i][k] G[k][c] for one 64-column block: the whole
+// kdim x 64 block of G (kdim <= 512) stays in LDS as [k/4][c][k%4], so a lane
+// fetches the four k of one MFMA group with one 16-byte read.  Waves are
+// persistent over 32-row tiles (no barrier in the main loop) and prefetch A
+// two 16-k steps ahead.
+template <bool DOT, class Epi>
+__global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim, const float* __restrict__ A,
+                                                        int64_t lda, const float* __restrict__ G, int ldg, int ncols,
+                                                        Epi epi, double* __restrict__ dot_part, int ld_dot) {
+  extern __shared__ __attribute__((aligned(16))) float gres[];
+  __shared__ double red[16][64];
+  typedef Mfma<float>::acc acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.y * 64;
+  for (int e = threadIdx.x; e < kdim * 64; e += blockDim.x) {
+    int k = e >> 6, cc = e & 63;
+    float v = (c0 + cc < ncols) ? G[(int64_t)k * ldg + c0 + cc] : 0.f;
+    gres[(((k >> 2) * 64 + cc) << 2) + (k & 3)] = v;
+  }
+  __syncthreads();
+  double dsum[4] = {0, 0, 0, 0};
+  const int64_t ntile = (nrows + 31) / 32;
+  for (int64_t tile = (int64_t)blockIdx.x * nw + w; tile < ntile; tile += (int64_t)gridDim.x * nw) {
+    const int64_t row0 = tile * 32;
+    const int64_t ia = min(row0 + r16, nrows - 1), ib = min(row0 + 16 + r16, nrows - 1);
+    const float* pa = A + ia * lda + 4 * q;
+    const float* pb = A + ib * lda + 4 * q;
+    acc_t acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    f4 fa0 = *reinterpret_cast<const f4*>(pa), fb0 = *reinterpret_cast<const f4*>(pb);
+    f4 fa1 = kdim > 16 ? *reinterpret_cast<const f4*>(pa + 16) : f4{0, 0, 0, 0};
+    f4 fb1 = kdim > 16 ? *reinterpret_cast<const f4*>(pb + 16) : f4{0, 0, 0, 0};
+    for (int ks = 0; ks < kdim; ks += 16) {
+      f4 ca = fa0, cb = fb0;
+      fa0 = fa1;
+      fb0 = fb1;
+      if (ks + 32 < kdim) {
+        fa1 = *reinterpret_cast<const f4*>(pa + ks + 32);
+        fb1 = *reinterpret_cast<const f4*>(pb + ks + 32);
+      }
+      f4 g[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) g[b] = *reinterpret_cast<const f4*>(&gres[((((ks >> 2) + q) * 64) + b * 16 + r16) << 2]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[0][b] = Mfma<float>::op(ca[j], g[b][j], acc[0][b]);
+          acc[1][b] = Mfma<float>::op(cb[j], g[b][j], acc[1][b]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      typename Epi::In in[4][4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int64_t i = row0 + a * 16 + Mfma<float>::orow(q, r);
+          int c = c0 + b * 16 + r16;
+          if (i < nrows && c < ncols) in[b][r] = epi.load(i, c);
+        }
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int64_t i = row0 + a * 16 + Mfma<float>::orow(q, r);
+          int c = c0 + b * 16 + r16;
+          if (i < nrows && c < ncols) dsum[b] += epi.apply(i, c, acc[a][b][r], in[b][r]);
+        }
+    }
+  }
+  if constexpr (DOT) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double v = dsum[b];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (q == 0) red[w][b * 16 + r16] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      double sacc = 0.0;
+      for (int k = 0; k < nw; ++k) sacc += red[k][threadIdx.x];
+      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + threadIdx.x] = sacc;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ reduce GEMM
 // grid: (nchunks, ncb = ceil(ncols/64), ceil(kdim / 512)); block 64*NW.
 // Partial tile layout: part[((chunk*ncb + cb)*nmb + mb)*4096 + (tile*4 + r)*64 + lane]

@@ -9,6 +9,7 @@ namespace fsa {
 constexpr int RT_ROWS = 2;  // row tiles per wave in k_rows_gemm
 
 static int64_t rows_grid(int64_t n) { return ceil_div(n, 64 * RT_ROWS); }
+static int64_t f32_rows_grid() { return 256; }
 
 // ================================================================ functors
 struct CovRowsOp {
@@ -105,6 +106,16 @@ struct DivDPro {
   struct In { T s; double d; };
   __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c], D[p]}; }
   __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)((double)x.s / x.d); }
+};
+// X(p, c) = S[p][c] * Dinv[p]
+template <typename T>
+struct MulDinvPro {
+  const T* S;
+  int64_t ld;
+  const double* Dinv;
+  struct In { T s; double d; };
+  __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c], Dinv[p]}; }
+  __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)((double)x.s * x.d); }
 };
 // X(p, c) = S[p][c]
 template <typename T, typename TS>
@@ -313,6 +324,15 @@ fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T*
                           int ldo, hipStream_t st) {
   StoreEpi<T> epi{OUT, ldo, 0};
   dim3 grid(rows_grid(n), ceil_div(ncols, 64));
+  if constexpr (sizeof(T) == 4) {
+    if (!A2 && kdim <= 512) {
+      hipLaunchKernelGGL((k_rows_gemm_f32<false, StoreEpi<T>>), dim3(f32_rows_grid(), ceil_div(ncols, 64)),
+                         dim3(1024), (size_t)kdim * 64 * sizeof(float), st, n, kdim, (const float*)A, (int64_t)kdim,
+                         (const float*)G, ldg, ncols, epi, (double*)nullptr, 0);
+      FSA_HIP(hipGetLastError());
+      return FSA_OK;
+    }
+  }
   if (A2) {
     Rows2Op<T> op{A, A2, kdim / 2, kdim / 2};
     hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, false, Rows2Op<T>, StoreEpi<T>>), grid, dim3(256), 0, st, n, kdim, G,
@@ -471,36 +491,25 @@ fsa_status mspace_apply(const double* M, const double* W, int ldw, int kdim, int
 #define KT_END(b, cls) \
   if ((b).timer) (b).timer->stop((cls), _kt, st)
 
-// Pass-1 prologue of an iteration: u += alpha h, r -= alpha v, |r|^2, X = r / D.
+// Pass-1 prologue of an iteration: r -= alpha v, |r|^2, X = r / D.
 template <typename T>
 struct PcgPass1Pro {
-  double* U;
-  const T* H;
   T* R;
   const T* V;
-  const double* D;
+  const double* Dinv;
   const double* alpha;
   int64_t ld;
-  int update;
-  struct In { double u; T h, r, v; double d, a; };
+  struct In { T r, v; double di, a; };
   __device__ __forceinline__ In load(int64_t p, int c) const {
     int64_t o = p * ld + c;
-    if (update) return In{U[o], H[o], R[o], V[o], D[p], alpha[c]};
-    return In{0.0, T(0), R[o], T(0), D[p], 0.0};
+    return In{R[o], V[o], Dinv[p], alpha[c]};
   }
   __device__ __forceinline__ T apply(int64_t p, int c, const In& x, double& dot) const {
-    int64_t o = p * ld + c;
-    double r;
-    if (update) {
-      U[o] = x.u + x.a * (double)x.h;
-      T rt = (T)((double)x.r - x.a * (double)x.v);
-      R[o] = rt;
-      r = (double)rt;
-    } else {
-      r = (double)x.r;
-    }
+    T rt = (T)((double)x.r - x.a * (double)x.v);
+    R[p * ld + c] = rt;
+    double r = (double)rt;
     dot += r * r;
-    return (T)(r / x.d);
+    return (T)(r * x.di);
   }
 };
 
@@ -509,18 +518,18 @@ template <typename T>
 struct PcgPass2Epi {
   T* Tt;
   const T* R;
-  const double* D;
+  const double* Dinv;
   T* H;
   T* P;
   T* Q0;
   int64_t ld;
   int init;
-  struct In { T r; double d; };
-  __device__ __forceinline__ In load(int64_t i, int c) const { return In{R[i * ld + c], D[i]}; }
+  struct In { T r; double di; };
+  __device__ __forceinline__ In load(int64_t i, int c) const { return In{R[i * ld + c], Dinv[i]}; }
   __device__ __forceinline__ double apply(int64_t i, int c, T v, const In& x) const {
     int64_t o = i * ld + c;
     double r = (double)x.r;
-    double qv = (r - (double)v) / x.d;
+    double qv = (r - (double)v) * x.di;
     if (init) {
       H[o] = (T)qv;
       P[o] = v;
@@ -554,8 +563,8 @@ struct PcgSpmmEpi {
 
 // Sparse-only variants (no low-rank part): elementwise
 template <typename T>
-__global__ __launch_bounds__(256) void k_pcg_sparse_update(int64_t n, int ncols, int64_t ld, double* U, const T* H, T* R,
-                                                           const T* V, const double* D, const double* alpha, int update,
+__global__ __launch_bounds__(256) void k_pcg_sparse_update(int64_t n, int ncols, int64_t ld, T* R, const T* V,
+                                                           const double* Dinv, const double* alpha, int update,
                                                            int init, T* Hout, T* Q0, double* rr_part,
                                                            double* rq_part, int ld_dot) {
   __shared__ double red1[4][64], red2[4][64];
@@ -567,15 +576,13 @@ __global__ __launch_bounds__(256) void k_pcg_sparse_update(int64_t n, int ncols,
       int64_t o = p * ld + c;
       double r;
       if (update) {
-        double a = alpha[c];
-        U[o] += a * (double)H[o];
-        r = (double)R[o] - a * (double)V[o];
-        R[o] = (T)r;
-        r = (double)R[o];
+        T rt = (T)((double)R[o] - alpha[c] * (double)V[o]);
+        R[o] = rt;
+        r = (double)rt;
       } else {
         r = (double)R[o];
       }
-      double qv = r / D[p];
+      double qv = r * Dinv[p];
       if (init) {
         Hout[o] = (T)qv;
         Q0[o] = (T)qv;
@@ -594,21 +601,28 @@ __global__ __launch_bounds__(256) void k_pcg_sparse_update(int64_t n, int ncols,
   }
 }
 
-// h = q + beta h with q = (r - t)/D (t = 0 when no low-rank part); p = t + beta p.
+// u += alpha h (the direction of this iteration), then h = q + beta h with
+// q = (r - t)/D (t = 0 when there is no low-rank part) and p = t + beta p.
 template <typename T>
 __global__ void k_pcg_hupdate(int64_t n, int ncols, int64_t ld, const T* __restrict__ R, const T* __restrict__ Tt,
-                              const double* __restrict__ D, const double* __restrict__ beta, T* __restrict__ H,
-                              T* __restrict__ P, int has_lr) {
+                              const double* __restrict__ Dinv, const double* __restrict__ alpha,
+                              const double* __restrict__ beta, T* __restrict__ H, T* __restrict__ P,
+                              double* __restrict__ U, int has_lr) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t p = e / ncols;
   int c = (int)(e % ncols);
   if (p >= n) return;
   int64_t o = p * ld + c;
-  double b = beta[c];
-  double t = has_lr ? (double)Tt[o] : 0.0;
-  double q = ((double)R[o] - t) / D[p];
-  H[o] = (T)(q + b * (double)H[o]);
-  if (has_lr) P[o] = (T)(t + b * (double)P[o]);
+  const double b = beta[c], a = alpha[c];
+  const double h = (double)H[o];
+  const double t = has_lr ? (double)Tt[o] : 0.0;
+  const double r = (double)R[o];
+  const double di = Dinv[p];
+  const double u = U[o];
+  const double pv = has_lr ? (double)P[o] : 0.0;
+  U[o] = u + a * h;
+  H[o] = (T)((r - t) * di + b * h);
+  if (has_lr) P[o] = (T)(t + b * pv);
 }
 
 __global__ void k_pcg_setup(int ncols, const double* __restrict__ bn2_part, int nb, int ldb, const double* __restrict__ rq_part,
@@ -700,16 +714,28 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
     FSA_TRY(mspace_apply<T>(op.Cinv, s.w.p, b.ldw, op.kdim, b.ncols, b.g, b.ldw, st));
     KT_END(b, KT_SMALL);
   }
-  PcgPass2Epi<T> epi{b.Tt, b.R, op.D, b.H, b.P, b.Q0, b.ld, init};
-  RowsOp<T> aop{op.A, op.kdim};
-  int64_t gx = rows_grid(b.n);
+  PcgPass2Epi<T> epi{b.Tt, b.R, op.Dinv, b.H, b.P, b.Q0, b.ld, init};
   int ncb = (int)ceil_div(b.ncols, 64);
-  size_t need = (size_t)gx * ncb * 64;
-  if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
-  KT_BEGIN(b);
-  hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, true, RowsOp<T>, PcgPass2Epi<T>>), dim3(gx, ncb), dim3(256), 0, st, b.n,
-                     op.kdim, b.g, b.ldw, b.ncols, 0, aop, epi, s.dot.p, ncb * 64);
-  KT_END(b, KT_PASS2);
+  int64_t gx;
+  if constexpr (sizeof(T) == 4) {
+    gx = f32_rows_grid();
+    size_t need = (size_t)gx * ncb * 64;
+    if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
+    KT_BEGIN(b);
+    hipLaunchKernelGGL((k_rows_gemm_f32<true, PcgPass2Epi<T>>), dim3(gx, ncb), dim3(1024),
+                       (size_t)op.kdim * 64 * sizeof(float), st, b.n, op.kdim, (const float*)op.A, (int64_t)op.kdim,
+                       (const float*)b.g, b.ldw, b.ncols, epi, s.dot.p, ncb * 64);
+    KT_END(b, KT_PASS2);
+  } else {
+    RowsOp<T> aop{op.A, op.kdim};
+    gx = rows_grid(b.n);
+    size_t need = (size_t)gx * ncb * 64;
+    if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
+    KT_BEGIN(b);
+    hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, true, RowsOp<T>, PcgPass2Epi<T>>), dim3(gx, ncb), dim3(256), 0, st,
+                       b.n, op.kdim, b.g, b.ldw, b.ncols, 0, aop, epi, s.dot.p, ncb * 64);
+    KT_END(b, KT_PASS2);
+  }
   FSA_HIP(hipGetLastError());
   nparts_rq = (int)gx;
   return FSA_OK;
@@ -725,9 +751,9 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
   if (op.kdim > 0) {
     ReduceShape r = reduce_shape(b.n, op.kdim, b.ncols);
     FSA_TRY(ensure_part<T>(s, r));
-    DivDPro<T> pro{b.R, b.ld, op.D};
+    MulDinvPro<T> pro{b.R, b.ld, op.Dinv};
     RowsOp<T> acol{op.A, op.kdim};
-    hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, DivDPro<T>>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads),
+    hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, MulDinvPro<T>>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads),
                        0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0, 0);
     FSA_HIP(hipGetLastError());
     FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
@@ -747,8 +773,8 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
     size_t need = (size_t)g * ncb * 64;
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
     if (s.dot2.count < need) FSA_TRY(s.dot2.alloc(need));
-    hipLaunchKernelGGL((k_pcg_sparse_update<T>), dim3(g, ncb), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, b.U,
-                       (const T*)b.H, b.R, (const T*)b.V, op.D, b.alpha, 0, 1, b.H, b.Q0, s.dot2.p, s.dot.p, ncb * 64);
+    hipLaunchKernelGGL((k_pcg_sparse_update<T>), dim3(g, ncb), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, b.R,
+                       (const T*)b.V, op.Dinv, b.alpha, 0, 1, b.H, b.Q0, s.dot2.p, s.dot.p, ncb * 64);
     FSA_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_pcg_setup, dim3(1), dim3(256), 0, st, b.ncols, s.dot2.p, (int)g, ncb * 64, s.dot.p, (int)g,
                        ncb * 64, b.bn2, b.rz, b.rz0, b.active, b.iters, b.flags);
@@ -785,7 +811,7 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     // 2. u += alpha h, r -= alpha v, |r|^2, W = A D^{-1} r
     ReduceShape r = reduce_shape(b.n, op.kdim, b.ncols);
     FSA_TRY(ensure_part<T>(s, r));
-    PcgPass1Pro<T> pro{b.U, b.H, b.R, b.V, op.D, b.alpha, b.ld, 1};
+    PcgPass1Pro<T> pro{b.R, b.V, op.Dinv, b.alpha, b.ld};
     RowsOp<T> acol{op.A, op.kdim};
     {
       KT_BEGIN(b);
@@ -804,8 +830,8 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     FSA_TRY(pcg_precond_and_dots<T>(b, op, 0, s, nparts_rq, st));
   } else {
     int64_t g = spmm_grid(b.n);
-    hipLaunchKernelGGL((k_pcg_sparse_update<T>), dim3(g, ncb), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, b.U,
-                       (const T*)b.H, b.R, (const T*)b.V, op.D, b.alpha, 1, 0, b.H, b.Q0, s.dot2.p, s.dot.p, ldd);
+    hipLaunchKernelGGL((k_pcg_sparse_update<T>), dim3(g, ncb), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, b.R,
+                       (const T*)b.V, op.Dinv, b.alpha, 1, 0, b.H, b.Q0, s.dot2.p, s.dot.p, ldd);
     FSA_HIP(hipGetLastError());
     nparts_rq = nparts_rr = (int)g;
   }
@@ -821,7 +847,7 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
   int64_t tot = b.n * b.ncols;
   KT_BEGIN(b);
   hipLaunchKernelGGL(k_pcg_hupdate<T>, dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld,
-                     (const T*)b.R, (const T*)b.Tt, op.D, b.beta, b.H, b.P, lr ? 1 : 0);
+                     (const T*)b.R, (const T*)b.Tt, op.Dinv, b.alpha, b.beta, b.H, b.P, b.U, lr ? 1 : 0);
   KT_END(b, KT_UPDATE);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -1066,6 +1092,17 @@ fsa_status scal_block(double* X, int ld, int64_t n, int ncols, double a, hipStre
   int64_t tot = n * ncols;
   if (tot == 0) return FSA_OK;
   hipLaunchKernelGGL(k_scal_block, dim3(ceil_div(tot, 256)), dim3(256), 0, st, X, ld, n, ncols, a);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+__global__ void k_reciprocal(const double* __restrict__ D, double* __restrict__ Dinv, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) Dinv[i] = 1.0 / D[i];
+}
+
+fsa_status reciprocal(const double* D, double* Dinv, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_reciprocal, dim3(ceil_div(n, 256)), dim3(256), 0, st, D, Dinv, n);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }

@@ -123,6 +123,7 @@ struct OpDesc {
   const Csr* S = nullptr;
   const T* val = nullptr;
   const double* D = nullptr;
+  const double* Dinv = nullptr;  // 1 / D
   const T* A = nullptr;
   int kdim = 0;
   const double* Cinv = nullptr;
@@ -164,5 +165,6 @@ fsa_status permute_rows(const double* in, int ldi, double* out, int ldo, const i
 fsa_status scale_rows(double* X, int ld, const double* D, int64_t n, int ncols, int invert, hipStream_t st);
 fsa_status scal_block(double* X, int ld, int64_t n, int ncols, double a, hipStream_t st);
 fsa_status axpy_block(const double* X, double a, double* Y, int ld, int64_t n, int ncols, hipStream_t st);
+fsa_status reciprocal(const double* D, double* Dinv, int64_t n, hipStream_t st);
 
 }  // namespace fsa
