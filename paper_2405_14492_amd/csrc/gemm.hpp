@@ -189,25 +189,23 @@ __global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim,
         }
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      typename Epi::In in[4][4];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int64_t i = row0 + a * 16 + Mfma<float>::orow(q, r);
-          int c = c0 + b * 16 + r16;
-          if (i < nrows && c < ncols) in[b][r] = epi.load(i, c);
-        }
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < 4; ++b) {
+        typename Epi::In in[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           int64_t i = row0 + a * 16 + Mfma<float>::orow(q, r);
           int c = c0 + b * 16 + r16;
-          if (i < nrows && c < ncols) dsum[b] += epi.apply(i, c, acc[a][b][r], in[b][r]);
+          if (i < nrows && c < ncols) in[r] = epi.load(i, c);
         }
-    }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int64_t i = row0 + a * 16 + Mfma<float>::orow(q, r);
+          int c = c0 + b * 16 + r16;
+          if (i < nrows && c < ncols) dsum[b] += epi.apply(i, c, acc[a][b][r], in[r]);
+        }
+      }
   }
   if constexpr (DOT) {
 #pragma unroll
@@ -259,17 +257,18 @@ __global__ __launch_bounds__(512) void k_reduce_gemm(int64_t npts, int pts_per_c
   double dacc = 0.0;
   for (int64_t p0 = pbeg; p0 < pend; p0 += 64) {
     __syncthreads();
-    for (int pb = tp0; pb < 64; pb += 8 * nw) {
-      typename Pro::In in[8];
+    constexpr int PB = sizeof(T) == 8 ? 4 : 8;
+    for (int pb = tp0; pb < 64; pb += PB * nw) {
+      typename Pro::In in[PB];
       const int c = c0 + tc;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < PB; ++u) {
         int pp = pb + u * nw;
         int64_t p = p0 + pp;
         if (pp < 64 && p < pend && c < ncols) in[u] = pro.load(p, c);
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < PB; ++u) {
         int pp = pb + u * nw;
         if (pp < 64) {
           int64_t p = p0 + pp;
