@@ -350,181 +350,175 @@ __global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ part,
                                                 double* __restrict__ out);
 
 // ------------------------------------------------------------------ SpMM
-// Y(p, c) = sum_q S_pq X(q, c) for the rows of one grid cell per workgroup.
-// The candidate columns are the points of the 3x3 block of cells (three
-// contiguous ranges); their block rows are staged in LDS in chunks of CH
-// rows, and every row reads its neighbours from LDS.  Waves own rows; lanes
-// own columns (64-column block per grid.y).
-// Position of column q in the concatenation of the three neighbour ranges
-// (empty ranges never match).
-__device__ __forceinline__ int64_t spmm_v_of_q(int64_t q, const int64_t* qb, const int64_t* qe, const int64_t* off) {
-  if (q >= qb[2] && q < qe[2]) return q - qb[2] + off[2];
-  if (q >= qb[1] && q < qe[1]) return q - qb[1] + off[1];
-  return q - qb[0] + off[0];
-}
-__device__ __forceinline__ double readlane_t(double v, int j) {
-  int64_t b = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_readlane((int)b, j);
-  int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
-  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
-}
-__device__ __forceinline__ float readlane_t(float v, int j) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+// Y(p, c) = sum_q S_pq X(q, c), one workgroup per (row cell, 64-column block).
+// The rows of the cell are taken 32 at a time; for each chunk of CH
+// positions of the cell's 3x3 neighbourhood (Csr::key), the group's sparse
+// rows are scattered into a dense 32 x CH LDS tile, the matching block rows
+// of X are staged in LDS, and the tile product runs on MFMA 16x16x4 (four
+// waves, each two 16x16 output tiles).  The zero entries of the tile cost
+// matrix-core cycles only; every nonzero costs one coalesced load and one
+// LDS store.  The next chunk's block rows are loaded into registers while
+// the current chunk is scattered and multiplied, and the epilogue inputs are
+// loaded before the first chunk.  Workgroups are mapped so that each XCD
+// (dispatched round-robin) walks a contiguous run of cells, keeping the
+// shared block rows of neighbouring cells in its own L2.
+template <typename T>
+struct SpmmShape {
+  static constexpr int CH = sizeof(T) == 8 ? 64 : 128;  // neighbourhood positions per chunk
+  static constexpr int XLD = 68;                        // LDS row stride of staged block rows
+  static constexpr int SLD = CH + 4;                    // LDS row stride of the sparse tile
+  static constexpr int XU = CH * 16 / 256;              // 4-column units per thread per chunk
+  static constexpr int EPT = 8;                         // entries per thread per batch
+};
+
+__device__ __forceinline__ int64_t xcd_cell(int64_t b, int64_t ncell) {
+  const int64_t per = (ncell + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
 }
 
-template <typename T, bool DOT, int R, class Epi>
-__global__ __launch_bounds__(256) void k_spmm_cell(const int64_t* __restrict__ rcs, const int64_t* __restrict__ ccs,
-                                                   GridDesc gd, const int64_t* __restrict__ rp,
-                                                   const int* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ X, int ldx, int ncols, int CH, Epi epi,
-                                                   double* __restrict__ dot_part, int ld_dot) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char spmm_smem[];
-  T* Xs = reinterpret_cast<T*>(spmm_smem);
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t cell = blockIdx.x;
+template <typename T, bool DOT, class Epi>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_spmm_dense(const int64_t* __restrict__ rcs, int64_t ncell,
+                                                    const int64_t* __restrict__ ccs, GridDesc gd,
+                                                    const int64_t* __restrict__ rp, const int* __restrict__ key,
+                                                    const T* __restrict__ val, const T* __restrict__ X, int ldx,
+                                                    int ncols, Epi epi, double* __restrict__ dot_part, int ld_dot) {
+  typedef SpmmShape<T> Sh;
+  constexpr int CH = Sh::CH, XLD = Sh::XLD, SLD = Sh::SLD, XU = Sh::XU, EPT = Sh::EPT;
+  __shared__ __attribute__((aligned(16))) T Xs[CH * XLD];
+  __shared__ __attribute__((aligned(16))) T Ss[32 * SLD];
+  typedef typename Mfma<T>::acc acc_t;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int64_t cell = xcd_cell(blockIdx.x, ncell);
+  if (cell >= ncell) return;
   const int c0 = blockIdx.y * 64;
-  const int c = c0 + lane;
   const int64_t rb = rcs[cell], re = rcs[cell + 1];
-  double dacc = 0.0;
+  const int rt = w >> 1, ct0 = (w & 1) * 2;  // this wave's tiles: rows rt*16.., columns (ct0, ct0+1)*16..
+  double dsum0 = 0.0, dsum1 = 0.0;
   if (rb < re) {
-    const int64_t cx = cell % gd.gx, cy = cell / gd.gx;
-    int64_t qb[3], qe[3], off[3];
-    int64_t V = 0;
-    for (int t = 0; t < 3; ++t) {
-      int64_t yy = cy - 1 + t;
-      qb[t] = qe[t] = 0;
-      if (yy >= 0 && yy < gd.gy) {
-        int64_t xlo = cx - 1 < 0 ? 0 : cx - 1;
-        int64_t xhi = cx + 1 >= gd.gx ? gd.gx - 1 : cx + 1;
-        qb[t] = ccs[yy * gd.gx + xlo];
-        qe[t] = ccs[yy * gd.gx + xhi + 1];
-      }
-      off[t] = V;
-      V += qe[t] - qb[t];
-    }
-    for (int64_t g0 = rb; g0 < re; g0 += 4 * R) {
-      // prefetch up to 128 entries of each of this wave's R rows: slot index
-      // in the neighbourhood and value, two per lane
-      T acc[R];
-      int vq0[R], vq1[R];
-      T vv0[R], vv1[R];
-      int nent[R];
-      int64_t ebeg[R];
+    int qb[3], qe[3], off[3];
+    const int V = cell_ranges(cell, gd, ccs, qb, qe, off);
+    // staging unit u = tid + 256 k: row (tid >> 4) + 16 k of the chunk, columns 4 (tid & 15)..+3
+    const int sc4 = (tid & 15) * 4;
+    const bool col_ok = c0 + sc4 < ncols;
+    auto load_chunk = [&](int vb, V4<T>* xr) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        acc[r] = T(0);
-        int64_t p = g0 + w + 4 * r;
-        int64_t e0 = p < re ? rp[p] : 0;
-        int64_t e1 = p < re ? rp[p + 1] : 0;
-        ebeg[r] = e0;
-        nent[r] = (int)(e1 - e0);
-        int ne = nent[r];
-        int qa = lane < ne ? col[e0 + lane] : 0;
-        int qc = lane + 64 < ne ? col[e0 + 64 + lane] : 0;
-        vv0[r] = lane < ne ? val[e0 + lane] : T(0);
-        vv1[r] = lane + 64 < ne ? val[e0 + 64 + lane] : T(0);
-        vq0[r] = lane < ne ? (int)spmm_v_of_q(qa, qb, qe, off) : 0x7fffffff;
-        vq1[r] = lane + 64 < ne ? (int)spmm_v_of_q(qc, qb, qe, off) : 0x7fffffff;
+      for (int k = 0; k < XU; ++k) {
+        const int v = vb + (tid >> 4) + 16 * k;
+        xr[k] = V4<T>{{T(0), T(0), T(0), T(0)}};
+        if (v < V && col_ok) {
+          const int qq = v >= off[2] ? v - off[2] + qb[2] : (v >= off[1] ? v - off[1] + qb[1] : v - off[0] + qb[0]);
+          xr[k] = load4(X + (int64_t)qq * ldx + c0 + sc4);
+        }
       }
-      for (int64_t vb = 0; vb < V; vb += CH) {
-        __syncthreads();
-        const int vn = (int)min((int64_t)CH, V - vb);
-        // 16 four-element vectors per staged row; batches of 8 loads in flight
-        for (int u0 = threadIdx.x; u0 < vn * 16; u0 += 256 * 8) {
-          V4<T> tmp[8];
+    };
+    for (int64_t g0 = rb; g0 < re; g0 += 32) {
+      const int64_t E0 = rp[g0];
+      const int ne = (int)(rp[min(g0 + 32, re)] - E0);
+      const int nbatch = (ne + 256 * EPT - 1) / (256 * EPT);
+      int kk[EPT];
+      T vv[EPT];
+      auto load_batch = [&](int bi) {
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            int u = u0 + 256 * k;
-            tmp[k] = V4<T>{{T(0), T(0), T(0), T(0)}};
-            if (u < vn * 16) {
-              int vr = u >> 4, c4 = (u & 15) * 4;
-              int64_t v = vb + vr;
-              int64_t q = v >= off[2] ? v - off[2] + qb[2] : (v >= off[1] ? v - off[1] + qb[1] : v - off[0] + qb[0]);
-              if (c0 + c4 < ncols) tmp[k] = load4(X + q * ldx + c0 + c4);
-            }
+        for (int k = 0; k < EPT; ++k) {
+          const int i = bi * 256 * EPT + 256 * k + tid;
+          kk[k] = i < ne ? key[E0 + i] : 0;
+          vv[k] = i < ne ? val[E0 + i] : T(0);
+        }
+      };
+      V4<T> xr[XU];
+      load_chunk(0, xr);
+      load_batch(0);
+      // epilogue inputs of this wave's two tiles
+      typename Epi::In in[2][4];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int c = c0 + (ct0 + t) * 16 + r16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t p = g0 + rt * 16 + Mfma<T>::orow(q, r);
+          if (p < re && c < ncols) in[t][r] = epi.load(p, c);
+        }
+      }
+      acc_t acc0 = acc_t{0, 0, 0, 0}, acc1 = acc_t{0, 0, 0, 0};
+      for (int vb = 0; vb < V; vb += CH) {
+        __syncthreads();  // the previous chunk's products are done with Xs and Ss
+#pragma unroll
+        for (int k = 0; k < XU; ++k) {
+          T* dst = &Xs[((tid >> 4) + 16 * k) * XLD + sc4];
+          if constexpr (sizeof(T) == 8) {
+            *reinterpret_cast<d2*>(dst) = d2{xr[k].v[0], xr[k].v[1]};
+            *reinterpret_cast<d2*>(dst + 2) = d2{xr[k].v[2], xr[k].v[3]};
+          } else {
+            *reinterpret_cast<f4*>(dst) = f4{xr[k].v[0], xr[k].v[1], xr[k].v[2], xr[k].v[3]};
           }
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            int u = u0 + 256 * k;
-            if (u < vn * 16) {
-              int vr = u >> 4, c4 = (u & 15) * 4;
-#pragma unroll
-              for (int z = 0; z < 4; ++z) Xs[vr * 64 + c4 + z] = (c0 + c4 + z < ncols) ? tmp[k].v[z] : T(0);
-            }
+        }
+        for (int i = tid; i < 32 * SLD / 4; i += 256) {
+          if constexpr (sizeof(T) == 8) {
+            *reinterpret_cast<d2*>(&Ss[4 * i]) = d2{0.0, 0.0};
+            *reinterpret_cast<d2*>(&Ss[4 * i + 2]) = d2{0.0, 0.0};
+          } else {
+            *reinterpret_cast<f4*>(&Ss[4 * i]) = f4{0.f, 0.f, 0.f, 0.f};
           }
         }
         __syncthreads();
-        const int lo = (int)vb, hi = (int)vb + vn;
+        if (vb + CH < V) load_chunk(vb + CH, xr);
+        for (int bi = 0; bi < nbatch; ++bi) {
+          if (nbatch > 1) load_batch(bi);
+          const int lim = ne - bi * 256 * EPT - tid;  // entry k of this thread exists iff 256 k < lim
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if (nent[r] == 0) continue;
-          // entries are sorted, so the ones in [lo, hi) are a contiguous run
-          uint64_t m0 = __ballot(vq0[r] >= lo && vq0[r] < hi);
-          uint64_t m1 = __ballot(vq1[r] >= lo && vq1[r] < hi);
-          int j = m0 ? __ffsll((unsigned long long)m0) - 1 : 64;
-          int jn = 64 - __clzll((unsigned long long)m0);
-          if (!m0) jn = 64;
-          T a0 = T(0), a1 = T(0);
-          if (m0) {
-            for (; j + 2 <= jn; j += 2) {
-              int v0 = __builtin_amdgcn_readlane(vq0[r], j) - lo;
-              int v1 = __builtin_amdgcn_readlane(vq0[r], j + 1) - lo;
-              T w0 = readlane_t(vv0[r], j), w1 = readlane_t(vv0[r], j + 1);
-              a0 += w0 * Xs[v0 * 64 + lane];
-              a1 += w1 * Xs[v1 * 64 + lane];
-            }
-            if (j < jn) {
-              int v0 = __builtin_amdgcn_readlane(vq0[r], j) - lo;
-              a0 += readlane_t(vv0[r], j) * Xs[v0 * 64 + lane];
-            }
+          for (int k = 0; k < EPT; ++k) {
+            const unsigned kv = (unsigned)kk[k];
+            const int sl = (int)(kv & KEY_SLOT_MASK) - vb;
+            if (256 * k < lim && (unsigned)sl < (unsigned)CH) Ss[(kv >> KEY_SLOT_BITS) * SLD + sl] = vv[k];
           }
-          if (m1) {
-            j = __ffsll((unsigned long long)m1) - 1;
-            jn = 64 - __clzll((unsigned long long)m1);
-            for (; j + 2 <= jn; j += 2) {
-              int v0 = __builtin_amdgcn_readlane(vq1[r], j) - lo;
-              int v1 = __builtin_amdgcn_readlane(vq1[r], j + 1) - lo;
-              T w0 = readlane_t(vv1[r], j), w1 = readlane_t(vv1[r], j + 1);
-              a0 += w0 * Xs[v0 * 64 + lane];
-              a1 += w1 * Xs[v1 * 64 + lane];
-            }
-            if (j < jn) {
-              int v0 = __builtin_amdgcn_readlane(vq1[r], j) - lo;
-              a0 += readlane_t(vv1[r], j) * Xs[v0 * 64 + lane];
-            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int ks = 0; ks < CH; ks += 16) {
+          const V4<T> a = load4(&Ss[(rt * 16 + r16) * SLD + ks + 4 * q]);
+          const T* xb = &Xs[(ks + 4 * q) * XLD + ct0 * 16 + r16];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            acc0 = Mfma<T>::op(a.v[j], xb[j * XLD], acc0);
+            acc1 = Mfma<T>::op(a.v[j], xb[j * XLD + 16], acc1);
           }
-          // rows with more than 128 entries: the rest straight from memory
-          if (nent[r] > 128) {
-            for (int64_t e = ebeg[r] + 128; e < ebeg[r] + nent[r]; ++e) {
-              int v0 = (int)spmm_v_of_q(col[e], qb, qe, off);
-              if (v0 >= lo && v0 < hi) a0 += val[e] * Xs[(v0 - lo) * 64 + lane];
-            }
-          }
-          acc[r] += a0 + a1;
         }
       }
-      typename Epi::In in[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        int64_t p = g0 + w + 4 * r;
-        if (p < re && c < ncols) in[r] = epi.load(p, c);
-      }
+      for (int t = 0; t < 2; ++t) {
+        const int c = c0 + (ct0 + t) * 16 + r16;
+        double d = 0.0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        int64_t p = g0 + w + 4 * r;
-        if (p < re && c < ncols) dacc += epi.apply(p, c, acc[r], in[r]);
+        for (int r = 0; r < 4; ++r) {
+          const int64_t p = g0 + rt * 16 + Mfma<T>::orow(q, r);
+          if (p < re && c < ncols) d += epi.apply(p, c, t == 0 ? acc0[r] : acc1[r], in[t][r]);
+        }
+        if (t == 0) dsum0 += d;
+        else dsum1 += d;
       }
     }
   }
   if constexpr (DOT) {
-    __shared__ double red[4][64];
+    // column c0 + 16 b + r16 gathers the q groups of the two waves owning tile column b
+    dsum0 += __shfl_xor(dsum0, 16, 64);
+    dsum0 += __shfl_xor(dsum0, 32, 64);
+    dsum1 += __shfl_xor(dsum1, 16, 64);
+    dsum1 += __shfl_xor(dsum1, 32, 64);
+    double* red = reinterpret_cast<double*>(Ss);
     __syncthreads();
-    red[w][lane] = dacc;
+    if (q == 0) {
+      red[w * 32 + r16] = dsum0;
+      red[w * 32 + 16 + r16] = dsum1;
+    }
     __syncthreads();
-    if (threadIdx.x < 64)
-      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + threadIdx.x] =
-          red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    if (tid < 64) {
+      // wave w holds columns (2 (w & 1)) * 16 .. +31 of row tile w >> 1
+      const int half = tid >> 5, o = tid & 31;
+      dot_part[cell * ld_dot + c0 + tid] = red[half * 32 + o] + red[(half + 2) * 32 + o];
+    }
   }
 }
 

@@ -286,8 +286,35 @@ __global__ __launch_bounds__(256) void k_pattern(const double* __restrict__ xr, 
   if (!FILL) count[p] = (int)cnt;
 }
 
+// Sparse-product keys (see Csr::key): one workgroup per row cell.
+__global__ __launch_bounds__(256) void k_pattern_keys(const int64_t* __restrict__ rcs, const int64_t* __restrict__ ccs,
+                                                      GridDesc gd, const int64_t* __restrict__ rp,
+                                                      const int* __restrict__ col, int* __restrict__ key) {
+  const int64_t cell = blockIdx.x;
+  const int64_t rb = rcs[cell], re = rcs[cell + 1];
+  if (rb >= re) return;
+  int qb[3], qe[3], off[3];
+  cell_ranges(cell, gd, ccs, qb, qe, off);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t p = rb + w; p < re; p += 4) {
+    const int rowbits = (int)((p - rb) & 31) << KEY_SLOT_BITS;
+    for (int64_t e = rp[p] + lane; e < rp[p + 1]; e += 64) {
+      const int q = col[e];
+      int v;
+      if (q >= qb[2] && q < qe[2]) v = q - qb[2] + off[2];
+      else if (q >= qb[1] && q < qe[1]) v = q - qb[1] + off[1];
+      else v = q - qb[0] + off[0];
+      key[e] = rowbits | v;
+    }
+  }
+}
+
 fsa_status build_pattern(const Grid& rows, const Grid& cols, Csr& csr, hipStream_t st) {
   int64_t nr = rows.n;
+  if (cols.n > KEY_SLOT_MASK) {
+    set_error("at most %d points per point set", KEY_SLOT_MASK);
+    return FSA_ERR_INVALID_ARG;
+  }
   csr.nrows = nr;
   Buf<int> cnt;
   FSA_TRY(cnt.alloc(nr));
@@ -309,6 +336,12 @@ fsa_status build_pattern(const Grid& rows, const Grid& cols, Csr& csr, hipStream
   hipLaunchKernelGGL(k_pattern<true>, dim3(nb), dim3(256), 0, st, rows.xs.p, nr, cols.xs.p, cols.cstart.p,
                      cols.desc, (int*)nullptr, csr.row_ptr.p, csr.col.p);
   FSA_HIP(hipGetLastError());
+  FSA_TRY(csr.key.alloc(nnz > 0 ? nnz : 1));
+  if (rows.ncell > 0 && nnz > 0) {
+    hipLaunchKernelGGL(k_pattern_keys, dim3(rows.ncell), dim3(256), 0, st, rows.cstart.p, cols.cstart.p, cols.desc,
+                       csr.row_ptr.p, csr.col.p, csr.key.p);
+    FSA_HIP(hipGetLastError());
+  }
   FSA_HIP(hipStreamSynchronize(st));
   return FSA_OK;
 }

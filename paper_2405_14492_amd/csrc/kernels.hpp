@@ -32,8 +32,40 @@ struct Csr {
   int64_t nrows = 0, nnz = 0;
   Buf<int64_t> row_ptr;
   Buf<int> col;
-  void release() { row_ptr.release(); col.release(); }
+  // Per nonzero: (row - first row of its cell) mod 32 in the top 5 bits,
+  // position of the column in its row cell's 3x3 neighbourhood (the three
+  // contiguous column ranges of cell_ranges, concatenated) in the low 27.
+  Buf<int> key;
+  void release() { row_ptr.release(); col.release(); key.release(); }
 };
+
+constexpr int KEY_SLOT_BITS = 27;
+constexpr int KEY_SLOT_MASK = (1 << KEY_SLOT_BITS) - 1;
+
+// The column points that can neighbour row cell `cell`: the cells of rows
+// cy-1, cy, cy+1 (clipped) and columns cx-1..cx+1 (clipped) of the column
+// grid, which is laid out like the row grid.  Range t is [qb[t], qe[t]) in
+// the column set's sorted order and starts at position off[t] of the
+// concatenation; the return value is the total length.
+__device__ __forceinline__ int cell_ranges(int64_t cell, const GridDesc& gd, const int64_t* __restrict__ ccs,
+                                           int* qb, int* qe, int* off) {
+  const int64_t cx = cell % gd.gx, cy = cell / gd.gx;
+  const int64_t xlo = cx - 1 < 0 ? 0 : cx - 1;
+  const int64_t xhi = cx + 1 >= gd.gx ? gd.gx - 1 : cx + 1;
+  int tot = 0;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int64_t yy = cy - 1 + t;
+    qb[t] = qe[t] = 0;
+    if (yy >= 0 && yy < gd.gy) {
+      qb[t] = (int)ccs[yy * gd.gx + xlo];
+      qe[t] = (int)ccs[yy * gd.gx + xhi + 1];
+    }
+    off[t] = tot;
+    tot += qe[t] - qb[t];
+  }
+  return tot;
+}
 
 __global__ void k_cstart_to_cursor(const int64_t* cstart, int64_t ncell, int* cursor);
 

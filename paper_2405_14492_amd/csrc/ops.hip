@@ -353,8 +353,6 @@ static int64_t spmm_grid(int64_t n) {
   if (g < 1) g = 1;
   return g;
 }
-constexpr int SPMM_R = 8;
-static int spmm_ch(size_t elem) { return elem == 8 ? 64 : 128; }
 
 template <typename T, bool DOT, class Epi>
 static fsa_status launch_spmm_cell(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx,
@@ -364,12 +362,10 @@ static fsa_status launch_spmm_cell(const Csr& S, const Grid& rg, const Grid& cg,
     set_error("spmm: block rows must be 16-byte aligned (ld multiple of 4)");
     return FSA_ERR_INVALID_ARG;
   }
-  int CH = spmm_ch(sizeof(T));
-  size_t smem = (size_t)CH * 64 * sizeof(T);
-  dim3 grid(rg.ncell, ceil_div(ncols, 64));
+  dim3 grid(8 * ceil_div(rg.ncell, 8), ceil_div(ncols, 64));
   GridDesc gd = cg.desc;
-  hipLaunchKernelGGL((k_spmm_cell<T, DOT, SPMM_R, Epi>), grid, dim3(256), smem, st, rg.cstart.p, cg.cstart.p, gd,
-                     S.row_ptr.p, S.col.p, val, X, ldx, ncols, CH, epi, dot_part, ld_dot);
+  hipLaunchKernelGGL((k_spmm_dense<T, DOT, Epi>), grid, dim3(256), 0, st, rg.cstart.p, rg.ncell, cg.cstart.p, gd,
+                     S.row_ptr.p, S.key.p, val, X, ldx, ncols, epi, dot_part, ld_dot);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
