@@ -314,6 +314,192 @@ __global__ __launch_bounds__(512) void k_reduce_gemm(int64_t npts, int pts_per_c
   }
 }
 
+// Prologue of the float32 reduce GEMM: X(p, c) = x(p, c) * scale, where
+// x = S(p, c), or with UPD the updated residual x = S - alpha_c V (written
+// back to S, and |x|^2 accumulated per column), and scale = 1 (SC = 0),
+// sc[p] (SC = 1) or 1 / sc[p] (SC = 2).
+struct F32Pro {
+  float* S;
+  const float* V;        // with UPD
+  const double* alpha;   // with UPD
+  const double* sc;      // with SC != 0
+  int64_t ld;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+constexpr int BUF_OOR = 0x7ff00000;  // a buffer offset past every range used here
+
+// Float32 reduce GEMM, software-pipelined.  grid (nchunks, ncb, zb), 512
+// threads; wave w owns the 64 rows 512 z + 64 w .. +63 of the kdim side
+// (four 16-row MFMA tiles, rows interleaved by four so that a lane loads four
+// adjacent A entries) and the workgroup's 64-column block.  Points are taken
+// 24 per step; the A rows of the next two steps are in flight in registers
+// while the matrix cores work on the current one, and the next step's
+// prologue inputs load meanwhile and land in the other half of a
+// double-buffered LDS block (one barrier per step).  Every load and store in
+// the loop is an unconditional buffer access over the chunk's rows (zero
+// fill and dropped stores past the last point or column), so no branch
+// forces the memory pipeline to drain.  Partials are row-major:
+// part[((chunk * ncb + cb) * kdim + k) * 64 + c - 64 cb].
+template <bool UPD, int SC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_reduce_gemm_f32(
+    int64_t npts, int pts_per_chunk, int kdim, int ncols, const float* __restrict__ A, F32Pro pro,
+    float* __restrict__ part, double* __restrict__ dot_part, int ld_dot) {
+  constexpr int SP = 24;        // points per step
+  constexpr int NA = SP / 4;    // A loads per lane per step
+  constexpr int NP = SP / 8;    // prologue elements per thread per step
+  __shared__ __attribute__((aligned(16))) float Xs[2][SP * XS_LD];
+  __shared__ double red[512];
+  typedef Mfma<float>::acc acc_t;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.y * 64;
+  const int ncb = gridDim.y;
+  const int kb = blockIdx.z * 512 + w * 64;
+  const bool mactive = kb < kdim;
+  const int64_t pbeg = (int64_t)blockIdx.x * pts_per_chunk;
+  const int64_t pend = min(npts, pbeg + pts_per_chunk);
+  const int np = pend > pbeg ? (int)(pend - pbeg) : 0;
+  const int nsteps = (np + SP - 1) / SP;
+  const int tc = tid & 63, tp = tid >> 6;  // prologue: column c0 + tc, points tp + 8 u
+  const int c = c0 + tc;
+  const bool cval = c < ncols;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  double dacc = 0.0;
+  f4 ab0[NA] = {}, ab1[NA] = {}, ab2[NA] = {};
+  const __amdgpu_buffer_rsrc_t arsrc = rsrc_of(A + pbeg * kdim, (int64_t)np * kdim * 4);
+  const __amdgpu_buffer_rsrc_t srsrc = rsrc_of(pro.S + pbeg * pro.ld, (int64_t)np * pro.ld * 4);
+  const __amdgpu_buffer_rsrc_t vrsrc = rsrc_of(UPD ? pro.V + pbeg * pro.ld : pro.S, UPD ? (int64_t)np * pro.ld * 4 : 0);
+  const __amdgpu_buffer_rsrc_t drsrc = rsrc_of(SC ? pro.sc + pbeg : (const double*)pro.S, SC ? (int64_t)np * 8 : 0);
+  const double a_c = (UPD && cval) ? pro.alpha[c] : 0.0;
+  // byte offsets into the chunk (unsigned: BUF_OOR plus an offset stays out of range)
+  const unsigned a_off = mactive ? (unsigned)(q * kdim + kb + 4 * r16) * 4u : (unsigned)BUF_OOR;
+  const unsigned s_off = cval ? (unsigned)(tp * (int)pro.ld + c) * 4u : (unsigned)BUF_OOR;  // element (tp, c)
+  const unsigned s_step = 8u * (unsigned)pro.ld * 4u;                                       // + 8 points
+  float sv[NP], vv[NP];
+  double dv[NP];
+  auto load_a = [&](int s, f4* ab) {
+    const unsigned so = a_off + (unsigned)(s * SP * kdim) * 4u;
+#pragma unroll
+    for (int k = 0; k < NA; ++k)
+      ab[k] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(arsrc, so + 16u * k * kdim, 0, 0));
+  };
+  auto pro_load = [&](int s) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int pr = s * SP + tp + 8 * u;
+      const unsigned o = s_off + (unsigned)(s * SP / 8 + u) * s_step;
+      sv[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(srsrc, o, 0, 0));
+      vv[u] = UPD ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(vrsrc, o, 0, 0)) : 0.f;
+      dv[u] = SC ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(drsrc, (unsigned)pr * 8u, 0, 0)) : 1.0;
+    }
+  };
+  auto pro_apply = [&](int s, float* xs) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int pr = s * SP + tp + 8 * u;
+      double x = (double)sv[u];
+      if constexpr (UPD) {
+        const float rt = (float)(x - a_c * (double)vv[u]);
+        const unsigned o = s_off + (unsigned)(s * SP / 8 + u) * s_step;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, rt), srsrc, o, 0, 0);
+        x = (double)rt;
+        dacc += x * x;  // zero for padding columns and points past the chunk
+      }
+      const double y = SC == 0 ? x : (SC == 1 ? x * dv[u] : x / dv[u]);
+      xs[(tp + 8 * u) * XS_LD + tc] = (pr < np && cval) ? (float)y : 0.f;
+    }
+  };
+  auto mma = [&](const f4* ab, const float* xs) {
+    if (!mactive) return;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const V4<float> xv = load4(&xs[(4 * k + q) * XS_LD + 4 * r16]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<float>::op(ab[k][a], xv.v[b], acc[a][b]);
+    }
+  };
+  // step s: prologue inputs of step s + 1 and A of step s + 2 load (in that
+  // order, so that the prologue's wait leaves the A loads in flight), the
+  // matrix cores take step s from (abc, Xs[s & 1])
+  auto step = [&](int s, const f4* abc, f4* abn) {
+    pro_load(s + 1);
+    load_a(s + 2, abn);
+    mma(abc, Xs[s & 1]);
+    pro_apply(s + 1, Xs[(s + 1) & 1]);
+    __syncthreads();
+  };
+  if (nsteps > 0) {
+    pro_load(0);
+    load_a(0, ab0);
+    load_a(1, ab1);
+    pro_apply(0, Xs[0]);
+    __syncthreads();
+    int s = 0;
+    for (; s + 2 < nsteps; s += 3) {
+      step(s, ab0, ab2);
+      step(s + 1, ab1, ab0);
+      step(s + 2, ab2, ab1);
+    }
+    if (s < nsteps) step(s, ab0, ab2);
+    if (s + 1 < nsteps) step(s + 1, ab1, ab0);
+  }
+  if (mactive) {
+    // tile (a, b) row i = 4 q' + r, column r16: k = kb + 4 i + a, c = 4 r16 + b
+    float* dst = part + (((int64_t)blockIdx.x * ncb + blockIdx.y) * kdim + kb) * 64 + 4 * r16;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        *reinterpret_cast<f4*>(dst + (4 * (4 * q + r) + a) * 64) =
+            f4{acc[a][0][r], acc[a][1][r], acc[a][2][r], acc[a][3][r]};
+  }
+  if constexpr (UPD) {
+    red[tid] = dacc;
+    __syncthreads();
+    if (tid < 64) {
+      double sum = 0.0;
+      for (int k = 0; k < 8; ++k) sum += red[k * 64 + tid];
+      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + tid] = sum;
+    }
+  }
+}
+
+// Sum the row-major per-chunk partials of k_reduce_gemm_f32 (fixed order,
+// eight interleaved partial sums) into W (float64, row-major kdim x ldw, all
+// 64 ncb columns); optionally add the identity.
+__global__ void k_reduce_parts_rm(const float* __restrict__ part, int nchunks, int ncb, int kdim,
+                                  double* __restrict__ W, int ldw, int add_identity) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)ncb * kdim * 64;
+  if (e >= per) return;
+  double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int ch = 0;
+  for (; ch + 8 <= nchunks; ch += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s8[u] += (double)part[(int64_t)(ch + u) * per + e];
+  }
+  for (int u = 0; ch < nchunks; ++ch, ++u) s8[u] += (double)part[(int64_t)ch * per + e];
+  double sum = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+  const int cl = (int)(e & 63);
+  const int64_t rest = e >> 6;
+  const int k = (int)(rest % kdim);
+  const int cb = (int)(rest / kdim);
+  const int cc = cb * 64 + cl;
+  if (add_identity && k == cc) sum += 1.0;
+  W[(int64_t)k * ldw + cc] = sum;
+}
+
 // Sum the per-chunk partial tiles (fixed order, eight interleaved partial
 // sums) into W (float64, row-major kdim x ldw); optionally add the identity.
 template <typename T>

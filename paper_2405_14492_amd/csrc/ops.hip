@@ -1,6 +1,7 @@
 // FSA operations: covariance generation + whitening, residual values,
 // capacitance, sparse and low-rank block products, the fused PCG steps of
 // Algorithm 2, and the Lanczos-quadrature eigensolve.
+#include <type_traits>
 #include "gemm.hpp"
 #include "ops.hpp"
 
@@ -104,6 +105,9 @@ struct DivDPro {
   int64_t ld;
   const double* D;
   struct In { T s; double d; };
+  static constexpr bool kUpd = false;
+  static constexpr int kSc = 2;
+  F32Pro f32() const { return F32Pro{(float*)S, nullptr, nullptr, D, ld}; }
   __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c], D[p]}; }
   __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)((double)x.s / x.d); }
 };
@@ -114,6 +118,9 @@ struct MulDinvPro {
   int64_t ld;
   const double* Dinv;
   struct In { T s; double d; };
+  static constexpr bool kUpd = false;
+  static constexpr int kSc = 1;
+  F32Pro f32() const { return F32Pro{(float*)S, nullptr, nullptr, Dinv, ld}; }
   __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c], Dinv[p]}; }
   __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)((double)x.s * x.d); }
 };
@@ -123,6 +130,12 @@ struct PlainPro {
   const TS* S;
   int64_t ld;
   struct In { TS s; };
+  static constexpr bool kUpd = false;
+  static constexpr int kSc = 0;
+  F32Pro f32() const {
+    static_assert(std::is_same<TS, float>::value, "float32 prologue reads float32");
+    return F32Pro{(float*)S, nullptr, nullptr, nullptr, ld};
+  }
   __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c]}; }
   __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)x.s; }
 };
@@ -278,12 +291,47 @@ static fsa_status ensure_part(Scratch& s, const ReduceShape& r) {
   return FSA_OK;
 }
 
+// Reduce GEMM launch: the pipelined kernel for float32, the general one for
+// float64.  Prologues that write their input (the PCG residual update) need a
+// single workgroup along z, which kdim <= 512 guarantees.
+template <typename T, bool DOT, class Pro>
+static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int ncols, const T* A, const Pro& pro,
+                                T* part, double* dot_part, int ld_dot, hipStream_t st) {
+  if (DOT && r.zb != 1) {
+    set_error("reduce GEMM with a dot prologue needs kdim <= 512 (got %d)", kdim);
+    return FSA_ERR_INVALID_ARG;
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    dim3 grid(r.nchunks, r.ncb, (kdim + 511) / 512);
+    F32Pro fp = pro.f32();
+    if constexpr (Pro::kUpd) {
+      hipLaunchKernelGGL((k_reduce_gemm_f32<true, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim, ncols, A, fp,
+                         part, dot_part, ld_dot);
+    } else {
+      hipLaunchKernelGGL((k_reduce_gemm_f32<false, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim, ncols, A, fp,
+                         part, dot_part, ld_dot);
+    }
+  } else {
+    RowsOp<T> acol{A, kdim};
+    hipLaunchKernelGGL((k_reduce_gemm<T, DOT, RowsOp<T>, Pro>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads), 0, st,
+                       n, r.ppc, kdim, ncols, acol, pro, part, dot_part, ld_dot, 0);
+  }
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
 template <typename T>
 static fsa_status reduce_finish(Scratch& s, const ReduceShape& r, double* W, int ldw, int add_id, hipStream_t st,
                                 int lower_only = 0) {
   int64_t per = (int64_t)r.ncb * r.nmb * 4096;
-  hipLaunchKernelGGL(k_reduce_parts<T>, dim3(ceil_div(per, 256)), dim3(256), 0, st, (const T*)s.part.p, r.nchunks,
-                     r.ncb, r.nmb, W, ldw, add_id, lower_only);
+  if constexpr (std::is_same<T, float>::value) {
+    // row-major partials of the pipelined float32 kernel (all of kdim)
+    hipLaunchKernelGGL(k_reduce_parts_rm, dim3(ceil_div(per, 256)), dim3(256), 0, st, (const float*)s.part.p,
+                       r.nchunks, r.ncb, r.nmb * 64, W, ldw, add_id);
+  } else {
+    hipLaunchKernelGGL(k_reduce_parts<T>, dim3(ceil_div(per, 256)), dim3(256), 0, st, (const T*)s.part.p, r.nchunks,
+                       r.ncb, r.nmb, W, ldw, add_id, lower_only);
+  }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -305,17 +353,13 @@ fsa_status lowrank_reduce(const T* A, int64_t n, int kdim, const T* X, int ldx, 
                           Scratch& s, double* W, int ldw, hipStream_t st) {
   ReduceShape r = reduce_shape(n, kdim, ncols);
   FSA_TRY(ensure_part<T>(s, r));
-  RowsOp<T> acol{A, kdim};
   if (Dinv_src) {
     DivDPro<T> pro{X, ldx, Dinv_src};
-    hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, DivDPro<T>>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads),
-                       0, st, n, r.ppc, kdim, ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0, 0);
+    FSA_TRY((launch_reduce<T, false>(r, n, kdim, ncols, A, pro, (T*)s.part.p, nullptr, 0, st)));
   } else {
     PlainPro<T, T> pro{X, ldx};
-    hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, PlainPro<T, T>>), dim3(r.nchunks, r.ncb, r.zb),
-                       dim3(r.threads), 0, st, n, r.ppc, kdim, ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0, 0);
+    FSA_TRY((launch_reduce<T, false>(r, n, kdim, ncols, A, pro, (T*)s.part.p, nullptr, 0, st)));
   }
-  FSA_HIP(hipGetLastError());
   return reduce_finish<T>(s, r, W, ldw, 0, st);
 }
 
@@ -496,6 +540,9 @@ struct PcgPass1Pro {
   const double* alpha;
   int64_t ld;
   struct In { T r, v; double di, a; };
+  static constexpr bool kUpd = true;
+  static constexpr int kSc = 1;
+  F32Pro f32() const { return F32Pro{(float*)R, (const float*)V, alpha, Dinv, ld}; }
   __device__ __forceinline__ In load(int64_t p, int c) const {
     int64_t o = p * ld + c;
     return In{R[o], V[o], Dinv[p], alpha[c]};
@@ -748,10 +795,7 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
     ReduceShape r = reduce_shape(b.n, op.kdim, b.ncols);
     FSA_TRY(ensure_part<T>(s, r));
     MulDinvPro<T> pro{b.R, b.ld, op.Dinv};
-    RowsOp<T> acol{op.A, op.kdim};
-    hipLaunchKernelGGL((k_reduce_gemm<T, false, RowsOp<T>, MulDinvPro<T>>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads),
-                       0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, (double*)nullptr, 0, 0);
-    FSA_HIP(hipGetLastError());
+    FSA_TRY((launch_reduce<T, false>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, nullptr, 0, st)));
     FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
     FSA_TRY(pcg_precond_and_dots<T>(b, op, 1, s, nparts_rq, st));
     // |b|^2 partials
@@ -808,14 +852,11 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     ReduceShape r = reduce_shape(b.n, op.kdim, b.ncols);
     FSA_TRY(ensure_part<T>(s, r));
     PcgPass1Pro<T> pro{b.R, b.V, op.Dinv, b.alpha, b.ld};
-    RowsOp<T> acol{op.A, op.kdim};
     {
       KT_BEGIN(b);
-      hipLaunchKernelGGL((k_reduce_gemm<T, true, RowsOp<T>, PcgPass1Pro<T>>), dim3(r.nchunks, r.ncb, r.zb),
-                         dim3(r.threads), 0, st, b.n, r.ppc, op.kdim, b.ncols, acol, pro, (T*)s.part.p, s.dot2.p, ldd, 0);
+      FSA_TRY((launch_reduce<T, true>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, s.dot2.p, ldd, st)));
       KT_END(b, KT_PASS1);
     }
-    FSA_HIP(hipGetLastError());
     nparts_rr = r.nchunks;
     {
       KT_BEGIN(b);
