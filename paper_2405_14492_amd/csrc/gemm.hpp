@@ -131,82 +131,170 @@ __global__ __launch_bounds__(256) void k_rows_gemm(int64_t nrows, int kdim, cons
   }
 }
 
+// Buffer resource over [base, base + bytes): loads past the end return zero,
+// stores past the end are dropped (gfx9 raw buffer, stride 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+constexpr int BUF_OOR = 0x7ff00000;  // a buffer offset past every range used here
+
 // ------------------------------------------------------------------ rows GEMM, float32, resident G
+// Epilogue of the float32 rows GEMM, out-of-place over row-major n x ld
+// blocks.  Modes: ROWS_STORE Y = acc; ROWS_ACC Y += acc; ROWS_PCG t = acc
+// written to Y, dot += r (r - t) Dinv; ROWS_PCG_INIT q = (r - acc) Dinv,
+// H = Q0 = q, P = acc, dot += r q.
+enum { ROWS_STORE = 0, ROWS_ACC = 1, ROWS_PCG = 2, ROWS_PCG_INIT = 3 };
+struct F32RowsEpi {
+  float* Y;  // ROWS_STORE / ROWS_ACC / ROWS_PCG output
+  const float* R;
+  const double* Dinv;
+  float* H;
+  float* P;
+  float* Q0;
+  int64_t ld;
+};
+
 // OUT(i, c) = sum_k A[i][k] G[k][c] for one 64-column block: the whole
-// kdim x 64 block of G (kdim <= 512) stays in LDS as [k/4][c][k%4], so a lane
-// fetches the four k of one MFMA group with one 16-byte read.  Waves are
-// persistent over 32-row tiles (no barrier in the main loop) and prefetch A
-// two 16-k steps ahead.
-template <bool DOT, class Epi>
+// kdim x 64 block of G (kdim <= 512) stays in LDS as [k/4][c][k%4].  Each of
+// the 16 waves is persistent over 16-row tiles and walks k in steps of 64: a
+// lane loads 64 contiguous bytes of its row (k = 64 kb + 16 q' + 4 t + j for
+// MFMA t, j) through a range-checked buffer resource over the tile's rows.
+// The A loads of the step two ahead in the flattened (tile, k block) stream
+// are issued before the matrix cores take the current step, and the
+// epilogue reads and writes through buffer resources too, so no divergent
+// branch in the loop forces the memory pipeline to drain.
+template <bool DOT, int EM>
 __global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim, const float* __restrict__ A,
                                                         int64_t lda, const float* __restrict__ G, int ldg, int ncols,
-                                                        Epi epi, double* __restrict__ dot_part, int ld_dot) {
+                                                        F32RowsEpi epi, double* __restrict__ dot_part, int ld_dot) {
   extern __shared__ __attribute__((aligned(16))) float gres[];
   __shared__ double red[16][64];
   typedef Mfma<float>::acc acc_t;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q = lane >> 4, r16 = lane & 15;
   const int c0 = blockIdx.y * 64;
-  for (int e = threadIdx.x; e < kdim * 64; e += blockDim.x) {
-    int k = e >> 6, cc = e & 63;
-    float v = (c0 + cc < ncols) ? G[(int64_t)k * ldg + c0 + cc] : 0.f;
+  for (int e = tid; e < kdim * 64; e += 1024) {
+    const int k = e >> 6, cc = e & 63;
+    const float v = (c0 + cc < ncols) ? G[(int64_t)k * ldg + c0 + cc] : 0.f;
     gres[(((k >> 2) * 64 + cc) << 2) + (k & 3)] = v;
   }
   __syncthreads();
+  const int nkb = kdim / 64;
+  const int64_t ntile = (nrows + 15) / 16;
+  const int64_t gw = (int64_t)blockIdx.x * 16 + w, GW = (int64_t)gridDim.x * 16;
+  const int64_t ntw = gw < ntile ? (ntile - gw + GW - 1) / GW : 0;  // tiles of this wave
+  const unsigned lane_off = (unsigned)(r16 * lda + 16 * q) * 4u;
   double dsum[4] = {0, 0, 0, 0};
-  const int64_t ntile = (nrows + 31) / 32;
-  for (int64_t tile = (int64_t)blockIdx.x * nw + w; tile < ntile; tile += (int64_t)gridDim.x * nw) {
-    const int64_t row0 = tile * 32;
-    const int64_t ia = min(row0 + r16, nrows - 1), ib = min(row0 + 16 + r16, nrows - 1);
-    const float* pa = A + ia * lda + 4 * q;
-    const float* pb = A + ib * lda + 4 * q;
-    acc_t acc[2][4];
+  // load cursor: tile ordinal lj, k block lkb
+  int64_t lj = 0;
+  int lkb = 0;
+  auto load_next = [&](f4* ab) {
+    const int64_t row0 = (gw + lj * GW) * 16;
+    const int64_t nr = lj < ntw ? min((int64_t)16, nrows - row0) : 0;
+    const __amdgpu_buffer_rsrc_t rs = rsrc_of(A + (lj < ntw ? row0 * lda : 0), nr * lda * 4);
+    const unsigned o = lane_off + (unsigned)lkb * 256u;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-    f4 fa0 = *reinterpret_cast<const f4*>(pa), fb0 = *reinterpret_cast<const f4*>(pb);
-    f4 fa1 = kdim > 16 ? *reinterpret_cast<const f4*>(pa + 16) : f4{0, 0, 0, 0};
-    f4 fb1 = kdim > 16 ? *reinterpret_cast<const f4*>(pb + 16) : f4{0, 0, 0, 0};
-    for (int ks = 0; ks < kdim; ks += 16) {
-      f4 ca = fa0, cb = fb0;
-      fa0 = fa1;
-      fb0 = fb1;
-      if (ks + 32 < kdim) {
-        fa1 = *reinterpret_cast<const f4*>(pa + ks + 32);
-        fb1 = *reinterpret_cast<const f4*>(pb + ks + 32);
-      }
-      f4 g[4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) g[b] = *reinterpret_cast<const f4*>(&gres[((((ks >> 2) + q) * 64) + b * 16 + r16) << 2]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          acc[0][b] = Mfma<float>::op(ca[j], g[b][j], acc[0][b]);
-          acc[1][b] = Mfma<float>::op(cb[j], g[b][j], acc[1][b]);
-        }
+    for (int t = 0; t < 4; ++t) ab[t] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u * t, 0, 0));
+    if (++lkb == nkb) {
+      lkb = 0;
+      ++lj;
     }
+  };
+  acc_t acc[4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+  for (int b = 0; b < 4; ++b) acc[b] = acc_t{0, 0, 0, 0};
+  // compute cursor: tile ordinal cj, k block ckb
+  int64_t cj = 0;
+  int ckb = 0;
+  auto epilogue = [&]() {
+    const int64_t row0 = (gw + cj * GW) * 16;
+    const int64_t nr = min((int64_t)16, nrows - row0);
+    const __amdgpu_buffer_rsrc_t ry = rsrc_of(epi.Y ? epi.Y + row0 * epi.ld : (float*)A, epi.Y ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rr = rsrc_of(epi.R ? epi.R + row0 * epi.ld : A, epi.R ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rd = rsrc_of(epi.Dinv ? epi.Dinv + row0 : (const double*)A, epi.Dinv ? nr * 8 : 0);
+    const __amdgpu_buffer_rsrc_t rh = rsrc_of(EM == ROWS_PCG_INIT ? epi.H + row0 * epi.ld : A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rp = rsrc_of(EM == ROWS_PCG_INIT ? epi.P + row0 * epi.ld : A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rq = rsrc_of(EM == ROWS_PCG_INIT ? epi.Q0 + row0 * epi.ld : A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    float xin[4][4];
+    double di[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if constexpr (EM >= ROWS_PCG)
+        di[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rd, (unsigned)(4 * q + r) * 8u, 0, 0));
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        typename Epi::In in[4];
+        const int c = c0 + b * 16 + r16;
+        const unsigned o = c < ncols ? (unsigned)((4 * q + r) * (int)epi.ld + c) * 4u : (unsigned)BUF_OOR;
+        if constexpr (EM == ROWS_ACC)
+          xin[r][b] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ry, o, 0, 0));
+        if constexpr (EM >= ROWS_PCG)
+          xin[r][b] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rr, o, 0, 0));
+      }
+    }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int64_t i = row0 + a * 16 + Mfma<float>::orow(q, r);
-          int c = c0 + b * 16 + r16;
-          if (i < nrows && c < ncols) in[r] = epi.load(i, c);
-        }
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int64_t i = row0 + a * 16 + Mfma<float>::orow(q, r);
-          int c = c0 + b * 16 + r16;
-          if (i < nrows && c < ncols) dsum[b] += epi.apply(i, c, acc[a][b][r], in[r]);
+      for (int b = 0; b < 4; ++b) {
+        const int c = c0 + b * 16 + r16;
+        const unsigned o = c < ncols ? (unsigned)((4 * q + r) * (int)epi.ld + c) * 4u : (unsigned)BUF_OOR;
+        const float v = acc[b][r];
+        if constexpr (EM == ROWS_STORE) {
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), ry, o, 0, 0);
+        } else if constexpr (EM == ROWS_ACC) {
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v + xin[r][b]), ry, o, 0, 0);
+        } else {
+          const double rv = (double)xin[r][b];
+          const double qv = (rv - (double)v) * di[r];
+          // zero for points past the tile and padding columns (r = 0, Dinv = 0)
+          dsum[b] += rv * qv;
+          if constexpr (EM == ROWS_PCG) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), ry, o, 0, 0);
+          } else {
+            const unsigned qb = __builtin_bit_cast(unsigned, (float)qv);
+            __builtin_amdgcn_raw_buffer_store_b32(qb, rh, o, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rp, o, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(qb, rq, o, 0, 0);
+          }
         }
       }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = acc_t{0, 0, 0, 0};
+  };
+  // one step of the flattened (tile, k block) stream: the loads of the step
+  // two ahead go into `ahead`, the matrix cores take `cur`
+  auto step = [&](const f4* cur, f4* ahead) {
+    load_next(ahead);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f4 g[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) g[b] = *reinterpret_cast<const f4*>(&gres[((ckb * 16 + 4 * q + t) * 64 + b * 16 + r16) << 2]);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = Mfma<float>::op(cur[t][jj], g[b][jj], acc[b]);
+    }
+    if (++ckb == nkb) {
+      epilogue();
+      ckb = 0;
+      ++cj;
+    }
+  };
+  const int64_t nflat = ntw * nkb;
+  f4 b0[4], b1[4], b2[4];
+  load_next(b0);
+  load_next(b1);
+  int64_t f = 0;
+  for (; f + 2 < nflat; f += 3) {
+    step(b0, b2);
+    step(b1, b0);
+    step(b2, b1);
   }
+  if (f < nflat) step(b0, b2);
+  if (f + 1 < nflat) step(b1, b0);
   if constexpr (DOT) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -216,10 +304,10 @@ __global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim,
       if (q == 0) red[w][b * 16 + r16] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
+    if (tid < 64) {
       double sacc = 0.0;
-      for (int k = 0; k < nw; ++k) sacc += red[k][threadIdx.x];
-      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + threadIdx.x] = sacc;
+      for (int k = 0; k < 16; ++k) sacc += red[k][tid];
+      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + tid] = sacc;
     }
   }
 }
@@ -326,10 +414,6 @@ struct F32Pro {
   int64_t ld;
 };
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base, int64_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
-constexpr int BUF_OOR = 0x7ff00000;  // a buffer offset past every range used here
 
 // Float32 reduce GEMM, software-pipelined.  grid (nchunks, ncb, zb), 512
 // threads; wave w owns the 64 rows 512 z + 64 w .. +63 of the kdim side

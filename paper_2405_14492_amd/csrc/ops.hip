@@ -370,9 +370,10 @@ fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T*
   dim3 grid(rows_grid(n), ceil_div(ncols, 64));
   if constexpr (sizeof(T) == 4) {
     if (!A2 && kdim <= 512) {
-      hipLaunchKernelGGL((k_rows_gemm_f32<false, StoreEpi<T>>), dim3(f32_rows_grid(), ceil_div(ncols, 64)),
+      F32RowsEpi fe{(float*)OUT, nullptr, nullptr, nullptr, nullptr, nullptr, ldo};
+      hipLaunchKernelGGL((k_rows_gemm_f32<false, ROWS_STORE>), dim3(f32_rows_grid(), ceil_div(ncols, 64)),
                          dim3(1024), (size_t)kdim * 64 * sizeof(float), st, n, kdim, (const float*)A, (int64_t)kdim,
-                         (const float*)G, ldg, ncols, epi, (double*)nullptr, 0);
+                         (const float*)G, ldg, ncols, fe, (double*)nullptr, 0);
       FSA_HIP(hipGetLastError());
       return FSA_OK;
     }
@@ -765,9 +766,16 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
     size_t need = (size_t)gx * ncb * 64;
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
     KT_BEGIN(b);
-    hipLaunchKernelGGL((k_rows_gemm_f32<true, PcgPass2Epi<T>>), dim3(gx, ncb), dim3(1024),
-                       (size_t)op.kdim * 64 * sizeof(float), st, b.n, op.kdim, (const float*)op.A, (int64_t)op.kdim,
-                       (const float*)b.g, b.ldw, b.ncols, epi, s.dot.p, ncb * 64);
+    F32RowsEpi fe{init ? nullptr : (float*)b.Tt, (const float*)b.R, op.Dinv, (float*)b.H, (float*)b.P, (float*)b.Q0,
+                  (int64_t)b.ld};
+    if (init)
+      hipLaunchKernelGGL((k_rows_gemm_f32<true, ROWS_PCG_INIT>), dim3(gx, ncb), dim3(1024),
+                         (size_t)op.kdim * 64 * sizeof(float), st, b.n, op.kdim, (const float*)op.A, (int64_t)op.kdim,
+                         (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
+    else
+      hipLaunchKernelGGL((k_rows_gemm_f32<true, ROWS_PCG>), dim3(gx, ncb), dim3(1024),
+                         (size_t)op.kdim * 64 * sizeof(float), st, b.n, op.kdim, (const float*)op.A, (int64_t)op.kdim,
+                         (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
     KT_END(b, KT_PASS2);
   } else {
     RowsOp<T> aop{op.A, op.kdim};
