@@ -627,14 +627,17 @@ __global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ part,
 // of X are staged in LDS, and the tile product runs on MFMA 16x16x4 (four
 // waves, each two 16x16 output tiles).  The zero entries of the tile cost
 // matrix-core cycles only; every nonzero costs one coalesced load and one
-// LDS store.  The next chunk's block rows are loaded into registers while
-// the current chunk is scattered and multiplied, and the epilogue inputs are
-// loaded before the first chunk.  Workgroups are mapped so that each XCD
-// (dispatched round-robin) walks a contiguous run of cells, keeping the
-// shared block rows of neighbouring cells in its own L2.
+// LDS store.  All global accesses go through range-checked buffer resources
+// (the group's entries, the neighbourhood's row window of X, the group's
+// output rows), so the loop has no divergent branch around a memory access:
+// the entries and epilogue inputs load before the first chunk, and the next
+// chunk's block rows load while the current chunk is scattered and
+// multiplied.  Workgroups are mapped so that each XCD (dispatched
+// round-robin) walks a contiguous run of cells, keeping the shared block
+// rows of neighbouring cells in its own L2.
 template <typename T>
 struct SpmmShape {
-  static constexpr int CH = sizeof(T) == 8 ? 64 : 128;  // neighbourhood positions per chunk
+  static constexpr int CH = 64;                         // neighbourhood positions per chunk
   static constexpr int XLD = 68;                        // LDS row stride of staged block rows
   static constexpr int SLD = CH + 4;                    // LDS row stride of the sparse tile
   static constexpr int XU = CH * 16 / 256;              // 4-column units per thread per chunk
@@ -646,14 +649,52 @@ __device__ __forceinline__ int64_t xcd_cell(int64_t b, int64_t ncell) {
   return (b & 7) * per + (b >> 3);
 }
 
-template <typename T, bool DOT, class Epi>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_spmm_dense(const int64_t* __restrict__ rcs, int64_t ncell,
-                                                    const int64_t* __restrict__ ccs, GridDesc gd,
-                                                    const int64_t* __restrict__ rp, const int* __restrict__ key,
-                                                    const T* __restrict__ val, const T* __restrict__ X, int ldx,
-                                                    int ncols, Epi epi, double* __restrict__ dot_part, int ld_dot) {
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, off, 0, 0);
+  else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ V4<T> bload4(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  V4<T> o;
+  if constexpr (sizeof(T) == 8) {
+    const d2 a = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const d2 b = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0));
+    o.v[0] = a[0]; o.v[1] = a[1]; o.v[2] = b[0]; o.v[3] = b[1];
+  } else {
+    const f4 a = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    o.v[0] = a[0]; o.v[1] = a[1]; o.v[2] = a[2]; o.v[3] = a[3];
+  }
+  return o;
+}
+
+// Epilogue of the sparse product over row-major n x ld blocks.  Modes:
+// SP_STORE Y = acc; SP_ACC Y += acc; SP_PCG Y = acc + P (P may be null),
+// dot += H . Y per column.
+enum { SP_STORE = 0, SP_ACC = 1, SP_PCG = 2 };
+template <typename T>
+struct SpmmEpi {
+  T* Y;
+  const T* H;
+  const T* P;
+  int64_t ld;
+};
+
+template <typename T, int EM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4))) void k_spmm_dense(
+    const int64_t* __restrict__ rcs, int64_t ncell, const int64_t* __restrict__ ccs, GridDesc gd,
+    const int64_t* __restrict__ rp, const int* __restrict__ key, const T* __restrict__ val, const T* __restrict__ X,
+    int ldx, int ncols, SpmmEpi<T> epi, double* __restrict__ dot_part, int ld_dot) {
   typedef SpmmShape<T> Sh;
   constexpr int CH = Sh::CH, XLD = Sh::XLD, SLD = Sh::SLD, XU = Sh::XU, EPT = Sh::EPT;
+  constexpr unsigned TS = sizeof(T);
   __shared__ __attribute__((aligned(16))) T Xs[CH * XLD];
   __shared__ __attribute__((aligned(16))) T Ss[32 * SLD];
   typedef typename Mfma<T>::acc acc_t;
@@ -670,108 +711,171 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   if (rb < re) {
     int qb[3], qe[3], off[3];
     const int V = cell_ranges(cell, gd, ccs, qb, qe, off);
-    // staging unit u = tid + 256 k: row (tid >> 4) + 16 k of the chunk, columns 4 (tid & 15)..+3
+    int qlo = 0x7fffffff, qhi = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (qe[t] > qb[t]) {
+        qlo = min(qlo, qb[t]);
+        qhi = max(qhi, qe[t]);
+      }
+    if (qhi == 0) qlo = 0;
+    // the neighbourhood's row window of X
+    const __amdgpu_buffer_rsrc_t xrs = rsrc_of(X + (int64_t)qlo * ldx, (int64_t)(qhi - qlo) * ldx * TS);
+    // staging unit u = tid + 256 k: chunk row (tid >> 4) + 16 k, columns 4 (tid & 15)..+3
     const int sc4 = (tid & 15) * 4;
     const bool col_ok = c0 + sc4 < ncols;
     auto load_chunk = [&](int vb, V4<T>* xr) {
 #pragma unroll
       for (int k = 0; k < XU; ++k) {
         const int v = vb + (tid >> 4) + 16 * k;
-        xr[k] = V4<T>{{T(0), T(0), T(0), T(0)}};
-        if (v < V && col_ok) {
-          const int qq = v >= off[2] ? v - off[2] + qb[2] : (v >= off[1] ? v - off[1] + qb[1] : v - off[0] + qb[0]);
-          xr[k] = load4(X + (int64_t)qq * ldx + c0 + sc4);
+        const int qq = v >= off[2] ? v - off[2] + qb[2] : (v >= off[1] ? v - off[1] + qb[1] : v - off[0] + qb[0]);
+        const unsigned o = (v < V && col_ok) ? (unsigned)((qq - qlo) * ldx + c0 + sc4) * TS : (unsigned)BUF_OOR;
+        xr[k] = bload4<T>(xrs, o);
+      }
+    };
+    auto stage = [&](const V4<T>* xr) {
+#pragma unroll
+      for (int k = 0; k < XU; ++k) {
+        T* dst = &Xs[((tid >> 4) + 16 * k) * XLD + sc4];
+        if constexpr (sizeof(T) == 8) {
+          *reinterpret_cast<d2*>(dst) = d2{xr[k].v[0], xr[k].v[1]};
+          *reinterpret_cast<d2*>(dst + 2) = d2{xr[k].v[2], xr[k].v[3]};
+        } else {
+          *reinterpret_cast<f4*>(dst) = f4{xr[k].v[0], xr[k].v[1], xr[k].v[2], xr[k].v[3]};
+        }
+      }
+      for (int i = tid; i < 32 * SLD / 4; i += 256) {
+        if constexpr (sizeof(T) == 8) {
+          *reinterpret_cast<d2*>(&Ss[4 * i]) = d2{0.0, 0.0};
+          *reinterpret_cast<d2*>(&Ss[4 * i + 2]) = d2{0.0, 0.0};
+        } else {
+          *reinterpret_cast<f4*>(&Ss[4 * i]) = f4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    };
+    auto mma = [&](acc_t& acc0, acc_t& acc1) {
+#pragma unroll 4
+      for (int ks = 0; ks < CH; ks += 16) {
+        const V4<T> a = load4(&Ss[(rt * 16 + r16) * SLD + ks + 4 * q]);
+        const T* xb = &Xs[(ks + 4 * q) * XLD + ct0 * 16 + r16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc0 = Mfma<T>::op(a.v[j], xb[j * XLD], acc0);
+          acc1 = Mfma<T>::op(a.v[j], xb[j * XLD + 16], acc1);
         }
       }
     };
     for (int64_t g0 = rb; g0 < re; g0 += 32) {
       const int64_t E0 = rp[g0];
       const int ne = (int)(rp[min(g0 + 32, re)] - E0);
-      const int nbatch = (ne + 256 * EPT - 1) / (256 * EPT);
+      const int nrg = (int)min((int64_t)32, re - g0);
+      const __amdgpu_buffer_rsrc_t krs = rsrc_of(key + E0, (int64_t)ne * 4);
+      const __amdgpu_buffer_rsrc_t vrs = rsrc_of(val + E0, (int64_t)ne * TS);
       int kk[EPT];
       T vv[EPT];
       auto load_batch = [&](int bi) {
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {
-          const int i = bi * 256 * EPT + 256 * k + tid;
-          kk[k] = i < ne ? key[E0 + i] : 0;
-          vv[k] = i < ne ? val[E0 + i] : T(0);
+          const unsigned i = (unsigned)(bi * 256 * EPT + 256 * k + tid);
+          kk[k] = (int)__builtin_amdgcn_raw_buffer_load_b32(krs, i * 4u, 0, 0);
+          vv[k] = bload<T>(vrs, i * TS);
         }
       };
-      V4<T> xr[XU];
-      load_chunk(0, xr);
-      load_batch(0);
+      auto scatter = [&](int bi, int vb) {
+        const int lim = ne - bi * 256 * EPT - tid;  // entry k of this thread exists iff 256 k < lim
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const unsigned kv = (unsigned)kk[k];
+          const int sl = (int)(kv & KEY_SLOT_MASK) - vb;
+          if (256 * k < lim && (unsigned)sl < (unsigned)CH) Ss[(kv >> KEY_SLOT_BITS) * SLD + sl] = vv[k];
+        }
+      };
       // epilogue inputs of this wave's two tiles
-      typename Epi::In in[2][4];
+      const __amdgpu_buffer_rsrc_t yrs = rsrc_of(epi.Y + g0 * epi.ld, (int64_t)nrg * epi.ld * TS);
+      const __amdgpu_buffer_rsrc_t hrs = rsrc_of(EM == SP_PCG ? epi.H + g0 * epi.ld : epi.Y, EM == SP_PCG ? (int64_t)nrg * epi.ld * TS : 0);
+      const __amdgpu_buffer_rsrc_t prs = rsrc_of(EM == SP_PCG && epi.P ? epi.P + g0 * epi.ld : epi.Y, EM == SP_PCG && epi.P ? (int64_t)nrg * epi.ld * TS : 0);
+      unsigned eo[2][4];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const int c = c0 + (ct0 + t) * 16 + r16;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t p = g0 + rt * 16 + Mfma<T>::orow(q, r);
-          if (p < re && c < ncols) in[t][r] = epi.load(p, c);
-        }
+        for (int r = 0; r < 4; ++r)
+          eo[t][r] = c < ncols ? (unsigned)((rt * 16 + Mfma<T>::orow(q, r)) * (int)epi.ld + c) * TS : (unsigned)BUF_OOR;
       }
+      T in0[2][4], in1[2][4];
       acc_t acc0 = acc_t{0, 0, 0, 0}, acc1 = acc_t{0, 0, 0, 0};
-      for (int vb = 0; vb < V; vb += CH) {
-        __syncthreads();  // the previous chunk's products are done with Xs and Ss
+      V4<T> xr[XU];
+      if (ne <= 256 * EPT) {
+        // entries resident in registers for all chunks
+        load_batch(0);
 #pragma unroll
-        for (int k = 0; k < XU; ++k) {
-          T* dst = &Xs[((tid >> 4) + 16 * k) * XLD + sc4];
-          if constexpr (sizeof(T) == 8) {
-            *reinterpret_cast<d2*>(dst) = d2{xr[k].v[0], xr[k].v[1]};
-            *reinterpret_cast<d2*>(dst + 2) = d2{xr[k].v[2], xr[k].v[3]};
-          } else {
-            *reinterpret_cast<f4*>(dst) = f4{xr[k].v[0], xr[k].v[1], xr[k].v[2], xr[k].v[3]};
-          }
-        }
-        for (int i = tid; i < 32 * SLD / 4; i += 256) {
-          if constexpr (sizeof(T) == 8) {
-            *reinterpret_cast<d2*>(&Ss[4 * i]) = d2{0.0, 0.0};
-            *reinterpret_cast<d2*>(&Ss[4 * i + 2]) = d2{0.0, 0.0};
-          } else {
-            *reinterpret_cast<f4*>(&Ss[4 * i]) = f4{0.f, 0.f, 0.f, 0.f};
-          }
-        }
-        __syncthreads();
-        if (vb + CH < V) load_chunk(vb + CH, xr);
-        for (int bi = 0; bi < nbatch; ++bi) {
-          if (nbatch > 1) load_batch(bi);
-          const int lim = ne - bi * 256 * EPT - tid;  // entry k of this thread exists iff 256 k < lim
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-          for (int k = 0; k < EPT; ++k) {
-            const unsigned kv = (unsigned)kk[k];
-            const int sl = (int)(kv & KEY_SLOT_MASK) - vb;
-            if (256 * k < lim && (unsigned)sl < (unsigned)CH) Ss[(kv >> KEY_SLOT_BITS) * SLD + sl] = vv[k];
+          for (int r = 0; r < 4; ++r) {
+            if constexpr (EM == SP_ACC) in0[t][r] = bload<T>(yrs, eo[t][r]);
+            if constexpr (EM == SP_PCG) {
+              in0[t][r] = bload<T>(hrs, eo[t][r]);
+              in1[t][r] = bload<T>(prs, eo[t][r]);
+            }
           }
+        load_chunk(0, xr);
+        for (int vb = 0; vb < V; vb += CH) {
+          __syncthreads();  // the previous chunk's products are done with Xs and Ss
+          stage(xr);
+          __syncthreads();
+          load_chunk(vb + CH, xr);  // past the neighbourhood: zero, no traffic
+          scatter(0, vb);
+          __syncthreads();
+          mma(acc0, acc1);
         }
-        __syncthreads();
-#pragma unroll 4
-        for (int ks = 0; ks < CH; ks += 16) {
-          const V4<T> a = load4(&Ss[(rt * 16 + r16) * SLD + ks + 4 * q]);
-          const T* xb = &Xs[(ks + 4 * q) * XLD + ct0 * 16 + r16];
+      } else {
+        // long rows: entries re-read per chunk in batches
+        const int nbatch = (ne + 256 * EPT - 1) / (256 * EPT);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            acc0 = Mfma<T>::op(a.v[j], xb[j * XLD], acc0);
-            acc1 = Mfma<T>::op(a.v[j], xb[j * XLD + 16], acc1);
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if constexpr (EM == SP_ACC) in0[t][r] = bload<T>(yrs, eo[t][r]);
+            if constexpr (EM == SP_PCG) {
+              in0[t][r] = bload<T>(hrs, eo[t][r]);
+              in1[t][r] = bload<T>(prs, eo[t][r]);
+            }
           }
+        for (int vb = 0; vb < V; vb += CH) {
+          load_chunk(vb, xr);
+          __syncthreads();
+          stage(xr);
+          __syncthreads();
+          for (int bi = 0; bi < nbatch; ++bi) {
+            load_batch(bi);
+            scatter(bi, vb);
+          }
+          __syncthreads();
+          mma(acc0, acc1);
         }
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const int c = c0 + (ct0 + t) * 16 + r16;
         double d = 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t p = g0 + rt * 16 + Mfma<T>::orow(q, r);
-          if (p < re && c < ncols) d += epi.apply(p, c, t == 0 ? acc0[r] : acc1[r], in[t][r]);
+          const T a = t == 0 ? acc0[r] : acc1[r];
+          if constexpr (EM == SP_STORE) {
+            bstore<T>(a, yrs, eo[t][r]);
+          } else if constexpr (EM == SP_ACC) {
+            bstore<T>(a + in0[t][r], yrs, eo[t][r]);
+          } else {
+            const T v = (T)((double)a + (double)in1[t][r]);
+            bstore<T>(v, yrs, eo[t][r]);
+            d += (double)in0[t][r] * (double)v;  // zero past the group's rows and columns
+          }
         }
         if (t == 0) dsum0 += d;
         else dsum1 += d;
       }
     }
   }
-  if constexpr (DOT) {
+  if constexpr (EM == SP_PCG) {
     // column c0 + 16 b + r16 gathers the q groups of the two waves owning tile column b
     dsum0 += __shfl_xor(dsum0, 16, 64);
     dsum0 += __shfl_xor(dsum0, 32, 64);

@@ -289,12 +289,24 @@ __global__ __launch_bounds__(256) void k_pattern(const double* __restrict__ xr, 
 // Sparse-product keys (see Csr::key): one workgroup per row cell.
 __global__ __launch_bounds__(256) void k_pattern_keys(const int64_t* __restrict__ rcs, const int64_t* __restrict__ ccs,
                                                       GridDesc gd, const int64_t* __restrict__ rp,
-                                                      const int* __restrict__ col, int* __restrict__ key) {
+                                                      const int* __restrict__ col, int* __restrict__ key,
+                                                      unsigned long long* __restrict__ stats) {
   const int64_t cell = blockIdx.x;
   const int64_t rb = rcs[cell], re = rcs[cell + 1];
   if (rb >= re) return;
   int qb[3], qe[3], off[3];
   cell_ranges(cell, gd, ccs, qb, qe, off);
+  if (threadIdx.x == 0) {
+    int qlo = 0x7fffffff, qhi = 0;
+    for (int t = 0; t < 3; ++t)
+      if (qe[t] > qb[t]) {
+        qlo = min(qlo, qb[t]);
+        qhi = max(qhi, qe[t]);
+      }
+    atomicMax(&stats[0], (unsigned long long)(qhi > 0 ? qhi - qlo : 0));
+    for (int64_t g0 = rb; g0 < re; g0 += 32)
+      atomicMax(&stats[1], (unsigned long long)(rp[min(g0 + 32, re)] - rp[g0]));
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t p = rb + w; p < re; p += 4) {
     const int rowbits = (int)((p - rb) & 31) << KEY_SLOT_BITS;
@@ -337,10 +349,19 @@ fsa_status build_pattern(const Grid& rows, const Grid& cols, Csr& csr, hipStream
                      cols.desc, (int*)nullptr, csr.row_ptr.p, csr.col.p);
   FSA_HIP(hipGetLastError());
   FSA_TRY(csr.key.alloc(nnz > 0 ? nnz : 1));
+  csr.max_window = csr.max_group_nnz = 0;
   if (rows.ncell > 0 && nnz > 0) {
+    Buf<unsigned long long> stats;
+    FSA_TRY(stats.alloc(2));
+    FSA_HIP(hipMemsetAsync(stats.p, 0, 2 * sizeof(unsigned long long), st));
     hipLaunchKernelGGL(k_pattern_keys, dim3(rows.ncell), dim3(256), 0, st, rows.cstart.p, cols.cstart.p, cols.desc,
-                       csr.row_ptr.p, csr.col.p, csr.key.p);
+                       csr.row_ptr.p, csr.col.p, csr.key.p, stats.p);
     FSA_HIP(hipGetLastError());
+    unsigned long long h[2] = {0, 0};
+    FSA_HIP(hipMemcpyAsync(h, stats.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    FSA_HIP(hipStreamSynchronize(st));
+    csr.max_window = (int64_t)h[0];
+    csr.max_group_nnz = (int64_t)h[1];
   }
   FSA_HIP(hipStreamSynchronize(st));
   return FSA_OK;

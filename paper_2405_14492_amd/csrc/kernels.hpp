@@ -36,6 +36,9 @@ struct Csr {
   // position of the column in its row cell's 3x3 neighbourhood (the three
   // contiguous column ranges of cell_ranges, concatenated) in the low 27.
   Buf<int> key;
+  // largest neighbourhood row window (rows between the first and last
+  // candidate column of a row cell) and largest 32-row group entry count
+  int64_t max_window = 0, max_group_nnz = 0;
   void release() { row_ptr.release(); col.release(); key.release(); }
 };
 

@@ -399,17 +399,23 @@ static int64_t spmm_grid(int64_t n) {
   return g;
 }
 
-template <typename T, bool DOT, class Epi>
+template <typename T, int EM>
 static fsa_status launch_spmm_cell(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx,
-                                   int ncols, const Epi& epi, double* dot_part, int ld_dot, hipStream_t st) {
+                                   int ncols, const SpmmEpi<T>& epi, double* dot_part, int ld_dot, hipStream_t st) {
   if (rg.ncell == 0) return FSA_OK;
   if ((ldx & 3) || (reinterpret_cast<uintptr_t>(X) & 15)) {
     set_error("spmm: block rows must be 16-byte aligned (ld multiple of 4)");
     return FSA_ERR_INVALID_ARG;
   }
+  // buffer resources span 32-bit byte ranges
+  if (S.max_window * ldx * (int64_t)sizeof(T) > INT32_MAX || S.max_group_nnz * (int64_t)sizeof(T) > INT32_MAX) {
+    set_error("spmm: a cell neighbourhood of %lld rows or a row group of %lld nonzeros exceeds the 2 GiB window",
+              (long long)S.max_window, (long long)S.max_group_nnz);
+    return FSA_ERR_INVALID_ARG;
+  }
   dim3 grid(8 * ceil_div(rg.ncell, 8), ceil_div(ncols, 64));
   GridDesc gd = cg.desc;
-  hipLaunchKernelGGL((k_spmm_dense<T, DOT, Epi>), grid, dim3(256), 0, st, rg.cstart.p, rg.ncell, cg.cstart.p, gd,
+  hipLaunchKernelGGL((k_spmm_dense<T, EM>), grid, dim3(256), 0, st, rg.cstart.p, rg.ncell, cg.cstart.p, gd,
                      S.row_ptr.p, S.key.p, val, X, ldx, ncols, epi, dot_part, ld_dot);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -418,8 +424,9 @@ static fsa_status launch_spmm_cell(const Csr& S, const Grid& rg, const Grid& cg,
 template <typename T>
 fsa_status spmm(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx, int ncols, T* Y,
                 int ldy, bool accumulate, hipStream_t st) {
-  StoreEpi<T> epi{Y, ldy, accumulate ? 1 : 0};
-  return launch_spmm_cell<T, false, StoreEpi<T>>(S, rg, cg, val, X, ldx, ncols, epi, nullptr, 0, st);
+  SpmmEpi<T> epi{Y, nullptr, nullptr, ldy};
+  if (accumulate) return launch_spmm_cell<T, SP_ACC>(S, rg, cg, val, X, ldx, ncols, epi, nullptr, 0, st);
+  return launch_spmm_cell<T, SP_STORE>(S, rg, cg, val, X, ldx, ncols, epi, nullptr, 0, st);
 }
 
 __global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ part, int nparts, int ldp,
@@ -487,41 +494,51 @@ fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double
 
 // ---------------------------------------------------------------- m-space
 // G (kdim x ldg, type T) = M (kdim x kdim) W (kdim x ldw, columns < ncols),
-// 32 x 32 output tiles through LDS, float64 accumulation.
+// float64 MFMA 16x16x4: one workgroup per 16 x 16 output tile, the four waves
+// split k into quarters and their partial tiles are summed in LDS (fixed
+// order).  Lane (q, r) of a wave reads four consecutive k of row r of M.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mspace(const double* __restrict__ M, const double* __restrict__ W, int ldw,
                                                 int kdim, int ncols, T* __restrict__ G, int ldg) {
-  __shared__ double Ms[32][33], Ws[32][33];
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // ty 0..7
-  const int k0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
-  double acc[4] = {0, 0, 0, 0};
-  for (int j0 = 0; j0 < kdim; j0 += 32) {
-    for (int r = ty; r < 32; r += 8) {
-      int k = k0 + r, j = j0 + tx, cc = c0 + tx;
-      Ms[r][tx] = (k < kdim && j < kdim) ? M[(int64_t)k * kdim + j] : 0.0;
-      int jj = j0 + r;
-      Ws[r][tx] = (jj < kdim && cc < ncols) ? W[(int64_t)jj * ldw + cc] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int j = 0; j < 32; ++j) {
-      double wv = Ws[j][tx];
+  __shared__ double red[4][4][64];
+  typedef Mfma<double>::acc acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int k0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
+  const int kq = kdim / 4;  // kdim is a multiple of 64
+  const int cc = c0 + r16;
+  const bool cok = cc < ncols;
+  const double* mrow = M + (int64_t)(k0 + r16) * kdim;
+  acc_t acc = acc_t{0, 0, 0, 0};
+  for (int kb = w * kq; kb < (w + 1) * kq; kb += 16) {
+    const V4<double> a = load4(mrow + kb + 4 * q);
+    double bv[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += Ms[ty + 8 * u][j] * wv;
-    }
-    __syncthreads();
+    for (int j = 0; j < 4; ++j) bv[j] = cok ? W[(int64_t)(kb + 4 * q + j) * ldw + cc] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc = Mfma<double>::op(a.v[j], bv[j], acc);
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    int k = k0 + ty + 8 * u, cc = c0 + tx;
-    if (k < kdim && cc < ldg) G[(int64_t)k * ldg + cc] = (T)(cc < ncols ? acc[u] : 0.0);
+  for (int r = 0; r < 4; ++r) red[w][r][lane] = acc[r];
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double v = (red[0][r][lane] + red[1][r][lane]) + (red[2][r][lane] + red[3][r][lane]);
+      const int k = k0 + Mfma<double>::orow(q, r);
+      if (cc < ldg) G[(int64_t)k * ldg + cc] = (T)(cok ? v : 0.0);
+    }
   }
 }
 
 template <typename T>
 fsa_status mspace_apply(const double* M, const double* W, int ldw, int kdim, int ncols, T* G, int ldg,
                         hipStream_t st) {
-  dim3 grid(ceil_div(ldg, 32), ceil_div(kdim, 32));
+  if (kdim % 64) {
+    set_error("mspace: kdim must be a multiple of 64");
+    return FSA_ERR_INVALID_ARG;
+  }
+  dim3 grid(ceil_div(ldg, 16), kdim / 16);
   hipLaunchKernelGGL(k_mspace<T>, grid, dim3(256), 0, st, M, W, ldw, kdim, ncols, G, ldg);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -582,26 +599,6 @@ struct PcgPass2Epi {
       Tt[o] = v;
     }
     return r * qv;
-  }
-};
-
-// SpMM epilogue: v = (S h)_i + p_i; accumulates h . v
-template <typename T>
-struct PcgSpmmEpi {
-  const T* H;
-  const T* P;
-  T* V;
-  int64_t ld;
-  int has_p;
-  struct In { T h, p; };
-  __device__ __forceinline__ In load(int64_t i, int c) const {
-    int64_t o = i * ld + c;
-    return In{H[o], has_p ? P[o] : T(0)};
-  }
-  __device__ __forceinline__ double apply(int64_t i, int c, T acc, const In& x) const {
-    T v = (T)((double)acc + (double)x.p);
-    V[i * ld + c] = v;
-    return (double)x.h * (double)v;
   }
 };
 
@@ -691,6 +688,26 @@ __global__ void k_pcg_setup(int ncols, const double* __restrict__ bn2_part, int 
   if (threadIdx.x == 0) {
     flags[0] = cnt;
     flags[1] = 0;
+  }
+}
+
+// First stage of a fixed-order column sum over many partial rows: workgroup
+// g sums rows g, g + G, g + 2G, ... of part (coalesced: 64 columns per row
+// block), out[g][c].  The second stage sums the G rows per column.
+constexpr int COLSUM_G = 128;
+__global__ __launch_bounds__(256) void k_colsum_stage1(const double* __restrict__ part, int nparts, int ldp, int ncols,
+                                                       double* __restrict__ out, int ldo) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncols; c0 += 64) {
+    const int c = c0 + lane;
+    double s = 0.0;
+    if (c < ncols)
+      for (int k = blockIdx.x + COLSUM_G * w; k < nparts; k += 4 * COLSUM_G) s += part[(int64_t)k * ldp + c];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && c < ncols) out[(int64_t)blockIdx.x * ldo + c] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    __syncthreads();
   }
 }
 
@@ -838,19 +855,22 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
   const bool lr = op.kdim > 0;
   // 1. V = S H + P, h^T v
   {
-    PcgSpmmEpi<T> epi{b.H, b.P, b.V, b.ld, lr ? 1 : 0};
+    SpmmEpi<T> epi{b.V, b.H, lr ? b.P : nullptr, b.ld};
     int64_t g = op.grid->ncell;
     size_t need = (size_t)g * ldd;
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
     {
       KT_BEGIN(b);
-      FSA_TRY((launch_spmm_cell<T, true, PcgSpmmEpi<T>>(*op.S, *op.grid, *op.grid, op.val, b.H, b.ld, b.ncols, epi,
+      FSA_TRY((launch_spmm_cell<T, SP_PCG>(*op.S, *op.grid, *op.grid, op.val, b.H, b.ld, b.ncols, epi,
                                                           s.dot.p, ldd, st)));
       KT_END(b, KT_SPMM);
     }
     KT_BEGIN(b);
-    hipLaunchKernelGGL(k_pcg_alpha, dim3(b.ncols), dim3(256), 0, st, b.ncols, s.dot.p, (int)g, ldd, b.rz, b.active,
-                       b.alpha, b.flags);
+    if (s.dot1.count < (size_t)COLSUM_G * ldd) FSA_TRY(s.dot1.alloc((size_t)COLSUM_G * ldd));
+    hipLaunchKernelGGL(k_colsum_stage1, dim3(COLSUM_G), dim3(256), 0, st, s.dot.p, (int)g, ldd, b.ncols, s.dot1.p,
+                       ldd);
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(b.ncols), dim3(256), 0, st, b.ncols, s.dot1.p, COLSUM_G, ldd, b.rz,
+                       b.active, b.alpha, b.flags);
     KT_END(b, KT_SMALL);
     FSA_HIP(hipGetLastError());
   }

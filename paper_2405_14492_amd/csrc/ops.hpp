@@ -12,6 +12,7 @@ struct Scratch {
   Buf<double> dot2;
   Buf<char> part;    // reduce-GEMM partial tiles
   Buf<double> w;     // reduced m-space block (kdim x ldw)
+  Buf<double> dot1;  // first-stage column sums of many partials
 };
 
 // HIP-event timing of kernel classes on one stream (enabled per context).
