@@ -39,20 +39,66 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# rocprofv3 kernel names of the four PCG kernel classes, per element type
+KERNEL_NAMES = {
+    "f32": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<true, 1>", "k_rows_gemm_f32<true, 2>",
+            "k_pcg_hupdate<float>"],
+    "f64": ["k_spmm_dense<double, 2>", "k_reduce_gemm<double, true, RowsOp<double>, PcgPass1Pro<double> >",
+            "k_rows_gemm<double, 2, true, RowsOp<double>, PcgPass2Epi<double> >", "k_pcg_hupdate<double>"],
+}
+COUNTERS = os.path.join(ROOT, "profiles", "pcg_kernels_n500k_m500_t50_counters.md")
+
+
 def kernel_work(k, n, m, tp, nnz, b):
     """Algorithmic (bytes, flops) per launch of kernel class k with element
     size b (block vectors, sparse values and low-rank factor); the solution
-    accumulator is float64 in both modes."""
+    accumulator U is float64 in both modes.  Every operand counted once."""
     blk = n * tp
-    if k == 0:   # V = S H + P (CSR values+cols, row_ptr, H gathered once, P in, V out)
+    if k == 0:   # V = S H + P, h.v: key (4 B) + value per nonzero, H in, P in, V out, row pointers
         return nnz * (b + 4) + 8 * (n + 1) + 3 * blk * b, 2.0 * nnz * tp
-    if k == 1:   # u += a h, r -= a v (U f64 r/w, H, R r/w, V), D, then A (n x m) reduction
-        return n * m * b + blk * (16 + 4 * b) + 8 * n, 2.0 * n * m * tp
-    if k == 2:   # t = A g, q = (r - t)/D: A, R in, T out, D
+    if k == 1:   # r -= a v (R in/out, V in), W = A D^-1 r: A (n x m) once, D^-1
+        return n * m * b + 3 * blk * b + 8 * n, 2.0 * n * m * tp
+    if k == 2:   # t = A g, r.q with q = (r - t)/D: A once, R in, T out, D^-1
         return n * m * b + 2 * blk * b + 8 * n, 2.0 * n * m * tp
-    if k == 3:   # h = (r - t)/D + beta h, p = t + beta p
-        return 6 * blk * b + 8 * n, 4.0 * blk
+    if k == 3:   # u += a h (U in/out f64), h = (r - t)/D + beta h, p = t + beta p: R, T, H, P in; H, P out
+        return blk * (6 * b + 16) + 8 * n, 6.0 * blk
     return 0, 0
+
+
+def source_fingerprint():
+    """sha256 over the kernel sources and the ABI header: hardware-counter
+    traffic is reported only for the sources it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2405_14492_amd", "csrc")
+    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    for f in files:
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "fsa.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name):
+    """HBM bytes per launch (fetch + write, copy-calibrated) of a kernel from
+    the committed counter summary, or None if absent or measured on other
+    sources."""
+    try:
+        with open(COUNTERS) as fh:
+            lines = [ln for ln in fh if ln.startswith("traffic-json: ")]
+    except OSError:
+        return None
+    if not lines:
+        return None
+    rec = json.loads(lines[-1][len("traffic-json: "):])
+    if rec.get("fingerprint") != source_fingerprint():
+        return None
+    k = rec.get("kernels", {}).get(kernel_name)
+    if not k:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
 
 
 def run_mode(F, dev, w, precision, steps, warmup, tol, torch):
@@ -111,8 +157,10 @@ def roofline(res, n, m, tp, precision):
         r = {"bound": "mfma", "achieved": tfl, "peak": peak_t, "unit": "TFLOP/s", "frac": tfl / peak_t}
     else:
         r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
-    r.update({"kernel": KERNELS[dom], "avg_launch_ms": avg[dom], "algorithmic_bytes": byt,
-              "algorithmic_flops": flop, "achieved_GBps": gbs, "achieved_TFLOPs": tfl, "traffic": None,
+    name = KERNEL_NAMES[precision][dom]
+    r.update({"traffic": measured_traffic(name), "kernel": KERNELS[dom], "rocprof_kernel": name,
+              "avg_launch_ms": avg[dom], "algorithmic_bytes": byt, "algorithmic_flops": flop, "achieved_GBps": gbs,
+              "achieved_TFLOPs": tfl, "source_fingerprint": source_fingerprint(),
               "per_kernel_avg_ms": dict(zip(KERNELS, avg))})
     return r
 
@@ -159,8 +207,8 @@ def main():
     ap.add_argument("--m", type=int, default=500)
     ap.add_argument("--probes", type=int, default=50)
     ap.add_argument("--modes", default="fp64,mixed")
-    ap.add_argument("--cpu-sample-n", type=int, default=40_000)
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-sample-n", type=int, default=80_000)
+    ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for hardware-counter scaling)")
