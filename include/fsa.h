@@ -90,7 +90,9 @@ typedef struct {
 typedef struct {
   int32_t iters_min, iters_max; /* PCG iterations over the right-hand-side columns */
   int64_t probe_iters;          /* sum over columns of iterations executed */
-  double rel_res_max;           /* largest final relative residual */
+  double rel_res_max;           /* largest final ||r|| / ||b|| over the likelihood solve's columns, from the
+                                   CG recurrence residual (mixed precision: the float32 residual updated since
+                                   the last float64 replacement) */
   double logdet;                /* SLQ estimate of log det Sigma~_dagger */
   double logdet_P;              /* log det of the FITC preconditioner (Sylvester) */
   double quad;                  /* y^T Sigma~_dagger^{-1} y */
@@ -119,7 +121,9 @@ void fsa_default_options(fsa_options* opt);
  *   locs      host, n x d row-major; n >= 2 (Assumption 1)
  *   y         host, n responses (zero mean assumed: no fixed effects)
  *   theta     covariance parameters
- *   inducing  host, m x d row-major; 1 <= m <= min(n, 1024), distinct
+ *   inducing  host, m x d row-major; 1 <= m <= min(n, 512), distinct
+ *             (n below 2^27: the sparse product packs a neighbourhood
+ *             position into 27 bits)
  *   taper_range gamma > 0
  *   opt       options (copied); NULL = defaults
  *   out       receives the new context

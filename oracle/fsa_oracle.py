@@ -157,14 +157,19 @@ def splitmix64(seed, counter):
 STREAM_RHO, STREAM_E, STREAM_PRED = 0, 1, 2
 
 
-def rademacher(seed, stream, n_rows, n_cols):
-    """(n_rows, n_cols) matrix of +-1: entry (i, c) is +1 iff the top bit of
+def rademacher_rows(seed, stream, rows, n_cols):
+    """Rows `rows` of the +-1 matrix: entry (i, c) is +1 iff the top bit of
     splitmix64(seed, stream<<60 | c<<40 | i) is 0."""
-    i = np.arange(n_rows, dtype=np.uint64)[:, None]
+    i = np.asarray(rows, dtype=np.uint64)[:, None]
     c = np.arange(n_cols, dtype=np.uint64)[None, :]
     ctr = (np.uint64(stream) << np.uint64(60)) | (c << np.uint64(40)) | i
     top = splitmix64(seed, ctr) >> np.uint64(63)
     return 1.0 - 2.0 * top.astype(np.float64)
+
+
+def rademacher(seed, stream, n_rows, n_cols):
+    """(n_rows, n_cols) matrix of +-1 (rows 0 .. n_rows-1 of rademacher_rows)."""
+    return rademacher_rows(seed, stream, np.arange(n_rows), n_cols)
 
 
 # ---------------------------------------------------------------------------
@@ -274,6 +279,82 @@ class FSA:
         KX = self.K_T.T @ X
         low = dSmn_T @ KX + self.K_T @ (dSmn_T.T @ X) - self.K_T @ (dSm @ KX)
         return dS @ X + low
+
+
+class FSARows:
+    """The quantities of FSA for requested rows only, for inputs too large to
+    assemble: Sigma_m and its Cholesky factor once; taper rows, residual
+    values, D_s, rows of Sigma~_dagger X and rows of the probe block on
+    demand.  The low-rank sum Sigma_m^{-1} Sigma_mn X over all points is
+    streamed in chunks.  Same definitions as FSA (Section 2.1, App. F)."""
+
+    def __init__(self, locs, inducing, theta, gamma, jitter=0.0, chunk=1 << 15):
+        kind, s1, rho, s2 = theta
+        self.locs = np.ascontiguousarray(locs, dtype=np.float64)
+        self.inducing = np.ascontiguousarray(inducing, dtype=np.float64)
+        self.theta = (int(kind), float(s1), float(rho), float(s2))
+        self.gamma = float(gamma)
+        self.n, self.m = self.locs.shape[0], self.inducing.shape[0]
+        self.chunk = chunk
+        self.Sigma_m = covariance(cdist(self.inducing, self.inducing), s1, rho, kind)
+        self.Sigma_m[np.diag_indices(self.m)] += jitter * s1
+        self.chol_m = sla.cho_factor(self.Sigma_m, lower=True)
+
+    def smn_T(self, idx):
+        """Sigma_mn^T rows idx (len(idx) x m)."""
+        kind, s1, rho, _ = self.theta
+        return covariance(cdist(self.locs[idx], self.inducing), s1, rho, kind)
+
+    def k_T(self, idx):
+        """(Sigma_m^{-1} Sigma_mn)^T rows idx."""
+        return np.ascontiguousarray(sla.cho_solve(self.chol_m, self.smn_T(idx).T).T)
+
+    def pattern_rows(self, idx):
+        """Taper pattern of rows idx against all points (CSR over idx)."""
+        return taper_pattern(self.locs[np.asarray(idx)], self.locs, self.gamma)
+
+    def value_rows(self, idx):
+        """Pattern, residual values and D_s of rows idx: (c(d) - Sigma_l)
+        o T + sigma^2 on the diagonal."""
+        kind, s1, rho, s2 = self.theta
+        idx = np.asarray(idx, dtype=np.int64)
+        rp, col = self.pattern_rows(idx)
+        r_loc = np.repeat(np.arange(idx.shape[0], dtype=np.int64), np.diff(rp))
+        cols = col.astype(np.int64)
+        d = _pair_dist(self.locs[idx], self.locs, r_loc, cols)
+        uc, inv = np.unique(cols, return_inverse=True)
+        low = _pair_dots(self.smn_T(idx), self.k_T(uc), r_loc, inv)
+        vals = (covariance(d, s1, rho, kind) - low) * wendland_taper(d, self.gamma)
+        diag = idx[r_loc] == cols
+        vals[diag] += s2
+        D = np.zeros(idx.shape[0])
+        D[r_loc[diag]] = vals[diag]
+        return rp, col, vals, D
+
+    def lowrank_sum(self, X):
+        """Sigma_m^{-1} Sigma_mn X (m x k), streamed over the points."""
+        X = np.asarray(X, dtype=np.float64)
+        acc = np.zeros((self.m, X.shape[1]))
+        for s in range(0, self.n, self.chunk):
+            e = min(self.n, s + self.chunk)
+            acc += self.smn_T(np.arange(s, e)).T @ X[s:e]
+        return sla.cho_solve(self.chol_m, acc)
+
+    def matvec_rows(self, idx, X):
+        """Rows idx of Sigma~_dagger X."""
+        idx = np.asarray(idx, dtype=np.int64)
+        rp, col, vals, _ = self.value_rows(idx)
+        S = sp.csr_matrix((vals, col, rp), shape=(idx.shape[0], self.n))
+        return S @ X + self.smn_T(idx) @ self.lowrank_sum(X)
+
+    def probe_rows(self, idx, t, seed):
+        """Rows idx of the probe block z = Sigma_mn^T L_m^{-T} e + D_s^{1/2} rho."""
+        idx = np.asarray(idx, dtype=np.int64)
+        e = rademacher(seed, STREAM_E, self.m, t)
+        r = rademacher_rows(seed, STREAM_RHO, idx, t)
+        Lm = np.tril(self.chol_m[0])
+        D = self.value_rows(idx)[3]
+        return self.smn_T(idx) @ sla.solve_triangular(Lm, e, lower=True, trans="T") + np.sqrt(D)[:, None] * r
 
 
 # ---------------------------------------------------------------------------

@@ -521,6 +521,15 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   c->stats.iters_min = imin;
   c->stats.iters_max = imax;
   c->stats.probe_iters = tot;
+  {
+    std::vector<double> rr(tp), bn(tp);
+    FSA_HIP(hipMemcpy(rr.data(), b.rr, tp * sizeof(double), hipMemcpyDeviceToHost));
+    FSA_HIP(hipMemcpy(bn.data(), b.bn2, tp * sizeof(double), hipMemcpyDeviceToHost));
+    double rmax = 0.0;
+    for (int k = 0; k < tp; ++k)
+      if (bn[k] > 0.0) rmax = std::max(rmax, std::sqrt(std::max(rr[k], 0.0) / bn[k]));
+    c->stats.rel_res_max = rmax;
+  }
   if (flags[1]) {
     set_error("CG breakdown (h^T Sigma h <= 0 or non-finite)");
     return FSA_ERR_BREAKDOWN;

@@ -667,7 +667,8 @@ __global__ void k_pcg_hupdate(int64_t n, int ncols, int64_t ld, const T* __restr
 }
 
 __global__ void k_pcg_setup(int ncols, const double* __restrict__ bn2_part, int nb, int ldb, const double* __restrict__ rq_part,
-                            int nr, int ldr, double* bn2, double* rz, double* rz0, int* active, int* iters, int* flags) {
+                            int nr, int ldr, double* bn2, double* rz, double* rz0, double* rr, int* active, int* iters,
+                            int* flags) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -677,6 +678,7 @@ __global__ void k_pcg_setup(int ncols, const double* __restrict__ bn2_part, int 
     double r = block_colsum(rq_part, nr, ldr, c, red);
     if (threadIdx.x != 0) continue;
     bn2[c] = b;
+    rr[c] = b;
     rz[c] = r;
     rz0[c] = r;
     iters[c] = 0;
@@ -736,7 +738,7 @@ __global__ __launch_bounds__(256) void k_pcg_beta(int ncols, const double* __res
                                                   const double* __restrict__ rr_part, int nr, int ldr, double* rz,
                                                   const double* __restrict__ alpha, double* beta, int* active,
                                                   int* iters, double* ah, double* bh, const double* __restrict__ bn2,
-                                                  double tol2, int fixed, int max_iter, int* flags) {
+                                                  double* rr_out, double tol2, int fixed, int max_iter, int* flags) {
   __shared__ double red[256];
   const int c = blockIdx.x;
   const bool act = active[c] != 0;
@@ -757,6 +759,7 @@ __global__ __launch_bounds__(256) void k_pcg_beta(int ncols, const double* __res
       }
       iters[c] = it + 1;
       rz[c] = rq;
+      rr_out[c] = rr;
       if (!isfinite(rq)) atomicOr(&flags[1], 1);
       still = (fixed || !(rr < tol2 * bn2[c])) ? 1 : 0;
       active[c] = still;
@@ -832,7 +835,7 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
     nparts_rr = (int)g;
     FSA_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_pcg_setup, dim3(1), dim3(256), 0, st, b.ncols, s.dot2.p, nparts_rr, ncb * 64, s.dot.p,
-                       nparts_rq, ncb * 64, b.bn2, b.rz, b.rz0, b.active, b.iters, b.flags);
+                       nparts_rq, ncb * 64, b.bn2, b.rz, b.rz0, b.rr, b.active, b.iters, b.flags);
   } else {
     int64_t g = spmm_grid(b.n);
     size_t need = (size_t)g * ncb * 64;
@@ -842,7 +845,7 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
                        (const T*)b.V, op.Dinv, b.alpha, 0, 1, b.H, b.Q0, s.dot2.p, s.dot.p, ncb * 64);
     FSA_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_pcg_setup, dim3(1), dim3(256), 0, st, b.ncols, s.dot2.p, (int)g, ncb * 64, s.dot.p, (int)g,
-                       ncb * 64, b.bn2, b.rz, b.rz0, b.active, b.iters, b.flags);
+                       ncb * 64, b.bn2, b.rz, b.rz0, b.rr, b.active, b.iters, b.flags);
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -904,8 +907,8 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
   {
     KT_BEGIN(b);
     hipLaunchKernelGGL(k_pcg_beta, dim3(b.ncols), dim3(256), 0, st, b.ncols, s.dot.p, nparts_rq, ldd, s.dot2.p, nparts_rr,
-                       ldd, b.rz, b.alpha, b.beta, b.active, b.iters, b.alpha_hist, b.beta_hist, b.bn2, tol * tol,
-                       fixed, b.max_iter, b.flags);
+                       ldd, b.rz, b.alpha, b.beta, b.active, b.iters, b.alpha_hist, b.beta_hist, b.bn2, b.rr,
+                       tol * tol, fixed, b.max_iter, b.flags);
     KT_END(b, KT_SMALL);
   }
   // 5. h = q + beta h, p = t + beta p

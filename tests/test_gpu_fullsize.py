@@ -1,0 +1,135 @@
+"""Full-size checks on the MI355X, in the configurations bench.py times.
+
+Likelihood workload: n = 500,000 uniform points, Matérn-3/2 (sigma1^2 = 1,
+rho = 0.05, sigma^2 = 0.1), m = 500 kmeans++ inducing points, ~80 nonzeros
+per row, t = 50 probes.  Sampled rows are checked against the oracle, which
+evaluates them one by one:
+  - taper pattern, bit-exact;
+  - residual values and D_s;
+  - rows of Sigma~_dagger X;
+  - rows of the probe block.
+Properties that hold at any size are checked on the whole problem: mixed
+precision against float64 on the same probes at the benchmark spec tolerance,
+and final relative residuals below the CG tolerance.
+
+Prediction workload: n = n_p = 200,000, exponential, m = 500, s = 100.
+Mixed precision is checked against float64 per variance, with the same
+Rademacher draws."""
+import numpy as np
+import pytest
+
+from oracle import fsa_oracle as O
+from workloads import configs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2405_14492_amd import fsa
+    fsa.lib()
+    return fsa
+
+
+@pytest.fixture(scope="module")
+def c2():
+    w = configs.large_matern()
+    say("workload", w.name, "gamma", w.gamma)
+    return w
+
+
+@pytest.fixture(scope="module")
+def c2_rows(c2):
+    return O.FSARows(c2.locs, c2.inducing, c2.theta, c2.gamma)
+
+
+@pytest.fixture(scope="module")
+def sample(c2):
+    rng = np.random.default_rng(7)
+    idx = rng.choice(c2.n, 1500, replace=False)
+    # include both ends of the sorted-by-cell order's extremes and the corners
+    corners = [int(np.argmin(c2.locs.sum(1))), int(np.argmax(c2.locs.sum(1))), 0, c2.n - 1]
+    return np.unique(np.concatenate([idx, corners]))
+
+
+def test_c2_pattern_values_diag_on_sampled_rows(F, c2, c2_rows, sample):
+    with F.FSA(c2.locs, c2.y, c2.theta, c2.inducing, c2.gamma, num_probes=c2.num_probes, seed=c2.seed) as f:
+        rp, col, vals = f.export_csr(with_values=True)
+        D, _ = f.export_diag()
+    say("nnz", rp[-1], "per row", rp[-1] / c2.n)
+    orp, ocol, ovals, oD = c2_rows.value_rows(sample)
+    scale = np.abs(ovals).max()
+    worst = 0.0
+    for k, i in enumerate(sample):
+        a, b = rp[i], rp[i + 1]
+        assert np.array_equal(col[a:b], ocol[orp[k]:orp[k + 1]]), f"row {i}"
+        worst = max(worst, np.abs(vals[a:b] - ovals[orp[k]:orp[k + 1]]).max() / scale)
+    say("sampled rows", len(sample), "max value error / scale", worst)
+    assert worst < 1e-11
+    np.testing.assert_allclose(D[sample], oD, rtol=1e-11)
+    # every row holds its diagonal; the mean row length matches the taper range's design
+    assert np.all(np.diff(rp) >= 1)
+    assert abs(rp[-1] / c2.n - 80.0) < 1.0
+
+
+def test_c2_operator_and_probe_rows(F, c2, c2_rows, sample):
+    X = np.random.default_rng(8).standard_normal((c2.n, 3))
+    with F.FSA(c2.locs, c2.y, c2.theta, c2.inducing, c2.gamma, num_probes=c2.num_probes, seed=c2.seed) as f:
+        Y = f.apply(F.OP_SIGMA_DAGGER, X)
+        Z = f.apply(F.OP_PROBES, None, ncols=4)
+    ref = c2_rows.matvec_rows(sample, X)
+    err = np.abs(Y[sample] - ref).max() / np.abs(ref).max()
+    refz = c2_rows.probe_rows(sample, 4, c2.seed)
+    errz = np.abs(Z[sample] - refz).max() / np.abs(refz).max()
+    say("operator rows err", err, "probe rows err", errz)
+    assert err < 1e-10
+    assert errz < 1e-10
+
+
+def test_c2_mixed_precision_matches_float64(F, c2):
+    """The bench configuration: float64 to 1e-8 and mixed precision to 1e-6
+    with the same probes; NLL within 1e-4 relative and each gradient
+    component within 1e-4 of its scale; residuals below tolerance."""
+    res = {}
+    for prec, tol in ((F.FP64, 1e-8), (F.MIXED_FP32, 1e-6)):
+        with F.FSA(c2.locs, c2.y, c2.theta, c2.inducing, c2.gamma, num_probes=c2.num_probes, seed=c2.seed,
+                   tol=tol, precision=prec, rr_period=10) as f:
+            nll, grad, st = f.nll_grad()
+        say("precision", prec, "nll", nll, "grad", grad, "iters", st["iters_min"], st["iters_max"],
+            "rel_res_max", st["rel_res_max"])
+        assert 0.0 < st["rel_res_max"] < tol
+        res[prec] = (nll, np.asarray(grad), st)
+    nll64, g64, st64 = res[F.FP64]
+    nllm, gm, _ = res[F.MIXED_FP32]
+    assert abs(nllm - nll64) <= 1e-4 * abs(nll64)
+    scale = np.maximum(np.abs(g64), 0.5 * np.abs(np.asarray(st64["grad_trace"])))
+    assert np.all(np.abs(gm - g64) <= 1e-4 * scale), (gm, g64)
+
+
+def test_c4_predictive_variances_mixed_matches_float64():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2405_14492_amd import fsa as F
+    w = configs.predictive()
+    say("workload", w.name, "gamma", w.gamma)
+    out = {}
+    for prec, tol in ((F.FP64, 1e-8), (F.MIXED_FP32, 1e-7)):
+        with F.FSA(w.locs, w.y, w.theta, w.inducing, w.gamma, num_probes=w.num_probes, seed=w.seed, tol=tol,
+                   precision=prec) as f:
+            var, _, st = f.predict_var(w.pred_locs, w.num_samples)
+        say("precision", prec, "iters", st["iters_max"], "var range", var.min(), var.max())
+        assert np.all(np.isfinite(var))
+        out[prec] = var
+    rel = np.abs(out[F.MIXED_FP32] - out[F.FP64]) / np.abs(out[F.FP64])
+    say("mixed vs float64 max rel", rel.max())
+    assert rel.max() < 1e-4
+    # the predictive variance lies between the nugget and sigma1^2 + sigma^2
+    # up to the Monte-Carlo error of the simulated term
+    s1, s2 = w.sigma1_sq, w.sigma_sq
+    assert np.median(out[F.FP64]) > s2 and np.median(out[F.FP64]) < s1 + s2

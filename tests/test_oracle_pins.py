@@ -376,3 +376,25 @@ def test_algorithm1_stochastic_term_is_unbiased():
     draws = np.array([O.predict_var(mdl, pred, 50, s, tol=1e-12)[0] for s in range(40)])
     se = draws.std(0, ddof=1) / math.sqrt(draws.shape[0])
     assert np.all(np.abs(draws.mean(0) - exact) < 4.5 * se + 1e-12)
+
+
+def test_row_sampled_oracle_equals_assembled_oracle():
+    """FSARows (rows on demand, low-rank sums streamed in chunks) gives the
+    same pattern rows, values, D_s, operator rows and probe rows as the
+    assembled FSA on a problem small enough to assemble."""
+    locs = G.uniform_locations(900, 61)
+    ind = G.random_subset_inducing(locs, 40, 62)
+    theta = (M32, 1.3, 0.08, 0.07)
+    gamma = G.taper_range_for_uniform(900, 25)
+    full = O.FSA(locs, ind, theta, gamma)
+    rows = O.FSARows(locs, ind, theta, gamma, chunk=128)
+    idx = np.array([0, 5, 17, 450, 899, 233])
+    rp, col, vals, D = rows.value_rows(idx)
+    for k, i in enumerate(idx):
+        a, b = full.row_ptr[i], full.row_ptr[i + 1]
+        assert np.array_equal(col[rp[k]:rp[k + 1]], full.col[a:b])
+        np.testing.assert_allclose(vals[rp[k]:rp[k + 1]], full.vals[a:b], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(D, full.D[idx], rtol=1e-13)
+    X = np.random.default_rng(63).standard_normal((900, 3))
+    np.testing.assert_allclose(rows.matvec_rows(idx, X), full.matvec(X)[idx], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(rows.probe_rows(idx, 4, 64), O.probes(full, 4, 64)[idx], rtol=0, atol=1e-12)
