@@ -172,7 +172,7 @@ struct fsa_ctx {
   Grid grid;
   Csr csr;
   Buf<double> ind, y;
-  Buf<double> Sm, Lm, Lminv, LminvT, C, LCinv, Cinv;
+  Buf<double> Sm, Lm, Lminv, C, LCinv, Cinv;
   Buf<double> A, vals, D, Dinv;
   Buf<float> Af, valsf;
   Buf<double> logdet_parts;  // [0] = 2 sum log diag L_C, [1] = sum log D
@@ -185,8 +185,9 @@ struct fsa_ctx {
   Buf<double> hist;
   Buf<double> slq_scratch, results;
   // gradient
-  Buf<double> F, dvals, Xb, SX, DX, tmp, G2, dSm, Ework;
+  Buf<double> F, dvals, Xb, SX, DX, tmp, dSm, Ework;
   Scratch scr;
+  BlasHandle blas;
   KernelTimer timer;
   bool solved = false;
   double last_logdet_P = 0;
@@ -229,8 +230,8 @@ static fsa_status build_values(fsa_ctx* c) {
     return FSA_ERR_NOT_SPD;
   }
   FSA_TRY(dense_tri_inverse(c->Lm.p, c->Lminv.p, mp, st));
-  FSA_TRY(transpose_scale(c->Lminv.p, c->LminvT.p, mp, 1.0, st));
-  FSA_TRY(whiten(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->LminvT.p, 0, c->A.p, st));
+  FSA_TRY(blas_acquire(c->blas));
+  FSA_TRY(whiten(c->blas, c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->Lm.p, c->A.p, st));
   FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, true, false,
                           c->vals.p, c->D.p, st));
   FSA_TRY(reciprocal(c->D.p, c->Dinv.p, c->n, st));
@@ -293,7 +294,6 @@ static fsa_status build_core(fsa_ctx* c, const double* locs, const double* y, co
   FSA_TRY(c->Sm.alloc(mm));
   FSA_TRY(c->Lm.alloc(mm));
   FSA_TRY(c->Lminv.alloc(mm));
-  FSA_TRY(c->LminvT.alloc(mm));
   FSA_TRY(c->C.alloc(mm));
   FSA_TRY(c->LCinv.alloc(mm));
   FSA_TRY(c->Cinv.alloc(mm));
@@ -366,7 +366,10 @@ void fsa_default_options(fsa_options* o) {
 
 const char* fsa_last_error(void) { return get_error(); }
 
-void fsa_pool_trim(void) { pool_trim(); }
+void fsa_pool_trim(void) {
+  pool_trim();
+  blas_trim();
+}
 
 fsa_status fsa_build_dev(const double* locs, int64_t n, int32_t d, const double* y, const fsa_theta* theta,
                          const double* inducing, int32_t m, double gamma, const fsa_options* opt, fsa_ctx** out) {
@@ -405,6 +408,7 @@ fsa_status fsa_build(const double* locs, int64_t n, int32_t d, const double* y, 
 void fsa_destroy(fsa_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->st);
+  blas_release(c->blas);
   delete c;  // Buf members return their blocks to the pool
 }
 
@@ -583,17 +587,17 @@ static fsa_status build_derivative(fsa_ctx* c) {
   size_t mm = (size_t)mp * mp;
   FSA_TRY(c->dSm.alloc(mm));
   FSA_TRY(c->Ework.alloc(2 * mm));
-  FSA_TRY(c->G2.alloc(2 * mm));
   FSA_TRY(dense_sigma_m(c->ind.p, c->m, mp, c->th, 0.0, true, c->dSm.p, st));
   double* T1 = c->Ework.p;
   double* E = c->Ework.p + mm;
   FSA_TRY(dense_gemm(c->Lminv.p, false, c->dSm.p, false, T1, mp, 1.0, st));   // L^{-1} dSm
   FSA_TRY(dense_gemm(T1, false, c->Lminv.p, true, E, mp, 1.0, st));           // E = L^{-1} dSm L^{-T}
-  FSA_TRY(dense_gemm(E, false, c->Lminv.p, false, T1, mp, 1.0, st));          // E L^{-1}
-  FSA_HIP(hipMemcpyAsync(c->G2.p, c->LminvT.p, mm * sizeof(double), hipMemcpyDeviceToDevice, st));
-  FSA_TRY(transpose_scale(T1, c->G2.p + mm, mp, -0.5, st));                 // -(E L^{-1})^T / 2
+  // F = L^{-1} dSigma_mn - E A / 2 (point-major n x mp)
   FSA_TRY(c->F.alloc((size_t)c->n * mp));
-  FSA_TRY(whiten(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->G2.p, 1, c->F.p, st));
+  FSA_TRY(blas_acquire(c->blas));
+  FSA_TRY(cov_block(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, true, c->F.p, st));
+  FSA_TRY(blas_solve_lower(c->blas, st, c->Lm.p, mp, c->F.p, c->n));
+  FSA_TRY(blas_left_mul(c->blas, st, E, mp, c->A.p, c->F.p, c->n, -0.5, 1.0));
   FSA_TRY(c->dvals.alloc(c->csr.nnz));
   FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, c->F.p, c->F.p, mp, c->th, c->gamma, true, true,
                           c->dvals.p, nullptr, st));
@@ -769,7 +773,8 @@ static fsa_status predict_core(fsa_ctx* c, const double* pred_locs_h, int64_t n_
   FSA_TRY(Ap.alloc((size_t)n_p * mp));
   FSA_TRY(vPT.alloc(cPT.nnz));
   FSA_TRY(vTP.alloc(cTP.nnz));
-  FSA_TRY(whiten(pg.xs.p, n_p, c->ind.p, c->m, mp, c->th, c->LminvT.p, 0, Ap.p, st));
+  FSA_TRY(blas_acquire(c->blas));
+  FSA_TRY(whiten(c->blas, pg.xs.p, n_p, c->ind.p, c->m, mp, c->th, c->Lm.p, Ap.p, st));
   FSA_TRY(residual_values(pg, c->grid, cPT, Ap.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, false, false, vPT.p,
                           nullptr, st));
   FSA_TRY(residual_values(c->grid, pg, cTP, c->A.p, Ap.p, nullptr, nullptr, mp, c->th, c->gamma, false, false, vTP.p,

@@ -141,101 +141,51 @@ struct PlainPro {
 };
 
 // ================================================================ build-time
-// OUT[i][c] = sum_k Gen(i, k) G[k][c] for all c < mp, 64 points per
-// workgroup (8 waves, wave w owns columns [64w, 64w+64)).  Gen is the
-// covariance row c(x_i, s*_k) (mode 0, K = mp) or [dc/drho | c] (mode 1,
-// K = 2 mp), generated once per (i, k) into LDS.  With upper != 0, G is upper
-// triangular and wave w stops at k = 64 (w+1).
-__global__ __launch_bounds__(512) void k_whiten(const double* __restrict__ xs, int64_t n,
-                                                const double* __restrict__ ind, int m, int mp, Theta th,
-                                                const double* __restrict__ G, int mode, int upper,
-                                                double* __restrict__ out) {
-  __shared__ double As[64][20];
-  __shared__ double Bs[16][520];
-  typedef Mfma<double>::acc acc_t;
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int q = lane >> 4, r16 = lane & 15;
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
-  const int K = mode ? 2 * mp : mp;
-  const int nw = mp / 64;
-  const int kend = upper ? min(K, 64 * (w + 1)) : K;
-  acc_t acc[4][4];
+// out[i][k] = c(x_i, ind_k) or dc/drho for k < m, 0 on the padding; each
+// thread writes four consecutive k of one row.
+__global__ __launch_bounds__(256) void k_cov_block(const double* __restrict__ xs, int64_t n,
+                                                   const double* __restrict__ ind, int m, int mp, Theta th, int deriv,
+                                                   double* __restrict__ out) {
+  const int nq = mp / 4;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * nq) return;
+  const int64_t i = e / nq;
+  const int k0 = (int)(e - i * nq) * 4;
+  const double px = xs[2 * i], py = xs[2 * i + 1];
+  double v[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  // generator mapping: thread -> (row gr, two consecutive k)
-  const int gr = threadIdx.x >> 3;
-  const int gk = (threadIdx.x & 7) * 2;
-  const int64_t gi = row0 + gr;
-  double px = 0.0, py = 0.0;
-  if (gi < n) {
-    px = xs[2 * gi];
-    py = xs[2 * gi + 1];
-  }
-  const int kmax_wg = upper ? min(K, 64 * nw) : K;
-  for (int k0 = 0; k0 < kmax_wg; k0 += 16) {
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      int kk = k0 + gk + u;
-      bool der = false;
-      if (mode == 1) {
-        if (kk < mp) der = true;
-        else kk -= mp;
-      }
-      double v = 0.0;
-      if (gi < n && kk < m) {
-        double dx = px - ind[2 * kk], dy = py - ind[2 * kk + 1];
-        double d = sqrt(dx * dx + dy * dy);
-        v = der ? dcov_drho(d, th) : cov_d(d, th);
-      }
-      As[gr][gk + u] = v;
-    }
-    for (int e = threadIdx.x; e < 16 * mp; e += 512) {
-      int rr = e / mp, cc = e - rr * mp;
-      Bs[rr][cc] = G[(int64_t)(k0 + rr) * mp + cc];
-    }
-    __syncthreads();
-    if (w < nw && k0 < kend) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[a * 16 + r16][4 * q + j];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = Bs[4 * q + j][64 * w + 16 * b + r16];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<double>::op(av[a], bv[b], acc[a][b]);
-      }
+  for (int u = 0; u < 4; ++u) {
+    const int k = k0 + u;
+    v[u] = 0.0;
+    if (k < m) {
+      const double dx = px - ind[2 * k], dy = py - ind[2 * k + 1];
+      const double d = sqrt(dx * dx + dy * dy);
+      v[u] = deriv ? dcov_drho(d, th) : cov_d(d, th);
     }
   }
-  if (w < nw) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int64_t i = row0 + a * 16 + Mfma<double>::orow(q, r);
-          if (i < n) out[i * mp + 64 * w + 16 * b + r16] = acc[a][b][r];
-        }
-  }
+  d2* o = reinterpret_cast<d2*>(out + i * mp + k0);
+  o[0] = d2{v[0], v[1]};
+  o[1] = d2{v[2], v[3]};
 }
 
-fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th, const double* G,
-                  int mode, double* A_out, hipStream_t st) {
-  if (mp > 512) {
-    set_error("whiten: m too large");
+fsa_status cov_block(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th, bool deriv,
+                     double* out, hipStream_t st) {
+  if (mp % 4) {
+    set_error("cov_block: padded m must be a multiple of 4");
     return FSA_ERR_INVALID_ARG;
   }
-  hipLaunchKernelGGL(k_whiten, dim3(ceil_div(n, 64)), dim3(512), 0, st, xs, n, ind, m, mp, th, G, mode,
-                     mode == 0 ? 1 : 0, A_out);
+  const int64_t tot = n * (mp / 4);
+  if (tot == 0) return FSA_OK;
+  hipLaunchKernelGGL(k_cov_block, dim3(ceil_div(tot, 256)), dim3(256), 0, st, xs, n, ind, m, mp, th, deriv ? 1 : 0,
+                     out);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
+}
+
+fsa_status whiten(BlasHandle& b, const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
+                  const double* Lm, double* A_out, hipStream_t st) {
+  FSA_TRY(cov_block(xs, n, ind, m, mp, th, false, A_out, st));
+  return blas_solve_lower(b, st, Lm, mp, A_out, n);
 }
 
 fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const double* Xr, const double* Yc,

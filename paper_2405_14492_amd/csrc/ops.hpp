@@ -61,11 +61,28 @@ struct KernelTimer {
 };
 enum { KT_SPMM = 0, KT_PASS1 = 1, KT_PASS2 = 2, KT_UPDATE = 3, KT_SMALL = 4 };
 
+// ---- dense float64 library products (rocBLAS, pooled handles) ----
+struct BlasHandle {
+  void* h = nullptr;
+  int dev = -1;
+};
+fsa_status blas_acquire(BlasHandle& b);
+void blas_release(BlasHandle& b);
+void blas_trim();
+// X := L^{-1} X (L row-major lower mp x mp, X point-major n x mp)
+fsa_status blas_solve_lower(BlasHandle& b, hipStream_t st, const double* L, int mp, double* X, int64_t n);
+// X := alpha M Y + beta X (M row-major mp x mp; X, Y point-major n x mp)
+fsa_status blas_left_mul(BlasHandle& b, hipStream_t st, const double* M, int mp, const double* Y, double* X, int64_t n,
+                         double alpha, double beta);
+
 // ---- build-time contractions (float64) ----
-// A_out[i][k] = sum_j G[j][k] c(x_i, ind_j)   (G = L_m^{-T}: whitening)
-// mode 1: K = 2 mp, row = [dc/drho(x_i, ind_j) | c(x_i, ind_j)] (derivative factor F)
-fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th, const double* G,
-                  int mode, double* A_out, hipStream_t st);
+// out[i][k] = c(x_i, ind_k) (deriv: dc/drho) for k < m, 0 for m <= k < mp
+// (point-major n x mp, Section 2.1)
+fsa_status cov_block(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th, bool deriv,
+                     double* out, hipStream_t st);
+// A = L_m^{-1} Sigma_mn (point-major n x mp): whitened low-rank factor
+fsa_status whiten(BlasHandle& b, const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
+                  const double* Lm, double* A_out, hipStream_t st);
 // Residual values of a taper pattern (rows of grid rg, columns of grid cg):
 // v = (c(d) - Xr_p . Yc_q) W(d/gamma) (+ s2 on the self diagonal, D[p] = v_pp).
 // deriv: v = (dc/drho(d) - [F|A]_p . [A|F]_q) W(d/gamma).
