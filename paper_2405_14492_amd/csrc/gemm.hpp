@@ -896,76 +896,121 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   }
 }
 
-// ------------------------------------------------------------------ SDDMM
-// One workgroup per row cell; rows are the row set's points in that cell,
-// candidate columns the column set's points in the 3x3 block of cells.
-template <typename T, class XOp, class YOp, class Fn>
-__global__ __launch_bounds__(256) void k_sddmm(const int64_t* __restrict__ rcs, const double* __restrict__ rxs,
-                                               const int64_t* __restrict__ ccs, const double* __restrict__ cxs,
-                                               GridDesc gd, const int64_t* __restrict__ row_ptr,
-                                               const int* __restrict__ col, int kdim, XOp xop, YOp yop, Fn fn,
-                                               double* __restrict__ vals) {
+// ------------------------------------------------------------------ SDDMM (cell-blocked)
+// vals[e] = fn(p, q, d_pq, X_p . Y_q) for every nonzero e = (p, q) of the
+// pattern, float64.  One workgroup (8 waves) per row cell; its rows are
+// taken 32 at a time and the candidate columns (the 3x3 neighbourhood, in
+// Csr::key positions) 256 at a time.  For each 256-wide k chunk the 32 row
+// operands are staged in LDS once; wave w owns column tiles w and w + 8 of
+// the block and keeps their 2 x 2 (row tile x column tile) MFMA 16x16x4
+// accumulators in registers across the chunks, reading its column operands
+// from global memory one step ahead.  The dense 32 x 256 block then goes to
+// LDS, and a coalesced pass over the group's nonzeros picks each value by
+// its key and applies fn.
+template <class XOp, class YOp, class Fn>
+__global__ __launch_bounds__(512) void k_sddmm_cell(const int64_t* __restrict__ rcs, int64_t ncell,
+                                                    const double* __restrict__ rxs, const int64_t* __restrict__ ccs,
+                                                    const double* __restrict__ cxs, GridDesc gd,
+                                                    const int64_t* __restrict__ rp, const int* __restrict__ col,
+                                                    const int* __restrict__ key, int kdim, XOp xop, YOp yop, Fn fn,
+                                                    double* __restrict__ vals) {
 #pragma clang fp contract(off)
-  typedef typename Mfma<T>::acc acc_t;
-  const int64_t cell = blockIdx.x;
+  constexpr int KC = 256, XLD = KC + 2, VB = 256, DLD = VB + 2;
+  __shared__ __attribute__((aligned(16))) double Xs[32 * XLD];
+  __shared__ __attribute__((aligned(16))) double Dv[32 * DLD];
+  typedef Mfma<double>::acc acc_t;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int64_t cell = xcd_cell(blockIdx.x, ncell);
+  if (cell >= ncell) return;
   const int64_t rb = rcs[cell], re = rcs[cell + 1];
   if (rb >= re) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int q = lane >> 4, r16 = lane & 15;
-  const int64_t cx = cell % gd.gx, cy = cell / gd.gx;
-  int64_t qb[3], qe[3], nt[3];
-  int64_t ntot = 0;
-  for (int t = 0; t < 3; ++t) {
-    int64_t yy = cy - 1 + t;
-    qb[t] = qe[t] = 0;
-    if (yy >= 0 && yy < gd.gy) {
-      int64_t xlo = cx - 1 < 0 ? 0 : cx - 1;
-      int64_t xhi = cx + 1 >= gd.gx ? gd.gx - 1 : cx + 1;
-      qb[t] = ccs[yy * gd.gx + xlo];
-      qe[t] = ccs[yy * gd.gx + xhi + 1];
-    }
-    nt[t] = (qe[t] - qb[t] + 15) / 16;
-    ntot += nt[t];
-  }
-  const int64_t nrt = (re - rb + 15) / 16;
-  const int64_t items = nrt * ntot;
-  const double g2 = gd.gamma * gd.gamma;
-  for (int64_t it = w; it < items; it += 4) {
-    int64_t rt = it / ntot, ti = it % ntot;
-    int t = 0;
-    while (ti >= nt[t]) { ti -= nt[t]; ++t; }
-    const int64_t p0 = rb + rt * 16;
-    const int64_t q0 = qb[t] + ti * 16;
-    const int64_t qend = qe[t];
-    const int64_t pa = min(p0 + r16, re - 1);
-    const int64_t qa = min(q0 + r16, qend - 1);
-    acc_t acc = acc_t{0, 0, 0, 0};
-    for (int ks = 0; ks < kdim; ks += 16) {
-      V4<T> a = xop(pa, ks + 4 * q);
-      V4<T> b = yop(qa, ks + 4 * q);
+  int qb[3], qe[3], off[3];
+  const int V = cell_ranges(cell, gd, ccs, qb, qe, off);
+  if (V == 0) return;
+  for (int64_t g0 = rb; g0 < re; g0 += 32) {
+    const int nrg = (int)min((int64_t)32, re - g0);
+    const int64_t E0 = rp[g0], E1 = rp[g0 + nrg];
+    for (int vb0 = 0; vb0 < V; vb0 += VB) {
+      const int vn = min(VB, V - vb0);
+      // this lane's candidate column in each of the wave's two tiles (clamped into range)
+      int64_t qcol[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc = Mfma<T>::op(a.v[j], b.v[j], acc);
-    }
+      for (int t = 0; t < 2; ++t) {
+        int v = vb0 + 16 * (w + 8 * t) + r16;
+        if (v >= V) v = V - 1;
+        qcol[t] = v >= off[2] ? v - off[2] + qb[2] : (v >= off[1] ? v - off[1] + qb[1] : v - off[0] + qb[0]);
+      }
+      const bool tile_on[2] = {16 * w < vn, 16 * (w + 8) < vn};
+      acc_t acc[2][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int64_t p = p0 + Mfma<T>::orow(q, r);
-      int64_t qq = q0 + r16;
-      if (p < re && qq < qend) {
-        double dx = rxs[2 * p] - cxs[2 * qq];
-        double dy = rxs[2 * p + 1] - cxs[2 * qq + 1];
-        double dx2 = dx * dx;
-        double dy2 = dy * dy;
-        double d2 = dx2 + dy2;
-        if (d2 < g2) {
-          int64_t lo = row_ptr[p], hi = row_ptr[p + 1] - 1;
-          while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            if (col[mid] < qq) lo = mid + 1;
-            else hi = mid;
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) acc[t][a] = acc_t{0, 0, 0, 0};
+      for (int kc0 = 0; kc0 < kdim; kc0 += KC) {
+        const int kn = min(KC, kdim - kc0);
+        __syncthreads();
+        // stage rows g0 .. g0+31 (clamped), k in [kc0, kc0 + kn): 4 k per thread item
+        for (int u = tid; u < 32 * (kn / 4); u += 512) {
+          const int r = u / (kn / 4), k4 = (u - r * (kn / 4)) * 4;
+          const int64_t p = g0 + min(r, nrg - 1);
+          const V4<double> x = xop(p, kc0 + k4);
+          double* dst = &Xs[r * XLD + k4];
+          *reinterpret_cast<d2*>(dst) = d2{x.v[0], x.v[1]};
+          *reinterpret_cast<d2*>(dst + 2) = d2{x.v[2], x.v[3]};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (!tile_on[t]) continue;
+          V4<double> b0 = yop(qcol[t], kc0 + 4 * q), b1;
+          for (int ks = 0; ks < kn; ks += 32) {
+            b1 = yop(qcol[t], kc0 + min(ks + 16, kn - 16) + 4 * q);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              const double* xa = &Xs[(a * 16 + r16) * XLD + ks + 4 * q];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc[t][a] = Mfma<double>::op(xa[j], b0.v[j], acc[t][a]);
+            }
+            // kn is a multiple of 64, so the second half-step always exists
+            b0 = yop(qcol[t], kc0 + min(ks + 32, kn - 16) + 4 * q);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              const double* xa = &Xs[(a * 16 + r16) * XLD + ks + 16 + 4 * q];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc[t][a] = Mfma<double>::op(xa[j], b1.v[j], acc[t][a]);
+            }
           }
-          if (lo <= hi && col[lo] == qq) vals[lo] = fn(p, qq, sqrt(d2), (double)acc[r]);
         }
       }
+      // dense block to LDS: row a*16 + orow(q, r), position 16 (w + 8 t) + r16
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if (!tile_on[t]) continue;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Dv[(a * 16 + Mfma<double>::orow(q, r)) * DLD + 16 * (w + 8 * t) + r16] = acc[t][a][r];
+      }
+      __syncthreads();
+      for (int64_t e = E0 + tid; e < E1; e += 512) {
+        const unsigned kv = (unsigned)key[e];
+        const int sl = (int)(kv & KEY_SLOT_MASK) - vb0;
+        if ((unsigned)sl < (unsigned)vn) {
+          const int row = (int)(kv >> KEY_SLOT_BITS);
+          const int64_t p = g0 + row;
+          const int64_t qq = col[e];
+          const double dx = rxs[2 * p] - cxs[2 * qq];
+          const double dy = rxs[2 * p + 1] - cxs[2 * qq + 1];
+          const double dx2 = dx * dx;
+          const double dy2 = dy * dy;
+          const double d2v = dx2 + dy2;
+          vals[e] = fn(p, qq, sqrt(d2v), Dv[row * DLD + sl]);
+        }
+      }
+      __syncthreads();  // Dv and Xs are reused by the next block
     }
   }
 }

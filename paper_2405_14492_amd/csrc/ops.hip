@@ -194,18 +194,20 @@ fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const
   if (rg.ncell == 0) return FSA_OK;
   GridDesc gd = cg.desc;
   gd.gamma = gamma;
+  if (csr.nnz == 0) return FSA_OK;
+  dim3 grid(8 * ceil_div(rg.ncell, 8));
   if (!deriv) {
     RowsOp<double> xo{Xr, mp}, yo{Yc, mp};
     ValFn fn{th, gamma, self ? 1 : 0, D};
-    hipLaunchKernelGGL((k_sddmm<double, RowsOp<double>, RowsOp<double>, ValFn>), dim3(rg.ncell), dim3(256), 0, st,
-                       rg.cstart.p, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, mp, xo, yo, fn,
-                       vals);
+    hipLaunchKernelGGL((k_sddmm_cell<RowsOp<double>, RowsOp<double>, ValFn>), grid, dim3(512), 0, st, rg.cstart.p,
+                       rg.ncell, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, mp, xo, yo,
+                       fn, vals);
   } else {
     Rows2Op<double> xo{Fr, Xr, mp, mp}, yo{Yc, Fc, mp, mp};
     DValFn fn{th, gamma};
-    hipLaunchKernelGGL((k_sddmm<double, Rows2Op<double>, Rows2Op<double>, DValFn>), dim3(rg.ncell), dim3(256), 0, st,
-                       rg.cstart.p, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, 2 * mp, xo, yo, fn,
-                       vals);
+    hipLaunchKernelGGL((k_sddmm_cell<Rows2Op<double>, Rows2Op<double>, DValFn>), grid, dim3(512), 0, st, rg.cstart.p,
+                       rg.ncell, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, 2 * mp, xo,
+                       yo, fn, vals);
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
