@@ -93,4 +93,14 @@ fsa_status blas_left_mul(BlasHandle& b, hipStream_t st, const double* M, int mp,
                      "rocblas_dgemm");
 }
 
+// Linv := L^{-1} for row-major lower-triangular L (mp x mp).  Column-major,
+// row-major L is the upper-triangular L^T, whose inverse (L^{-1})^T read
+// back row-major is L^{-1}.
+fsa_status blas_tri_inverse(BlasHandle& b, hipStream_t st, const double* L, double* Linv, int mp) {
+  auto h = static_cast<rocblas_handle>(b.h);
+  FSA_TRY(blas_status(rocblas_set_stream(h, st), "rocblas_set_stream"));
+  return blas_status(rocblas_dtrtri(h, rocblas_fill_upper, rocblas_diagonal_non_unit, mp, L, mp, Linv, mp),
+                     "rocblas_dtrtri");
+}
+
 }  // namespace fsa

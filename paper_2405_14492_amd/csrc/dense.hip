@@ -151,44 +151,6 @@ fsa_status dense_cholesky(double* A, int mp, int* info_dev, hipStream_t st) {
   return FSA_OK;
 }
 
-// L^{-1} for lower-triangular L: one workgroup per block of 32 columns.
-// Rows are solved in order; row i of the block is
-// x_i = (e_i - sum_{k<i} L_ik x_k) / L_ii with the sum split over 8 lanes
-// per column; the block lives in LDS.
-__global__ __launch_bounds__(256) void k_tri_inverse(const double* __restrict__ L, double* __restrict__ X, int n) {
-  __shared__ double Xs[512][33];
-  const int j0 = blockIdx.x * 32;
-  const int c = threadIdx.x >> 3;   // column within the block
-  const int g = threadIdx.x & 7;    // summation lane
-  for (int i = 0; i < n; ++i) {
-    double s = 0.0;
-    if (i >= j0) {
-      const double* Li = L + (int64_t)i * n;
-      for (int k = j0 + g; k < i; k += 8) s += Li[k] * Xs[k][c];
-    }
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 4, 64);
-    double x = 0.0;
-    if (i >= j0) x = ((i == j0 + c ? 1.0 : 0.0) - s) / L[(int64_t)i * n + i];
-    if (g == 0) {
-      Xs[i][c] = x;
-      X[(int64_t)i * n + j0 + c] = x;
-    }
-    __syncthreads();
-  }
-}
-
-fsa_status dense_tri_inverse(const double* L, double* Linv, int mp, hipStream_t st) {
-  if (mp > 512 || mp % 32) {
-    set_error("triangular inverse: unsupported order %d", mp);
-    return FSA_ERR_INVALID_ARG;
-  }
-  hipLaunchKernelGGL(k_tri_inverse, dim3(mp / 32), dim3(256), 0, st, L, Linv, mp);
-  FSA_HIP(hipGetLastError());
-  return FSA_OK;
-}
-
 // C[i][j] = alpha * sum_k op(A)[i][k] op(B)[k][j]; 16x16 tiles through LDS.
 __global__ __launch_bounds__(256) void k_dense_gemm(const double* __restrict__ A, int ta, const double* __restrict__ B,
                                                     int tb, double* __restrict__ C, int n, double alpha) {

@@ -81,11 +81,14 @@ void pool_trim() {
 }
 
 // ---------------------------------------------------------------- small kernels
-__global__ __launch_bounds__(1024) void k_sum_log(const double* __restrict__ D, int64_t n, double* out, int* bad) {
-  __shared__ double s[1024];
+// sum_i log D_i in two fixed-order stages: part[b] over the points
+// b, b + G, b + 2G, ... (G = gridDim.x), then the G partials; flags a
+// non-positive or non-finite D_i.
+__global__ __launch_bounds__(256) void k_sum_log_part(const double* __restrict__ D, int64_t n, double* part, int* bad) {
+  __shared__ double s[256];
   double a = 0.0;
   int b = 0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int64_t i = blockIdx.x + (int64_t)gridDim.x * threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double v = D[i];
     if (!(v > 0.0) || !isfinite(v)) b = 1;
     a += log(v);
@@ -93,7 +96,19 @@ __global__ __launch_bounds__(1024) void k_sum_log(const double* __restrict__ D, 
   s[threadIdx.x] = a;
   if (b) atomicOr(bad, 1);
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+__global__ __launch_bounds__(256) void k_sum_fixed(const double* __restrict__ part, int np, double* out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) a += part[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
     __syncthreads();
   }
@@ -229,8 +244,8 @@ static fsa_status build_values(fsa_ctx* c) {
     set_error("Cholesky of Sigma_m failed at column %d (duplicate inducing points?)", info - 1);
     return FSA_ERR_NOT_SPD;
   }
-  FSA_TRY(dense_tri_inverse(c->Lm.p, c->Lminv.p, mp, st));
   FSA_TRY(blas_acquire(c->blas));
+  FSA_TRY(blas_tri_inverse(c->blas, st, c->Lm.p, c->Lminv.p, mp));
   FSA_TRY(whiten(c->blas, c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->Lm.p, c->A.p, st));
   FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, true, false,
                           c->vals.p, c->D.p, st));
@@ -241,8 +256,13 @@ static fsa_status build_values(fsa_ctx* c) {
   FSA_HIP(hipMemcpyAsync(&info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipMemsetAsync(c->info.p + 1, 0, sizeof(int), st));
   FSA_TRY(dense_logdet_chol(c->C.p, mp, c->logdet_parts.p, st));
-  hipLaunchKernelGGL(k_sum_log, dim3(1), dim3(1024), 0, st, c->D.p, c->n, c->logdet_parts.p + 1, c->info.p + 1);
-  FSA_TRY(dense_tri_inverse(c->C.p, c->LCinv.p, mp, st));
+  {
+    const int nb = 256;
+    FSA_TRY(c->scr.dot1.alloc(nb));
+    hipLaunchKernelGGL(k_sum_log_part, dim3(nb), dim3(256), 0, st, c->D.p, c->n, c->scr.dot1.p, c->info.p + 1);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, c->scr.dot1.p, nb, c->logdet_parts.p + 1);
+  }
+  FSA_TRY(blas_tri_inverse(c->blas, st, c->C.p, c->LCinv.p, mp));
   FSA_TRY(dense_gemm(c->LCinv.p, true, c->LCinv.p, false, c->Cinv.p, mp, 1.0, st));
   int bad = 0;
   FSA_HIP(hipMemcpyAsync(&bad, c->info.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -812,7 +832,8 @@ static fsa_status predict_core(fsa_ctx* c, const double* pred_locs_h, int64_t n_
   FSA_HIP(hipMemcpyAsync(&info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   if (info) { set_error("Cholesky of I + A Sigma~_s^{-1} A^T failed at column %d", info - 1); return FSA_ERR_NOT_SPD; }
-  FSA_TRY(dense_tri_inverse(Mt.p, LMi.p, mp, st));
+  FSA_TRY(blas_acquire(c->blas));
+  FSA_TRY(blas_tri_inverse(c->blas, st, Mt.p, LMi.p, mp));
   FSA_TRY(transpose_scale(LMi.p, G.p, mp, 1.0, st));
   // Y = A_p L_M^{-T}, Z2 = (S_p^T V~) L_M^{-T}, Z_l = S_p^T W_l
   Buf<double> Y, Y2, Z2, Zl;

@@ -85,8 +85,6 @@ fsa_status dense_sigma_m(const double* ind, int m, int mp, const Theta& th, doub
                          hipStream_t st);
 // In-place lower Cholesky; *info_dev = 0 or (failed column + 1).
 fsa_status dense_cholesky(double* A, int mp, int* info_dev, hipStream_t st);
-// Linv = L^{-1} (lower triangular).
-fsa_status dense_tri_inverse(const double* L, double* Linv, int mp, hipStream_t st);
 // C = alpha * op(A) op(B), op = transpose if flag set; all mp x mp.
 fsa_status dense_gemm(const double* A, bool ta, const double* B, bool tb, double* C, int mp, double alpha,
                       hipStream_t st);
