@@ -138,6 +138,33 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base, int6
 }
 constexpr int BUF_OOR = 0x7ff00000;  // a buffer offset past every range used here
 
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, off, 0, 0);
+  else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ V4<T> bload4(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  V4<T> o;
+  if constexpr (sizeof(T) == 8) {
+    const d2 a = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const d2 b = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0));
+    o.v[0] = a[0]; o.v[1] = a[1]; o.v[2] = b[0]; o.v[3] = b[1];
+  } else {
+    const f4 a = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    o.v[0] = a[0]; o.v[1] = a[1]; o.v[2] = a[2]; o.v[3] = a[3];
+  }
+  return o;
+}
+
+
 // ------------------------------------------------------------------ rows GEMM, float32, resident G
 // Epilogue of the float32 rows GEMM, out-of-place over row-major n x ld
 // blocks.  Modes: ROWS_STORE Y = acc; ROWS_ACC Y += acc; ROWS_PCG t = acc
@@ -313,95 +340,6 @@ __global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim,
 }
 
 // ------------------------------------------------------------------ reduce GEMM
-// grid: (nchunks, ncb = ceil(ncols/64), ceil(kdim / 512)); block 64*NW.
-// Partial tile layout: part[((chunk*ncb + cb)*nmb + mb)*4096 + (tile*4 + r)*64 + lane]
-// with tile = tau*4 + ct, k = mb*64 + 4*orow(lane/16, r) + tau, c = cb*64 + 4*(lane%16) + ct.
-template <typename T, bool DOT, class AOp, class Pro>
-__global__ __launch_bounds__(512) void k_reduce_gemm(int64_t npts, int pts_per_chunk, int kdim, int ncols, AOp acol,
-                                                     Pro pro, T* __restrict__ part, double* __restrict__ dot_part,
-                                                     int ld_dot, int lower_only) {
-  __shared__ __attribute__((aligned(16))) T Xs[64 * XS_LD];
-  __shared__ double red[512];
-  typedef typename Mfma<T>::acc acc_t;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-  const int q = lane >> 4, r16 = lane & 15;
-  const int c0 = blockIdx.y * 64;
-  const int ncb = gridDim.y;
-  const int nmb = kdim / 64;
-  const int mb = blockIdx.z * 8 + w;
-  const bool mactive = mb < nmb && (!lower_only || mb >= (int)blockIdx.y);
-  const int kb = mb * 64;
-  const int64_t pbeg = (int64_t)blockIdx.x * pts_per_chunk;
-  const int64_t pend = min(npts, pbeg + pts_per_chunk);
-  acc_t acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  // prologue thread mapping: column tc, points tp0 + k*(nthreads/64)
-  const int tc = threadIdx.x & 63;
-  const int tp0 = threadIdx.x >> 6;
-  double dacc = 0.0;
-  for (int64_t p0 = pbeg; p0 < pend; p0 += 64) {
-    __syncthreads();
-    constexpr int PB = sizeof(T) == 8 ? 4 : 8;
-    for (int pb = tp0; pb < 64; pb += PB * nw) {
-      typename Pro::In in[PB];
-      const int c = c0 + tc;
-#pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        int pp = pb + u * nw;
-        int64_t p = p0 + pp;
-        if (pp < 64 && p < pend && c < ncols) in[u] = pro.load(p, c);
-      }
-#pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        int pp = pb + u * nw;
-        if (pp < 64) {
-          int64_t p = p0 + pp;
-          T xv = T(0);
-          if (p < pend && c < ncols) xv = pro.apply(p, c, in[u], dacc);
-          Xs[pp * XS_LD + tc] = xv;
-        }
-      }
-    }
-    __syncthreads();
-    if (mactive) {
-#pragma unroll 4
-      for (int kk = 0; kk < 64; kk += 4) {
-        int64_t i = p0 + kk + q;
-        V4<T> av;
-        if (i < pend) av = acol(i, kb + 4 * r16);
-        else av = V4<T>{{T(0), T(0), T(0), T(0)}};
-        V4<T> xv = load4(&Xs[(kk + q) * XS_LD + 4 * r16]);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::op(av.v[a], xv.v[b], acc[a][b]);
-      }
-    }
-  }
-  if (mactive) {
-    T* dst = part + (((int64_t)blockIdx.x * ncb + blockIdx.y) * nmb + mb) * 4096;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dst[((a * 4 + b) * 4 + r) * 64 + lane] = acc[a][b][r];
-  }
-  if constexpr (DOT) {
-    red[threadIdx.x] = dacc;
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      double s = 0.0;
-      for (int k = 0; k < nw; ++k) s += red[k * 64 + threadIdx.x];
-      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + threadIdx.x] = s;
-    }
-  }
-}
-
 // Prologue of the float32 reduce GEMM: X(p, c) = x(p, c) * scale, where
 // x = S(p, c), or with UPD the updated residual x = S - alpha_c V (written
 // back to S, and |x|^2 accumulated per column), and scale = 1 (SC = 0),
@@ -441,11 +379,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q = lane >> 4, r16 = lane & 15;
-  const int c0 = blockIdx.y * 64;
-  const int ncb = gridDim.y;
+  const int c0 = blockIdx.x * 64;
+  const int ncb = gridDim.x;
+  const int chunk = blockIdx.y;
   const int kb = blockIdx.z * 512 + w * 64;
   const bool mactive = kb < kdim;
-  const int64_t pbeg = (int64_t)blockIdx.x * pts_per_chunk;
+  const int64_t pbeg = (int64_t)chunk * pts_per_chunk;
   const int64_t pend = min(npts, pbeg + pts_per_chunk);
   const int np = pend > pbeg ? (int)(pend - pbeg) : 0;
   const int nsteps = (np + SP - 1) / SP;
@@ -540,7 +479,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   if (mactive) {
     // tile (a, b) row i = 4 q' + r, column r16: k = kb + 4 i + a, c = 4 r16 + b
-    float* dst = part + (((int64_t)blockIdx.x * ncb + blockIdx.y) * kdim + kb) * 64 + 4 * r16;
+    float* dst = part + (((int64_t)chunk * ncb + blockIdx.x) * kdim + kb) * 64 + 4 * r16;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -554,7 +493,142 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (tid < 64) {
       double sum = 0.0;
       for (int k = 0; k < 8; ++k) sum += red[k * 64 + tid];
-      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + tid] = sum;
+      dot_part[(int64_t)chunk * ld_dot + c0 + tid] = sum;
+    }
+  }
+}
+
+// Float64 version: grid (ncb, nchunks, zb), 1024 threads; wave w owns the
+// 32 rows 512 z + 32 w .. +31 of the kdim side (two 16-row MFMA tiles, rows
+// interleaved by two so that a lane loads two adjacent A entries with one
+// 16-byte buffer load) for the workgroup's 64-column block.  Points are taken
+// 16 per step; the next step's A rows and prologue inputs are in flight
+// while the matrix cores work on the current step (double-buffered
+// registers and LDS).  Same prologue modes and partial layout as the float32
+// kernel.  With lower_only, rows below the column block's diagonal block are
+// skipped (symmetric products).
+struct F64Pro {
+  double* S;
+  const double* V;
+  const double* alpha;
+  const double* sc;
+  int64_t ld;
+};
+
+template <bool UPD, int SC>
+__global__ __launch_bounds__(1024) void k_reduce_gemm_f64(int64_t npts, int pts_per_chunk, int kdim, int ncols,
+                                                          const double* __restrict__ A, F64Pro pro,
+                                                          double* __restrict__ part, double* __restrict__ dot_part,
+                                                          int ld_dot, int lower_only) {
+  constexpr int SP = 16;       // points per step
+  constexpr int NA = SP / 4;   // A loads per lane per step
+  __shared__ __attribute__((aligned(16))) double Xs[2][SP * XS_LD];
+  __shared__ double red[1024];
+  typedef Mfma<double>::acc acc_t;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.x * 64;
+  const int ncb = gridDim.x;
+  const int chunk = blockIdx.y;
+  const int kb = blockIdx.z * 512 + w * 32;
+  const bool mactive = kb < kdim && (!lower_only || kb >= c0);
+  const int64_t pbeg = (int64_t)chunk * pts_per_chunk;
+  const int64_t pend = min(npts, pbeg + pts_per_chunk);
+  const int np = pend > pbeg ? (int)(pend - pbeg) : 0;
+  const int nsteps = (np + SP - 1) / SP;
+  const int tc = tid & 63, tp = tid >> 6;  // prologue: column c0 + tc, point tp of the step
+  const int c = c0 + tc;
+  const bool cval = c < ncols;
+  acc_t acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  double dacc = 0.0;
+  d2 ab0[NA] = {}, ab1[NA] = {};
+  const __amdgpu_buffer_rsrc_t arsrc = rsrc_of(A + pbeg * kdim, (int64_t)np * kdim * 8);
+  const __amdgpu_buffer_rsrc_t srsrc = rsrc_of(pro.S + pbeg * pro.ld, (int64_t)np * pro.ld * 8);
+  const __amdgpu_buffer_rsrc_t vrsrc = rsrc_of(UPD ? pro.V + pbeg * pro.ld : pro.S, UPD ? (int64_t)np * pro.ld * 8 : 0);
+  const __amdgpu_buffer_rsrc_t drsrc = rsrc_of(SC ? pro.sc + pbeg : (const double*)pro.S, SC ? (int64_t)np * 8 : 0);
+  const double a_c = (UPD && cval) ? pro.alpha[c] : 0.0;
+  const unsigned a_off = mactive ? (unsigned)(q * kdim + kb + 2 * r16) * 8u : (unsigned)BUF_OOR;
+  const unsigned s_off = cval ? (unsigned)(tp * (int)pro.ld + c) * 8u : (unsigned)BUF_OOR;
+  const unsigned s_step = (unsigned)SP * (unsigned)pro.ld * 8u;
+  double sv = 0.0, vv = 0.0, dv = 1.0;
+  auto load_a = [&](int s, d2* ab) {
+    const unsigned so = a_off + (unsigned)(s * SP * kdim) * 8u;
+#pragma unroll
+    for (int k = 0; k < NA; ++k)
+      ab[k] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(arsrc, so + 32u * k * kdim, 0, 0));
+  };
+  auto pro_load = [&](int s) {
+    const unsigned o = s_off + (unsigned)s * s_step;
+    sv = bload<double>(srsrc, o);
+    if constexpr (UPD) vv = bload<double>(vrsrc, o);
+    if constexpr (SC != 0) dv = bload<double>(drsrc, (unsigned)(s * SP + tp) * 8u);
+  };
+  auto pro_apply = [&](int s, double* xs) {
+    const int pr = s * SP + tp;
+    double x = sv;
+    if constexpr (UPD) {
+      x = x - a_c * vv;
+      bstore<double>(x, srsrc, s_off + (unsigned)s * s_step);
+      dacc += x * x;  // zero for padding columns and points past the chunk
+    }
+    const double y = SC == 0 ? x : (SC == 1 ? x * dv : x / dv);
+    xs[tp * XS_LD + tc] = (pr < np && cval) ? y : 0.0;
+  };
+  auto mma = [&](const d2* ab, const double* xs) {
+    if (!mactive) return;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const V4<double> xv = load4(&xs[(4 * k + q) * XS_LD + 4 * r16]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<double>::op(ab[k][a], xv.v[b], acc[a][b]);
+    }
+  };
+  auto step = [&](int s, const d2* abc, d2* abn) {
+    pro_load(s + 1);
+    load_a(s + 1, abn);
+    mma(abc, Xs[s & 1]);
+    pro_apply(s + 1, Xs[(s + 1) & 1]);
+    __syncthreads();
+  };
+  if (nsteps > 0) {
+    pro_load(0);
+    load_a(0, ab0);
+    pro_apply(0, Xs[0]);
+    __syncthreads();
+    int s = 0;
+    for (; s + 1 < nsteps; s += 2) {
+      step(s, ab0, ab1);
+      step(s + 1, ab1, ab0);
+    }
+    if (s < nsteps) step(s, ab0, ab1);
+  }
+  if (mactive) {
+    // tile (a, b) row i = orow(q, r), column r16: k = kb + 2 i + a, c = 4 r16 + b
+    double* dst = part + (((int64_t)chunk * ncb + blockIdx.x) * kdim + kb) * 64 + 4 * r16;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double* o = dst + (2 * Mfma<double>::orow(q, r) + a) * 64;
+        *reinterpret_cast<d2*>(o) = d2{acc[a][0][r], acc[a][1][r]};
+        *reinterpret_cast<d2*>(o + 2) = d2{acc[a][2][r], acc[a][3][r]};
+      }
+  }
+  if constexpr (UPD) {
+    red[tid] = dacc;
+    __syncthreads();
+    if (tid < 64) {
+      double sum = 0.0;
+      for (int k = 0; k < 16; ++k) sum += red[k * 64 + tid];
+      dot_part[(int64_t)chunk * ld_dot + c0 + tid] = sum;
     }
   }
 }
@@ -562,11 +636,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 // Sum the row-major per-chunk partials of k_reduce_gemm_f32 (fixed order,
 // eight interleaved partial sums) into W (float64, row-major kdim x ldw, all
 // 64 ncb columns); optionally add the identity.
-__global__ void k_reduce_parts_rm(const float* __restrict__ part, int nchunks, int ncb, int kdim,
-                                  double* __restrict__ W, int ldw, int add_identity) {
+template <typename TP>
+__global__ void k_reduce_parts_rm(const TP* __restrict__ part, int nchunks, int ncb, int kdim,
+                                  double* __restrict__ W, int ldw, int add_identity, int lower_only) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)ncb * kdim * 64;
   if (e >= per) return;
+  if (lower_only && (int)((e >> 6) % kdim) < 64 * (int)((e >> 6) / kdim)) return;
   double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int ch = 0;
   for (; ch + 8 <= nchunks; ch += 8) {
@@ -582,36 +658,6 @@ __global__ void k_reduce_parts_rm(const float* __restrict__ part, int nchunks, i
   const int cc = cb * 64 + cl;
   if (add_identity && k == cc) sum += 1.0;
   W[(int64_t)k * ldw + cc] = sum;
-}
-
-// Sum the per-chunk partial tiles (fixed order, eight interleaved partial
-// sums) into W (float64, row-major kdim x ldw); optionally add the identity.
-template <typename T>
-__global__ void k_reduce_parts(const T* __restrict__ part, int nchunks, int ncb, int nmb, double* __restrict__ W,
-                               int ldw, int add_identity, int lower_only) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t per = (int64_t)ncb * nmb * 4096;
-  if (e >= per) return;
-  if (lower_only && (int)((e >> 12) % nmb) < (int)((e >> 12) / nmb)) return;
-  double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int ch = 0;
-  for (; ch + 8 <= nchunks; ch += 8) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s8[u] += (double)part[(int64_t)(ch + u) * per + e];
-  }
-  for (int u = 0; ch < nchunks; ++ch, ++u) s8[u] += (double)part[(int64_t)ch * per + e];
-  double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
-  int lane = (int)(e & 63);
-  int r = (int)((e >> 6) & 3);
-  int tile = (int)((e >> 8) & 15);
-  int64_t blk = e >> 12;
-  int mb = (int)(blk % nmb);
-  int cb = (int)(blk / nmb);
-  int tau = tile >> 2, ct = tile & 3;
-  int k = mb * 64 + 4 * Mfma<T>::orow(lane >> 4, r) + tau;
-  int c = cb * 64 + 4 * (lane & 15) + ct;
-  if (add_identity && k == c) s += 1.0;
-  W[(int64_t)k * ldw + c] = s;
 }
 
 // Column sums of per-workgroup partials: out[c] = sum_k part[k*ldp + c],
@@ -647,32 +693,6 @@ struct SpmmShape {
 __device__ __forceinline__ int64_t xcd_cell(int64_t b, int64_t ncell) {
   const int64_t per = (ncell + 7) >> 3;
   return (b & 7) * per + (b >> 3);
-}
-
-typedef unsigned u2v __attribute__((ext_vector_type(2)));
-typedef unsigned u4v __attribute__((ext_vector_type(4)));
-template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-template <typename T>
-__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, off, 0, 0);
-  else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
-}
-template <typename T>
-__device__ __forceinline__ V4<T> bload4(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  V4<T> o;
-  if constexpr (sizeof(T) == 8) {
-    const d2 a = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-    const d2 b = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0));
-    o.v[0] = a[0]; o.v[1] = a[1]; o.v[2] = b[0]; o.v[3] = b[1];
-  } else {
-    const f4 a = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-    o.v[0] = a[0]; o.v[1] = a[1]; o.v[2] = a[2]; o.v[3] = a[3];
-  }
-  return o;
 }
 
 // Epilogue of the sparse product over row-major n x ld blocks.  Modes:

@@ -108,6 +108,7 @@ struct DivDPro {
   static constexpr bool kUpd = false;
   static constexpr int kSc = 2;
   F32Pro f32() const { return F32Pro{(float*)S, nullptr, nullptr, D, ld}; }
+  F64Pro f64() const { return F64Pro{(double*)S, nullptr, nullptr, D, ld}; }
   __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c], D[p]}; }
   __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)((double)x.s / x.d); }
 };
@@ -121,6 +122,7 @@ struct MulDinvPro {
   static constexpr bool kUpd = false;
   static constexpr int kSc = 1;
   F32Pro f32() const { return F32Pro{(float*)S, nullptr, nullptr, Dinv, ld}; }
+  F64Pro f64() const { return F64Pro{(double*)S, nullptr, nullptr, Dinv, ld}; }
   __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c], Dinv[p]}; }
   __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)((double)x.s * x.d); }
 };
@@ -135,6 +137,10 @@ struct PlainPro {
   F32Pro f32() const {
     static_assert(std::is_same<TS, float>::value, "float32 prologue reads float32");
     return F32Pro{(float*)S, nullptr, nullptr, nullptr, ld};
+  }
+  F64Pro f64() const {
+    static_assert(std::is_same<TS, double>::value, "float64 prologue reads float64");
+    return F64Pro{(double*)S, nullptr, nullptr, nullptr, ld};
   }
   __device__ __forceinline__ In load(int64_t p, int c) const { return In{S[p * ld + c]}; }
   __device__ __forceinline__ T apply(int64_t, int, const In& x, double&) const { return (T)x.s; }
@@ -248,13 +254,28 @@ static fsa_status ensure_part(Scratch& s, const ReduceShape& r) {
 // single workgroup along z, which kdim <= 512 guarantees.
 template <typename T, bool DOT, class Pro>
 static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int ncols, const T* A, const Pro& pro,
-                                T* part, double* dot_part, int ld_dot, hipStream_t st) {
+                                T* part, double* dot_part, int ld_dot, hipStream_t st, int lower_only = 0) {
   if (DOT && r.zb != 1) {
     set_error("reduce GEMM with a dot prologue needs kdim <= 512 (got %d)", kdim);
     return FSA_ERR_INVALID_ARG;
   }
-  if constexpr (std::is_same<T, float>::value) {
-    dim3 grid(r.nchunks, r.ncb, (kdim + 511) / 512);
+  // grid (column blocks, chunks, kdim blocks): the column blocks of one chunk run back to back
+  if constexpr (std::is_same<T, double>::value) {
+    dim3 grid(r.ncb, r.nchunks, (kdim + 511) / 512);
+    F64Pro fp = pro.f64();
+    if constexpr (Pro::kUpd) {
+      hipLaunchKernelGGL((k_reduce_gemm_f64<true, Pro::kSc>), grid, dim3(1024), 0, st, n, r.ppc, kdim, ncols, A, fp,
+                         part, dot_part, ld_dot, lower_only);
+    } else {
+      hipLaunchKernelGGL((k_reduce_gemm_f64<false, Pro::kSc>), grid, dim3(1024), 0, st, n, r.ppc, kdim, ncols, A,
+                         fp, part, dot_part, ld_dot, lower_only);
+    }
+  } else if constexpr (std::is_same<T, float>::value) {
+    if (lower_only) {
+      set_error("reduce GEMM: lower-only products are float64");
+      return FSA_ERR_INVALID_ARG;
+    }
+    dim3 grid(r.ncb, r.nchunks, (kdim + 511) / 512);
     F32Pro fp = pro.f32();
     if constexpr (Pro::kUpd) {
       hipLaunchKernelGGL((k_reduce_gemm_f32<true, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim, ncols, A, fp,
@@ -264,9 +285,7 @@ static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int n
                          part, dot_part, ld_dot);
     }
   } else {
-    RowsOp<T> acol{A, kdim};
-    hipLaunchKernelGGL((k_reduce_gemm<T, DOT, RowsOp<T>, Pro>), dim3(r.nchunks, r.ncb, r.zb), dim3(r.threads), 0, st,
-                       n, r.ppc, kdim, ncols, acol, pro, part, dot_part, ld_dot, 0);
+    static_assert(std::is_same<T, float>::value || std::is_same<T, double>::value, "float32 or float64 only");
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -276,14 +295,9 @@ template <typename T>
 static fsa_status reduce_finish(Scratch& s, const ReduceShape& r, double* W, int ldw, int add_id, hipStream_t st,
                                 int lower_only = 0) {
   int64_t per = (int64_t)r.ncb * r.nmb * 4096;
-  if constexpr (std::is_same<T, float>::value) {
-    // row-major partials of the pipelined float32 kernel (all of kdim)
-    hipLaunchKernelGGL(k_reduce_parts_rm, dim3(ceil_div(per, 256)), dim3(256), 0, st, (const float*)s.part.p,
-                       r.nchunks, r.ncb, r.nmb * 64, W, ldw, add_id);
-  } else {
-    hipLaunchKernelGGL(k_reduce_parts<T>, dim3(ceil_div(per, 256)), dim3(256), 0, st, (const T*)s.part.p, r.nchunks,
-                       r.ncb, r.nmb, W, ldw, add_id, lower_only);
-  }
+  // row-major partials of the pipelined kernels (all of kdim)
+  hipLaunchKernelGGL(k_reduce_parts_rm<T>, dim3(ceil_div(per, 256)), dim3(256), 0, st, (const T*)s.part.p, r.nchunks,
+                     r.ncb, r.nmb * 64, W, ldw, add_id, lower_only);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -292,10 +306,7 @@ fsa_status capacitance(const double* A, const double* D, int64_t n, int mp, doub
   ReduceShape r = reduce_shape(n, mp, mp);
   FSA_TRY(ensure_part<double>(s, r));
   DivDPro<double> pro{A, mp, D};
-  RowsOp<double> acol{A, mp};
-  hipLaunchKernelGGL((k_reduce_gemm<double, false, RowsOp<double>, DivDPro<double>>), dim3(r.nchunks, r.ncb, r.zb),
-                     dim3(r.threads), 0, st, n, r.ppc, mp, mp, acol, pro, (double*)s.part.p, (double*)nullptr, 0, 1);
-  FSA_HIP(hipGetLastError());
+  FSA_TRY((launch_reduce<double, false>(r, n, mp, mp, A, pro, (double*)s.part.p, nullptr, 0, st, 1)));
   return reduce_finish<double>(s, r, C, mp, 1, st, 1);
 }
 
@@ -513,6 +524,7 @@ struct PcgPass1Pro {
   static constexpr bool kUpd = true;
   static constexpr int kSc = 1;
   F32Pro f32() const { return F32Pro{(float*)R, (const float*)V, alpha, Dinv, ld}; }
+  F64Pro f64() const { return F64Pro{(double*)R, (const double*)V, alpha, Dinv, ld}; }
   __device__ __forceinline__ In load(int64_t p, int c) const {
     int64_t o = p * ld + c;
     return In{R[o], V[o], Dinv[p], alpha[c]};
