@@ -44,7 +44,7 @@ KERNEL_NAMES = {
     "f32": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<true, 1>", "k_rows_gemm_f32<true, 2>",
             "k_pcg_hupdate<float>"],
     "f64": ["k_spmm_dense<double, 2>", "k_reduce_gemm_f64<true, 1>",
-            "k_rows_gemm<double, 2, true, RowsOp<double>, PcgPass2Epi<double> >", "k_pcg_hupdate<double>"],
+            "k_rows_gemm_f64<true, 2, 3>", "k_pcg_hupdate<double>"],
 }
 COUNTERS = os.path.join(ROOT, "profiles", "pcg_kernels_n500k_m500_t50_counters.md")
 

@@ -339,6 +339,161 @@ __global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim,
   }
 }
 
+// ------------------------------------------------------------------ rows GEMM, float64, resident G slice
+// OUT(i, c) = sum_k A[i][acol0 + k] G[grow0 + k][c], k < kh <= 256, one
+// 64-column block: the kh x 64 slice of G stays in LDS as [k/4][c][k%4]
+// (128 KB).  A product with a longer k runs as passes over 256-k slices:
+// the first stores its partial sums in `part`, middle passes add to them,
+// the last adds them and applies the epilogue (PM: 0 single pass, 1 first,
+// 2 middle, 3 last).  The 16 waves are persistent over 16-row tiles and
+// walk k in steps of 32: a lane loads 64 contiguous bytes of its row
+// (k = 32 s + 8 q' + 4 t + j for MFMA t, j) through a per-tile buffer
+// resource, one step ahead across tile boundaries.  Epilogue modes as in
+// the float32 kernel (ROWS_STORE, ROWS_PCG, ROWS_PCG_INIT).
+struct F64RowsEpi {
+  double* Y;
+  const double* R;
+  const double* Dinv;
+  double* H;
+  double* P;
+  double* Q0;
+  int64_t ld;
+};
+
+template <bool DOT, int EM, int PM>
+__global__ __launch_bounds__(1024) void k_rows_gemm_f64(int64_t nrows, const double* __restrict__ A, int64_t lda,
+                                                        int acol0, int kh, const double* __restrict__ G, int ldg,
+                                                        int grow0, int ncols, F64RowsEpi epi,
+                                                        double* __restrict__ part, double* __restrict__ dot_part,
+                                                        int ld_dot) {
+  extern __shared__ __attribute__((aligned(16))) double gres64[];
+  __shared__ double red[16][64];
+  typedef Mfma<double>::acc acc_t;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.y * 64;
+  for (int e = tid; e < kh * 64; e += 1024) {
+    const int k = e >> 6, cc = e & 63;
+    const double v = (c0 + cc < ncols) ? G[(int64_t)(grow0 + k) * ldg + c0 + cc] : 0.0;
+    gres64[(((k >> 2) * 64 + cc) << 2) + (k & 3)] = v;
+  }
+  __syncthreads();
+  const int nks = kh / 32;
+  const int64_t ntile = (nrows + 15) / 16;
+  const int64_t gw = (int64_t)blockIdx.x * 16 + w, GW = (int64_t)gridDim.x * 16;
+  const int64_t ntw = gw < ntile ? (ntile - gw + GW - 1) / GW : 0;
+  const unsigned lane_off = (unsigned)(r16 * (int)lda + acol0 + 8 * q) * 8u;
+  double dsum[4] = {0, 0, 0, 0};
+  int64_t lj = 0;
+  int lks = 0;
+  auto load_next = [&](d2* ab) {
+    const int64_t row0 = (gw + lj * GW) * 16;
+    const int64_t nr = lj < ntw ? min((int64_t)16, nrows - row0) : 0;
+    const __amdgpu_buffer_rsrc_t rs = rsrc_of(A + (lj < ntw ? row0 * lda : 0), nr * lda * 8);
+    const unsigned o = lane_off + (unsigned)lks * 256u;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ab[t] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u * t, 0, 0));
+    if (++lks == nks) {
+      lks = 0;
+      ++lj;
+    }
+  };
+  acc_t acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = acc_t{0, 0, 0, 0};
+  int64_t cj = 0;
+  int cks = 0;
+  auto epilogue = [&]() {
+    const int64_t row0 = (gw + cj * GW) * 16;
+    const int64_t nr = min((int64_t)16, nrows - row0);
+    const int64_t bytes = nr * epi.ld * 8;
+    const __amdgpu_buffer_rsrc_t rpart = rsrc_of(part ? part + row0 * epi.ld : A, part ? bytes : 0);
+    const __amdgpu_buffer_rsrc_t ry = rsrc_of(epi.Y ? epi.Y + row0 * epi.ld : A, epi.Y ? bytes : 0);
+    const __amdgpu_buffer_rsrc_t rr = rsrc_of(epi.R ? epi.R + row0 * epi.ld : A, epi.R ? bytes : 0);
+    const __amdgpu_buffer_rsrc_t rd = rsrc_of(epi.Dinv ? epi.Dinv + row0 : A, epi.Dinv ? nr * 8 : 0);
+    const __amdgpu_buffer_rsrc_t rh = rsrc_of(EM == ROWS_PCG_INIT ? epi.H + row0 * epi.ld : A, EM == ROWS_PCG_INIT ? bytes : 0);
+    const __amdgpu_buffer_rsrc_t rp = rsrc_of(EM == ROWS_PCG_INIT ? epi.P + row0 * epi.ld : A, EM == ROWS_PCG_INIT ? bytes : 0);
+    const __amdgpu_buffer_rsrc_t rq = rsrc_of(EM == ROWS_PCG_INIT ? epi.Q0 + row0 * epi.ld : A, EM == ROWS_PCG_INIT ? bytes : 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = Mfma<double>::orow(q, r);
+      double di = 0.0;
+      if constexpr ((PM == 0 || PM == 3) && EM >= ROWS_PCG) di = bload<double>(rd, (unsigned)i * 8u);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int c = c0 + b * 16 + r16;
+        const unsigned o = c < ncols ? (unsigned)(i * (int)epi.ld + c) * 8u : (unsigned)BUF_OOR;
+        double v = acc[b][r];
+        if constexpr (PM >= 2) v += bload<double>(rpart, o);
+        if constexpr (PM == 1 || PM == 2) {
+          bstore<double>(v, rpart, o);
+        } else if constexpr (EM == ROWS_STORE) {
+          bstore<double>(v, ry, o);
+        } else {
+          const double rv = bload<double>(rr, o);
+          const double qv = (rv - v) * di;
+          dsum[b] += rv * qv;  // zero past the tile's rows and columns
+          if constexpr (EM == ROWS_PCG) {
+            bstore<double>(v, ry, o);
+          } else {
+            bstore<double>(qv, rh, o);
+            bstore<double>(v, rp, o);
+            bstore<double>(qv, rq, o);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = acc_t{0, 0, 0, 0};
+  };
+  auto step = [&](const d2* cur, d2* nxt) {
+    load_next(nxt);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      V4<double> g[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) g[b] = load4(&gres64[((cks * 8 + 2 * q + t) * 64 + b * 16 + r16) << 2]);
+      const double av[4] = {cur[2 * t][0], cur[2 * t][1], cur[2 * t + 1][0], cur[2 * t + 1][1]};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = Mfma<double>::op(av[j], g[b].v[j], acc[b]);
+    }
+    if (++cks == nks) {
+      epilogue();
+      cks = 0;
+      ++cj;
+    }
+  };
+  const int64_t nflat = ntw * nks;
+  d2 b0[4], b1[4];
+  load_next(b0);
+  int64_t f = 0;
+  for (; f + 1 < nflat; f += 2) {
+    step(b0, b1);
+    step(b1, b0);
+  }
+  if (f < nflat) step(b0, b1);
+  if constexpr (DOT) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double v = dsum[b];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (q == 0) red[w][b * 16 + r16] = v;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double sacc = 0.0;
+      for (int k = 0; k < 16; ++k) sacc += red[k][tid];
+      dot_part[(int64_t)blockIdx.x * ld_dot + c0 + tid] = sacc;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ reduce GEMM
 // Prologue of the float32 reduce GEMM: X(p, c) = x(p, c) * scale, where
 // x = S(p, c), or with UPD the updated residual x = S - alpha_c V (written

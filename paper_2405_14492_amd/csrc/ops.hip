@@ -1,6 +1,7 @@
 // FSA operations: covariance generation + whitening, residual values,
 // capacitance, sparse and low-rank block products, the fused PCG steps of
 // Algorithm 2, and the Lanczos-quadrature eigensolve.
+#include <algorithm>
 #include <type_traits>
 #include "gemm.hpp"
 #include "ops.hpp"
@@ -326,6 +327,52 @@ fsa_status lowrank_reduce(const T* A, int64_t n, int kdim, const T* X, int ldx, 
   return reduce_finish<T>(s, r, W, ldw, 0, st);
 }
 
+// Float64 rows GEMM over [A | A2] (kseg columns each, A2 optional) in passes
+// of at most 256 k; `part` holds the partial sums between passes (it may be
+// the epilogue's own output block).
+template <int EM, int PM>
+static void launch_rows_f64(dim3 grid, size_t smem, hipStream_t st, int64_t n, const double* M, int kseg, int acol0,
+                            int kh, const double* G, int ldg, int grow0, int ncols, const F64RowsEpi& epi,
+                            double* part, double* dot, int ld_dot) {
+  hipLaunchKernelGGL((k_rows_gemm_f64<(EM >= ROWS_PCG), EM, PM>), grid, dim3(1024), smem, st, n, M, (int64_t)kseg,
+                     acol0, kh, G, ldg, grow0, ncols, epi, part, dot, ld_dot);
+}
+template <int EM>
+static fsa_status rows_f64(const double* A, const double* A2, int64_t n, int kseg, const double* G, int ldg,
+                           int ncols, const F64RowsEpi& epi, double* part, double* dot, int ld_dot, int64_t gx,
+                           hipStream_t st) {
+  struct Slice { const double* M; int acol0, kh, grow0; };
+  Slice sl[16];
+  int ns = 0;
+  for (int mat = 0; mat < (A2 ? 2 : 1); ++mat)
+    for (int k0 = 0; k0 < kseg; k0 += 256) {
+      if (ns == 16) {
+        set_error("rows GEMM: k too long");
+        return FSA_ERR_INVALID_ARG;
+      }
+      sl[ns++] = Slice{mat ? A2 : A, k0, std::min(256, kseg - k0), mat * kseg + k0};
+    }
+  if (kseg % 32) {
+    set_error("rows GEMM: k must be a multiple of 32");
+    return FSA_ERR_INVALID_ARG;
+  }
+  if (ns > 1 && !part) {
+    set_error("rows GEMM: multi-pass product needs a partial-sum block");
+    return FSA_ERR_INVALID_ARG;
+  }
+  dim3 grid(gx, ceil_div(ncols, 64));
+  for (int i = 0; i < ns; ++i) {
+    const Slice& x = sl[i];
+    const size_t smem = (size_t)x.kh * 64 * sizeof(double);
+    if (ns == 1) launch_rows_f64<EM, 0>(grid, smem, st, n, x.M, kseg, x.acol0, x.kh, G, ldg, x.grow0, ncols, epi, part, dot, ld_dot);
+    else if (i == 0) launch_rows_f64<EM, 1>(grid, smem, st, n, x.M, kseg, x.acol0, x.kh, G, ldg, x.grow0, ncols, epi, part, dot, ld_dot);
+    else if (i + 1 < ns) launch_rows_f64<EM, 2>(grid, smem, st, n, x.M, kseg, x.acol0, x.kh, G, ldg, x.grow0, ncols, epi, part, dot, ld_dot);
+    else launch_rows_f64<EM, 3>(grid, smem, st, n, x.M, kseg, x.acol0, x.kh, G, ldg, x.grow0, ncols, epi, part, dot, ld_dot);
+    FSA_HIP(hipGetLastError());
+  }
+  return FSA_OK;
+}
+
 template <typename T>
 fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T* G, int ldg, int ncols, T* OUT,
                           int ldo, hipStream_t st) {
@@ -341,17 +388,23 @@ fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T*
       return FSA_OK;
     }
   }
-  if (A2) {
-    Rows2Op<T> op{A, A2, kdim / 2, kdim / 2};
-    hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, false, Rows2Op<T>, StoreEpi<T>>), grid, dim3(256), 0, st, n, kdim, G,
-                       ldg, ncols, 0, op, epi, (double*)nullptr, 0);
+  if constexpr (sizeof(T) == 8) {
+    F64RowsEpi fe{(double*)OUT, nullptr, nullptr, nullptr, nullptr, nullptr, ldo};
+    return rows_f64<ROWS_STORE>((const double*)A, (const double*)A2, n, A2 ? kdim / 2 : kdim, (const double*)G, ldg,
+                                ncols, fe, (double*)OUT, nullptr, 0, f32_rows_grid(), st);
   } else {
-    RowsOp<T> op{A, kdim};
-    hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, false, RowsOp<T>, StoreEpi<T>>), grid, dim3(256), 0, st, n, kdim, G,
-                       ldg, ncols, 0, op, epi, (double*)nullptr, 0);
+    if (A2) {
+      Rows2Op<T> op{A, A2, kdim / 2, kdim / 2};
+      hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, false, Rows2Op<T>, StoreEpi<T>>), grid, dim3(256), 0, st, n, kdim,
+                         G, ldg, ncols, 0, op, epi, (double*)nullptr, 0);
+    } else {
+      RowsOp<T> op{A, kdim};
+      hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, false, RowsOp<T>, StoreEpi<T>>), grid, dim3(256), 0, st, n, kdim,
+                         G, ldg, ncols, 0, op, epi, (double*)nullptr, 0);
+    }
+    FSA_HIP(hipGetLastError());
+    return FSA_OK;
   }
-  FSA_HIP(hipGetLastError());
-  return FSA_OK;
 }
 
 // ---------------------------------------------------------------- SpMM
@@ -762,13 +815,19 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
                          (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
     KT_END(b, KT_PASS2);
   } else {
-    RowsOp<T> aop{op.A, op.kdim};
-    gx = rows_grid(b.n);
+    gx = f32_rows_grid();
     size_t need = (size_t)gx * ncb * 64;
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
+    F64RowsEpi fe{init ? nullptr : (double*)b.Tt, (const double*)b.R, op.Dinv, (double*)b.H, (double*)b.P,
+                  (double*)b.Q0, (int64_t)b.ld};
+    double* part = init ? (double*)b.P : (double*)b.Tt;  // partial sums between the k passes
     KT_BEGIN(b);
-    hipLaunchKernelGGL((k_rows_gemm<T, RT_ROWS, true, RowsOp<T>, PcgPass2Epi<T>>), dim3(gx, ncb), dim3(256), 0, st,
-                       b.n, op.kdim, b.g, b.ldw, b.ncols, 0, aop, epi, s.dot.p, ncb * 64);
+    if (init)
+      FSA_TRY(rows_f64<ROWS_PCG_INIT>((const double*)op.A, nullptr, b.n, op.kdim, (const double*)b.g, b.ldw, b.ncols,
+                                      fe, part, s.dot.p, ncb * 64, gx, st));
+    else
+      FSA_TRY(rows_f64<ROWS_PCG>((const double*)op.A, nullptr, b.n, op.kdim, (const double*)b.g, b.ldw, b.ncols, fe,
+                                 part, s.dot.p, ncb * 64, gx, st));
     KT_END(b, KT_PASS2);
   }
   FSA_HIP(hipGetLastError());
