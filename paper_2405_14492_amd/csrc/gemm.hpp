@@ -863,7 +863,7 @@ struct SpmmEpi {
 };
 
 template <typename T, int EM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4))) void k_spmm_dense(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 5))) void k_spmm_dense(
     const int64_t* __restrict__ rcs, int64_t ncell, const int64_t* __restrict__ ccs, GridDesc gd,
     const int64_t* __restrict__ rp, const int* __restrict__ key, const T* __restrict__ val, const T* __restrict__ X,
     int ldx, int ncols, SpmmEpi<T> epi, double* __restrict__ dot_part, int ld_dot) {
@@ -981,8 +981,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       acc_t acc0 = acc_t{0, 0, 0, 0}, acc1 = acc_t{0, 0, 0, 0};
       V4<T> xr[XU];
       if (ne <= 256 * EPT) {
-        // entries resident in registers for all chunks
-        load_batch(0);
+        // one batch of entries, re-read from cache per chunk (no registers
+        // held across the chunk loop); epilogue inputs load at the end
+        load_chunk(0, xr);
+        for (int vb = 0; vb < V; vb += CH) {
+          __syncthreads();  // the previous chunk's products are done with Xs and Ss
+          stage(xr);
+          __syncthreads();
+          load_batch(0);
+          load_chunk(vb + CH, xr);  // past the neighbourhood: zero, no traffic
+          scatter(0, vb);
+          __syncthreads();
+          mma(acc0, acc1);
+        }
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -993,16 +1004,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
               in1[t][r] = bload<T>(prs, eo[t][r]);
             }
           }
-        load_chunk(0, xr);
-        for (int vb = 0; vb < V; vb += CH) {
-          __syncthreads();  // the previous chunk's products are done with Xs and Ss
-          stage(xr);
-          __syncthreads();
-          load_chunk(vb + CH, xr);  // past the neighbourhood: zero, no traffic
-          scatter(0, vb);
-          __syncthreads();
-          mma(acc0, acc1);
-        }
       } else {
         // long rows: entries re-read per chunk in batches
         const int nbatch = (ne + 256 * EPT - 1) / (256 * EPT);
