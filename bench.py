@@ -41,25 +41,29 @@ def log(*a):
 
 # rocprofv3 kernel names of the four PCG kernel classes, per element type
 KERNEL_NAMES = {
-    "f32": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<true, 1>", "k_rows_gemm_f32<true, 2>",
+    "f32": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<float, true, 1>", "k_rows_gemm_f32<float, true, 2>",
             "k_pcg_hupdate<float>"],
+    "bf16a": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<unsigned short, true, 1>",
+              "k_rows_gemm_f32<unsigned short, true, 2>", "k_pcg_hupdate<float>"],
     "f64": ["k_spmm_dense<double, 2>", "k_reduce_gemm_f64<true, 1>",
             "k_rows_gemm_f64<true, 2, 3>", "k_pcg_hupdate<double>"],
 }
 COUNTERS = os.path.join(ROOT, "profiles", "pcg_kernels_n500k_m500_t50_counters.md")
 
 
-def kernel_work(k, n, m, tp, nnz, b):
+def kernel_work(k, n, m, tp, nnz, b, ba=None):
     """Algorithmic (bytes, flops) per launch of kernel class k with element
-    size b (block vectors, sparse values and low-rank factor); the solution
-    accumulator U is float64 in both modes.  Every operand counted once."""
+    size b (block vectors and sparse values) and ba (low-rank factor, b if
+    None); the solution accumulator U is float64 in every mode.  Every
+    operand counted once."""
     blk = n * tp
+    ba = b if ba is None else ba
     if k == 0:   # V = S H + P, h.v: key (4 B) + value per nonzero, H in, P in, V out, row pointers
         return nnz * (b + 4) + 8 * (n + 1) + 3 * blk * b, 2.0 * nnz * tp
     if k == 1:   # r -= a v (R in/out, V in), W = A D^-1 r: A (n x m) once, D^-1
-        return n * m * b + 3 * blk * b + 8 * n, 2.0 * n * m * tp
+        return n * m * ba + 3 * blk * b + 8 * n, 2.0 * n * m * tp
     if k == 2:   # t = A g, r.q with q = (r - t)/D: A once, R in, T out, D^-1
-        return n * m * b + 2 * blk * b + 8 * n, 2.0 * n * m * tp
+        return n * m * ba + 2 * blk * b + 8 * n, 2.0 * n * m * tp
     if k == 3:   # u += a h (U in/out f64), h = (r - t)/D + beta h, p = t + beta p: R, T, H, P in; H, P out
         return blk * (6 * b + 16) + 8 * n, 6.0 * blk
     return 0, 0
@@ -143,14 +147,17 @@ def run_mode(F, dev, w, precision, steps, warmup, tol, torch):
 
 
 def roofline(res, n, m, tp, precision):
-    b = 4 if precision == "f32" else 8
+    """precision: "f64", "f32" (float32 operator) or "bf16a" (float32
+    operator with A read in bfloat16 and widened to float32 for the MFMA)."""
+    b = 8 if precision == "f64" else 4
+    ba = 2 if precision == "bf16a" else b
     avg = [res["kernel_ms"][k] / max(res["kernel_launches"][k], 1) for k in range(5)]
     dom = int(np.argmax(res["kernel_ms"][:4]))
-    byt, flop = kernel_work(dom, n, m, tp, res["nnz"], b)
+    byt, flop = kernel_work(dom, n, m, tp, res["nnz"], b, ba)
     t_s = avg[dom] / 1000.0
     gbs = byt / t_s / 1e9
     tfl = flop / t_s / 1e12
-    peak_t = PEAK_TFLOPS[precision]
+    peak_t = PEAK_TFLOPS["f64" if precision == "f64" else "f32"]
     t_hbm = byt / (HBM_PEAK_GBS * 1e9)
     t_cmp = flop / (peak_t * 1e12)
     if t_cmp > t_hbm:
@@ -206,7 +213,8 @@ def main():
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--m", type=int, default=500)
     ap.add_argument("--probes", type=int, default=50)
-    ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--modes", default="fp64,mixed",
+                    help="comma list of fp64, mixed (float32 operator), bf16a (float32 operator, bfloat16 A)")
     ap.add_argument("--cpu-sample-n", type=int, default=80_000)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -239,8 +247,8 @@ def main():
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
     results = {}
     for mode in args.modes.split(","):
-        prec = F.MIXED_FP32 if mode == "mixed" else F.FP64
-        tol = 1e-6 if mode == "mixed" else 1e-8
+        prec = {"mixed": F.MIXED_FP32, "bf16a": F.MIXED_BF16A, "fp64": F.FP64}[mode]
+        tol = 1e-8 if mode == "fp64" else 1e-6
         log(f"mode {mode}: warmup {args.warmup}, steps {args.steps}")
         results[mode] = run_mode(F, dev, w, prec, args.steps, args.warmup, tol, torch)
         log(f"mode {mode}: {results[mode]['value']:.1f} probe-iters/s, {results[mode]['ms_per_step']:.2f} ms/step, "
@@ -248,7 +256,8 @@ def main():
             f"{[round(a / max(b, 1), 4) for a, b in zip(results[mode]['kernel_ms'], results[mode]['kernel_launches'])]}")
     main_mode = "mixed" if "mixed" in results else list(results)[0]
     r = results[main_mode]
-    dtype = "f32" if main_mode == "mixed" else "f64"
+    dtype = "f64" if main_mode == "fp64" else "f32"
+    rkey = {"mixed": "f32", "bf16a": "bf16a", "fp64": "f64"}[main_mode]
     out = {
         "metric": "PCG probe-iters/s at n=500k,m=500,t=50 (mixed precision; fp64 beside it)",
         "value": r["value"],
@@ -263,9 +272,9 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"fsa_nll_grad n={args.n} m={args.m} t={args.probes} matern32 "
-                               f"rho=0.05 sigma2=0.1 n_gamma=80 tol={'1e-6' if main_mode == 'mixed' else '1e-8'}",
+                               f"rho=0.05 sigma2=0.1 n_gamma=80 tol={'1e-8' if main_mode == 'fp64' else '1e-6'}",
                    "n": args.n, "m": args.m, "t": args.probes, "gamma": w.gamma, "nnz": r["nnz"]},
-        "roofline": roofline(r, args.n, args.m, args.probes + 1, dtype),
+        "roofline": roofline(r, args.n, args.m, args.probes + 1, rkey),
         "pcg_only_probe_iters_per_s": r["pcg_only_probe_iters_per_s"],
         "modes": results,
     }
@@ -273,6 +282,12 @@ def main():
         out["mixed_over_fp64"] = results["mixed"]["value"] / results["fp64"]["value"]
         out["mixed_vs_fp64_rel_nll"] = abs(results["mixed"]["nll"] - results["fp64"]["nll"]) / abs(results["fp64"]["nll"])
         out["roofline_fp64"] = roofline(results["fp64"], args.n, args.m, args.probes + 1, "f64")
+    if "fp64" in results and "bf16a" in results:
+        f, g = results["fp64"], results["bf16a"]
+        out["bf16a_over_fp64"] = g["value"] / f["value"]
+        out["bf16a_vs_fp64_rel_nll"] = abs(g["nll"] - f["nll"]) / abs(f["nll"])
+        out["bf16a_vs_fp64_rel_grad"] = [abs(a - c) / max(abs(c), 1e-300) for a, c in zip(g["grad"], f["grad"])]
+        out["roofline_bf16a"] = roofline(g, args.n, args.m, args.probes + 1, "bf16a")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_n, args.cpu_iters)

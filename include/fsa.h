@@ -63,8 +63,21 @@ typedef enum { FSA_COV_EXPONENTIAL = 0, FSA_COV_MATERN32 = 1 } fsa_cov;
  *     PCG block vectors in float32; Cholesky factors, inner products, the
  *     CG coefficients, the solution accumulator and the tridiagonal
  *     eigensolve in float64; the residual is recomputed with the float64
- *     operator every rr_period iterations. */
-typedef enum { FSA_FP64 = 0, FSA_MIXED_FP32 = 1 } fsa_precision;
+ *     operator every rr_period iterations.
+ *   MIXED_BF16A: MIXED_FP32 on a model whose whitened low-rank factor A is
+ *     rounded to bfloat16 (to nearest even, once, right after whitening).
+ *     The rounded factor is used everywhere, in float64 where the method is
+ *     float64: the tapered residual is computed against it (so inside the
+ *     taper range the rounding is absorbed and the diagonal stays exact),
+ *     and D_s, the capacitance, the probes, the gradient and the prediction
+ *     factor use it too.  The PCG passes read A as bfloat16 (half the bytes
+ *     of float32) and widen it to float32 in registers.  Results are those
+ *     of the perturbed model: they differ from FP64 by the rounding of A
+ *     outside the taper range, not by solver error.  Its sigma1^2 derivative
+ *     takes the rounded model as proportional to sigma1^2 (as the unrounded
+ *     one is); its rho derivative uses the exact dSigma_mn/drho and
+ *     dSigma_m/drho with the rounded A. */
+typedef enum { FSA_FP64 = 0, FSA_MIXED_FP32 = 1, FSA_MIXED_BF16A = 2 } fsa_precision;
 
 typedef struct {
   int32_t cov;      /* fsa_cov */

@@ -181,7 +181,12 @@ class FSA:
     """Sigma~_dagger = Sigma_mn^T Sigma_m^{-1} Sigma_mn + Sigma_s + sigma^2 I
     (Section 2.1) with its FITC preconditioner (eq. eqfitcp)."""
 
-    def __init__(self, locs, inducing, theta, gamma, jitter=0.0):
+    def __init__(self, locs, inducing, theta, gamma, jitter=0.0, smn_T=None):
+        """smn_T: the n x m matrix to take as Sigma_mn^T in place of the
+        covariance between locations and inducing points (default).  The
+        construction of Section 2.1 holds for any such matrix; tests use it
+        for a model whose low-rank part was rounded.  The derivatives keep
+        the exact dSigma_mn/dtheta."""
         kind, s1, rho, s2 = theta
         self.locs = np.ascontiguousarray(locs, dtype=np.float64)
         self.inducing = np.ascontiguousarray(inducing, dtype=np.float64)
@@ -193,7 +198,12 @@ class FSA:
         # Sigma_m (m x m) and Sigma_mn, stored point-major as Sigma_mn^T (n x m).
         self.Sigma_m = covariance(cdist(self.inducing, self.inducing), s1, rho, kind)
         self.Sigma_m[np.diag_indices(m)] += jitter * s1
-        self.Smn_T = covariance(cdist(self.locs, self.inducing), s1, rho, kind)
+        if smn_T is None:
+            self.Smn_T = covariance(cdist(self.locs, self.inducing), s1, rho, kind)
+        else:
+            self.Smn_T = np.ascontiguousarray(smn_T, dtype=np.float64)
+            if self.Smn_T.shape != (n, m):
+                raise ValueError("smn_T must be n x m")
         self.chol_m = sla.cho_factor(self.Sigma_m, lower=True)
         # K = Sigma_m^{-1} Sigma_mn, stored point-major as K^T (n x m).
         self.K_T = np.ascontiguousarray(sla.cho_solve(self.chol_m, self.Smn_T.T).T)
@@ -493,17 +503,21 @@ def nll_grad(model, y, num_probes, seed, tol=1e-8, max_iter=1000, fixed_iter=0,
 
 
 def predict_var(model, pred_locs, num_samples, seed, tol=1e-8, max_iter=1000, fixed_iter=0,
-                exact_Dl=False, u=None):
+                exact_Dl=False, u=None, smp_T=None):
     """Algorithm 1: D^p = sigma1^2 + sigma^2 - D1 - 2 D2 + D3 - D_l.
 
     Sigma~_s solves use CG preconditioned by D_s (Section 3.3).  With
     exact_Dl the stochastic diagonal is replaced by its exact value (dense,
     small inputs only).  Returns (variances, details); with u =
-    Sigma~^{-1} y given, also the predictive mean (Section 2.3)."""
+    Sigma~^{-1} y given, also the predictive mean (Section 2.3).  smp_T
+    replaces Sigma_{m n_p}^T as smn_T does Sigma_mn^T in FSA."""
     kind, s1, rho, s2 = model.theta
     P = np.ascontiguousarray(pred_locs, dtype=np.float64)
     n_p = P.shape[0]
-    Smp_T = covariance(cdist(P, model.inducing), s1, rho, kind)       # Sigma_{m n_p}^T
+    if smp_T is None:
+        Smp_T = covariance(cdist(P, model.inducing), s1, rho, kind)   # Sigma_{m n_p}^T
+    else:
+        Smp_T = np.ascontiguousarray(smp_T, dtype=np.float64)
     G_T = np.ascontiguousarray(sla.cho_solve(model.chol_m, Smp_T.T).T)   # (Sigma_m^{-1} Sigma_{m n_p})^T
     # Sigma^s_{n n_p} = (Sigma_{n n_p} - Sigma^l_{n n_p}) o T_{n n_p}(gamma), stored n x n_p.
     rp, cl = taper_pattern(model.locs, P, model.gamma)

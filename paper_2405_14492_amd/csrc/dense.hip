@@ -202,6 +202,22 @@ __global__ void k_to_float(const double* __restrict__ in, float* __restrict__ ou
   if (i < cnt) out[i] = (float)in[i];
 }
 
+__global__ void k_to_bf16(const double* in, uint16_t* out, double* rounded, int64_t cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  // the float32 value rounded to the nearest bfloat16, ties to even (finite inputs)
+  const unsigned u = __float_as_uint((float)in[i]);
+  const unsigned h = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  if (out) out[i] = (uint16_t)h;
+  if (rounded) rounded[i] = (double)__uint_as_float(h << 16);
+}
+fsa_status to_bf16(const double* in, uint16_t* out, double* rounded, int64_t cnt, hipStream_t st) {
+  if (cnt <= 0) return FSA_OK;
+  hipLaunchKernelGGL(k_to_bf16, dim3(ceil_div(cnt, 256)), dim3(256), 0, st, in, out, rounded, cnt);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
 fsa_status to_float(const double* in, float* out, int64_t cnt, hipStream_t st) {
   if (cnt <= 0) return FSA_OK;
   hipLaunchKernelGGL(k_to_float, dim3(ceil_div(cnt, 256)), dim3(256), 0, st, in, out, cnt);

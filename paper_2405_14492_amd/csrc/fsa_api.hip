@@ -190,6 +190,7 @@ struct fsa_ctx {
   Buf<double> Sm, Lm, Lminv, C, LCinv, Cinv;
   Buf<double> A, vals, D, Dinv;
   Buf<float> Af, valsf;
+  Buf<uint16_t> Abf;  // bfloat16 copy of A (MIXED_BF16A)
   Buf<double> logdet_parts;  // [0] = 2 sum log diag L_C, [1] = sum log D
   Buf<int> info;
   // PCG / SLQ
@@ -247,6 +248,10 @@ static fsa_status build_values(fsa_ctx* c) {
   FSA_TRY(blas_acquire(c->blas));
   FSA_TRY(blas_tri_inverse(c->blas, st, c->Lm.p, c->Lminv.p, mp));
   FSA_TRY(whiten(c->blas, c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->Lm.p, c->A.p, st));
+  // MIXED_BF16A: the model takes the bfloat16-rounded factor from here on
+  // (residual values, D_s, capacitance, probes, gradient and prediction), so
+  // the PCG operator read in bfloat16 is the float64 operator of that model
+  if (c->opt.precision == FSA_MIXED_BF16A) FSA_TRY(to_bf16(c->A.p, c->Abf.p, c->A.p, c->n * (int64_t)mp, st));
   FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, true, false,
                           c->vals.p, c->D.p, st));
   FSA_TRY(reciprocal(c->D.p, c->Dinv.p, c->n, st));
@@ -278,10 +283,8 @@ static fsa_status build_values(fsa_ctx* c) {
     return FSA_ERR_NOT_SPD;
   }
   c->last_logdet_P = ld2[0] + ld2[1];
-  if (c->opt.precision == FSA_MIXED_FP32) {
-    FSA_TRY(to_float(c->A.p, c->Af.p, c->n * (int64_t)mp, st));
-    FSA_TRY(to_float(c->vals.p, c->valsf.p, c->csr.nnz, st));
-  }
+  if (c->opt.precision == FSA_MIXED_FP32) FSA_TRY(to_float(c->A.p, c->Af.p, c->n * (int64_t)mp, st));
+  if (c->opt.precision != FSA_FP64) FSA_TRY(to_float(c->vals.p, c->valsf.p, c->csr.nnz, st));
   c->solved = false;
   return FSA_OK;
 }
@@ -322,10 +325,9 @@ static fsa_status build_core(fsa_ctx* c, const double* locs, const double* y, co
   FSA_TRY(c->D.alloc(n));
   FSA_TRY(c->Dinv.alloc(n));
   FSA_TRY(c->logdet_parts.alloc(2));
-  if (c->opt.precision == FSA_MIXED_FP32) {
-    FSA_TRY(c->Af.alloc((size_t)n * mp));
-    FSA_TRY(c->valsf.alloc(c->csr.nnz));
-  }
+  if (c->opt.precision == FSA_MIXED_FP32) FSA_TRY(c->Af.alloc((size_t)n * mp));
+  if (c->opt.precision == FSA_MIXED_BF16A) FSA_TRY(c->Abf.alloc((size_t)n * mp));
+  if (c->opt.precision != FSA_FP64) FSA_TRY(c->valsf.alloc(c->csr.nnz));
   return build_values(c);
 }
 
@@ -342,7 +344,7 @@ static fsa_status validate_build(int64_t n, int32_t d, const fsa_theta* theta, i
     if (opt->num_probes < 1 || opt->num_probes > 4096) { set_error("num_probes must be in [1, 4096]"); return FSA_ERR_INVALID_ARG; }
     if (opt->max_iter < 1 && opt->fixed_iter < 1) { set_error("max_iter must be >= 1"); return FSA_ERR_INVALID_ARG; }
     if (!(opt->cg_rel_tol >= 0)) { set_error("cg_rel_tol must be >= 0"); return FSA_ERR_INVALID_ARG; }
-    if (opt->precision != FSA_FP64 && opt->precision != FSA_MIXED_FP32) { set_error("unknown precision"); return FSA_ERR_INVALID_ARG; }
+    if (opt->precision != FSA_FP64 && opt->precision != FSA_MIXED_FP32 && opt->precision != FSA_MIXED_BF16A) { set_error("unknown precision"); return FSA_ERR_INVALID_ARG; }
     if (!(opt->sigma_m_jitter >= 0)) { set_error("sigma_m_jitter must be >= 0"); return FSA_ERR_INVALID_ARG; }
   }
   return FSA_OK;
@@ -499,7 +501,8 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
     op.A = reinterpret_cast<const T*>(c->A.p);
   } else {
     op.val = reinterpret_cast<const T*>(c->valsf.p);
-    op.A = reinterpret_cast<const T*>(c->Af.p);
+    op.A = reinterpret_cast<const T*>(c->Af.p);  // null in MIXED_BF16A
+    op.Abf = c->Abf.p;                            // null unless MIXED_BF16A
   }
   const double tol = c->opt.cg_rel_tol;
   const int fixed = c->opt.fixed_iter > 0 ? 1 : 0;
@@ -795,6 +798,7 @@ static fsa_status predict_core(fsa_ctx* c, const double* pred_locs_h, int64_t n_
   FSA_TRY(vTP.alloc(cTP.nnz));
   FSA_TRY(blas_acquire(c->blas));
   FSA_TRY(whiten(c->blas, pg.xs.p, n_p, c->ind.p, c->m, mp, c->th, c->Lm.p, Ap.p, st));
+  if (c->opt.precision == FSA_MIXED_BF16A) FSA_TRY(to_bf16(Ap.p, nullptr, Ap.p, n_p * (int64_t)mp, st));
   FSA_TRY(residual_values(pg, c->grid, cPT, Ap.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, false, false, vPT.p,
                           nullptr, st));
   FSA_TRY(residual_values(c->grid, pg, cTP, c->A.p, Ap.p, nullptr, nullptr, mp, c->th, c->gamma, false, false, vTP.p,
@@ -813,7 +817,7 @@ static fsa_status predict_core(fsa_ctx* c, const double* pred_locs_h, int64_t n_
   FSA_TRY(spmm<double>(cTP, c->grid, pg, vTP.p, Z1.p, lds, s, B.p + mp, ld, false, st));
   int its = 0;
   double t1 = now_ms();
-  fsa_status ps = c->opt.precision == FSA_MIXED_FP32 ? run_sparse_pcg<float>(c, B.p, ncols, ld, W.p, &its)
+  fsa_status ps = c->opt.precision != FSA_FP64 ? run_sparse_pcg<float>(c, B.p, ncols, ld, W.p, &its)
                                                       : run_sparse_pcg<double>(c, B.p, ncols, ld, W.p, &its);
   if (ps != FSA_OK && ps != FSA_ERR_NOT_CONVERGED) return ps;
   double t2 = now_ms();
@@ -906,7 +910,7 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
                       c->Emat.p, st));
   double ms_pcg = 0;
   fsa_status s;
-  if (c->opt.precision == FSA_MIXED_FP32) s = run_pcg<float>(c, &ms_pcg);
+  if (c->opt.precision != FSA_FP64) s = run_pcg<float>(c, &ms_pcg);
   else s = run_pcg<double>(c, &ms_pcg);
   if (s != FSA_OK && s != FSA_ERR_NOT_CONVERGED) {
     *nll = INFINITY;

@@ -150,6 +150,22 @@ __device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned o
   if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, off, 0, 0);
   else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
+// The low-rank factor A is float32 or bfloat16 (stored as its upper 16 bits;
+// widened to float32 exactly by a shift).
+typedef uint16_t bf16_t;
+__device__ __forceinline__ float bf16_lo(unsigned x) { return __uint_as_float(x << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned x) { return __uint_as_float(x & 0xffff0000u); }
+// four consecutive A entries at byte offset off
+template <typename TA>
+__device__ __forceinline__ f4 load_a4(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(TA) == 4) {
+    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  } else {
+    const u2v x = __builtin_bit_cast(u2v, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    return f4{bf16_lo(x[0]), bf16_hi(x[0]), bf16_lo(x[1]), bf16_hi(x[1])};
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ V4<T> bload4(__amdgpu_buffer_rsrc_t r, unsigned off) {
   V4<T> o;
@@ -190,8 +206,8 @@ struct F32RowsEpi {
 // are issued before the matrix cores take the current step, and the
 // epilogue reads and writes through buffer resources too, so no divergent
 // branch in the loop forces the memory pipeline to drain.
-template <bool DOT, int EM>
-__global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim, const float* __restrict__ A,
+template <typename TA, bool DOT, int EM>
+__global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim, const TA* __restrict__ A,
                                                         int64_t lda, const float* __restrict__ G, int ldg, int ncols,
                                                         F32RowsEpi epi, double* __restrict__ dot_part, int ld_dot) {
   extern __shared__ __attribute__((aligned(16))) float gres[];
@@ -212,7 +228,8 @@ __global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim,
   const int64_t ntile = (nrows + 15) / 16;
   const int64_t gw = (int64_t)blockIdx.x * 16 + w, GW = (int64_t)gridDim.x * 16;
   const int64_t ntw = gw < ntile ? (ntile - gw + GW - 1) / GW : 0;  // tiles of this wave
-  const unsigned lane_off = (unsigned)(r16 * lda + 16 * q) * 4u;
+  constexpr unsigned EB = sizeof(TA);
+  const unsigned lane_off = (unsigned)(r16 * lda + 16 * q) * EB;
   double dsum[4] = {0, 0, 0, 0};
   // load cursor: tile ordinal lj, k block lkb
   int64_t lj = 0;
@@ -220,10 +237,10 @@ __global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim,
   auto load_next = [&](f4* ab) {
     const int64_t row0 = (gw + lj * GW) * 16;
     const int64_t nr = lj < ntw ? min((int64_t)16, nrows - row0) : 0;
-    const __amdgpu_buffer_rsrc_t rs = rsrc_of(A + (lj < ntw ? row0 * lda : 0), nr * lda * 4);
-    const unsigned o = lane_off + (unsigned)lkb * 256u;
+    const __amdgpu_buffer_rsrc_t rs = rsrc_of(A + (lj < ntw ? row0 * lda : 0), nr * lda * EB);
+    const unsigned o = lane_off + (unsigned)lkb * 64u * EB;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) ab[t] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u * t, 0, 0));
+    for (int t = 0; t < 4; ++t) ab[t] = load_a4<TA>(rs, o + 4u * EB * t);
     if (++lkb == nkb) {
       lkb = 0;
       ++lj;
@@ -238,12 +255,12 @@ __global__ __launch_bounds__(1024) void k_rows_gemm_f32(int64_t nrows, int kdim,
   auto epilogue = [&]() {
     const int64_t row0 = (gw + cj * GW) * 16;
     const int64_t nr = min((int64_t)16, nrows - row0);
-    const __amdgpu_buffer_rsrc_t ry = rsrc_of(epi.Y ? epi.Y + row0 * epi.ld : (float*)A, epi.Y ? nr * epi.ld * 4 : 0);
-    const __amdgpu_buffer_rsrc_t rr = rsrc_of(epi.R ? epi.R + row0 * epi.ld : A, epi.R ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t ry = rsrc_of(epi.Y ? epi.Y + row0 * epi.ld : (const void*)A, epi.Y ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rr = rsrc_of(epi.R ? epi.R + row0 * epi.ld : (const void*)A, epi.R ? nr * epi.ld * 4 : 0);
     const __amdgpu_buffer_rsrc_t rd = rsrc_of(epi.Dinv ? epi.Dinv + row0 : (const double*)A, epi.Dinv ? nr * 8 : 0);
-    const __amdgpu_buffer_rsrc_t rh = rsrc_of(EM == ROWS_PCG_INIT ? epi.H + row0 * epi.ld : A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
-    const __amdgpu_buffer_rsrc_t rp = rsrc_of(EM == ROWS_PCG_INIT ? epi.P + row0 * epi.ld : A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
-    const __amdgpu_buffer_rsrc_t rq = rsrc_of(EM == ROWS_PCG_INIT ? epi.Q0 + row0 * epi.ld : A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rh = rsrc_of(EM == ROWS_PCG_INIT ? epi.H + row0 * epi.ld : (const void*)A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rp = rsrc_of(EM == ROWS_PCG_INIT ? epi.P + row0 * epi.ld : (const void*)A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rq = rsrc_of(EM == ROWS_PCG_INIT ? epi.Q0 + row0 * epi.ld : (const void*)A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
     float xin[4][4];
     double di[4];
 #pragma unroll
@@ -520,9 +537,9 @@ struct F32Pro {
 // fill and dropped stores past the last point or column), so no branch
 // forces the memory pipeline to drain.  Partials are row-major:
 // part[((chunk * ncb + cb) * kdim + k) * 64 + c - 64 cb].
-template <bool UPD, int SC>
+template <typename TA, bool UPD, int SC>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_reduce_gemm_f32(
-    int64_t npts, int pts_per_chunk, int kdim, int ncols, const float* __restrict__ A, F32Pro pro,
+    int64_t npts, int pts_per_chunk, int kdim, int ncols, const TA* __restrict__ A, F32Pro pro,
     float* __restrict__ part, double* __restrict__ dot_part, int ld_dot) {
   constexpr int SP = 24;        // points per step
   constexpr int NA = SP / 4;    // A loads per lane per step
@@ -553,22 +570,22 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
   double dacc = 0.0;
   f4 ab0[NA] = {}, ab1[NA] = {}, ab2[NA] = {};
-  const __amdgpu_buffer_rsrc_t arsrc = rsrc_of(A + pbeg * kdim, (int64_t)np * kdim * 4);
+  constexpr unsigned EB = sizeof(TA);
+  const __amdgpu_buffer_rsrc_t arsrc = rsrc_of(A + pbeg * kdim, (int64_t)np * kdim * EB);
   const __amdgpu_buffer_rsrc_t srsrc = rsrc_of(pro.S + pbeg * pro.ld, (int64_t)np * pro.ld * 4);
   const __amdgpu_buffer_rsrc_t vrsrc = rsrc_of(UPD ? pro.V + pbeg * pro.ld : pro.S, UPD ? (int64_t)np * pro.ld * 4 : 0);
   const __amdgpu_buffer_rsrc_t drsrc = rsrc_of(SC ? pro.sc + pbeg : (const double*)pro.S, SC ? (int64_t)np * 8 : 0);
   const double a_c = (UPD && cval) ? pro.alpha[c] : 0.0;
   // byte offsets into the chunk (unsigned: BUF_OOR plus an offset stays out of range)
-  const unsigned a_off = mactive ? (unsigned)(q * kdim + kb + 4 * r16) * 4u : (unsigned)BUF_OOR;
+  const unsigned a_off = mactive ? (unsigned)(q * kdim + kb + 4 * r16) * EB : (unsigned)BUF_OOR;
   const unsigned s_off = cval ? (unsigned)(tp * (int)pro.ld + c) * 4u : (unsigned)BUF_OOR;  // element (tp, c)
   const unsigned s_step = 8u * (unsigned)pro.ld * 4u;                                       // + 8 points
   float sv[NP], vv[NP];
   double dv[NP];
   auto load_a = [&](int s, f4* ab) {
-    const unsigned so = a_off + (unsigned)(s * SP * kdim) * 4u;
+    const unsigned so = a_off + (unsigned)(s * SP * kdim) * EB;
 #pragma unroll
-    for (int k = 0; k < NA; ++k)
-      ab[k] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(arsrc, so + 16u * k * kdim, 0, 0));
+    for (int k = 0; k < NA; ++k) ab[k] = load_a4<TA>(arsrc, so + 4u * EB * k * kdim);
   };
   auto pro_load = [&](int s) {
 #pragma unroll

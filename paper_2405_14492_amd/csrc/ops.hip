@@ -255,7 +255,8 @@ static fsa_status ensure_part(Scratch& s, const ReduceShape& r) {
 // single workgroup along z, which kdim <= 512 guarantees.
 template <typename T, bool DOT, class Pro>
 static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int ncols, const T* A, const Pro& pro,
-                                T* part, double* dot_part, int ld_dot, hipStream_t st, int lower_only = 0) {
+                                T* part, double* dot_part, int ld_dot, hipStream_t st, int lower_only = 0,
+                                const uint16_t* Abf = nullptr) {
   if (DOT && r.zb != 1) {
     set_error("reduce GEMM with a dot prologue needs kdim <= 512 (got %d)", kdim);
     return FSA_ERR_INVALID_ARG;
@@ -278,12 +279,12 @@ static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int n
     }
     dim3 grid(r.ncb, r.nchunks, (kdim + 511) / 512);
     F32Pro fp = pro.f32();
-    if constexpr (Pro::kUpd) {
-      hipLaunchKernelGGL((k_reduce_gemm_f32<true, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim, ncols, A, fp,
-                         part, dot_part, ld_dot);
+    if (Abf) {
+      hipLaunchKernelGGL((k_reduce_gemm_f32<bf16_t, Pro::kUpd, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim,
+                         ncols, Abf, fp, part, dot_part, ld_dot);
     } else {
-      hipLaunchKernelGGL((k_reduce_gemm_f32<false, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim, ncols, A, fp,
-                         part, dot_part, ld_dot);
+      hipLaunchKernelGGL((k_reduce_gemm_f32<float, Pro::kUpd, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim,
+                         ncols, (const float*)A, fp, part, dot_part, ld_dot);
     }
   } else {
     static_assert(std::is_same<T, float>::value || std::is_same<T, double>::value, "float32 or float64 only");
@@ -381,7 +382,7 @@ fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T*
   if constexpr (sizeof(T) == 4) {
     if (!A2 && kdim <= 512) {
       F32RowsEpi fe{(float*)OUT, nullptr, nullptr, nullptr, nullptr, nullptr, ldo};
-      hipLaunchKernelGGL((k_rows_gemm_f32<false, ROWS_STORE>), dim3(f32_rows_grid(), ceil_div(ncols, 64)),
+      hipLaunchKernelGGL((k_rows_gemm_f32<float, false, ROWS_STORE>), dim3(f32_rows_grid(), ceil_div(ncols, 64)),
                          dim3(1024), (size_t)kdim * 64 * sizeof(float), st, n, kdim, (const float*)A, (int64_t)kdim,
                          (const float*)G, ldg, ncols, fe, (double*)nullptr, 0);
       FSA_HIP(hipGetLastError());
@@ -805,14 +806,25 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
     KT_BEGIN(b);
     F32RowsEpi fe{init ? nullptr : (float*)b.Tt, (const float*)b.R, op.Dinv, (float*)b.H, (float*)b.P, (float*)b.Q0,
                   (int64_t)b.ld};
-    if (init)
-      hipLaunchKernelGGL((k_rows_gemm_f32<true, ROWS_PCG_INIT>), dim3(gx, ncb), dim3(1024),
-                         (size_t)op.kdim * 64 * sizeof(float), st, b.n, op.kdim, (const float*)op.A, (int64_t)op.kdim,
-                         (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
-    else
-      hipLaunchKernelGGL((k_rows_gemm_f32<true, ROWS_PCG>), dim3(gx, ncb), dim3(1024),
-                         (size_t)op.kdim * 64 * sizeof(float), st, b.n, op.kdim, (const float*)op.A, (int64_t)op.kdim,
-                         (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
+    const size_t smem = (size_t)op.kdim * 64 * sizeof(float);
+    dim3 grid2(gx, ncb);
+    if (op.Abf) {
+      if (init)
+        hipLaunchKernelGGL((k_rows_gemm_f32<bf16_t, true, ROWS_PCG_INIT>), grid2, dim3(1024), smem, st, b.n, op.kdim,
+                           op.Abf, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
+      else
+        hipLaunchKernelGGL((k_rows_gemm_f32<bf16_t, true, ROWS_PCG>), grid2, dim3(1024), smem, st, b.n, op.kdim,
+                           op.Abf, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
+    } else {
+      if (init)
+        hipLaunchKernelGGL((k_rows_gemm_f32<float, true, ROWS_PCG_INIT>), grid2, dim3(1024), smem, st, b.n, op.kdim,
+                           (const float*)op.A, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p,
+                           ncb * 64);
+      else
+        hipLaunchKernelGGL((k_rows_gemm_f32<float, true, ROWS_PCG>), grid2, dim3(1024), smem, st, b.n, op.kdim,
+                           (const float*)op.A, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p,
+                           ncb * 64);
+    }
     KT_END(b, KT_PASS2);
   } else {
     gx = f32_rows_grid();
@@ -846,7 +858,7 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
     ReduceShape r = reduce_shape(b.n, op.kdim, b.ncols);
     FSA_TRY(ensure_part<T>(s, r));
     MulDinvPro<T> pro{b.R, b.ld, op.Dinv};
-    FSA_TRY((launch_reduce<T, false>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, nullptr, 0, st)));
+    FSA_TRY((launch_reduce<T, false>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, nullptr, 0, st, 0, op.Abf)));
     FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
     FSA_TRY(pcg_precond_and_dots<T>(b, op, 1, s, nparts_rq, st));
     // |b|^2 partials
@@ -908,7 +920,8 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     PcgPass1Pro<T> pro{b.R, b.V, op.Dinv, b.alpha, b.ld};
     {
       KT_BEGIN(b);
-      FSA_TRY((launch_reduce<T, true>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, s.dot2.p, ldd, st)));
+      FSA_TRY((launch_reduce<T, true>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, s.dot2.p, ldd, st, 0,
+                                      op.Abf)));
       KT_END(b, KT_PASS1);
     }
     nparts_rr = r.nchunks;

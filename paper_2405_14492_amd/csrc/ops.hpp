@@ -145,6 +145,7 @@ struct OpDesc {
   const double* D = nullptr;
   const double* Dinv = nullptr;  // 1 / D
   const T* A = nullptr;
+  const uint16_t* Abf = nullptr;  // float32 operator only: A in bfloat16 for the PCG passes (else null)
   int kdim = 0;
   const double* Cinv = nullptr;
 };
@@ -176,6 +177,11 @@ fsa_status pred_combine(int64_t np, int mp, const double* Ap, const double* Y, c
 fsa_status pred_mean(int64_t np, int mp, const double* Ap, const double* w, const double* su, const int* perm,
                      double* out, hipStream_t st);
 fsa_status symmetrize(double* A, int n, hipStream_t st);
+
+// bfloat16 (round to nearest even, through float32) of a float64 array: the
+// bits to out and/or the rounded value to rounded (either may be null;
+// rounded may alias in)
+fsa_status to_bf16(const double* in, uint16_t* out, double* rounded, int64_t cnt, hipStream_t st);
 
 // elementwise helpers
 template <typename TI, typename TO>

@@ -19,6 +19,7 @@ EXPONENTIAL = 0
 MATERN32 = 1
 FP64 = 0
 MIXED_FP32 = 1
+MIXED_BF16A = 2
 
 OP_SIGMA_DAGGER, OP_SIGMA_S, OP_P_INV, OP_D_SIGMA1, OP_D_RHO, OP_PROBES = range(6)
 

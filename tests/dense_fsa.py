@@ -16,12 +16,14 @@ from scipy.spatial.distance import cdist
 from oracle import fsa_oracle as O
 
 
-def dense_parts(locs, inducing, theta, gamma, jitter=0.0):
+def dense_parts(locs, inducing, theta, gamma, jitter=0.0, Smn=None):
+    """Smn (m x n) replaces the cross covariance when given."""
     kind, s1, rho, s2 = theta
     n = locs.shape[0]
     Sig = O.covariance(cdist(locs, locs), s1, rho, kind)
     Sm = O.covariance(cdist(inducing, inducing), s1, rho, kind) + jitter * s1 * np.eye(inducing.shape[0])
-    Smn = O.covariance(cdist(inducing, locs), s1, rho, kind)
+    if Smn is None:
+        Smn = O.covariance(cdist(inducing, locs), s1, rho, kind)
     Sl = Smn.T @ np.linalg.solve(Sm, Smn)
     T = O.wendland_taper(cdist(locs, locs), gamma)
     Ss = (Sig - Sl) * T + s2 * np.eye(n)
@@ -66,3 +68,38 @@ def dense_pred_var(locs, inducing, pred, theta, gamma):
     cross = Sl_np + (Snp - Sl_np) * Tnp
     S = dense_fsa(locs, inducing, theta, gamma)
     return s1 + s2 - np.einsum("ij,ij->j", cross, np.linalg.solve(S, cross)), cross, S
+
+
+def bf16_round(x):
+    """float64 -> float32 (nearest) -> bfloat16 (nearest, ties to even),
+    returned as float64: the rounding of the MIXED_BF16A factor."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    h = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint32)
+    return (h << 16).view(np.float32).astype(np.float64)
+
+
+def bf16_cross_covariance(locs, inducing, theta, pred=None):
+    """Sigma_mn^T (n x m) of the model whose whitened factor
+    A = L_m^{-1} Sigma_mn is rounded to bfloat16: L_m A~ with A~ rounded, so
+    Sigma_mn^T Sigma_m^{-1} Sigma_mn = A~^T A~.  With pred, the same for the
+    prediction locations."""
+    import scipy.linalg as sla
+    kind, s1, rho, s2 = theta
+    Sm = O.covariance(cdist(inducing, inducing), s1, rho, kind)
+    L = np.linalg.cholesky(Sm)
+    pts = locs if pred is None else pred
+    Smn = O.covariance(cdist(inducing, pts), s1, rho, kind)
+    A = sla.solve_triangular(L, Smn, lower=True)
+    return np.ascontiguousarray((L @ bf16_round(A)).T)
+
+
+class RoundedFSA(O.FSA):
+    """The oracle's FSA on a supplied cross covariance, differentiated in
+    sigma1^2 as a model proportional to sigma1^2 (the unrounded FSA is, with
+    no jitter): dSigma~/dsigma1^2 = (Sigma~ - sigma^2 I) / sigma1^2.  The
+    rho-derivative is the oracle's (exact dSigma_mn, dSigma_m)."""
+
+    def dmatvec(self, which, X):
+        if which == 0:
+            return (self.matvec(X) - self.theta[3] * X) / self.theta[1]
+        return super().dmatvec(which, X)

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import fsa_oracle as O
+from tests import dense_fsa as DF
 from workloads import configs
 from workloads import generators as G
 
@@ -202,3 +203,67 @@ def test_predictive_variances_mixed_precision(F):
     err = np.abs(var - ref_var) / np.abs(ref_var)
     say("mixed var rel err max", err.max())
     assert err.max() < 1e-4
+
+
+@pytest.mark.parametrize("name", ["exp_n700_m40", "m32_n1500_m100", "ragged_n333_m7"])
+def test_bf16a_matches_oracle_of_rounded_model(F, name):
+    """MIXED_BF16A is MIXED_FP32 on the model whose whitened factor is
+    rounded to bfloat16: against the float64 oracle of that model (converged
+    to 1e-10, same probes) the bar is the mixed-precision one, NLL within
+    1e-4 relative and each gradient component within 1e-4 of its scale.  The
+    deviation from the unrounded model is printed beside it.  The sigma1^2
+    derivative is that of the rounded model scaled with sigma1^2."""
+    say("case", name)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    mdl = DF.RoundedFSA(locs, ind, theta, gamma, smn_T=DF.bf16_cross_covariance(locs, ind, theta))
+    ref = O.nll_grad(mdl, y, 8, 5, tol=1e-10, max_iter=3000)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=8, seed=5, tol=1e-6, max_iter=3000,
+               precision=F.MIXED_BF16A, rr_period=10) as f:
+        nll, grad, st = f.nll_grad()
+    exact = O.nll_grad(O.FSA(locs, ind, theta, gamma), y, 8, 5, tol=1e-10, max_iter=3000)
+    gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
+    say("bf16a nll", nll, "rounded-model oracle", ref["nll"], "rel", abs(nll - ref["nll"]) / abs(ref["nll"]),
+        "grad err / scale", np.abs(grad - ref["grad"]) / gscale, "iters", st["iters_max"])
+    say("rounding of A moves the nll by", abs(ref["nll"] - exact["nll"]) / abs(exact["nll"]),
+        "and the gradient by", np.abs(ref["grad"] - exact["grad"]) / gscale, "of its scale")
+    assert abs(nll - ref["nll"]) <= 1e-4 * abs(ref["nll"])
+    assert np.all(np.abs(grad - ref["grad"]) <= 1e-4 * gscale), (grad, ref["grad"])
+    assert 0.0 < st["rel_res_max"] < 1e-6
+
+
+def test_bf16a_predictive_variances_match_oracle_of_rounded_model(F):
+    locs, y, theta, ind, gamma = case(**CASES["m32_n1500_m100"])
+    pred = G.uniform_locations(300, 901)
+    mdl = O.FSA(locs, ind, theta, gamma, smn_T=DF.bf16_cross_covariance(locs, ind, theta))
+    ref_var, _ = O.predict_var(mdl, pred, 16, 22, tol=1e-12, max_iter=3000,
+                               smp_T=DF.bf16_cross_covariance(locs, ind, theta, pred=pred))
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=2, seed=22, tol=1e-7, max_iter=3000,
+               precision=F.MIXED_BF16A) as f:
+        var, _, _ = f.predict_var(pred, 16)
+    err = np.abs(var - ref_var) / np.abs(ref_var)
+    say("bf16a var rel err max", err.max())
+    assert err.max() < 1e-4
+
+
+def test_bf16a_rejects_rounded_model_with_negative_residual_diagonal(F):
+    """Clustered points with inducing points among them and a small nugget
+    (sigma^2 = 0.01, sigma1^2 = 2): at an inducing point the unrounded
+    residual diagonal is the nugget alone, and the bfloat16 rounding of A
+    moves ||A_i||^2 by more than that, so the rounded model is not positive
+    definite.  The build must refuse it rather than run PCG on it."""
+    locs, y, theta, ind, gamma = case(**CASES["exp_clustered_n2000_m70"])
+    mdl_T = DF.bf16_cross_covariance(locs, ind, theta)
+    kind, s1, rho, s2 = theta
+    import scipy.linalg as sla
+    from scipy.spatial.distance import cdist
+    Sm = O.covariance(cdist(ind, ind), s1, rho, kind)
+    Ar = sla.solve_triangular(np.linalg.cholesky(Sm), mdl_T.T, lower=True)  # = A~
+    dmin = (s1 + s2 - (Ar * Ar).sum(0)).min()
+    say("rounded residual diagonal min", dmin)
+    assert dmin < -1e-4
+    with pytest.raises(F.FsaError, match="NOT_SPD"):
+        with F.FSA(locs, y, theta, ind, gamma, num_probes=4, seed=5, precision=F.MIXED_BF16A) as f:
+            f.nll_grad()
+    # float32 mixed precision keeps the unrounded model and runs
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=4, seed=5, tol=1e-6, precision=F.MIXED_FP32) as f:
+        f.nll_grad()

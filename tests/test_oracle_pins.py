@@ -120,6 +120,51 @@ def test_operator_equals_dense_definition():
     np.testing.assert_allclose(mdl.matvec(X), ref, rtol=1e-10, atol=1e-10)
 
 
+def test_supplied_cross_covariance_equals_dense_definition():
+    """FSA with a rounded low-rank part (whitened factor in bfloat16): the
+    operator, FITC solve and log det P follow the dense definitions built on
+    the same Sigma_mn; the diagonal stays sigma1^2 + sigma^2 because the
+    residual absorbs the low-rank part on it; the rho-derivative keeps the
+    exact dSigma_mn (dense: dSmn^T K + K^T dSmn - K^T dSm K with K = Sm^{-1} Smn,
+    then tapered); bf16_round is exact on bfloat16 values and moves others by
+    at most half a bfloat16 unit."""
+    from scipy.spatial.distance import cdist
+    locs, ind, theta, gamma = small_case(kind=M32, rho=0.08)
+    kind, s1, rho, s2 = theta
+    n = locs.shape[0]
+    smn_T = DF.bf16_cross_covariance(locs, ind, theta)
+    exact_T = O.covariance(cdist(locs, ind), s1, rho, kind)
+    assert 0 < np.abs(smn_T - exact_T).max() < 1e-2
+    mdl = O.FSA(locs, ind, theta, gamma, smn_T=smn_T)
+    p = DF.dense_parts(locs, ind, theta, gamma, Smn=smn_T.T)
+    X = np.random.default_rng(0).standard_normal((n, 3))
+    np.testing.assert_allclose(mdl.matvec(X), p["full"] @ X, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(np.diag(p["full"]), s1 + s2, rtol=1e-12)
+    P = np.diag(np.diag(p["Ss"])) + p["Sl"]
+    np.testing.assert_allclose(mdl.precond_solve(X), np.linalg.solve(P, X), rtol=1e-9, atol=1e-9)
+    assert abs(mdl.logdet_P - np.linalg.slogdet(P)[1]) < 1e-9 * abs(np.linalg.slogdet(P)[1])
+    K = np.linalg.solve(p["Sm"], smn_T.T)
+    dSm = O.covariance_drho(cdist(ind, ind), s1, rho, kind)
+    dSmn = O.covariance_drho(cdist(ind, locs), s1, rho, kind)
+    dSl = dSmn.T @ K + K.T @ dSmn - K.T @ dSm @ K
+    dS = (O.covariance_drho(cdist(locs, locs), s1, rho, kind) - dSl) * p["T"] + dSl
+    np.testing.assert_allclose(mdl.dmatvec(1, X), dS @ X, rtol=1e-9, atol=1e-9 * np.abs(dS @ X).max())
+    # the sigma1^2 derivative of the rounded model by proportionality is the
+    # oracle's exact one on the unrounded model
+    plain = O.FSA(locs, ind, theta, gamma)
+    np.testing.assert_allclose(plain.dmatvec(0, X), (plain.matvec(X) - s2 * X) / s1, rtol=1e-9,
+                               atol=1e-9 * np.abs(X).max())
+    rnd = DF.RoundedFSA(locs, ind, theta, gamma, smn_T=smn_T)
+    np.testing.assert_allclose(rnd.dmatvec(0, X), (p["full"] @ X - s2 * X) / s1, rtol=1e-9, atol=1e-9)
+    v = np.array([1.0, -2.5, 3.0e-3, 0.1, 1.0078125])
+    r = DF.bf16_round(v)
+    np.testing.assert_array_equal(r[[0, 1, 4]], v[[0, 1, 4]])
+    assert np.all(np.abs(r - v) <= np.abs(v) * 2.0 ** -8)
+    # a tie rounds to the even neighbour: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7
+    assert DF.bf16_round(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
+    assert DF.bf16_round(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+
+
 def test_inducing_equal_to_locations_gives_exact_gp():
     """S* = S makes Sigma_l = Sigma, so Sigma~_dagger = Sigma + sigma^2 I and
     the FITC preconditioner is exact too."""
