@@ -105,9 +105,9 @@ def measured_traffic(kernel_name):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
-def run_mode(F, dev, w, precision, steps, warmup, tol, torch):
+def run_mode(F, dev, w, precision, steps, warmup, tol, torch, rr_period=20):
     opt = F.make_options(num_probes=w.num_probes, seed=w.seed, tol=tol, max_iter=1000, precision=precision,
-                         rr_period=10, profile=True)
+                         rr_period=rr_period, profile=True)
     theta = w.theta
 
     def step():
@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--probes", type=int, default=50)
     ap.add_argument("--modes", default="fp64,mixed",
                     help="comma list of fp64, mixed (float32 operator), bf16a (float32 operator, bfloat16 A)")
+    ap.add_argument("--rr-period", type=int, default=20,
+                    help="mixed modes: float64 residual replacement every this many iterations (0 = never)")
     ap.add_argument("--cpu-sample-n", type=int, default=80_000)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -250,7 +252,7 @@ def main():
         prec = {"mixed": F.MIXED_FP32, "bf16a": F.MIXED_BF16A, "fp64": F.FP64}[mode]
         tol = 1e-8 if mode == "fp64" else 1e-6
         log(f"mode {mode}: warmup {args.warmup}, steps {args.steps}")
-        results[mode] = run_mode(F, dev, w, prec, args.steps, args.warmup, tol, torch)
+        results[mode] = run_mode(F, dev, w, prec, args.steps, args.warmup, tol, torch, args.rr_period)
         log(f"mode {mode}: {results[mode]['value']:.1f} probe-iters/s, {results[mode]['ms_per_step']:.2f} ms/step, "
             f"iters {results[mode]['iters']}, kernel ms/launch "
             f"{[round(a / max(b, 1), 4) for a, b in zip(results[mode]['kernel_ms'], results[mode]['kernel_launches'])]}")
@@ -273,7 +275,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"fsa_nll_grad n={args.n} m={args.m} t={args.probes} matern32 "
                                f"rho=0.05 sigma2=0.1 n_gamma=80 tol={'1e-8' if main_mode == 'fp64' else '1e-6'}",
-                   "n": args.n, "m": args.m, "t": args.probes, "gamma": w.gamma, "nnz": r["nnz"]},
+                   "n": args.n, "m": args.m, "t": args.probes, "gamma": w.gamma, "nnz": r["nnz"],
+                   "rr_period": args.rr_period},
         "roofline": roofline(r, args.n, args.m, args.probes + 1, rkey),
         "pcg_only_probe_iters_per_s": r["pcg_only_probe_iters_per_s"],
         "modes": results,

@@ -95,11 +95,14 @@ def test_c2_operator_and_probe_rows(F, c2, c2_rows, sample):
 def test_c2_mixed_precision_matches_float64(F, c2):
     """The bench configuration: float64 to 1e-8 and mixed precision to 1e-6
     with the same probes; NLL within 1e-4 relative and each gradient
-    component within 1e-4 of its scale; residuals below tolerance."""
+    component within 1e-4 of its scale; residuals below tolerance.  BF16-A
+    solves the model with A rounded to bfloat16, so it is held to what that
+    rounding moves (measured: NLL 1.9e-4 relative, gradient components up to
+    4e-3 relative): 1e-3 and 1e-2 of the scale."""
     res = {}
-    for prec, tol in ((F.FP64, 1e-8), (F.MIXED_FP32, 1e-6)):
+    for prec, tol in ((F.FP64, 1e-8), (F.MIXED_FP32, 1e-6), (F.MIXED_BF16A, 1e-6)):
         with F.FSA(c2.locs, c2.y, c2.theta, c2.inducing, c2.gamma, num_probes=c2.num_probes, seed=c2.seed,
-                   tol=tol, precision=prec, rr_period=10) as f:
+                   tol=tol, precision=prec, rr_period=20) as f:
             nll, grad, st = f.nll_grad()
         say("precision", prec, "nll", nll, "grad", grad, "iters", st["iters_min"], st["iters_max"],
             "rel_res_max", st["rel_res_max"])
@@ -110,6 +113,10 @@ def test_c2_mixed_precision_matches_float64(F, c2):
     assert abs(nllm - nll64) <= 1e-4 * abs(nll64)
     scale = np.maximum(np.abs(g64), 0.5 * np.abs(np.asarray(st64["grad_trace"])))
     assert np.all(np.abs(gm - g64) <= 1e-4 * scale), (gm, g64)
+    nllb, gb, _ = res[F.MIXED_BF16A]
+    say("bf16a vs float64: nll rel", abs(nllb - nll64) / abs(nll64), "grad / scale", np.abs(gb - g64) / scale)
+    assert abs(nllb - nll64) <= 1e-3 * abs(nll64)
+    assert np.all(np.abs(gb - g64) <= 1e-2 * scale), (gb, g64)
 
 
 def test_c4_predictive_variances_mixed_matches_float64():
