@@ -42,11 +42,11 @@ def log(*a):
 # rocprofv3 kernel names of the four PCG kernel classes, per element type
 KERNEL_NAMES = {
     "f32": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<float, true, 1>", "k_rows_gemm_f32<float, true, 2>",
-            "k_pcg_hupdate<float>"],
+            "k_pcg_hupdate<float, float>"],
     "bf16a": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<unsigned short, true, 1>",
-              "k_rows_gemm_f32<unsigned short, true, 2>", "k_pcg_hupdate<float>"],
+              "k_rows_gemm_f32<unsigned short, true, 2>", "k_pcg_hupdate<float, float>"],
     "f64": ["k_spmm_dense<double, 2>", "k_reduce_gemm_f64<true, 1>",
-            "k_rows_gemm_f64<true, 2, 3>", "k_pcg_hupdate<double>"],
+            "k_rows_gemm_f64<true, 2, 3>", "k_pcg_hupdate<double, double>"],
 }
 COUNTERS = os.path.join(ROOT, "profiles", "pcg_kernels_n500k_m500_t50_counters.md")
 
@@ -54,8 +54,9 @@ COUNTERS = os.path.join(ROOT, "profiles", "pcg_kernels_n500k_m500_t50_counters.m
 def kernel_work(k, n, m, tp, nnz, b, ba=None):
     """Algorithmic (bytes, flops) per launch of kernel class k with element
     size b (block vectors and sparse values) and ba (low-rank factor, b if
-    None); the solution accumulator U is float64 in every mode.  Every
-    operand counted once."""
+    None); the solution accumulates in float64 (float64 operator) or as
+    float32 increments folded into float64 at each residual replacement.
+    Every operand counted once."""
     blk = n * tp
     ba = b if ba is None else ba
     if k == 0:   # V = S H + P, h.v: key (4 B) + value per nonzero, H in, P in, V out, row pointers
@@ -64,8 +65,9 @@ def kernel_work(k, n, m, tp, nnz, b, ba=None):
         return n * m * ba + 3 * blk * b + 8 * n, 2.0 * n * m * tp
     if k == 2:   # t = A g, r.q with q = (r - t)/D: A once, R in, T out, D^-1
         return n * m * ba + 2 * blk * b + 8 * n, 2.0 * n * m * tp
-    if k == 3:   # u += a h (U in/out f64), h = (r - t)/D + beta h, p = t + beta p: R, T, H, P in; H, P out
-        return blk * (6 * b + 16) + 8 * n, 6.0 * blk
+    if k == 3:   # u += a h (U in/out: float64, or the float32 increment block with a float32 operator),
+        #          h = (r - t)/D + beta h, p = t + beta p: R, T, H, P in; H, P out
+        return blk * (6 * b + (8 if b == 4 else 16)) + 8 * n, 6.0 * blk
     return 0, 0
 
 

@@ -191,6 +191,16 @@ int64_t fsa_nnz(const fsa_ctx* ctx);
 fsa_status fsa_export_csr(fsa_ctx* ctx, int64_t* row_ptr, int32_t* col_idx, double* vals);
 /* D_s (host, n) and log det P. */
 fsa_status fsa_export_diag(fsa_ctx* ctx, double* D, double* logdet_P);
+/* Lanczos record of the last likelihood solve (Algorithm 2), for the t + 1
+ * right-hand-side columns (0 = y, 1..t = probes), all host buffers, any may
+ * be NULL: iters[t+1] iterations per column; alpha and beta
+ * [L x (t+1)], row-major by iteration, the CG coefficients of each
+ * iteration (entries past a column's count undefined), with L = fixed_iter
+ * if set, else max_iter; weight[t+1] the quadrature weights and slq[t+1]
+ * the terms weight_c e_1^T log(T_c) e_1 of Section 3.1 (column 0: 0).
+ * FSA_ERR_INVALID_ARG before the first solve. */
+fsa_status fsa_export_lanczos(fsa_ctx* ctx, int32_t* iters, double* alpha, double* beta, double* weight,
+                              double* slq);
 
 enum {
   FSA_OP_SIGMA_DAGGER = 0, /* Sigma~_dagger X */

@@ -200,6 +200,7 @@ struct fsa_ctx {
   Buf<int> colint;
   Buf<double> hist;
   Buf<double> slq_scratch, results;
+  const double* lanczos_weight = nullptr;  // quadrature weights of the last solve (in colbuf)
   // gradient
   Buf<double> F, dvals, Xb, SX, DX, tmp, dSm, Ework;
   Scratch scr;
@@ -446,7 +447,8 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   const int tp = c->tp, ld = c->ld, ldw = c->ldw, mp = c->mp;
   const int max_iter = c->opt.fixed_iter > 0 ? c->opt.fixed_iter : c->opt.max_iter;
   size_t blk = (size_t)n * ld;
-  FSA_TRY(c->blockmem.alloc(6 * blk * sizeof(T)));
+  const int nblk = sizeof(T) == 4 ? 7 : 6;
+  FSA_TRY(c->blockmem.alloc(nblk * blk * sizeof(T)));
   T* base = reinterpret_cast<T*>(c->blockmem.p);
   PcgBlock<T> b;
   b.n = n;
@@ -460,6 +462,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   b.P = base + 3 * blk;
   b.Tt = base + 4 * blk;
   b.Q0 = base + 5 * blk;
+  if constexpr (sizeof(T) == 4) b.U32 = base + 6 * blk;
   FSA_TRY(c->U.alloc(blk));
   b.U = c->U.p;
   FSA_TRY(c->colbuf.alloc(8 * (size_t)ldw));
@@ -531,6 +534,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
       }
     }
   }
+  if constexpr (sizeof(T) == 4) FSA_TRY(pcg_fold_u(reinterpret_cast<PcgBlock<float>&>(b), st));
   FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   *ms_pcg = now_ms() - t0;
@@ -572,6 +576,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
     hipLaunchKernelGGL(k_fill_weight_n, dim3(ceil_div(tp, 64)), dim3(64), 0, st, b.rr, tp, (double)n);
     weight = b.rr;
   }
+  c->lanczos_weight = weight;
   FSA_TRY(slq_terms(b.alpha_hist, b.beta_hist, b.iters, tp, 1, weight, slq, c->slq_scratch.p, max_iter, st));
   FSA_TRY((coldot<double, double>(c->B.p, c->U.p, n, ld, 1, quad, c->scr, st)));
   hipLaunchKernelGGL(k_finalize_nll, dim3(1), dim3(1), 0, st, slq, tp, c->logdet_parts.p, quad, n, fin);
@@ -683,7 +688,7 @@ static fsa_status run_sparse_pcg(fsa_ctx* c, const double* B, int ncols, int ld,
   const int ldw = (int)round_up(ncols, 64);
   size_t blk = (size_t)n * ld;
   Buf<T> mem;
-  FSA_TRY(mem.alloc(6 * blk));
+  FSA_TRY(mem.alloc((sizeof(T) == 4 ? 7 : 6) * blk));
   PcgBlock<T> b;
   b.n = n;
   b.ncols = ncols;
@@ -696,6 +701,7 @@ static fsa_status run_sparse_pcg(fsa_ctx* c, const double* B, int ncols, int ld,
   b.P = mem.p + 3 * blk;
   b.Tt = mem.p + 4 * blk;
   b.Q0 = mem.p + 5 * blk;
+  if constexpr (sizeof(T) == 4) b.U32 = mem.p + 6 * blk;
   b.U = W;
   Buf<double> colb, hist;
   Buf<int> coli;
@@ -745,6 +751,7 @@ static fsa_status run_sparse_pcg(fsa_ctx* c, const double* B, int ncols, int ld,
       if (flags[1] || flags[0] == 0) break;
     }
   }
+  if constexpr (sizeof(T) == 4) FSA_TRY(pcg_fold_u(reinterpret_cast<PcgBlock<float>&>(b), st));
   FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   std::vector<int> its(ncols);
   FSA_HIP(hipMemcpyAsync(its.data(), b.iters, ncols * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -973,6 +980,25 @@ fsa_status fsa_export_diag(fsa_ctx* c, double* D, double* logdet_P) {
     FSA_HIP(hipStreamSynchronize(c->st));
   }
   if (logdet_P) *logdet_P = c->last_logdet_P;
+  return FSA_OK;
+}
+
+fsa_status fsa_export_lanczos(fsa_ctx* c, int32_t* iters, double* alpha, double* beta, double* weight,
+                              double* slq) {
+  if (!c) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (!c->solved || !c->lanczos_weight) { set_error("no likelihood solve to export"); return FSA_ERR_INVALID_ARG; }
+  const int tp = c->tp;
+  const int L = c->opt.fixed_iter > 0 ? c->opt.fixed_iter : c->opt.max_iter;
+  hipStream_t st = c->st;
+  if (iters) FSA_HIP(hipMemcpyAsync(iters, c->colint.p + c->ldw, tp * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  if (alpha) FSA_HIP(hipMemcpyAsync(alpha, c->hist.p, (size_t)L * tp * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (beta)
+    FSA_HIP(hipMemcpyAsync(beta, c->hist.p + (size_t)L * tp, (size_t)L * tp * sizeof(double), hipMemcpyDeviceToHost,
+                           st));
+  if (weight) FSA_HIP(hipMemcpyAsync(weight, c->lanczos_weight, tp * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (slq) FSA_HIP(hipMemcpyAsync(slq, c->results.p, tp * sizeof(double), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (slq) slq[0] = 0.0;
   return FSA_OK;
 }
 

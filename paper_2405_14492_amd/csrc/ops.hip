@@ -662,11 +662,11 @@ __global__ __launch_bounds__(256) void k_pcg_sparse_update(int64_t n, int ncols,
 
 // u += alpha h (the direction of this iteration), then h = q + beta h with
 // q = (r - t)/D (t = 0 when there is no low-rank part) and p = t + beta p.
-template <typename T>
+template <typename T, typename TU>
 __global__ void k_pcg_hupdate(int64_t n, int ncols, int64_t ld, const T* __restrict__ R, const T* __restrict__ Tt,
                               const double* __restrict__ Dinv, const double* __restrict__ alpha,
                               const double* __restrict__ beta, T* __restrict__ H, T* __restrict__ P,
-                              double* __restrict__ U, int has_lr) {
+                              TU* __restrict__ U, int has_lr) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t p = e / ncols;
   int c = (int)(e % ncols);
@@ -677,9 +677,9 @@ __global__ void k_pcg_hupdate(int64_t n, int ncols, int64_t ld, const T* __restr
   const double t = has_lr ? (double)Tt[o] : 0.0;
   const double r = (double)R[o];
   const double di = Dinv[p];
-  const double u = U[o];
+  const double u = (double)U[o];
   const double pv = has_lr ? (double)P[o] : 0.0;
-  U[o] = u + a * h;
+  U[o] = (TU)(u + a * h);
   H[o] = (T)((r - t) * di + b * h);
   if (has_lr) P[o] = (T)(t + b * pv);
 }
@@ -852,6 +852,7 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
   (void)tol;
   FSA_TRY((copy_block<double, T>(B, b.ld, b.R, b.ld, b.n, b.ncols, st)));
   FSA_HIP(hipMemsetAsync(b.U, 0, (size_t)b.n * b.ld * sizeof(double), st));
+  if (sizeof(T) == 4 && b.U32) FSA_HIP(hipMemsetAsync(b.U32, 0, (size_t)b.n * b.ld * sizeof(float), st));
   int ncb = (int)ceil_div(b.ncols, 64);
   int nparts_rq = 0, nparts_rr = 0;
   if (op.kdim > 0) {
@@ -950,8 +951,19 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
   // 5. h = q + beta h, p = t + beta p
   int64_t tot = b.n * b.ncols;
   KT_BEGIN(b);
-  hipLaunchKernelGGL(k_pcg_hupdate<T>, dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld,
-                     (const T*)b.R, (const T*)b.Tt, op.Dinv, b.alpha, b.beta, b.H, b.P, b.U, lr ? 1 : 0);
+  bool u32 = false;
+  if constexpr (sizeof(T) == 4) {
+    if (b.U32) {
+      hipLaunchKernelGGL((k_pcg_hupdate<T, float>), dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols,
+                         (int64_t)b.ld, (const T*)b.R, (const T*)b.Tt, op.Dinv, b.alpha, b.beta, b.H, b.P, b.U32,
+                         lr ? 1 : 0);
+      u32 = true;
+    }
+  }
+  if (!u32)
+    hipLaunchKernelGGL((k_pcg_hupdate<T, double>), dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols,
+                       (int64_t)b.ld, (const T*)b.R, (const T*)b.Tt, op.Dinv, b.alpha, b.beta, b.H, b.P, b.U,
+                       lr ? 1 : 0);
   KT_END(b, KT_UPDATE);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -968,9 +980,28 @@ __global__ void k_residual_f32(int64_t n, int ncols, int64_t ld, const double* _
   R[o] = (float)(B[o] - SU[o] - LU[o]);
 }
 
+__global__ void k_fold_u(int64_t n, int ncols, int64_t ld, double* __restrict__ U, float* __restrict__ U32) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t p = e / ncols;
+  int c = (int)(e % ncols);
+  if (p >= n) return;
+  int64_t o = p * ld + c;
+  U[o] += (double)U32[o];
+  U32[o] = 0.f;
+}
+
+fsa_status pcg_fold_u(PcgBlock<float>& b, hipStream_t st) {
+  if (!b.U32) return FSA_OK;
+  int64_t tot = b.n * b.ncols;
+  hipLaunchKernelGGL(k_fold_u, dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, b.U, b.U32);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
 fsa_status pcg_replace_residual_f32(PcgBlock<float>& b, const OpDesc<double>& op64, const OpDesc<float>& op32,
                                     const double* B, Scratch& s, hipStream_t st) {
   (void)op32;
+  FSA_TRY(pcg_fold_u(b, st));
   Buf<double> SU, LU;
   FSA_TRY(SU.alloc((size_t)b.n * b.ld));
   FSA_TRY(LU.alloc((size_t)b.n * b.ld));
@@ -994,6 +1025,8 @@ fsa_status pcg_replace_residual_f32(PcgBlock<float>& b, const OpDesc<double>& op
 // sqrt(beta_j)/alpha_j (Algorithm 2).  Eigenvalues by the implicit QL
 // iteration with Wilkinson-type shifts (Bowdler, Martin, Reinsch &
 // Wilkinson 1968), tracking only the first row of the eigenvector matrix.
+// The rotation lengths use sqrt(f^2 + g^2) directly: the Lanczos entries
+// are of the order of the preconditioned spectrum, far from overflow.
 __global__ __launch_bounds__(64) void k_slq(const double* __restrict__ ah, const double* __restrict__ bh,
                                             const int* __restrict__ iters, int ncols, int c_first,
                                             const double* __restrict__ weight, double* __restrict__ out,
@@ -1026,13 +1059,13 @@ __global__ __launch_bounds__(64) void k_slq(const double* __restrict__ ah, const
         if (mm != l) {
           if (iter++ == 200) { ok = false; break; }
           double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-          double r = hypot(g, 1.0);
+          double r = sqrt(g * g + 1.0);
           g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
           double s = 1.0, cc = 1.0, p = 0.0;
           bool deflated = false;
           for (int i = mm - 1; i >= l; --i) {
             double f = s * e[i], bb = cc * e[i];
-            r = hypot(f, g);
+            r = sqrt(f * f + g * g);
             e[i + 1] = r;
             if (r == 0.0) {
               d[i + 1] -= p;
@@ -1040,8 +1073,9 @@ __global__ __launch_bounds__(64) void k_slq(const double* __restrict__ ah, const
               deflated = true;
               break;
             }
-            s = f / r;
-            cc = g / r;
+            const double rinv = 1.0 / r;
+            s = f * rinv;
+            cc = g * rinv;
             g = d[i + 1] - p;
             r = (d[i] - g) * s + 2.0 * cc * bb;
             p = s * r;

@@ -125,6 +125,10 @@ struct PcgBlock {
   // block vectors (n x ld)
   T *R = nullptr, *H = nullptr, *V = nullptr, *P = nullptr, *Tt = nullptr, *Q0 = nullptr;
   double* U = nullptr;  // solution accumulator (float64)
+  // float32 operator only (may be null): the solution increments since the
+  // last fold into U, accumulated in float32 (half the bytes of U per
+  // iteration); pcg_fold_u adds them to U and clears them
+  float* U32 = nullptr;
   // per column
   double *rz = nullptr, *rz0 = nullptr, *alpha = nullptr, *beta = nullptr, *rr = nullptr, *bn2 = nullptr;
   int *active = nullptr, *iters = nullptr, *flags = nullptr;  // flags[0] = #active, flags[1] = breakdown
@@ -157,7 +161,10 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
 // iteration are appended to alpha_hist/beta_hist.
 template <typename T>
 fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, Scratch& s, hipStream_t st);
-// Replace R by B - A_op U with the float64 operator (mixed precision).
+// U += U32, U32 = 0 (no-op when U32 is null).
+fsa_status pcg_fold_u(PcgBlock<float>& b, hipStream_t st);
+// Replace R by B - A_op U with the float64 operator (mixed precision); folds
+// U32 into U first.
 fsa_status pcg_replace_residual_f32(PcgBlock<float>& b, const OpDesc<double>& op64, const OpDesc<float>& op32,
                                     const double* B, Scratch& s, hipStream_t st);
 

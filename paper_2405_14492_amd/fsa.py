@@ -29,7 +29,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfsa.so")
 
 EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad", "fsa_grad", "fsa_predict_var",
             "fsa_destroy",
-            "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_apply", "fsa_pool_trim"]
+            "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_export_lanczos", "fsa_apply",
+            "fsa_pool_trim"]
 
 
 class FsaError(RuntimeError):
@@ -99,6 +100,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fsa_export_csr.restype = C.c_int
     lib.fsa_export_diag.argtypes = [vp, dp, dp]
     lib.fsa_export_diag.restype = C.c_int
+    lib.fsa_export_lanczos.argtypes = [vp, P(C.c_int32), dp, dp, dp, dp]
+    lib.fsa_export_lanczos.restype = C.c_int
     lib.fsa_apply.argtypes = [vp, C.c_int32, dp, dp, C.c_int32]
     lib.fsa_apply.restype = C.c_int
     lib.fsa_pool_trim.argtypes = []
@@ -235,6 +238,20 @@ def fsa_export_diag(ctx, n):
     return D, ld.value
 
 
+def fsa_export_lanczos(ctx, ncols, max_iter):
+    """Lanczos record of the last likelihood solve: per column iterations,
+    alpha and beta (max_iter x ncols, by iteration), quadrature weights and
+    the weighted terms e_1^T log(T) e_1 (column 0: 0)."""
+    it = np.zeros(ncols, dtype=np.int32)
+    a = np.zeros((max_iter, ncols))
+    b = np.zeros((max_iter, ncols))
+    w = np.zeros(ncols)
+    q = np.zeros(ncols)
+    _check(lib().fsa_export_lanczos(ctx, it.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(a), _dptr(b), _dptr(w),
+                                    _dptr(q)))
+    return {"iters": it, "alpha": a, "beta": b, "weight": w, "slq": q}
+
+
 def fsa_apply(ctx, which, X, ncols=None):
     if which == OP_PROBES:
         n = int(X)
@@ -284,6 +301,10 @@ class FSA:
 
     def export_diag(self):
         return fsa_export_diag(self.ctx, self.n)
+
+    def export_lanczos(self):
+        L = self.opt.fixed_iter if self.opt.fixed_iter > 0 else self.opt.max_iter
+        return fsa_export_lanczos(self.ctx, self.opt.num_probes + 1, L)
 
     def apply(self, which, X, ncols=None):
         return fsa_apply(self.ctx, which, X if which != OP_PROBES else self.n, ncols)

@@ -129,6 +129,52 @@ def test_nll_grad_fixed_iterations_match_oracle(F, name):
     assert st["iters_min"] == k and st["iters_max"] == k
 
 
+def lanczos_tridiagonal(alpha, beta, k):
+    """T of Algorithm 2 from a column's CG coefficients (same entries as the
+    oracle's pcg_lanczos records)."""
+    d = np.array([1.0 / alpha[j] + (beta[j - 1] / alpha[j - 1] if j > 0 else 0.0) for j in range(k)])
+    e = np.array([np.sqrt(beta[j]) / alpha[j] for j in range(k - 1)])
+    return d, e
+
+
+@pytest.mark.parametrize("name,kw", [("m32_n1500_m100", dict(tol=1e-11, max_iter=2000)),
+                                     ("exp_n700_m40", dict(tol=1e-11, max_iter=2000)),
+                                     ("exp_clustered_n2000_m70", dict(tol=1e-6, max_iter=3000)),
+                                     ("ragged_n333_m7", dict(fixed_iter=40))])
+def test_quadrature_matches_oracle_on_device_coefficients(F, name, kw):
+    """The device's e_1^T log(T) e_1 (implicit QL) against the oracle's
+    eigendecomposition of the same T, built from the device's own CG
+    coefficients, 1e-12 relative per probe; the converged runs hold
+    near-multiple Ritz values (gaps below 1e-14)."""
+    say("case", name, kw)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=8, seed=5, **kw) as f:
+        f.nll_grad(with_grad=False)
+        rec = f.export_lanczos()
+    worst = 0.0
+    for c in range(1, 9):
+        k = int(rec["iters"][c])
+        d, e = lanczos_tridiagonal(rec["alpha"][:, c], rec["beta"][:, c], k)
+        ref = rec["weight"][c] * O.e1_log_e1(d, e)
+        err = abs(rec["slq"][c] - ref) / abs(ref)
+        worst = max(worst, err)
+        if err > 1e-12:
+            say("column", c, "k", k, "device", rec["slq"][c], "oracle", ref)
+    say("worst", worst)
+    assert worst < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_quadrature_of_short_krylov_spaces_matches_oracle(F, k):
+    """1-3 iterations: T of order 1 (a single node of weight 1), 2 and 3."""
+    locs, y, theta, ind, gamma = case(**CASES["ragged_n333_m7"])
+    ref = O.nll_grad(O.FSA(locs, ind, theta, gamma), y, 5, 31, fixed_iter=k, with_grad=False)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=5, seed=31, fixed_iter=k) as f:
+        nll, _, st = f.nll_grad(with_grad=False)
+    say("k", k, "nll", nll, ref["nll"])
+    assert abs(nll - ref["nll"]) <= 1e-9 * abs(ref["nll"])
+
+
 @pytest.mark.parametrize("name", ["exp_n700_m40", "m32_n1500_m100"])
 def test_nll_converged_matches_oracle(F, name):
     say("case", name)
