@@ -691,7 +691,7 @@ template <bool UPD, int SC>
 __global__ __launch_bounds__(1024) void k_reduce_gemm_f64(int64_t npts, int pts_per_chunk, int kdim, int ncols,
                                                           const double* __restrict__ A, F64Pro pro,
                                                           double* __restrict__ part, double* __restrict__ dot_part,
-                                                          int ld_dot, int lower_only) {
+                                                          int ld_dot, int lower_only, int nchunks) {
   constexpr int SP = 16;       // points per step
   constexpr int NA = SP / 4;   // A loads per lane per step
   __shared__ __attribute__((aligned(16))) double Xs[2][SP * XS_LD];
@@ -701,9 +701,16 @@ __global__ __launch_bounds__(1024) void k_reduce_gemm_f64(int64_t npts, int pts_
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q = lane >> 4, r16 = lane & 15;
-  const int c0 = blockIdx.x * 64;
+  // XCD-aware order: linear workgroup b runs on XCD b % 8, and the column
+  // blocks of one chunk go to the same XCD back to back, so that the
+  // chunk's A rows come from HBM once and from that XCD's L2 after (the
+  // grid's y extent is the chunk count rounded up to a multiple of 8)
   const int ncb = gridDim.x;
-  const int chunk = blockIdx.y;
+  const int bl = blockIdx.x + ncb * blockIdx.y;
+  const int cbx = (bl >> 3) % ncb;
+  const int chunk = (bl & 7) + 8 * ((bl >> 3) / ncb);
+  if (chunk >= nchunks) return;
+  const int c0 = cbx * 64;
   const int kb = blockIdx.z * 512 + w * 32;
   const bool mactive = kb < kdim && (!lower_only || kb >= c0);
   const int64_t pbeg = (int64_t)chunk * pts_per_chunk;
@@ -784,7 +791,7 @@ __global__ __launch_bounds__(1024) void k_reduce_gemm_f64(int64_t npts, int pts_
   }
   if (mactive) {
     // tile (a, b) row i = orow(q, r), column r16: k = kb + 2 i + a, c = 4 r16 + b
-    double* dst = part + (((int64_t)chunk * ncb + blockIdx.x) * kdim + kb) * 64 + 4 * r16;
+    double* dst = part + (((int64_t)chunk * ncb + cbx) * kdim + kb) * 64 + 4 * r16;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1201,6 +1208,153 @@ __global__ __launch_bounds__(512) void k_sddmm_cell(const int64_t* __restrict__ 
           const double dy2 = dy * dy;
           const double d2v = dx2 + dy2;
           vals[e] = fn(p, qq, sqrt(d2v), Dv[row * DLD + sl]);
+        }
+      }
+      __syncthreads();  // Dv and Xs are reused by the next block
+    }
+  }
+}
+
+// Symmetric SDDMM over one point set (rows = columns, X_p . Y_q = X_q . Y_p
+// and fn symmetric off the diagonal): each unordered pair of cells is
+// computed once.  The workgroup of cell c = (cx, cy) forms the dense block
+// of its rows against its forward neighbourhood only, the cells (cx, cy),
+// (cx + 1, cy) and (cx - 1 .. cx + 1, cy + 1), two contiguous column ranges
+// [c, right neighbour] and [row cy + 1]; it writes (a) every nonzero of its
+// rows whose column lies in that set, and (b) the mirror nonzeros (p', q)
+// with p' in a forward cell other than c and q among its rows, from the
+// transposed block entry.  A nonzero (p, q) with q behind c is written by
+// the workgroup of q's cell under (b).  Same blocking and MFMA scheme as
+// k_sddmm_cell on half the columns.
+template <class XOp, class YOp, class Fn>
+__global__ __launch_bounds__(512) void k_sddmm_sym(const int64_t* __restrict__ cs, int64_t ncell,
+                                                   const double* __restrict__ xs, GridDesc gd,
+                                                   const int64_t* __restrict__ rp, const int* __restrict__ col,
+                                                   const int* __restrict__ key, int kdim, XOp xop, YOp yop, Fn fn,
+                                                   double* __restrict__ vals) {
+#pragma clang fp contract(off)
+  constexpr int KC = 256, XLD = KC + 2, VB = 256, DLD = VB + 2;
+  __shared__ __attribute__((aligned(16))) double Xs[32 * XLD];
+  __shared__ __attribute__((aligned(16))) double Dv[32 * DLD];
+  typedef Mfma<double>::acc acc_t;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int64_t cell = xcd_cell(blockIdx.x, ncell);
+  if (cell >= ncell) return;
+  const int64_t rb = cs[cell], re = cs[cell + 1];
+  if (rb >= re) return;
+  const int64_t cx = cell % gd.gx, cy = cell / gd.gx;
+  const int64_t xlo = cx - 1 < 0 ? 0 : cx - 1;
+  const int64_t xhi = cx + 1 >= gd.gx ? gd.gx - 1 : cx + 1;
+  // forward ranges: [f1b, f1e) = this cell and its right neighbour,
+  // [f2b, f2e) = the three cells of the next cell row (empty on the last)
+  const int64_t f1b = rb, f1e = cs[cy * gd.gx + xhi + 1];
+  int64_t f2b = 0, f2e = 0;
+  if (cy + 1 < gd.gy) {
+    f2b = cs[(cy + 1) * gd.gx + xlo];
+    f2e = cs[(cy + 1) * gd.gx + xhi + 1];
+  }
+  const int n1 = (int)(f1e - f1b);
+  const int V = n1 + (int)(f2e - f2b);
+  for (int64_t g0 = rb; g0 < re; g0 += 32) {
+    const int nrg = (int)min((int64_t)32, re - g0);
+    const int64_t E0 = rp[g0], E1 = rp[g0 + nrg];
+    for (int vb0 = 0; vb0 < V; vb0 += VB) {
+      const int vn = min(VB, V - vb0);
+      int64_t qcol[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        int v = vb0 + 16 * (w + 8 * t) + r16;
+        if (v >= V) v = V - 1;
+        qcol[t] = v < n1 ? f1b + v : f2b + (v - n1);
+      }
+      const bool tile_on[2] = {16 * w < vn, 16 * (w + 8) < vn};
+      acc_t acc[2][2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) acc[t][a] = acc_t{0, 0, 0, 0};
+      for (int kc0 = 0; kc0 < kdim; kc0 += KC) {
+        const int kn = min(KC, kdim - kc0);
+        __syncthreads();
+        for (int u = tid; u < 32 * (kn / 4); u += 512) {
+          const int r = u / (kn / 4), k4 = (u - r * (kn / 4)) * 4;
+          const int64_t p = g0 + min(r, nrg - 1);
+          const V4<double> x = xop(p, kc0 + k4);
+          double* dst = &Xs[r * XLD + k4];
+          *reinterpret_cast<d2*>(dst) = d2{x.v[0], x.v[1]};
+          *reinterpret_cast<d2*>(dst + 2) = d2{x.v[2], x.v[3]};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (!tile_on[t]) continue;
+          V4<double> b0 = yop(qcol[t], kc0 + 4 * q), b1;
+          for (int ks = 0; ks < kn; ks += 32) {
+            b1 = yop(qcol[t], kc0 + min(ks + 16, kn - 16) + 4 * q);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              const double* xa = &Xs[(a * 16 + r16) * XLD + ks + 4 * q];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc[t][a] = Mfma<double>::op(xa[j], b0.v[j], acc[t][a]);
+            }
+            b0 = yop(qcol[t], kc0 + min(ks + 32, kn - 16) + 4 * q);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              const double* xa = &Xs[(a * 16 + r16) * XLD + ks + 16 + 4 * q];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc[t][a] = Mfma<double>::op(xa[j], b1.v[j], acc[t][a]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if (!tile_on[t]) continue;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Dv[(a * 16 + Mfma<double>::orow(q, r)) * DLD + 16 * (w + 8 * t) + r16] = acc[t][a][r];
+      }
+      __syncthreads();
+      // (a) this group's nonzeros with a forward column
+      for (int64_t e = E0 + tid; e < E1; e += 512) {
+        const int64_t qq = col[e];
+        const int fp = (qq >= f1b && qq < f1e) ? (int)(qq - f1b) : ((qq >= f2b && qq < f2e) ? n1 + (int)(qq - f2b) : -1);
+        const int sl = fp - vb0;
+        if (fp >= 0 && (unsigned)sl < (unsigned)vn) {
+          const int row = (int)((unsigned)key[e] >> KEY_SLOT_BITS);
+          const int64_t p = g0 + row;
+          const double dx = xs[2 * p] - xs[2 * qq];
+          const double dy = xs[2 * p + 1] - xs[2 * qq + 1];
+          const double dx2 = dx * dx;
+          const double dy2 = dy * dy;
+          vals[e] = fn(p, qq, sqrt(dx2 + dy2), Dv[row * DLD + sl]);
+        }
+      }
+      // (b) mirror nonzeros: rows p' of the forward cells after this one
+      // whose column is in this group; wave w takes rows w, w + 8, ...
+      {
+        const int64_t m1 = cs[cell + 1];  // first row after this cell
+        const int nm1 = (int)(f1e - m1), nm = nm1 + (int)(f2e - f2b);
+        for (int j = w; j < nm; j += 8) {
+          const int64_t pp = j < nm1 ? m1 + j : f2b + (j - nm1);
+          const int fp = pp < f1e ? (int)(pp - f1b) : n1 + (int)(pp - f2b);
+          const int sl = fp - vb0;
+          if ((unsigned)sl >= (unsigned)vn) continue;
+          const int64_t a0 = rp[pp], a1 = rp[pp + 1];
+          for (int64_t e = a0 + lane; e < a1; e += 64) {
+            const int64_t qq = col[e];
+            if (qq >= g0 && qq < g0 + nrg) {
+              const double dx = xs[2 * pp] - xs[2 * qq];
+              const double dy = xs[2 * pp + 1] - xs[2 * qq + 1];
+              const double dx2 = dx * dx;
+              const double dy2 = dy * dy;
+              vals[e] = fn(pp, qq, sqrt(dx2 + dy2), Dv[(int)(qq - g0) * DLD + sl]);
+            }
+          }
         }
       }
       __syncthreads();  // Dv and Xs are reused by the next block

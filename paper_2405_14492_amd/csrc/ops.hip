@@ -203,18 +203,30 @@ fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const
   gd.gamma = gamma;
   if (csr.nnz == 0) return FSA_OK;
   dim3 grid(8 * ceil_div(rg.ncell, 8));
+  // one point set with symmetric dot products (X = Y, or [F|A] against
+  // [A|F]): each pair of cells once
+  const bool sym = self && Xr == Yc && (!deriv || Fr == Fc);
   if (!deriv) {
     RowsOp<double> xo{Xr, mp}, yo{Yc, mp};
     ValFn fn{th, gamma, self ? 1 : 0, D};
-    hipLaunchKernelGGL((k_sddmm_cell<RowsOp<double>, RowsOp<double>, ValFn>), grid, dim3(512), 0, st, rg.cstart.p,
-                       rg.ncell, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, mp, xo, yo,
-                       fn, vals);
+    if (sym)
+      hipLaunchKernelGGL((k_sddmm_sym<RowsOp<double>, RowsOp<double>, ValFn>), grid, dim3(512), 0, st, rg.cstart.p,
+                         rg.ncell, rg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, mp, xo, yo, fn, vals);
+    else
+      hipLaunchKernelGGL((k_sddmm_cell<RowsOp<double>, RowsOp<double>, ValFn>), grid, dim3(512), 0, st, rg.cstart.p,
+                         rg.ncell, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, mp, xo, yo,
+                         fn, vals);
   } else {
     Rows2Op<double> xo{Fr, Xr, mp, mp}, yo{Yc, Fc, mp, mp};
     DValFn fn{th, gamma};
-    hipLaunchKernelGGL((k_sddmm_cell<Rows2Op<double>, Rows2Op<double>, DValFn>), grid, dim3(512), 0, st, rg.cstart.p,
-                       rg.ncell, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, 2 * mp, xo,
-                       yo, fn, vals);
+    if (sym)
+      hipLaunchKernelGGL((k_sddmm_sym<Rows2Op<double>, Rows2Op<double>, DValFn>), grid, dim3(512), 0, st,
+                         rg.cstart.p, rg.ncell, rg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, 2 * mp, xo, yo, fn,
+                         vals);
+    else
+      hipLaunchKernelGGL((k_sddmm_cell<Rows2Op<double>, Rows2Op<double>, DValFn>), grid, dim3(512), 0, st,
+                         rg.cstart.p, rg.ncell, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p,
+                         csr.key.p, 2 * mp, xo, yo, fn, vals);
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -223,13 +235,15 @@ fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const
 struct ReduceShape {
   int nchunks, ppc, ncb, nmb, zb, threads;
 };
-static ReduceShape reduce_shape(int64_t n, int kdim, int ncols) {
+// wg_target: about how many workgroups to launch (one per CU by default;
+// more where workgroups carry unequal work and the scheduler must balance)
+static ReduceShape reduce_shape(int64_t n, int kdim, int ncols, int wg_target = 256) {
   ReduceShape r;
   r.ncb = (int)ceil_div(ncols, 64);
   r.nmb = kdim / 64;
   r.zb = (int)ceil_div(r.nmb, 8);
   r.threads = 64 * (r.nmb < 8 ? r.nmb : 8);
-  int64_t target = 256 / (r.ncb * r.zb);
+  int64_t target = wg_target / (r.ncb * r.zb);
   if (target < 16) target = 16;
   int64_t nch = ceil_div(n, 1024);
   if (nch > target) nch = target;
@@ -263,14 +277,14 @@ static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int n
   }
   // grid (column blocks, chunks, kdim blocks): the column blocks of one chunk run back to back
   if constexpr (std::is_same<T, double>::value) {
-    dim3 grid(r.ncb, r.nchunks, (kdim + 511) / 512);
+    dim3 grid(r.ncb, (int)round_up(r.nchunks, 8), (kdim + 511) / 512);
     F64Pro fp = pro.f64();
     if constexpr (Pro::kUpd) {
       hipLaunchKernelGGL((k_reduce_gemm_f64<true, Pro::kSc>), grid, dim3(1024), 0, st, n, r.ppc, kdim, ncols, A, fp,
-                         part, dot_part, ld_dot, lower_only);
+                         part, dot_part, ld_dot, lower_only, r.nchunks);
     } else {
       hipLaunchKernelGGL((k_reduce_gemm_f64<false, Pro::kSc>), grid, dim3(1024), 0, st, n, r.ppc, kdim, ncols, A,
-                         fp, part, dot_part, ld_dot, lower_only);
+                         fp, part, dot_part, ld_dot, lower_only, r.nchunks);
     }
   } else if constexpr (std::is_same<T, float>::value) {
     if (lower_only) {
@@ -305,7 +319,9 @@ static fsa_status reduce_finish(Scratch& s, const ReduceShape& r, double* W, int
 }
 
 fsa_status capacitance(const double* A, const double* D, int64_t n, int mp, double* C, Scratch& s, hipStream_t st) {
-  ReduceShape r = reduce_shape(n, mp, mp);
+  // lower blocks only: column block cb works on mp - 64 cb rows, so four
+  // workgroups per CU let the scheduler even out the triangle
+  ReduceShape r = reduce_shape(n, mp, mp, 1024);
   FSA_TRY(ensure_part<double>(s, r));
   DivDPro<double> pro{A, mp, D};
   FSA_TRY((launch_reduce<double, false>(r, n, mp, mp, A, pro, (double*)s.part.p, nullptr, 0, st, 1)));
