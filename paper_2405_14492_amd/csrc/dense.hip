@@ -218,6 +218,24 @@ fsa_status to_bf16(const double* in, uint16_t* out, double* rounded, int64_t cnt
   return FSA_OK;
 }
 
+__global__ void k_bf16_interleave8(const uint16_t* __restrict__ A, int64_t n, int kdim, uint16_t* __restrict__ out,
+                                   int64_t tot) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // output element
+  if (e >= tot) return;
+  const int j = (int)(e & 7);
+  const int64_t gk = e >> 3;
+  const int k = (int)(gk % kdim);
+  const int64_t p = (gk / kdim) * 8 + j;
+  out[e] = p < n ? A[p * kdim + k] : (uint16_t)0;
+}
+fsa_status bf16_interleave8(const uint16_t* A, int64_t n, int kdim, uint16_t* out, hipStream_t st) {
+  const int64_t tot = ceil_div(n, 8) * 8 * kdim;
+  if (tot <= 0) return FSA_OK;
+  hipLaunchKernelGGL(k_bf16_interleave8, dim3(ceil_div(tot, 256)), dim3(256), 0, st, A, n, kdim, out, tot);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
 fsa_status to_float(const double* in, float* out, int64_t cnt, hipStream_t st) {
   if (cnt <= 0) return FSA_OK;
   hipLaunchKernelGGL(k_to_float, dim3(ceil_div(cnt, 256)), dim3(256), 0, st, in, out, cnt);

@@ -190,7 +190,8 @@ struct fsa_ctx {
   Buf<double> Sm, Lm, Lminv, C, LCinv, Cinv;
   Buf<double> A, vals, D, Dinv;
   Buf<float> Af, valsf;
-  Buf<uint16_t> Abf;  // bfloat16 copy of A (MIXED_BF16A)
+  Buf<uint16_t> Abf;   // bfloat16 copy of A (MIXED_BF16A), point-major
+  Buf<uint16_t> Abf8;  // the same, point-interleaved by 8 (bfloat16-MFMA residual pass)
   Buf<double> logdet_parts;  // [0] = 2 sum log diag L_C, [1] = sum log D
   Buf<int> info;
   // PCG / SLQ
@@ -252,7 +253,10 @@ static fsa_status build_values(fsa_ctx* c) {
   // MIXED_BF16A: the model takes the bfloat16-rounded factor from here on
   // (residual values, D_s, capacitance, probes, gradient and prediction), so
   // the PCG operator read in bfloat16 is the float64 operator of that model
-  if (c->opt.precision == FSA_MIXED_BF16A) FSA_TRY(to_bf16(c->A.p, c->Abf.p, c->A.p, c->n * (int64_t)mp, st));
+  if (c->opt.precision == FSA_MIXED_BF16A) {
+    FSA_TRY(to_bf16(c->A.p, c->Abf.p, c->A.p, c->n * (int64_t)mp, st));
+    FSA_TRY(bf16_interleave8(c->Abf.p, c->n, mp, c->Abf8.p, st));
+  }
   FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, true, false,
                           c->vals.p, c->D.p, st));
   FSA_TRY(reciprocal(c->D.p, c->Dinv.p, c->n, st));
@@ -327,7 +331,10 @@ static fsa_status build_core(fsa_ctx* c, const double* locs, const double* y, co
   FSA_TRY(c->Dinv.alloc(n));
   FSA_TRY(c->logdet_parts.alloc(2));
   if (c->opt.precision == FSA_MIXED_FP32) FSA_TRY(c->Af.alloc((size_t)n * mp));
-  if (c->opt.precision == FSA_MIXED_BF16A) FSA_TRY(c->Abf.alloc((size_t)n * mp));
+  if (c->opt.precision == FSA_MIXED_BF16A) {
+    FSA_TRY(c->Abf.alloc((size_t)n * mp));
+    FSA_TRY(c->Abf8.alloc((size_t)ceil_div(n, 8) * 8 * mp));
+  }
   if (c->opt.precision != FSA_FP64) FSA_TRY(c->valsf.alloc(c->csr.nnz));
   return build_values(c);
 }
@@ -506,6 +513,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
     op.val = reinterpret_cast<const T*>(c->valsf.p);
     op.A = reinterpret_cast<const T*>(c->Af.p);  // null in MIXED_BF16A
     op.Abf = c->Abf.p;                            // null unless MIXED_BF16A
+    op.Abf8 = c->Abf8.p;
   }
   const double tol = c->opt.cg_rel_tol;
   const int fixed = c->opt.fixed_iter > 0 ? 1 : 0;

@@ -1362,4 +1362,338 @@ __global__ __launch_bounds__(512) void k_sddmm_sym(const int64_t* __restrict__ c
   }
 }
 
+// ------------------------------------------------------------------ bfloat16 MFMA passes (MIXED_BF16A)
+// v_mfma_f32_16x16x32_bf16: lane l supplies A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16], j = 0..7, and holds D[4 (l / 16) + r][l % 16],
+// r = 0..3.  A (the rounded factor) is exact in bfloat16; the float32 block
+// operand x is split into three bfloat16 parts, hi = bf16(x), mid =
+// bf16(x - hi), lo = bf16(x - hi - mid) (each difference exact in float32),
+// which leave |x - hi - mid - lo| <= 2^-27 |x|.  The three products per tile
+// are exact and accumulate in float32, so a pass agrees with the float32
+// product of the widened factor to float32 accumulation order.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned bf16_rne_bits(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+// the three bfloat16 parts of x
+__device__ __forceinline__ void bf16_split3(float x, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
+  const unsigned h = bf16_rne_bits(x);
+  const float r1 = x - __uint_as_float(h << 16);
+  const unsigned m = bf16_rne_bits(r1);
+  const float r2 = r1 - __uint_as_float(m << 16);
+  hi = (uint16_t)h;
+  mid = (uint16_t)m;
+  lo = (uint16_t)bf16_rne_bits(r2);
+}
+__device__ __forceinline__ f4 mfma_bf16(u4v a, u4v b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                 0);
+}
+
+// Residual pass on the bfloat16 MFMA: same contract, prologue modes and
+// partial layout as k_reduce_gemm_f32 (grid (ncb, nchunks), 512 threads,
+// wave w owns kdim rows 64 w .. 64 w + 63 as four 16-row tiles against the
+// workgroup's 64 columns).  A comes point-interleaved, [n/8][kdim][8], so
+// one 16-byte load gives a lane the eight points of its MFMA k slice for
+// one kdim row.  Points are taken 32 per step (one MFMA k extent); the
+// prologue of the next step writes the three parts of X to the other half
+// of a double-buffered LDS block as [part][column][point], and the A loads
+// of the step two ahead are in flight while the matrix cores work.
+template <bool UPD, int SC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_reduce_bf16(
+    int64_t npts, int pts_per_chunk, int kdim, int ncols, const uint16_t* __restrict__ A8, F32Pro pro,
+    float* __restrict__ part, double* __restrict__ dot_part, int ld_dot) {
+  constexpr int SP = 32;       // points per step
+  constexpr int NP = SP / 8;   // prologue elements per thread per step
+  constexpr int XST = 40;      // LDS stride (bfloat16) of one column's points
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][3][64 * XST];
+  __shared__ double red[512];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.x * 64;
+  const int ncb = gridDim.x;
+  const int chunk = blockIdx.y;
+  const int kb = w * 64;
+  const bool mactive = kb < kdim;
+  const int64_t pbeg = (int64_t)chunk * pts_per_chunk;  // a multiple of 8
+  const int64_t pend = min(npts, pbeg + pts_per_chunk);
+  const int np = pend > pbeg ? (int)(pend - pbeg) : 0;
+  const int nsteps = (np + SP - 1) / SP;
+  const int tc = tid & 63, tp = tid >> 6;  // prologue: column c0 + tc, points tp + 8 u
+  const int c = c0 + tc;
+  const bool cval = c < ncols;
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+  double dacc = 0.0;
+  u4v ab0[4] = {}, ab1[4] = {}, ab2[4] = {};
+  const int ngr = (np + 7) / 8;  // point groups of the chunk (zero-padded past npts)
+  const __amdgpu_buffer_rsrc_t arsrc = rsrc_of(A8 + (pbeg / 8) * kdim * 8, (int64_t)ngr * kdim * 16);
+  const __amdgpu_buffer_rsrc_t srsrc = rsrc_of(pro.S + pbeg * pro.ld, (int64_t)np * pro.ld * 4);
+  const __amdgpu_buffer_rsrc_t vrsrc = rsrc_of(UPD ? pro.V + pbeg * pro.ld : pro.S, UPD ? (int64_t)np * pro.ld * 4 : 0);
+  const __amdgpu_buffer_rsrc_t drsrc = rsrc_of(SC ? pro.sc + pbeg : (const double*)pro.S, SC ? (int64_t)np * 8 : 0);
+  const double a_c = (UPD && cval) ? pro.alpha[c] : 0.0;
+  // byte offset of (group q of step 0, kdim row kb + r16)
+  const unsigned a_off = mactive ? (unsigned)(q * kdim + kb + r16) * 16u : (unsigned)BUF_OOR;
+  const unsigned a_step = (unsigned)(4 * kdim) * 16u;
+  const unsigned s_off = cval ? (unsigned)(tp * (int)pro.ld + c) * 4u : (unsigned)BUF_OOR;
+  const unsigned s_step = 8u * (unsigned)pro.ld * 4u;
+  float sv[NP], vv[NP];
+  double dv[NP];
+  auto load_a = [&](int s, u4v* ab) {
+    const unsigned so = a_off + (unsigned)s * a_step;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) ab[a] = __builtin_bit_cast(u4v, __builtin_amdgcn_raw_buffer_load_b128(arsrc, so + 256u * a, 0, 0));
+  };
+  auto pro_load = [&](int s) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int pr = s * SP + tp + 8 * u;
+      const unsigned o = s_off + (unsigned)(s * NP + u) * s_step;
+      sv[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(srsrc, o, 0, 0));
+      vv[u] = UPD ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(vrsrc, o, 0, 0)) : 0.f;
+      dv[u] = SC ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(drsrc, (unsigned)pr * 8u, 0, 0)) : 1.0;
+    }
+  };
+  auto pro_apply = [&](int s, int buf) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int pl = tp + 8 * u;
+      const int pr = s * SP + pl;
+      double x = (double)sv[u];
+      if constexpr (UPD) {
+        const float rt = (float)(x - a_c * (double)vv[u]);
+        const unsigned o = s_off + (unsigned)(s * NP + u) * s_step;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, rt), srsrc, o, 0, 0);
+        x = (double)rt;
+        dacc += x * x;  // zero for padding columns and points past the chunk
+      }
+      const double y = SC == 0 ? x : (SC == 1 ? x * dv[u] : x / dv[u]);
+      const float yf = (pr < np && cval) ? (float)y : 0.f;
+      uint16_t h, m, l;
+      bf16_split3(yf, h, m, l);
+      Xs[buf][0][tc * XST + pl] = h;
+      Xs[buf][1][tc * XST + pl] = m;
+      Xs[buf][2][tc * XST + pl] = l;
+    }
+  };
+  auto mma = [&](const u4v* ab, int buf) {
+    if (!mactive) return;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int P = 0; P < 3; ++P) {
+        const u4v bop = *reinterpret_cast<const u4v*>(&Xs[buf][P][(16 * b + r16) * XST + 8 * q]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(ab[a], bop, acc[a][b]);
+      }
+  };
+  auto step = [&](int s, const u4v* abc, u4v* abn) {
+    pro_load(s + 1);
+    load_a(s + 2, abn);
+    mma(abc, s & 1);
+    pro_apply(s + 1, (s + 1) & 1);
+    __syncthreads();
+  };
+  if (nsteps > 0) {
+    pro_load(0);
+    load_a(0, ab0);
+    load_a(1, ab1);
+    pro_apply(0, 0);
+    __syncthreads();
+    int s = 0;
+    for (; s + 2 < nsteps; s += 3) {
+      step(s, ab0, ab2);
+      step(s + 1, ab1, ab0);
+      step(s + 2, ab2, ab1);
+    }
+    if (s < nsteps) step(s, ab0, ab2);
+    if (s + 1 < nsteps) step(s + 1, ab1, ab0);
+  }
+  if (mactive) {
+    // tile (a, b) element r: k = kb + 16 a + 4 q + r, column 16 b + r16
+    float* dst = part + (((int64_t)chunk * ncb + blockIdx.x) * kdim + kb) * 64 + r16;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) dst[(16 * a + 4 * q + r) * 64 + 16 * b] = acc[a][b][r];
+  }
+  if constexpr (UPD) {
+    red[tid] = dacc;
+    __syncthreads();
+    if (tid < 64) {
+      double sum = 0.0;
+      for (int k = 0; k < 8; ++k) sum += red[k * 64 + tid];
+      dot_part[(int64_t)chunk * ld_dot + c0 + tid] = sum;
+    }
+  }
+}
+
+// Woodbury expansion on the bfloat16 MFMA: same contract and epilogue as
+// k_rows_gemm_f32 for a column block of at most BF16_ROWS_NC columns.  The
+// three parts of the kdim x 64 block of G live in LDS as [part][column][k]
+// (row stride kdim + 8) for the first BF16_ROWS_NC columns, with a zero row
+// standing in for the padding columns; that fits kdim <= 512 in 160 KB.
+// Each of the 16 waves is persistent over 16-row tiles and walks k in steps
+// of 64: a lane loads 32 contiguous bytes of its row (k = 64 kb + 16 q' +
+// 8 t + j for MFMA t, j), two steps ahead in the flattened (tile, k block)
+// stream.
+constexpr int BF16_ROWS_NC = 52;
+inline size_t bf16_rows_lds(int kdim) { return (size_t)(3 * BF16_ROWS_NC + 1) * (kdim + 8) * 2; }
+
+template <int EM>
+__global__ __launch_bounds__(1024) void k_rows_bf16(int64_t nrows, int kdim, const uint16_t* __restrict__ A,
+                                                    int64_t lda, const float* __restrict__ G, int ldg, int ncols,
+                                                    F32RowsEpi epi, double* __restrict__ dot_part, int ld_dot) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t gsh[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.y * 64;
+  const int gst = kdim + 8;
+  for (int e = tid; e < kdim * BF16_ROWS_NC; e += 1024) {
+    const int k = e / BF16_ROWS_NC, cc = e - k * BF16_ROWS_NC;
+    const float v = (c0 + cc < ncols) ? G[(int64_t)k * ldg + c0 + cc] : 0.f;
+    uint16_t h, m, l;
+    bf16_split3(v, h, m, l);
+    gsh[(0 * BF16_ROWS_NC + cc) * gst + k] = h;
+    gsh[(1 * BF16_ROWS_NC + cc) * gst + k] = m;
+    gsh[(2 * BF16_ROWS_NC + cc) * gst + k] = l;
+  }
+  for (int e = tid; e < gst; e += 1024) gsh[3 * BF16_ROWS_NC * gst + e] = 0;
+  __syncthreads();
+  // element offsets of this lane's G rows (column 16 b + r16, part P)
+  int brow[4][3];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int P = 0; P < 3; ++P) {
+      const int cc = 16 * b + r16;
+      brow[b][P] = (cc < BF16_ROWS_NC ? (P * BF16_ROWS_NC + cc) : 3 * BF16_ROWS_NC) * gst + 16 * q;
+    }
+  const int nkb = kdim / 64;
+  const int64_t ntile = (nrows + 15) / 16;
+  const int64_t gw = (int64_t)blockIdx.x * 16 + w, GW = (int64_t)gridDim.x * 16;
+  const int64_t ntw = gw < ntile ? (ntile - gw + GW - 1) / GW : 0;
+  const unsigned lane_off = (unsigned)(r16 * lda + 16 * q) * 2u;
+  double dsum[4] = {0, 0, 0, 0};
+  int64_t lj = 0;
+  int lkb = 0;
+  auto load_next = [&](u4v* ab) {
+    const int64_t row0 = (gw + lj * GW) * 16;
+    const int64_t nr = lj < ntw ? min((int64_t)16, nrows - row0) : 0;
+    const __amdgpu_buffer_rsrc_t rs = rsrc_of(A + (lj < ntw ? row0 * lda : 0), nr * lda * 2);
+    const unsigned o = lane_off + (unsigned)lkb * 128u;
+    ab[0] = __builtin_bit_cast(u4v, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0));
+    ab[1] = __builtin_bit_cast(u4v, __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u, 0, 0));
+    if (++lkb == nkb) {
+      lkb = 0;
+      ++lj;
+    }
+  };
+  f4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = f4{0, 0, 0, 0};
+  int64_t cj = 0;
+  int ckb = 0;
+  auto epilogue = [&]() {
+    const int64_t row0 = (gw + cj * GW) * 16;
+    const int64_t nr = min((int64_t)16, nrows - row0);
+    const __amdgpu_buffer_rsrc_t ry = rsrc_of(epi.Y ? epi.Y + row0 * epi.ld : (const void*)A, epi.Y ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rr = rsrc_of(epi.R + row0 * epi.ld, nr * epi.ld * 4);
+    const __amdgpu_buffer_rsrc_t rd = rsrc_of(epi.Dinv + row0, nr * 8);
+    const __amdgpu_buffer_rsrc_t rh = rsrc_of(EM == ROWS_PCG_INIT ? epi.H + row0 * epi.ld : (const void*)A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rp = rsrc_of(EM == ROWS_PCG_INIT ? epi.P + row0 * epi.ld : (const void*)A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rq = rsrc_of(EM == ROWS_PCG_INIT ? epi.Q0 + row0 * epi.ld : (const void*)A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    float xin[4][4];
+    double di[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      di[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rd, (unsigned)(4 * q + r) * 8u, 0, 0));
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int cc = c0 + b * 16 + r16;
+        const unsigned o = cc < ncols ? (unsigned)((4 * q + r) * (int)epi.ld + cc) * 4u : (unsigned)BUF_OOR;
+        xin[r][b] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rr, o, 0, 0));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int cc = c0 + b * 16 + r16;
+        const unsigned o = cc < ncols ? (unsigned)((4 * q + r) * (int)epi.ld + cc) * 4u : (unsigned)BUF_OOR;
+        const float v = acc[b][r];
+        const double rv = (double)xin[r][b];
+        const double qv = (rv - (double)v) * di[r];
+        dsum[b] += rv * qv;  // zero for points past the tile and padding columns
+        if constexpr (EM == ROWS_PCG) {
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), ry, o, 0, 0);
+        } else {
+          const unsigned qb = __builtin_bit_cast(unsigned, (float)qv);
+          __builtin_amdgcn_raw_buffer_store_b32(qb, rh, o, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rp, o, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(qb, rq, o, 0, 0);
+        }
+      }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = f4{0, 0, 0, 0};
+  };
+  auto step = [&](const u4v* cur, u4v* ahead) {
+    load_next(ahead);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int P = 0; P < 3; ++P) {
+          const u4v g = *reinterpret_cast<const u4v*>(&gsh[brow[b][P] + ckb * 64 + 8 * t]);
+          acc[b] = mfma_bf16(cur[t], g, acc[b]);
+        }
+    if (++ckb == nkb) {
+      epilogue();
+      ckb = 0;
+      ++cj;
+    }
+  };
+  const int64_t nflat = ntw * nkb;
+  u4v b0[2], b1[2], b2[2];
+  load_next(b0);
+  load_next(b1);
+  int64_t f = 0;
+  for (; f + 2 < nflat; f += 3) {
+    step(b0, b2);
+    step(b1, b0);
+    step(b2, b1);
+  }
+  if (f < nflat) step(b0, b2);
+  if (f + 1 < nflat) step(b1, b0);
+  // column dots: the four row groups of each wave, then the 16 waves
+  __syncthreads();  // G is no longer read: reuse its LDS
+  double* red = reinterpret_cast<double*>(gsh);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double v = dsum[b];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (q == 0) red[w * 64 + b * 16 + r16] = v;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double sacc = 0.0;
+    for (int k = 0; k < 16; ++k) sacc += red[k * 64 + tid];
+    dot_part[(int64_t)blockIdx.x * ld_dot + c0 + tid] = sacc;
+  }
+}
+
 }  // namespace fsa

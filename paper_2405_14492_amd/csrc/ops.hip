@@ -270,7 +270,7 @@ static fsa_status ensure_part(Scratch& s, const ReduceShape& r) {
 template <typename T, bool DOT, class Pro>
 static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int ncols, const T* A, const Pro& pro,
                                 T* part, double* dot_part, int ld_dot, hipStream_t st, int lower_only = 0,
-                                const uint16_t* Abf = nullptr) {
+                                const uint16_t* Abf = nullptr, const uint16_t* Abf8 = nullptr) {
   if (DOT && r.zb != 1) {
     set_error("reduce GEMM with a dot prologue needs kdim <= 512 (got %d)", kdim);
     return FSA_ERR_INVALID_ARG;
@@ -293,7 +293,10 @@ static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int n
     }
     dim3 grid(r.ncb, r.nchunks, (kdim + 511) / 512);
     F32Pro fp = pro.f32();
-    if (Abf) {
+    if (Abf8 && r.zb == 1 && r.ppc % 32 == 0) {
+      hipLaunchKernelGGL((k_reduce_bf16<Pro::kUpd, Pro::kSc>), dim3(r.ncb, r.nchunks), dim3(512), 0, st, n, r.ppc, kdim,
+                         ncols, Abf8, fp, part, dot_part, ld_dot);
+    } else if (Abf) {
       hipLaunchKernelGGL((k_reduce_gemm_f32<bf16_t, Pro::kUpd, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim,
                          ncols, Abf, fp, part, dot_part, ld_dot);
     } else {
@@ -824,7 +827,16 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
                   (int64_t)b.ld};
     const size_t smem = (size_t)op.kdim * 64 * sizeof(float);
     dim3 grid2(gx, ncb);
-    if (op.Abf) {
+    if (op.Abf8 && b.ncols <= BF16_ROWS_NC && op.kdim <= 512) {
+      // bfloat16 MFMA (op.Abf8 set means the bfloat16 kernels are in use)
+      const size_t smem16 = bf16_rows_lds(op.kdim);
+      if (init)
+        hipLaunchKernelGGL((k_rows_bf16<ROWS_PCG_INIT>), grid2, dim3(1024), smem16, st, b.n, op.kdim, op.Abf,
+                           (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
+      else
+        hipLaunchKernelGGL((k_rows_bf16<ROWS_PCG>), grid2, dim3(1024), smem16, st, b.n, op.kdim, op.Abf,
+                           (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
+    } else if (op.Abf) {
       if (init)
         hipLaunchKernelGGL((k_rows_gemm_f32<bf16_t, true, ROWS_PCG_INIT>), grid2, dim3(1024), smem, st, b.n, op.kdim,
                            op.Abf, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
@@ -875,7 +887,8 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
     ReduceShape r = reduce_shape(b.n, op.kdim, b.ncols);
     FSA_TRY(ensure_part<T>(s, r));
     MulDinvPro<T> pro{b.R, b.ld, op.Dinv};
-    FSA_TRY((launch_reduce<T, false>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, nullptr, 0, st, 0, op.Abf)));
+    FSA_TRY((launch_reduce<T, false>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, nullptr, 0, st, 0, op.Abf,
+                                     op.Abf8)));
     FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
     FSA_TRY(pcg_precond_and_dots<T>(b, op, 1, s, nparts_rq, st));
     // |b|^2 partials
@@ -938,7 +951,7 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     {
       KT_BEGIN(b);
       FSA_TRY((launch_reduce<T, true>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, s.dot2.p, ldd, st, 0,
-                                      op.Abf)));
+                                      op.Abf, op.Abf8)));
       KT_END(b, KT_PASS1);
     }
     nparts_rr = r.nchunks;

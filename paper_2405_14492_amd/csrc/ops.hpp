@@ -150,6 +150,9 @@ struct OpDesc {
   const double* Dinv = nullptr;  // 1 / D
   const T* A = nullptr;
   const uint16_t* Abf = nullptr;  // float32 operator only: A in bfloat16 for the PCG passes (else null)
+  // with Abf: the same values point-interleaved, [ceil(n/8)][kdim][8] (zero
+  // past n), for the bfloat16-MFMA residual pass (null: widen Abf instead)
+  const uint16_t* Abf8 = nullptr;
   int kdim = 0;
   const double* Cinv = nullptr;
 };
@@ -185,6 +188,9 @@ fsa_status pred_mean(int64_t np, int mp, const double* Ap, const double* w, cons
                      double* out, hipStream_t st);
 fsa_status symmetrize(double* A, int n, hipStream_t st);
 
+// out[((p/8) kdim + k) 8 + p%8] = A[p][k] (bfloat16, n x kdim point-major),
+// zero for the padding points up to a multiple of 8
+fsa_status bf16_interleave8(const uint16_t* A, int64_t n, int kdim, uint16_t* out, hipStream_t st);
 // bfloat16 (round to nearest even, through float32) of a float64 array: the
 // bits to out and/or the rounded value to rounded (either may be null;
 // rounded may alias in)
