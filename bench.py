@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}
 KERNELS = ["sparse_product", "update_and_reduce", "woodbury_expand", "direction_update", "small"]
 
 
@@ -43,8 +43,7 @@ def log(*a):
 KERNEL_NAMES = {
     "f32": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<float, true, 1>", "k_rows_gemm_f32<float, true, 2>",
             "k_pcg_hupdate<float, float>"],
-    "bf16a": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<unsigned short, true, 1>",
-              "k_rows_gemm_f32<unsigned short, true, 2>", "k_pcg_hupdate<float, float>"],
+    "bf16a": ["k_spmm_dense<float, 2>", "k_reduce_bf16<true, 1>", "k_rows_bf16<2>", "k_pcg_hupdate<float, float>"],
     "f64": ["k_spmm_dense<double, 2>", "k_reduce_gemm_f64<true, 1>",
             "k_rows_gemm_f64<true, 2, 3>", "k_pcg_hupdate<double, double>"],
 }
@@ -150,7 +149,9 @@ def run_mode(F, dev, w, precision, steps, warmup, tol, torch, rr_period=20):
 
 def roofline(res, n, m, tp, precision):
     """precision: "f64", "f32" (float32 operator) or "bf16a" (float32
-    operator with A read in bfloat16 and widened to float32 for the MFMA)."""
+    operator whose low-rank passes read A in bfloat16 and run on the
+    bfloat16 MFMA; their peak is the bfloat16 one, the other kernels'
+    the float32 one)."""
     b = 8 if precision == "f64" else 4
     ba = 2 if precision == "bf16a" else b
     avg = [res["kernel_ms"][k] / max(res["kernel_launches"][k], 1) for k in range(5)]
@@ -159,7 +160,7 @@ def roofline(res, n, m, tp, precision):
     t_s = avg[dom] / 1000.0
     gbs = byt / t_s / 1e9
     tfl = flop / t_s / 1e12
-    peak_t = PEAK_TFLOPS["f64" if precision == "f64" else "f32"]
+    peak_t = PEAK_TFLOPS["f64" if precision == "f64" else ("bf16" if precision == "bf16a" and dom in (1, 2) else "f32")]
     t_hbm = byt / (HBM_PEAK_GBS * 1e9)
     t_cmp = flop / (peak_t * 1e12)
     if t_cmp > t_hbm:
@@ -215,7 +216,7 @@ def main():
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--m", type=int, default=500)
     ap.add_argument("--probes", type=int, default=50)
-    ap.add_argument("--modes", default="fp64,mixed",
+    ap.add_argument("--modes", default="fp64,mixed,bf16a",
                     help="comma list of fp64, mixed (float32 operator), bf16a (float32 operator, bfloat16 A)")
     ap.add_argument("--rr-period", type=int, default=20,
                     help="mixed modes: float64 residual replacement every this many iterations (0 = never)")
