@@ -202,6 +202,13 @@ struct fsa_ctx {
   Buf<double> hist;
   Buf<double> slq_scratch, results;
   const double* lanczos_weight = nullptr;  // quadrature weights of the last solve (in colbuf)
+  // The derivative factor and values (backward) depend on theta only, so
+  // fsa_nll_grad builds them on a second, non-blocking stream (default
+  // priority) while the solve runs: deriv_state 0 = not built for this
+  // theta, 1 = enqueued on st2 (ev_deriv marks its end), 2 = ready on st.
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_ready = nullptr, ev_deriv = nullptr;
+  int deriv_state = 0;
   // gradient
   Buf<double> F, dvals, Xb, SX, DX, tmp, dSm, Ework;
   Scratch scr;
@@ -234,7 +241,11 @@ static fsa_status check_theta(const fsa_theta* th) {
 }
 
 // Sigma_m, L_m, whitened factor, residual values, D_s, FITC capacitance.
+static fsa_status settle_derivative(fsa_ctx* c);
+
 static fsa_status build_values(fsa_ctx* c) {
+  FSA_TRY(settle_derivative(c));  // nothing may still read A, L_m or F
+  c->deriv_state = 0;
   hipStream_t st = c->st;
   const int mp = c->mp;
   FSA_TRY(dense_sigma_m(c->ind.p, c->m, mp, c->th, c->opt.sigma_m_jitter, false, c->Sm.p, st));
@@ -438,6 +449,12 @@ fsa_status fsa_build(const double* locs, int64_t n, int32_t d, const double* y, 
 void fsa_destroy(fsa_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->st);
+  if (c->st2) {
+    (void)hipStreamSynchronize(c->st2);
+    (void)hipEventDestroy(c->ev_ready);
+    (void)hipEventDestroy(c->ev_deriv);
+    (void)hipStreamDestroy(c->st2);
+  }
   blas_release(c->blas);
   delete c;  // Buf members return their blocks to the pool
 }
@@ -617,8 +634,7 @@ static fsa_status apply_sigma(fsa_ctx* c, const double* X, double* Y, int ncols,
 }
 
 // F = dA - E A / 2 (whitened rho-derivative factor) and the derivative values.
-static fsa_status build_derivative(fsa_ctx* c) {
-  hipStream_t st = c->st;
+static fsa_status build_derivative(fsa_ctx* c, hipStream_t st) {
   const int mp = c->mp;
   size_t mm = (size_t)mp * mp;
   FSA_TRY(c->dSm.alloc(mm));
@@ -656,12 +672,48 @@ static fsa_status apply_drho(fsa_ctx* c, const double* X, double* Y, int ncols, 
   return FSA_OK;
 }
 
+// Wait (on the host) for derivative work still enqueued on the side stream.
+static fsa_status settle_derivative(fsa_ctx* c) {
+  if (c->deriv_state == 1) {
+    FSA_HIP(hipEventSynchronize(c->ev_deriv));
+    c->deriv_state = 2;
+  }
+  return FSA_OK;
+}
+
+// Enqueue the derivative build on the side stream behind everything on st.
+static fsa_status launch_derivative_async(fsa_ctx* c) {
+  if (!c->st2) {
+    FSA_HIP(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
+    FSA_HIP(hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming));
+    FSA_HIP(hipEventCreateWithFlags(&c->ev_deriv, hipEventDisableTiming));
+  }
+  FSA_HIP(hipEventRecord(c->ev_ready, c->st));
+  FSA_HIP(hipStreamWaitEvent(c->st2, c->ev_ready, 0));
+  FSA_TRY(build_derivative(c, c->st2));
+  FSA_HIP(hipEventRecord(c->ev_deriv, c->st2));
+  c->deriv_state = 1;
+  return FSA_OK;
+}
+
+// Make the derivative factor and values available to work on st.
+static fsa_status ensure_derivative(fsa_ctx* c) {
+  if (c->deriv_state == 1) {
+    FSA_HIP(hipStreamWaitEvent(c->st, c->ev_deriv, 0));
+    c->deriv_state = 2;
+  } else if (c->deriv_state == 0) {
+    FSA_TRY(build_derivative(c, c->st));
+    c->deriv_state = 2;
+  }
+  return FSA_OK;
+}
+
 static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   hipStream_t st = c->st;
   const int64_t n = c->n;
   const int tp = c->tp, ld = c->ld;
   size_t blk = (size_t)n * ld;
-  FSA_TRY(build_derivative(c));
+  FSA_TRY(ensure_derivative(c));
   FSA_TRY(c->SX.alloc(blk));
   FSA_TRY(c->DX.alloc(blk));
   FSA_TRY(apply_sigma(c, c->Xb.p, c->SX.p, tp, ld));
@@ -918,6 +970,7 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
     }
   }
   double t_build = now_ms();
+  if (grad && c->deriv_state == 0) FSA_TRY(launch_derivative_async(c));
   // probe block [y, z_1 .. z_t]
   FSA_TRY(c->B.alloc((size_t)c->n * c->ld));
   FSA_TRY(c->Emat.alloc((size_t)c->mp * c->ldw));
@@ -1037,7 +1090,7 @@ fsa_status fsa_apply(fsa_ctx* c, int32_t which, const double* X, double* Y, int3
       FSA_TRY(scal_block(ys.p, ld, n, ncols, 1.0 / c->th.s1, st));
       break;
     case FSA_OP_D_RHO:
-      FSA_TRY(build_derivative(c));
+      FSA_TRY(ensure_derivative(c));
       FSA_TRY(apply_drho(c, xs.p, ys.p, ncols, ld));
       break;
     case FSA_OP_P_INV: {
