@@ -541,7 +541,14 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   FSA_TRY(pcg_init<T>(b, op, c->B.p, tol, c->scr, st));
   int flags[2] = {0, 0};
   int it = 0;
-  const int check = 4;
+  // Convergence is read back at checkpoints only (each one drains the
+  // stream).  The next checkpoint comes where the slowest column's
+  // recurrence residual, at the log-linear rate seen since the last one,
+  // reaches the tolerance (between 1 and 8 iterations on): few drains while
+  // far from convergence, and no idle iterations once every column is done.
+  std::vector<double> rr_h(tp), bn_h(tp);
+  int next_check = 4, prev_it = 0;
+  double prev_res = -1.0;
   for (it = 0; it < max_iter; ++it) {
     FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
     if constexpr (sizeof(T) == 4) {
@@ -549,14 +556,28 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
         FSA_TRY(pcg_replace_residual_f32(reinterpret_cast<PcgBlock<float>&>(b), op64,
                                          reinterpret_cast<const OpDesc<float>&>(op), c->B.p, c->scr, st));
     }
-    if (!fixed && ((it + 1) % check == 0 || it + 1 == max_iter)) {
+    if (!fixed && (it + 1 == next_check || it + 1 == max_iter)) {
       FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      FSA_HIP(hipMemcpyAsync(rr_h.data(), b.rr, tp * sizeof(double), hipMemcpyDeviceToHost, st));
+      FSA_HIP(hipMemcpyAsync(bn_h.data(), b.bn2, tp * sizeof(double), hipMemcpyDeviceToHost, st));
       FSA_HIP(hipStreamSynchronize(st));
       if (flags[1]) break;
       if (flags[0] == 0) {
         ++it;
         break;
       }
+      double worst = 0.0;
+      for (int k = 0; k < tp; ++k)
+        if (bn_h[k] > 0.0) worst = std::max(worst, std::sqrt(std::max(rr_h[k], 0.0) / bn_h[k]));
+      int step = 4;
+      if (prev_res > 0.0 && worst > 0.0 && worst < prev_res && tol > 0.0) {
+        const double rate = std::log(worst / prev_res) / (double)(it + 1 - prev_it);  // < 0
+        const double remain = std::log(tol / worst) / rate;
+        step = (int)std::min(8.0, std::max(1.0, std::floor(remain)));
+      }
+      prev_res = worst;
+      prev_it = it + 1;
+      next_check = it + 1 + step;
     }
   }
   if constexpr (sizeof(T) == 4) FSA_TRY(pcg_fold_u(reinterpret_cast<PcgBlock<float>&>(b), st));
