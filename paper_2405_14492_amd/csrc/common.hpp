@@ -126,16 +126,46 @@ const char* get_error();
   } while (0)
 
 // ---------------------------------------------------------------- memory pool
-// Process-wide caching allocator: blocks released by one context are reused
-// by the next allocation of the same rounded size, so rebuilding a context
-// of the same shape performs no hipMalloc.
+// Process-wide, stream-ordered caching allocator: a released block is
+// reused by the next allocation of the same rounded size, so rebuilding a
+// context of the same shape performs no hipMalloc.  A release records an
+// event on the calling thread's current stream (set by PoolStream at each
+// entry point); an allocation from another stream makes that stream wait
+// for the event, so a block is never handed to new work while earlier work
+// that used it can still run.
 void* pool_alloc(size_t bytes);
 void pool_free(void* p);
+hipStream_t pool_stream();
+void pool_set_stream(hipStream_t st);
+struct PoolStream {  // scope guard: the current stream of this thread
+  hipStream_t prev;
+  explicit PoolStream(hipStream_t st) : prev(pool_stream()) { pool_set_stream(st); }
+  ~PoolStream() { pool_set_stream(prev); }
+  PoolStream(const PoolStream&) = delete;
+  PoolStream& operator=(const PoolStream&) = delete;
+};
 
+// Device buffer owned by its holder: released to the pool when it is
+// reallocated, released explicitly, or destroyed.
 template <typename T>
 struct Buf {
   T* p = nullptr;
   size_t count = 0;
+  Buf() = default;
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept : p(o.p), count(o.count) { o.p = nullptr; o.count = 0; }
+  Buf& operator=(Buf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      count = o.count;
+      o.p = nullptr;
+      o.count = 0;
+    }
+    return *this;
+  }
+  ~Buf() { release(); }
   fsa_status alloc(size_t n) {
     release();
     if (n == 0) n = 1;

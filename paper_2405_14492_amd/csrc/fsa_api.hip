@@ -27,14 +27,33 @@ const char* get_error() { return g_err; }
 
 // ---------------------------------------------------------------- pool
 namespace {
+struct FreeBlock {
+  void* p;
+  hipStream_t st;  // stream current when the block was released
+  hipEvent_t ev;   // recorded on st at the release
+};
 std::mutex g_pool_mu;
-std::multimap<size_t, void*> g_free;   // rounded size -> block
-std::map<void*, size_t> g_live;        // block -> rounded size
+std::multimap<size_t, FreeBlock> g_free;  // rounded size -> block
+std::map<void*, size_t> g_live;           // block -> rounded size
+std::vector<hipEvent_t> g_events;         // idle events
+thread_local hipStream_t t_stream = nullptr;
 size_t pool_round(size_t b) {
   const size_t g = b < (1u << 20) ? 4096 : (size_t(2) << 20);
   return (b + g - 1) / g * g;
 }
+// with g_pool_mu held
+void release_cached_locked() {
+  for (auto& kv : g_free) {
+    (void)hipEventSynchronize(kv.second.ev);
+    (void)hipFree(kv.second.p);
+    g_events.push_back(kv.second.ev);
+  }
+  g_free.clear();
+}
 }  // namespace
+
+hipStream_t pool_stream() { return t_stream; }
+void pool_set_stream(hipStream_t st) { t_stream = st; }
 
 void* pool_alloc(size_t bytes) {
   size_t r = pool_round(bytes);
@@ -42,10 +61,12 @@ void* pool_alloc(size_t bytes) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     auto it = g_free.find(r);
     if (it != g_free.end()) {
-      void* p = it->second;
+      FreeBlock fb = it->second;
       g_free.erase(it);
-      g_live[p] = r;
-      return p;
+      if (fb.st != t_stream) (void)hipStreamWaitEvent(t_stream, fb.ev, 0);
+      g_events.push_back(fb.ev);
+      g_live[fb.p] = r;
+      return fb.p;
     }
   }
   void* p = nullptr;
@@ -53,8 +74,7 @@ void* pool_alloc(size_t bytes) {
     (void)hipGetLastError();
     // release cached blocks and retry once
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    for (auto& kv : g_free) (void)hipFree(kv.second);
-    g_free.clear();
+    release_cached_locked();
     if (hipMalloc(&p, r) != hipSuccess) {
       (void)hipGetLastError();
       return nullptr;
@@ -70,14 +90,28 @@ void pool_free(void* p) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
   auto it = g_live.find(p);
   if (it == g_live.end()) return;
-  g_free.emplace(it->second, p);
+  hipEvent_t ev = nullptr;
+  if (!g_events.empty()) {
+    ev = g_events.back();
+    g_events.pop_back();
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    // no event: make the block safe to reuse anywhere by draining its stream
+    (void)hipStreamSynchronize(t_stream);
+    ev = nullptr;
+  }
+  if (ev) (void)hipEventRecord(ev, t_stream);
+  if (ev) {
+    g_free.emplace(it->second, FreeBlock{p, t_stream, ev});
+  } else {
+    (void)hipFree(p);
+  }
   g_live.erase(it);
 }
 
 void pool_trim() {
   std::lock_guard<std::mutex> lk(g_pool_mu);
-  for (auto& kv : g_free) (void)hipFree(kv.second);
-  g_free.clear();
+  release_cached_locked();
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -417,6 +451,7 @@ fsa_status fsa_build_dev(const double* locs, int64_t n, int32_t d, const double*
   if (!out || !locs || !y || !inducing) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
   *out = nullptr;
   FSA_TRY(validate_build(n, d, theta, m, gamma, opt));
+  PoolStream ps(opt ? as_stream(opt->hip_stream) : nullptr);
   fsa_ctx* c = nullptr;
   FSA_TRY(new_ctx(n, m, theta, gamma, opt, &c));
   fsa_status s = build_core(c, locs, y, inducing);
@@ -434,6 +469,7 @@ fsa_status fsa_build(const double* locs, int64_t n, int32_t d, const double* y, 
   *out = nullptr;
   FSA_TRY(validate_build(n, d, theta, m, gamma, opt));
   hipStream_t st = opt ? as_stream(opt->hip_stream) : nullptr;
+  PoolStream ps(st);
   Buf<double> dl, dy, di;
   FSA_TRY(dl.alloc(2 * (size_t)n));
   FSA_TRY(dy.alloc(n));
@@ -448,6 +484,7 @@ fsa_status fsa_build(const double* locs, int64_t n, int32_t d, const double* y, 
 
 void fsa_destroy(fsa_ctx* c) {
   if (!c) return;
+  PoolStream ps(c->st);
   (void)hipStreamSynchronize(c->st);
   if (c->st2) {
     (void)hipStreamSynchronize(c->st2);
@@ -979,6 +1016,7 @@ extern "C" {
 
 fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double* grad, fsa_stats* st_out) {
   if (!c || !nll) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(c->st);
   double t0 = now_ms();
   hipStream_t st = c->st;
   memset(&c->stats, 0, sizeof(c->stats));
@@ -1034,6 +1072,7 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
 
 fsa_status fsa_grad(fsa_ctx* c, double* grad, fsa_stats* st_out) {
   if (!c || !grad) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(c->st);
   if (!c->solved) { set_error("fsa_grad needs a preceding fsa_nll_grad on this context"); return FSA_ERR_INVALID_ARG; }
   double t0 = now_ms();
   double parts6[6];
@@ -1049,11 +1088,13 @@ fsa_status fsa_grad(fsa_ctx* c, double* grad, fsa_stats* st_out) {
 
 fsa_status fsa_export_csr(fsa_ctx* c, int64_t* row_ptr, int32_t* col_idx, double* vals) {
   if (!c || !row_ptr || !col_idx) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(c->st);
   return export_csr(c->csr, c->grid, c->grid, c->vals.p, row_ptr, col_idx, vals, c->st);
 }
 
 fsa_status fsa_export_diag(fsa_ctx* c, double* D, double* logdet_P) {
   if (!c) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(c->st);
   if (D) {
     Buf<double> tmp;
     FSA_TRY(tmp.alloc(c->n));
@@ -1068,6 +1109,7 @@ fsa_status fsa_export_diag(fsa_ctx* c, double* D, double* logdet_P) {
 fsa_status fsa_export_lanczos(fsa_ctx* c, int32_t* iters, double* alpha, double* beta, double* weight,
                               double* slq) {
   if (!c) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(c->st);
   if (!c->solved || !c->lanczos_weight) { set_error("no likelihood solve to export"); return FSA_ERR_INVALID_ARG; }
   const int tp = c->tp;
   const int L = c->opt.fixed_iter > 0 ? c->opt.fixed_iter : c->opt.max_iter;
@@ -1086,6 +1128,7 @@ fsa_status fsa_export_lanczos(fsa_ctx* c, int32_t* iters, double* alpha, double*
 
 fsa_status fsa_apply(fsa_ctx* c, int32_t which, const double* X, double* Y, int32_t ncols) {
   if (!c || !Y || ncols < 1 || (which != FSA_OP_PROBES && !X)) { set_error("bad argument"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(c->st);
   hipStream_t st = c->st;
   const int64_t n = c->n;
   int ld = (int)round_up(ncols, 4);
@@ -1153,6 +1196,7 @@ fsa_status fsa_apply(fsa_ctx* c, int32_t which, const double* X, double* Y, int3
 fsa_status fsa_predict_var(fsa_ctx* c, const double* pred_locs, int64_t n_p, int32_t num_samples, double* var_out,
                            double* mean_out, fsa_stats* st_out) {
   if (!c || !pred_locs || !var_out) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(c->st);
   if (n_p < 1 || n_p > (int64_t)INT32_MAX / 2) { set_error("n_p out of range"); return FSA_ERR_INVALID_ARG; }
   if (num_samples < 1 || num_samples > 4096) { set_error("num_samples must be in [1, 4096]"); return FSA_ERR_INVALID_ARG; }
   if (mean_out && !c->solved) { set_error("the predictive mean needs a preceding fsa_nll_grad"); return FSA_ERR_INVALID_ARG; }

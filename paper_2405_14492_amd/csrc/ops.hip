@@ -6,6 +6,8 @@
 #include "gemm.hpp"
 #include "ops.hpp"
 
+#include <mutex>
+
 namespace fsa {
 
 constexpr int RT_ROWS = 2;  // row tiles per wave in k_rows_gemm
@@ -75,6 +77,32 @@ struct ProbeEpi {
     return 0.0;
   }
 };
+
+namespace {
+std::mutex g_tev_mu;
+std::vector<hipEvent_t> g_tev;
+}  // namespace
+hipEvent_t timer_event_get() {
+  {
+    std::lock_guard<std::mutex> lk(g_tev_mu);
+    if (!g_tev.empty()) {
+      hipEvent_t e = g_tev.back();
+      g_tev.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+void timer_event_put(hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> lk(g_tev_mu);
+  g_tev.push_back(e);
+}
 
 struct ValFn {
   Theta th;

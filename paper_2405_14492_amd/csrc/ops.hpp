@@ -15,6 +15,10 @@ struct Scratch {
   Buf<double> dot1;  // first-stage column sums of many partials
 };
 
+// Timing events are kept in a process-wide free list across contexts.
+hipEvent_t timer_event_get();  // nullptr if none can be created
+void timer_event_put(hipEvent_t e);
+
 // HIP-event timing of kernel classes on one stream (enabled per context).
 struct KernelTimer {
   static constexpr int NCLS = 5;
@@ -27,8 +31,8 @@ struct KernelTimer {
     if (!on) return -1;
     if (used + 2 > pool.size()) {
       for (int k = 0; k < 256; ++k) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
+        hipEvent_t e = timer_event_get();
+        if (!e) return -1;
         pool.push_back(e);
       }
     }
@@ -56,7 +60,7 @@ struct KernelTimer {
     reset();
   }
   ~KernelTimer() {
-    for (auto e : pool) (void)hipEventDestroy(e);
+    for (auto e : pool) timer_event_put(e);
   }
 };
 enum { KT_SPMM = 0, KT_PASS1 = 1, KT_PASS2 = 2, KT_UPDATE = 3, KT_SMALL = 4 };

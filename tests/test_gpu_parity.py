@@ -313,3 +313,24 @@ def test_bf16a_rejects_rounded_model_with_negative_residual_diagonal(F):
     # float32 mixed precision keeps the unrounded model and runs
     with F.FSA(locs, y, theta, ind, gamma, num_probes=4, seed=5, tol=1e-6, precision=F.MIXED_FP32) as f:
         f.nll_grad()
+
+
+def test_contexts_return_device_memory(F):
+    """Every context's device buffers and every temporary go back to the
+    library's pool: after build / solve / gradient / destroy cycles and a
+    pool trim, the device has the free memory it had before."""
+    import torch
+    from paper_2405_14492_amd import fsa as Fm
+    locs, y, theta, ind, gamma = case(n=30000, m=200, kind=O.MATERN32, rho=0.05, s2=0.1, n_gamma=30, seed=4)
+    Fm.lib().fsa_pool_trim()
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    for prec in (F.FP64, F.MIXED_FP32, F.MIXED_BF16A, F.FP64):
+        with F.FSA(locs, y, theta, ind, gamma, num_probes=4, seed=1, tol=1e-6, precision=prec) as f:
+            f.nll_grad()
+            f.predict_var(locs[:500], 4)
+    Fm.lib().fsa_pool_trim()
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    say("device free before", free0 >> 20, "MiB, after", free1 >> 20, "MiB")
+    assert free0 - free1 < (64 << 20)
