@@ -277,6 +277,23 @@ def test_bf16a_matches_oracle_of_rounded_model(F, name):
     assert 0.0 < st["rel_res_max"] < 1e-6
 
 
+def test_bf16a_wide_block_matches_oracle_of_rounded_model(F):
+    """60 probes: 61 columns exceed the 52 the bfloat16-MFMA expansion holds
+    in LDS, so that pass widens A to float32 while the residual pass stays
+    on the bfloat16 MFMA; both against the rounded model's oracle with
+    fixed iterations."""
+    locs, y, theta, ind, gamma = case(**CASES["ragged_n333_m7"])
+    mdl = DF.RoundedFSA(locs, ind, theta, gamma, smn_T=DF.bf16_cross_covariance(locs, ind, theta))
+    ref = O.nll_grad(mdl, y, 60, 9, fixed_iter=12)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=60, seed=9, fixed_iter=12, precision=F.MIXED_BF16A,
+               rr_period=5) as f:
+        nll, grad, st = f.nll_grad()
+    gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
+    say("bf16a t=60 nll rel", abs(nll - ref["nll"]) / abs(ref["nll"]), "grad/scale", np.abs(grad - ref["grad"]) / gscale)
+    assert abs(nll - ref["nll"]) <= 1e-4 * abs(ref["nll"])
+    assert np.all(np.abs(grad - ref["grad"]) <= 1e-4 * gscale)
+
+
 def test_bf16a_predictive_variances_match_oracle_of_rounded_model(F):
     locs, y, theta, ind, gamma = case(**CASES["m32_n1500_m100"])
     pred = G.uniform_locations(300, 901)
