@@ -79,6 +79,9 @@ typedef enum { FSA_COV_EXPONENTIAL = 0, FSA_COV_MATERN32 = 1 } fsa_cov;
  *     dSigma_m/drho with the rounded A. */
 typedef enum { FSA_FP64 = 0, FSA_MIXED_FP32 = 1, FSA_MIXED_BF16A = 2 } fsa_precision;
 
+/* fsa_options.profile: all five kernel classes of fsa_stats.kernel_ms */
+#define FSA_PROFILE_ALL 0x1f
+
 typedef struct {
   int32_t cov;      /* fsa_cov */
   double sigma1_sq; /* marginal variance sigma1^2 > 0 */
@@ -95,7 +98,8 @@ typedef struct {
   int32_t precision;     /* fsa_precision */
   int32_t rr_period;     /* mixed precision: float64 residual replacement period (0 = never) */
   int32_t slq_weight_n;  /* 0: SLQ weight z^T P^{-1} z; 1: the weight n of Section 3.1 */
-  int32_t profile;       /* 1: time every PCG kernel launch with HIP events (fsa_stats.kernel_ms) */
+  int32_t profile;       /* bit k set: time every PCG launch of kernel class k (fsa_stats.kernel_ms[k]) with
+                            a pair of HIP events on the stream (about 3 us each); FSA_PROFILE_ALL times all */
   double sigma_m_jitter; /* adds jitter * sigma1^2 to the diagonal of Sigma_m (default 0) */
   void* hip_stream;      /* hipStream_t to run on, or NULL for the default stream */
 } fsa_options;
@@ -109,7 +113,10 @@ typedef struct {
   double logdet;                /* SLQ estimate of log det Sigma~_dagger */
   double logdet_P;              /* log det of the FITC preconditioner (Sylvester) */
   double quad;                  /* y^T Sigma~_dagger^{-1} y */
-  double ms_build, ms_pcg, ms_backward, ms_total;
+  double ms_build;              /* host wall time of a rebuild for a new theta inside the call (0 if none) */
+  double ms_pcg;                /* the block PCG solve with its SLQ quadrature and quadratic term */
+  double ms_backward;           /* the gradient after the solve (the derivative build overlaps the solve) */
+  double ms_total;
   int64_t nnz;                  /* nonzeros of the tapered residual */
   /* with options.profile: summed device time and launch count of the PCG
    * kernels: [0] sparse product Sigma~_s H, [1] fused update + A D^{-1} r
@@ -214,7 +221,9 @@ enum {
  * row-major, in the caller's point order. */
 fsa_status fsa_apply(fsa_ctx* ctx, int32_t which, const double* X, double* Y, int32_t ncols);
 
-/* Release every cached device block of the process-wide pool. */
+/* Release every cached device block of the process-wide pool and every
+ * cached pinned host block of the solvers' readbacks.  Blocks held by live
+ * contexts are not affected. */
 void fsa_pool_trim(void);
 
 #ifdef __cplusplus

@@ -201,6 +201,24 @@ __global__ void k_grad_block(int64_t n, int ncols, int64_t ld, const double* __r
   else X[o] = q0_f32 ? (double)((const float*)Q0)[o] : ((const double*)Q0)[o];
 }
 
+// The solver's small per-solve readback in one block: flags[2] (int), then
+// rr[tp], bn2[tp] (double), then iters[tp] (int, if given).
+__global__ void k_pack_status(const int* __restrict__ flags, const double* __restrict__ rr,
+                              const double* __restrict__ bn2, const int* __restrict__ iters, int tp,
+                              char* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int* fo = reinterpret_cast<int*>(out);
+  double* ro = reinterpret_cast<double*>(out + 8);
+  double* bo = ro + tp;
+  int* io = reinterpret_cast<int*>(bo + tp);
+  if (i < 2) fo[i] = flags[i];
+  if (i < tp) {
+    ro[i] = rr[i];
+    bo[i] = bn2[i];
+    if (iters) io[i] = iters[i];
+  }
+}
+
 __global__ void k_fill_weight_n(double* w, int ncols, double n) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < ncols) w[c] = n;
@@ -242,7 +260,17 @@ struct fsa_ctx {
   // theta, 1 = enqueued on st2 (ev_deriv marks its end), 2 = ready on st.
   hipStream_t st2 = nullptr;
   hipEvent_t ev_ready = nullptr, ev_deriv = nullptr;
+  // the quadrature of a solve also runs on st2, beside the gradient: ev_solve
+  // marks the solve's end on st, ev_slq the quadrature's end on st2
+  hipEvent_t ev_solve = nullptr, ev_slq = nullptr;
+  bool slq_pending = false;
+  // small device-to-host readbacks: a device staging block and its pinned
+  // host mirror (one asynchronous copy each)
+  Buf<char> dstage;
+  char* hstage = nullptr;
+  size_t hstage_bytes = 0;
   int deriv_state = 0;
+  bool timer_pending = false;  // the last solve's kernel events are not yet summed
   // gradient
   Buf<double> F, dvals, Xb, SX, DX, tmp, dSm, Ework;
   Scratch scr;
@@ -441,9 +469,46 @@ void fsa_default_options(fsa_options* o) {
 
 const char* fsa_last_error(void) { return get_error(); }
 
+// Pinned host blocks for the small readbacks of a solve.  A context holds
+// one while it lives and returns it at destroy, after draining its streams,
+// so a block on the free list has no copy in flight.
+static std::mutex g_pinned_mu;
+static std::vector<std::pair<char*, size_t>> g_pinned;
+
+static char* pinned_get(size_t bytes, size_t* got) {
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    for (size_t i = 0; i < g_pinned.size(); ++i)
+      if (g_pinned[i].second >= bytes) {
+        char* p = g_pinned[i].first;
+        *got = g_pinned[i].second;
+        g_pinned.erase(g_pinned.begin() + (ptrdiff_t)i);
+        return p;
+      }
+  }
+  const size_t sz = (bytes + 4095) & ~(size_t)4095;
+  char* p = nullptr;
+  if (hipHostMalloc((void**)&p, sz, hipHostMallocDefault) != hipSuccess) return nullptr;
+  *got = sz;
+  return p;
+}
+
+static void pinned_put(char* p, size_t bytes) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  g_pinned.emplace_back(p, bytes);
+}
+
+static void pinned_trim() {
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  for (auto& b : g_pinned) (void)hipHostFree(b.first);
+  g_pinned.clear();
+}
+
 void fsa_pool_trim(void) {
   pool_trim();
   blas_trim();
+  pinned_trim();
 }
 
 fsa_status fsa_build_dev(const double* locs, int64_t n, int32_t d, const double* y, const fsa_theta* theta,
@@ -490,8 +555,11 @@ void fsa_destroy(fsa_ctx* c) {
     (void)hipStreamSynchronize(c->st2);
     (void)hipEventDestroy(c->ev_ready);
     (void)hipEventDestroy(c->ev_deriv);
+    (void)hipEventDestroy(c->ev_solve);
+    (void)hipEventDestroy(c->ev_slq);
     (void)hipStreamDestroy(c->st2);
   }
+  pinned_put(c->hstage, c->hstage_bytes);
   blas_release(c->blas);
   delete c;  // Buf members return their blocks to the pool
 }
@@ -501,6 +569,61 @@ int64_t fsa_nnz(const fsa_ctx* c) { return c ? c->csr.nnz : -1; }
 }  // extern "C"
 
 // ---------------------------------------------------------------- PCG driver
+// The side stream (non-blocking, default priority) and its events.
+static fsa_status side_stream(fsa_ctx* c) {
+  if (!c->st2) {
+    FSA_HIP(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
+    FSA_HIP(hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming));
+    FSA_HIP(hipEventCreateWithFlags(&c->ev_deriv, hipEventDisableTiming));
+    FSA_HIP(hipEventCreateWithFlags(&c->ev_solve, hipEventDisableTiming));
+    FSA_HIP(hipEventCreateWithFlags(&c->ev_slq, hipEventDisableTiming));
+  }
+  return FSA_OK;
+}
+
+// Make the last solve's quadrature (results: slq, fin) visible to work on st.
+static fsa_status join_slq(fsa_ctx* c) {
+  if (c->slq_pending) {
+    FSA_HIP(hipStreamWaitEvent(c->st, c->ev_slq, 0));
+    c->slq_pending = false;
+  }
+  return FSA_OK;
+}
+
+// Stage the solver status (flags, rr, bn2 and, if given, iters) for the host:
+// packed on the device and copied to pinned host memory in one asynchronous
+// copy on st; the caller synchronises st before reading it.
+struct HostStatus {
+  const int* flags;
+  const double* rr;
+  const double* bn;
+  const int* iters;
+};
+static fsa_status stage_status(fsa_ctx* c, const int* flags, const double* rr, const double* bn2, const int* iters,
+                               int tp, HostStatus* hs) {
+  const size_t bytes = 8 + 16 * (size_t)tp + 4 * (size_t)tp;
+  if (c->hstage_bytes < bytes) {
+    FSA_HIP(hipStreamSynchronize(c->st));  // no copy into the old block is in flight
+    pinned_put(c->hstage, c->hstage_bytes);
+    c->hstage = pinned_get(bytes, &c->hstage_bytes);
+    if (!c->hstage) {
+      c->hstage_bytes = 0;
+      set_error("hipHostMalloc of %zu bytes failed", bytes);
+      return FSA_ERR_OOM;
+    }
+  }
+  FSA_TRY(c->dstage.alloc(bytes));
+  hipLaunchKernelGGL(k_pack_status, dim3(ceil_div(std::max(tp, 2), 256)), dim3(256), 0, c->st, flags, rr, bn2, iters,
+                     tp, c->dstage.p);
+  FSA_HIP(hipGetLastError());
+  FSA_HIP(hipMemcpyAsync(c->hstage, c->dstage.p, bytes, hipMemcpyDeviceToHost, c->st));
+  hs->flags = reinterpret_cast<const int*>(c->hstage);
+  hs->rr = reinterpret_cast<const double*>(c->hstage + 8);
+  hs->bn = hs->rr + tp;
+  hs->iters = iters ? reinterpret_cast<const int*>(hs->bn + tp) : nullptr;
+  return FSA_OK;
+}
+
 template <typename T>
 static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   hipStream_t st = c->st;
@@ -571,8 +694,11 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   }
   const double tol = c->opt.cg_rel_tol;
   const int fixed = c->opt.fixed_iter > 0 ? 1 : 0;
-  c->timer.on = c->opt.profile != 0;
+  FSA_TRY(join_slq(c));  // the last solve's quadrature reads the buffers reused here
+  c->timer.mask = (unsigned)c->opt.profile & ((1u << KernelTimer::NCLS) - 1u);
+  c->timer.on = c->timer.mask != 0;
   c->timer.reset();
+  c->timer_pending = false;
   b.timer = c->timer.on ? &c->timer : nullptr;
   double t0 = now_ms();
   FSA_TRY(pcg_init<T>(b, op, c->B.p, tol, c->scr, st));
@@ -583,7 +709,6 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   // recurrence residual, at the log-linear rate seen since the last one,
   // reaches the tolerance (between 1 and 8 iterations on): few drains while
   // far from convergence, and no idle iterations once every column is done.
-  std::vector<double> rr_h(tp), bn_h(tp);
   int next_check = 4, prev_it = 0;
   double prev_res = -1.0;
   for (it = 0; it < max_iter; ++it) {
@@ -594,18 +719,17 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
                                          reinterpret_cast<const OpDesc<float>&>(op), c->B.p, c->scr, st));
     }
     if (!fixed && (it + 1 == next_check || it + 1 == max_iter)) {
-      FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-      FSA_HIP(hipMemcpyAsync(rr_h.data(), b.rr, tp * sizeof(double), hipMemcpyDeviceToHost, st));
-      FSA_HIP(hipMemcpyAsync(bn_h.data(), b.bn2, tp * sizeof(double), hipMemcpyDeviceToHost, st));
+      HostStatus hs;
+      FSA_TRY(stage_status(c, b.flags, b.rr, b.bn2, nullptr, tp, &hs));
       FSA_HIP(hipStreamSynchronize(st));
-      if (flags[1]) break;
-      if (flags[0] == 0) {
+      if (hs.flags[1]) break;
+      if (hs.flags[0] == 0) {
         ++it;
         break;
       }
       double worst = 0.0;
       for (int k = 0; k < tp; ++k)
-        if (bn_h[k] > 0.0) worst = std::max(worst, std::sqrt(std::max(rr_h[k], 0.0) / bn_h[k]));
+        if (hs.bn[k] > 0.0) worst = std::max(worst, std::sqrt(std::max(hs.rr[k], 0.0) / hs.bn[k]));
       int step = 4;
       if (prev_res > 0.0 && worst > 0.0 && worst < prev_res && tol > 0.0) {
         const double rate = std::log(worst / prev_res) / (double)(it + 1 - prev_it);  // < 0
@@ -618,13 +742,47 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
     }
   }
   if constexpr (sizeof(T) == 4) FSA_TRY(pcg_fold_u(reinterpret_cast<PcgBlock<float>&>(b), st));
-  FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  // The quadratic term and the gradient block go in behind the solve on st,
+  // the quadrature and the likelihood on the side stream, where they run
+  // beside the gradient; all of it is enqueued before the host-side
+  // bookkeeping below (on a breakdown it runs on meaningless coefficients
+  // and is discarded).
+  FSA_TRY(c->slq_scratch.alloc((size_t)tp * 3 * max_iter));
+  FSA_TRY(c->results.alloc(4 * (size_t)ldw + 16));
+  double* slq = c->results.p;
+  double* quad = c->results.p + ldw;
+  double* fin = c->results.p + 2 * ldw;
+  const double* weight = b.rz0;
+  if (c->opt.slq_weight_n) {
+    double* wn = c->colbuf.p + 6 * ldw;  // spare per-column slot
+    hipLaunchKernelGGL(k_fill_weight_n, dim3(ceil_div(tp, 64)), dim3(64), 0, st, wn, tp, (double)n);
+    weight = wn;
+  }
+  c->lanczos_weight = weight;
+  FSA_TRY((coldot<double, double>(c->B.p, c->U.p, n, ld, 1, quad, c->scr, st)));
+  FSA_TRY(side_stream(c));
+  FSA_HIP(hipEventRecord(c->ev_solve, st));
+  FSA_HIP(hipStreamWaitEvent(c->st2, c->ev_solve, 0));
+  FSA_TRY(slq_terms(b.alpha_hist, b.beta_hist, b.iters, tp, 1, weight, slq, c->slq_scratch.p, max_iter, c->st2));
+  hipLaunchKernelGGL(k_finalize_nll, dim3(1), dim3(1), 0, c->st2, slq, tp, c->logdet_parts.p, quad, n, fin);
+  FSA_HIP(hipGetLastError());
+  FSA_HIP(hipEventRecord(c->ev_slq, c->st2));
+  c->slq_pending = true;
+  // keep Q0 (P^{-1} z) for the gradient in float64
+  FSA_TRY(c->Xb.alloc(blk));
+  hipLaunchKernelGGL(k_grad_block, dim3(ceil_div((int64_t)n * tp, 256)), dim3(256), 0, st, n, tp, (int64_t)ld, c->U.p,
+                     (const void*)b.Q0, sizeof(T) == 4 ? 1 : 0, c->Xb.p);
+  FSA_HIP(hipGetLastError());
+  // iteration statistics (staged behind the work above)
+  HostStatus hs;
+  FSA_TRY(stage_status(c, b.flags, b.rr, b.bn2, b.iters, tp, &hs));
   FSA_HIP(hipStreamSynchronize(st));
+  const int* iters = hs.iters;
+  const double *rr = hs.rr, *bn = hs.bn;
+  flags[0] = hs.flags[0];
+  flags[1] = hs.flags[1];
   *ms_pcg = now_ms() - t0;
-  if (c->timer.on) c->timer.collect(c->stats.kernel_ms, c->stats.kernel_launches);
-  // iteration statistics
-  std::vector<int> iters(tp);
-  FSA_HIP(hipMemcpy(iters.data(), b.iters, tp * sizeof(int), hipMemcpyDeviceToHost));
+  c->timer_pending = c->timer.on;  // collected while the device runs the next work
   int imin = 1 << 30, imax = 0;
   int64_t tot = 0;
   for (int k = 0; k < tp; ++k) {
@@ -635,41 +793,15 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   c->stats.iters_min = imin;
   c->stats.iters_max = imax;
   c->stats.probe_iters = tot;
-  {
-    std::vector<double> rr(tp), bn(tp);
-    FSA_HIP(hipMemcpy(rr.data(), b.rr, tp * sizeof(double), hipMemcpyDeviceToHost));
-    FSA_HIP(hipMemcpy(bn.data(), b.bn2, tp * sizeof(double), hipMemcpyDeviceToHost));
-    double rmax = 0.0;
-    for (int k = 0; k < tp; ++k)
-      if (bn[k] > 0.0) rmax = std::max(rmax, std::sqrt(std::max(rr[k], 0.0) / bn[k]));
-    c->stats.rel_res_max = rmax;
-  }
+  double rmax = 0.0;
+  for (int k = 0; k < tp; ++k)
+    if (bn[k] > 0.0) rmax = std::max(rmax, std::sqrt(std::max(rr[k], 0.0) / bn[k]));
+  c->stats.rel_res_max = rmax;
   if (flags[1]) {
+    c->lanczos_weight = nullptr;
     set_error("CG breakdown (h^T Sigma h <= 0 or non-finite)");
     return FSA_ERR_BREAKDOWN;
   }
-  // SLQ terms for probe columns
-  FSA_TRY(c->slq_scratch.alloc((size_t)tp * 3 * max_iter));
-  FSA_TRY(c->results.alloc(4 * (size_t)ldw + 16));
-  double* slq = c->results.p;
-  double* quad = c->results.p + ldw;
-  double* fin = c->results.p + 2 * ldw;
-  const double* weight = b.rz0;
-  if (c->opt.slq_weight_n) {
-    hipLaunchKernelGGL(k_fill_weight_n, dim3(ceil_div(tp, 64)), dim3(64), 0, st, b.rr, tp, (double)n);
-    weight = b.rr;
-  }
-  c->lanczos_weight = weight;
-  FSA_TRY(slq_terms(b.alpha_hist, b.beta_hist, b.iters, tp, 1, weight, slq, c->slq_scratch.p, max_iter, st));
-  FSA_TRY((coldot<double, double>(c->B.p, c->U.p, n, ld, 1, quad, c->scr, st)));
-  hipLaunchKernelGGL(k_finalize_nll, dim3(1), dim3(1), 0, st, slq, tp, c->logdet_parts.p, quad, n, fin);
-  FSA_HIP(hipGetLastError());
-  // keep Q0 (P^{-1} z) for the gradient in float64
-  FSA_TRY(c->Xb.alloc(blk));
-  hipLaunchKernelGGL(k_grad_block, dim3(ceil_div((int64_t)n * tp, 256)), dim3(256), 0, st, n, tp, (int64_t)ld, c->U.p,
-                     (const void*)b.Q0, sizeof(T) == 4 ? 1 : 0, c->Xb.p);
-  FSA_HIP(hipGetLastError());
-  FSA_HIP(hipStreamSynchronize(st));
   c->solved = true;
   if (!fixed && flags[0] > 0) {
     set_error("PCG did not converge in %d iterations (%d columns active)", max_iter, flags[0]);
@@ -741,11 +873,7 @@ static fsa_status settle_derivative(fsa_ctx* c) {
 
 // Enqueue the derivative build on the side stream behind everything on st.
 static fsa_status launch_derivative_async(fsa_ctx* c) {
-  if (!c->st2) {
-    FSA_HIP(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
-    FSA_HIP(hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming));
-    FSA_HIP(hipEventCreateWithFlags(&c->ev_deriv, hipEventDisableTiming));
-  }
+  FSA_TRY(side_stream(c));
   FSA_HIP(hipEventRecord(c->ev_ready, c->st));
   FSA_HIP(hipStreamWaitEvent(c->st2, c->ev_ready, 0));
   FSA_TRY(build_derivative(c, c->st2));
@@ -766,6 +894,14 @@ static fsa_status ensure_derivative(fsa_ctx* c) {
   return FSA_OK;
 }
 
+// Sum the solve's per-kernel event times into the stats (the events have
+// completed once the solve was read back).
+static void collect_timer(fsa_ctx* c) {
+  if (!c->timer_pending) return;
+  c->timer.collect(c->stats.kernel_ms, c->stats.kernel_launches);
+  c->timer_pending = false;
+}
+
 static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   hipStream_t st = c->st;
   const int64_t n = c->n;
@@ -776,7 +912,6 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   FSA_TRY(c->DX.alloc(blk));
   FSA_TRY(apply_sigma(c, c->Xb.p, c->SX.p, tp, ld));
   FSA_TRY(apply_drho(c, c->Xb.p, c->DX.p, tp, ld));
-  double* dots = c->results.p + 3 * c->ldw;  // 3 x tp (fits: results has 4 ldw + 16)
   Buf<double> dd;
   FSA_TRY(dd.alloc(3 * (size_t)tp + 9));
   FSA_TRY((coldot<double, double>(c->U.p, c->SX.p, n, ld, tp, dd.p, c->scr, st)));
@@ -785,10 +920,10 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   hipLaunchKernelGGL(k_finalize_grad, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, c->th.s1, c->th.s2,
                      dd.p + 3 * tp);
   FSA_HIP(hipGetLastError());
+  collect_timer(c);  // host work while the gradient kernels run
   double g9[9];
   FSA_HIP(hipMemcpyAsync(g9, dd.p + 3 * tp, sizeof(g9), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
-  (void)dots;
   for (int k = 0; k < 3; ++k) grad[k] = g9[k];
   if (parts6)
     for (int k = 0; k < 6; ++k) parts6[k] = g9[3 + k];
@@ -1040,23 +1175,31 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
   if (c->opt.precision != FSA_FP64) s = run_pcg<float>(c, &ms_pcg);
   else s = run_pcg<double>(c, &ms_pcg);
   if (s != FSA_OK && s != FSA_ERR_NOT_CONVERGED) {
+    FSA_TRY(join_slq(c));
+    collect_timer(c);
     *nll = INFINITY;
     return s;
   }
-  double fin[3];
-  FSA_HIP(hipMemcpyAsync(fin, c->results.p + 2 * c->ldw, sizeof(fin), hipMemcpyDeviceToHost, st));
-  FSA_HIP(hipStreamSynchronize(st));
-  *nll = fin[2];
   double t_b0 = now_ms();
   if (grad) {
     double parts6[6];
     fsa_status gs = run_gradient(c, grad, parts6);
-    if (gs != FSA_OK) return gs;
+    if (gs != FSA_OK) {
+      FSA_TRY(join_slq(c));
+      return gs;
+    }
     for (int k = 0; k < 3; ++k) {
       c->stats.grad_trace[k] = parts6[k];
       c->stats.grad_quad[k] = parts6[3 + k];
     }
   }
+  // the likelihood from the side stream (the quadrature ran beside the gradient)
+  FSA_TRY(join_slq(c));
+  double fin[3];
+  FSA_HIP(hipMemcpyAsync(fin, c->results.p + 2 * c->ldw, sizeof(fin), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  *nll = fin[2];
+  collect_timer(c);
   double t1 = now_ms();
   c->stats.logdet = fin[0];
   c->stats.quad = fin[1];
@@ -1111,6 +1254,7 @@ fsa_status fsa_export_lanczos(fsa_ctx* c, int32_t* iters, double* alpha, double*
   if (!c) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
   PoolStream ps(c->st);
   if (!c->solved || !c->lanczos_weight) { set_error("no likelihood solve to export"); return FSA_ERR_INVALID_ARG; }
+  FSA_TRY(join_slq(c));
   const int tp = c->tp;
   const int L = c->opt.fixed_iter > 0 ? c->opt.fixed_iter : c->opt.max_iter;
   hipStream_t st = c->st;

@@ -869,9 +869,24 @@ struct SpmmShape {
   static constexpr int EPT = 8;                         // entries per thread per batch
 };
 
-__device__ __forceinline__ int64_t xcd_cell(int64_t b, int64_t ncell) {
+// Workgroup b -> cell of a gx-wide grid (ncell = gx * gy, row-major cells).
+// Workgroups are dispatched to the 8 XCDs round-robin; XCD b & 7 takes the
+// (b & 7)-th eighth of a walk over the grid in vertical strips of sw cell
+// columns, each strip row by row.  The 3x3 neighbourhoods of the cells in
+// flight on one XCD then overlap within a few strip rows, so the block rows
+// they share are read from that XCD's L2; only the cell columns bordering a
+// strip are read again by the next strip (traffic (sw + 2) / sw of one
+// pass).  Returns ncell past the end.
+__device__ __forceinline__ int64_t xcd_cell(int64_t b, int64_t ncell, int64_t gx, int sw) {
   const int64_t per = (ncell + 7) >> 3;
-  return (b & 7) * per + (b >> 3);
+  const int64_t j = (b & 7) * per + (b >> 3);
+  if (j >= ncell) return ncell;
+  const int64_t strip = (int64_t)sw * (ncell / gx);  // cells of a full strip
+  const int64_t s = j / strip;                       // every strip before s is full
+  const int64_t rem = j - s * strip;
+  const int64_t wd = min((int64_t)sw, gx - s * sw);
+  const int64_t iy = rem / wd;
+  return iy * gx + s * sw + (rem - iy * wd);
 }
 
 // Epilogue of the sparse product over row-major n x ld blocks.  Modes:
@@ -890,7 +905,7 @@ template <typename T, int EM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 5))) void k_spmm_dense(
     const int64_t* __restrict__ rcs, int64_t ncell, const int64_t* __restrict__ ccs, GridDesc gd,
     const int64_t* __restrict__ rp, const int* __restrict__ key, const T* __restrict__ val, const T* __restrict__ X,
-    int ldx, int ncols, SpmmEpi<T> epi, double* __restrict__ dot_part, int ld_dot) {
+    int ldx, int ncols, SpmmEpi<T> epi, double* __restrict__ dot_part, int ld_dot, int sw) {
   typedef SpmmShape<T> Sh;
   constexpr int CH = Sh::CH, XLD = Sh::XLD, SLD = Sh::SLD, XU = Sh::XU, EPT = Sh::EPT;
   constexpr unsigned TS = sizeof(T);
@@ -901,7 +916,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q = lane >> 4, r16 = lane & 15;
-  const int64_t cell = xcd_cell(blockIdx.x, ncell);
+  const int64_t cell = xcd_cell(blockIdx.x, ncell, gd.gx, sw);
   if (cell >= ncell) return;
   const int c0 = blockIdx.y * 64;
   const int64_t rb = rcs[cell], re = rcs[cell + 1];
@@ -1105,25 +1120,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 // the block and keeps their 2 x 2 (row tile x column tile) MFMA 16x16x4
 // accumulators in registers across the chunks, reading its column operands
 // from global memory one step ahead.  The dense 32 x 256 block then goes to
-// LDS, and a coalesced pass over the group's nonzeros picks each value by
-// its key and applies fn.
+// LDS in place of the row operands, and a coalesced pass over the group's
+// nonzeros picks each value by its key and applies fn.
 template <class XOp, class YOp, class Fn>
-__global__ __launch_bounds__(512) void k_sddmm_cell(const int64_t* __restrict__ rcs, int64_t ncell,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_sddmm_cell(const int64_t* __restrict__ rcs, int64_t ncell,
                                                     const double* __restrict__ rxs, const int64_t* __restrict__ ccs,
                                                     const double* __restrict__ cxs, GridDesc gd,
                                                     const int64_t* __restrict__ rp, const int* __restrict__ col,
                                                     const int* __restrict__ key, int kdim, XOp xop, YOp yop, Fn fn,
-                                                    double* __restrict__ vals) {
+                                                    double* __restrict__ vals, int sw) {
 #pragma clang fp contract(off)
   constexpr int KC = 256, XLD = KC + 2, VB = 256, DLD = VB + 2;
+  // the dense block Dv reuses the row-operand tile once the products are
+  // done (66 KB of LDS: two workgroups per CU)
+  static_assert(DLD == XLD, "Dv aliases Xs");
   __shared__ __attribute__((aligned(16))) double Xs[32 * XLD];
-  __shared__ __attribute__((aligned(16))) double Dv[32 * DLD];
+  double* const Dv = Xs;
   typedef Mfma<double>::acc acc_t;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q = lane >> 4, r16 = lane & 15;
-  const int64_t cell = xcd_cell(blockIdx.x, ncell);
+  const int64_t cell = xcd_cell(blockIdx.x, ncell, gd.gx, sw);
   if (cell >= ncell) return;
   const int64_t rb = rcs[cell], re = rcs[cell + 1];
   if (rb >= re) return;
@@ -1186,6 +1204,7 @@ __global__ __launch_bounds__(512) void k_sddmm_cell(const int64_t* __restrict__ 
         }
       }
       // dense block to LDS: row a*16 + orow(q, r), position 16 (w + 8 t) + r16
+      __syncthreads();  // every wave is done reading Xs
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         if (!tile_on[t]) continue;
@@ -1227,21 +1246,24 @@ __global__ __launch_bounds__(512) void k_sddmm_cell(const int64_t* __restrict__ 
 // the workgroup of q's cell under (b).  Same blocking and MFMA scheme as
 // k_sddmm_cell on half the columns.
 template <class XOp, class YOp, class Fn>
-__global__ __launch_bounds__(512) void k_sddmm_sym(const int64_t* __restrict__ cs, int64_t ncell,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_sddmm_sym(const int64_t* __restrict__ cs, int64_t ncell,
                                                    const double* __restrict__ xs, GridDesc gd,
                                                    const int64_t* __restrict__ rp, const int* __restrict__ col,
                                                    const int* __restrict__ key, int kdim, XOp xop, YOp yop, Fn fn,
-                                                   double* __restrict__ vals) {
+                                                   double* __restrict__ vals, int sw) {
 #pragma clang fp contract(off)
   constexpr int KC = 256, XLD = KC + 2, VB = 256, DLD = VB + 2;
+  // the dense block Dv reuses the row-operand tile once the products are
+  // done (66 KB of LDS: two workgroups per CU)
+  static_assert(DLD == XLD, "Dv aliases Xs");
   __shared__ __attribute__((aligned(16))) double Xs[32 * XLD];
-  __shared__ __attribute__((aligned(16))) double Dv[32 * DLD];
+  double* const Dv = Xs;
   typedef Mfma<double>::acc acc_t;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q = lane >> 4, r16 = lane & 15;
-  const int64_t cell = xcd_cell(blockIdx.x, ncell);
+  const int64_t cell = xcd_cell(blockIdx.x, ncell, gd.gx, sw);
   if (cell >= ncell) return;
   const int64_t rb = cs[cell], re = cs[cell + 1];
   if (rb >= re) return;
@@ -1310,6 +1332,7 @@ __global__ __launch_bounds__(512) void k_sddmm_sym(const int64_t* __restrict__ c
           }
         }
       }
+      __syncthreads();  // every wave is done reading Xs
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         if (!tile_on[t]) continue;

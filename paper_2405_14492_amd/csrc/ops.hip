@@ -231,6 +231,7 @@ fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const
   gd.gamma = gamma;
   if (csr.nnz == 0) return FSA_OK;
   dim3 grid(8 * ceil_div(rg.ncell, 8));
+  const int sw = 16;  // cell columns per strip of the workgroup walk (measured best of 1..64)
   // one point set with symmetric dot products (X = Y, or [F|A] against
   // [A|F]): each pair of cells once
   const bool sym = self && Xr == Yc && (!deriv || Fr == Fc);
@@ -239,22 +240,22 @@ fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const
     ValFn fn{th, gamma, self ? 1 : 0, D};
     if (sym)
       hipLaunchKernelGGL((k_sddmm_sym<RowsOp<double>, RowsOp<double>, ValFn>), grid, dim3(512), 0, st, rg.cstart.p,
-                         rg.ncell, rg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, mp, xo, yo, fn, vals);
+                         rg.ncell, rg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, mp, xo, yo, fn, vals, sw);
     else
       hipLaunchKernelGGL((k_sddmm_cell<RowsOp<double>, RowsOp<double>, ValFn>), grid, dim3(512), 0, st, rg.cstart.p,
                          rg.ncell, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, mp, xo, yo,
-                         fn, vals);
+                         fn, vals, sw);
   } else {
     Rows2Op<double> xo{Fr, Xr, mp, mp}, yo{Yc, Fc, mp, mp};
     DValFn fn{th, gamma};
     if (sym)
       hipLaunchKernelGGL((k_sddmm_sym<Rows2Op<double>, Rows2Op<double>, DValFn>), grid, dim3(512), 0, st,
                          rg.cstart.p, rg.ncell, rg.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, 2 * mp, xo, yo, fn,
-                         vals);
+                         vals, sw);
     else
       hipLaunchKernelGGL((k_sddmm_cell<Rows2Op<double>, Rows2Op<double>, DValFn>), grid, dim3(512), 0, st,
                          rg.cstart.p, rg.ncell, rg.xs.p, cg.cstart.p, cg.xs.p, gd, csr.row_ptr.p, csr.col.p,
-                         csr.key.p, 2 * mp, xo, yo, fn, vals);
+                         csr.key.p, 2 * mp, xo, yo, fn, vals, sw);
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -479,8 +480,9 @@ static fsa_status launch_spmm_cell(const Csr& S, const Grid& rg, const Grid& cg,
   }
   dim3 grid(8 * ceil_div(rg.ncell, 8), ceil_div(ncols, 64));
   GridDesc gd = cg.desc;
+  const int sw = 32;  // cell columns per strip of the workgroup walk (measured best of 4..64)
   hipLaunchKernelGGL((k_spmm_dense<T, EM>), grid, dim3(256), 0, st, rg.cstart.p, rg.ncell, cg.cstart.p, gd,
-                     S.row_ptr.p, S.key.p, val, X, ldx, ncols, epi, dot_part, ld_dot);
+                     S.row_ptr.p, S.key.p, val, X, ldx, ncols, epi, dot_part, ld_dot, sw);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -609,7 +611,7 @@ fsa_status mspace_apply(const double* M, const double* W, int ldw, int kdim, int
 }
 
 // ================================================================ PCG (Algorithm 2)
-#define KT_BEGIN(b) int _kt = (b).timer ? (b).timer->start(st) : -1
+#define KT_BEGIN(b, cls) int _kt = (b).timer ? (b).timer->start((cls), st) : -1
 #define KT_END(b, cls) \
   if ((b).timer) (b).timer->stop((cls), _kt, st)
 
@@ -839,18 +841,18 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
                                        hipStream_t st) {
   // m-space: g = Cinv (A D^{-1} r), then q = (r - A^T g)/D
   {
-    KT_BEGIN(b);
+    KT_BEGIN(b, KT_SMALL);
     FSA_TRY(mspace_apply<T>(op.Cinv, s.w.p, b.ldw, op.kdim, b.ncols, b.g, b.ldw, st));
     KT_END(b, KT_SMALL);
   }
-  PcgPass2Epi<T> epi{b.Tt, b.R, op.Dinv, b.H, b.P, b.Q0, b.ld, init};
+  [[maybe_unused]] PcgPass2Epi<T> epi{b.Tt, b.R, op.Dinv, b.H, b.P, b.Q0, b.ld, init};
   int ncb = (int)ceil_div(b.ncols, 64);
   int64_t gx;
   if constexpr (sizeof(T) == 4) {
     gx = f32_rows_grid();
     size_t need = (size_t)gx * ncb * 64;
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
-    KT_BEGIN(b);
+    KT_BEGIN(b, KT_PASS2);
     F32RowsEpi fe{init ? nullptr : (float*)b.Tt, (const float*)b.R, op.Dinv, (float*)b.H, (float*)b.P, (float*)b.Q0,
                   (int64_t)b.ld};
     const size_t smem = (size_t)op.kdim * 64 * sizeof(float);
@@ -889,7 +891,7 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
     F64RowsEpi fe{init ? nullptr : (double*)b.Tt, (const double*)b.R, op.Dinv, (double*)b.H, (double*)b.P,
                   (double*)b.Q0, (int64_t)b.ld};
     double* part = init ? (double*)b.P : (double*)b.Tt;  // partial sums between the k passes
-    KT_BEGIN(b);
+    KT_BEGIN(b, KT_PASS2);
     if (init)
       FSA_TRY(rows_f64<ROWS_PCG_INIT>((const double*)op.A, nullptr, b.n, op.kdim, (const double*)b.g, b.ldw, b.ncols,
                                       fe, part, s.dot.p, ncb * 64, gx, st));
@@ -956,12 +958,12 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     size_t need = (size_t)g * ldd;
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
     {
-      KT_BEGIN(b);
+      KT_BEGIN(b, KT_SPMM);
       FSA_TRY((launch_spmm_cell<T, SP_PCG>(*op.S, *op.grid, *op.grid, op.val, b.H, b.ld, b.ncols, epi,
                                                           s.dot.p, ldd, st)));
       KT_END(b, KT_SPMM);
     }
-    KT_BEGIN(b);
+    KT_BEGIN(b, KT_SMALL);
     if (s.dot1.count < (size_t)COLSUM_G * ldd) FSA_TRY(s.dot1.alloc((size_t)COLSUM_G * ldd));
     hipLaunchKernelGGL(k_colsum_stage1, dim3(COLSUM_G), dim3(256), 0, st, s.dot.p, (int)g, ldd, b.ncols, s.dot1.p,
                        ldd);
@@ -977,14 +979,14 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     FSA_TRY(ensure_part<T>(s, r));
     PcgPass1Pro<T> pro{b.R, b.V, op.Dinv, b.alpha, b.ld};
     {
-      KT_BEGIN(b);
+      KT_BEGIN(b, KT_PASS1);
       FSA_TRY((launch_reduce<T, true>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, s.dot2.p, ldd, st, 0,
                                       op.Abf, op.Abf8)));
       KT_END(b, KT_PASS1);
     }
     nparts_rr = r.nchunks;
     {
-      KT_BEGIN(b);
+      KT_BEGIN(b, KT_SMALL);
       FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
       KT_END(b, KT_SMALL);
     }
@@ -999,7 +1001,7 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
   }
   // 4. beta, Lanczos entries, convergence
   {
-    KT_BEGIN(b);
+    KT_BEGIN(b, KT_SMALL);
     hipLaunchKernelGGL(k_pcg_beta, dim3(b.ncols), dim3(256), 0, st, b.ncols, s.dot.p, nparts_rq, ldd, s.dot2.p, nparts_rr,
                        ldd, b.rz, b.alpha, b.beta, b.active, b.iters, b.alpha_hist, b.beta_hist, b.bn2, b.rr,
                        tol * tol, fixed, b.max_iter, b.flags);
@@ -1007,7 +1009,7 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
   }
   // 5. h = q + beta h, p = t + beta p
   int64_t tot = b.n * b.ncols;
-  KT_BEGIN(b);
+  KT_BEGIN(b, KT_UPDATE);
   bool u32 = false;
   if constexpr (sizeof(T) == 4) {
     if (b.U32) {

@@ -20,15 +20,18 @@ hipEvent_t timer_event_get();  // nullptr if none can be created
 void timer_event_put(hipEvent_t e);
 
 // HIP-event timing of kernel classes on one stream (enabled per context).
+// Only the classes in `mask` (bit k: class k) are timed: each timed launch
+// costs two event records on the stream.
 struct KernelTimer {
   static constexpr int NCLS = 5;
   bool on = false;
+  unsigned mask = 0;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<int> cls;
   void reset() { used = 0; cls.clear(); }
-  int start(hipStream_t st) {
-    if (!on) return -1;
+  int start(int k, hipStream_t st) {
+    if (!on || !((mask >> k) & 1u)) return -1;
     if (used + 2 > pool.size()) {
       for (int k = 0; k < 256; ++k) {
         hipEvent_t e = timer_event_get();

@@ -20,6 +20,7 @@ MATERN32 = 1
 FP64 = 0
 MIXED_FP32 = 1
 MIXED_BF16A = 2
+PROFILE_ALL = 0x1f  # fsa_options.profile: all five kernel classes
 
 OP_SIGMA_DAGGER, OP_SIGMA_S, OP_P_INV, OP_D_SIGMA1, OP_D_RHO, OP_PROBES = range(6)
 
@@ -157,7 +158,8 @@ def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, p
     o.slq_weight_n = int(bool(slq_weight_n))
     o.sigma_m_jitter = float(jitter)
     o.hip_stream = stream
-    o.profile = int(bool(profile))
+    # True: every kernel class; an int: the class bit mask itself
+    o.profile = PROFILE_ALL if profile is True else int(profile)
     return o
 
 

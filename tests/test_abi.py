@@ -33,6 +33,18 @@ def test_every_declared_symbol_is_exported(L):
     assert set(fsa.EXPORTED) == set(names)
 
 
+def test_header_constants_match_binding(L):
+    from paper_2405_14492_amd import fsa
+    src = open(os.path.join(ROOT, "include", "fsa.h")).read()
+    for nm, val in (("FSA_FP64", fsa.FP64), ("FSA_MIXED_FP32", fsa.MIXED_FP32),
+                    ("FSA_MIXED_BF16A", fsa.MIXED_BF16A)):
+        assert re.search(r"\b%s = %d\b" % (nm, val), src), nm
+    assert int(re.search(r"#define FSA_PROFILE_ALL (0x[0-9a-f]+)", src).group(1), 16) == fsa.PROFILE_ALL
+    assert fsa.make_options(profile=True).profile == fsa.PROFILE_ALL
+    assert fsa.make_options(profile=1).profile == 1
+    assert fsa.make_options().profile == 0
+
+
 def test_struct_layouts(L):
     from paper_2405_14492_amd import fsa
     # fsa_options: int32, (pad) uint64, double, 5 x int32, (pad) double, void*

@@ -351,3 +351,22 @@ def test_contexts_return_device_memory(F):
     free1, _ = torch.cuda.mem_get_info()
     say("device free before", free0 >> 20, "MiB, after", free1 >> 20, "MiB")
     assert free0 - free1 < (64 << 20)
+
+
+@pytest.mark.gpu
+def test_kernel_timer_class_mask(F):
+    """options.profile times exactly the kernel classes in its bit mask; the
+    result does not depend on which classes are timed."""
+    locs, y, theta, ind, gamma = case(n=20000, m=150, kind=O.MATERN32, rho=0.05, s2=0.1, n_gamma=30, seed=6)
+    out = {}
+    for prof in (0, 1, 1 << 2, True):
+        with F.FSA(locs, y, theta, ind, gamma, num_probes=4, seed=1, tol=1e-6, precision=F.MIXED_FP32,
+                   profile=prof) as f:
+            out[prof] = f.nll_grad()
+    mask = {0: 0, 1: 1, 4: 4, True: 0x1f}
+    for prof, (nll, grad, st) in out.items():
+        timed = [k for k in range(5) if st["kernel_launches"][k] > 0]
+        assert timed == [k for k in range(5) if (mask[prof] >> k) & 1], (prof, st["kernel_launches"])
+        assert all(st["kernel_ms"][k] > 0 for k in timed)
+        assert abs(nll - out[0][0]) <= 1e-12 * abs(out[0][0])
+        np.testing.assert_allclose(grad, out[0][1], rtol=1e-12, atol=0)
