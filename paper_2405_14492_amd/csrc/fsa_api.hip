@@ -190,6 +190,29 @@ __global__ void k_finalize_grad(int ncols, const double* __restrict__ uSX, const
   }
 }
 
+// Low-rank parts of the gradient's column dots from the m-space blocks
+// (kdim x ldw, row-major): with a = A^T x, f = F^T x, au = A^T u, fu = F^T u,
+// u.(A A^T x) = au . a and u.((F A^T + A F^T) x) = fu . a + au . f.
+__global__ void k_grad_mdots(const double* __restrict__ a, const double* __restrict__ f,
+                             const double* __restrict__ au, const double* __restrict__ fu, int kdim, int ldw,
+                             int ncols, double* __restrict__ lr_sigma, double* __restrict__ lr_drho) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int k = 0; k < kdim; ++k) {
+    const int64_t o = (int64_t)k * ldw + c;
+    s0 += au[o] * a[o];
+    s1 += fu[o] * a[o] + au[o] * f[o];
+  }
+  lr_sigma[c] = s0;
+  lr_drho[c] = s1;
+}
+
+__global__ void k_add_cols(int ncols, const double* __restrict__ x, double* __restrict__ y) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncols) y[c] += x[c];
+}
+
 __global__ void k_grad_block(int64_t n, int ncols, int64_t ld, const double* __restrict__ U, const void* Q0, int q0_f32,
                              double* __restrict__ X) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -272,7 +295,7 @@ struct fsa_ctx {
   int deriv_state = 0;
   bool timer_pending = false;  // the last solve's kernel events are not yet summed
   // gradient
-  Buf<double> F, dvals, Xb, SX, DX, tmp, dSm, Ework;
+  Buf<double> F, dvals, Xb, tmp, dSm, Ework;
   Scratch scr;
   BlasHandle blas;
   KernelTimer timer;
@@ -906,23 +929,37 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   hipStream_t st = c->st;
   const int64_t n = c->n;
   const int tp = c->tp, ld = c->ld;
-  size_t blk = (size_t)n * ld;
   FSA_TRY(ensure_derivative(c));
-  FSA_TRY(c->SX.alloc(blk));
-  FSA_TRY(c->DX.alloc(blk));
-  FSA_TRY(apply_sigma(c, c->Xb.p, c->SX.p, tp, ld));
-  FSA_TRY(apply_drho(c, c->Xb.p, c->DX.p, tp, ld));
-  Buf<double> dd;
-  FSA_TRY(dd.alloc(3 * (size_t)tp + 9));
-  FSA_TRY((coldot<double, double>(c->U.p, c->SX.p, n, ld, tp, dd.p, c->scr, st)));
+  // Only the column dots u.(Sigma~ x), u.x and u.(dSigma~/drho x) are
+  // needed (u = U, x = Xb, column by column): the sparse parts come from the
+  // sparse product's epilogue without storing it, the low-rank parts from
+  // m-space reductions of x and u (no n x t expansion).
+  const int mp = c->mp;
+  const int ldw = (int)round_up(tp, 64);
+  Buf<double> dd, wm;
+  FSA_TRY(dd.alloc(5 * (size_t)tp + 9));
+  FSA_TRY(wm.alloc(4 * (size_t)mp * ldw));
+  double* w_ax = wm.p;
+  double* w_fx = wm.p + (size_t)mp * ldw;
+  double* w_au = wm.p + 2 * (size_t)mp * ldw;
+  double* w_fu = wm.p + 3 * (size_t)mp * ldw;
+  FSA_TRY(spmm_dot<double>(c->csr, c->grid, c->vals.p, c->Xb.p, c->U.p, ld, tp, dd.p, c->scr, st));
   FSA_TRY((coldot<double, double>(c->U.p, c->Xb.p, n, ld, tp, dd.p + tp, c->scr, st)));
-  FSA_TRY((coldot<double, double>(c->U.p, c->DX.p, n, ld, tp, dd.p + 2 * tp, c->scr, st)));
+  FSA_TRY(spmm_dot<double>(c->csr, c->grid, c->dvals.p, c->Xb.p, c->U.p, ld, tp, dd.p + 2 * tp, c->scr, st));
+  FSA_TRY(lowrank_reduce<double>(c->A.p, n, mp, c->Xb.p, ld, tp, nullptr, c->scr, w_ax, ldw, st));
+  FSA_TRY(lowrank_reduce<double>(c->F.p, n, mp, c->Xb.p, ld, tp, nullptr, c->scr, w_fx, ldw, st));
+  FSA_TRY(lowrank_reduce<double>(c->A.p, n, mp, c->U.p, ld, tp, nullptr, c->scr, w_au, ldw, st));
+  FSA_TRY(lowrank_reduce<double>(c->F.p, n, mp, c->U.p, ld, tp, nullptr, c->scr, w_fu, ldw, st));
+  hipLaunchKernelGGL(k_grad_mdots, dim3(ceil_div(tp, 64)), dim3(64), 0, st, w_ax, w_fx, w_au, w_fu, mp, ldw, tp,
+                     dd.p + 3 * tp, dd.p + 4 * tp);
+  hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 3 * tp, dd.p);
+  hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 4 * tp, dd.p + 2 * tp);
   hipLaunchKernelGGL(k_finalize_grad, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, c->th.s1, c->th.s2,
-                     dd.p + 3 * tp);
+                     dd.p + 5 * tp);
   FSA_HIP(hipGetLastError());
   collect_timer(c);  // host work while the gradient kernels run
   double g9[9];
-  FSA_HIP(hipMemcpyAsync(g9, dd.p + 3 * tp, sizeof(g9), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipMemcpyAsync(g9, dd.p + 5 * tp, sizeof(g9), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < 3; ++k) grad[k] = g9[k];
   if (parts6)

@@ -891,8 +891,8 @@ __device__ __forceinline__ int64_t xcd_cell(int64_t b, int64_t ncell, int64_t gx
 
 // Epilogue of the sparse product over row-major n x ld blocks.  Modes:
 // SP_STORE Y = acc; SP_ACC Y += acc; SP_PCG Y = acc + P (P may be null),
-// dot += H . Y per column.
-enum { SP_STORE = 0, SP_ACC = 1, SP_PCG = 2 };
+// dot += H . Y per column; SP_DOT dot += H . acc per column (Y not written).
+enum { SP_STORE = 0, SP_ACC = 1, SP_PCG = 2, SP_DOT = 3 };
 template <typename T>
 struct SpmmEpi {
   T* Y;
@@ -1006,7 +1006,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       };
       // epilogue inputs of this wave's two tiles
       const __amdgpu_buffer_rsrc_t yrs = rsrc_of(epi.Y + g0 * epi.ld, (int64_t)nrg * epi.ld * TS);
-      const __amdgpu_buffer_rsrc_t hrs = rsrc_of(EM == SP_PCG ? epi.H + g0 * epi.ld : epi.Y, EM == SP_PCG ? (int64_t)nrg * epi.ld * TS : 0);
+      constexpr bool HD = EM == SP_PCG || EM == SP_DOT;  // the epilogue reads H
+      const __amdgpu_buffer_rsrc_t hrs = rsrc_of(HD ? epi.H + g0 * epi.ld : epi.Y, HD ? (int64_t)nrg * epi.ld * TS : 0);
       const __amdgpu_buffer_rsrc_t prs = rsrc_of(EM == SP_PCG && epi.P ? epi.P + g0 * epi.ld : epi.Y, EM == SP_PCG && epi.P ? (int64_t)nrg * epi.ld * TS : 0);
       unsigned eo[2][4];
 #pragma unroll
@@ -1042,6 +1043,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
               in0[t][r] = bload<T>(hrs, eo[t][r]);
               in1[t][r] = bload<T>(prs, eo[t][r]);
             }
+            if constexpr (EM == SP_DOT) in0[t][r] = bload<T>(hrs, eo[t][r]);
           }
       } else {
         // long rows: entries re-read per chunk in batches
@@ -1055,6 +1057,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
               in0[t][r] = bload<T>(hrs, eo[t][r]);
               in1[t][r] = bload<T>(prs, eo[t][r]);
             }
+            if constexpr (EM == SP_DOT) in0[t][r] = bload<T>(hrs, eo[t][r]);
           }
         for (int vb = 0; vb < V; vb += CH) {
           load_chunk(vb, xr);
@@ -1079,6 +1082,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
             bstore<T>(a, yrs, eo[t][r]);
           } else if constexpr (EM == SP_ACC) {
             bstore<T>(a + in0[t][r], yrs, eo[t][r]);
+          } else if constexpr (EM == SP_DOT) {
+            d += (double)in0[t][r] * (double)a;  // zero past the group's rows and columns
           } else {
             const T v = (T)((double)a + (double)in1[t][r]);
             bstore<T>(v, yrs, eo[t][r]);
@@ -1090,7 +1095,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       }
     }
   }
-  if constexpr (EM == SP_PCG) {
+  if constexpr (EM >= SP_PCG) {
     // column c0 + 16 b + r16 gathers the q groups of the two waves owning tile column b
     dsum0 += __shfl_xor(dsum0, 16, 64);
     dsum0 += __shfl_xor(dsum0, 32, 64);

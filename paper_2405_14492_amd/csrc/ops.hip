@@ -60,24 +60,6 @@ struct StoreEpi {
   }
 };
 
-struct ProbeEpi {
-  double* B;
-  int64_t ld;
-  const double* y;
-  const double* D;
-  const int* perm;
-  uint64_t seed;
-  struct In { double a; int pi; };
-  __device__ __forceinline__ In load(int64_t i, int c) const {
-    return c == 0 ? In{y[i], 0} : In{D[i], perm[i]};
-  }
-  __device__ __forceinline__ double apply(int64_t i, int c, double v, const In& x) const {
-    if (c == 0) B[i * ld] = x.a;
-    else B[i * ld + c] = sqrt(x.a) * rademacher(seed, STREAM_RHO, (uint64_t)(c - 1), (uint64_t)x.pi) + v;
-    return 0.0;
-  }
-};
-
 namespace {
 std::mutex g_tev_mu;
 std::vector<hipEvent_t> g_tev;
@@ -534,9 +516,20 @@ __global__ __launch_bounds__(256) void k_coldot(const TX* __restrict__ X, const 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = blockIdx.y * 64 + lane;
   double a = 0.0;
-  if (c < ncols)
-    for (int64_t p = (int64_t)blockIdx.x * 4 + w; p < n; p += (int64_t)gridDim.x * 4)
+  if (c < ncols) {
+    // four rows in flight per wave, summed in a fixed order
+    const int64_t st = (int64_t)gridDim.x * 4;
+    int64_t p = (int64_t)blockIdx.x * 4 + w;
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (; p + 3 * st < n; p += 4 * st) {
       a += (double)X[p * ld + c] * (double)Y[p * ld + c];
+      a1 += (double)X[(p + st) * ld + c] * (double)Y[(p + st) * ld + c];
+      a2 += (double)X[(p + 2 * st) * ld + c] * (double)Y[(p + 2 * st) * ld + c];
+      a3 += (double)X[(p + 3 * st) * ld + c] * (double)Y[(p + 3 * st) * ld + c];
+    }
+    for (; p < n; p += st) a += (double)X[p * ld + c] * (double)Y[p * ld + c];
+    a = (a + a1) + (a2 + a3);
+  }
   red[w][lane] = a;
   __syncthreads();
   if (threadIdx.x < 64)
@@ -733,31 +726,25 @@ __global__ void k_pcg_hupdate(int64_t n, int ncols, int64_t ld, const T* __restr
   if (has_lr) P[o] = (T)(t + b * pv);
 }
 
-__global__ void k_pcg_setup(int ncols, const double* __restrict__ bn2_part, int nb, int ldb, const double* __restrict__ rq_part,
-                            int nr, int ldr, double* bn2, double* rz, double* rz0, double* rr, int* active, int* iters,
-                            int* flags) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
+// One workgroup per column c (flags zeroed beforehand): |b|^2, r^T q and the
+// column's activity; flags[0] counts the active columns.
+__global__ __launch_bounds__(256) void k_pcg_setup(const double* __restrict__ bn2_part, int nb, int ldb,
+                                                   const double* __restrict__ rq_part, int nr, int ldr, double* bn2,
+                                                   double* rz, double* rz0, double* rr, int* active, int* iters,
+                                                   int* flags) {
   __shared__ double red[256];
-  for (int c = 0; c < ncols; ++c) {
-    double b = block_colsum(bn2_part, nb, ldb, c, red);
-    double r = block_colsum(rq_part, nr, ldr, c, red);
-    if (threadIdx.x != 0) continue;
-    bn2[c] = b;
-    rr[c] = b;
-    rz[c] = r;
-    rz0[c] = r;
-    iters[c] = 0;
-    int a = b > 0.0 ? 1 : 0;
-    active[c] = a;
-    if (a) atomicAdd(&cnt, 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    flags[0] = cnt;
-    flags[1] = 0;
-  }
+  const int c = blockIdx.x;
+  const double b = block_colsum(bn2_part, nb, ldb, c, red);
+  const double r = block_colsum(rq_part, nr, ldr, c, red);
+  if (threadIdx.x != 0) return;
+  bn2[c] = b;
+  rr[c] = b;
+  rz[c] = r;
+  rz0[c] = r;
+  iters[c] = 0;
+  const int a = b > 0.0 ? 1 : 0;
+  active[c] = a;
+  if (a) atomicAdd(&flags[0], 1);
 }
 
 // First stage of a fixed-order column sum over many partial rows: workgroup
@@ -779,6 +766,25 @@ __global__ __launch_bounds__(256) void k_colsum_stage1(const double* __restrict_
     __syncthreads();
   }
 }
+
+template <typename T>
+fsa_status spmm_dot(const Csr& S, const Grid& g, const T* val, const T* X, const T* H, int ld, int ncols,
+                    double* out, Scratch& s, hipStream_t st) {
+  if (ncols <= 0) return FSA_OK;
+  const int ldd = (int)ceil_div(ncols, 64) * 64;
+  const int64_t np = std::max<int64_t>(g.ncell, 1);
+  if (s.dot.count < (size_t)np * ldd) FSA_TRY(s.dot.alloc((size_t)np * ldd));
+  if (s.dot1.count < (size_t)COLSUM_G * ldd) FSA_TRY(s.dot1.alloc((size_t)COLSUM_G * ldd));
+  if (g.ncell == 0) FSA_HIP(hipMemsetAsync(s.dot.p, 0, (size_t)ldd * sizeof(double), st));
+  SpmmEpi<T> epi{const_cast<T*>(H), H, nullptr, ld};  // Y is not written in this mode
+  FSA_TRY((launch_spmm_cell<T, SP_DOT>(S, g, g, val, X, ld, ncols, epi, s.dot.p, ldd, st)));
+  hipLaunchKernelGGL(k_colsum_stage1, dim3(COLSUM_G), dim3(256), 0, st, s.dot.p, (int)np, ldd, ncols, s.dot1.p, ldd);
+  hipLaunchKernelGGL(k_colsum, dim3(ncols), dim3(256), 0, st, s.dot1.p, COLSUM_G, ldd, out);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+template fsa_status spmm_dot<double>(const Csr&, const Grid&, const double*, const double*, const double*, int, int,
+                                     double*, Scratch&, hipStream_t);
 
 // One workgroup per column: alpha = r^T q / h^T v for active columns.
 __global__ __launch_bounds__(256) void k_pcg_alpha(int ncols, const double* __restrict__ hv_part, int np, int ldp,
@@ -908,6 +914,10 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
 template <typename T>
 fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double tol, Scratch& s, hipStream_t st) {
   (void)tol;
+  if (b.ncols <= 0) {
+    set_error("PCG needs at least one right-hand side");
+    return FSA_ERR_INVALID_ARG;
+  }
   FSA_TRY((copy_block<double, T>(B, b.ld, b.R, b.ld, b.n, b.ncols, st)));
   FSA_HIP(hipMemsetAsync(b.U, 0, (size_t)b.n * b.ld * sizeof(double), st));
   if (sizeof(T) == 4 && b.U32) FSA_HIP(hipMemsetAsync(b.U32, 0, (size_t)b.n * b.ld * sizeof(float), st));
@@ -929,7 +939,8 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
     hipLaunchKernelGGL((k_coldot<double, double>), dim3(g, ncb), dim3(256), 0, st, B, B, b.n, b.ld, b.ncols, s.dot2.p);
     nparts_rr = (int)g;
     FSA_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_pcg_setup, dim3(1), dim3(256), 0, st, b.ncols, s.dot2.p, nparts_rr, ncb * 64, s.dot.p,
+    FSA_HIP(hipMemsetAsync(b.flags, 0, 2 * sizeof(int), st));
+    hipLaunchKernelGGL(k_pcg_setup, dim3(b.ncols), dim3(256), 0, st, s.dot2.p, nparts_rr, ncb * 64, s.dot.p,
                        nparts_rq, ncb * 64, b.bn2, b.rz, b.rz0, b.rr, b.active, b.iters, b.flags);
   } else {
     int64_t g = spmm_grid(b.n);
@@ -939,7 +950,8 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
     hipLaunchKernelGGL((k_pcg_sparse_update<T>), dim3(g, ncb), dim3(256), 0, st, b.n, b.ncols, (int64_t)b.ld, b.R,
                        (const T*)b.V, op.Dinv, b.alpha, 0, 1, b.H, b.Q0, s.dot2.p, s.dot.p, ncb * 64);
     FSA_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_pcg_setup, dim3(1), dim3(256), 0, st, b.ncols, s.dot2.p, (int)g, ncb * 64, s.dot.p, (int)g,
+    FSA_HIP(hipMemsetAsync(b.flags, 0, 2 * sizeof(int), st));
+    hipLaunchKernelGGL(k_pcg_setup, dim3(b.ncols), dim3(256), 0, st, s.dot2.p, (int)g, ncb * 64, s.dot.p, (int)g,
                        ncb * 64, b.bn2, b.rz, b.rz0, b.rr, b.active, b.iters, b.flags);
   }
   FSA_HIP(hipGetLastError());
@@ -1193,17 +1205,29 @@ __global__ void k_probe_e(int m, int mp, int nprobe, uint64_t seed, double* E, i
   E[e] = v;
 }
 
+// B[p][0] = y[p]; B[p][c] += sqrt(D[p]) rho_{c-1}(perm[p]) for 1 <= c < ncols
+__global__ void k_probe_finish(double* __restrict__ B, int64_t ldb, const double* __restrict__ y,
+                               const double* __restrict__ D, const int* __restrict__ perm, uint64_t seed, int64_t n,
+                               int ncols) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t p = e / ncols;
+  const int c = (int)(e % ncols);
+  if (p >= n) return;
+  if (c == 0) B[p * ldb] = y[p];
+  else B[p * ldb + c] += sqrt(D[p]) * rademacher(seed, STREAM_RHO, (uint64_t)(c - 1), (uint64_t)perm[p]);
+}
+
 fsa_status make_probes(const double* A, int64_t n, int m, int mp, const double* D, const double* y, const int* perm,
                        uint64_t seed, int nprobe, double* B, int ldb, double* Emat, hipStream_t st) {
   int ncols = nprobe + 1;
   int ldE = (int)round_up(ncols, 64);
   hipLaunchKernelGGL(k_probe_e, dim3(ceil_div((int64_t)mp * ldE, 256)), dim3(256), 0, st, m, mp, nprobe, seed, Emat,
                      ldE);
-  ProbeEpi epi{B, ldb, y, D, perm, seed};
-  RowsOp<double> op{A, mp};
-  dim3 grid(rows_grid(n), ceil_div(ncols, 64));
-  hipLaunchKernelGGL((k_rows_gemm<double, RT_ROWS, false, RowsOp<double>, ProbeEpi>), grid, dim3(256), 0, st, n, mp,
-                     Emat, ldE, ncols, 0, op, epi, (double*)nullptr, 0);
+  // A^T-side products A E (column 0 of E is zero), then y and sqrt(D) rho
+  F64RowsEpi fe{B, nullptr, nullptr, nullptr, nullptr, nullptr, ldb};
+  FSA_TRY(rows_f64<ROWS_STORE>(A, nullptr, n, mp, Emat, ldE, ncols, fe, B, nullptr, 0, f32_rows_grid(), st));
+  hipLaunchKernelGGL(k_probe_finish, dim3(ceil_div(n * ncols, 256)), dim3(256), 0, st, B, (int64_t)ldb, y, D, perm,
+                     seed, n, ncols);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }

@@ -115,6 +115,11 @@ fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T*
 template <typename T>
 fsa_status spmm(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx, int ncols, T* Y,
                 int ldy, bool accumulate, hipStream_t st);
+// out[c] = sum_p H[p][c] (S X)[p][c] for c < ncols (float64 result; S X is
+// not stored), S with the pattern of grid g on both sides
+template <typename T>
+fsa_status spmm_dot(const Csr& S, const Grid& g, const T* val, const T* X, const T* H, int ld, int ncols,
+                    double* out, Scratch& s, hipStream_t st);
 // out[c] = sum_p X[p][c] Y[p][c] (float64 result, c < ncols)
 template <typename TX, typename TY>
 fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double* out, Scratch& s, hipStream_t st);
