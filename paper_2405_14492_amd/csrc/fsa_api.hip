@@ -193,19 +193,33 @@ __global__ void k_finalize_grad(int ncols, const double* __restrict__ uSX, const
 // Low-rank parts of the gradient's column dots from the m-space blocks
 // (kdim x ldw, row-major): with a = A^T x, f = F^T x, au = A^T u, fu = F^T u,
 // u.(A A^T x) = au . a and u.((F A^T + A F^T) x) = fu . a + au . f.
-__global__ void k_grad_mdots(const double* __restrict__ a, const double* __restrict__ f,
-                             const double* __restrict__ au, const double* __restrict__ fu, int kdim, int ldw,
-                             int ncols, double* __restrict__ lr_sigma, double* __restrict__ lr_drho) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
+// One workgroup (256 threads) per column, fixed-order tree sum over k.
+__global__ __launch_bounds__(256) void k_grad_mdots(const double* __restrict__ a, const double* __restrict__ f,
+                                                    const double* __restrict__ au, const double* __restrict__ fu,
+                                                    int kdim, int ldw, double* __restrict__ lr_sigma,
+                                                    double* __restrict__ lr_drho) {
+  __shared__ double r0[256], r1[256];
+  const int c = blockIdx.x, t = threadIdx.x;
   double s0 = 0.0, s1 = 0.0;
-  for (int k = 0; k < kdim; ++k) {
+  for (int k = t; k < kdim; k += 256) {
     const int64_t o = (int64_t)k * ldw + c;
     s0 += au[o] * a[o];
     s1 += fu[o] * a[o] + au[o] * f[o];
   }
-  lr_sigma[c] = s0;
-  lr_drho[c] = s1;
+  r0[t] = s0;
+  r1[t] = s1;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      r0[t] += r0[t + h];
+      r1[t] += r1[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    lr_sigma[c] = r0[0];
+    lr_drho[c] = r1[0];
+  }
 }
 
 __global__ void k_add_cols(int ncols, const double* __restrict__ x, double* __restrict__ y) {
@@ -287,6 +301,10 @@ struct fsa_ctx {
   // marks the solve's end on st, ev_slq the quadrature's end on st2
   hipEvent_t ev_solve = nullptr, ev_slq = nullptr;
   bool slq_pending = false;
+  // the two Cholesky factorizations of a build run on st2 beside other
+  // build work: ev_fact marks the end of the one in flight
+  hipEvent_t ev_fact = nullptr;
+  bool lm_pending = false;  // Sigma_m -> L_m enqueued on st2
   // small device-to-host readbacks: a device staging block and its pinned
   // host mirror (one asynchronous copy each)
   Buf<char> dstage;
@@ -327,15 +345,32 @@ static fsa_status check_theta(const fsa_theta* th) {
 
 // Sigma_m, L_m, whitened factor, residual values, D_s, FITC capacitance.
 static fsa_status settle_derivative(fsa_ctx* c);
+static fsa_status side_stream(fsa_ctx* c);
+
+// Sigma_m and its Cholesky factor L_m on the side stream, behind everything
+// enqueued on st so far (ev_fact marks the end): one workgroup's work that
+// runs beside the grid and pattern build or the cross-covariance block.
+static fsa_status launch_sigma_m(fsa_ctx* c) {
+  FSA_TRY(side_stream(c));
+  const int mp = c->mp;
+  FSA_HIP(hipEventRecord(c->ev_ready, c->st));
+  FSA_HIP(hipStreamWaitEvent(c->st2, c->ev_ready, 0));
+  FSA_TRY(dense_sigma_m(c->ind.p, c->m, mp, c->th, c->opt.sigma_m_jitter, false, c->Sm.p, c->st2));
+  FSA_HIP(hipMemcpyAsync(c->Lm.p, c->Sm.p, (size_t)mp * mp * sizeof(double), hipMemcpyDeviceToDevice, c->st2));
+  FSA_TRY(dense_cholesky(c->Lm.p, mp, c->info.p, c->st2));
+  FSA_HIP(hipEventRecord(c->ev_fact, c->st2));
+  c->lm_pending = true;
+  return FSA_OK;
+}
 
 static fsa_status build_values(fsa_ctx* c) {
   FSA_TRY(settle_derivative(c));  // nothing may still read A, L_m or F
   c->deriv_state = 0;
   hipStream_t st = c->st;
   const int mp = c->mp;
-  FSA_TRY(dense_sigma_m(c->ind.p, c->m, mp, c->th, c->opt.sigma_m_jitter, false, c->Sm.p, st));
-  FSA_HIP(hipMemcpyAsync(c->Lm.p, c->Sm.p, (size_t)mp * mp * sizeof(double), hipMemcpyDeviceToDevice, st));
-  FSA_TRY(dense_cholesky(c->Lm.p, mp, c->info.p, st));
+  if (!c->lm_pending) FSA_TRY(launch_sigma_m(c));
+  FSA_HIP(hipStreamWaitEvent(st, c->ev_fact, 0));
+  c->lm_pending = false;
   int info = 0;
   FSA_HIP(hipMemcpyAsync(&info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
@@ -357,19 +392,32 @@ static fsa_status build_values(fsa_ctx* c) {
                           c->vals.p, c->D.p, st));
   FSA_TRY(reciprocal(c->D.p, c->Dinv.p, c->n, st));
   FSA_TRY(capacitance(c->A.p, c->D.p, c->n, mp, c->C.p, c->scr, st));
-  // C -> L_C (in place), L_C^{-1}, C^{-1} = L_C^{-T} L_C^{-1}
-  FSA_TRY(dense_cholesky(c->C.p, mp, c->info.p, st));
-  FSA_HIP(hipMemcpyAsync(&info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  FSA_HIP(hipMemsetAsync(c->info.p + 1, 0, sizeof(int), st));
-  FSA_TRY(dense_logdet_chol(c->C.p, mp, c->logdet_parts.p, st));
+  // On the side stream: C -> L_C (in place), log det, L_C^{-1} and
+  // C^{-1} = L_C^{-T} L_C^{-1}; meanwhile st converts the factor and values
+  // and forms the probe block (none of which reads C).
+  FSA_HIP(hipMemsetAsync(c->info.p, 0, 2 * sizeof(int), st));
+  FSA_HIP(hipEventRecord(c->ev_ready, st));
+  FSA_HIP(hipStreamWaitEvent(c->st2, c->ev_ready, 0));
+  FSA_TRY(dense_cholesky(c->C.p, mp, c->info.p, c->st2));
+  FSA_TRY(dense_logdet_chol(c->C.p, mp, c->logdet_parts.p, c->st2));
+  FSA_TRY(blas_tri_inverse(c->blas, c->st2, c->C.p, c->LCinv.p, mp));
+  FSA_TRY(dense_gemm(c->LCinv.p, true, c->LCinv.p, false, c->Cinv.p, mp, 1.0, c->st2));
+  FSA_HIP(hipEventRecord(c->ev_fact, c->st2));
   {
     const int nb = 256;
     FSA_TRY(c->scr.dot1.alloc(nb));
     hipLaunchKernelGGL(k_sum_log_part, dim3(nb), dim3(256), 0, st, c->D.p, c->n, c->scr.dot1.p, c->info.p + 1);
     hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, c->scr.dot1.p, nb, c->logdet_parts.p + 1);
   }
-  FSA_TRY(blas_tri_inverse(c->blas, st, c->C.p, c->LCinv.p, mp));
-  FSA_TRY(dense_gemm(c->LCinv.p, true, c->LCinv.p, false, c->Cinv.p, mp, 1.0, st));
+  if (c->opt.precision == FSA_MIXED_FP32) FSA_TRY(to_float(c->A.p, c->Af.p, c->n * (int64_t)mp, st));
+  if (c->opt.precision != FSA_FP64) FSA_TRY(to_float(c->vals.p, c->valsf.p, c->csr.nnz, st));
+  // probe block [y, z_1 .. z_t] (Section 3.3)
+  FSA_TRY(c->B.alloc((size_t)c->n * c->ld));
+  FSA_TRY(c->Emat.alloc((size_t)mp * c->ldw));
+  FSA_TRY(make_probes(c->A.p, c->n, c->m, mp, c->D.p, c->y.p, c->grid.perm.p, c->opt.seed, c->t, c->B.p, c->ld,
+                      c->Emat.p, st));
+  FSA_HIP(hipStreamWaitEvent(st, c->ev_fact, 0));
+  FSA_HIP(hipMemcpyAsync(&info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   int bad = 0;
   FSA_HIP(hipMemcpyAsync(&bad, c->info.p + 1, sizeof(int), hipMemcpyDeviceToHost, st));
   double ld2[2];
@@ -384,8 +432,6 @@ static fsa_status build_values(fsa_ctx* c) {
     return FSA_ERR_NOT_SPD;
   }
   c->last_logdet_P = ld2[0] + ld2[1];
-  if (c->opt.precision == FSA_MIXED_FP32) FSA_TRY(to_float(c->A.p, c->Af.p, c->n * (int64_t)mp, st));
-  if (c->opt.precision != FSA_FP64) FSA_TRY(to_float(c->vals.p, c->valsf.p, c->csr.nnz, st));
   c->solved = false;
   return FSA_OK;
 }
@@ -408,15 +454,16 @@ static fsa_status build_core(fsa_ctx* c, const double* locs, const double* y, co
     set_error("non-finite value in locations, responses or inducing points");
     return FSA_ERR_INVALID_ARG;
   }
-  FSA_TRY(build_grid(c->grid, locs, n, c->gamma, st, nullptr, nullptr));
-  FSA_TRY(build_pattern(c->grid, c->grid, c->csr, st));
-  FSA_TRY(c->y.alloc(n));
-  FSA_TRY(permute_rows(y, 1, c->y.p, 1, c->grid.perm.p, n, 1, st));
   FSA_TRY(c->ind.alloc(2 * (size_t)mp));
   hipLaunchKernelGGL(k_pad_inducing, dim3(ceil_div(mp, 256)), dim3(256), 0, st, inducing, c->m, mp, c->ind.p);
   size_t mm = (size_t)mp * mp;
   FSA_TRY(c->Sm.alloc(mm));
   FSA_TRY(c->Lm.alloc(mm));
+  FSA_TRY(launch_sigma_m(c));  // beside the grid and pattern build
+  FSA_TRY(build_grid(c->grid, locs, n, c->gamma, st, nullptr, nullptr));
+  FSA_TRY(build_pattern(c->grid, c->grid, c->csr, st));
+  FSA_TRY(c->y.alloc(n));
+  FSA_TRY(permute_rows(y, 1, c->y.p, 1, c->grid.perm.p, n, 1, st));
   FSA_TRY(c->Lminv.alloc(mm));
   FSA_TRY(c->C.alloc(mm));
   FSA_TRY(c->LCinv.alloc(mm));
@@ -580,6 +627,7 @@ void fsa_destroy(fsa_ctx* c) {
     (void)hipEventDestroy(c->ev_deriv);
     (void)hipEventDestroy(c->ev_solve);
     (void)hipEventDestroy(c->ev_slq);
+    (void)hipEventDestroy(c->ev_fact);
     (void)hipStreamDestroy(c->st2);
   }
   pinned_put(c->hstage, c->hstage_bytes);
@@ -600,6 +648,7 @@ static fsa_status side_stream(fsa_ctx* c) {
     FSA_HIP(hipEventCreateWithFlags(&c->ev_deriv, hipEventDisableTiming));
     FSA_HIP(hipEventCreateWithFlags(&c->ev_solve, hipEventDisableTiming));
     FSA_HIP(hipEventCreateWithFlags(&c->ev_slq, hipEventDisableTiming));
+    FSA_HIP(hipEventCreateWithFlags(&c->ev_fact, hipEventDisableTiming));
   }
   return FSA_OK;
 }
@@ -950,8 +999,8 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   FSA_TRY(lowrank_reduce<double>(c->F.p, n, mp, c->Xb.p, ld, tp, nullptr, c->scr, w_fx, ldw, st));
   FSA_TRY(lowrank_reduce<double>(c->A.p, n, mp, c->U.p, ld, tp, nullptr, c->scr, w_au, ldw, st));
   FSA_TRY(lowrank_reduce<double>(c->F.p, n, mp, c->U.p, ld, tp, nullptr, c->scr, w_fu, ldw, st));
-  hipLaunchKernelGGL(k_grad_mdots, dim3(ceil_div(tp, 64)), dim3(64), 0, st, w_ax, w_fx, w_au, w_fu, mp, ldw, tp,
-                     dd.p + 3 * tp, dd.p + 4 * tp);
+  hipLaunchKernelGGL(k_grad_mdots, dim3(tp), dim3(256), 0, st, w_ax, w_fx, w_au, w_fu, mp, ldw, dd.p + 3 * tp,
+                     dd.p + 4 * tp);
   hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 3 * tp, dd.p);
   hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 4 * tp, dd.p + 2 * tp);
   hipLaunchKernelGGL(k_finalize_grad, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, c->th.s1, c->th.s2,
@@ -1202,11 +1251,6 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
   }
   double t_build = now_ms();
   if (grad && c->deriv_state == 0) FSA_TRY(launch_derivative_async(c));
-  // probe block [y, z_1 .. z_t]
-  FSA_TRY(c->B.alloc((size_t)c->n * c->ld));
-  FSA_TRY(c->Emat.alloc((size_t)c->mp * c->ldw));
-  FSA_TRY(make_probes(c->A.p, c->n, c->m, c->mp, c->D.p, c->y.p, c->grid.perm.p, c->opt.seed, c->t, c->B.p, c->ld,
-                      c->Emat.p, st));
   double ms_pcg = 0;
   fsa_status s;
   if (c->opt.precision != FSA_FP64) s = run_pcg<float>(c, &ms_pcg);
