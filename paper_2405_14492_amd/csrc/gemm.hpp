@@ -1116,6 +1116,192 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   }
 }
 
+// ------------------------------------------------------------------ SpMM on pre-scattered tiles
+// The float32 operator's pattern and values are fixed for a whole solve, so
+// the build scatters each 32-row group's nonzeros once into dense 32 x 64
+// tiles, one per 64-position chunk of the cell's 3x3 neighbourhood (in
+// Csr::key positions), tiles of a cell in (group, chunk) order.  Inside a
+// tile the values sit in the order the MFMA 16x16x4 reads them: for row
+// tile rt, 16-position step ks and lane (q, r16), the four positions
+// 16 ks + 4 q + j (j = 0..3) of row 16 rt + r16 are one 16-byte word.  The
+// product then loads its sparse operand straight into registers (no
+// scatter, no tile clearing, no keys); the chunk's block rows of X go
+// through LDS, double-buffered, so a chunk costs one workgroup barrier.
+// The stored zeros make a tile about twice the bytes of the key/value
+// entries it replaces.
+struct SpmmTile {
+  static constexpr int ROWS = 32, CH = 64, FLOATS = ROWS * CH;
+  __host__ __device__ static int offset(int r, int v) {
+    const int rt = r >> 4, r16 = r & 15, ks = v >> 4, q = (v >> 2) & 3, j = v & 3;
+    return (((rt * 4 + ks) * 64 + q * 16 + r16) << 2) + j;
+  }
+};
+
+template <int EM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_spmm_tiled(
+    const int64_t* __restrict__ rcs, int64_t ncell, const int64_t* __restrict__ ccs, GridDesc gd,
+    const int64_t* __restrict__ toff, const float* __restrict__ tiles, const float* __restrict__ X, int ldx,
+    int ncols, SpmmEpi<float> epi, double* __restrict__ dot_part, int ld_dot, int sw) {
+  constexpr int CH = SpmmTile::CH, XLD = 68, XU = CH * 16 / 256;
+  constexpr unsigned TB = SpmmTile::FLOATS * 4;  // bytes per tile
+  __shared__ __attribute__((aligned(16))) float Xs[2][CH * XLD];
+  typedef Mfma<float>::acc acc_t;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int64_t cell = xcd_cell(blockIdx.x, ncell, gd.gx, sw);
+  if (cell >= ncell) return;
+  const int c0 = blockIdx.y * 64;
+  const int64_t rb = rcs[cell], re = rcs[cell + 1];
+  const int rt = w >> 1, ct0 = (w & 1) * 2;  // this wave's tiles: rows rt*16.., columns (ct0, ct0+1)*16..
+  double dsum0 = 0.0, dsum1 = 0.0;
+  if (rb < re) {
+    int qb[3], qe[3], off[3];
+    const int V = cell_ranges(cell, gd, ccs, qb, qe, off);
+    int qlo = 0x7fffffff, qhi = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (qe[t] > qb[t]) {
+        qlo = min(qlo, qb[t]);
+        qhi = max(qhi, qe[t]);
+      }
+    if (qhi == 0) qlo = 0;
+    const __amdgpu_buffer_rsrc_t xrs = rsrc_of(X + (int64_t)qlo * ldx, (int64_t)(qhi - qlo) * ldx * 4);
+    const int nk = (V + CH - 1) / CH;
+    const int ng = (int)((re - rb + SpmmTile::ROWS - 1) / SpmmTile::ROWS);
+    const int nt = ng * nk;  // this cell's tiles, (group, chunk) order
+    const int64_t t0 = toff[cell];
+    const __amdgpu_buffer_rsrc_t trs = rsrc_of(tiles + t0 * SpmmTile::FLOATS, (int64_t)nt * TB);
+    // staging unit u = tid + 256 k: chunk row (tid >> 4) + 16 k, columns 4 (tid & 15)..+3
+    const int sc4 = (tid & 15) * 4;
+    const bool col_ok = c0 + sc4 < ncols;
+    auto load_chunk = [&](int vb, V4<float>* xr) {
+#pragma unroll
+      for (int k = 0; k < XU; ++k) {
+        const int v = vb + (tid >> 4) + 16 * k;
+        const int qq = v >= off[2] ? v - off[2] + qb[2] : (v >= off[1] ? v - off[1] + qb[1] : v - off[0] + qb[0]);
+        const unsigned o = (v < V && col_ok) ? (unsigned)((qq - qlo) * ldx + c0 + sc4) * 4u : (unsigned)BUF_OOR;
+        xr[k] = bload4<float>(xrs, o);
+      }
+    };
+    // the sparse operand of tile i for this wave (zero past the cell's tiles
+    // and for a row tile past the group's rows)
+    auto load_a = [&](int i, f4* ar) {
+      const int g = i / nk;
+      const bool on = i < nt && rt * 16 < (int)min((int64_t)SpmmTile::ROWS, re - rb - (int64_t)g * SpmmTile::ROWS);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const unsigned o = on ? (unsigned)i * TB + (unsigned)(((rt * 4 + ks) * 64 + lane) * 16) : (unsigned)BUF_OOR;
+        ar[ks] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(trs, o, 0, 0));
+      }
+    };
+    auto stage = [&](float* xs, const V4<float>* xr) {
+#pragma unroll
+      for (int k = 0; k < XU; ++k)
+        *reinterpret_cast<f4*>(&xs[((tid >> 4) + 16 * k) * XLD + sc4]) = f4{xr[k].v[0], xr[k].v[1], xr[k].v[2], xr[k].v[3]};
+    };
+    auto mma = [&](const float* xs, const f4* a, acc_t& acc0, acc_t& acc1) {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const float* xb = &xs[(ks * 16 + 4 * q) * XLD + ct0 * 16 + r16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc0 = Mfma<float>::op(a[ks][j], xb[j * XLD], acc0);
+          acc1 = Mfma<float>::op(a[ks][j], xb[j * XLD + 16], acc1);
+        }
+      }
+    };
+    V4<float> xr[XU];
+    f4 ar[4], ac[4];
+    load_chunk(0, xr);
+    load_a(0, ar);
+    acc_t acc0 = acc_t{0, 0, 0, 0}, acc1 = acc_t{0, 0, 0, 0};
+    for (int i = 0; i < nt; ++i) {
+      const int g = i / nk, k = i - g * nk;
+      // chunk buffers alternate over the whole (group, chunk) sequence: the
+      // barrier of step i - 1 orders the products of step i - 2 before this write
+      float* xs = Xs[i & 1];
+      stage(xs, xr);
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) ac[ks] = ar[ks];
+      if (i + 1 < nt) {
+        const int kn = k + 1 < nk ? k + 1 : 0;  // the next group starts again at chunk 0
+        load_chunk(kn * CH, xr);
+        load_a(i + 1, ar);
+      }
+      const int64_t g0 = rb + (int64_t)g * SpmmTile::ROWS;
+      const int nrg = (int)min((int64_t)SpmmTile::ROWS, re - g0);
+      const __amdgpu_buffer_rsrc_t yrs = rsrc_of(epi.Y + g0 * epi.ld, (int64_t)nrg * epi.ld * 4);
+      constexpr bool HD = EM == SP_PCG || EM == SP_DOT;
+      const __amdgpu_buffer_rsrc_t hrs = rsrc_of(HD ? epi.H + g0 * epi.ld : epi.Y, HD ? (int64_t)nrg * epi.ld * 4 : 0);
+      const __amdgpu_buffer_rsrc_t prs = rsrc_of(EM == SP_PCG && epi.P ? epi.P + g0 * epi.ld : epi.Y,
+                                                 EM == SP_PCG && epi.P ? (int64_t)nrg * epi.ld * 4 : 0);
+      unsigned eo[2][4];
+      float in0[2][4], in1[2][4];
+      const bool last = k == nk - 1;
+      if (last) {
+        // epilogue inputs of this wave's two tiles, in flight during the products
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int c = c0 + (ct0 + t) * 16 + r16;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            eo[t][r] = c < ncols ? (unsigned)((rt * 16 + Mfma<float>::orow(q, r)) * (int)epi.ld + c) * 4u : (unsigned)BUF_OOR;
+            if constexpr (EM == SP_ACC) in0[t][r] = bload<float>(yrs, eo[t][r]);
+            if constexpr (HD) in0[t][r] = bload<float>(hrs, eo[t][r]);
+            if constexpr (EM == SP_PCG) in1[t][r] = bload<float>(prs, eo[t][r]);
+          }
+        }
+      }
+      mma(xs, ac, acc0, acc1);
+      if (last) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          double d = 0.0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float a = t == 0 ? acc0[r] : acc1[r];
+            if constexpr (EM == SP_STORE) {
+              bstore<float>(a, yrs, eo[t][r]);
+            } else if constexpr (EM == SP_ACC) {
+              bstore<float>(a + in0[t][r], yrs, eo[t][r]);
+            } else if constexpr (EM == SP_DOT) {
+              d += (double)in0[t][r] * (double)a;  // zero past the group's rows and columns
+            } else {
+              const float v = (float)((double)a + (double)in1[t][r]);
+              bstore<float>(v, yrs, eo[t][r]);
+              d += (double)in0[t][r] * (double)v;  // zero past the group's rows and columns
+            }
+          }
+          if (t == 0) dsum0 += d;
+          else dsum1 += d;
+        }
+        acc0 = acc_t{0, 0, 0, 0};
+        acc1 = acc_t{0, 0, 0, 0};
+      }
+    }
+  }
+  if constexpr (EM >= SP_PCG) {
+    dsum0 += __shfl_xor(dsum0, 16, 64);
+    dsum0 += __shfl_xor(dsum0, 32, 64);
+    dsum1 += __shfl_xor(dsum1, 16, 64);
+    dsum1 += __shfl_xor(dsum1, 32, 64);
+    double* red = reinterpret_cast<double*>(&Xs[0][0]);
+    __syncthreads();
+    if (q == 0) {
+      red[w * 32 + r16] = dsum0;
+      red[w * 32 + 16 + r16] = dsum1;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int half = tid >> 5, o = tid & 31;
+      dot_part[cell * ld_dot + c0 + tid] = red[half * 32 + o] + red[(half + 2) * 32 + o];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ SDDMM (cell-blocked)
 // vals[e] = fn(p, q, d_pq, X_p . Y_q) for every nonzero e = (p, q) of the
 // pattern, float64.  One workgroup (8 waves) per row cell; its rows are

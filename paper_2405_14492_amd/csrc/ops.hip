@@ -469,6 +469,81 @@ static fsa_status launch_spmm_cell(const Csr& S, const Grid& rg, const Grid& cg,
   return FSA_OK;
 }
 
+// ---------------------------------------------------------------- pre-scattered tiles
+// tiles of cell c: ceil(rows / 32) groups x ceil(V / 64) neighbourhood chunks
+__global__ void k_tile_counts(const int64_t* __restrict__ cs, int64_t ncell, GridDesc gd, int* __restrict__ cnt) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int64_t nr = cs[c + 1] - cs[c];
+  int qb[3], qe[3], off[3];
+  const int V = nr > 0 ? cell_ranges(c, gd, cs, qb, qe, off) : 0;
+  cnt[c] = nr > 0 ? (int)((nr + SpmmTile::ROWS - 1) / SpmmTile::ROWS) * ((V + SpmmTile::CH - 1) / SpmmTile::CH) : 0;
+}
+
+// one workgroup per cell, one wave per row at a time: every nonzero of the
+// cell's rows goes to its (group, chunk) tile at its MFMA-order slot
+__global__ __launch_bounds__(256) void k_tile_fill(const int64_t* __restrict__ cs, int64_t ncell, GridDesc gd,
+                                                   const int64_t* __restrict__ toff, const int64_t* __restrict__ rp,
+                                                   const int* __restrict__ key, const float* __restrict__ val,
+                                                   float* __restrict__ tiles) {
+  const int64_t c = blockIdx.x;
+  if (c >= ncell) return;
+  const int64_t rb = cs[c], re = cs[c + 1];
+  if (rb >= re) return;
+  int qb[3], qe[3], off[3];
+  const int V = cell_ranges(c, gd, cs, qb, qe, off);
+  const int nk = (V + SpmmTile::CH - 1) / SpmmTile::CH;
+  float* base = tiles + toff[c] * SpmmTile::FLOATS;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t p = rb + w; p < re; p += 4) {
+    const int g = (int)((p - rb) / SpmmTile::ROWS), r = (int)((p - rb) % SpmmTile::ROWS);
+    for (int64_t e = rp[p] + lane; e < rp[p + 1]; e += 64) {
+      const int slot = key[e] & KEY_SLOT_MASK;
+      base[(int64_t)(g * nk + slot / SpmmTile::CH) * SpmmTile::FLOATS + SpmmTile::offset(r, slot % SpmmTile::CH)] =
+          val[e];
+    }
+  }
+}
+
+fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<int64_t>& toff, Buf<float>& tiles,
+                            hipStream_t st) {
+  const int64_t nc = g.ncell;
+  FSA_TRY(toff.alloc(nc + 1));
+  Buf<int> cnt;
+  Buf<int64_t> scr;
+  FSA_TRY(cnt.alloc(nc > 0 ? nc : 1));
+  hipLaunchKernelGGL(k_tile_counts, dim3(ceil_div(nc > 0 ? nc : 1, 256)), dim3(256), 0, st, g.cstart.p, nc, g.desc,
+                     cnt.p);
+  FSA_TRY(scan_counts(cnt.p, nc, toff.p, scr, st));
+  int64_t ntile = 0;
+  FSA_HIP(hipMemcpyAsync(&ntile, toff.p + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  const size_t nf = (size_t)(ntile > 0 ? ntile : 1) * SpmmTile::FLOATS;
+  FSA_TRY(tiles.alloc(nf));
+  FSA_HIP(hipMemsetAsync(tiles.p, 0, nf * sizeof(float), st));
+  if (nc > 0)
+    hipLaunchKernelGGL(k_tile_fill, dim3(nc), dim3(256), 0, st, g.cstart.p, nc, g.desc, toff.p, S.row_ptr.p, S.key.p,
+                       val, tiles.p);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+static fsa_status launch_spmm_tiled(const Grid& g, const int64_t* toff, const float* tiles, const float* X, int ldx,
+                                    int ncols, const SpmmEpi<float>& epi, double* dot_part, int ld_dot,
+                                    hipStream_t st) {
+  if (g.ncell == 0) return FSA_OK;
+  if ((ldx & 3) || (reinterpret_cast<uintptr_t>(X) & 15)) {
+    set_error("spmm: block rows must be 16-byte aligned (ld multiple of 4)");
+    return FSA_ERR_INVALID_ARG;
+  }
+  dim3 grid(8 * ceil_div(g.ncell, 8), ceil_div(ncols, 64));
+  const int sw = 32;  // cell columns per strip of the workgroup walk
+  hipLaunchKernelGGL(k_spmm_tiled<SP_PCG>, grid, dim3(256), 0, st, g.cstart.p, g.ncell, g.cstart.p, g.desc, toff,
+                     tiles, X, ldx, ncols, epi, dot_part, ld_dot, sw);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
 template <typename T>
 fsa_status spmm(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx, int ncols, T* Y,
                 int ldy, bool accumulate, hipStream_t st) {
@@ -971,8 +1046,17 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
     {
       KT_BEGIN(b, KT_SPMM);
-      FSA_TRY((launch_spmm_cell<T, SP_PCG>(*op.S, *op.grid, *op.grid, op.val, b.H, b.ld, b.ncols, epi,
-                                                          s.dot.p, ldd, st)));
+      if constexpr (sizeof(T) == 4) {
+        if (op.tiles)
+          FSA_TRY(launch_spmm_tiled(*op.grid, op.tile_off, op.tiles, (const float*)b.H, b.ld, b.ncols,
+                                    reinterpret_cast<const SpmmEpi<float>&>(epi), s.dot.p, ldd, st));
+        else
+          FSA_TRY((launch_spmm_cell<T, SP_PCG>(*op.S, *op.grid, *op.grid, op.val, b.H, b.ld, b.ncols, epi, s.dot.p,
+                                               ldd, st)));
+      } else {
+        FSA_TRY((launch_spmm_cell<T, SP_PCG>(*op.S, *op.grid, *op.grid, op.val, b.H, b.ld, b.ncols, epi, s.dot.p,
+                                             ldd, st)));
+      }
       KT_END(b, KT_SPMM);
     }
     KT_BEGIN(b, KT_SMALL);

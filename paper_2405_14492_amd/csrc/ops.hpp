@@ -115,6 +115,12 @@ fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T*
 template <typename T>
 fsa_status spmm(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx, int ncols, T* Y,
                 int ldy, bool accumulate, hipStream_t st);
+// The float32 sparse part as dense 32 x 64 tiles in MFMA order, one per
+// (32-row group, 64-position neighbourhood chunk) of each cell; toff (ncell
+// + 1) gives each cell's first tile.  The pattern's rows and columns are
+// both the grid g.
+fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<int64_t>& toff, Buf<float>& tiles,
+                            hipStream_t st);
 // out[c] = sum_p H[p][c] (S X)[p][c] for c < ncols (float64 result; S X is
 // not stored), S with the pattern of grid g on both sides
 template <typename T>
@@ -167,6 +173,10 @@ struct OpDesc {
   const uint16_t* Abf8 = nullptr;
   int kdim = 0;
   const double* Cinv = nullptr;
+  // float32 operator only (may be null): the sparse part pre-scattered into
+  // dense MFMA-order tiles (build_spmm_tiles), used by the sparse product
+  const int64_t* tile_off = nullptr;
+  const float* tiles = nullptr;
 };
 
 // Initialise: R = B, U = 0, Q0 = H = P^{-1} R, P = A^T A H, rz = r^T q.
