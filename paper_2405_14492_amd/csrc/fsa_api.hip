@@ -281,6 +281,7 @@ struct fsa_ctx {
   Buf<float> Af, valsf;
   Buf<int64_t> tile_off;  // the float32 sparse part as MFMA-order tiles (mixed modes)
   Buf<float> tiles;
+  Buf<unsigned> tile_mask;
   Buf<uint16_t> Abf;   // bfloat16 copy of A (MIXED_BF16A), point-major
   Buf<uint16_t> Abf8;  // the same, point-interleaved by 8 (bfloat16-MFMA residual pass)
   Buf<double> logdet_parts;  // [0] = 2 sum log diag L_C, [1] = sum log D
@@ -414,7 +415,7 @@ static fsa_status build_values(fsa_ctx* c) {
   if (c->opt.precision == FSA_MIXED_FP32) FSA_TRY(to_float(c->A.p, c->Af.p, c->n * (int64_t)mp, st));
   if (c->opt.precision != FSA_FP64) {
     FSA_TRY(to_float(c->vals.p, c->valsf.p, c->csr.nnz, st));
-    FSA_TRY(build_spmm_tiles(c->csr, c->grid, c->valsf.p, c->tile_off, c->tiles, st));
+    FSA_TRY(build_spmm_tiles(c->csr, c->grid, c->valsf.p, c->tile_off, c->tiles, c->tile_mask, st));
   }
   // probe block [y, z_1 .. z_t] (Section 3.3)
   FSA_TRY(c->B.alloc((size_t)c->n * c->ld));
@@ -767,6 +768,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
     op.val = reinterpret_cast<const T*>(c->valsf.p);
     op.tile_off = c->tile_off.p;
     op.tiles = c->tiles.p;
+    op.tile_mask = c->tile_mask.p;
     op.A = reinterpret_cast<const T*>(c->Af.p);  // null in MIXED_BF16A
     op.Abf = c->Abf.p;                            // null unless MIXED_BF16A
     op.Abf8 = c->Abf8.p;
@@ -1077,6 +1079,7 @@ static fsa_status run_sparse_pcg(fsa_ctx* c, const double* B, int ncols, int ld,
     op.val = reinterpret_cast<const T*>(c->valsf.p);
     op.tile_off = c->tile_off.p;
     op.tiles = c->tiles.p;
+    op.tile_mask = c->tile_mask.p;
   }
   OpDesc<double> op64;
   op64.grid = &c->grid;

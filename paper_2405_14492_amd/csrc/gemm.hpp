@@ -1128,7 +1128,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 // scatter, no tile clearing, no keys); the chunk's block rows of X go
 // through LDS, double-buffered, so a chunk costs one workgroup barrier.
 // The stored zeros make a tile about twice the bytes of the key/value
-// entries it replaces.
+// entries it replaces; a per-tile mask marks the 16 x 16 blocks (row tile,
+// 16-position step) that hold a nonzero, and a wave neither loads nor
+// multiplies the others (padding rows and positions, and neighbour points
+// beyond the taper range of all 16 rows: about a quarter of the blocks
+// with the points of each cell in ascending y).
 struct SpmmTile {
   static constexpr int ROWS = 32, CH = 64, FLOATS = ROWS * CH;
   __host__ __device__ static int offset(int r, int v) {
@@ -1140,8 +1144,9 @@ struct SpmmTile {
 template <int EM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_spmm_tiled(
     const int64_t* __restrict__ rcs, int64_t ncell, const int64_t* __restrict__ ccs, GridDesc gd,
-    const int64_t* __restrict__ toff, const float* __restrict__ tiles, const float* __restrict__ X, int ldx,
-    int ncols, SpmmEpi<float> epi, double* __restrict__ dot_part, int ld_dot, int sw) {
+    const int64_t* __restrict__ toff, const float* __restrict__ tiles, const unsigned* __restrict__ tmask,
+    const float* __restrict__ X, int ldx, int ncols, SpmmEpi<float> epi, double* __restrict__ dot_part, int ld_dot,
+    int sw) {
   constexpr int CH = SpmmTile::CH, XLD = 68, XU = CH * 16 / 256;
   constexpr unsigned TB = SpmmTile::FLOATS * 4;  // bytes per tile
   __shared__ __attribute__((aligned(16))) float Xs[2][CH * XLD];
@@ -1185,25 +1190,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         xr[k] = bload4<float>(xrs, o);
       }
     };
-    // the sparse operand of tile i for this wave (zero past the cell's tiles
-    // and for a row tile past the group's rows)
-    auto load_a = [&](int i, f4* ar) {
-      const int g = i / nk;
-      const bool on = i < nt && rt * 16 < (int)min((int64_t)SpmmTile::ROWS, re - rb - (int64_t)g * SpmmTile::ROWS);
+    // the sparse operand of tile i for this wave: its four blocks' bits of
+    // the tile mask, and the blocks that hold a nonzero (no load for the others)
+    auto load_a = [&](int i, f4* ar) -> unsigned {
+      const unsigned mk = i < nt ? (tmask[t0 + i] >> (rt * 4)) & 15u : 0u;
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
-        const unsigned o = on ? (unsigned)i * TB + (unsigned)(((rt * 4 + ks) * 64 + lane) * 16) : (unsigned)BUF_OOR;
+        const unsigned o = (mk >> ks) & 1u ? (unsigned)i * TB + (unsigned)(((rt * 4 + ks) * 64 + lane) * 16)
+                                           : (unsigned)BUF_OOR;
         ar[ks] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(trs, o, 0, 0));
       }
+      return mk;
     };
     auto stage = [&](float* xs, const V4<float>* xr) {
 #pragma unroll
       for (int k = 0; k < XU; ++k)
         *reinterpret_cast<f4*>(&xs[((tid >> 4) + 16 * k) * XLD + sc4]) = f4{xr[k].v[0], xr[k].v[1], xr[k].v[2], xr[k].v[3]};
     };
-    auto mma = [&](const float* xs, const f4* a, acc_t& acc0, acc_t& acc1) {
+    auto mma = [&](const float* xs, const f4* a, unsigned mk, acc_t& acc0, acc_t& acc1) {
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
+        if (!((mk >> ks) & 1u)) continue;  // uniform over the wave
         const float* xb = &xs[(ks * 16 + 4 * q) * XLD + ct0 * 16 + r16];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1215,7 +1222,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     V4<float> xr[XU];
     f4 ar[4], ac[4];
     load_chunk(0, xr);
-    load_a(0, ar);
+    unsigned mnext = load_a(0, ar);
     acc_t acc0 = acc_t{0, 0, 0, 0}, acc1 = acc_t{0, 0, 0, 0};
     for (int i = 0; i < nt; ++i) {
       const int g = i / nk, k = i - g * nk;
@@ -1226,10 +1233,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       __syncthreads();
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) ac[ks] = ar[ks];
+      const unsigned mcur = mnext;
       if (i + 1 < nt) {
         const int kn = k + 1 < nk ? k + 1 : 0;  // the next group starts again at chunk 0
         load_chunk(kn * CH, xr);
-        load_a(i + 1, ar);
+        mnext = load_a(i + 1, ar);
       }
       const int64_t g0 = rb + (int64_t)g * SpmmTile::ROWS;
       const int nrg = (int)min((int64_t)SpmmTile::ROWS, re - g0);
@@ -1255,7 +1263,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
           }
         }
       }
-      mma(xs, ac, acc0, acc1);
+      mma(xs, ac, mcur, acc0, acc1);
       if (last) {
 #pragma unroll
         for (int t = 0; t < 2; ++t) {

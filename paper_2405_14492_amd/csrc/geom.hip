@@ -71,15 +71,23 @@ __global__ void k_scatter_cell(const int* __restrict__ cell, int64_t n, int* __r
 
 // Final slot of a point: start of its cell plus the number of points of the
 // same cell with a smaller original index (stable, deterministic).
-__global__ void k_rank_cell(const int* __restrict__ tmp, const int* __restrict__ cell,
+// Points of a cell in ascending y (ties by index): the sparse product's
+// 16 x 16 blocks of a row group against a neighbour cell then often fall
+// entirely outside the taper range and are skipped.
+__global__ void k_rank_cell(const int* __restrict__ tmp, const int* __restrict__ cell, const double* __restrict__ locs,
                             const int64_t* __restrict__ cstart, int64_t n, int* __restrict__ perm) {
   int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= n) return;
   int i = tmp[s];
   int c = cell[i];
+  const double yi = locs[2 * (int64_t)i + 1];
   int64_t b = cstart[c], e = cstart[c + 1];
   int64_t r = 0;
-  for (int64_t k = b; k < e; ++k) r += (tmp[k] < i);
+  for (int64_t k = b; k < e; ++k) {
+    const int j = tmp[k];
+    const double yj = locs[2 * (int64_t)j + 1];
+    r += (yj < yi || (yj == yi && j < i)) ? 1 : 0;
+  }
   perm[b + r] = i;
 }
 
@@ -239,7 +247,7 @@ fsa_status build_grid(Grid& g, const double* locs, int64_t n, double gamma, hipS
   hipLaunchKernelGGL(k_cstart_to_cursor, dim3(ceil_div(ncell, 256)), dim3(256), 0, st, g.cstart.p, ncell,
                      cursor.p);
   hipLaunchKernelGGL(k_scatter_cell, dim3(nb), dim3(256), 0, st, g.cell.p, n, cursor.p, tmp.p);
-  hipLaunchKernelGGL(k_rank_cell, dim3(nb), dim3(256), 0, st, tmp.p, g.cell.p, g.cstart.p, n, g.perm.p);
+  hipLaunchKernelGGL(k_rank_cell, dim3(nb), dim3(256), 0, st, tmp.p, g.cell.p, locs, g.cstart.p, n, g.perm.p);
   hipLaunchKernelGGL(k_gather_sorted, dim3(nb), dim3(256), 0, st, locs, g.perm.p, n, g.xs.p, g.iperm.p);
   FSA_HIP(hipGetLastError());
   FSA_HIP(hipStreamSynchronize(st));  // tmp/cursor go back to the pool

@@ -505,8 +505,26 @@ __global__ __launch_bounds__(256) void k_tile_fill(const int64_t* __restrict__ c
   }
 }
 
+// bit rt * 4 + ks of mask[t]: block (row tile rt, 16-position step ks) of
+// tile t holds a nonzero (one wave per tile; block b is words b*64 .. +63)
+__global__ __launch_bounds__(256) void k_tile_mask(const float* __restrict__ tiles, int64_t ntile,
+                                                   unsigned* __restrict__ mask) {
+  const int64_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= ntile) return;
+  const f4* w4 = reinterpret_cast<const f4*>(tiles + t * SpmmTile::FLOATS);
+  unsigned m = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const f4 v = w4[b * 64 + lane];
+    const bool nz = v[0] != 0.f || v[1] != 0.f || v[2] != 0.f || v[3] != 0.f;
+    if (__any(nz)) m |= 1u << b;
+  }
+  if (lane == 0) mask[t] = m;
+}
+
 fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<int64_t>& toff, Buf<float>& tiles,
-                            hipStream_t st) {
+                            Buf<unsigned>& tmask, hipStream_t st) {
   const int64_t nc = g.ncell;
   FSA_TRY(toff.alloc(nc + 1));
   Buf<int> cnt;
@@ -524,13 +542,16 @@ fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<i
   if (nc > 0)
     hipLaunchKernelGGL(k_tile_fill, dim3(nc), dim3(256), 0, st, g.cstart.p, nc, g.desc, toff.p, S.row_ptr.p, S.key.p,
                        val, tiles.p);
+  FSA_TRY(tmask.alloc(ntile > 0 ? ntile : 1));
+  if (ntile > 0)
+    hipLaunchKernelGGL(k_tile_mask, dim3(ceil_div(ntile, 4)), dim3(256), 0, st, tiles.p, ntile, tmask.p);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
 
-static fsa_status launch_spmm_tiled(const Grid& g, const int64_t* toff, const float* tiles, const float* X, int ldx,
-                                    int ncols, const SpmmEpi<float>& epi, double* dot_part, int ld_dot,
-                                    hipStream_t st) {
+static fsa_status launch_spmm_tiled(const Grid& g, const int64_t* toff, const float* tiles, const unsigned* tmask,
+                                    const float* X, int ldx, int ncols, const SpmmEpi<float>& epi, double* dot_part,
+                                    int ld_dot, hipStream_t st) {
   if (g.ncell == 0) return FSA_OK;
   if ((ldx & 3) || (reinterpret_cast<uintptr_t>(X) & 15)) {
     set_error("spmm: block rows must be 16-byte aligned (ld multiple of 4)");
@@ -539,7 +560,7 @@ static fsa_status launch_spmm_tiled(const Grid& g, const int64_t* toff, const fl
   dim3 grid(8 * ceil_div(g.ncell, 8), ceil_div(ncols, 64));
   const int sw = 32;  // cell columns per strip of the workgroup walk
   hipLaunchKernelGGL(k_spmm_tiled<SP_PCG>, grid, dim3(256), 0, st, g.cstart.p, g.ncell, g.cstart.p, g.desc, toff,
-                     tiles, X, ldx, ncols, epi, dot_part, ld_dot, sw);
+                     tiles, tmask, X, ldx, ncols, epi, dot_part, ld_dot, sw);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -1048,7 +1069,7 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
       KT_BEGIN(b, KT_SPMM);
       if constexpr (sizeof(T) == 4) {
         if (op.tiles)
-          FSA_TRY(launch_spmm_tiled(*op.grid, op.tile_off, op.tiles, (const float*)b.H, b.ld, b.ncols,
+          FSA_TRY(launch_spmm_tiled(*op.grid, op.tile_off, op.tiles, op.tile_mask, (const float*)b.H, b.ld, b.ncols,
                                     reinterpret_cast<const SpmmEpi<float>&>(epi), s.dot.p, ldd, st));
         else
           FSA_TRY((launch_spmm_cell<T, SP_PCG>(*op.S, *op.grid, *op.grid, op.val, b.H, b.ld, b.ncols, epi, s.dot.p,

@@ -120,7 +120,7 @@ fsa_status spmm(const Csr& S, const Grid& rg, const Grid& cg, const T* val, cons
 // + 1) gives each cell's first tile.  The pattern's rows and columns are
 // both the grid g.
 fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<int64_t>& toff, Buf<float>& tiles,
-                            hipStream_t st);
+                            Buf<unsigned>& tmask, hipStream_t st);
 // out[c] = sum_p H[p][c] (S X)[p][c] for c < ncols (float64 result; S X is
 // not stored), S with the pattern of grid g on both sides
 template <typename T>
@@ -177,6 +177,7 @@ struct OpDesc {
   // dense MFMA-order tiles (build_spmm_tiles), used by the sparse product
   const int64_t* tile_off = nullptr;
   const float* tiles = nullptr;
+  const unsigned* tile_mask = nullptr;  // per tile: its 16 x 16 blocks that hold a nonzero
 };
 
 // Initialise: R = B, U = 0, Q0 = H = P^{-1} R, P = A^T A H, rz = r^T q.

@@ -370,3 +370,33 @@ def test_kernel_timer_class_mask(F):
         assert all(st["kernel_ms"][k] > 0 for k in timed)
         assert abs(nll - out[0][0]) <= 1e-12 * abs(out[0][0])
         np.testing.assert_allclose(grad, out[0][1], rtol=1e-12, atol=0)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["dense_cells_n3000_m60", "exp_clustered_n2000_m70"])
+def test_float32_operator_tracks_float64(F, name):
+    """The float32 iteration's operator (the sparse product on pre-scattered
+    MFMA-order tiles, here with cells of more than one 32-row group) against
+    the float64 one: with no residual replacement, the first Lanczos
+    coefficients of the float32 solve match the float64 solve's to float32
+    accuracy.  A misplaced tile entry moves them by orders of magnitude more."""
+    cases = dict(CASES, dense_cells_n3000_m60=dict(n=3000, m=60, kind=O.MATERN32, rho=0.1, s2=0.1, n_gamma=150,
+                                                   seed=7))
+    say("case", name)
+    locs, y, theta, ind, gamma = case(**cases[name])
+    h = gamma * (1.0 + 2.0 ** -20)
+    cell = np.floor((locs - locs.min(0)) / h).astype(np.int64)
+    counts = np.unique(cell[:, 0] * 100003 + cell[:, 1], return_counts=True)[1]
+    say("largest cell", counts.max(), "points")
+    assert counts.max() > 32  # some cells hold two or more row groups
+    rec = {}
+    for prec in (F.FP64, F.MIXED_FP32):
+        with F.FSA(locs, y, theta, ind, gamma, num_probes=4, seed=3, fixed_iter=6, precision=prec,
+                   rr_period=0) as f:
+            f.nll_grad(with_grad=False)
+            rec[prec] = f.export_lanczos()
+    for key in ("alpha", "beta"):
+        a64, a32 = rec[F.FP64][key][:6], rec[F.MIXED_FP32][key][:6]
+        err = np.abs(a32 - a64).max() / np.abs(a64).max()
+        say(key, "max rel diff", err)
+        assert err < 1e-4, key
