@@ -41,9 +41,9 @@ def log(*a):
 
 # rocprofv3 kernel names of the four PCG kernel classes, per element type
 KERNEL_NAMES = {
-    "f32": ["k_spmm_dense<float, 2>", "k_reduce_gemm_f32<float, true, 1>", "k_rows_gemm_f32<float, true, 2>",
+    "f32": ["k_spmm_tiled<2>", "k_reduce_gemm_f32<float, true, 1>", "k_rows_gemm_f32<float, true, 2>",
             "k_pcg_hupdate<float, float>"],
-    "bf16a": ["k_spmm_dense<float, 2>", "k_reduce_bf16<true, 1>", "k_rows_bf16<2>", "k_pcg_hupdate<float, float>"],
+    "bf16a": ["k_spmm_tiled<2>", "k_reduce_bf16<true, 1>", "k_rows_bf16<2>", "k_pcg_hupdate<float, float>"],
     "f64": ["k_spmm_dense<double, 2>", "k_reduce_gemm_f64<true, 1>",
             "k_rows_gemm_f64<true, 2, 3>", "k_pcg_hupdate<double, double>"],
 }
@@ -58,7 +58,9 @@ def kernel_work(k, n, m, tp, nnz, b, ba=None):
     Every operand counted once."""
     blk = n * tp
     ba = b if ba is None else ba
-    if k == 0:   # V = S H + P, h.v: key (4 B) + value per nonzero, H in, P in, V out, row pointers
+    if k == 0:   # V = S H + P, h.v: key (4 B) + value per nonzero, H in, P in, V out, row pointers (the
+        #          float32 product reads the same values as MFMA-order tiles, zeros included: the
+        #          algorithmic figure stays that of the compressed rows)
         return nnz * (b + 4) + 8 * (n + 1) + 3 * blk * b, 2.0 * nnz * tp
     if k == 1:   # r -= a v (R in/out, V in), W = A D^-1 r: A (n x m) once, D^-1
         return n * m * ba + 3 * blk * b + 8 * n, 2.0 * n * m * tp
