@@ -290,6 +290,30 @@ class FSA:
         low = dSmn_T @ KX + self.K_T @ (dSmn_T.T @ X) - self.K_T @ (dSm @ KX)
         return dS @ X + low
 
+    def precond_dmatvec(self, which, X):
+        """(dP/dtheta) X for the FITC preconditioner P = D_s + Sigma_l (eq.
+        eqfitcp): D_s = diag(Sigma~_s), so dP/dtheta = diag(dSigma~_s/dtheta)
+        + dSigma_l/dtheta, and dP/dsigma^2 = I."""
+        if which == 2:
+            return X.copy()
+        dSm, dSmn_T, dS = self._deriv(which)
+        dD = dS.diagonal()
+        KX = self.K_T.T @ X
+        low = dSmn_T @ KX + self.K_T @ (dSmn_T.T @ X) - self.K_T @ (dSm @ KX)
+        return (dD[:, None] * X if X.ndim == 2 else dD * X) + low
+
+    def precond_dense(self):
+        """P as a dense n x n matrix (small n only)."""
+        return np.diag(self.D) + self.Smn_T @ sla.cho_solve(self.chol_m, self.Smn_T.T)
+
+    def precond_trace_deriv(self):
+        """Tr(P^{-1} dP/dtheta) for theta = (sigma1^2, rho, sigma^2), from the
+        dense definition (small n only): the deterministic term of the
+        control variate (App. E)."""
+        P = self.precond_dense()
+        eye = np.eye(self.n)
+        return np.array([np.trace(np.linalg.solve(P, self.precond_dmatvec(k, eye))) for k in range(3)])
+
 
 class FSARows:
     """The quantities of FSA for requested rows only, for inputs too large to
@@ -461,13 +485,23 @@ def probes(model, t, seed):
 
 
 def nll_grad(model, y, num_probes, seed, tol=1e-8, max_iter=1000, fixed_iter=0,
-             slq_weight_n=False, with_grad=True):
+             slq_weight_n=False, with_grad=True, control_variate=None):
     """Negative log-likelihood and its gradient in (sigma1^2, rho, sigma^2).
 
     log det: preconditioned SLQ, (1/t) sum_i w_i e_1^T log(T_i) e_1 + log det P
     (Section 3.3); quadratic term y^T Sigma~^{-1} y from the same PCG run;
     gradient: (1/2) STE of Tr(Sigma~^{-1} dSigma~) with P^{-1} z_i (Section 3.3)
-    minus (1/2) u^T dSigma~ u, u = Sigma~^{-1} y (eq. NEGLLDNEGLLFSA)."""
+    minus (1/2) u^T dSigma~ u, u = Sigma~^{-1} y (eq. NEGLLDNEGLLFSA).
+
+    control_variate (App. E, eq. Troptc): None for the plain estimate;
+    otherwise subtract c * b_i, b_i = (P^{-1} z_i)^T dP/dtheta (P^{-1} z_i), from
+    each sample a_i and add c Tr(P^{-1} dP/dtheta), per parameter, with
+    "one": c = 1;
+    "opt": c = sum_i (a_i - mean a)(b_i - mean b) / sum_i (b_i - mean b)^2, the
+           coefficient that minimises the sample variance of a_i - c b_i
+           (the printed c_opt with its denominator centred, the reading under
+           which it is the optimal coefficient the text describes);
+    "opt_printed": c = sum_i (a_i - mean a) b_i / sum_i b_i^2, as printed."""
     n = model.n
     y = np.asarray(y, dtype=np.float64)
     Z = probes(model, num_probes, seed)
@@ -488,12 +522,31 @@ def nll_grad(model, y, num_probes, seed, tol=1e-8, max_iter=1000, fixed_iter=0,
         X = np.column_stack([u, res.Q0[:, 1:]])
         grad = np.empty(3)
         trace_terms = np.empty((3, num_probes))
+        quad_terms = np.empty(3)
         for k in range(3):
             dX = model.dmatvec(k, X)
             trace_terms[k] = np.einsum("ij,ij->j", res.U[:, 1:], dX[:, 1:])
-            grad[k] = 0.5 * np.mean(trace_terms[k]) - 0.5 * float(u @ dX[:, 0])
-        out["grad"] = grad
+            quad_terms[k] = float(u @ dX[:, 0])
+            grad[k] = 0.5 * np.mean(trace_terms[k]) - 0.5 * quad_terms[k]
         out["trace_terms"] = trace_terms
+        if control_variate is not None:
+            Xp = res.Q0[:, 1:]  # P^{-1} z_i
+            cv_terms = np.array([np.einsum("ij,ij->j", Xp, model.precond_dmatvec(k, Xp)) for k in range(3)])
+            trace_P = model.precond_trace_deriv()
+            c = np.ones(3)
+            for k in range(3):
+                a, b = trace_terms[k], cv_terms[k]
+                if control_variate == "opt":
+                    bc = b - np.mean(b)
+                    c[k] = np.sum((a - np.mean(a)) * bc) / np.sum(bc * bc)
+                elif control_variate == "opt_printed":
+                    c[k] = np.sum((a - np.mean(a)) * b) / np.sum(b * b)
+                elif control_variate != "one":
+                    raise ValueError("control_variate must be None, 'one', 'opt' or 'opt_printed'")
+                est = np.mean(a - c[k] * b) + c[k] * trace_P[k]
+                grad[k] = 0.5 * est - 0.5 * quad_terms[k]
+            out.update(cv_terms=cv_terms, trace_P=trace_P, cv_c=c)
+        out["grad"] = grad
     return out
 
 

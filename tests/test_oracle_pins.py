@@ -395,6 +395,106 @@ def test_stochastic_gradient_matches_exact_trace():
         assert abs(out["grad"][k] - exact) < 4 * se + 1e-5 * abs(exact), (k, out["grad"][k], exact, se)
 
 
+# ---------------------------------------------------------------- control variate (App. E)
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_preconditioner_derivative_equals_finite_difference(which):
+    """dP/dtheta X against a central difference of the dense FITC matrix
+    D_s + Sigma_l (eq. eqfitcp) built from the definitions."""
+    locs, ind, theta, gamma = small_case(n=200, m=20, kind=M32, rho=0.09, s1=1.3, s2=0.15)
+    mdl = O.FSA(locs, ind, theta, gamma)
+    X = np.random.default_rng(11).standard_normal((200, 3))
+    th = list(theta)
+    h = 1e-5 * th[which + 1]
+    th[which + 1] += h
+    Pp = DF.dense_fitc(locs, ind, tuple(th), gamma)
+    th[which + 1] -= 2 * h
+    Pm = DF.dense_fitc(locs, ind, tuple(th), gamma)
+    ref = (Pp - Pm) / (2 * h) @ X
+    got = mdl.precond_dmatvec(which, X)
+    np.testing.assert_allclose(got, ref, rtol=2e-6, atol=2e-6 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("kind", [EXP, M32])
+def test_preconditioner_trace_is_derivative_of_its_logdet(kind):
+    """Jacobi's formula: Tr(P^{-1} dP/dtheta) = d log det P / dtheta, the
+    right side by central differences of slogdet of the dense FITC matrix."""
+    locs, ind, theta, gamma = small_case(n=180, m=18, kind=kind, rho=0.1, s1=0.8, s2=0.2)
+    got = O.FSA(locs, ind, theta, gamma).precond_trace_deriv()
+    for k in range(3):
+        th = list(theta)
+        h = 1e-5 * th[k + 1]
+        th[k + 1] += h
+        lp = np.linalg.slogdet(DF.dense_fitc(locs, ind, tuple(th), gamma))[1]
+        th[k + 1] -= 2 * h
+        lm = np.linalg.slogdet(DF.dense_fitc(locs, ind, tuple(th), gamma))[1]
+        fd = (lp - lm) / (2 * h)
+        assert abs(got[k] - fd) < 1e-6 * max(1.0, abs(fd)), (k, got[k], fd)
+
+
+def test_c_opt_is_least_squares_slope():
+    """The control-variate coefficients as regression slopes of the samples
+    a_i on b_i: c_opt (centred reading) is the ordinary least-squares slope
+    with intercept, so a_i - c b_i has the smallest sample variance; the
+    printed form minimises sum_i (a_i - mean a - c b_i)^2, the slope through
+    the origin of the centred samples."""
+    locs, ind, theta, gamma = small_case(n=250, m=25, kind=EXP, rho=0.12, s1=1.0, s2=0.1)
+    mdl = O.FSA(locs, ind, theta, gamma)
+    y = G.rff_response(locs, EXP, 1.0, 0.12, 0.1, 300, 31)
+    out = O.nll_grad(mdl, y, 12, 32, tol=1e-11, control_variate="opt")
+    outp = O.nll_grad(mdl, y, 12, 32, tol=1e-11, control_variate="opt_printed")
+    for k in range(3):
+        a, b = out["trace_terms"][k], out["cv_terms"][k]
+        slope = np.polyfit(b, a, 1)[0]
+        assert abs(out["cv_c"][k] - slope) <= 1e-9 * max(1.0, abs(slope))
+        v = lambda c: np.var(a - c * b)
+        assert v(out["cv_c"][k]) <= min(v(out["cv_c"][k] * 1.01), v(out["cv_c"][k] * 0.99), v(1.0), v(0.0))
+        slope0 = np.linalg.lstsq(b[:, None], a - a.mean(), rcond=None)[0][0]
+        assert abs(outp["cv_c"][k] - slope0) <= 1e-12 * max(1.0, abs(slope0))
+        # b_i with exact solves: (P^{-1} z_i)^T dP (P^{-1} z_i)
+    P = DF.dense_fitc(locs, ind, theta, gamma)
+    Z = O.probes(mdl, 12, 32)
+    X = np.linalg.solve(P, Z)
+    th = list(theta)
+    h = 1e-5 * th[2]
+    th[2] += h
+    Pp = DF.dense_fitc(locs, ind, tuple(th), gamma)
+    th[2] -= 2 * h
+    dP = (Pp - DF.dense_fitc(locs, ind, tuple(th), gamma)) / (2 * h)
+    np.testing.assert_allclose(out["cv_terms"][1], np.einsum("ij,ij->j", X, dP @ X), rtol=1e-5)
+
+
+def test_control_variate_is_unbiased_and_reduces_variance():
+    """Over independent probe sets the plain and control-variate gradient
+    estimates all centre on the dense gradient (within four standard
+    errors), and c_opt lowers the spread of the sigma1^2 and rho components
+    (App. E, Fig. GradNEGLL)."""
+    locs, ind, theta, gamma = small_case(n=200, m=20, kind=M32, rho=0.1, s1=1.0, s2=0.1)
+    mdl = O.FSA(locs, ind, theta, gamma)
+    y = G.rff_response(locs, M32, 1.0, 0.1, 0.1, 300, 33)
+    S = DF.dense_fsa(locs, ind, theta, gamma)
+    Si = np.linalg.inv(S)
+    u = Si @ y
+    exact = []
+    for k in range(3):
+        dS = DF.fd_operator(locs, ind, theta, gamma, k)
+        exact.append(0.5 * np.trace(Si @ dS) - 0.5 * u @ dS @ u)
+    est = {cv: [] for cv in (None, "one", "opt", "opt_printed")}
+    for seed in range(40):
+        for cv in est:
+            est[cv].append(O.nll_grad(mdl, y, 8, 100 + seed, tol=1e-11, control_variate=cv)["grad"])
+    sd = {cv: np.std(np.array(v), axis=0, ddof=1) for cv, v in est.items()}
+    for cv, v in est.items():
+        m = np.mean(np.array(v), axis=0)
+        assert np.all(np.abs(m - exact) < 4 * sd[cv] / math.sqrt(40) + 1e-6 * np.abs(exact)), (cv, m, exact)
+    # sigma1^2 and rho: b_i tracks a_i and the spread falls (by about 2.3x
+    # for rho here); sigma^2 (b_i = |P^{-1} z_i|^2) gains little, and c
+    # estimated from eight samples may cost a few percent there
+    assert np.all(sd["opt"][:2] < 0.8 * sd[None][:2]), (sd["opt"], sd[None])
+    assert sd["opt"][2] < 1.1 * sd[None][2], (sd["opt"], sd[None])
+    assert np.all(sd["opt"][:2] < 1.05 * sd["one"][:2]), (sd["opt"], sd["one"])
+
+
 # ---------------------------------------------------------------- predictive variances
 
 def test_algorithm1_with_exact_diagonal_equals_dense():
