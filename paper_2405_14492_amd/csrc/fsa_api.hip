@@ -194,31 +194,176 @@ __global__ void k_finalize_grad(int ncols, const double* __restrict__ uSX, const
 // (kdim x ldw, row-major): with a = A^T x, f = F^T x, au = A^T u, fu = F^T u,
 // u.(A A^T x) = au . a and u.((F A^T + A F^T) x) = fu . a + au . f.
 // One workgroup (256 threads) per column, fixed-order tree sum over k.
+// Also |a|^2 and f . a (the control variate's low-rank terms).
 __global__ __launch_bounds__(256) void k_grad_mdots(const double* __restrict__ a, const double* __restrict__ f,
                                                     const double* __restrict__ au, const double* __restrict__ fu,
                                                     int kdim, int ldw, double* __restrict__ lr_sigma,
-                                                    double* __restrict__ lr_drho) {
-  __shared__ double r0[256], r1[256];
+                                                    double* __restrict__ lr_drho, double* __restrict__ aa,
+                                                    double* __restrict__ fa) {
+  __shared__ double r[4][256];
   const int c = blockIdx.x, t = threadIdx.x;
-  double s0 = 0.0, s1 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int k = t; k < kdim; k += 256) {
     const int64_t o = (int64_t)k * ldw + c;
     s0 += au[o] * a[o];
     s1 += fu[o] * a[o] + au[o] * f[o];
+    s2 += a[o] * a[o];
+    s3 += f[o] * a[o];
   }
-  r0[t] = s0;
-  r1[t] = s1;
+  r[0][t] = s0;
+  r[1][t] = s1;
+  r[2][t] = s2;
+  r[3][t] = s3;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (t < h) {
-      r0[t] += r0[t + h];
-      r1[t] += r1[t + h];
-    }
+    if (t < h)
+      for (int j = 0; j < 4; ++j) r[j][t] += r[j][t + h];
     __syncthreads();
   }
   if (t == 0) {
-    lr_sigma[c] = r0[0];
-    lr_drho[c] = r1[0];
+    lr_sigma[c] = r[0][0];
+    lr_drho[c] = r[1][0];
+    aa[c] = r[2][0];
+    fa[c] = r[3][0];
+  }
+}
+
+// ---- control variate (App. E) ----
+// out[p] = the value of row p's diagonal entry (0 if the pattern has none)
+__global__ void k_csr_diag(const int64_t* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ v,
+                           int64_t n, double* __restrict__ out) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double d = 0.0;
+  for (int64_t e = rp[p]; e < rp[p + 1]; ++e)
+    if (col[e] == (int)p) d = v[e];
+  out[p] = d;
+}
+
+// Per-workgroup partial sums for the exact Tr(P^{-1} dP/dtheta): with rows
+// ba_p = L_C^{-1} A_p and bf_p = L_C^{-1} F_p (so s_p = |ba_p|^2 = A_p C^{-1} A_p^T and
+// r_p = ba_p . bf_p = A_p C^{-1} F_p^T),
+//   [0] sum 1/D_p  [1] sum s_p/D_p^2  [2] sum dD_p/D_p  [3] sum dD_p s_p/D_p^2  [4] sum r_p/D_p.
+// One wave per point (kdim a multiple of 64), fixed order throughout.
+__global__ __launch_bounds__(256) void k_cv_trace_parts(const double* __restrict__ BA, const double* __restrict__ BF,
+                                                        const double* __restrict__ D, const double* __restrict__ dD,
+                                                        int64_t n, int kdim, double* __restrict__ part) {
+  __shared__ double red[4][5];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t p = blockIdx.x * 4 + w; p < n; p += (int64_t)gridDim.x * 4) {
+    double sa = 0.0, sr = 0.0;
+    for (int k = lane; k < kdim; k += 64) {
+      const double a = BA[p * kdim + k];
+      sa += a * a;
+      sr += a * BF[p * kdim + k];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      sa += __shfl_xor(sa, o, 64);
+      sr += __shfl_xor(sr, o, 64);
+    }
+    const double d = D[p], dd = dD[p];
+    acc[0] += 1.0 / d;
+    acc[1] += sa / (d * d);
+    acc[2] += dd / d;
+    acc[3] += dd * sa / (d * d);
+    acc[4] += sr / d;
+  }
+  if (lane == 0)
+    for (int j = 0; j < 5; ++j) red[w][j] = acc[j];
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int j = threadIdx.x;
+    part[(int64_t)blockIdx.x * 5 + j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+  }
+}
+
+__global__ void k_cv_trace_final(const double* __restrict__ part, int nparts, double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= 5) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * 5 + j];
+  out[j] = s;
+}
+
+// Per column c of X (n x ld): partial sums of x^2, D x^2 and dD x^2 per
+// workgroup, planes [3][gridDim.x][ldp] (coalesced over columns).
+__global__ __launch_bounds__(256) void k_cv_xdots(const double* __restrict__ X, int64_t n, int ld, int ncols,
+                                                  const double* __restrict__ D, const double* __restrict__ dD,
+                                                  double* __restrict__ part, int ldp) {
+  __shared__ double red[3][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + lane;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (c < ncols)
+    for (int64_t p = (int64_t)blockIdx.x * 4 + w; p < n; p += (int64_t)gridDim.x * 4) {
+      const double x = X[p * ld + c];
+      const double x2 = x * x;
+      a0 += x2;
+      a1 += D[p] * x2;
+      a2 += dD[p] * x2;
+    }
+  red[0][w][lane] = a0;
+  red[1][w][lane] = a1;
+  red[2][w][lane] = a2;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int64_t o = (int64_t)blockIdx.x * ldp + blockIdx.y * 64 + threadIdx.x;
+    const int64_t plane = (int64_t)gridDim.x * ldp;
+    for (int j = 0; j < 3; ++j)
+      part[j * plane + o] = (red[j][0][threadIdx.x] + red[j][1][threadIdx.x]) + (red[j][2][threadIdx.x] + red[j][3][threadIdx.x]);
+  }
+}
+
+// The gradient with the control variate (App. E, eq. Troptc), one thread.
+// Per probe column i >= 1: samples a_k and control terms b_k,
+//   a_0 = (u.Sx - s2 u.x)/s1, a_1 = u.dx, a_2 = u.x;
+//   b_0 = (x.Dx + |A^T x|^2 - s2 |x|^2)/s1, b_1 = x.dD x + 2 (F^T x).(A^T x), b_2 = |x|^2;
+// exact traces from tr5 (k_cv_trace_parts): T_2 = Tr P^{-1} = tr5[0] - tr5[1],
+// T_0 = (n - s2 T_2)/s1, T_1 = tr5[2] - tr5[3] + 2 tr5[4].
+// out: [0..2] gradient, [3..5] trace estimates, [6..8] quadratic terms,
+// [9..11] coefficients c, [12..14] T.
+__global__ void k_finalize_grad_cv(int ncols, const double* __restrict__ uSX, const double* __restrict__ uX,
+                                   const double* __restrict__ uDX, const double* __restrict__ xx,
+                                   const double* __restrict__ xDx, const double* __restrict__ xdDx,
+                                   const double* __restrict__ ax2, const double* __restrict__ fax,
+                                   const double* __restrict__ tr5, double n, double s1, double s2, int mode,
+                                   double* __restrict__ out) {
+  const double T2 = tr5[0] - tr5[1];
+  const double T[3] = {(n - s2 * T2) / s1, tr5[2] - tr5[3] + 2.0 * tr5[4], T2};
+  const double t = (double)(ncols - 1);
+  double ma[3] = {0, 0, 0}, mb[3] = {0, 0, 0};
+  for (int c = 1; c < ncols; ++c) {
+    const double a[3] = {(uSX[c] - s2 * uX[c]) / s1, uDX[c], uX[c]};
+    const double b[3] = {(xDx[c] + ax2[c] - s2 * xx[c]) / s1, xdDx[c] + 2.0 * fax[c], xx[c]};
+    for (int k = 0; k < 3; ++k) {
+      ma[k] += a[k];
+      mb[k] += b[k];
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    ma[k] /= t;
+    mb[k] /= t;
+  }
+  double num[3] = {0, 0, 0}, den[3] = {0, 0, 0};
+  for (int c = 1; c < ncols; ++c) {
+    const double a[3] = {(uSX[c] - s2 * uX[c]) / s1, uDX[c], uX[c]};
+    const double b[3] = {(xDx[c] + ax2[c] - s2 * xx[c]) / s1, xdDx[c] + 2.0 * fax[c], xx[c]};
+    for (int k = 0; k < 3; ++k) {
+      const double bc = mode == FSA_CV_OPT ? b[k] - mb[k] : b[k];
+      num[k] += (a[k] - ma[k]) * bc;
+      den[k] += bc * bc;
+    }
+  }
+  const double qd[3] = {(uSX[0] - s2 * uX[0]) / s1, uDX[0], uX[0]};
+  for (int k = 0; k < 3; ++k) {
+    const double cc = mode == FSA_CV_ONE ? 1.0 : (den[k] > 0.0 ? num[k] / den[k] : 0.0);
+    const double est = ma[k] - cc * mb[k] + cc * T[k];
+    out[k] = 0.5 * est - 0.5 * qd[k];
+    out[3 + k] = est;
+    out[6 + k] = qd[k];
+    out[9 + k] = cc;
+    out[12 + k] = T[k];
   }
 }
 
@@ -317,6 +462,9 @@ struct fsa_ctx {
   bool timer_pending = false;  // the last solve's kernel events are not yet summed
   // gradient
   Buf<double> F, dvals, Xb, tmp, dSm, Ework;
+  // control variate (options.grad_cv): diagonal of the derivative values,
+  // L_C^{-1} A and L_C^{-1} F by rows, and the five trace sums (per theta)
+  Buf<double> dD, cvBA, cvBF, cvpart, cvtr;
   Scratch scr;
   BlasHandle blas;
   KernelTimer timer;
@@ -502,6 +650,7 @@ static fsa_status validate_build(int64_t n, int32_t d, const fsa_theta* theta, i
     if (opt->max_iter < 1 && opt->fixed_iter < 1) { set_error("max_iter must be >= 1"); return FSA_ERR_INVALID_ARG; }
     if (!(opt->cg_rel_tol >= 0)) { set_error("cg_rel_tol must be >= 0"); return FSA_ERR_INVALID_ARG; }
     if (opt->precision != FSA_FP64 && opt->precision != FSA_MIXED_FP32 && opt->precision != FSA_MIXED_BF16A) { set_error("unknown precision"); return FSA_ERR_INVALID_ARG; }
+    if (opt->grad_cv < FSA_CV_NONE || opt->grad_cv > FSA_CV_OPT_PRINTED) { set_error("unknown grad_cv"); return FSA_ERR_INVALID_ARG; }
     if (!(opt->sigma_m_jitter >= 0)) { set_error("sigma_m_jitter must be >= 0"); return FSA_ERR_INVALID_ARG; }
   }
   return FSA_OK;
@@ -924,6 +1073,28 @@ static fsa_status build_derivative(fsa_ctx* c, hipStream_t st) {
   FSA_TRY(c->dvals.alloc(c->csr.nnz));
   FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, c->F.p, c->F.p, mp, c->th, c->gamma, true, true,
                           c->dvals.p, nullptr, st));
+  if (c->opt.grad_cv != FSA_CV_NONE) {
+    // Tr(P^{-1} dP/dtheta) by Woodbury (App. E, F): with C = L_C L_C^T,
+    // Tr P^{-1} = sum 1/D - sum |L_C^{-1} A_p|^2 / D^2, Tr(P^{-1} dD) likewise
+    // weighted by dD, and Tr(P^{-1}(F A^T + A F^T)) = 2 Tr(C^{-1} A^T D^{-1} F)
+    const int64_t n = c->n;
+    FSA_TRY(c->dD.alloc(n));
+    hipLaunchKernelGGL(k_csr_diag, dim3(ceil_div(n, 256)), dim3(256), 0, st, c->csr.row_ptr.p, c->csr.col.p,
+                       c->dvals.p, n, c->dD.p);
+    FSA_TRY(c->cvBA.alloc((size_t)n * mp));
+    FSA_TRY(c->cvBF.alloc((size_t)n * mp));
+    FSA_HIP(hipMemcpyAsync(c->cvBA.p, c->A.p, (size_t)n * mp * sizeof(double), hipMemcpyDeviceToDevice, st));
+    FSA_HIP(hipMemcpyAsync(c->cvBF.p, c->F.p, (size_t)n * mp * sizeof(double), hipMemcpyDeviceToDevice, st));
+    FSA_TRY(blas_solve_lower(c->blas, st, c->C.p, mp, c->cvBA.p, n));
+    FSA_TRY(blas_solve_lower(c->blas, st, c->C.p, mp, c->cvBF.p, n));
+    const int G = 1024;
+    FSA_TRY(c->cvpart.alloc((size_t)G * 5));
+    FSA_TRY(c->cvtr.alloc(8));
+    hipLaunchKernelGGL(k_cv_trace_parts, dim3(G), dim3(256), 0, st, c->cvBA.p, c->cvBF.p, c->D.p, c->dD.p, n, mp,
+                       c->cvpart.p);
+    hipLaunchKernelGGL(k_cv_trace_final, dim3(1), dim3(64), 0, st, c->cvpart.p, G, c->cvtr.p);
+    FSA_HIP(hipGetLastError());
+  }
   return FSA_OK;
 }
 
@@ -995,7 +1166,9 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   const int mp = c->mp;
   const int ldw = (int)round_up(tp, 64);
   Buf<double> dd, wm;
-  FSA_TRY(dd.alloc(5 * (size_t)tp + 9));
+  // dd: [0] u.Sx [1] u.x [2] u.dx [3] low-rank u.Sx [4] low-rank u.dx [5] |A^T x|^2
+  // [6] (F^T x).(A^T x) [7] |x|^2 [8] x.Dx [9] x.dDx (tp each), then the results
+  FSA_TRY(dd.alloc(10 * (size_t)tp + 15));
   FSA_TRY(wm.alloc(4 * (size_t)mp * ldw));
   double* w_ax = wm.p;
   double* w_fx = wm.p + (size_t)mp * ldw;
@@ -1009,19 +1182,40 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   FSA_TRY(lowrank_reduce<double>(c->A.p, n, mp, c->U.p, ld, tp, nullptr, c->scr, w_au, ldw, st));
   FSA_TRY(lowrank_reduce<double>(c->F.p, n, mp, c->U.p, ld, tp, nullptr, c->scr, w_fu, ldw, st));
   hipLaunchKernelGGL(k_grad_mdots, dim3(tp), dim3(256), 0, st, w_ax, w_fx, w_au, w_fu, mp, ldw, dd.p + 3 * tp,
-                     dd.p + 4 * tp);
+                     dd.p + 4 * tp, dd.p + 5 * tp, dd.p + 6 * tp);
   hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 3 * tp, dd.p);
   hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 4 * tp, dd.p + 2 * tp);
-  hipLaunchKernelGGL(k_finalize_grad, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, c->th.s1, c->th.s2,
-                     dd.p + 5 * tp);
+  double* res = dd.p + 10 * (size_t)tp;
+  const int cv = c->opt.grad_cv;
+  if (cv == FSA_CV_NONE) {
+    hipLaunchKernelGGL(k_finalize_grad, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, c->th.s1,
+                       c->th.s2, res);
+  } else {
+    // |x|^2, x.Dx, x.dDx per column of the probe block
+    const int ncb = (int)ceil_div(tp, 64);
+    const int ldp = ncb * 64;
+    const int64_t g = std::min<int64_t>(std::max<int64_t>(ceil_div(n, 64), 1), 1024);
+    Buf<double> xp;
+    FSA_TRY(xp.alloc(3 * (size_t)g * ldp));
+    hipLaunchKernelGGL(k_cv_xdots, dim3(g, ncb), dim3(256), 0, st, c->Xb.p, n, ld, tp, c->D.p, c->dD.p, xp.p, ldp);
+    for (int j = 0; j < 3; ++j)
+      FSA_TRY(colsum(xp.p + (size_t)j * g * ldp, (int)g, ldp, tp, dd.p + (7 + j) * (size_t)tp, st));
+    hipLaunchKernelGGL(k_finalize_grad_cv, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, dd.p + 7 * tp,
+                       dd.p + 8 * tp, dd.p + 9 * tp, dd.p + 5 * tp, dd.p + 6 * tp, c->cvtr.p, (double)n, c->th.s1,
+                       c->th.s2, cv, res);
+  }
   FSA_HIP(hipGetLastError());
   collect_timer(c);  // host work while the gradient kernels run
-  double g9[9];
-  FSA_HIP(hipMemcpyAsync(g9, dd.p + 5 * tp, sizeof(g9), hipMemcpyDeviceToHost, st));
+  double g9[15];
+  FSA_HIP(hipMemcpyAsync(g9, res, (cv == FSA_CV_NONE ? 9 : 15) * sizeof(double), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   for (int k = 0; k < 3; ++k) grad[k] = g9[k];
   if (parts6)
     for (int k = 0; k < 6; ++k) parts6[k] = g9[3 + k];
+  for (int k = 0; k < 3; ++k) {
+    c->stats.cv_c[k] = cv == FSA_CV_NONE ? 0.0 : g9[9 + k];
+    c->stats.trace_P[k] = cv == FSA_CV_NONE ? 0.0 : g9[12 + k];
+  }
   return FSA_OK;
 }
 

@@ -588,6 +588,13 @@ __global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ part,
   if (threadIdx.x == 0) out[c] = red[0];
 }
 
+fsa_status colsum(const double* part, int nparts, int ldp, int ncols, double* out, hipStream_t st) {
+  if (ncols <= 0) return FSA_OK;
+  hipLaunchKernelGGL(k_colsum, dim3(ncols), dim3(256), 0, st, part, nparts, ldp, out);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
 // block-wide fixed-order sum of nparts partials of column c (256 threads)
 __device__ __forceinline__ double block_colsum(const double* __restrict__ part, int nparts, int ldp, int c,
                                                double* red) {

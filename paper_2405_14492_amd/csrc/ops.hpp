@@ -126,6 +126,8 @@ fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<i
 template <typename T>
 fsa_status spmm_dot(const Csr& S, const Grid& g, const T* val, const T* X, const T* H, int ld, int ncols,
                     double* out, Scratch& s, hipStream_t st);
+// out[c] = sum_k part[k * ldp + c], k < nparts, for c < ncols (fixed order)
+fsa_status colsum(const double* part, int nparts, int ldp, int ncols, double* out, hipStream_t st);
 // out[c] = sum_p X[p][c] Y[p][c] (float64 result, c < ncols)
 template <typename TX, typename TY>
 fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double* out, Scratch& s, hipStream_t st);

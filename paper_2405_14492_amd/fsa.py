@@ -21,6 +21,7 @@ FP64 = 0
 MIXED_FP32 = 1
 MIXED_BF16A = 2
 PROFILE_ALL = 0x1f  # fsa_options.profile: all five kernel classes
+CV_NONE, CV_ONE, CV_OPT, CV_OPT_PRINTED = range(4)  # fsa_options.grad_cv
 
 OP_SIGMA_DAGGER, OP_SIGMA_S, OP_P_INV, OP_D_SIGMA1, OP_D_RHO, OP_PROBES = range(6)
 
@@ -49,7 +50,7 @@ class fsa_theta(C.Structure):
 
 
 class fsa_options(C.Structure):
-    _fields_ = [("num_probes", C.c_int32), ("seed", C.c_uint64), ("cg_rel_tol", C.c_double),
+    _fields_ = [("num_probes", C.c_int32), ("grad_cv", C.c_int32), ("seed", C.c_uint64), ("cg_rel_tol", C.c_double),
                 ("max_iter", C.c_int32), ("fixed_iter", C.c_int32), ("precision", C.c_int32),
                 ("rr_period", C.c_int32), ("slq_weight_n", C.c_int32), ("profile", C.c_int32),
                 ("sigma_m_jitter", C.c_double),
@@ -62,11 +63,12 @@ class fsa_stats(C.Structure):
                 ("quad", C.c_double), ("ms_build", C.c_double), ("ms_pcg", C.c_double),
                 ("ms_backward", C.c_double), ("ms_total", C.c_double), ("nnz", C.c_int64),
                 ("kernel_ms", C.c_double * 5), ("kernel_launches", C.c_int32 * 5),
-                ("grad_trace", C.c_double * 3), ("grad_quad", C.c_double * 3)]
+                ("grad_trace", C.c_double * 3), ("grad_quad", C.c_double * 3),
+                ("cv_c", C.c_double * 3), ("trace_P", C.c_double * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        for k in ("kernel_ms", "kernel_launches", "grad_trace", "grad_quad"):
+        for k in ("kernel_ms", "kernel_launches", "grad_trace", "grad_quad", "cv_c", "trace_P"):
             d[k] = list(getattr(self, k))
         return d
 
@@ -145,7 +147,7 @@ def make_theta(theta) -> fsa_theta:
 
 
 def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, precision=FP64, rr_period=10,
-                 slq_weight_n=False, jitter=0.0, stream=None, profile=False) -> fsa_options:
+                 slq_weight_n=False, jitter=0.0, stream=None, profile=False, grad_cv=CV_NONE) -> fsa_options:
     o = fsa_options()
     lib().fsa_default_options(C.byref(o))
     o.num_probes = int(num_probes)
@@ -160,6 +162,7 @@ def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, p
     o.hip_stream = stream
     # True: every kernel class; an int: the class bit mask itself
     o.profile = PROFILE_ALL if profile is True else int(profile)
+    o.grad_cv = int(grad_cv)
     return o
 
 
@@ -278,9 +281,9 @@ class FSA:
 
     def __init__(self, locs, y, theta, inducing, taper_range, num_probes=50, seed=0, tol=1e-8, max_iter=1000,
                  fixed_iter=0, precision=FP64, rr_period=10, slq_weight_n=False, jitter=0.0, stream=None,
-                 device=False, profile=False):
+                 device=False, profile=False, grad_cv=CV_NONE):
         self.opt = make_options(num_probes, seed, tol, max_iter, fixed_iter, precision, rr_period, slq_weight_n,
-                                jitter, stream, profile)
+                                jitter, stream, profile, grad_cv)
         self.n = int(locs.shape[0])
         self.theta = tuple(theta)
         build = fsa_build_dev if device else fsa_build

@@ -103,3 +103,11 @@ class RoundedFSA(O.FSA):
         if which == 0:
             return (self.matvec(X) - self.theta[3] * X) / self.theta[1]
         return super().dmatvec(which, X)
+
+    def precond_dmatvec(self, which, X):
+        """The preconditioner under the same convention: dP/dsigma1^2 =
+        (P - sigma^2 I) / sigma1^2."""
+        if which == 0:
+            DX = self.D[:, None] * X if X.ndim == 2 else self.D * X
+            return (DX + self.lowrank_matvec(X) - self.theta[3] * X) / self.theta[1]
+        return super().precond_dmatvec(which, X)

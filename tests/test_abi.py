@@ -37,25 +37,31 @@ def test_header_constants_match_binding(L):
     from paper_2405_14492_amd import fsa
     src = open(os.path.join(ROOT, "include", "fsa.h")).read()
     for nm, val in (("FSA_FP64", fsa.FP64), ("FSA_MIXED_FP32", fsa.MIXED_FP32),
-                    ("FSA_MIXED_BF16A", fsa.MIXED_BF16A)):
+                    ("FSA_MIXED_BF16A", fsa.MIXED_BF16A), ("FSA_CV_NONE", fsa.CV_NONE), ("FSA_CV_ONE", fsa.CV_ONE),
+                    ("FSA_CV_OPT", fsa.CV_OPT), ("FSA_CV_OPT_PRINTED", fsa.CV_OPT_PRINTED)):
         assert re.search(r"\b%s = %d\b" % (nm, val), src), nm
     assert int(re.search(r"#define FSA_PROFILE_ALL (0x[0-9a-f]+)", src).group(1), 16) == fsa.PROFILE_ALL
     assert fsa.make_options(profile=True).profile == fsa.PROFILE_ALL
     assert fsa.make_options(profile=1).profile == 1
     assert fsa.make_options().profile == 0
+    assert fsa.make_options().grad_cv == 0 and fsa.make_options(grad_cv=2).grad_cv == 2
+    # the options struct keeps its size: grad_cv fills the hole after num_probes
+    assert fsa.fsa_options.grad_cv.offset == 4 and fsa.fsa_options.seed.offset == 8
 
 
 def test_struct_layouts(L):
     from paper_2405_14492_amd import fsa
-    # fsa_options: int32, (pad) uint64, double, 5 x int32, (pad) double, void*
+    # fsa_options: 2 x int32, uint64, double, 6 x int32, double, void*
     assert ctypes.sizeof(fsa.fsa_options) == 64
     assert ctypes.sizeof(fsa.fsa_theta) == 32
     o = fsa.fsa_options()
     L.fsa_default_options(ctypes.byref(o))
     assert o.num_probes == 50 and o.cg_rel_tol == 1e-8 and o.max_iter == 1000 and o.precision == 0
+    assert o.grad_cv == 0
 
 
-@pytest.mark.parametrize("case", ["n1", "d3", "m0", "m_gt_n", "gamma0", "sigma2_0", "rho_neg", "cov_bad", "probes0"])
+@pytest.mark.parametrize("case", ["n1", "d3", "m0", "m_gt_n", "gamma0", "sigma2_0", "rho_neg", "cov_bad", "probes0",
+                                  "cv_bad"])
 def test_invalid_arguments_rejected_on_host(L, case):
     from paper_2405_14492_amd import fsa
     n, d, m, gamma = 10, 2, 3, 0.1
@@ -80,6 +86,8 @@ def test_invalid_arguments_rejected_on_host(L, case):
         theta[0] = 7
     elif case == "probes0":
         opt.num_probes = 0
+    elif case == "cv_bad":
+        opt.grad_cv = 4
     locs = np.zeros((max(n, 1), d))
     y = np.zeros(max(n, 1))
     ind = np.zeros((max(m, 1), d))

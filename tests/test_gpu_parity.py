@@ -400,3 +400,46 @@ def test_float32_operator_tracks_float64(F, name):
         err = np.abs(a32 - a64).max() / np.abs(a64).max()
         say(key, "max rel diff", err)
         assert err < 1e-4, key
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["exp_n700_m40", "m32_n1500_m100", "ragged_n333_m7"])
+@pytest.mark.parametrize("mode", ["one", "opt", "opt_printed"])
+def test_gradient_control_variate_matches_oracle(F, name, mode):
+    """The FITC preconditioner as control variate (App. E): the float64
+    gradient with c = 1, the centred c_opt or the printed c_opt against the
+    oracle with the same probes and fixed iterations, together with the
+    coefficients and the exact traces Tr(P^{-1} dP/dtheta)."""
+    say("case", name, mode)
+    cvm = {"one": F.CV_ONE, "opt": F.CV_OPT, "opt_printed": F.CV_OPT_PRINTED}[mode]
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    mdl = O.FSA(locs, ind, theta, gamma)
+    t, k = 8, 20
+    ref = O.nll_grad(mdl, y, t, 41, fixed_iter=k, control_variate=mode)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=t, seed=41, fixed_iter=k, grad_cv=cvm) as f:
+        nll, grad, st = f.nll_grad()
+    gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
+    say("grad", grad, ref["grad"], "c", st["cv_c"], ref["cv_c"], "trace_P", st["trace_P"], ref["trace_P"])
+    np.testing.assert_allclose(st["trace_P"], ref["trace_P"], rtol=1e-9)
+    np.testing.assert_allclose(st["cv_c"], ref["cv_c"], rtol=1e-7, atol=1e-12)
+    assert np.all(np.abs(grad - ref["grad"]) <= 1e-9 * gscale + 1e-12), (grad, ref["grad"])
+
+
+@pytest.mark.gpu
+def test_gradient_control_variate_mixed_and_bf16a(F):
+    """The control variate on the float32 solves: MIXED_FP32 against the
+    float64 oracle, MIXED_BF16A against the oracle of its rounded model
+    (whose sigma1^2 derivative, of Sigma~ and of P, scales with sigma1^2), at
+    the mixed-precision bar."""
+    locs, y, theta, ind, gamma = case(**CASES["m32_n1500_m100"])
+    for prec, mdl in ((F.MIXED_FP32, O.FSA(locs, ind, theta, gamma)),
+                      (F.MIXED_BF16A, DF.RoundedFSA(locs, ind, theta, gamma,
+                                                    smn_T=DF.bf16_cross_covariance(locs, ind, theta)))):
+        ref = O.nll_grad(mdl, y, 8, 5, tol=1e-10, max_iter=3000, control_variate="opt")
+        with F.FSA(locs, y, theta, ind, gamma, num_probes=8, seed=5, tol=1e-6, max_iter=3000, precision=prec,
+                   rr_period=10, grad_cv=F.CV_OPT) as f:
+            nll, grad, st = f.nll_grad()
+        gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
+        say(prec, "grad err / scale", np.abs(grad - ref["grad"]) / gscale, "trace_P", st["trace_P"], ref["trace_P"])
+        np.testing.assert_allclose(st["trace_P"], ref["trace_P"], rtol=1e-9)
+        assert np.all(np.abs(grad - ref["grad"]) <= 1e-4 * gscale), (prec, grad, ref["grad"])
