@@ -82,20 +82,26 @@ typedef enum { FSA_FP64 = 0, FSA_MIXED_FP32 = 1, FSA_MIXED_BF16A = 2 } fsa_preci
 /* fsa_options.profile: all five kernel classes of fsa_stats.kernel_ms */
 #define FSA_PROFILE_ALL 0x1f
 
-/* fsa_options.grad_cv: the FITC preconditioner as control variate for the
- * gradient's trace estimate (App. E, eq. Troptc).  Each probe's sample
- * a_i = (z_i^T Sigma~^{-1}) dSigma~/dtheta (P^{-1} z_i) gets c * b_i subtracted,
- * b_i = (P^{-1} z_i)^T dP/dtheta (P^{-1} z_i), and c Tr(P^{-1} dP/dtheta) added
- * (exact, by Woodbury), per parameter:
- *   FSA_CV_NONE         the plain estimate;
+/* fsa_options.control_variate: the FITC preconditioner as control variate
+ * (App. E) in both stochastic estimates of the method, per parameter or per
+ * prediction point:
+ * - the gradient's trace estimate (eq. Troptc): each probe's sample
+ *   a_i = (z_i^T Sigma~^{-1}) dSigma~/dtheta (P^{-1} z_i) gets c * b_i subtracted,
+ *   b_i = (P^{-1} z_i)^T dP/dtheta (P^{-1} z_i), and c Tr(P^{-1} dP/dtheta)
+ *   (exact, by Woodbury) added;
+ * - Algorithm 1's stochastic diagonal of Sigma^s_{nn_p}^T Sigma~_s^{-1} Sigma^s_{nn_p}:
+ *   each sample z_i o (S^T Sigma~_s^{-1} S z_i) gets c o z_i o (S^T D_s^{-1} S z_i)
+ *   subtracted and c o diag(S^T D_s^{-1} S) (exact) added (P_s = D_s).
+ *   FSA_CV_NONE         the plain estimates;
  *   FSA_CV_ONE          c = 1;
  *   FSA_CV_OPT          c = sum_i (a_i - mean a)(b_i - mean b) / sum_i (b_i - mean b)^2,
  *                       the coefficient of least sample variance (the paper's
  *                       c_opt read with a centred denominator);
  *   FSA_CV_OPT_PRINTED  c = sum_i (a_i - mean a) b_i / sum_i b_i^2, as printed.
- * Costs two m x m-triangular solves over n x m blocks per theta (beside the
- * solve, on the side stream) and one pass over the probe block per gradient. */
-typedef enum { FSA_CV_NONE = 0, FSA_CV_ONE = 1, FSA_CV_OPT = 2, FSA_CV_OPT_PRINTED = 3 } fsa_grad_cv;
+ * The gradient's costs two m x m-triangular solves over n x m blocks per
+ * theta (beside the solve, on the side stream) and one pass over the probe
+ * block per gradient; the diagonal's two sparse products per prediction. */
+typedef enum { FSA_CV_NONE = 0, FSA_CV_ONE = 1, FSA_CV_OPT = 2, FSA_CV_OPT_PRINTED = 3 } fsa_control_variate;
 
 typedef struct {
   int32_t cov;      /* fsa_cov */
@@ -106,7 +112,7 @@ typedef struct {
 
 typedef struct {
   int32_t num_probes;    /* number of probe vectors ell >= 1 (Section 3.1) */
-  int32_t grad_cv;       /* fsa_grad_cv (default FSA_CV_NONE) */
+  int32_t control_variate; /* fsa_control_variate (default FSA_CV_NONE) */
   uint64_t seed;         /* key of the counter-based Rademacher generator */
   double cg_rel_tol;     /* per column ||r||_2 / ||b||_2 < tol stops the column */
   int32_t max_iter;      /* iteration cap; reaching it gives FSA_ERR_NOT_CONVERGED */
@@ -144,7 +150,7 @@ typedef struct {
    * and quadratic term u^T dSigma~ u (u = Sigma~^{-1} y), order (sigma1^2, rho, sigma^2) */
   double grad_trace[3];
   double grad_quad[3];
-  /* with options.grad_cv: the coefficient c used and Tr(P^{-1} dP/dtheta),
+  /* with options.control_variate: the gradient's coefficients c and Tr(P^{-1} dP/dtheta),
    * order (sigma1^2, rho, sigma^2); grad_trace then holds the control-variate
    * estimate */
   double cv_c[3];

@@ -556,14 +556,20 @@ def nll_grad(model, y, num_probes, seed, tol=1e-8, max_iter=1000, fixed_iter=0,
 
 
 def predict_var(model, pred_locs, num_samples, seed, tol=1e-8, max_iter=1000, fixed_iter=0,
-                exact_Dl=False, u=None, smp_T=None):
+                exact_Dl=False, u=None, smp_T=None, control_variate=None):
     """Algorithm 1: D^p = sigma1^2 + sigma^2 - D1 - 2 D2 + D3 - D_l.
 
     Sigma~_s solves use CG preconditioned by D_s (Section 3.3).  With
     exact_Dl the stochastic diagonal is replaced by its exact value (dense,
     small inputs only).  Returns (variances, details); with u =
     Sigma~^{-1} y given, also the predictive mean (Section 2.3).  smp_T
-    replaces Sigma_{m n_p}^T as smn_T does Sigma_mn^T in FSA."""
+    replaces Sigma_{m n_p}^T as smn_T does Sigma_mn^T in FSA.
+
+    control_variate (App. E, second display): None for the plain D_l;
+    otherwise, with P_s = D_s and per prediction point, the samples
+    a_i = z_i o (S^T Sigma~_s^{-1} S z_i) get c o b_i subtracted, b_i =
+    z_i o (S^T D_s^{-1} S z_i), and c o diag(S^T D_s^{-1} S) added (S =
+    Sigma^s_{n n_p}); c as in nll_grad ("one", "opt" centred, "opt_printed")."""
     kind, s1, rho, s2 = model.theta
     P = np.ascontiguousarray(pred_locs, dtype=np.float64)
     n_p = P.shape[0]
@@ -603,8 +609,27 @@ def predict_var(model, pred_locs, num_samples, seed, tol=1e-8, max_iter=1000, fi
         Wl = pcg_lanczos(model.sparse_matvec, model.diag_solve, X, tol, max_iter, fixed_iter).U
         Z2 = SsT @ Wl
         Dl = np.mean(Z1 * Z2, axis=1)
+        if control_variate is not None:
+            a = Z1 * Z2
+            b = Z1 * (SsT @ (X / model.D[:, None]))
+            E = np.asarray(Ss.multiply(Ss).T @ (1.0 / model.D)).ravel()   # diag(S^T D_s^{-1} S)
+            if control_variate == "one":
+                c = np.ones(n_p)
+            elif control_variate in ("opt", "opt_printed"):
+                bc = b - b.mean(axis=1, keepdims=True) if control_variate == "opt" else b
+                num = np.sum((a - Dl[:, None]) * bc, axis=1)
+                den = np.sum(bc * bc, axis=1)
+                c = np.divide(num, den, out=np.zeros(n_p), where=den > 0)
+            else:
+                raise ValueError("control_variate must be None, 'one', 'opt' or 'opt_printed'")
+            Dl = np.mean(a - c[:, None] * b, axis=1) + c * E
+            det_cv = {"cv_c": c, "cv_E": E, "cv_a": a, "cv_b": b}
+        else:
+            det_cv = {}
     var = s1 + s2 - D1 - 2.0 * D2 + D3 - Dl
     det = {"D1": D1, "D2": D2, "D3": D3, "Dl": Dl, "cross_row_ptr": rp, "cross_col": cl}
+    if not exact_Dl:
+        det.update(det_cv)
     if u is not None:
         det["mean"] = G_T @ (model.Smn_T.T @ u) + SsT @ u
     return var, det

@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_cv_xdots(const double* __restrict__ X, 
 // T_0 = (n - s2 T_2)/s1, T_1 = tr5[2] - tr5[3] + 2 tr5[4].
 // out: [0..2] gradient, [3..5] trace estimates, [6..8] quadratic terms,
 // [9..11] coefficients c, [12..14] T.
-__global__ void k_finalize_grad_cv(int ncols, const double* __restrict__ uSX, const double* __restrict__ uX,
+__global__ void k_finalize_control_variate(int ncols, const double* __restrict__ uSX, const double* __restrict__ uX,
                                    const double* __restrict__ uDX, const double* __restrict__ xx,
                                    const double* __restrict__ xDx, const double* __restrict__ xdDx,
                                    const double* __restrict__ ax2, const double* __restrict__ fax,
@@ -462,7 +462,7 @@ struct fsa_ctx {
   bool timer_pending = false;  // the last solve's kernel events are not yet summed
   // gradient
   Buf<double> F, dvals, Xb, tmp, dSm, Ework;
-  // control variate (options.grad_cv): diagonal of the derivative values,
+  // control variate (options.control_variate): diagonal of the derivative values,
   // L_C^{-1} A and L_C^{-1} F by rows, and the five trace sums (per theta)
   Buf<double> dD, cvBA, cvBF, cvpart, cvtr;
   Scratch scr;
@@ -650,7 +650,7 @@ static fsa_status validate_build(int64_t n, int32_t d, const fsa_theta* theta, i
     if (opt->max_iter < 1 && opt->fixed_iter < 1) { set_error("max_iter must be >= 1"); return FSA_ERR_INVALID_ARG; }
     if (!(opt->cg_rel_tol >= 0)) { set_error("cg_rel_tol must be >= 0"); return FSA_ERR_INVALID_ARG; }
     if (opt->precision != FSA_FP64 && opt->precision != FSA_MIXED_FP32 && opt->precision != FSA_MIXED_BF16A) { set_error("unknown precision"); return FSA_ERR_INVALID_ARG; }
-    if (opt->grad_cv < FSA_CV_NONE || opt->grad_cv > FSA_CV_OPT_PRINTED) { set_error("unknown grad_cv"); return FSA_ERR_INVALID_ARG; }
+    if (opt->control_variate < FSA_CV_NONE || opt->control_variate > FSA_CV_OPT_PRINTED) { set_error("unknown control_variate"); return FSA_ERR_INVALID_ARG; }
     if (!(opt->sigma_m_jitter >= 0)) { set_error("sigma_m_jitter must be >= 0"); return FSA_ERR_INVALID_ARG; }
   }
   return FSA_OK;
@@ -1073,7 +1073,7 @@ static fsa_status build_derivative(fsa_ctx* c, hipStream_t st) {
   FSA_TRY(c->dvals.alloc(c->csr.nnz));
   FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, c->F.p, c->F.p, mp, c->th, c->gamma, true, true,
                           c->dvals.p, nullptr, st));
-  if (c->opt.grad_cv != FSA_CV_NONE) {
+  if (c->opt.control_variate != FSA_CV_NONE) {
     // Tr(P^{-1} dP/dtheta) by Woodbury (App. E, F): with C = L_C L_C^T,
     // Tr P^{-1} = sum 1/D - sum |L_C^{-1} A_p|^2 / D^2, Tr(P^{-1} dD) likewise
     // weighted by dD, and Tr(P^{-1}(F A^T + A F^T)) = 2 Tr(C^{-1} A^T D^{-1} F)
@@ -1186,7 +1186,7 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 3 * tp, dd.p);
   hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 4 * tp, dd.p + 2 * tp);
   double* res = dd.p + 10 * (size_t)tp;
-  const int cv = c->opt.grad_cv;
+  const int cv = c->opt.control_variate;
   if (cv == FSA_CV_NONE) {
     hipLaunchKernelGGL(k_finalize_grad, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, c->th.s1,
                        c->th.s2, res);
@@ -1200,7 +1200,7 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
     hipLaunchKernelGGL(k_cv_xdots, dim3(g, ncb), dim3(256), 0, st, c->Xb.p, n, ld, tp, c->D.p, c->dD.p, xp.p, ldp);
     for (int j = 0; j < 3; ++j)
       FSA_TRY(colsum(xp.p + (size_t)j * g * ldp, (int)g, ldp, tp, dd.p + (7 + j) * (size_t)tp, st));
-    hipLaunchKernelGGL(k_finalize_grad_cv, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, dd.p + 7 * tp,
+    hipLaunchKernelGGL(k_finalize_control_variate, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, dd.p + 7 * tp,
                        dd.p + 8 * tp, dd.p + 9 * tp, dd.p + 5 * tp, dd.p + 6 * tp, c->cvtr.p, (double)n, c->th.s1,
                        c->th.s2, cv, res);
   }

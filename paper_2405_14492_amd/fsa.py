@@ -21,7 +21,7 @@ FP64 = 0
 MIXED_FP32 = 1
 MIXED_BF16A = 2
 PROFILE_ALL = 0x1f  # fsa_options.profile: all five kernel classes
-CV_NONE, CV_ONE, CV_OPT, CV_OPT_PRINTED = range(4)  # fsa_options.grad_cv
+CV_NONE, CV_ONE, CV_OPT, CV_OPT_PRINTED = range(4)  # fsa_options.control_variate
 
 OP_SIGMA_DAGGER, OP_SIGMA_S, OP_P_INV, OP_D_SIGMA1, OP_D_RHO, OP_PROBES = range(6)
 
@@ -50,7 +50,8 @@ class fsa_theta(C.Structure):
 
 
 class fsa_options(C.Structure):
-    _fields_ = [("num_probes", C.c_int32), ("grad_cv", C.c_int32), ("seed", C.c_uint64), ("cg_rel_tol", C.c_double),
+    _fields_ = [("num_probes", C.c_int32), ("control_variate", C.c_int32), ("seed", C.c_uint64),
+                ("cg_rel_tol", C.c_double),
                 ("max_iter", C.c_int32), ("fixed_iter", C.c_int32), ("precision", C.c_int32),
                 ("rr_period", C.c_int32), ("slq_weight_n", C.c_int32), ("profile", C.c_int32),
                 ("sigma_m_jitter", C.c_double),
@@ -147,7 +148,7 @@ def make_theta(theta) -> fsa_theta:
 
 
 def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, precision=FP64, rr_period=10,
-                 slq_weight_n=False, jitter=0.0, stream=None, profile=False, grad_cv=CV_NONE) -> fsa_options:
+                 slq_weight_n=False, jitter=0.0, stream=None, profile=False, control_variate=CV_NONE) -> fsa_options:
     o = fsa_options()
     lib().fsa_default_options(C.byref(o))
     o.num_probes = int(num_probes)
@@ -162,7 +163,7 @@ def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, p
     o.hip_stream = stream
     # True: every kernel class; an int: the class bit mask itself
     o.profile = PROFILE_ALL if profile is True else int(profile)
-    o.grad_cv = int(grad_cv)
+    o.control_variate = int(control_variate)
     return o
 
 
@@ -281,9 +282,9 @@ class FSA:
 
     def __init__(self, locs, y, theta, inducing, taper_range, num_probes=50, seed=0, tol=1e-8, max_iter=1000,
                  fixed_iter=0, precision=FP64, rr_period=10, slq_weight_n=False, jitter=0.0, stream=None,
-                 device=False, profile=False, grad_cv=CV_NONE):
+                 device=False, profile=False, control_variate=CV_NONE):
         self.opt = make_options(num_probes, seed, tol, max_iter, fixed_iter, precision, rr_period, slq_weight_n,
-                                jitter, stream, profile, grad_cv)
+                                jitter, stream, profile, control_variate)
         self.n = int(locs.shape[0])
         self.theta = tuple(theta)
         build = fsa_build_dev if device else fsa_build

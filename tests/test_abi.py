@@ -44,9 +44,9 @@ def test_header_constants_match_binding(L):
     assert fsa.make_options(profile=True).profile == fsa.PROFILE_ALL
     assert fsa.make_options(profile=1).profile == 1
     assert fsa.make_options().profile == 0
-    assert fsa.make_options().grad_cv == 0 and fsa.make_options(grad_cv=2).grad_cv == 2
-    # the options struct keeps its size: grad_cv fills the hole after num_probes
-    assert fsa.fsa_options.grad_cv.offset == 4 and fsa.fsa_options.seed.offset == 8
+    assert fsa.make_options().control_variate == 0 and fsa.make_options(control_variate=2).control_variate == 2
+    # the options struct keeps its size: control_variate fills the hole after num_probes
+    assert fsa.fsa_options.control_variate.offset == 4 and fsa.fsa_options.seed.offset == 8
 
 
 def test_struct_layouts(L):
@@ -57,7 +57,7 @@ def test_struct_layouts(L):
     o = fsa.fsa_options()
     L.fsa_default_options(ctypes.byref(o))
     assert o.num_probes == 50 and o.cg_rel_tol == 1e-8 and o.max_iter == 1000 and o.precision == 0
-    assert o.grad_cv == 0
+    assert o.control_variate == 0
 
 
 @pytest.mark.parametrize("case", ["n1", "d3", "m0", "m_gt_n", "gamma0", "sigma2_0", "rho_neg", "cov_bad", "probes0",
@@ -87,7 +87,7 @@ def test_invalid_arguments_rejected_on_host(L, case):
     elif case == "probes0":
         opt.num_probes = 0
     elif case == "cv_bad":
-        opt.grad_cv = 4
+        opt.control_variate = 4
     locs = np.zeros((max(n, 1), d))
     y = np.zeros(max(n, 1))
     ind = np.zeros((max(m, 1), d))

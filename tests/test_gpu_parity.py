@@ -416,7 +416,7 @@ def test_gradient_control_variate_matches_oracle(F, name, mode):
     mdl = O.FSA(locs, ind, theta, gamma)
     t, k = 8, 20
     ref = O.nll_grad(mdl, y, t, 41, fixed_iter=k, control_variate=mode)
-    with F.FSA(locs, y, theta, ind, gamma, num_probes=t, seed=41, fixed_iter=k, grad_cv=cvm) as f:
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=t, seed=41, fixed_iter=k, control_variate=cvm) as f:
         nll, grad, st = f.nll_grad()
     gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
     say("grad", grad, ref["grad"], "c", st["cv_c"], ref["cv_c"], "trace_P", st["trace_P"], ref["trace_P"])
@@ -437,7 +437,7 @@ def test_gradient_control_variate_mixed_and_bf16a(F):
                                                     smn_T=DF.bf16_cross_covariance(locs, ind, theta)))):
         ref = O.nll_grad(mdl, y, 8, 5, tol=1e-10, max_iter=3000, control_variate="opt")
         with F.FSA(locs, y, theta, ind, gamma, num_probes=8, seed=5, tol=1e-6, max_iter=3000, precision=prec,
-                   rr_period=10, grad_cv=F.CV_OPT) as f:
+                   rr_period=10, control_variate=F.CV_OPT) as f:
             nll, grad, st = f.nll_grad()
         gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
         say(prec, "grad err / scale", np.abs(grad - ref["grad"]) / gscale, "trace_P", st["trace_P"], ref["trace_P"])

@@ -495,6 +495,52 @@ def test_control_variate_is_unbiased_and_reduces_variance():
     assert np.all(sd["opt"][:2] < 1.05 * sd["one"][:2]), (sd["opt"], sd["one"])
 
 
+def dense_residual_cross(locs, ind, pred, theta, gamma):
+    """Sigma^s_{n n_p} = (Sigma_{n n_p} - Sigma^l_{n n_p}) o T_{n n_p}, dense."""
+    from scipy.spatial.distance import cdist
+    kind, s1, rho, s2 = theta
+    Sm = O.covariance(cdist(ind, ind), s1, rho, kind)
+    Smn = O.covariance(cdist(ind, locs), s1, rho, kind)
+    Smp = O.covariance(cdist(ind, pred), s1, rho, kind)
+    Snp = O.covariance(cdist(locs, pred), s1, rho, kind)
+    low = Smn.T @ np.linalg.solve(Sm, Smp)
+    return (Snp - low) * O.wendland_taper(cdist(locs, pred), gamma)
+
+
+def test_diagonal_control_variate_is_unbiased_and_reduces_variance():
+    """Algorithm 1's stochastic diagonal with D_s as control variate (App.
+    E): the exact term diag(S^T D_s^{-1} S) against the dense definition; the
+    c slopes as regressions; over independent draws every estimate centres
+    on the exact diagonal (dense solve) and c_opt spreads far less than the
+    plain estimate.  c = 1 spreads more here: S^T D_s^{-1} S is a loose
+    stand-in for S^T Sigma~_s^{-1} S and c = 1 over-corrects."""
+    locs, ind, theta, gamma = small_case(n=300, m=30, kind=M32, rho=0.1, s1=1.0, s2=0.1, n_gamma=25)
+    mdl = O.FSA(locs, ind, theta, gamma)
+    pred = G.uniform_locations(60, 901)
+    _, det0 = O.predict_var(mdl, pred, 8, 0, tol=1e-12, exact_Dl=True)
+    S = dense_residual_cross(locs, ind, pred, theta, gamma)
+    _, d1 = O.predict_var(mdl, pred, 8, 5, tol=1e-12, control_variate="opt")
+    np.testing.assert_allclose(d1["cv_E"], np.einsum("ij,ij->j", S, S / mdl.D[:, None]), rtol=1e-10)
+    _, dp = O.predict_var(mdl, pred, 8, 5, tol=1e-12, control_variate="opt_printed")
+    for j in (0, 7, 31):
+        a, b = d1["cv_a"][j], d1["cv_b"][j]
+        if np.ptp(b) > 0:
+            assert abs(d1["cv_c"][j] - np.polyfit(b, a, 1)[0]) <= 1e-8 * max(1.0, abs(d1["cv_c"][j]))
+        slope0 = np.linalg.lstsq(b[:, None], a - a.mean(), rcond=None)[0][0]
+        assert abs(dp["cv_c"][j] - slope0) <= 1e-10 * max(1.0, abs(slope0))
+    est = {cv: [] for cv in (None, "one", "opt", "opt_printed")}
+    for seed in range(30):
+        for cv in est:
+            est[cv].append(O.predict_var(mdl, pred, 8, 200 + seed, tol=1e-12, control_variate=cv)[1]["Dl"])
+    exact = det0["Dl"]
+    sd = {cv: np.std(np.array(v), axis=0, ddof=1) for cv, v in est.items()}
+    for cv, v in est.items():
+        m = np.mean(np.array(v), axis=0)
+        assert np.all(np.abs(m - exact) < 4.5 * sd[cv] / math.sqrt(30) + 1e-9), cv
+    ratio_opt = np.median(sd["opt"] / sd[None])
+    assert ratio_opt < 0.5, ratio_opt
+
+
 # ---------------------------------------------------------------- predictive variances
 
 def test_algorithm1_with_exact_diagonal_equals_dense():
