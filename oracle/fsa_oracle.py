@@ -49,6 +49,12 @@ SQRT3 = math.sqrt(3.0)
 # ---------------------------------------------------------------------------
 
 
+# A control-variate coefficient is taken as 0 when its b_i hardly vary: the
+# centred sum of squares at most this fraction of sum_i b_i^2 (then any c
+# leaves the estimate unchanged up to rounding, and the ratio is noise).
+CV_DEGENERATE = 1e-12
+
+
 def covariance(d, sigma1_sq, rho, kind):
     """c(s_i, s_j) as a function of the Euclidean distance d (Section 2;
     Assumption 3 form sigma1^2 r(d) with r(0) = 1)."""
@@ -536,11 +542,11 @@ def nll_grad(model, y, num_probes, seed, tol=1e-8, max_iter=1000, fixed_iter=0,
             c = np.ones(3)
             for k in range(3):
                 a, b = trace_terms[k], cv_terms[k]
-                if control_variate == "opt":
-                    bc = b - np.mean(b)
-                    c[k] = np.sum((a - np.mean(a)) * bc) / np.sum(bc * bc)
-                elif control_variate == "opt_printed":
-                    c[k] = np.sum((a - np.mean(a)) * b) / np.sum(b * b)
+                if control_variate in ("opt", "opt_printed"):
+                    bc = b - np.mean(b) if control_variate == "opt" else b
+                    den = np.sum(bc * bc)
+                    # b_i (nearly) constant: any c leaves the estimate as it is
+                    c[k] = np.sum((a - np.mean(a)) * bc) / den if den > CV_DEGENERATE * np.sum(b * b) else 0.0
                 elif control_variate != "one":
                     raise ValueError("control_variate must be None, 'one', 'opt' or 'opt_printed'")
                 est = np.mean(a - c[k] * b) + c[k] * trace_P[k]
@@ -619,7 +625,7 @@ def predict_var(model, pred_locs, num_samples, seed, tol=1e-8, max_iter=1000, fi
                 bc = b - b.mean(axis=1, keepdims=True) if control_variate == "opt" else b
                 num = np.sum((a - Dl[:, None]) * bc, axis=1)
                 den = np.sum(bc * bc, axis=1)
-                c = np.divide(num, den, out=np.zeros(n_p), where=den > 0)
+                c = np.divide(num, den, out=np.zeros(n_p), where=den > CV_DEGENERATE * np.sum(b * b, axis=1))
             else:
                 raise ValueError("control_variate must be None, 'one', 'opt' or 'opt_printed'")
             Dl = np.mean(a - c[:, None] * b, axis=1) + c * E

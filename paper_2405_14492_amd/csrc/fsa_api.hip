@@ -229,6 +229,10 @@ __global__ __launch_bounds__(256) void k_grad_mdots(const double* __restrict__ a
 }
 
 // ---- control variate (App. E) ----
+// A coefficient is taken as 0 when its b_i hardly vary (centred sum of
+// squares at most this fraction of sum_i b_i^2): then any c leaves the
+// estimate unchanged up to rounding, and the ratio is noise.
+constexpr double CV_DEGENERATE = 1e-12;
 // out[p] = the value of row p's diagonal entry (0 if the pattern has none)
 __global__ void k_csr_diag(const int64_t* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ v,
                            int64_t n, double* __restrict__ out) {
@@ -345,7 +349,7 @@ __global__ void k_finalize_control_variate(int ncols, const double* __restrict__
     ma[k] /= t;
     mb[k] /= t;
   }
-  double num[3] = {0, 0, 0}, den[3] = {0, 0, 0};
+  double num[3] = {0, 0, 0}, den[3] = {0, 0, 0}, bb[3] = {0, 0, 0};
   for (int c = 1; c < ncols; ++c) {
     const double a[3] = {(uSX[c] - s2 * uX[c]) / s1, uDX[c], uX[c]};
     const double b[3] = {(xDx[c] + ax2[c] - s2 * xx[c]) / s1, xdDx[c] + 2.0 * fax[c], xx[c]};
@@ -353,11 +357,12 @@ __global__ void k_finalize_control_variate(int ncols, const double* __restrict__
       const double bc = mode == FSA_CV_OPT ? b[k] - mb[k] : b[k];
       num[k] += (a[k] - ma[k]) * bc;
       den[k] += bc * bc;
+      bb[k] += b[k] * b[k];
     }
   }
   const double qd[3] = {(uSX[0] - s2 * uX[0]) / s1, uDX[0], uX[0]};
   for (int k = 0; k < 3; ++k) {
-    const double cc = mode == FSA_CV_ONE ? 1.0 : (den[k] > 0.0 ? num[k] / den[k] : 0.0);
+    const double cc = mode == FSA_CV_ONE ? 1.0 : (den[k] > CV_DEGENERATE * bb[k] ? num[k] / den[k] : 0.0);
     const double est = ma[k] - cc * mb[k] + cc * T[k];
     out[k] = 0.5 * est - 0.5 * qd[k];
     out[3 + k] = est;
@@ -365,6 +370,50 @@ __global__ void k_finalize_control_variate(int ncols, const double* __restrict__
     out[9 + k] = cc;
     out[12 + k] = T[k];
   }
+}
+
+// E[j] = sum over row j of the cross pattern of v^2 / D[col]: diag(S^T D_s^{-1} S)
+// for the prediction points (rows of S^T)
+__global__ void k_cross_diag_w(const int64_t* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ v,
+                               const double* __restrict__ D, int64_t np_, double* __restrict__ E) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= np_) return;
+  double e = 0.0;
+  for (int64_t k = rp[j]; k < rp[j + 1]; ++k) e += v[k] * v[k] / D[col[k]];
+  E[j] = e;
+}
+
+// Algorithm 1's stochastic diagonal with D_s as control variate, in place:
+// per prediction point j, a_i = z_i Zl_i, b_i = z_i Zv_i (i < s), c by mode,
+// Zl_i <- Zl_i - c Zv_i + c E z_i, so that mean_i z_i Zl_i becomes
+// mean(a) - c mean(b) + c E (z_i = +-1).
+__global__ void k_pred_cv(int64_t np_, int s, const double* __restrict__ Z1, double* __restrict__ Zl,
+                          const double* __restrict__ Zv, int ld, const double* __restrict__ E, int mode) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= np_) return;
+  const double* z = Z1 + j * ld;
+  double* zl = Zl + j * ld;
+  const double* zv = Zv + j * ld;
+  double ma = 0.0, mb = 0.0;
+  for (int i = 0; i < s; ++i) {
+    ma += z[i] * zl[i];
+    mb += z[i] * zv[i];
+  }
+  ma /= s;
+  mb /= s;
+  double c = 1.0;
+  if (mode != FSA_CV_ONE) {
+    double num = 0.0, den = 0.0, bb = 0.0;
+    for (int i = 0; i < s; ++i) {
+      const double a = z[i] * zl[i], b = z[i] * zv[i];
+      const double bc = mode == FSA_CV_OPT ? b - mb : b;
+      num += (a - ma) * bc;
+      den += bc * bc;
+      bb += b * b;
+    }
+    c = den > CV_DEGENERATE * bb ? num / den : 0.0;
+  }
+  for (int i = 0; i < s; ++i) zl[i] = zl[i] - c * zv[i] + c * E[j] * z[i];
 }
 
 __global__ void k_add_cols(int ncols, const double* __restrict__ x, double* __restrict__ y) {
@@ -1405,6 +1454,23 @@ static fsa_status predict_core(fsa_ctx* c, const double* pred_locs_h, int64_t n_
   FSA_TRY(spmm<double>(cPT, pg, c->grid, vPT.p, W.p, ld, mp, Y2.p, mp, false, st));
   FSA_TRY(lowrank_expand<double>(Y2.p, nullptr, n_p, mp, G.p, mp, mp, Z2.p, mp, st));
   FSA_TRY(spmm<double>(cPT, pg, c->grid, vPT.p, W.p + mp, ld, s, Zl.p, lds, false, st));
+  if (c->opt.control_variate != FSA_CV_NONE) {
+    // D_s as control variate (App. E): Zv = S^T D_s^{-1} S z and diag(S^T D_s^{-1} S)
+    Buf<double> Xd, Zv, Ev;
+    FSA_TRY(Xd.alloc((size_t)n * lds));
+    FSA_TRY(Zv.alloc((size_t)n_p * lds));
+    FSA_TRY(Ev.alloc(n_p));
+    FSA_HIP(hipMemsetAsync(Xd.p, 0, (size_t)n * lds * sizeof(double), st));
+    FSA_TRY((copy_block<double, double>(B.p + mp, ld, Xd.p, lds, n, s, st)));
+    FSA_TRY(scale_rows(Xd.p, lds, c->D.p, n, s, 1, st));
+    FSA_HIP(hipMemsetAsync(Zv.p, 0, (size_t)n_p * lds * sizeof(double), st));
+    FSA_TRY(spmm<double>(cPT, pg, c->grid, vPT.p, Xd.p, lds, s, Zv.p, lds, false, st));
+    hipLaunchKernelGGL(k_cross_diag_w, dim3(ceil_div(n_p, 256)), dim3(256), 0, st, cPT.row_ptr.p, cPT.col.p, vPT.p,
+                       c->D.p, n_p, Ev.p);
+    hipLaunchKernelGGL(k_pred_cv, dim3(ceil_div(n_p, 256)), dim3(256), 0, st, n_p, s, Z1.p, Zl.p, Zv.p, lds, Ev.p,
+                       c->opt.control_variate);
+    FSA_HIP(hipGetLastError());
+  }
   Buf<double> vdev;
   FSA_TRY(vdev.alloc(n_p));
   Buf<double> pdev;

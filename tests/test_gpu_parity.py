@@ -443,3 +443,23 @@ def test_gradient_control_variate_mixed_and_bf16a(F):
         say(prec, "grad err / scale", np.abs(grad - ref["grad"]) / gscale, "trace_P", st["trace_P"], ref["trace_P"])
         np.testing.assert_allclose(st["trace_P"], ref["trace_P"], rtol=1e-9)
         assert np.all(np.abs(grad - ref["grad"]) <= 1e-4 * gscale), (prec, grad, ref["grad"])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["m32_n1500_m100", "exp_clustered_n2000_m70", "ragged_n333_m7"])
+@pytest.mark.parametrize("mode", ["one", "opt", "opt_printed"])
+def test_predictive_variance_control_variate_matches_oracle(F, name, mode):
+    """Algorithm 1 with D_s as control variate for its stochastic diagonal
+    (App. E), float64 at a tight tolerance, identical Rademacher draws."""
+    say("case", name, mode)
+    cvm = {"one": F.CV_ONE, "opt": F.CV_OPT, "opt_printed": F.CV_OPT_PRINTED}[mode]
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    pred = np.vstack([G.uniform_locations(257, 902), [[1.3, 0.5], [5.0, 5.0]]])
+    mdl = O.FSA(locs, ind, theta, gamma)
+    ref, det = O.predict_var(mdl, pred, 16, 23, tol=1e-12, max_iter=3000, control_variate=mode)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=2, seed=23, tol=1e-12, max_iter=3000,
+               control_variate=cvm) as f:
+        var, _, st = f.predict_var(pred, 16)
+    err = np.abs(var - ref).max() / np.abs(ref).max()
+    say("var err", err, "c range", det["cv_c"].min(), det["cv_c"].max())
+    assert err < 1e-9
