@@ -34,6 +34,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+from scipy.special import erfc
 import scipy.linalg as sla
 import scipy.sparse as sp
 from scipy.spatial import cKDTree
@@ -639,3 +640,26 @@ def predict_var(model, pred_locs, num_samples, seed, tol=1e-8, max_iter=1000, fi
     if u is not None:
         det["mean"] = G_T @ (model.Smn_T.T @ u) + SsT @ u
     return var, det
+
+
+# ---------------------------------------------------------------------------
+# Scores of a Gaussian predictive distribution (Section 4)
+# ---------------------------------------------------------------------------
+
+
+def scores(y, mean, var):
+    """(log-score, CRPS, RMSE) of predictive means and variances against test
+    responses y, averaged over the points: log-score -log phi(y; mu, sigma^2),
+    CRPS in the closed form for a normal predictive distribution,
+    sigma (-1/sqrt(pi) + 2 phi(z) + z (2 Phi(z) - 1)) with z = (y - mu)/sigma,
+    and the root mean squared error of the means."""
+    y, mu, v = (np.asarray(a, dtype=np.float64) for a in (y, mean, var))
+    sd = np.sqrt(v)
+    z = (y - mu) / sd
+    ls = np.mean(0.5 * np.log(2.0 * math.pi * v) + 0.5 * z * z)
+    phi = np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+    Phi = 0.5 * erfc(-z / math.sqrt(2.0))
+    crps = np.mean(sd * (-1.0 / math.sqrt(math.pi) + 2.0 * phi + z * (2.0 * Phi - 1.0)))
+    rmse = math.sqrt(np.mean((y - mu) ** 2))
+    return float(ls), float(crps), float(rmse)
+

@@ -589,3 +589,27 @@ def test_row_sampled_oracle_equals_assembled_oracle():
     X = np.random.default_rng(63).standard_normal((900, 3))
     np.testing.assert_allclose(rows.matvec_rows(idx, X), full.matvec(X)[idx], rtol=0, atol=1e-12)
     np.testing.assert_allclose(rows.probe_rows(idx, 4, 64), O.probes(full, 4, 64)[idx], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- scores (Section 4)
+
+def test_scores_match_definitions():
+    """Log-score against scipy's normal log density; the closed-form CRPS
+    against its definition, the integral of (F(x) - 1{x >= y})^2 over x,
+    by quadrature; RMSE of the means."""
+    from scipy import integrate, stats
+    rng = np.random.default_rng(3)
+    n = 40
+    mu = rng.normal(size=n)
+    var = rng.uniform(0.05, 2.0, size=n)
+    y = mu + rng.normal(size=n) * np.sqrt(var) * 1.5
+    ls, crps, rmse = O.scores(y, mu, var)
+    assert abs(ls + np.mean(stats.norm.logpdf(y, mu, np.sqrt(var)))) < 1e-12
+    c = []
+    for i in range(n):
+        F = lambda x: stats.norm.cdf(x, mu[i], math.sqrt(var[i]))
+        lo, hi = mu[i] - 12 * math.sqrt(var[i]), mu[i] + 12 * math.sqrt(var[i])
+        c.append(integrate.quad(lambda x: F(x) ** 2, lo, y[i], epsabs=1e-13, limit=200)[0]
+                 + integrate.quad(lambda x: (1.0 - F(x)) ** 2, y[i], hi, epsabs=1e-13, limit=200)[0])
+    assert abs(crps - np.mean(c)) < 1e-9
+    assert abs(rmse - math.sqrt(np.mean((y - mu) ** 2))) < 1e-15
