@@ -248,6 +248,16 @@ enum {
  * row-major, in the caller's point order. */
 fsa_status fsa_apply(fsa_ctx* ctx, int32_t which, const double* X, double* Y, int32_t ncols);
 
+/* Scores of Gaussian predictive distributions against test responses
+ * (Section 4), averaged over the n points: out[0] log-score
+ * -log phi(y; mu, var), out[1] CRPS sigma (-1/sqrt(pi) + 2 phi(z) + z (2 Phi(z) - 1)),
+ * z = (y - mu)/sigma, out[2] RMSE of the means.  y, mean, var: host arrays
+ * of n doubles (var > 0), e.g. the outputs of fsa_predict_var; out: host,
+ * 3 doubles.  Computed on the device (default stream) with fixed-order sums;
+ * INVALID_ARG for n < 1, a null pointer, or a non-finite or non-positive
+ * variance. */
+fsa_status fsa_scores(const double* y, const double* mean, const double* var, int64_t n, double* out);
+
 /* Release every cached device block of the process-wide pool and every
  * cached pinned host block of the solvers' readbacks.  Blocks held by live
  * contexts are not affected. */

@@ -416,6 +416,52 @@ __global__ void k_pred_cv(int64_t np_, int s, const double* __restrict__ Z1, dou
   for (int i = 0; i < s; ++i) zl[i] = zl[i] - c * zv[i] + c * E[j] * z[i];
 }
 
+// ---- scores (Section 4) ----
+// per-workgroup partial sums of the log-score, CRPS and squared-error terms,
+// and a count of variances that are not finite and positive
+__global__ __launch_bounds__(256) void k_score_parts(const double* __restrict__ y, const double* __restrict__ mu,
+                                                     const double* __restrict__ var, int64_t n,
+                                                     double* __restrict__ part, int* __restrict__ bad) {
+  __shared__ double red[3][256];
+  const int t = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  int nb = 0;
+  for (int64_t i = blockIdx.x * 256 + t; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = var[i];
+    if (!(v > 0.0) || !isfinite(v)) {
+      ++nb;
+      continue;
+    }
+    const double sd = sqrt(v), e = y[i] - mu[i], z = e / sd;
+    a0 += 0.5 * log(2.0 * M_PI * v) + 0.5 * z * z;
+    const double phi = exp(-0.5 * z * z) / sqrt(2.0 * M_PI);
+    const double Phi = 0.5 * erfc(-z / sqrt(2.0));
+    a1 += sd * (-1.0 / sqrt(M_PI) + 2.0 * phi + z * (2.0 * Phi - 1.0));
+    a2 += e * e;
+  }
+  if (nb) atomicAdd(bad, nb);
+  red[0][t] = a0;
+  red[1][t] = a1;
+  red[2][t] = a2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+      for (int j = 0; j < 3; ++j) red[j][t] += red[j][t + h];
+    __syncthreads();
+  }
+  if (t < 3) part[(int64_t)blockIdx.x * 3 + t] = red[t][0];
+}
+
+// the scores from the partials (fixed order): mean log-score, mean CRPS, RMSE
+__global__ void k_score_final(const double* __restrict__ part, int nparts, int64_t n, double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= 3) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * 3 + j];
+  s /= (double)n;
+  out[j] = j == 2 ? sqrt(s) : s;
+}
+
 __global__ void k_add_cols(int ncols, const double* __restrict__ x, double* __restrict__ y) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < ncols) y[c] += x[c];
@@ -777,6 +823,34 @@ static void pinned_trim() {
   std::lock_guard<std::mutex> lk(g_pinned_mu);
   for (auto& b : g_pinned) (void)hipHostFree(b.first);
   g_pinned.clear();
+}
+
+fsa_status fsa_scores(const double* y, const double* mean, const double* var, int64_t n, double* out) {
+  if (!y || !mean || !var || !out) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (n < 1) { set_error("n must be >= 1"); return FSA_ERR_INVALID_ARG; }
+  hipStream_t st = nullptr;
+  PoolStream ps(st);
+  Buf<double> d;
+  Buf<int> bad;
+  const int G = (int)std::min<int64_t>(ceil_div(n, 256), 1024);
+  FSA_TRY(d.alloc(3 * (size_t)n + 3 * (size_t)G + 3));
+  FSA_TRY(bad.alloc(1));
+  FSA_HIP(hipMemcpyAsync(d.p, y, n * sizeof(double), hipMemcpyHostToDevice, st));
+  FSA_HIP(hipMemcpyAsync(d.p + n, mean, n * sizeof(double), hipMemcpyHostToDevice, st));
+  FSA_HIP(hipMemcpyAsync(d.p + 2 * n, var, n * sizeof(double), hipMemcpyHostToDevice, st));
+  FSA_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+  double* part = d.p + 3 * n;
+  hipLaunchKernelGGL(k_score_parts, dim3(G), dim3(256), 0, st, d.p, d.p + n, d.p + 2 * n, n, part, bad.p);
+  hipLaunchKernelGGL(k_score_final, dim3(1), dim3(64), 0, st, part, G, n, part + 3 * (size_t)G);
+  FSA_HIP(hipGetLastError());
+  double res[3];
+  int hb = 0;
+  FSA_HIP(hipMemcpyAsync(res, part + 3 * (size_t)G, sizeof(res), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (hb) { set_error("%d predictive variances are not finite and positive", hb); return FSA_ERR_INVALID_ARG; }
+  for (int j = 0; j < 3; ++j) out[j] = res[j];
+  return FSA_OK;
 }
 
 void fsa_pool_trim(void) {

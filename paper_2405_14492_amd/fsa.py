@@ -32,7 +32,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfsa.so")
 EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad", "fsa_grad", "fsa_predict_var",
             "fsa_destroy",
             "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_export_lanczos", "fsa_apply",
-            "fsa_pool_trim"]
+            "fsa_pool_trim", "fsa_scores"]
 
 
 class FsaError(RuntimeError):
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fsa_apply.restype = C.c_int
     lib.fsa_pool_trim.argtypes = []
     lib.fsa_pool_trim.restype = None
+    lib.fsa_scores.argtypes = [dp, dp, dp, C.c_int64, dp]
+    lib.fsa_scores.restype = C.c_int
     return lib
 
 
@@ -256,6 +258,17 @@ def fsa_export_lanczos(ctx, ncols, max_iter):
     _check(lib().fsa_export_lanczos(ctx, it.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(a), _dptr(b), _dptr(w),
                                     _dptr(q)))
     return {"iters": it, "alpha": a, "beta": b, "weight": w, "slq": q}
+
+
+def fsa_scores(y, mean, var):
+    """(log-score, CRPS, RMSE) of Gaussian predictive distributions against
+    test responses y (Section 4), computed on the device."""
+    y, mean, var = _f64(y).ravel(), _f64(mean).ravel(), _f64(var).ravel()
+    if not (y.shape == mean.shape == var.shape):
+        raise ValueError("y, mean and var must have the same length")
+    out = np.zeros(3)
+    _check(lib().fsa_scores(_dptr(y), _dptr(mean), _dptr(var), y.shape[0], _dptr(out)))
+    return float(out[0]), float(out[1]), float(out[2])
 
 
 def fsa_apply(ctx, which, X, ncols=None):

@@ -463,3 +463,28 @@ def test_predictive_variance_control_variate_matches_oracle(F, name, mode):
     err = np.abs(var - ref).max() / np.abs(ref).max()
     say("var err", err, "c range", det["cv_c"].min(), det["cv_c"].max())
     assert err < 1e-9
+
+
+@pytest.mark.gpu
+def test_scores_match_oracle(F):
+    """Log-score, CRPS and RMSE of the predictive distribution at held-out
+    points (Section 4) against the oracle's, from the same means and
+    variances; and the refusal of a non-positive variance."""
+    locs, y, theta, ind, gamma = case(**CASES["m32_n1500_m100"])
+    pred = G.uniform_locations(400, 903)
+    ytest = G.rff_response(pred, O.MATERN32, 1.0, 0.05, 0.1, 300, 301)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=2, seed=3, tol=1e-10, max_iter=3000) as f:
+        f.nll_grad(with_grad=False)
+        # enough samples that the stochastic diagonal leaves every variance
+        # positive (with a few dozen, one of these 400 went below zero)
+        var, mean, _ = f.predict_var(pred, 512, with_mean=True)
+    say("smallest predictive variance", var.min())
+    assert var.min() > 0
+    got = F.fsa_scores(ytest, mean, var)
+    ref = O.scores(ytest, mean, var)
+    say("scores", got, ref)
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
+    bad = var.copy()
+    bad[7] = 0.0
+    with pytest.raises(F.FsaError):
+        F.fsa_scores(ytest, mean, bad)
