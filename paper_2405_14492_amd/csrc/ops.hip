@@ -853,7 +853,7 @@ __global__ __launch_bounds__(256) void k_pcg_setup(const double* __restrict__ bn
 // First stage of a fixed-order column sum over many partial rows: workgroup
 // g sums rows g, g + G, g + 2G, ... of part (coalesced: 64 columns per row
 // block), out[g][c].  The second stage sums the G rows per column.
-constexpr int COLSUM_G = 128;
+constexpr int COLSUM_G = 512;
 __global__ __launch_bounds__(256) void k_colsum_stage1(const double* __restrict__ part, int nparts, int ldp, int ncols,
                                                        double* __restrict__ out, int ldo) {
   __shared__ double red[4][64];
