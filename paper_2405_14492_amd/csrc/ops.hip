@@ -481,11 +481,17 @@ __global__ void k_tile_counts(const int64_t* __restrict__ cs, int64_t ncell, Gri
 }
 
 // one workgroup per cell, one wave per row at a time: every nonzero of the
-// cell's rows goes to its (group, chunk) tile at its MFMA-order slot
+// cell's rows goes to its (group, chunk) tile at its MFMA-order slot, and the
+// tile's mask gets the bit of the 16 x 16 block (row tile, step) it lands in
+// (bit rt * 4 + ks; a nonzero value, so a block with only zeros stays off).
+// The masks of the cell's first TILE_MASK_LDS tiles gather in LDS, the rest
+// (cells of very many points) in global memory.
+constexpr int TILE_MASK_LDS = 512;
 __global__ __launch_bounds__(256) void k_tile_fill(const int64_t* __restrict__ cs, int64_t ncell, GridDesc gd,
                                                    const int64_t* __restrict__ toff, const int64_t* __restrict__ rp,
                                                    const int* __restrict__ key, const float* __restrict__ val,
-                                                   float* __restrict__ tiles) {
+                                                   float* __restrict__ tiles, unsigned* __restrict__ mask) {
+  __shared__ unsigned msk[TILE_MASK_LDS];
   const int64_t c = blockIdx.x;
   if (c >= ncell) return;
   const int64_t rb = cs[c], re = cs[c + 1];
@@ -493,34 +499,31 @@ __global__ __launch_bounds__(256) void k_tile_fill(const int64_t* __restrict__ c
   int qb[3], qe[3], off[3];
   const int V = cell_ranges(c, gd, cs, qb, qe, off);
   const int nk = (V + SpmmTile::CH - 1) / SpmmTile::CH;
+  const int nt = (int)((re - rb + SpmmTile::ROWS - 1) / SpmmTile::ROWS) * nk;
   float* base = tiles + toff[c] * SpmmTile::FLOATS;
+  unsigned* gmask = mask + toff[c];
+  for (int i = threadIdx.x; i < nt; i += 256) {
+    if (i < TILE_MASK_LDS) msk[i] = 0u;
+    else gmask[i] = 0u;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t p = rb + w; p < re; p += 4) {
     const int g = (int)((p - rb) / SpmmTile::ROWS), r = (int)((p - rb) % SpmmTile::ROWS);
     for (int64_t e = rp[p] + lane; e < rp[p + 1]; e += 64) {
       const int slot = key[e] & KEY_SLOT_MASK;
-      base[(int64_t)(g * nk + slot / SpmmTile::CH) * SpmmTile::FLOATS + SpmmTile::offset(r, slot % SpmmTile::CH)] =
-          val[e];
+      const int t = g * nk + slot / SpmmTile::CH, v = slot % SpmmTile::CH;
+      const float x = val[e];
+      base[(int64_t)t * SpmmTile::FLOATS + SpmmTile::offset(r, v)] = x;
+      if (x != 0.f) {
+        const unsigned bit = 1u << ((r >> 4) * 4 + (v >> 4));
+        if (t < TILE_MASK_LDS) atomicOr(&msk[t], bit);
+        else atomicOr(&gmask[t], bit);
+      }
     }
   }
-}
-
-// bit rt * 4 + ks of mask[t]: block (row tile rt, 16-position step ks) of
-// tile t holds a nonzero (one wave per tile; block b is words b*64 .. +63)
-__global__ __launch_bounds__(256) void k_tile_mask(const float* __restrict__ tiles, int64_t ntile,
-                                                   unsigned* __restrict__ mask) {
-  const int64_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t >= ntile) return;
-  const f4* w4 = reinterpret_cast<const f4*>(tiles + t * SpmmTile::FLOATS);
-  unsigned m = 0;
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const f4 v = w4[b * 64 + lane];
-    const bool nz = v[0] != 0.f || v[1] != 0.f || v[2] != 0.f || v[3] != 0.f;
-    if (__any(nz)) m |= 1u << b;
-  }
-  if (lane == 0) mask[t] = m;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nt && i < TILE_MASK_LDS; i += 256) gmask[i] = msk[i];
 }
 
 fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<int64_t>& toff, Buf<float>& tiles,
@@ -539,12 +542,10 @@ fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<i
   const size_t nf = (size_t)(ntile > 0 ? ntile : 1) * SpmmTile::FLOATS;
   FSA_TRY(tiles.alloc(nf));
   FSA_HIP(hipMemsetAsync(tiles.p, 0, nf * sizeof(float), st));
+  FSA_TRY(tmask.alloc(ntile > 0 ? ntile : 1));
   if (nc > 0)
     hipLaunchKernelGGL(k_tile_fill, dim3(nc), dim3(256), 0, st, g.cstart.p, nc, g.desc, toff.p, S.row_ptr.p, S.key.p,
-                       val, tiles.p);
-  FSA_TRY(tmask.alloc(ntile > 0 ? ntile : 1));
-  if (ntile > 0)
-    hipLaunchKernelGGL(k_tile_mask, dim3(ceil_div(ntile, 4)), dim3(256), 0, st, tiles.p, ntile, tmask.p);
+                       val, tiles.p, tmask.p);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
