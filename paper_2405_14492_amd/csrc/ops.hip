@@ -480,8 +480,9 @@ __global__ void k_tile_counts(const int64_t* __restrict__ cs, int64_t ncell, Gri
   cnt[c] = nr > 0 ? (int)((nr + SpmmTile::ROWS - 1) / SpmmTile::ROWS) * ((V + SpmmTile::CH - 1) / SpmmTile::CH) : 0;
 }
 
-// one workgroup per cell, one wave per row at a time: every nonzero of the
-// cell's rows goes to its (group, chunk) tile at its MFMA-order slot, and the
+// one workgroup per cell: the cell's tiles are cleared, then, one wave per
+// row at a time, every nonzero of the cell's rows goes to its (group, chunk)
+// tile at its MFMA-order slot, and the
 // tile's mask gets the bit of the 16 x 16 block (row tile, step) it lands in
 // (bit rt * 4 + ks; a nonzero value, so a block with only zeros stays off).
 // The masks of the cell's first TILE_MASK_LDS tiles gather in LDS, the rest
@@ -506,6 +507,10 @@ __global__ __launch_bounds__(256) void k_tile_fill(const int64_t* __restrict__ c
     if (i < TILE_MASK_LDS) msk[i] = 0u;
     else gmask[i] = 0u;
   }
+  // the cell's tiles start from zero (written here, so the scattered
+  // entries below update lines this workgroup has just written)
+  f4* base4 = reinterpret_cast<f4*>(base);
+  for (int64_t i = threadIdx.x; i < (int64_t)nt * (SpmmTile::FLOATS / 4); i += 256) base4[i] = f4{0.f, 0.f, 0.f, 0.f};
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t p = rb + w; p < re; p += 4) {
@@ -540,8 +545,7 @@ fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<i
   FSA_HIP(hipMemcpyAsync(&ntile, toff.p + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   const size_t nf = (size_t)(ntile > 0 ? ntile : 1) * SpmmTile::FLOATS;
-  FSA_TRY(tiles.alloc(nf));
-  FSA_HIP(hipMemsetAsync(tiles.p, 0, nf * sizeof(float), st));
+  FSA_TRY(tiles.alloc(nf));  // cleared cell by cell by the fill
   FSA_TRY(tmask.alloc(ntile > 0 ? ntile : 1));
   if (nc > 0)
     hipLaunchKernelGGL(k_tile_fill, dim3(nc), dim3(256), 0, st, g.cstart.p, nc, g.desc, toff.p, S.row_ptr.p, S.key.p,
