@@ -488,3 +488,20 @@ def test_scores_match_oracle(F):
     bad[7] = 0.0
     with pytest.raises(F.FsaError):
         F.fsa_scores(ytest, mean, bad)
+
+
+@pytest.mark.gpu
+def test_control_variate_with_one_probe(F):
+    """One probe: the centred and printed coefficients have nothing to
+    regress on (c = 0, the plain estimate); c = 1 still applies.  Against the
+    oracle with fixed iterations; no NaN anywhere."""
+    locs, y, theta, ind, gamma = case(**CASES["ragged_n333_m7"])
+    mdl = O.FSA(locs, ind, theta, gamma)
+    for mode, cvm in (("one", F.CV_ONE), ("opt", F.CV_OPT), ("opt_printed", F.CV_OPT_PRINTED)):
+        ref = O.nll_grad(mdl, y, 1, 13, fixed_iter=10, control_variate=mode)
+        with F.FSA(locs, y, theta, ind, gamma, num_probes=1, seed=13, fixed_iter=10, control_variate=cvm) as f:
+            nll, grad, st = f.nll_grad()
+        assert np.all(np.isfinite(grad)) and np.all(np.isfinite(st["cv_c"]))
+        np.testing.assert_allclose(st["cv_c"], ref["cv_c"], atol=1e-12)
+        gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
+        assert np.all(np.abs(grad - ref["grad"]) <= 1e-9 * gscale + 1e-12), (mode, grad, ref["grad"])
