@@ -554,6 +554,7 @@ struct fsa_ctx {
   char* hstage = nullptr;
   size_t hstage_bytes = 0;
   int deriv_state = 0;
+  bool deriv_marked = false;  // derivative build requested, not yet enqueued
   bool timer_pending = false;  // the last solve's kernel events are not yet summed
   // gradient
   Buf<double> F, dvals, Xb, tmp, dSm, Ework;
@@ -918,6 +919,8 @@ int64_t fsa_nnz(const fsa_ctx* c) { return c ? c->csr.nnz : -1; }
 }  // extern "C"
 
 // ---------------------------------------------------------------- PCG driver
+static fsa_status enqueue_derivative(fsa_ctx* c);
+
 // The side stream (non-blocking, default priority) and its events.
 static fsa_status side_stream(fsa_ctx* c) {
   if (!c->st2) {
@@ -1066,6 +1069,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   double prev_res = -1.0;
   for (it = 0; it < max_iter; ++it) {
     FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
+    if (it == 0) FSA_TRY(enqueue_derivative(c));  // a derivative build marked before the solve
     if constexpr (sizeof(T) == 4) {
       if (c->opt.rr_period > 0 && (it + 1) % c->opt.rr_period == 0 && it + 1 < max_iter)
         FSA_TRY(pcg_replace_residual_f32(reinterpret_cast<PcgBlock<float>&>(b), op64,
@@ -1246,8 +1250,16 @@ static fsa_status settle_derivative(fsa_ctx* c) {
   return FSA_OK;
 }
 
-// Enqueue the derivative build on the side stream behind everything on st.
-static fsa_status launch_derivative_async(fsa_ctx* c) {
+// A requested derivative build (mark_derivative) is enqueued on the side
+// stream by the solve once its first iteration is queued, so that the device
+// works while the host enqueues the derivative's ~20 launches; it runs
+// behind everything on st at that point (ev_ready), which also orders any
+// block the pool hands it after earlier users on st.
+static void mark_derivative(fsa_ctx* c) { c->deriv_marked = true; }
+
+static fsa_status enqueue_derivative(fsa_ctx* c) {
+  if (!c->deriv_marked) return FSA_OK;
+  c->deriv_marked = false;
   FSA_TRY(side_stream(c));
   FSA_HIP(hipEventRecord(c->ev_ready, c->st));
   FSA_HIP(hipStreamWaitEvent(c->st2, c->ev_ready, 0));
@@ -1599,11 +1611,12 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
     }
   }
   double t_build = now_ms();
-  if (grad && c->deriv_state == 0) FSA_TRY(launch_derivative_async(c));
+  if (grad && c->deriv_state == 0) mark_derivative(c);
   double ms_pcg = 0;
   fsa_status s;
   if (c->opt.precision != FSA_FP64) s = run_pcg<float>(c, &ms_pcg);
   else s = run_pcg<double>(c, &ms_pcg);
+  if (c->deriv_marked) FSA_TRY(enqueue_derivative(c));  // the solve ended before its first iteration
   if (s != FSA_OK && s != FSA_ERR_NOT_CONVERGED) {
     FSA_TRY(join_slq(c));
     collect_timer(c);
