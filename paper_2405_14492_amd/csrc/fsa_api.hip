@@ -467,15 +467,25 @@ __global__ void k_add_cols(int ncols, const double* __restrict__ x, double* __re
   if (c < ncols) y[c] += x[c];
 }
 
+// The gradient's block X (n x 2 ld): columns [0, ld) hold x = [u | P^{-1} z]
+// (u = U's column 0), columns [ld, 2 ld) hold U, both zero past ncols, so
+// that one reduction over A (or F) serves x and u together.
 __global__ void k_grad_block(int64_t n, int ncols, int64_t ld, const double* __restrict__ U, const void* Q0, int q0_f32,
                              double* __restrict__ X) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t p = e / ncols;
-  int c = (int)(e % ncols);
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t p = e / (2 * ld);
+  const int c = (int)(e % (2 * ld));
   if (p >= n) return;
-  int64_t o = p * ld + c;
-  if (c == 0) X[o] = U[o];
-  else X[o] = q0_f32 ? (double)((const float*)Q0)[o] : ((const double*)Q0)[o];
+  double v = 0.0;
+  if (c < ld) {
+    if (c < ncols) {
+      const int64_t o = p * ld + c;
+      v = c == 0 ? U[o] : (q0_f32 ? (double)((const float*)Q0)[o] : ((const double*)Q0)[o]);
+    }
+  } else if (c - ld < ncols) {
+    v = U[p * ld + (c - ld)];
+  }
+  X[e] = v;
 }
 
 // The solver's small per-solve readback in one block: flags[2] (int), then
@@ -1126,9 +1136,9 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   FSA_HIP(hipEventRecord(c->ev_slq, c->st2));
   c->slq_pending = true;
   // keep Q0 (P^{-1} z) for the gradient in float64
-  FSA_TRY(c->Xb.alloc(blk));
-  hipLaunchKernelGGL(k_grad_block, dim3(ceil_div((int64_t)n * tp, 256)), dim3(256), 0, st, n, tp, (int64_t)ld, c->U.p,
-                     (const void*)b.Q0, sizeof(T) == 4 ? 1 : 0, c->Xb.p);
+  FSA_TRY(c->Xb.alloc(2 * blk));
+  hipLaunchKernelGGL(k_grad_block, dim3(ceil_div((int64_t)n * 2 * ld, 256)), dim3(256), 0, st, n, tp, (int64_t)ld,
+                     c->U.p, (const void*)b.Q0, sizeof(T) == 4 ? 1 : 0, c->Xb.p);
   FSA_HIP(hipGetLastError());
   // iteration statistics (staged behind the work above)
   HostStatus hs;
@@ -1299,24 +1309,27 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
   // sparse product's epilogue without storing it, the low-rank parts from
   // m-space reductions of x and u (no n x t expansion).
   const int mp = c->mp;
-  const int ldw = (int)round_up(tp, 64);
+  // x and u side by side in one n x 2 ld block (k_grad_block): one reduction
+  // over A and one over F give A^T x, A^T u, F^T x, F^T u (two launches, not
+  // four; the float64 reduction's cost is its MFMA work per 64-column block,
+  // which does not change)
+  const int ldx = 2 * ld;
+  const double* X = c->Xb.p;
+  const double* Ux = c->Xb.p + ld;
+  const int ldw = (int)round_up(ld + tp, 64);
   Buf<double> dd, wm;
   // dd: [0] u.Sx [1] u.x [2] u.dx [3] low-rank u.Sx [4] low-rank u.dx [5] |A^T x|^2
   // [6] (F^T x).(A^T x) [7] |x|^2 [8] x.Dx [9] x.dDx (tp each), then the results
   FSA_TRY(dd.alloc(10 * (size_t)tp + 15));
-  FSA_TRY(wm.alloc(4 * (size_t)mp * ldw));
-  double* w_ax = wm.p;
-  double* w_fx = wm.p + (size_t)mp * ldw;
-  double* w_au = wm.p + 2 * (size_t)mp * ldw;
-  double* w_fu = wm.p + 3 * (size_t)mp * ldw;
-  FSA_TRY(spmm_dot<double>(c->csr, c->grid, c->vals.p, c->Xb.p, c->U.p, ld, tp, dd.p, c->scr, st));
-  FSA_TRY((coldot<double, double>(c->U.p, c->Xb.p, n, ld, tp, dd.p + tp, c->scr, st)));
-  FSA_TRY(spmm_dot<double>(c->csr, c->grid, c->dvals.p, c->Xb.p, c->U.p, ld, tp, dd.p + 2 * tp, c->scr, st));
-  FSA_TRY(lowrank_reduce<double>(c->A.p, n, mp, c->Xb.p, ld, tp, nullptr, c->scr, w_ax, ldw, st));
-  FSA_TRY(lowrank_reduce<double>(c->F.p, n, mp, c->Xb.p, ld, tp, nullptr, c->scr, w_fx, ldw, st));
-  FSA_TRY(lowrank_reduce<double>(c->A.p, n, mp, c->U.p, ld, tp, nullptr, c->scr, w_au, ldw, st));
-  FSA_TRY(lowrank_reduce<double>(c->F.p, n, mp, c->U.p, ld, tp, nullptr, c->scr, w_fu, ldw, st));
-  hipLaunchKernelGGL(k_grad_mdots, dim3(tp), dim3(256), 0, st, w_ax, w_fx, w_au, w_fu, mp, ldw, dd.p + 3 * tp,
+  FSA_TRY(wm.alloc(2 * (size_t)mp * ldw));
+  double* w_a = wm.p;                     // columns [0, tp): A^T x; [ld, ld + tp): A^T u
+  double* w_f = wm.p + (size_t)mp * ldw;  // the same with F
+  FSA_TRY(spmm_dot<double>(c->csr, c->grid, c->vals.p, X, Ux, ldx, tp, dd.p, c->scr, st));
+  FSA_TRY((coldot<double, double>(Ux, X, n, ldx, tp, dd.p + tp, c->scr, st)));
+  FSA_TRY(spmm_dot<double>(c->csr, c->grid, c->dvals.p, X, Ux, ldx, tp, dd.p + 2 * tp, c->scr, st));
+  FSA_TRY(lowrank_reduce<double>(c->A.p, n, mp, X, ldx, ld + tp, nullptr, c->scr, w_a, ldw, st));
+  FSA_TRY(lowrank_reduce<double>(c->F.p, n, mp, X, ldx, ld + tp, nullptr, c->scr, w_f, ldw, st));
+  hipLaunchKernelGGL(k_grad_mdots, dim3(tp), dim3(256), 0, st, w_a, w_f, w_a + ld, w_f + ld, mp, ldw, dd.p + 3 * tp,
                      dd.p + 4 * tp, dd.p + 5 * tp, dd.p + 6 * tp);
   hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 3 * tp, dd.p);
   hipLaunchKernelGGL(k_add_cols, dim3(ceil_div(tp, 64)), dim3(64), 0, st, tp, dd.p + 4 * tp, dd.p + 2 * tp);
@@ -1332,7 +1345,7 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
     const int64_t g = std::min<int64_t>(std::max<int64_t>(ceil_div(n, 64), 1), 1024);
     Buf<double> xp;
     FSA_TRY(xp.alloc(3 * (size_t)g * ldp));
-    hipLaunchKernelGGL(k_cv_xdots, dim3(g, ncb), dim3(256), 0, st, c->Xb.p, n, ld, tp, c->D.p, c->dD.p, xp.p, ldp);
+    hipLaunchKernelGGL(k_cv_xdots, dim3(g, ncb), dim3(256), 0, st, X, n, ldx, tp, c->D.p, c->dD.p, xp.p, ldp);
     for (int j = 0; j < 3; ++j)
       FSA_TRY(colsum(xp.p + (size_t)j * g * ldp, (int)g, ldp, tp, dd.p + (7 + j) * (size_t)tp, st));
     hipLaunchKernelGGL(k_finalize_control_variate, dim3(1), dim3(1), 0, st, tp, dd.p, dd.p + tp, dd.p + 2 * tp, dd.p + 7 * tp,
