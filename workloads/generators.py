@@ -167,3 +167,11 @@ def taper_range_by_count(locs: np.ndarray, n_gamma: float, sample: int = 20000, 
 def poisson_arrivals(n_requests: int, rate: float, seed: int) -> np.ndarray:
     """Arrival times (s) of a Poisson process with `rate` requests per second."""
     return np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, n_requests))
+
+
+def laplace_weights(n: int, seed: int, lo: float = 0.05, hi: float = 0.25) -> np.ndarray:
+    """n diagonal weights uniform on [lo, hi]: the range that the negative
+    second derivative of a Bernoulli-logit log-likelihood takes for latent
+    values |b| <= 3 (its maximum is 1/4)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, n)
