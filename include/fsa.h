@@ -263,6 +263,89 @@ fsa_status fsa_scores(const double* y, const double* mean, const double* var, in
  * contexts are not affected. */
 void fsa_pool_trim(void);
 
+/* ------------------------------------------------------------------------
+ * The FITC preconditioner in iterative methods for Vecchia approximations
+ * (Section 5).
+ *
+ * Vecchia approximation of a latent process b ~ N(0, Sigma) (Section 5.1):
+ * points in the given order; N(i) = the min(m_v, i) nearest of points
+ * 0 .. i-1 (nearest first, a tie in distance to the lower index, squared
+ * distances dx*dx + dy*dy in float64 without fused multiply-add);
+ * A_i = Sigma_{N(i),i}^T Sigma_{N(i)}^{-1}, D_i = Sigma_ii - A_i Sigma_{N(i),i};
+ * B unit lower triangular with B_{i,N(i)} = -A_i; Sigma_V^{-1} = B^T D^{-1} B.
+ * W is a positive diagonal (negative second derivatives of a log-likelihood,
+ * Section 5.1), given by the caller.
+ *
+ * Linear solves (Sigma_V^{-1} + W)^{-1} v are computed as
+ * W^{-1} (Sigma_V + W^{-1})^{-1} Sigma_V v: block PCG on Sigma_V + W^{-1}
+ * with the FITC preconditioner P = Sigma_mn^T Sigma_m^{-1} Sigma_mn + D_s,
+ * D_s = diag(Sigma - Sigma_mn^T Sigma_m^{-1} Sigma_mn) + W^{-1} (Woodbury,
+ * App. F).  (The printed equivalent form of eq. VL_v2 is not this inverse;
+ * this one is.)  log det(Sigma_V^{-1} + W) = sum log W - sum log D +
+ * log det(Sigma_V + W^{-1}), the last by preconditioned SLQ (Section 3.3)
+ * with probes z ~ (0, P) drawn as for fsa_nll_grad (Rademacher, keyed by the
+ * seed and the point index), weight z^T P^{-1} z.  Sigma_V products run as
+ * two sparse triangular solves scheduled by levels of the neighbour graph.
+ *
+ * All pointers of these calls are device pointers; work runs on the stream
+ * given at build (null: the default stream) and every call returns after it
+ * has finished.
+ * ------------------------------------------------------------------------ */
+typedef struct fsa_vecchia fsa_vecchia; /* opaque; owned by the library until fsa_vecchia_destroy */
+
+typedef struct {
+  int32_t nlevels;      /* levels of the triangular-solve schedule */
+  int32_t iters_max;    /* largest PCG iteration count over the columns */
+  int32_t iters_rhs;    /* PCG iterations of the solve's column */
+  int32_t converged;    /* 1 if every column met the tolerance */
+  double logdet_P;      /* log det P (Sylvester, App. F) */
+  double logdet_offset; /* sum log W - sum log D */
+  double logdet_sw;     /* SLQ estimate of log det(Sigma_V + W^{-1}) */
+  double ms_solve;      /* host wall-clock of the solve call */
+} fsa_vecchia_stats;
+
+typedef enum {
+  FSA_V_SIGMA = 0,     /* Sigma_V X = B^{-1} D B^{-T} X */
+  FSA_V_PRECISION = 1, /* Sigma_V^{-1} X = B^T D^{-1} B X */
+  FSA_V_OPERATOR = 2,  /* (Sigma_V + W^{-1}) X, the PCG operator */
+  FSA_V_P_INV = 3      /* P^{-1} X */
+} fsa_vecchia_op;
+
+/* Build the Vecchia factor (neighbours, A_i, D_i), its level schedule and
+ * the FITC preconditioner of Sigma + W^{-1} (Section 5.1).
+ *   locs: n x 2 row-major; inducing: m x 2 row-major; w: n weights W_ii > 0;
+ *   covariance kind (fsa_cov) with sigma1^2 > 0 and rho > 0 (no nugget:
+ *   the process is latent); 0 <= m_v <= 32; 1 <= m <= 512.
+ * The inputs are copied; the caller keeps ownership.  INVALID_ARG for bad
+ * sizes or parameters or a weight that is not finite and positive; NOT_SPD
+ * if a conditioning matrix Sigma_{N(i)} (duplicate locations), Sigma_m or
+ * the capacitance cannot be factored or a D_i is not positive. */
+fsa_status fsa_vecchia_build_dev(const double* locs, int64_t n, const double* inducing, int32_t m, int32_t kind,
+                                 double sigma1_sq, double rho, int32_t mv, const double* w, void* hip_stream,
+                                 fsa_vecchia** out);
+
+/* Copy out the factor: nbr (n x m_v int32, -1 past the min(m_v, i)
+ * neighbours of point i, nearest first), coef (n x m_v, A_i in the order of
+ * nbr, 0 on the padding) and d (n, D_i). */
+fsa_status fsa_vecchia_factor_dev(fsa_vecchia* v, int32_t* nbr, double* coef, double* d);
+
+/* Y = op X for ncols columns of n x ncols row-major blocks with leading
+ * dimensions ldx, ldy >= ncols; X and Y must not overlap. */
+fsa_status fsa_vecchia_apply_dev(fsa_vecchia* v, int32_t which, const double* X, int64_t ldx, int32_t ncols,
+                                 double* Y, int64_t ldy);
+
+/* One block PCG run on Sigma_V + W^{-1} over [Sigma_V rhs, z_1 .. z_t]
+ * (t = num_probes, 1..1023), each column stopped once ||r|| < tol ||b||:
+ * x (n) = (Sigma_V^{-1} + W)^{-1} rhs and *logdet (host) = the SLQ estimate
+ * of log det(Sigma_V^{-1} + W).  stats (host, may be null).  NOT_CONVERGED
+ * if max_iter (<= 6000) was reached (outputs are still written); BREAKDOWN
+ * if h^T K h <= 0 or a non-finite value appeared. */
+fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, double* x, int32_t num_probes,
+                                        uint64_t seed, double tol, int32_t max_iter, double* logdet,
+                                        fsa_vecchia_stats* stats);
+
+fsa_status fsa_vecchia_destroy(fsa_vecchia* v);
+
 #ifdef __cplusplus
 }
 #endif

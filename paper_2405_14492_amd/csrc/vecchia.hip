@@ -1,0 +1,986 @@
+// Iterative methods for Vecchia approximations with the FITC preconditioner
+// (Section 5): the Vecchia factor of the latent process, products with
+// Sigma_V = B^{-1} D B^{-T} by level-scheduled triangular solves, block PCG
+// on Sigma_V + W^{-1} preconditioned by P = Sigma_mn^T Sigma_m^{-1} Sigma_mn
+// + D_s (D_s = diag(Sigma - Sigma_mn^T Sigma_m^{-1} Sigma_mn) + W^{-1}), the
+// solve (Sigma_V^{-1} + W)^{-1} v = W^{-1} (Sigma_V + W^{-1})^{-1} Sigma_V v
+// and the SLQ estimate of log det(Sigma_V^{-1} + W).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "ops.hpp"
+
+namespace fsa {
+namespace {
+
+constexpr int VMV_MAX = 32;   // largest neighbour count (lists held in LDS)
+constexpr int KNN_TPB = 128;  // points per neighbour-search workgroup
+constexpr int KNN_TILE = 256; // earlier points staged per LDS tile
+
+// ---------------------------------------------------------------- neighbours
+// N(i) = the min(mv, i) nearest of points 0 .. i-1, ordered by (squared
+// distance, index), -1 past the list.  One thread per point scans the
+// earlier points in LDS tiles and keeps its sorted list in LDS
+// ([slot][thread]).  Squared distances are dx*dx + dy*dy without fused
+// multiply-add, so that the choice is the one a plain float64 evaluation
+// makes.
+__global__ __launch_bounds__(KNN_TPB) void k_vknn(const double* __restrict__ xs, int64_t n, int mv,
+                                                  int* __restrict__ nbr) {
+#pragma clang fp contract(off)
+  __shared__ double tx[KNN_TILE], ty[KNN_TILE];
+  __shared__ double sd[VMV_MAX][KNN_TPB];
+  __shared__ int sj[VMV_MAX][KNN_TPB];
+  const int t = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * KNN_TPB;
+  const int64_t i = i0 + t;
+  const bool live = i < n;
+  const double px = live ? xs[2 * i] : 0.0, py = live ? xs[2 * i + 1] : 0.0;
+  const int k = live ? (int)min<int64_t>(mv, i) : 0;
+  int cnt = 0;
+  double worst = INFINITY;
+  const int64_t jend = min(i0 + KNN_TPB, n);
+  for (int64_t j0 = 0; j0 < jend; j0 += KNN_TILE) {
+    __syncthreads();
+    for (int q = t; q < KNN_TILE; q += KNN_TPB) {
+      const int64_t j = j0 + q;
+      tx[q] = j < n ? xs[2 * j] : 0.0;
+      ty[q] = j < n ? xs[2 * j + 1] : 0.0;
+    }
+    __syncthreads();
+    const int lim = k > 0 ? (int)min<int64_t>(KNN_TILE, i - j0) : 0;
+    for (int q = 0; q < lim; ++q) {
+      const double dx = tx[q] - px;
+      const double dy = ty[q] - py;
+      const double dx2 = dx * dx;
+      const double dy2 = dy * dy;
+      const double d2 = dx2 + dy2;
+      if (cnt < k || d2 < worst) {
+        // the new index is larger than every listed one: it goes after all
+        // entries of equal distance; a full list drops its last entry
+        int p = cnt < k ? cnt : k - 1;
+        while (p > 0 && sd[p - 1][t] > d2) {
+          sd[p][t] = sd[p - 1][t];
+          sj[p][t] = sj[p - 1][t];
+          --p;
+        }
+        sd[p][t] = d2;
+        sj[p][t] = (int)(j0 + q);
+        if (cnt < k) ++cnt;
+        worst = cnt == k ? sd[k - 1][t] : INFINITY;
+      }
+    }
+  }
+  if (!live) return;
+  for (int s = 0; s < mv; ++s) nbr[i * mv + s] = s < cnt ? sj[s][t] : -1;
+}
+
+// ---------------------------------------------------------------- factor
+// A_i = Sigma_{N(i),i}^T Sigma_{N(i)}^{-1} and D_i = Sigma_ii - A_i
+// Sigma_{N(i),i} (Section 5.1): one wave per point, Sigma_{N(i)} factored by
+// Cholesky in LDS.  D_i is taken as sigma1^2 - |L^{-1} Sigma_{N(i),i}|^2 (the
+// same number).  info[0] counts points whose matrix is not positive definite
+// or whose D_i is not positive.
+__global__ __launch_bounds__(64) void k_vfactor(const double* __restrict__ xs, int64_t n, int mv,
+                                                const int* __restrict__ nbr, Theta th, double* __restrict__ coef,
+                                                double* __restrict__ Dv, int* __restrict__ info) {
+  __shared__ double S[VMV_MAX][VMV_MAX + 1];
+  __shared__ double r[VMV_MAX];
+  __shared__ double nx[VMV_MAX], ny[VMV_MAX];
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int my = lane < mv ? nbr[i * mv + lane] : -1;
+  const int k = __popcll(__ballot(my >= 0));
+  const double px = xs[2 * i], py = xs[2 * i + 1];
+  if (lane < k) {
+    nx[lane] = xs[2 * (int64_t)my];
+    ny[lane] = xs[2 * (int64_t)my + 1];
+  }
+  __syncthreads();
+  for (int e = lane; e < k * k; e += 64) {
+    const int a = e / k, b = e - a * k;
+    const double dx = nx[a] - nx[b], dy = ny[a] - ny[b];
+    S[a][b] = cov_d(sqrt(dx * dx + dy * dy), th);
+  }
+  if (lane < k) {
+    const double dx = nx[lane] - px, dy = ny[lane] - py;
+    r[lane] = cov_d(sqrt(dx * dx + dy * dy), th);
+  }
+  __syncthreads();
+  bool ok = true;
+  for (int j = 0; j < k; ++j) {
+    const double djj = S[j][j];
+    if (!(djj > 0.0) || !isfinite(djj)) {  // uniform: every lane read the same value
+      ok = false;
+      break;
+    }
+    const double l = sqrt(djj);
+    __syncthreads();
+    if (lane == j) S[j][j] = l;
+    if (lane > j && lane < k) S[lane][j] /= l;
+    __syncthreads();
+    const int w = k - j - 1;
+    for (int e = lane; e < w * w; e += 64) {
+      const int a = j + 1 + e / w, b = j + 1 + e % w;
+      if (b <= a) S[a][b] -= S[a][j] * S[b][j];
+    }
+    __syncthreads();
+  }
+  double D = th.s1;
+  if (ok) {
+    for (int j = 0; j < k; ++j) {  // L y = r (y overwrites r)
+      const double yj = r[j] / S[j][j];
+      __syncthreads();
+      if (lane == j) r[j] = yj;
+      if (lane > j && lane < k) r[lane] -= S[lane][j] * yj;
+      __syncthreads();
+    }
+    D = th.s1 - wave_sum(lane < k ? r[lane] * r[lane] : 0.0);
+    for (int j = k - 1; j >= 0; --j) {  // L^T a = y (a overwrites r)
+      const double aj = r[j] / S[j][j];
+      __syncthreads();
+      if (lane == j) r[j] = aj;
+      if (lane < j) r[lane] -= S[j][lane] * aj;
+      __syncthreads();
+    }
+  }
+  if (!(D > 0.0) || !isfinite(D)) ok = false;
+  if (lane < mv) coef[i * mv + lane] = (ok && lane < k) ? r[lane] : 0.0;
+  if (lane == 0) {
+    Dv[i] = ok ? D : 1.0;
+    if (!ok) atomicAdd(info, 1);
+  }
+}
+
+// ---------------------------------------------------------------- schedule
+// level[i] = 0 without neighbours, else 1 + max level of N(i): relaxed in
+// place (values only grow toward the fixed point; every neighbour has a
+// smaller index, so depth + 1 sweeps settle it).
+__global__ void k_vlevel(const int* __restrict__ nbr, int64_t n, int mv, int* level, int* changed) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int L = 0;
+  for (int s = 0; s < mv; ++s) {
+    const int j = nbr[i * mv + s];
+    if (j < 0) break;
+    L = max(L, level[j] + 1);
+  }
+  if (L != level[i]) {
+    level[i] = L;
+    changed[0] = 1;
+  }
+}
+
+__global__ void k_vlevel_hist(const int* __restrict__ level, int64_t n, int* cnt, int* maxlev) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(&cnt[level[i]], 1);
+  atomicMax(maxlev, level[i]);
+}
+
+__global__ void k_vmaxlevel(const int* __restrict__ level, int64_t n, int* maxlev) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) atomicMax(maxlev, level[i]);
+}
+
+// points grouped by level (order inside a level is free: its points are
+// independent of each other)
+__global__ void k_vlevel_scatter(const int* __restrict__ level, int64_t n, const int* __restrict__ lptr, int* cursor,
+                                 int* __restrict__ order) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int L = level[i];
+  order[lptr[L] + atomicAdd(&cursor[L], 1)] = (int)i;
+}
+
+// children of each point (the rows of B^T): counts, then fill, then each
+// list sorted by child index so that sums run in a fixed order
+__global__ void k_vchild_count(const int* __restrict__ nbr, int64_t n, int mv, int* cnt) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * mv) return;
+  const int j = nbr[e];
+  if (j >= 0) atomicAdd(&cnt[j], 1);
+}
+
+__global__ void k_vchild_fill(const int* __restrict__ nbr, const double* __restrict__ coef, int64_t n, int mv,
+                              const int64_t* __restrict__ cptr, int* cursor, int* __restrict__ ci,
+                              double* __restrict__ cv) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * mv) return;
+  const int j = nbr[e];
+  if (j < 0) return;
+  const int64_t pos = cptr[j] + atomicAdd(&cursor[j], 1);
+  ci[pos] = (int)(e / mv);
+  cv[pos] = coef[e];
+}
+
+__global__ void k_vchild_sort(const int64_t* __restrict__ cptr, int64_t n, int* ci, double* cv) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t b = cptr[j], e = cptr[j + 1];
+  for (int64_t p = b + 1; p < e; ++p) {
+    const int key = ci[p];
+    const double val = cv[p];
+    int64_t q = p - 1;
+    while (q >= b && ci[q] > key) {
+      ci[q + 1] = ci[q];
+      cv[q + 1] = cv[q];
+      --q;
+    }
+    ci[q + 1] = key;
+    cv[q + 1] = val;
+  }
+}
+
+// ---------------------------------------------------------------- B products
+// One wave per point of a level, one lane per column (64-column passes).
+// Forward solve B x = y in place: x_i = y_i + sum_s A_i[s] x_{N(i)[s]}.
+__global__ __launch_bounds__(256) void k_vtri_fwd(const int* __restrict__ pts, int cnt, const int* __restrict__ nbr,
+                                                  const double* __restrict__ coef, int mv, double* X, int64_t ld,
+                                                  int ncols) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= cnt) return;
+  const int64_t i = pts[w];
+  for (int c = lane; c < ncols; c += 64) {
+    double acc = X[i * ld + c];
+    for (int s = 0; s < mv; ++s) {
+      const int j = nbr[i * mv + s];
+      if (j < 0) break;
+      acc += coef[i * mv + s] * X[(int64_t)j * ld + c];
+    }
+    X[i * ld + c] = acc;
+  }
+}
+
+// Backward solve B^T z = y in place: z_j = y_j + sum over children i of j of
+// A_i[s] z_i (children have higher levels).
+__global__ __launch_bounds__(256) void k_vtri_bwd(const int* __restrict__ pts, int cnt, const int64_t* __restrict__ cptr,
+                                                  const int* __restrict__ ci, const double* __restrict__ cv, double* X,
+                                                  int64_t ld, int ncols) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= cnt) return;
+  const int64_t j = pts[w];
+  const int64_t b = cptr[j], e = cptr[j + 1];
+  for (int c = lane; c < ncols; c += 64) {
+    double acc = X[j * ld + c];
+    for (int64_t p = b; p < e; ++p) acc += cv[p] * X[(int64_t)ci[p] * ld + c];
+    X[j * ld + c] = acc;
+  }
+}
+
+// T = (B X) / D: t_i = (x_i - sum_s A_i[s] x_{N(i)[s]}) / D_i
+__global__ __launch_bounds__(256) void k_vB_div(int64_t n, const int* __restrict__ nbr, const double* __restrict__ coef,
+                                                int mv, const double* __restrict__ Dv, const double* __restrict__ X,
+                                                int64_t ldx, int ncols, double* __restrict__ T, int64_t ldt) {
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  for (int c = lane; c < ncols; c += 64) {
+    double acc = X[i * ldx + c];
+    for (int s = 0; s < mv; ++s) {
+      const int j = nbr[i * mv + s];
+      if (j < 0) break;
+      acc -= coef[i * mv + s] * X[(int64_t)j * ldx + c];
+    }
+    T[i * ldt + c] = acc / Dv[i];
+  }
+}
+
+// Y = B^T T: y_j = t_j - sum over children i of A_i[s] t_i
+__global__ __launch_bounds__(256) void k_vBt(int64_t n, const int64_t* __restrict__ cptr, const int* __restrict__ ci,
+                                             const double* __restrict__ cv, const double* __restrict__ T, int64_t ldt,
+                                             int ncols, double* __restrict__ Y, int64_t ldy) {
+  const int64_t j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= n) return;
+  const int64_t b = cptr[j], e = cptr[j + 1];
+  for (int c = lane; c < ncols; c += 64) {
+    double acc = T[j * ldt + c];
+    for (int64_t p = b; p < e; ++p) acc -= cv[p] * T[(int64_t)ci[p] * ldt + c];
+    Y[j * ldy + c] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- elementwise
+__global__ void k_vcopy(int64_t n, int ncols, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
+                        int64_t ldy) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t p = e / ncols;
+  const int c = (int)(e - p * ncols);
+  Y[p * ldy + c] = X[p * ldx + c];
+}
+
+// Y = Y * D (rows), or Y += X / w with addw
+__global__ void k_vscale_rows(int64_t n, int ncols, double* __restrict__ Y, int64_t ldy, const double* __restrict__ D) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t p = e / ncols;
+  const int c = (int)(e - p * ncols);
+  Y[p * ldy + c] *= D[p];
+}
+
+__global__ void k_vadd_winv(int64_t n, int ncols, const double* __restrict__ X, int64_t ldx,
+                            const double* __restrict__ w, double* __restrict__ Y, int64_t ldy) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t p = e / ncols;
+  const int c = (int)(e - p * ncols);
+  Y[p * ldy + c] += X[p * ldx + c] / w[p];
+}
+
+// D_s = sigma1^2 - |A_p|^2 + 1 / w_p (the FITC diagonal of Sigma + W^{-1})
+__global__ void k_vds(const double* __restrict__ A, int64_t n, int mp, double s1, const double* __restrict__ w,
+                      double* __restrict__ Ds) {
+  const int64_t p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= n) return;
+  double a = 0.0;
+  for (int k = lane; k < mp; k += 64) {
+    const double v = A[p * mp + k];
+    a += v * v;
+  }
+  a = wave_sum(a);
+  if (lane == 0) Ds[p] = s1 - a + 1.0 / w[p];
+}
+
+// Z = (R - T) / D_s
+__global__ void k_vprec_finish(int64_t n, int ncols, int64_t ld, const double* __restrict__ R,
+                               const double* __restrict__ T, const double* __restrict__ Ds, double* __restrict__ Z) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t p = e / ncols;
+  const int c = (int)(e - p * ncols);
+  Z[p * ld + c] = (R[p * ld + c] - T[p * ld + c]) / Ds[p];
+}
+
+// sum of log x (count of entries not finite or <= 0 in bad), partials per block
+__global__ __launch_bounds__(256) void k_vsumlog_part(const double* __restrict__ x, int64_t n, double* part,
+                                                      int* bad) {
+  __shared__ double s[256];
+  double a = 0.0;
+  int nb = 0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = x[i];
+    if (!(v > 0.0) || !isfinite(v)) ++nb;
+    else a += log(v);
+  }
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+  if (nb) atomicAdd(bad, nb);
+}
+
+__global__ void k_vsum_fixed(const double* __restrict__ part, int np, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0;
+  for (int i = 0; i < np; ++i) a += part[i];
+  *out = a;
+}
+
+__global__ void k_viota(int* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int)i;
+}
+
+// ---------------------------------------------------------------- PCG
+// One thread per column.  rz = r^T z, bn2 = |b|^2, active iff |b| > 0.
+__global__ void k_vpcg_init(int ncols, const double* __restrict__ rz0, const double* __restrict__ bn2, double* rz,
+                            int* active, int* iters, int* flags) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) {
+    flags[0] = 0;
+    flags[1] = 0;
+  }
+  if (c >= ncols) return;
+  rz[c] = rz0[c];
+  active[c] = bn2[c] > 0.0 ? 1 : 0;
+  iters[c] = 0;
+}
+
+// alpha = r^T z / h^T K h on active columns (0 elsewhere); a breakdown
+// (h^T K h not positive or not finite) sets flags[1]
+__global__ void k_vpcg_alpha(int ncols, const double* __restrict__ hv, const double* __restrict__ rz,
+                             const int* __restrict__ active, double* alpha, int* flags) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  double a = 0.0;
+  if (active[c]) {
+    const double h = hv[c];
+    if (!(h > 0.0) || !isfinite(h)) atomicOr(&flags[1], 1);
+    else a = rz[c] / h;
+  }
+  alpha[c] = a;
+}
+
+// u += alpha h, r -= alpha v (alpha = 0 leaves frozen columns as they are)
+__global__ void k_vpcg_update(int64_t n, int ncols, int64_t ld, const double* __restrict__ alpha,
+                              const double* __restrict__ H, const double* __restrict__ V, double* __restrict__ U,
+                              double* __restrict__ R) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t p = e / ncols;
+  const int c = (int)(e - p * ncols);
+  const double a = alpha[c];
+  if (a == 0.0) return;
+  const int64_t o = p * ld + c;
+  U[o] += a * H[o];
+  R[o] -= a * V[o];
+}
+
+// beta = r'^T z' / r^T z on active columns; the iteration's (alpha, beta)
+// appended to the Lanczos history; a column stays active while |r|^2 >=
+// tol^2 |b|^2; flags[0] counts the active columns after the iteration
+__global__ void k_vpcg_beta(int ncols, const double* __restrict__ rzn, const double* __restrict__ rr,
+                            const double* __restrict__ bn2, const double* __restrict__ alpha, double* rz, double* beta,
+                            int* active, int* iters, double* ah, double* bh, int max_iter, double tol2, int* flags) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  double b = 0.0;
+  if (active[c]) {
+    b = rzn[c] / rz[c];
+    const int it = iters[c];
+    if (it < max_iter) {
+      ah[(int64_t)it * ncols + c] = alpha[c];
+      bh[(int64_t)it * ncols + c] = b;
+    }
+    iters[c] = it + 1;
+    rz[c] = rzn[c];
+    if (!isfinite(rzn[c])) atomicOr(&flags[1], 1);
+    const int still = rr[c] < tol2 * bn2[c] ? 0 : 1;
+    active[c] = still;
+    if (still) atomicAdd(&flags[0], 1);
+  }
+  beta[c] = b;
+}
+
+// h = z + beta h on the columns of this iteration (beta = 0 elsewhere
+// leaves h = z, which no later step reads)
+__global__ void k_vpcg_direction(int64_t n, int ncols, int64_t ld, const double* __restrict__ beta,
+                                 const double* __restrict__ Z, double* __restrict__ H) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t p = e / ncols;
+  const int c = (int)(e - p * ncols);
+  const int64_t o = p * ld + c;
+  H[o] = Z[o] + beta[c] * H[o];
+}
+
+// x = u_0 / w
+__global__ void k_vsolution(int64_t n, const double* __restrict__ U, int64_t ld, const double* __restrict__ w,
+                            double* __restrict__ x) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p < n) x[p] = U[p * ld] / w[p];
+}
+
+// log det(Sigma_V^{-1} + W) = offset + log det P + mean of the SLQ terms
+__global__ void k_vlogdet(const double* __restrict__ terms, int c_first, int ncols, const double* __restrict__ parts,
+                          double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0;
+  for (int c = c_first; c < ncols; ++c) a += terms[c];
+  const double sw = a / (double)(ncols - c_first) + parts[0];
+  out[0] = parts[1] + sw;
+  out[1] = sw;
+}
+
+inline unsigned grid1(int64_t cnt, int tpb = 256) { return (unsigned)ceil_div(cnt > 0 ? cnt : 1, tpb); }
+
+}  // namespace
+}  // namespace fsa
+
+using namespace fsa;
+
+struct fsa_vecchia {
+  hipStream_t st = nullptr;
+  int64_t n = 0;
+  int m = 0, mp = 0, mv = 0;
+  Theta th{};
+  Buf<double> xs, ind, w;
+  Buf<int> nbr, level, order, perm, info;
+  Buf<double> coef, Dv;
+  Buf<int64_t> cptr, scan_scratch;
+  Buf<int> ci;
+  Buf<double> cv;
+  std::vector<int> lptr;  // level l holds order[lptr[l] .. lptr[l+1])
+  // FITC preconditioner of Sigma + W^{-1}
+  Buf<double> Sm, Lm, A, Ds, C, LCinv, Cinv, parts;  // parts: [0] log det P, [1] sum log w - sum log D
+  BlasHandle blas;
+  Scratch scr;
+  double logdet_P = 0.0, offset = 0.0;
+  ~fsa_vecchia() {
+    if (st) (void)hipStreamSynchronize(st);
+    blas_release(blas);
+  }
+};
+
+namespace {
+
+fsa_status sum_log(const double* x, int64_t n, double* out_dev, int* bad_dev, hipStream_t st, Buf<double>& part) {
+  const int nb = (int)std::min<int64_t>(grid1(n), 256);
+  FSA_TRY(part.alloc(nb));
+  hipLaunchKernelGGL(k_vsumlog_part, dim3(nb), dim3(256), 0, st, x, n, part.p, bad_dev);
+  hipLaunchKernelGGL(k_vsum_fixed, dim3(1), dim3(64), 0, st, part.p, nb, out_dev);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// Y = Sigma_V X = B^{-1} (D (B^{-T} X))
+fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, double* Y, int64_t ldy) {
+  hipStream_t st = v->st;
+  const int64_t n = v->n;
+  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, X, ldx, Y, ldy);
+  const int nlev = (int)v->lptr.size() - 1;
+  for (int l = nlev - 1; l >= 0; --l) {
+    const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
+    hipLaunchKernelGGL(k_vtri_bwd, dim3(grid1(cnt, 4)), dim3(256), 0, st, v->order.p + b, cnt, v->cptr.p, v->ci.p,
+                       v->cv.p, Y, ldy, ncols);
+  }
+  hipLaunchKernelGGL(k_vscale_rows, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Y, ldy, v->Dv.p);
+  for (int l = 0; l < nlev; ++l) {
+    const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
+    hipLaunchKernelGGL(k_vtri_fwd, dim3(grid1(cnt, 4)), dim3(256), 0, st, v->order.p + b, cnt, v->nbr.p, v->coef.p,
+                       v->mv, Y, ldy, ncols);
+  }
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// Y = Sigma_V^{-1} X = B^T D^{-1} B X (T: n x ncols scratch)
+fsa_status precision_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, double* Y, int64_t ldy) {
+  hipStream_t st = v->st;
+  const int64_t n = v->n;
+  Buf<double> T;
+  FSA_TRY(T.alloc((size_t)n * ncols));
+  hipLaunchKernelGGL(k_vB_div, dim3(grid1(n, 4)), dim3(256), 0, st, n, v->nbr.p, v->coef.p, v->mv, v->Dv.p, X, ldx,
+                     ncols, T.p, (int64_t)ncols);
+  hipLaunchKernelGGL(k_vBt, dim3(grid1(n, 4)), dim3(256), 0, st, n, v->cptr.p, v->ci.p, v->cv.p, T.p,
+                     (int64_t)ncols, ncols, Y, ldy);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// Z = P^{-1} R by Woodbury: (R - A C^{-1} A^T D_s^{-1} R) / D_s; T, Wm, G scratch
+fsa_status precond(fsa_vecchia* v, const double* R, int64_t ld, int ncols, double* Z, double* T, double* Wm,
+                   double* G, int ldw) {
+  hipStream_t st = v->st;
+  FSA_TRY(lowrank_reduce<double>(v->A.p, v->n, v->mp, R, (int)ld, ncols, v->Ds.p, v->scr, Wm, ldw, st));
+  FSA_TRY(mspace_apply<double>(v->Cinv.p, Wm, ldw, v->mp, ncols, G, ldw, st));
+  FSA_TRY(lowrank_expand<double>(v->A.p, nullptr, v->n, v->mp, G, ldw, ncols, T, (int)ld, st));
+  hipLaunchKernelGGL(k_vprec_finish, dim3(grid1(v->n * ncols)), dim3(256), 0, st, v->n, ncols, ld, R, T, v->Ds.p, Z);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// Y = (Sigma_V + W^{-1}) X
+fsa_status operator_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, double* Y, int64_t ldy) {
+  FSA_TRY(sigma_v(v, X, ldx, ncols, Y, ldy));
+  hipLaunchKernelGGL(k_vadd_winv, dim3(grid1(v->n * ncols)), dim3(256), 0, v->st, v->n, ncols, X, ldx, v->w.p, Y, ldy);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, const double* w) {
+  hipStream_t st = v->st;
+  const int64_t n = v->n;
+  const int mv = v->mv, mp = v->mp;
+  FSA_TRY(v->info.alloc(4));
+  FSA_HIP(hipMemsetAsync(v->info.p, 0, 4 * sizeof(int), st));
+  FSA_TRY(v->xs.alloc(2 * (size_t)n));
+  FSA_TRY(v->w.alloc(n));
+  FSA_TRY(v->ind.alloc(2 * (size_t)mp));
+  FSA_HIP(hipMemcpyAsync(v->xs.p, locs, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  FSA_HIP(hipMemcpyAsync(v->w.p, w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  FSA_HIP(hipMemsetAsync(v->ind.p, 0, 2 * (size_t)mp * sizeof(double), st));
+  FSA_HIP(hipMemcpyAsync(v->ind.p, inducing, 2 * (size_t)v->m * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // sum log w (also rejects w not finite and positive)
+  FSA_TRY(v->parts.alloc(4));
+  Buf<double> part;
+  FSA_TRY(sum_log(v->w.p, n, v->parts.p + 2, v->info.p + 1, st, part));
+  // neighbours, factor
+  FSA_TRY(v->nbr.alloc((size_t)n * std::max(mv, 1)));
+  FSA_TRY(v->coef.alloc((size_t)n * std::max(mv, 1)));
+  FSA_TRY(v->Dv.alloc(n));
+  if (mv > 0) {
+    hipLaunchKernelGGL(k_vknn, dim3(grid1(n, KNN_TPB)), dim3(KNN_TPB), 0, st, v->xs.p, n, mv, v->nbr.p);
+  }
+  hipLaunchKernelGGL(k_vfactor, dim3((unsigned)n), dim3(64), 0, st, v->xs.p, n, mv, v->nbr.p, v->th, v->coef.p,
+                     v->Dv.p, v->info.p);
+  FSA_HIP(hipGetLastError());
+  int hinfo[2] = {0, 0};
+  FSA_HIP(hipMemcpyAsync(hinfo, v->info.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (hinfo[1]) {
+    set_error("%d weights W are not finite and positive", hinfo[1]);
+    return FSA_ERR_INVALID_ARG;
+  }
+  if (hinfo[0]) {
+    set_error("Vecchia factor: %d points have a conditioning matrix that is not positive definite "
+              "(duplicate locations?)", hinfo[0]);
+    return FSA_ERR_NOT_SPD;
+  }
+  // level schedule: relax until a batch of sweeps changes nothing
+  FSA_TRY(v->level.alloc(n));
+  FSA_HIP(hipMemsetAsync(v->level.p, 0, n * sizeof(int), st));
+  {
+    const int batch = 16;
+    int64_t sweeps = 0;
+    for (;;) {
+      FSA_HIP(hipMemsetAsync(v->info.p + 2, 0, sizeof(int), st));
+      for (int b = 0; b < batch; ++b)
+        hipLaunchKernelGGL(k_vlevel, dim3(grid1(n)), dim3(256), 0, st, v->nbr.p, n, mv, v->level.p, v->info.p + 2);
+      FSA_HIP(hipGetLastError());
+      int changed = 0;
+      FSA_HIP(hipMemcpyAsync(&changed, v->info.p + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+      FSA_HIP(hipStreamSynchronize(st));
+      sweeps += batch;
+      if (!changed) break;
+      if (sweeps > n + 2 * batch) {
+        set_error("Vecchia level schedule did not settle");
+        return FSA_ERR_DEVICE;
+      }
+    }
+  }
+  int maxlev = 0;
+  FSA_HIP(hipMemsetAsync(v->info.p + 3, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_vmaxlevel, dim3(grid1(n)), dim3(256), 0, st, v->level.p, n, v->info.p + 3);
+  FSA_HIP(hipMemcpyAsync(&maxlev, v->info.p + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  const int nlev = maxlev + 1;
+  {
+    Buf<int> cnt, cur, lp;
+    FSA_TRY(cnt.alloc(nlev));
+    FSA_TRY(cur.alloc(nlev));
+    FSA_TRY(lp.alloc(nlev + 1));
+    FSA_HIP(hipMemsetAsync(cnt.p, 0, nlev * sizeof(int), st));
+    FSA_HIP(hipMemsetAsync(cur.p, 0, nlev * sizeof(int), st));
+    hipLaunchKernelGGL(k_vlevel_hist, dim3(grid1(n)), dim3(256), 0, st, v->level.p, n, cnt.p, v->info.p + 3);
+    std::vector<int> hc(nlev);
+    FSA_HIP(hipMemcpyAsync(hc.data(), cnt.p, nlev * sizeof(int), hipMemcpyDeviceToHost, st));
+    FSA_HIP(hipStreamSynchronize(st));
+    v->lptr.assign(nlev + 1, 0);
+    for (int l = 0; l < nlev; ++l) v->lptr[l + 1] = v->lptr[l] + hc[l];
+    if (v->lptr[nlev] != n) {
+      set_error("Vecchia level schedule: %d points counted of %lld", v->lptr[nlev], (long long)n);
+      return FSA_ERR_DEVICE;
+    }
+    FSA_HIP(hipMemcpyAsync(lp.p, v->lptr.data(), (nlev + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    FSA_TRY(v->order.alloc(n));
+    hipLaunchKernelGGL(k_vlevel_scatter, dim3(grid1(n)), dim3(256), 0, st, v->level.p, n, lp.p, cur.p, v->order.p);
+    FSA_HIP(hipGetLastError());
+    FSA_HIP(hipStreamSynchronize(st));  // lp, cnt and cur leave scope
+  }
+  // children lists (rows of B^T)
+  {
+    Buf<int> ccnt, cur;
+    FSA_TRY(ccnt.alloc(n));
+    FSA_TRY(cur.alloc(n));
+    FSA_TRY(v->cptr.alloc(n + 1));
+    FSA_HIP(hipMemsetAsync(ccnt.p, 0, n * sizeof(int), st));
+    FSA_HIP(hipMemsetAsync(cur.p, 0, n * sizeof(int), st));
+    if (mv > 0)
+      hipLaunchKernelGGL(k_vchild_count, dim3(grid1(n * mv)), dim3(256), 0, st, v->nbr.p, n, mv, ccnt.p);
+    FSA_TRY(scan_counts(ccnt.p, n, v->cptr.p, v->scan_scratch, st));
+    int64_t nnz = 0;
+    FSA_HIP(hipMemcpyAsync(&nnz, v->cptr.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    FSA_HIP(hipStreamSynchronize(st));
+    FSA_TRY(v->ci.alloc(std::max<int64_t>(nnz, 1)));
+    FSA_TRY(v->cv.alloc(std::max<int64_t>(nnz, 1)));
+    if (mv > 0) {
+      hipLaunchKernelGGL(k_vchild_fill, dim3(grid1(n * mv)), dim3(256), 0, st, v->nbr.p, v->coef.p, n, mv, v->cptr.p,
+                         cur.p, v->ci.p, v->cv.p);
+      hipLaunchKernelGGL(k_vchild_sort, dim3(grid1(n)), dim3(256), 0, st, v->cptr.p, n, v->ci.p, v->cv.p);
+    }
+    FSA_HIP(hipGetLastError());
+    FSA_HIP(hipStreamSynchronize(st));
+  }
+  // FITC preconditioner of Sigma + W^{-1}: A = L_m^{-1} Sigma_mn, D_s, C = I + A D_s^{-1} A^T
+  FSA_TRY(v->Sm.alloc((size_t)mp * mp));
+  FSA_TRY(v->Lm.alloc((size_t)mp * mp));
+  FSA_TRY(dense_sigma_m(v->ind.p, v->m, mp, v->th, 0.0, false, v->Sm.p, st));
+  FSA_HIP(hipMemcpyAsync(v->Lm.p, v->Sm.p, (size_t)mp * mp * sizeof(double), hipMemcpyDeviceToDevice, st));
+  FSA_TRY(dense_cholesky(v->Lm.p, mp, v->info.p, st));
+  FSA_HIP(hipMemcpyAsync(hinfo, v->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (hinfo[0]) {
+    set_error("Cholesky of Sigma_m failed at column %d (duplicate inducing points?)", hinfo[0] - 1);
+    return FSA_ERR_NOT_SPD;
+  }
+  FSA_TRY(blas_acquire(v->blas));
+  FSA_TRY(v->A.alloc((size_t)n * mp));
+  FSA_TRY(whiten(v->blas, v->xs.p, n, v->ind.p, v->m, mp, v->th, v->Lm.p, v->A.p, st));
+  FSA_TRY(v->Ds.alloc(n));
+  hipLaunchKernelGGL(k_vds, dim3(grid1(n, 4)), dim3(256), 0, st, v->A.p, n, mp, v->th.s1, v->w.p, v->Ds.p);
+  FSA_TRY(v->C.alloc((size_t)mp * mp));
+  FSA_TRY(capacitance(v->A.p, v->Ds.p, n, mp, v->C.p, v->scr, st));
+  FSA_TRY(dense_cholesky(v->C.p, mp, v->info.p, st));
+  FSA_TRY(dense_logdet_chol(v->C.p, mp, v->parts.p, st));
+  FSA_TRY(v->LCinv.alloc((size_t)mp * mp));
+  FSA_TRY(v->Cinv.alloc((size_t)mp * mp));
+  FSA_TRY(blas_tri_inverse(v->blas, st, v->C.p, v->LCinv.p, mp));
+  FSA_TRY(dense_gemm(v->LCinv.p, true, v->LCinv.p, false, v->Cinv.p, mp, 1.0, st));
+  // sums of logs: [1] log D_s, [3] log D (Vecchia)
+  FSA_TRY(sum_log(v->Ds.p, n, v->parts.p + 1, v->info.p + 1, st, part));
+  Buf<double> part2;
+  FSA_TRY(sum_log(v->Dv.p, n, v->parts.p + 3, v->info.p + 1, st, part2));
+  double hp[4];
+  FSA_HIP(hipMemcpyAsync(hp, v->parts.p, sizeof(hp), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipMemcpyAsync(hinfo, v->info.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (hinfo[0]) {
+    set_error("Cholesky of the FITC capacitance failed at column %d", hinfo[0] - 1);
+    return FSA_ERR_NOT_SPD;
+  }
+  if (hinfo[1]) {
+    set_error("FITC diagonal D_s has a non-positive or non-finite entry");
+    return FSA_ERR_NOT_SPD;
+  }
+  v->logdet_P = hp[0] + hp[1];
+  v->offset = hp[2] - hp[3];
+  // parts[0] = log det P, parts[1] = sum log w - sum log D (read by k_vlogdet)
+  const double hp2[2] = {v->logdet_P, v->offset};
+  FSA_HIP(hipMemcpyAsync(v->parts.p, hp2, sizeof(hp2), hipMemcpyHostToDevice, st));
+  FSA_TRY(v->perm.alloc(n));
+  hipLaunchKernelGGL(k_viota, dim3(grid1(n)), dim3(256), 0, st, v->perm.p, n);
+  FSA_HIP(hipGetLastError());
+  FSA_HIP(hipStreamSynchronize(st));
+  return FSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fsa_status fsa_vecchia_build_dev(const double* locs, int64_t n, const double* inducing, int32_t m, int32_t kind,
+                                 double sigma1_sq, double rho, int32_t mv, const double* w, void* hip_stream,
+                                 fsa_vecchia** out) {
+  if (!out) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (!locs || !inducing || !w) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (n < 1 || n > (int64_t)INT32_MAX) { set_error("n must be in [1, 2^31)"); return FSA_ERR_INVALID_ARG; }
+  if (m < 1 || m > 512) { set_error("m must be in [1, 512]"); return FSA_ERR_INVALID_ARG; }
+  if (mv < 0 || mv > VMV_MAX) { set_error("m_v must be in [0, %d]", VMV_MAX); return FSA_ERR_INVALID_ARG; }
+  if (kind != FSA_COV_EXPONENTIAL && kind != FSA_COV_MATERN32) { set_error("unknown covariance"); return FSA_ERR_INVALID_ARG; }
+  if (!(sigma1_sq > 0.0) || !(rho > 0.0) || !std::isfinite(sigma1_sq) || !std::isfinite(rho)) {
+    set_error("sigma1^2 and rho must be finite and positive");
+    return FSA_ERR_INVALID_ARG;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  PoolStream ps(st);
+  fsa_vecchia* v = new (std::nothrow) fsa_vecchia();
+  if (!v) { set_error("out of host memory"); return FSA_ERR_OOM; }
+  v->st = st;
+  v->n = n;
+  v->m = m;
+  v->mp = (int)round_up(m, 64);
+  v->mv = mv;
+  v->th = Theta{kind, sigma1_sq, rho, 0.0};
+  fsa_status s = build(v, locs, inducing, w);
+  if (s != FSA_OK) {
+    delete v;
+    return s;
+  }
+  *out = v;
+  return FSA_OK;
+}
+
+fsa_status fsa_vecchia_factor_dev(fsa_vecchia* v, int32_t* nbr, double* coef, double* d) {
+  if (!v || !nbr || !coef || !d) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(v->st);
+  const size_t cnt = (size_t)v->n * v->mv;
+  if (cnt) {
+    FSA_HIP(hipMemcpyAsync(nbr, v->nbr.p, cnt * sizeof(int), hipMemcpyDeviceToDevice, v->st));
+    FSA_HIP(hipMemcpyAsync(coef, v->coef.p, cnt * sizeof(double), hipMemcpyDeviceToDevice, v->st));
+  }
+  FSA_HIP(hipMemcpyAsync(d, v->Dv.p, v->n * sizeof(double), hipMemcpyDeviceToDevice, v->st));
+  FSA_HIP(hipStreamSynchronize(v->st));
+  return FSA_OK;
+}
+
+fsa_status fsa_vecchia_apply_dev(fsa_vecchia* v, int32_t which, const double* X, int64_t ldx, int32_t ncols,
+                                 double* Y, int64_t ldy) {
+  if (!v || !X || !Y) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (ncols < 1 || ldx < ncols || ldy < ncols) { set_error("need 1 <= ncols <= ldx, ldy"); return FSA_ERR_INVALID_ARG; }
+  if (X == Y) { set_error("X and Y must not alias"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(v->st);
+  switch (which) {
+    case FSA_V_SIGMA:
+      FSA_TRY(sigma_v(v, X, ldx, ncols, Y, ldy));
+      break;
+    case FSA_V_PRECISION:
+      FSA_TRY(precision_v(v, X, ldx, ncols, Y, ldy));
+      break;
+    case FSA_V_OPERATOR:
+      FSA_TRY(operator_v(v, X, ldx, ncols, Y, ldy));
+      break;
+    case FSA_V_P_INV: {
+      const int ld = (int)round_up(ncols, 4), ldw = (int)round_up(ncols, 64);
+      Buf<double> R, Z, T, Wm, G;
+      FSA_TRY(R.alloc((size_t)v->n * ld));
+      FSA_TRY(Z.alloc((size_t)v->n * ld));
+      FSA_TRY(T.alloc((size_t)v->n * ld));
+      FSA_TRY(Wm.alloc((size_t)v->mp * ldw));
+      FSA_TRY(G.alloc((size_t)v->mp * ldw));
+      hipLaunchKernelGGL(k_vcopy, dim3(grid1(v->n * ncols)), dim3(256), 0, v->st, v->n, ncols, X, ldx, R.p,
+                         (int64_t)ld);
+      FSA_TRY(precond(v, R.p, ld, ncols, Z.p, T.p, Wm.p, G.p, ldw));
+      hipLaunchKernelGGL(k_vcopy, dim3(grid1(v->n * ncols)), dim3(256), 0, v->st, v->n, ncols, Z.p, (int64_t)ld, Y,
+                         ldy);
+      FSA_HIP(hipGetLastError());
+      FSA_HIP(hipStreamSynchronize(v->st));
+      break;
+    }
+    default:
+      set_error("unknown operator %d", which);
+      return FSA_ERR_INVALID_ARG;
+  }
+  FSA_HIP(hipStreamSynchronize(v->st));
+  return FSA_OK;
+}
+
+fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, double* x, int32_t num_probes,
+                                        uint64_t seed, double tol, int32_t max_iter, double* logdet,
+                                        fsa_vecchia_stats* stats) {
+  if (!v || !rhs || !x || !logdet) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (num_probes < 1 || num_probes > 1023) { set_error("num_probes must be in [1, 1023]"); return FSA_ERR_INVALID_ARG; }
+  if (!(tol > 0.0) || !std::isfinite(tol)) { set_error("tol must be finite and positive"); return FSA_ERR_INVALID_ARG; }
+  if (max_iter < 1 || max_iter > 6000) { set_error("max_iter must be in [1, 6000]"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(v->st);
+  hipStream_t st = v->st;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = v->n;
+  const int ncols = num_probes + 1;
+  const int64_t ld = round_up(ncols, 64);
+  const int ldw = (int)round_up(ncols, 64);
+  const size_t blk = (size_t)n * ld;
+  Buf<double> mem, Wm, G, Emat, col, hist;
+  Buf<int> ivec;
+  FSA_TRY(mem.alloc(8 * blk));
+  double* Bk = mem.p;
+  double* R = mem.p + blk;
+  double* H = mem.p + 2 * blk;
+  double* V = mem.p + 3 * blk;
+  double* Z = mem.p + 4 * blk;
+  double* U = mem.p + 5 * blk;
+  double* Q0 = mem.p + 6 * blk;
+  double* T = mem.p + 7 * blk;
+  FSA_TRY(Wm.alloc((size_t)v->mp * ldw));
+  FSA_TRY(G.alloc((size_t)v->mp * ldw));
+  FSA_TRY(Emat.alloc((size_t)v->mp * ldw));
+  // per column: [0] rz [1] bn2 [2] hv [3] alpha [4] beta [5] rzn [6] rr [7] weight [8] slq terms, then 2 results
+  FSA_TRY(col.alloc(9 * (size_t)ncols + 2));
+  double* c_rz = col.p;
+  double* c_bn2 = col.p + ncols;
+  double* c_hv = col.p + 2 * ncols;
+  double* c_alpha = col.p + 3 * ncols;
+  double* c_beta = col.p + 4 * ncols;
+  double* c_rzn = col.p + 5 * ncols;
+  double* c_rr = col.p + 6 * ncols;
+  double* c_w = col.p + 7 * ncols;
+  double* c_slq = col.p + 8 * ncols;
+  double* res = col.p + 9 * ncols;
+  FSA_TRY(hist.alloc(2 * (size_t)max_iter * ncols));
+  double* ah = hist.p;
+  double* bh = hist.p + (size_t)max_iter * ncols;
+  FSA_TRY(ivec.alloc(2 * (size_t)ncols + 2));
+  int* active = ivec.p;
+  int* iters = ivec.p + ncols;
+  int* flags = ivec.p + 2 * ncols;
+  FSA_HIP(hipMemsetAsync(mem.p, 0, 8 * blk * sizeof(double), st));
+  FSA_HIP(hipMemsetAsync(hist.p, 0, hist.bytes(), st));
+  // right-hand sides [Sigma_V v, z_1 .. z_t], z ~ (0, P) (App. F sampling recipe)
+  FSA_TRY(sigma_v(v, rhs, 1, 1, T, ld));
+  {
+    Buf<double> y;
+    FSA_TRY(y.alloc(n));
+    FSA_HIP(hipMemcpy2DAsync(y.p, sizeof(double), T, ld * sizeof(double), sizeof(double), n,
+                             hipMemcpyDeviceToDevice, st));
+    FSA_HIP(hipMemsetAsync(T, 0, blk * sizeof(double), st));
+    FSA_TRY(make_probes(v->A.p, n, v->m, v->mp, v->Ds.p, y.p, v->perm.p, seed, num_probes, Bk, (int)ld, Emat.p, st));
+    FSA_HIP(hipStreamSynchronize(st));  // y leaves scope
+  }
+  // init: R = B, Z = P^{-1} R, H = Q0 = Z
+  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Bk, ld, R, ld);
+  FSA_TRY(precond(v, R, ld, ncols, Z, T, Wm.p, G.p, ldw));
+  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Z, ld, H, ld);
+  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Z, ld, Q0, ld);
+  FSA_TRY((coldot<double, double>(R, Z, n, (int)ld, ncols, c_rzn, v->scr, st)));
+  FSA_TRY((coldot<double, double>(Bk, Bk, n, (int)ld, ncols, c_bn2, v->scr, st)));
+  FSA_TRY((coldot<double, double>(Bk, Q0, n, (int)ld, ncols, c_w, v->scr, st)));
+  hipLaunchKernelGGL(k_vpcg_init, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_rzn, c_bn2, c_rz, active, iters, flags);
+  FSA_HIP(hipGetLastError());
+  const double tol2 = tol * tol;
+  int hflags[2] = {0, 0};
+  int it = 0;
+  bool converged = false;
+  for (; it < max_iter; ++it) {
+    FSA_TRY(operator_v(v, H, ld, ncols, V, ld));
+    FSA_TRY((coldot<double, double>(H, V, n, (int)ld, ncols, c_hv, v->scr, st)));
+    hipLaunchKernelGGL(k_vpcg_alpha, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_hv, c_rz, active, c_alpha, flags);
+    hipLaunchKernelGGL(k_vpcg_update, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, ld, c_alpha, H, V, U, R);
+    FSA_TRY(precond(v, R, ld, ncols, Z, T, Wm.p, G.p, ldw));
+    FSA_TRY((coldot<double, double>(R, Z, n, (int)ld, ncols, c_rzn, v->scr, st)));
+    FSA_TRY((coldot<double, double>(R, R, n, (int)ld, ncols, c_rr, v->scr, st)));
+    FSA_HIP(hipMemsetAsync(flags, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_vpcg_beta, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_rzn, c_rr, c_bn2, c_alpha, c_rz,
+                       c_beta, active, iters, ah, bh, max_iter, tol2, flags);
+    hipLaunchKernelGGL(k_vpcg_direction, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, ld, c_beta, Z, H);
+    FSA_HIP(hipGetLastError());
+    FSA_HIP(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    FSA_HIP(hipStreamSynchronize(st));
+    if (hflags[1]) {
+      set_error("CG breakdown in the Vecchia solve (h^T K h <= 0 or non-finite)");
+      return FSA_ERR_BREAKDOWN;
+    }
+    if (hflags[0] == 0) {
+      converged = true;
+      ++it;
+      break;
+    }
+  }
+  // solution and log det
+  hipLaunchKernelGGL(k_vsolution, dim3(grid1(n)), dim3(256), 0, st, n, U, ld, v->w.p, x);
+  FSA_TRY(slq_terms(ah, bh, iters, ncols, 1, c_w, c_slq, nullptr, max_iter, st));
+  hipLaunchKernelGGL(k_vlogdet, dim3(1), dim3(64), 0, st, c_slq, 1, ncols, v->parts.p, res);
+  FSA_HIP(hipGetLastError());
+  double hres[2];
+  std::vector<int> hit(ncols);
+  FSA_HIP(hipMemcpyAsync(hres, res, sizeof(hres), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipMemcpyAsync(hit.data(), iters, ncols * sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  *logdet = hres[0];
+  if (stats) {
+    *stats = fsa_vecchia_stats{};
+    stats->nlevels = (int32_t)v->lptr.size() - 1;
+    stats->iters_rhs = hit[0];
+    stats->iters_max = *std::max_element(hit.begin(), hit.end());
+    stats->converged = converged ? 1 : 0;
+    stats->logdet_P = v->logdet_P;
+    stats->logdet_offset = v->offset;
+    stats->logdet_sw = hres[1];
+    stats->ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (!converged) {
+    set_error("Vecchia solve: max_iter (%d) reached", max_iter);
+    return FSA_ERR_NOT_CONVERGED;
+  }
+  return FSA_OK;
+}
+
+fsa_status fsa_vecchia_destroy(fsa_vecchia* v) {
+  if (!v) return FSA_OK;
+  PoolStream ps(v->st);
+  delete v;
+  return FSA_OK;
+}
+
+}  // extern "C"

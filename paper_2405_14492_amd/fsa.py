@@ -24,6 +24,7 @@ PROFILE_ALL = 0x1f  # fsa_options.profile: all five kernel classes
 CV_NONE, CV_ONE, CV_OPT, CV_OPT_PRINTED = range(4)  # fsa_options.control_variate
 
 OP_SIGMA_DAGGER, OP_SIGMA_S, OP_P_INV, OP_D_SIGMA1, OP_D_RHO, OP_PROBES = range(6)
+V_SIGMA, V_PRECISION, V_OPERATOR, V_P_INV = range(4)
 
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "NOT_SPD", 4: "NOT_CONVERGED", 5: "BREAKDOWN", 6: "DEVICE"}
 
@@ -32,7 +33,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfsa.so")
 EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad", "fsa_grad", "fsa_predict_var",
             "fsa_destroy",
             "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_export_lanczos", "fsa_apply",
-            "fsa_pool_trim", "fsa_scores"]
+            "fsa_pool_trim", "fsa_scores",
+            "fsa_vecchia_build_dev", "fsa_vecchia_factor_dev", "fsa_vecchia_apply_dev", "fsa_vecchia_solve_logdet_dev",
+            "fsa_vecchia_destroy"]
 
 
 class FsaError(RuntimeError):
@@ -74,6 +77,15 @@ class fsa_stats(C.Structure):
         return d
 
 
+class fsa_vecchia_stats(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("iters_max", C.c_int32), ("iters_rhs", C.c_int32), ("converged", C.c_int32),
+                ("logdet_P", C.c_double), ("logdet_offset", C.c_double), ("logdet_sw", C.c_double),
+                ("ms_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2405_14492_amd.build`")
@@ -112,6 +124,18 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fsa_pool_trim.restype = None
     lib.fsa_scores.argtypes = [dp, dp, dp, C.c_int64, dp]
     lib.fsa_scores.restype = C.c_int
+    lib.fsa_vecchia_build_dev.argtypes = [vp, C.c_int64, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                          vp, vp, P(vp)]
+    lib.fsa_vecchia_build_dev.restype = C.c_int
+    lib.fsa_vecchia_factor_dev.argtypes = [vp, vp, vp, vp]
+    lib.fsa_vecchia_factor_dev.restype = C.c_int
+    lib.fsa_vecchia_apply_dev.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_int32, vp, C.c_int64]
+    lib.fsa_vecchia_apply_dev.restype = C.c_int
+    lib.fsa_vecchia_solve_logdet_dev.argtypes = [vp, vp, vp, C.c_int32, C.c_uint64, C.c_double, C.c_int32, dp,
+                                                 P(fsa_vecchia_stats)]
+    lib.fsa_vecchia_solve_logdet_dev.restype = C.c_int
+    lib.fsa_vecchia_destroy.argtypes = [vp]
+    lib.fsa_vecchia_destroy.restype = C.c_int
     return lib
 
 
@@ -348,3 +372,71 @@ class FSA:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Vecchia:
+    """The FITC preconditioner for a Vecchia approximation (Section 5) on
+    device tensors: build with locations (n x 2), inducing points (m x 2) and
+    weights W (n), all float64 CUDA tensors; then factor(), apply() and
+    solve_logdet().  Argument marshalling only: every step runs in libfsa."""
+
+    def __init__(self, locs, inducing, kind, sigma1_sq, rho, mv, w, stream=None):
+        import torch
+        self._torch = torch
+        self.locs = locs.contiguous()
+        self.n = self.locs.shape[0]
+        self.mv = int(mv)
+        ind = inducing.contiguous()
+        wc = w.contiguous()
+        for t in (self.locs, ind, wc):
+            if t.dtype != torch.float64 or not t.is_cuda:
+                raise TypeError("Vecchia takes float64 device tensors")
+        st = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        _check(lib().fsa_vecchia_build_dev(self.locs.data_ptr(), self.n, ind.data_ptr(), ind.shape[0], int(kind),
+                                           float(sigma1_sq), float(rho), self.mv, wc.data_ptr(), C.c_void_p(st),
+                                           C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().fsa_vecchia_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def factor(self):
+        torch = self._torch
+        mv = max(self.mv, 1)
+        nbr = torch.empty((self.n, mv), dtype=torch.int32, device=self.locs.device)
+        coef = torch.empty((self.n, mv), dtype=torch.float64, device=self.locs.device)
+        d = torch.empty(self.n, dtype=torch.float64, device=self.locs.device)
+        _check(lib().fsa_vecchia_factor_dev(self._h, nbr.data_ptr(), coef.data_ptr(), d.data_ptr()))
+        return nbr[:, :self.mv], coef[:, :self.mv], d
+
+    def apply(self, which, X):
+        X2 = X.contiguous() if X.dim() == 2 else X.reshape(-1, 1).contiguous()
+        Y = self._torch.empty_like(X2)
+        k = X2.shape[1]
+        _check(lib().fsa_vecchia_apply_dev(self._h, int(which), X2.data_ptr(), k, k, Y.data_ptr(), k))
+        return Y if X.dim() == 2 else Y[:, 0]
+
+    def solve_logdet(self, rhs, num_probes, seed, tol=1e-8, max_iter=1000, allow_not_converged=False):
+        r = rhs.contiguous()
+        x = self._torch.empty_like(r)
+        ld = C.c_double()
+        st = fsa_vecchia_stats()
+        _check(lib().fsa_vecchia_solve_logdet_dev(self._h, r.data_ptr(), x.data_ptr(), int(num_probes), int(seed),
+                                                  float(tol), int(max_iter), C.byref(ld), C.byref(st)),
+               allow_not_converged)
+        return x, ld.value, st.as_dict()
