@@ -191,6 +191,42 @@ def roofline(res, n, m, tp, precision):
     return r
 
 
+def run_vecchia(F, torch, n, mv, m, t, steps, warmup, seed=0):
+    """The Vecchia path with the FITC preconditioner (Section 5) at the size
+    of its experiments: n points uniform on the unit square, m_v nearest
+    earlier neighbours, m kmeans++ inducing points, Matern-3/2 with rho =
+    0.05, W uniform on [0.05, 0.25] (a Bernoulli-logit Hessian's range), t
+    probes; a step is one solve + SLQ log det (one block PCG run)."""
+    from workloads import generators as G
+    locs = G.uniform_locations(n, seed + 100)
+    ind = G.kmeanspp_inducing(locs, m, seed + 101)
+    wts = G.laplace_weights(n, seed + 102)
+    rhs = np.random.default_rng(seed + 103).standard_normal(n)
+    d = {k: torch.from_numpy(np.ascontiguousarray(a)).cuda() for k, a in
+         (("locs", locs), ("ind", ind), ("w", wts), ("rhs", rhs))}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v = F.Vecchia(d["locs"], d["ind"], F.MATERN32, 1.0, 0.05, mv, d["w"])
+    torch.cuda.synchronize()
+    ms_build = (time.perf_counter() - t0) * 1e3
+    for i in range(warmup):
+        v.solve_logdet(d["rhs"], t, i, tol=1e-6, max_iter=3000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, lds = 0, []
+    for i in range(steps):
+        _, ld, st = v.solve_logdet(d["rhs"], t, 1000 + i, tol=1e-6, max_iter=3000)
+        its += st["probe_iters"]
+        lds.append(ld)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    v.close()
+    return {"workload": f"vecchia_solve_logdet n={n} m_v={mv} m={m} t={t} matern32 rho=0.05 W~U[0.05,0.25] tol=1e-6",
+            "value": its / sec, "unit": "probe-iters/s", "ms_per_step": sec * 1e3 / steps, "ms_build": ms_build,
+            "probe_iters_per_step": its / steps, "iters_max": st["iters_max"], "nlevels": st["nlevels"],
+            "logdet": lds[-1], "logdet_spread": float(np.std(lds)) if len(lds) > 1 else 0.0, "steps": steps}
+
+
 def cpu_baseline(w, sample_n, iters):
     """The oracle on a spatial window of the same workload (same density,
     taper range, covariance and all m inducing points), `iters` PCG
@@ -239,6 +275,8 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=80_000)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-vecchia", action="store_true", help="skip the Vecchia (Section 5) leg")
+    ap.add_argument("--vecchia-only", action="store_true", help="run only the Vecchia (Section 5) leg")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for hardware-counter scaling)")
     args = ap.parse_args()
@@ -253,6 +291,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     F.lib()
+    if args.vecchia_only:
+        log("vecchia leg")
+        print(json.dumps({"vecchia": run_vecchia(F, torch, 100_000, 30, 200, args.probes, args.steps, args.warmup)}),
+              flush=True)
+        return
     log(f"generating inputs n={args.n} m={args.m} t={args.probes}")
     t0 = time.perf_counter()
     w = configs.large_matern(n=args.n, m=args.m, t=args.probes)
@@ -310,6 +353,11 @@ def main():
         out["bf16a_vs_fp64_rel_nll"] = abs(g["nll"] - f["nll"]) / abs(f["nll"])
         out["bf16a_vs_fp64_rel_grad"] = [abs(a - c) / max(abs(c), 1e-300) for a, c in zip(g["grad"], f["grad"])]
         out["roofline_bf16a"] = roofline(g, args.n, args.m, args.probes + 1, "bf16a")
+    if not args.no_vecchia:
+        log("vecchia leg (Section 5): n=100000 m_v=30 m=200")
+        out["vecchia"] = run_vecchia(F, torch, 100_000, 30, 200, args.probes, args.steps, args.warmup)
+        log(f"vecchia: {out['vecchia']['value']:.1f} probe-iters/s, {out['vecchia']['ms_per_step']:.2f} ms/step, "
+            f"{out['vecchia']['nlevels']} levels")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_n, args.cpu_iters)

@@ -298,6 +298,7 @@ typedef struct {
   int32_t iters_max;    /* largest PCG iteration count over the columns */
   int32_t iters_rhs;    /* PCG iterations of the solve's column */
   int32_t converged;    /* 1 if every column met the tolerance */
+  int64_t probe_iters;  /* PCG iterations summed over the columns */
   double logdet_P;      /* log det P (Sylvester, App. F) */
   double logdet_offset; /* sum log W - sum log D */
   double logdet_sw;     /* SLQ estimate of log det(Sigma_V + W^{-1}) */

@@ -236,7 +236,16 @@ __global__ void k_vchild_sort(const int64_t* __restrict__ cptr, int64_t n, int* 
 }
 
 // ---------------------------------------------------------------- B products
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int2 u = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(u.x, l), __builtin_amdgcn_readlane(u.y, l)));
+}
+
 // One wave per point of a level, one lane per column (64-column passes).
+// The point's list (neighbours or children, with coefficients) is loaded
+// once across the lanes and broadcast entry by entry (readlane reads a lane
+// whatever the exec mask), so the row gathers of four entries are in flight
+// together.
 // Forward solve B x = y in place: x_i = y_i + sum_s A_i[s] x_{N(i)[s]}.
 __global__ __launch_bounds__(256) void k_vtri_fwd(const int* __restrict__ pts, int cnt, const int* __restrict__ nbr,
                                                   const double* __restrict__ coef, int mv, double* X, int64_t ld,
@@ -245,19 +254,27 @@ __global__ __launch_bounds__(256) void k_vtri_fwd(const int* __restrict__ pts, i
   const int lane = threadIdx.x & 63;
   if (w >= cnt) return;
   const int64_t i = pts[w];
+  const int js = lane < mv ? nbr[i * mv + lane] : -1;
+  const double as = lane < mv ? coef[i * mv + lane] : 0.0;
+  const int k = __popcll(__ballot(js >= 0));  // the neighbours are a prefix of the list
   for (int c = lane; c < ncols; c += 64) {
-    double acc = X[i * ld + c];
-    for (int s = 0; s < mv; ++s) {
-      const int j = nbr[i * mv + s];
-      if (j < 0) break;
-      acc += coef[i * mv + s] * X[(int64_t)j * ld + c];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int s = 0;
+    for (; s + 4 <= k; s += 4) {
+      const int64_t j0 = __builtin_amdgcn_readlane(js, s), j1 = __builtin_amdgcn_readlane(js, s + 1);
+      const int64_t j2 = __builtin_amdgcn_readlane(js, s + 2), j3 = __builtin_amdgcn_readlane(js, s + 3);
+      a0 += readlane_d(as, s) * X[j0 * ld + c];
+      a1 += readlane_d(as, s + 1) * X[j1 * ld + c];
+      a2 += readlane_d(as, s + 2) * X[j2 * ld + c];
+      a3 += readlane_d(as, s + 3) * X[j3 * ld + c];
     }
-    X[i * ld + c] = acc;
+    for (; s < k; ++s) a0 += readlane_d(as, s) * X[(int64_t)__builtin_amdgcn_readlane(js, s) * ld + c];
+    X[i * ld + c] += (a0 + a1) + (a2 + a3);
   }
 }
 
 // Backward solve B^T z = y in place: z_j = y_j + sum over children i of j of
-// A_i[s] z_i (children have higher levels).
+// A_i[s] z_i (children have higher levels), the list taken 64 at a time.
 __global__ __launch_bounds__(256) void k_vtri_bwd(const int* __restrict__ pts, int cnt, const int64_t* __restrict__ cptr,
                                                   const int* __restrict__ ci, const double* __restrict__ cv, double* X,
                                                   int64_t ld, int ncols) {
@@ -266,10 +283,27 @@ __global__ __launch_bounds__(256) void k_vtri_bwd(const int* __restrict__ pts, i
   if (w >= cnt) return;
   const int64_t j = pts[w];
   const int64_t b = cptr[j], e = cptr[j + 1];
-  for (int c = lane; c < ncols; c += 64) {
-    double acc = X[j * ld + c];
-    for (int64_t p = b; p < e; ++p) acc += cv[p] * X[(int64_t)ci[p] * ld + c];
-    X[j * ld + c] = acc;
+  for (int c0 = 0; c0 < ncols; c0 += 64) {
+    const int c = c0 + lane;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int64_t p0 = b; p0 < e; p0 += 64) {
+      const int nq = (int)min<int64_t>(64, e - p0);
+      const int iq = lane < nq ? ci[p0 + lane] : 0;
+      const double vq = lane < nq ? cv[p0 + lane] : 0.0;
+      if (c < ncols) {
+        int q = 0;
+        for (; q + 4 <= nq; q += 4) {
+          const int64_t i0 = __builtin_amdgcn_readlane(iq, q), i1 = __builtin_amdgcn_readlane(iq, q + 1);
+          const int64_t i2 = __builtin_amdgcn_readlane(iq, q + 2), i3 = __builtin_amdgcn_readlane(iq, q + 3);
+          a0 += readlane_d(vq, q) * X[i0 * ld + c];
+          a1 += readlane_d(vq, q + 1) * X[i1 * ld + c];
+          a2 += readlane_d(vq, q + 2) * X[i2 * ld + c];
+          a3 += readlane_d(vq, q + 3) * X[i3 * ld + c];
+        }
+        for (; q < nq; ++q) a0 += readlane_d(vq, q) * X[(int64_t)__builtin_amdgcn_readlane(iq, q) * ld + c];
+      }
+    }
+    if (c < ncols) X[j * ld + c] += (a0 + a1) + (a2 + a3);
   }
 }
 
@@ -964,6 +998,7 @@ fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, doubl
     stats->iters_rhs = hit[0];
     stats->iters_max = *std::max_element(hit.begin(), hit.end());
     stats->converged = converged ? 1 : 0;
+    for (int c = 0; c < ncols; ++c) stats->probe_iters += hit[c];
     stats->logdet_P = v->logdet_P;
     stats->logdet_offset = v->offset;
     stats->logdet_sw = hres[1];

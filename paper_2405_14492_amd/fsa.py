@@ -79,7 +79,7 @@ class fsa_stats(C.Structure):
 
 class fsa_vecchia_stats(C.Structure):
     _fields_ = [("nlevels", C.c_int32), ("iters_max", C.c_int32), ("iters_rhs", C.c_int32), ("converged", C.c_int32),
-                ("logdet_P", C.c_double), ("logdet_offset", C.c_double), ("logdet_sw", C.c_double),
+                ("probe_iters", C.c_int64), ("logdet_P", C.c_double), ("logdet_offset", C.c_double), ("logdet_sw", C.c_double),
                 ("ms_solve", C.c_double)]
 
     def as_dict(self):
