@@ -241,69 +241,52 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(u.x, l), __builtin_amdgcn_readlane(u.y, l)));
 }
 
-// One wave per point of a level, one lane per column (64-column passes).
-// The point's list (neighbours or children, with coefficients) is loaded
-// once across the lanes and broadcast entry by entry (readlane reads a lane
-// whatever the exec mask), so the row gathers of four entries are in flight
-// together.
-// Forward solve B x = y in place: x_i = y_i + sum_s A_i[s] x_{N(i)[s]}.
-__global__ __launch_bounds__(256) void k_vtri_fwd(const int* __restrict__ pts, int cnt, const int* __restrict__ nbr,
-                                                  const double* __restrict__ coef, int mv, double* X, int64_t ld,
-                                                  int ncols) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+// One workgroup (NW waves) per point of a level, one lane per column
+// (64-column passes).  The point's list (neighbours or children, with
+// coefficients) is loaded across the lanes 64 entries at a time and
+// broadcast entry by entry (readlane reads a lane whatever the exec mask);
+// wave q takes the groups of four entries q, q + NW, q + 2 NW, ... so that
+// up to 4 NW row gathers per point are in flight, and the NW partial sums
+// are added in a fixed order.
+template <bool CHILDREN, int NW>
+__global__ __launch_bounds__(NW * 64) void k_vtri(const int* __restrict__ pts, int cnt, const int64_t* __restrict__ cptr,
+                                              const int* __restrict__ idx, const double* __restrict__ val, int mv,
+                                              double* X, int64_t ld, int ncols) {
+  __shared__ double part[NW][64];
+  if ((int)blockIdx.x >= cnt) return;  // uniform per workgroup
+  const int wq = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  if (w >= cnt) return;
-  const int64_t i = pts[w];
-  const int js = lane < mv ? nbr[i * mv + lane] : -1;
-  const double as = lane < mv ? coef[i * mv + lane] : 0.0;
-  const int k = __popcll(__ballot(js >= 0));  // the neighbours are a prefix of the list
-  for (int c = lane; c < ncols; c += 64) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int s = 0;
-    for (; s + 4 <= k; s += 4) {
-      const int64_t j0 = __builtin_amdgcn_readlane(js, s), j1 = __builtin_amdgcn_readlane(js, s + 1);
-      const int64_t j2 = __builtin_amdgcn_readlane(js, s + 2), j3 = __builtin_amdgcn_readlane(js, s + 3);
-      a0 += readlane_d(as, s) * X[j0 * ld + c];
-      a1 += readlane_d(as, s + 1) * X[j1 * ld + c];
-      a2 += readlane_d(as, s + 2) * X[j2 * ld + c];
-      a3 += readlane_d(as, s + 3) * X[j3 * ld + c];
-    }
-    for (; s < k; ++s) a0 += readlane_d(as, s) * X[(int64_t)__builtin_amdgcn_readlane(js, s) * ld + c];
-    X[i * ld + c] += (a0 + a1) + (a2 + a3);
-  }
-}
-
-// Backward solve B^T z = y in place: z_j = y_j + sum over children i of j of
-// A_i[s] z_i (children have higher levels), the list taken 64 at a time.
-__global__ __launch_bounds__(256) void k_vtri_bwd(const int* __restrict__ pts, int cnt, const int64_t* __restrict__ cptr,
-                                                  const int* __restrict__ ci, const double* __restrict__ cv, double* X,
-                                                  int64_t ld, int ncols) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (w >= cnt) return;
-  const int64_t j = pts[w];
-  const int64_t b = cptr[j], e = cptr[j + 1];
+  const int64_t i = pts[blockIdx.x];
+  // forward: the neighbours of i (a prefix of its mv slots); backward: its children
+  const int64_t b = CHILDREN ? cptr[i] : i * mv;
+  const int64_t e = CHILDREN ? cptr[i + 1] : i * mv + mv;
   for (int c0 = 0; c0 < ncols; c0 += 64) {
     const int c = c0 + lane;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     for (int64_t p0 = b; p0 < e; p0 += 64) {
-      const int nq = (int)min<int64_t>(64, e - p0);
-      const int iq = lane < nq ? ci[p0 + lane] : 0;
-      const double vq = lane < nq ? cv[p0 + lane] : 0.0;
+      const int64_t rem = e - p0;
+      const int m64 = (int)(rem < 64 ? rem : 64);
+      const int iq = lane < m64 ? idx[p0 + lane] : -1;
+      const double vq = lane < m64 ? val[p0 + lane] : 0.0;
+      const int nq = CHILDREN ? m64 : __popcll(__ballot(iq >= 0));
       if (c < ncols) {
-        int q = 0;
-        for (; q + 4 <= nq; q += 4) {
-          const int64_t i0 = __builtin_amdgcn_readlane(iq, q), i1 = __builtin_amdgcn_readlane(iq, q + 1);
-          const int64_t i2 = __builtin_amdgcn_readlane(iq, q + 2), i3 = __builtin_amdgcn_readlane(iq, q + 3);
-          a0 += readlane_d(vq, q) * X[i0 * ld + c];
-          a1 += readlane_d(vq, q + 1) * X[i1 * ld + c];
-          a2 += readlane_d(vq, q + 2) * X[i2 * ld + c];
-          a3 += readlane_d(vq, q + 3) * X[i3 * ld + c];
+        for (int q = 4 * wq; q < nq; q += 4 * NW) {
+          const int i0 = __builtin_amdgcn_readlane(iq, q);
+          a0 += readlane_d(vq, q) * X[(int64_t)i0 * ld + c];
+          if (q + 1 < nq) a1 += readlane_d(vq, q + 1) * X[(int64_t)__builtin_amdgcn_readlane(iq, q + 1) * ld + c];
+          if (q + 2 < nq) a2 += readlane_d(vq, q + 2) * X[(int64_t)__builtin_amdgcn_readlane(iq, q + 2) * ld + c];
+          if (q + 3 < nq) a3 += readlane_d(vq, q + 3) * X[(int64_t)__builtin_amdgcn_readlane(iq, q + 3) * ld + c];
         }
-        for (; q < nq; ++q) a0 += readlane_d(vq, q) * X[(int64_t)__builtin_amdgcn_readlane(iq, q) * ld + c];
       }
     }
-    if (c < ncols) X[j * ld + c] += (a0 + a1) + (a2 + a3);
+    part[wq][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (wq == 0 && c < ncols) {
+      double t = part[0][lane];
+      for (int u = 1; u < NW; ++u) t += part[u][lane];
+      X[i * ld + c] += t;
+    }
+    __syncthreads();
   }
 }
 
@@ -545,7 +528,8 @@ struct fsa_vecchia {
   Buf<int64_t> cptr, scan_scratch;
   Buf<int> ci;
   Buf<double> cv;
-  std::vector<int> lptr;  // level l holds order[lptr[l] .. lptr[l+1])
+  std::vector<int> lptr;   // level l holds order[lptr[l] .. lptr[l+1])
+  std::vector<int> lmaxc;  // longest child list among the points of level l
   // FITC preconditioner of Sigma + W^{-1}
   Buf<double> Sm, Lm, A, Ds, C, LCinv, Cinv, parts;  // parts: [0] log det P, [1] sum log w - sum log D
   BlasHandle blas;
@@ -576,14 +560,19 @@ fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, doub
   const int nlev = (int)v->lptr.size() - 1;
   for (int l = nlev - 1; l >= 0; --l) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
-    hipLaunchKernelGGL(k_vtri_bwd, dim3(grid1(cnt, 4)), dim3(256), 0, st, v->order.p + b, cnt, v->cptr.p, v->ci.p,
-                       v->cv.p, Y, ldy, ncols);
+    // levels with long child lists (the early points) take 16 waves per point
+    if (v->lmaxc[l] > 96)
+      hipLaunchKernelGGL((k_vtri<true, 16>), dim3((unsigned)cnt), dim3(1024), 0, st, v->order.p + b, cnt, v->cptr.p,
+                         v->ci.p, v->cv.p, 0, Y, ldy, ncols);
+    else
+      hipLaunchKernelGGL((k_vtri<true, 4>), dim3((unsigned)cnt), dim3(256), 0, st, v->order.p + b, cnt, v->cptr.p,
+                         v->ci.p, v->cv.p, 0, Y, ldy, ncols);
   }
   hipLaunchKernelGGL(k_vscale_rows, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Y, ldy, v->Dv.p);
   for (int l = 0; l < nlev; ++l) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
-    hipLaunchKernelGGL(k_vtri_fwd, dim3(grid1(cnt, 4)), dim3(256), 0, st, v->order.p + b, cnt, v->nbr.p, v->coef.p,
-                       v->mv, Y, ldy, ncols);
+    hipLaunchKernelGGL((k_vtri<false, 4>), dim3((unsigned)cnt), dim3(256), 0, st, v->order.p + b, cnt,
+                       (const int64_t*)nullptr, v->nbr.p, v->coef.p, v->mv, Y, ldy, ncols);
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -729,6 +718,21 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
     FSA_HIP(hipStreamSynchronize(st));
     FSA_TRY(v->ci.alloc(std::max<int64_t>(nnz, 1)));
     FSA_TRY(v->cv.alloc(std::max<int64_t>(nnz, 1)));
+    // per level, the longest child list (host-side launch planning)
+    {
+      std::vector<int64_t> hcp(n + 1);
+      std::vector<int> hord(n);
+      FSA_HIP(hipMemcpyAsync(hcp.data(), v->cptr.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      FSA_HIP(hipMemcpyAsync(hord.data(), v->order.p, n * sizeof(int), hipMemcpyDeviceToHost, st));
+      FSA_HIP(hipStreamSynchronize(st));
+      const int nl = (int)v->lptr.size() - 1;
+      v->lmaxc.assign(nl, 0);
+      for (int l = 0; l < nl; ++l)
+        for (int q = v->lptr[l]; q < v->lptr[l + 1]; ++q) {
+          const int j = hord[q];
+          v->lmaxc[l] = std::max(v->lmaxc[l], (int)(hcp[j + 1] - hcp[j]));
+        }
+    }
     if (mv > 0) {
       hipLaunchKernelGGL(k_vchild_fill, dim3(grid1(n * mv)), dim3(256), 0, st, v->nbr.p, v->coef.p, n, mv, v->cptr.p,
                          cur.p, v->ci.p, v->cv.p);
