@@ -241,6 +241,8 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(u.x, l), __builtin_amdgcn_readlane(u.y, l)));
 }
 
+// Points, lists and block rows are stored in level order, so level l is the
+// range of positions [base, base + cnt) and a list holds positions.
 // One workgroup (NW waves) per point of a level, one lane per column
 // (64-column passes).  The point's list (neighbours or children, with
 // coefficients) is loaded across the lanes 64 entries at a time and
@@ -249,14 +251,14 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 // up to 4 NW row gathers per point are in flight, and the NW partial sums
 // are added in a fixed order.
 template <bool CHILDREN, int NW>
-__global__ __launch_bounds__(NW * 64) void k_vtri(const int* __restrict__ pts, int cnt, const int64_t* __restrict__ cptr,
+__global__ __launch_bounds__(NW * 64) void k_vtri(int base, int cnt, const int64_t* __restrict__ cptr,
                                               const int* __restrict__ idx, const double* __restrict__ val, int mv,
                                               double* X, int64_t ld, int ncols) {
   __shared__ double part[NW][64];
   if ((int)blockIdx.x >= cnt) return;  // uniform per workgroup
   const int wq = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int64_t i = pts[blockIdx.x];
+  const int64_t i = base + (int64_t)blockIdx.x;
   // forward: the neighbours of i (a prefix of its mv slots); backward: its children
   const int64_t b = CHILDREN ? cptr[i] : i * mv;
   const int64_t e = CHILDREN ? cptr[i + 1] : i * mv + mv;
@@ -321,6 +323,51 @@ __global__ __launch_bounds__(256) void k_vBt(int64_t n, const int64_t* __restric
     for (int64_t p = b; p < e; ++p) acc -= cv[p] * T[(int64_t)ci[p] * ldt + c];
     Y[j * ldy + c] = acc;
   }
+}
+
+// ---------------------------------------------------------------- level order
+__global__ void k_vposof(const int* __restrict__ order, int64_t n, int* __restrict__ posof) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p < n) posof[order[p]] = (int)p;
+}
+
+// the factor, D, W and the locations in level order; neighbour lists hold positions
+__global__ void k_vperm(const int* __restrict__ order, const int* __restrict__ posof, int64_t n, int mv,
+                        const int* __restrict__ nbr, const double* __restrict__ coef, const double* __restrict__ Dv,
+                        const double* __restrict__ w, const double* __restrict__ xs, int* __restrict__ fnbr,
+                        double* __restrict__ fcoef, double* __restrict__ Dvp, double* __restrict__ wp,
+                        double* __restrict__ xsp) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t i = order[p];
+  for (int s = 0; s < mv; ++s) {
+    const int j = nbr[i * mv + s];
+    fnbr[p * mv + s] = j < 0 ? -1 : posof[j];
+    fcoef[p * mv + s] = coef[i * mv + s];
+  }
+  Dvp[p] = Dv[i];
+  wp[p] = w[i];
+  xsp[2 * p] = xs[2 * i];
+  xsp[2 * p + 1] = xs[2 * i + 1];
+}
+
+// Y[p] = X[order[p]] (into level order) / Y[order[p]] = X[p] (back)
+__global__ void k_vgather(int64_t n, int ncols, const double* __restrict__ X, int64_t ldx,
+                          const int* __restrict__ order, double* __restrict__ Y, int64_t ldy) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t p = e / ncols;
+  const int c = (int)(e - p * ncols);
+  Y[p * ldy + c] = X[(int64_t)order[p] * ldx + c];
+}
+
+__global__ void k_vscatter(int64_t n, int ncols, const double* __restrict__ X, int64_t ldx,
+                           const int* __restrict__ order, double* __restrict__ Y, int64_t ldy) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t p = e / ncols;
+  const int c = (int)(e - p * ncols);
+  Y[(int64_t)order[p] * ldy + c] = X[p * ldx + c];
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -404,10 +451,6 @@ __global__ void k_vsum_fixed(const double* __restrict__ part, int np, double* ou
   *out = a;
 }
 
-__global__ void k_viota(int* p, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) p[i] = (int)i;
-}
 
 // ---------------------------------------------------------------- PCG
 // One thread per column.  rz = r^T z, bn2 = |b|^2, active iff |b| > 0.
@@ -492,11 +535,11 @@ __global__ void k_vpcg_direction(int64_t n, int ncols, int64_t ld, const double*
   H[o] = Z[o] + beta[c] * H[o];
 }
 
-// x = u_0 / w
-__global__ void k_vsolution(int64_t n, const double* __restrict__ U, int64_t ld, const double* __restrict__ w,
-                            double* __restrict__ x) {
+// x = u_0 / w, back to the caller's order
+__global__ void k_vsolution(int64_t n, const double* __restrict__ U, int64_t ld, const double* __restrict__ wp,
+                            const int* __restrict__ order, double* __restrict__ x) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p < n) x[p] = U[p * ld] / w[p];
+  if (p < n) x[order[p]] = U[p * ld] / wp[p];
 }
 
 // log det(Sigma_V^{-1} + W) = offset + log det P + mean of the SLQ terms
@@ -523,8 +566,11 @@ struct fsa_vecchia {
   int m = 0, mp = 0, mv = 0;
   Theta th{};
   Buf<double> xs, ind, w;
-  Buf<int> nbr, level, order, perm, info;
+  Buf<int> nbr, level, order, info;  // nbr, coef, Dv, w, xs in the caller's order
   Buf<double> coef, Dv;
+  // level order: position p holds point order[p]; fnbr/fcoef list positions
+  Buf<int> posof, fnbr;
+  Buf<double> fcoef, Dvp, wp, xsp;
   Buf<int64_t> cptr, scan_scratch;
   Buf<int> ci;
   Buf<double> cv;
@@ -562,17 +608,17 @@ fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, doub
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
     // levels with long child lists (the early points) take 16 waves per point
     if (v->lmaxc[l] > 96)
-      hipLaunchKernelGGL((k_vtri<true, 16>), dim3((unsigned)cnt), dim3(1024), 0, st, v->order.p + b, cnt, v->cptr.p,
+      hipLaunchKernelGGL((k_vtri<true, 16>), dim3((unsigned)cnt), dim3(1024), 0, st, b, cnt, v->cptr.p,
                          v->ci.p, v->cv.p, 0, Y, ldy, ncols);
     else
-      hipLaunchKernelGGL((k_vtri<true, 4>), dim3((unsigned)cnt), dim3(256), 0, st, v->order.p + b, cnt, v->cptr.p,
+      hipLaunchKernelGGL((k_vtri<true, 4>), dim3((unsigned)cnt), dim3(256), 0, st, b, cnt, v->cptr.p,
                          v->ci.p, v->cv.p, 0, Y, ldy, ncols);
   }
-  hipLaunchKernelGGL(k_vscale_rows, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Y, ldy, v->Dv.p);
+  hipLaunchKernelGGL(k_vscale_rows, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Y, ldy, v->Dvp.p);
   for (int l = 0; l < nlev; ++l) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
-    hipLaunchKernelGGL((k_vtri<false, 4>), dim3((unsigned)cnt), dim3(256), 0, st, v->order.p + b, cnt,
-                       (const int64_t*)nullptr, v->nbr.p, v->coef.p, v->mv, Y, ldy, ncols);
+    hipLaunchKernelGGL((k_vtri<false, 4>), dim3((unsigned)cnt), dim3(256), 0, st, b, cnt, (const int64_t*)nullptr,
+                       v->fnbr.p, v->fcoef.p, v->mv, Y, ldy, ncols);
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -584,7 +630,7 @@ fsa_status precision_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, 
   const int64_t n = v->n;
   Buf<double> T;
   FSA_TRY(T.alloc((size_t)n * ncols));
-  hipLaunchKernelGGL(k_vB_div, dim3(grid1(n, 4)), dim3(256), 0, st, n, v->nbr.p, v->coef.p, v->mv, v->Dv.p, X, ldx,
+  hipLaunchKernelGGL(k_vB_div, dim3(grid1(n, 4)), dim3(256), 0, st, n, v->fnbr.p, v->fcoef.p, v->mv, v->Dvp.p, X, ldx,
                      ncols, T.p, (int64_t)ncols);
   hipLaunchKernelGGL(k_vBt, dim3(grid1(n, 4)), dim3(256), 0, st, n, v->cptr.p, v->ci.p, v->cv.p, T.p,
                      (int64_t)ncols, ncols, Y, ldy);
@@ -607,7 +653,8 @@ fsa_status precond(fsa_vecchia* v, const double* R, int64_t ld, int ncols, doubl
 // Y = (Sigma_V + W^{-1}) X
 fsa_status operator_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, double* Y, int64_t ldy) {
   FSA_TRY(sigma_v(v, X, ldx, ncols, Y, ldy));
-  hipLaunchKernelGGL(k_vadd_winv, dim3(grid1(v->n * ncols)), dim3(256), 0, v->st, v->n, ncols, X, ldx, v->w.p, Y, ldy);
+  hipLaunchKernelGGL(k_vadd_winv, dim3(grid1(v->n * ncols)), dim3(256), 0, v->st, v->n, ncols, X, ldx, v->wp.p, Y,
+                     ldy);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -702,7 +749,18 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
     FSA_HIP(hipGetLastError());
     FSA_HIP(hipStreamSynchronize(st));  // lp, cnt and cur leave scope
   }
-  // children lists (rows of B^T)
+  // level order
+  FSA_TRY(v->posof.alloc(n));
+  FSA_TRY(v->fnbr.alloc((size_t)n * std::max(mv, 1)));
+  FSA_TRY(v->fcoef.alloc((size_t)n * std::max(mv, 1)));
+  FSA_TRY(v->Dvp.alloc(n));
+  FSA_TRY(v->wp.alloc(n));
+  FSA_TRY(v->xsp.alloc(2 * (size_t)n));
+  hipLaunchKernelGGL(k_vposof, dim3(grid1(n)), dim3(256), 0, st, v->order.p, n, v->posof.p);
+  hipLaunchKernelGGL(k_vperm, dim3(grid1(n)), dim3(256), 0, st, v->order.p, v->posof.p, n, mv, v->nbr.p, v->coef.p,
+                     v->Dv.p, v->w.p, v->xs.p, v->fnbr.p, v->fcoef.p, v->Dvp.p, v->wp.p, v->xsp.p);
+  FSA_HIP(hipGetLastError());
+  // children lists (rows of B^T), by position
   {
     Buf<int> ccnt, cur;
     FSA_TRY(ccnt.alloc(n));
@@ -711,7 +769,7 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
     FSA_HIP(hipMemsetAsync(ccnt.p, 0, n * sizeof(int), st));
     FSA_HIP(hipMemsetAsync(cur.p, 0, n * sizeof(int), st));
     if (mv > 0)
-      hipLaunchKernelGGL(k_vchild_count, dim3(grid1(n * mv)), dim3(256), 0, st, v->nbr.p, n, mv, ccnt.p);
+      hipLaunchKernelGGL(k_vchild_count, dim3(grid1(n * mv)), dim3(256), 0, st, v->fnbr.p, n, mv, ccnt.p);
     FSA_TRY(scan_counts(ccnt.p, n, v->cptr.p, v->scan_scratch, st));
     int64_t nnz = 0;
     FSA_HIP(hipMemcpyAsync(&nnz, v->cptr.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -721,20 +779,16 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
     // per level, the longest child list (host-side launch planning)
     {
       std::vector<int64_t> hcp(n + 1);
-      std::vector<int> hord(n);
       FSA_HIP(hipMemcpyAsync(hcp.data(), v->cptr.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-      FSA_HIP(hipMemcpyAsync(hord.data(), v->order.p, n * sizeof(int), hipMemcpyDeviceToHost, st));
       FSA_HIP(hipStreamSynchronize(st));
       const int nl = (int)v->lptr.size() - 1;
       v->lmaxc.assign(nl, 0);
       for (int l = 0; l < nl; ++l)
-        for (int q = v->lptr[l]; q < v->lptr[l + 1]; ++q) {
-          const int j = hord[q];
-          v->lmaxc[l] = std::max(v->lmaxc[l], (int)(hcp[j + 1] - hcp[j]));
-        }
+        for (int q = v->lptr[l]; q < v->lptr[l + 1]; ++q)
+          v->lmaxc[l] = std::max(v->lmaxc[l], (int)(hcp[q + 1] - hcp[q]));
     }
     if (mv > 0) {
-      hipLaunchKernelGGL(k_vchild_fill, dim3(grid1(n * mv)), dim3(256), 0, st, v->nbr.p, v->coef.p, n, mv, v->cptr.p,
+      hipLaunchKernelGGL(k_vchild_fill, dim3(grid1(n * mv)), dim3(256), 0, st, v->fnbr.p, v->fcoef.p, n, mv, v->cptr.p,
                          cur.p, v->ci.p, v->cv.p);
       hipLaunchKernelGGL(k_vchild_sort, dim3(grid1(n)), dim3(256), 0, st, v->cptr.p, n, v->ci.p, v->cv.p);
     }
@@ -755,9 +809,9 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
   }
   FSA_TRY(blas_acquire(v->blas));
   FSA_TRY(v->A.alloc((size_t)n * mp));
-  FSA_TRY(whiten(v->blas, v->xs.p, n, v->ind.p, v->m, mp, v->th, v->Lm.p, v->A.p, st));
+  FSA_TRY(whiten(v->blas, v->xsp.p, n, v->ind.p, v->m, mp, v->th, v->Lm.p, v->A.p, st));
   FSA_TRY(v->Ds.alloc(n));
-  hipLaunchKernelGGL(k_vds, dim3(grid1(n, 4)), dim3(256), 0, st, v->A.p, n, mp, v->th.s1, v->w.p, v->Ds.p);
+  hipLaunchKernelGGL(k_vds, dim3(grid1(n, 4)), dim3(256), 0, st, v->A.p, n, mp, v->th.s1, v->wp.p, v->Ds.p);
   FSA_TRY(v->C.alloc((size_t)mp * mp));
   FSA_TRY(capacitance(v->A.p, v->Ds.p, n, mp, v->C.p, v->scr, st));
   FSA_TRY(dense_cholesky(v->C.p, mp, v->info.p, st));
@@ -787,9 +841,6 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
   // parts[0] = log det P, parts[1] = sum log w - sum log D (read by k_vlogdet)
   const double hp2[2] = {v->logdet_P, v->offset};
   FSA_HIP(hipMemcpyAsync(v->parts.p, hp2, sizeof(hp2), hipMemcpyHostToDevice, st));
-  FSA_TRY(v->perm.alloc(n));
-  hipLaunchKernelGGL(k_viota, dim3(grid1(n)), dim3(256), 0, st, v->perm.p, n);
-  FSA_HIP(hipGetLastError());
   FSA_HIP(hipStreamSynchronize(st));
   return FSA_OK;
 }
@@ -849,39 +900,44 @@ fsa_status fsa_vecchia_apply_dev(fsa_vecchia* v, int32_t which, const double* X,
   if (!v || !X || !Y) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
   if (ncols < 1 || ldx < ncols || ldy < ncols) { set_error("need 1 <= ncols <= ldx, ldy"); return FSA_ERR_INVALID_ARG; }
   if (X == Y) { set_error("X and Y must not alias"); return FSA_ERR_INVALID_ARG; }
+  if (which < FSA_V_SIGMA || which > FSA_V_P_INV) {
+    set_error("unknown operator %d", which);
+    return FSA_ERR_INVALID_ARG;
+  }
   PoolStream ps(v->st);
+  hipStream_t st = v->st;
+  const int64_t n = v->n;
+  // into level order, apply, back to the caller's order
+  const int ld = (int)round_up(ncols, 4), ldw = (int)round_up(ncols, 64);
+  Buf<double> Xp, Yp;
+  FSA_TRY(Xp.alloc((size_t)n * ld));
+  FSA_TRY(Yp.alloc((size_t)n * ld));
+  hipLaunchKernelGGL(k_vgather, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, X, ldx, v->order.p, Xp.p,
+                     (int64_t)ld);
   switch (which) {
     case FSA_V_SIGMA:
-      FSA_TRY(sigma_v(v, X, ldx, ncols, Y, ldy));
+      FSA_TRY(sigma_v(v, Xp.p, ld, ncols, Yp.p, ld));
       break;
     case FSA_V_PRECISION:
-      FSA_TRY(precision_v(v, X, ldx, ncols, Y, ldy));
+      FSA_TRY(precision_v(v, Xp.p, ld, ncols, Yp.p, ld));
       break;
     case FSA_V_OPERATOR:
-      FSA_TRY(operator_v(v, X, ldx, ncols, Y, ldy));
+      FSA_TRY(operator_v(v, Xp.p, ld, ncols, Yp.p, ld));
       break;
-    case FSA_V_P_INV: {
-      const int ld = (int)round_up(ncols, 4), ldw = (int)round_up(ncols, 64);
-      Buf<double> R, Z, T, Wm, G;
-      FSA_TRY(R.alloc((size_t)v->n * ld));
-      FSA_TRY(Z.alloc((size_t)v->n * ld));
-      FSA_TRY(T.alloc((size_t)v->n * ld));
+    default: {
+      Buf<double> T, Wm, G;
+      FSA_TRY(T.alloc((size_t)n * ld));
       FSA_TRY(Wm.alloc((size_t)v->mp * ldw));
       FSA_TRY(G.alloc((size_t)v->mp * ldw));
-      hipLaunchKernelGGL(k_vcopy, dim3(grid1(v->n * ncols)), dim3(256), 0, v->st, v->n, ncols, X, ldx, R.p,
-                         (int64_t)ld);
-      FSA_TRY(precond(v, R.p, ld, ncols, Z.p, T.p, Wm.p, G.p, ldw));
-      hipLaunchKernelGGL(k_vcopy, dim3(grid1(v->n * ncols)), dim3(256), 0, v->st, v->n, ncols, Z.p, (int64_t)ld, Y,
-                         ldy);
-      FSA_HIP(hipGetLastError());
-      FSA_HIP(hipStreamSynchronize(v->st));
+      FSA_TRY(precond(v, Xp.p, ld, ncols, Yp.p, T.p, Wm.p, G.p, ldw));
+      FSA_HIP(hipStreamSynchronize(st));  // T, Wm, G leave scope
       break;
     }
-    default:
-      set_error("unknown operator %d", which);
-      return FSA_ERR_INVALID_ARG;
   }
-  FSA_HIP(hipStreamSynchronize(v->st));
+  hipLaunchKernelGGL(k_vscatter, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Yp.p, (int64_t)ld, v->order.p, Y,
+                     ldy);
+  FSA_HIP(hipGetLastError());
+  FSA_HIP(hipStreamSynchronize(st));
   return FSA_OK;
 }
 
@@ -936,14 +992,17 @@ fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, doubl
   FSA_HIP(hipMemsetAsync(mem.p, 0, 8 * blk * sizeof(double), st));
   FSA_HIP(hipMemsetAsync(hist.p, 0, hist.bytes(), st));
   // right-hand sides [Sigma_V v, z_1 .. z_t], z ~ (0, P) (App. F sampling recipe)
-  FSA_TRY(sigma_v(v, rhs, 1, 1, T, ld));
+  hipLaunchKernelGGL(k_vgather, dim3(grid1(n)), dim3(256), 0, st, n, 1, rhs, (int64_t)1, v->order.p, Q0, ld);
+  FSA_TRY(sigma_v(v, Q0, ld, 1, T, ld));
+  FSA_HIP(hipMemsetAsync(Q0, 0, blk * sizeof(double), st));
   {
     Buf<double> y;
     FSA_TRY(y.alloc(n));
     FSA_HIP(hipMemcpy2DAsync(y.p, sizeof(double), T, ld * sizeof(double), sizeof(double), n,
                              hipMemcpyDeviceToDevice, st));
     FSA_HIP(hipMemsetAsync(T, 0, blk * sizeof(double), st));
-    FSA_TRY(make_probes(v->A.p, n, v->m, v->mp, v->Ds.p, y.p, v->perm.p, seed, num_probes, Bk, (int)ld, Emat.p, st));
+    // the Rademacher draws are keyed by the caller's point index (order[p])
+    FSA_TRY(make_probes(v->A.p, n, v->m, v->mp, v->Ds.p, y.p, v->order.p, seed, num_probes, Bk, (int)ld, Emat.p, st));
     FSA_HIP(hipStreamSynchronize(st));  // y leaves scope
   }
   // init: R = B, Z = P^{-1} R, H = Q0 = Z
@@ -986,7 +1045,7 @@ fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, doubl
     }
   }
   // solution and log det
-  hipLaunchKernelGGL(k_vsolution, dim3(grid1(n)), dim3(256), 0, st, n, U, ld, v->w.p, x);
+  hipLaunchKernelGGL(k_vsolution, dim3(grid1(n)), dim3(256), 0, st, n, U, ld, v->wp.p, v->order.p, x);
   FSA_TRY(slq_terms(ah, bh, iters, ncols, 1, c_w, c_slq, nullptr, max_iter, st));
   hipLaunchKernelGGL(k_vlogdet, dim3(1), dim3(64), 0, st, c_slq, 1, ncols, v->parts.p, res);
   FSA_HIP(hipGetLastError());
