@@ -93,6 +93,30 @@ fsa_status blas_left_mul(BlasHandle& b, hipStream_t st, const double* M, int mp,
                      "rocblas_dgemm");
 }
 
+// Y := Y + alpha K X with K row-major lower triangular (mp x mp); X, Y
+// point-major n x mp (column-major mp x n).  One product per 128-row block
+// of K over its nonzero columns [0, r0 + 128): 10/16 of the full product's
+// work.  Row-major K read column-major is K^T, so each block enters
+// transposed.
+fsa_status blas_lower_mul_acc(BlasHandle& b, hipStream_t st, const double* K, int mp, const double* X, double* Y,
+                              int64_t n, double alpha) {
+  if (n <= 0) return FSA_OK;
+  if (n > INT32_MAX) {
+    set_error("blas_lower_mul_acc: n too large");
+    return FSA_ERR_INVALID_ARG;
+  }
+  auto h = static_cast<rocblas_handle>(b.h);
+  FSA_TRY(blas_status(rocblas_set_stream(h, st), "rocblas_set_stream"));
+  const double one = 1.0;
+  for (int r0 = 0; r0 < mp; r0 += 128) {
+    const int bs = std::min(128, mp - r0), kr = r0 + bs;
+    FSA_TRY(blas_status(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, bs, (rocblas_int)n, kr,
+                                      &alpha, K + (size_t)r0 * mp, mp, X, mp, &one, Y + r0, mp),
+                        "rocblas_dgemm"));
+  }
+  return FSA_OK;
+}
+
 // Linv := L^{-1} for row-major lower-triangular L (mp x mp).  Column-major,
 // row-major L is the upper-triangular L^T, whose inverse (L^{-1})^T read
 // back row-major is L^{-1}.

@@ -78,6 +78,9 @@ void blas_release(BlasHandle& b);
 void blas_trim();
 // X := L^{-1} X (L row-major lower mp x mp, X point-major n x mp)
 fsa_status blas_solve_lower(BlasHandle& b, hipStream_t st, const double* L, int mp, double* X, int64_t n);
+// Y := Y + alpha K X (K row-major lower-triangular mp x mp; X, Y point-major n x mp)
+fsa_status blas_lower_mul_acc(BlasHandle& b, hipStream_t st, const double* K, int mp, const double* X, double* Y,
+                              int64_t n, double alpha);
 // Linv := L^{-1} (row-major lower-triangular mp x mp)
 fsa_status blas_tri_inverse(BlasHandle& b, hipStream_t st, const double* L, double* Linv, int mp);
 // X := alpha M Y + beta X (M row-major mp x mp; X, Y point-major n x mp)
