@@ -220,11 +220,32 @@ def run_vecchia(F, torch, n, mv, m, t, steps, warmup, seed=0, cpu_sample_n=0):
         lds.append(ld)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
+    # the dominant kernels: the level-scheduled triangular solves of one
+    # Sigma_V product on t+1 columns, timed with HIP events on the stream the
+    # library runs on (torch's current stream, given at build)
+    X = torch.randn(n, t + 1, dtype=torch.float64, device="cuda")
+    v.apply(F.V_SIGMA, X)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        v.apply(F.V_SIGMA, X)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_prod = e0.elapsed_time(e1) / 3
+    nnz_b = n * mv - mv * (mv + 1) // 2  # sum over i of min(m_v, i)
+    # per pass: each list entry (4 B index, 8 B coefficient, a gathered row of
+    # t+1 doubles) and each point's own row read and written
+    prod_bytes = 2 * (nnz_b * (12 + 8 * (t + 1)) + n * 16 * (t + 1))
     v.close()
     out = {"workload": f"vecchia_solve_logdet n={n} m_v={mv} m={m} t={t} matern32 rho=0.05 W~U[0.05,0.25] tol=1e-6",
            "value": its / sec, "unit": "probe-iters/s", "ms_per_step": sec * 1e3 / steps, "ms_build": ms_build,
            "probe_iters_per_step": its / steps, "iters_max": st["iters_max"], "nlevels": st["nlevels"],
-           "logdet": lds[-1], "logdet_spread": float(np.std(lds)) if len(lds) > 1 else 0.0, "steps": steps}
+           "logdet": lds[-1], "logdet_spread": float(np.std(lds)) if len(lds) > 1 else 0.0, "steps": steps,
+           "roofline": {"bound": "hbm", "achieved": prod_bytes / (ms_prod * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                        "frac": prod_bytes / (ms_prod * 1e-3) / 1e9 / 8000.0, "traffic": None,
+                        "kernel": "Sigma_V product (k_vtri, both passes)", "ms_per_product": ms_prod,
+                        "algorithmic_bytes": prod_bytes,
+                        "note": f"latency-bound: {st['nlevels']} dependent levels per pass, one launch each"}}
     if cpu_sample_n:
         # The first ns points of the ordered workload are a Vecchia model of
         # their own (their neighbours are earlier points): the oracle solves
