@@ -98,3 +98,43 @@ def test_invalid_arguments_rejected_on_host(L, case):
     assert s == 1
     assert not ctx.value
     assert len(L.fsa_last_error()) > 0
+
+
+@pytest.mark.parametrize("case", ["n0", "m0", "m513", "mv33", "mv_neg", "kind_bad", "rho0", "s1_neg", "null_w"])
+def test_vecchia_invalid_arguments_rejected_on_host(L, case):
+    """fsa_vecchia_build_dev checks sizes and parameters before it touches
+    any pointer or the device (the buffers here are host memory, never read)."""
+    n, m, kind, s1, rho, mv = 10, 3, 1, 1.0, 0.1, 5
+    if case == "n0":
+        n = 0
+    elif case == "m0":
+        m = 0
+    elif case == "m513":
+        m = 513
+    elif case == "mv33":
+        mv = 33
+    elif case == "mv_neg":
+        mv = -1
+    elif case == "kind_bad":
+        kind = 9
+    elif case == "rho0":
+        rho = 0.0
+    elif case == "s1_neg":
+        s1 = -1.0
+    buf = np.zeros(2 * 1024)
+    w = None if case == "null_w" else buf.ctypes.data
+    h = ctypes.c_void_p()
+    s = L.fsa_vecchia_build_dev(buf.ctypes.data, n, buf.ctypes.data, m, kind, s1, rho, mv, w, None, ctypes.byref(h))
+    assert s == 1
+    assert not h.value
+    assert len(L.fsa_last_error()) > 0
+
+
+def test_vecchia_null_handle(L):
+    buf = np.zeros(16)
+    d = ctypes.c_double()
+    assert L.fsa_vecchia_apply_dev(None, 0, buf.ctypes.data, 1, 1, buf.ctypes.data, 1) == 1
+    assert L.fsa_vecchia_solve_logdet_dev(None, buf.ctypes.data, buf.ctypes.data, 4, 0, 1e-6, 10, ctypes.byref(d),
+                                          None) == 1
+    assert L.fsa_vecchia_factor_dev(None, None, None, None) == 1
+    assert L.fsa_vecchia_destroy(None) == 0
