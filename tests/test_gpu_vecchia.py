@@ -203,3 +203,65 @@ def test_fullsize_sampled_rows_and_identities():
     assert st["converged"] == 1
     assert rel < 1e-5, rel
     assert np.isfinite(logdet)
+
+
+def test_exponential_covariance_matches_oracle():
+    n, mv, m, t = 1500, 12, 32, 4
+    locs = G.uniform_locations(n, 31)
+    ind = G.random_subset_inducing(locs, m, 32)
+    w = G.laplace_weights(n, 33)
+    th = (F.EXPONENTIAL, 1.5, 0.1)
+    nbr_o = VO.neighbors(locs, mv)
+    coef_o, D_o = VO.factor(locs, nbr_o, th)
+    M = VO.Vecchia(locs, ind, th, mv, w)
+    vv = np.random.default_rng(4).standard_normal(n)
+    o = VO.solve_logdet(M, vv, t, seed=7, tol=1e-8, max_iter=2000)
+    with _gpu(locs, ind, w, th, mv) as v:
+        nbr, coef, D = (t_.cpu().numpy() for t_ in v.factor())
+        x, logdet, st = v.solve_logdet(_dev(vv), t, 7, tol=1e-8, max_iter=2000)
+    assert np.array_equal(nbr.astype(np.int64), nbr_o)
+    assert np.all(np.abs(coef - coef_o) <= _coef_tol(locs, nbr_o, coef_o, th) + 1e-300)
+    np.testing.assert_allclose(D, D_o, rtol=1e-9)
+    assert abs(st["iters_rhs"] - int(o["iters"][0])) <= 1
+    np.testing.assert_allclose(x.cpu().numpy(), o["x"], rtol=0, atol=1e-6 * np.abs(o["x"]).max())
+    assert abs(logdet - o["logdet"]) < 1e-6 * abs(o["logdet"])
+
+
+def test_solution_does_not_depend_on_the_probes():
+    """Every column runs CG on its own scalars, so the right-hand side's
+    column comes out the same whatever probes share the block."""
+    n, mv, m = 1200, 10, 24
+    locs, ind, w, th = _case(n, mv, m, seed=41)
+    vv = _dev(np.random.default_rng(5).standard_normal(n))
+    with _gpu(locs, ind, w, th, mv) as v:
+        x1, l1, s1 = v.solve_logdet(vv, 3, 1, tol=1e-9, max_iter=2000)
+        x2, l2, s2 = v.solve_logdet(vv, 9, 2, tol=1e-9, max_iter=2000)
+    assert s1["iters_rhs"] == s2["iters_rhs"]
+    assert torch.equal(x1, x2)
+    assert l1 != l2
+
+
+def test_side_stream():
+    """Built and run on a caller's non-default stream: the same results up to
+    rounding.  A second build may place the points of a level in another
+    order (they are scattered by an atomic cursor), which reorders the sums
+    over positions; within one build every sum has a fixed order."""
+    from paper_2405_14492_amd import fsa
+    n, mv, m = 900, 8, 16
+    locs, ind, w, th = _case(n, mv, m, seed=43)
+    X = _dev(np.random.default_rng(6).standard_normal((n, 3)))
+    vv = _dev(np.random.default_rng(7).standard_normal(n))
+    with _gpu(locs, ind, w, th, mv) as v:
+        Y0 = v.apply(fsa.V_SIGMA, X)
+        x0, l0, _ = v.solve_logdet(vv, 4, 3, tol=1e-9)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        dl, di, dw = _dev(locs), _dev(ind), _dev(w)
+        s.synchronize()
+        with fsa.Vecchia(dl, di, th[0], th[1], th[2], mv, dw, stream=s) as v:
+            Y1 = v.apply(fsa.V_SIGMA, X)
+            x1, l1, _ = v.solve_logdet(vv, 4, 3, tol=1e-9)
+        s.synchronize()
+    assert float((Y0 - Y1).abs().max() / Y0.abs().max()) < 1e-12
+    assert float((x0 - x1).abs().max() / x0.abs().max()) < 1e-9
+    assert abs(l0 - l1) < 1e-10 * abs(l0)
