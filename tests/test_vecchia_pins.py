@@ -36,11 +36,12 @@ def sigma_v_dense(M):
     return np.linalg.inv(B.T @ np.diag(1.0 / M.Dv) @ B)
 
 
-def test_full_conditioning_is_exact():
+@pytest.mark.parametrize("theta", [TH, (F.EXPONENTIAL, 2.0, 0.3)])
+def test_full_conditioning_is_exact(theta):
     """m_v = n - 1: every point conditions on all earlier ones, so
     B^T D^{-1} B is the exact precision Sigma^{-1}."""
-    M = model(40, 39)
-    S = dense_sigma(M.locs)
+    M = model(40, 39, theta=theta)
+    S = dense_sigma(M.locs, theta)
     np.testing.assert_allclose(sigma_v_dense(M), S, rtol=1e-8, atol=1e-8)
 
 
