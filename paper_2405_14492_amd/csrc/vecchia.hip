@@ -10,6 +10,8 @@
 #include <cmath>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "ops.hpp"
@@ -186,14 +188,9 @@ __global__ void k_vmaxlevel(const int* __restrict__ level, int64_t n, int* maxle
   if (i < n) atomicMax(maxlev, level[i]);
 }
 
-// points grouped by level (order inside a level is free: its points are
-// independent of each other)
-__global__ void k_vlevel_scatter(const int* __restrict__ level, int64_t n, const int* __restrict__ lptr, int* cursor,
-                                 int* __restrict__ order) {
+__global__ void k_viota(int* __restrict__ p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int L = level[i];
-  order[lptr[L] + atomicAdd(&cursor[L], 1)] = (int)i;
+  if (i < n) p[i] = (int)i;
 }
 
 // children of each point (the rows of B^T): counts, then fill, then each
@@ -727,12 +724,9 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
   FSA_HIP(hipStreamSynchronize(st));
   const int nlev = maxlev + 1;
   {
-    Buf<int> cnt, cur, lp;
+    Buf<int> cnt;
     FSA_TRY(cnt.alloc(nlev));
-    FSA_TRY(cur.alloc(nlev));
-    FSA_TRY(lp.alloc(nlev + 1));
     FSA_HIP(hipMemsetAsync(cnt.p, 0, nlev * sizeof(int), st));
-    FSA_HIP(hipMemsetAsync(cur.p, 0, nlev * sizeof(int), st));
     hipLaunchKernelGGL(k_vlevel_hist, dim3(grid1(n)), dim3(256), 0, st, v->level.p, n, cnt.p, v->info.p + 3);
     std::vector<int> hc(nlev);
     FSA_HIP(hipMemcpyAsync(hc.data(), cnt.p, nlev * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -743,11 +737,27 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
       set_error("Vecchia level schedule: %d points counted of %lld", v->lptr[nlev], (long long)n);
       return FSA_ERR_DEVICE;
     }
-    FSA_HIP(hipMemcpyAsync(lp.p, v->lptr.data(), (nlev + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+    // points grouped by level, in index order inside a level: a stable radix
+    // sort of (level, index), so positions, and every sum over them, are the
+    // same on every build
     FSA_TRY(v->order.alloc(n));
-    hipLaunchKernelGGL(k_vlevel_scatter, dim3(grid1(n)), dim3(256), 0, st, v->level.p, n, lp.p, cur.p, v->order.p);
-    FSA_HIP(hipGetLastError());
-    FSA_HIP(hipStreamSynchronize(st));  // lp, cnt and cur leave scope
+    {
+      Buf<int> keys_out, idx;
+      FSA_TRY(keys_out.alloc(n));
+      FSA_TRY(idx.alloc(n));
+      hipLaunchKernelGGL(k_viota, dim3(grid1(n)), dim3(256), 0, st, idx.p, n);
+      FSA_HIP(hipGetLastError());
+      int end_bit = 1;
+      while (end_bit < 31 && (1 << end_bit) <= maxlev) ++end_bit;
+      size_t tb = 0;
+      FSA_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, v->level.p, keys_out.p, idx.p, v->order.p, (int)n, 0,
+                                                 end_bit, st));
+      Buf<char> tmp;
+      FSA_TRY(tmp.alloc(tb));
+      FSA_HIP(hipcub::DeviceRadixSort::SortPairs((void*)tmp.p, tb, v->level.p, keys_out.p, idx.p, v->order.p, (int)n, 0,
+                                                 end_bit, st));
+      FSA_HIP(hipStreamSynchronize(st));  // the sort's buffers and cnt leave scope
+    }
   }
   // level order
   FSA_TRY(v->posof.alloc(n));
