@@ -614,7 +614,8 @@ fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, doub
   hipLaunchKernelGGL(k_vscale_rows, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Y, ldy, v->Dvp.p);
   for (int l = 0; l < nlev; ++l) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
-    hipLaunchKernelGGL((k_vtri<false, 4>), dim3((unsigned)cnt), dim3(256), 0, st, b, cnt, (const int64_t*)nullptr,
+    // at most 32 neighbours: 8 waves take four each, all gathers in one round
+    hipLaunchKernelGGL((k_vtri<false, 8>), dim3((unsigned)cnt), dim3(512), 0, st, b, cnt, (const int64_t*)nullptr,
                        v->fnbr.p, v->fcoef.p, v->mv, Y, ldy, ncols);
   }
   FSA_HIP(hipGetLastError());
