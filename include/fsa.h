@@ -63,7 +63,10 @@ typedef enum { FSA_COV_EXPONENTIAL = 0, FSA_COV_MATERN32 = 1 } fsa_cov;
  *     PCG block vectors in float32; Cholesky factors, inner products, the
  *     CG coefficients, the solution accumulator and the tridiagonal
  *     eigensolve in float64; the residual is recomputed with the float64
- *     operator every rr_period iterations.
+ *     operator every rr_period iterations.  A column stops once its float32
+ *     recurrence residual is below the tolerance and the float64 residual
+ *     b - Sigma~ u, recomputed then, confirms it; a column it does not
+ *     confirm continues its CG sequence from the float64 residual.
  *   MIXED_BF16A: MIXED_FP32 on a model whose whitened low-rank factor A is
  *     rounded to bfloat16 (to nearest even, once, right after whitening).
  *     The rounded factor is used everywhere, in float64 where the method is
@@ -118,7 +121,8 @@ typedef struct {
   int32_t max_iter;      /* iteration cap; reaching it gives FSA_ERR_NOT_CONVERGED */
   int32_t fixed_iter;    /* > 0: every column runs exactly this many iterations */
   int32_t precision;     /* fsa_precision */
-  int32_t rr_period;     /* mixed precision: float64 residual replacement period (0 = never) */
+  int32_t rr_period;     /* mixed precision: periodic float64 residual replacement every rr_period iterations
+                            (0 = none; the float64 stopping check of a tolerance run still replaces it once) */
   int32_t slq_weight_n;  /* 0: SLQ weight z^T P^{-1} z; 1: the weight n of Section 3.1 */
   int32_t profile;       /* bit k set: time every PCG launch of kernel class k (fsa_stats.kernel_ms[k]) with
                             a pair of HIP events on the stream (about 3 us each); FSA_PROFILE_ALL times all */
@@ -129,9 +133,9 @@ typedef struct {
 typedef struct {
   int32_t iters_min, iters_max; /* PCG iterations over the right-hand-side columns */
   int64_t probe_iters;          /* sum over columns of iterations executed */
-  double rel_res_max;           /* largest final ||r|| / ||b|| over the likelihood solve's columns, from the
-                                   CG recurrence residual (mixed precision: the float32 residual updated since
-                                   the last float64 replacement) */
+  double rel_res_max;           /* largest final ||r|| / ||b|| over the likelihood solve's columns: FP64, the
+                                   CG recurrence residual; mixed precision (tolerance mode), the float64
+                                   residual b - Sigma~_dagger u on which the stop is confirmed */
   double logdet;                /* SLQ estimate of log det Sigma~_dagger */
   double logdet_P;              /* log det of the FITC preconditioner (Sylvester) */
   double quad;                  /* y^T Sigma~_dagger^{-1} y */
@@ -235,6 +239,13 @@ fsa_status fsa_export_diag(fsa_ctx* ctx, double* D, double* logdet_P);
  * FSA_ERR_INVALID_ARG before the first solve. */
 fsa_status fsa_export_lanczos(fsa_ctx* ctx, int32_t* iters, double* alpha, double* beta, double* weight,
                               double* slq);
+
+/* Solution block U = Sigma~_dagger^{-1} [y, z_1 .. z_t] of the last
+ * likelihood solve (Section 3.1): host, n x (t+1) row-major, in the caller's
+ * point order (column 0: u = Sigma~^{-1} y).  With fsa_apply(FSA_OP_PROBES)
+ * it gives the residual b - Sigma~_dagger U of every column.
+ * FSA_ERR_INVALID_ARG before the first solve. */
+fsa_status fsa_export_solution(fsa_ctx* ctx, double* U);
 
 enum {
   FSA_OP_SIGMA_DAGGER = 0, /* Sigma~_dagger X */
@@ -343,14 +354,16 @@ fsa_status fsa_vecchia_apply_dev(fsa_vecchia* v, int32_t which, const double* X,
                                  double* Y, int64_t ldy);
 
 /* One block PCG run on Sigma_V + W^{-1} over [Sigma_V rhs, z_1 .. z_t]
- * (t = num_probes, 1..1023), each column stopped once ||r|| < tol ||b||:
+ * (t = num_probes, 1..1023), each column stopped once ||r|| < tol ||b||, or,
+ * with fixed_iter > 0 (<= 6000), every column run for exactly fixed_iter
+ * iterations (tol and max_iter then unused):
  * x (n) = (Sigma_V^{-1} + W)^{-1} rhs and *logdet (host) = the SLQ estimate
  * of log det(Sigma_V^{-1} + W).  stats (host, may be null).  NOT_CONVERGED
  * if max_iter (<= 6000) was reached (outputs are still written); BREAKDOWN
  * if h^T K h <= 0 or a non-finite value appeared. */
 fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, double* x, int32_t num_probes,
-                                        uint64_t seed, double tol, int32_t max_iter, double* logdet,
-                                        fsa_vecchia_stats* stats);
+                                        uint64_t seed, double tol, int32_t max_iter, int32_t fixed_iter,
+                                        double* logdet, fsa_vecchia_stats* stats);
 
 fsa_status fsa_vecchia_destroy(fsa_vecchia* v);
 

@@ -1080,10 +1080,13 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   for (it = 0; it < max_iter; ++it) {
     FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
     if (it == 0) FSA_TRY(enqueue_derivative(c));  // a derivative build marked before the solve
+    bool replaced = false;
     if constexpr (sizeof(T) == 4) {
-      if (c->opt.rr_period > 0 && (it + 1) % c->opt.rr_period == 0 && it + 1 < max_iter)
+      if (c->opt.rr_period > 0 && (it + 1) % c->opt.rr_period == 0 && it + 1 < max_iter) {
         FSA_TRY(pcg_replace_residual_f32(reinterpret_cast<PcgBlock<float>&>(b), op64,
                                          reinterpret_cast<const OpDesc<float>&>(op), c->B.p, c->scr, st));
+        replaced = true;
+      }
     }
     if (!fixed && (it + 1 == next_check || it + 1 == max_iter)) {
       HostStatus hs;
@@ -1091,8 +1094,29 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
       FSA_HIP(hipStreamSynchronize(st));
       if (hs.flags[1]) break;
       if (hs.flags[0] == 0) {
-        ++it;
-        break;
+        // Mixed precision: the float32 recurrence residual has drifted from
+        // b - Sigma~ u since the last float64 replacement, so the stop is
+        // confirmed on the float64 residual; columns still above the
+        // tolerance continue (same Krylov sequence, replaced residual).
+        bool done = true;
+        if constexpr (sizeof(T) == 4) {
+          auto& bf = reinterpret_cast<PcgBlock<float>&>(b);
+          if (!replaced)
+            FSA_TRY(pcg_replace_residual_f32(bf, op64, reinterpret_cast<const OpDesc<float>&>(op), c->B.p, c->scr,
+                                             st));
+          FSA_TRY(pcg_recheck_true_residual(bf, tol, c->scr, st));
+          FSA_TRY(stage_status(c, b.flags, b.rr, b.bn2, nullptr, tp, &hs));
+          FSA_HIP(hipStreamSynchronize(st));
+          done = hs.flags[0] == 0;
+        }
+        if (done) {
+          ++it;
+          break;
+        }
+        prev_res = -1.0;
+        prev_it = it + 1;
+        next_check = it + 2;
+        continue;
       }
       double worst = 0.0;
       for (int k = 0; k < tp; ++k)
@@ -1460,7 +1484,21 @@ static fsa_status run_sparse_pcg(fsa_ctx* c, const double* B, int ncols, int ld,
     if (!fixed && ((it + 1) % 4 == 0 || it + 1 == max_iter)) {
       FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
       FSA_HIP(hipStreamSynchronize(st));
-      if (flags[1] || flags[0] == 0) break;
+      if (flags[1]) break;
+      if (flags[0] == 0) {
+        // mixed precision: stop only on the float64 residual (as in run_pcg)
+        if constexpr (sizeof(T) == 4) {
+          auto& bf = reinterpret_cast<PcgBlock<float>&>(b);
+          if (!(c->opt.rr_period > 0 && (it + 1) % c->opt.rr_period == 0 && it + 1 < max_iter))
+            FSA_TRY(pcg_replace_residual_f32(bf, op64, reinterpret_cast<const OpDesc<float>&>(op), B, c->scr, st));
+          FSA_TRY(pcg_recheck_true_residual(bf, tol, c->scr, st));
+          FSA_HIP(hipMemcpyAsync(flags, b.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+          FSA_HIP(hipStreamSynchronize(st));
+          if (flags[0] == 0) break;
+        } else {
+          break;
+        }
+      }
     }
   }
   if constexpr (sizeof(T) == 4) FSA_TRY(pcg_fold_u(reinterpret_cast<PcgBlock<float>&>(b), st));
@@ -1739,6 +1777,21 @@ fsa_status fsa_export_lanczos(fsa_ctx* c, int32_t* iters, double* alpha, double*
   if (slq) FSA_HIP(hipMemcpyAsync(slq, c->results.p, tp * sizeof(double), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   if (slq) slq[0] = 0.0;
+  return FSA_OK;
+}
+
+fsa_status fsa_export_solution(fsa_ctx* c, double* U) {
+  if (!c || !U) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  PoolStream ps(c->st);
+  if (!c->solved) { set_error("no likelihood solve to export"); return FSA_ERR_INVALID_ARG; }
+  FSA_TRY(join_slq(c));
+  const int64_t n = c->n;
+  const int tp = c->tp;
+  Buf<double> tmp;
+  FSA_TRY(tmp.alloc((size_t)n * tp));
+  FSA_TRY(permute_rows(c->U.p, c->ld, tmp.p, tp, c->grid.iperm.p, n, tp, c->st));
+  FSA_HIP(hipMemcpyAsync(U, tmp.p, (size_t)n * tp * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  FSA_HIP(hipStreamSynchronize(c->st));
   return FSA_OK;
 }
 

@@ -823,6 +823,9 @@ __global__ void k_pcg_hupdate(int64_t n, int ncols, int64_t ld, const T* __restr
   if (p >= n) return;
   int64_t o = p * ld + c;
   const double b = beta[c], a = alpha[c];
+  // a frozen column (alpha 0) keeps its direction: if a float64 residual
+  // check reactivates it, its Krylov sequence continues where it stopped
+  if (a == 0.0) return;
   const double h = (double)H[o];
   const double t = has_lr ? (double)Tt[o] : 0.0;
   const double r = (double)R[o];
@@ -1176,6 +1179,40 @@ __global__ void k_fold_u(int64_t n, int ncols, int64_t ld, double* __restrict__ 
   int64_t o = p * ld + c;
   U[o] += (double)U32[o];
   U32[o] = 0.f;
+}
+
+// After a float64 residual replacement: rr_true[c] = |r_c|^2 of the replaced
+// residual; a column at or above the tolerance is active again (its
+// direction was kept while it was frozen), flags[0] = the active count.
+__global__ __launch_bounds__(256) void k_pcg_reactivate(int ncols, const double* __restrict__ rr_true,
+                                                        const double* __restrict__ bn2, double tol2, double* rr,
+                                                        int* active, int* flags) {
+  __shared__ int red[256];
+  int cnt = 0;
+  for (int c = threadIdx.x; c < ncols; c += 256) {
+    const double v = rr_true[c];
+    rr[c] = v;
+    const int a = (bn2[c] > 0.0 && !(v < tol2 * bn2[c])) ? 1 : 0;
+    active[c] = a;
+    cnt += a;
+  }
+  red[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) flags[0] = red[0];
+}
+
+fsa_status pcg_recheck_true_residual(PcgBlock<float>& b, double tol, Scratch& s, hipStream_t st) {
+  Buf<double> rrt;
+  FSA_TRY(rrt.alloc(b.ncols));
+  FSA_TRY((coldot<float, float>(b.R, b.R, b.n, b.ld, b.ncols, rrt.p, s, st)));
+  hipLaunchKernelGGL(k_pcg_reactivate, dim3(1), dim3(256), 0, st, b.ncols, rrt.p, b.bn2, tol * tol, b.rr, b.active,
+                     b.flags);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
 }
 
 fsa_status pcg_fold_u(PcgBlock<float>& b, hipStream_t st) {
@@ -1561,6 +1598,8 @@ template fsa_status spmm<float>(const Csr&, const Grid&, const Grid&, const floa
                                 bool, hipStream_t);
 template fsa_status coldot<double, double>(const double*, const double*, int64_t, int, int, double*, Scratch&,
                                            hipStream_t);
+template fsa_status coldot<float, float>(const float*, const float*, int64_t, int, int, double*, Scratch&,
+                                        hipStream_t);
 template fsa_status coldot<double, float>(const double*, const float*, int64_t, int, int, double*, Scratch&,
                                           hipStream_t);
 template fsa_status mspace_apply<double>(const double*, const double*, int, int, int, double*, int, hipStream_t);

@@ -192,6 +192,10 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
 // iteration are appended to alpha_hist/beta_hist.
 template <typename T>
 fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, Scratch& s, hipStream_t st);
+// Stopping test on the float64 residual (mixed precision), after R has just
+// been replaced by B - A_op U: rr = |R|^2 per column; the columns at or above
+// tol^2 |b|^2 become active again and flags[0] counts them.
+fsa_status pcg_recheck_true_residual(PcgBlock<float>& b, double tol, Scratch& s, hipStream_t st);
 // U += U32, U32 = 0 (no-op when U32 is null).
 fsa_status pcg_fold_u(PcgBlock<float>& b, hipStream_t st);
 // Replace R by B - A_op U with the float64 operator (mixed precision); folds

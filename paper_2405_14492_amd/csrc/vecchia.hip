@@ -499,7 +499,8 @@ __global__ void k_vpcg_update(int64_t n, int ncols, int64_t ld, const double* __
 // tol^2 |b|^2; flags[0] counts the active columns after the iteration
 __global__ void k_vpcg_beta(int ncols, const double* __restrict__ rzn, const double* __restrict__ rr,
                             const double* __restrict__ bn2, const double* __restrict__ alpha, double* rz, double* beta,
-                            int* active, int* iters, double* ah, double* bh, int max_iter, double tol2, int* flags) {
+                            int* active, int* iters, double* ah, double* bh, int max_iter, double tol2, int fixed,
+                            int* flags) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncols) return;
   double b = 0.0;
@@ -513,7 +514,7 @@ __global__ void k_vpcg_beta(int ncols, const double* __restrict__ rzn, const dou
     iters[c] = it + 1;
     rz[c] = rzn[c];
     if (!isfinite(rzn[c])) atomicOr(&flags[1], 1);
-    const int still = rr[c] < tol2 * bn2[c] ? 0 : 1;
+    const int still = (fixed || !(rr[c] < tol2 * bn2[c])) ? 1 : 0;
     active[c] = still;
     if (still) atomicAdd(&flags[0], 1);
   }
@@ -953,11 +954,14 @@ fsa_status fsa_vecchia_apply_dev(fsa_vecchia* v, int32_t which, const double* X,
 }
 
 fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, double* x, int32_t num_probes,
-                                        uint64_t seed, double tol, int32_t max_iter, double* logdet,
-                                        fsa_vecchia_stats* stats) {
+                                        uint64_t seed, double tol, int32_t max_iter, int32_t fixed_iter,
+                                        double* logdet, fsa_vecchia_stats* stats) {
   if (!v || !rhs || !x || !logdet) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
   if (num_probes < 1 || num_probes > 1023) { set_error("num_probes must be in [1, 1023]"); return FSA_ERR_INVALID_ARG; }
-  if (!(tol > 0.0) || !std::isfinite(tol)) { set_error("tol must be finite and positive"); return FSA_ERR_INVALID_ARG; }
+  if (fixed_iter < 0 || fixed_iter > 6000) { set_error("fixed_iter must be in [0, 6000]"); return FSA_ERR_INVALID_ARG; }
+  const int fixed = fixed_iter > 0 ? 1 : 0;
+  if (fixed) max_iter = fixed_iter;
+  if (!fixed && (!(tol > 0.0) || !std::isfinite(tol))) { set_error("tol must be finite and positive"); return FSA_ERR_INVALID_ARG; }
   if (max_iter < 1 || max_iter > 6000) { set_error("max_iter must be in [1, 6000]"); return FSA_ERR_INVALID_ARG; }
   PoolStream ps(v->st);
   hipStream_t st = v->st;
@@ -1040,16 +1044,17 @@ fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, doubl
     FSA_TRY((coldot<double, double>(R, R, n, (int)ld, ncols, c_rr, v->scr, st)));
     FSA_HIP(hipMemsetAsync(flags, 0, sizeof(int), st));
     hipLaunchKernelGGL(k_vpcg_beta, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_rzn, c_rr, c_bn2, c_alpha, c_rz,
-                       c_beta, active, iters, ah, bh, max_iter, tol2, flags);
+                       c_beta, active, iters, ah, bh, max_iter, tol2, fixed, flags);
     hipLaunchKernelGGL(k_vpcg_direction, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, ld, c_beta, Z, H);
     FSA_HIP(hipGetLastError());
+    if (fixed && it + 1 < max_iter) continue;  // breakdowns are read after the last iteration
     FSA_HIP(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     FSA_HIP(hipStreamSynchronize(st));
     if (hflags[1]) {
       set_error("CG breakdown in the Vecchia solve (h^T K h <= 0 or non-finite)");
       return FSA_ERR_BREAKDOWN;
     }
-    if (hflags[0] == 0) {
+    if (hflags[0] == 0 || fixed) {
       converged = true;
       ++it;
       break;

@@ -32,7 +32,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfsa.so")
 
 EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad", "fsa_grad", "fsa_predict_var",
             "fsa_destroy",
-            "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_export_lanczos", "fsa_apply",
+            "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_export_lanczos", "fsa_export_solution",
+            "fsa_apply",
             "fsa_pool_trim", "fsa_scores",
             "fsa_vecchia_build_dev", "fsa_vecchia_factor_dev", "fsa_vecchia_apply_dev", "fsa_vecchia_solve_logdet_dev",
             "fsa_vecchia_destroy"]
@@ -118,6 +119,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fsa_export_diag.restype = C.c_int
     lib.fsa_export_lanczos.argtypes = [vp, P(C.c_int32), dp, dp, dp, dp]
     lib.fsa_export_lanczos.restype = C.c_int
+    lib.fsa_export_solution.argtypes = [vp, dp]
+    lib.fsa_export_solution.restype = C.c_int
     lib.fsa_apply.argtypes = [vp, C.c_int32, dp, dp, C.c_int32]
     lib.fsa_apply.restype = C.c_int
     lib.fsa_pool_trim.argtypes = []
@@ -131,8 +134,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fsa_vecchia_factor_dev.restype = C.c_int
     lib.fsa_vecchia_apply_dev.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_int32, vp, C.c_int64]
     lib.fsa_vecchia_apply_dev.restype = C.c_int
-    lib.fsa_vecchia_solve_logdet_dev.argtypes = [vp, vp, vp, C.c_int32, C.c_uint64, C.c_double, C.c_int32, dp,
-                                                 P(fsa_vecchia_stats)]
+    lib.fsa_vecchia_solve_logdet_dev.argtypes = [vp, vp, vp, C.c_int32, C.c_uint64, C.c_double, C.c_int32,
+                                                 C.c_int32, dp, P(fsa_vecchia_stats)]
     lib.fsa_vecchia_solve_logdet_dev.restype = C.c_int
     lib.fsa_vecchia_destroy.argtypes = [vp]
     lib.fsa_vecchia_destroy.restype = C.c_int
@@ -284,6 +287,14 @@ def fsa_export_lanczos(ctx, ncols, max_iter):
     return {"iters": it, "alpha": a, "beta": b, "weight": w, "slq": q}
 
 
+def fsa_export_solution(ctx, n, ncols):
+    """Solution block Sigma~^{-1} [y, z_1 .. z_t] of the last likelihood solve
+    (n x ncols, caller's point order)."""
+    U = np.zeros((n, ncols))
+    _check(lib().fsa_export_solution(ctx, _dptr(U)))
+    return U
+
+
 def fsa_scores(y, mean, var):
     """(log-score, CRPS, RMSE) of Gaussian predictive distributions against
     test responses y (Section 4), computed on the device."""
@@ -349,6 +360,9 @@ class FSA:
         L = self.opt.fixed_iter if self.opt.fixed_iter > 0 else self.opt.max_iter
         return fsa_export_lanczos(self.ctx, self.opt.num_probes + 1, L)
 
+    def export_solution(self):
+        return fsa_export_solution(self.ctx, self.n, self.opt.num_probes + 1)
+
     def apply(self, which, X, ncols=None):
         return fsa_apply(self.ctx, which, X if which != OP_PROBES else self.n, ncols)
 
@@ -391,7 +405,9 @@ class Vecchia:
         for t in (self.locs, ind, wc):
             if t.dtype != torch.float64 or not t.is_cuda:
                 raise TypeError("Vecchia takes float64 device tensors")
-        st = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        st = self._stream.cuda_stream
+        self._stream.wait_stream(torch.cuda.current_stream())  # inputs written on the caller's stream
         h = C.c_void_p()
         _check(lib().fsa_vecchia_build_dev(self.locs.data_ptr(), self.n, ind.data_ptr(), ind.shape[0], int(kind),
                                            float(sigma1_sq), float(rho), self.mv, wc.data_ptr(), C.c_void_p(st),
@@ -424,19 +440,29 @@ class Vecchia:
         _check(lib().fsa_vecchia_factor_dev(self._h, nbr.data_ptr(), coef.data_ptr(), d.data_ptr()))
         return nbr[:, :self.mv], coef[:, :self.mv], d
 
+    def _order_after_caller(self):
+        # the library runs on the handle's stream; inputs (and the copies
+        # .contiguous() makes) come from torch's current stream
+        cur = self._torch.cuda.current_stream()
+        if cur != self._stream:
+            self._stream.wait_stream(cur)
+
     def apply(self, which, X):
         X2 = X.contiguous() if X.dim() == 2 else X.reshape(-1, 1).contiguous()
         Y = self._torch.empty_like(X2)
         k = X2.shape[1]
+        self._order_after_caller()
         _check(lib().fsa_vecchia_apply_dev(self._h, int(which), X2.data_ptr(), k, k, Y.data_ptr(), k))
         return Y if X.dim() == 2 else Y[:, 0]
 
-    def solve_logdet(self, rhs, num_probes, seed, tol=1e-8, max_iter=1000, allow_not_converged=False):
+    def solve_logdet(self, rhs, num_probes, seed, tol=1e-8, max_iter=1000, fixed_iter=0, allow_not_converged=False):
         r = rhs.contiguous()
         x = self._torch.empty_like(r)
         ld = C.c_double()
         st = fsa_vecchia_stats()
+        self._order_after_caller()
         _check(lib().fsa_vecchia_solve_logdet_dev(self._h, r.data_ptr(), x.data_ptr(), int(num_probes), int(seed),
-                                                  float(tol), int(max_iter), C.byref(ld), C.byref(st)),
+                                                  float(tol), int(max_iter), int(fixed_iter), C.byref(ld),
+                                                  C.byref(st)),
                allow_not_converged)
         return x, ld.value, st.as_dict()

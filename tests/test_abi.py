@@ -134,7 +134,7 @@ def test_vecchia_null_handle(L):
     buf = np.zeros(16)
     d = ctypes.c_double()
     assert L.fsa_vecchia_apply_dev(None, 0, buf.ctypes.data, 1, 1, buf.ctypes.data, 1) == 1
-    assert L.fsa_vecchia_solve_logdet_dev(None, buf.ctypes.data, buf.ctypes.data, 4, 0, 1e-6, 10, ctypes.byref(d),
-                                          None) == 1
+    assert L.fsa_vecchia_solve_logdet_dev(None, buf.ctypes.data, buf.ctypes.data, 4, 0, 1e-6, 10, 0,
+                                          ctypes.byref(d), None) == 1
     assert L.fsa_vecchia_factor_dev(None, None, None, None) == 1
     assert L.fsa_vecchia_destroy(None) == 0

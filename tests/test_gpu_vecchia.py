@@ -112,6 +112,30 @@ def test_solve_logdet_matches_oracle(n, mv, m, t, clustered):
     assert abs(logdet - o["logdet"]) < 1e-6 * abs(o["logdet"])
 
 
+@pytest.mark.parametrize("n,mv,m,t,k,clustered", [(3000, 10, 64, 8, 12, False), (1800, 30, 40, 5, 20, True),
+                                                   (257, 4, 16, 3, 7, False)])
+def test_solve_logdet_fixed_iterations_match_oracle(n, mv, m, t, k, clustered):
+    """With a fixed iteration count both sides run the same Krylov
+    sequence on the same probes, so the float64 results agree to the
+    method's 1e-9: the solution, the SLQ estimate of log det(Sigma_V +
+    W^{-1}) and the log det of Sigma_V^{-1} + W."""
+    locs, ind, w, th = _case(n, mv, m, seed=13, clustered=clustered)
+    vv = np.random.default_rng(4).standard_normal(n)
+    M = VO.Vecchia(locs, ind, th, mv, w)
+    o = VO.solve_logdet(M, vv, t, seed=23, fixed_iter=k)
+    with _gpu(locs, ind, w, th, mv) as v:
+        x, logdet, st = v.solve_logdet(_dev(vv), t, 23, fixed_iter=k)
+    x = x.cpu().numpy()
+    assert st["iters_rhs"] == k and st["iters_max"] == k and st["probe_iters"] == k * (t + 1)
+    xerr = np.abs(x - o["x"]).max() / np.abs(o["x"]).max()
+    swerr = abs(st["logdet_sw"] - o["logdet_sw"]) / abs(o["logdet_sw"])
+    lerr = abs(logdet - o["logdet"]) / abs(o["logdet"])
+    print("x", xerr, "logdet_sw", swerr, "logdet", lerr, flush=True)
+    assert xerr < 1e-9
+    assert swerr < 1e-9
+    assert lerr < 1e-9
+
+
 def _transformed_residual(v, fsa, x, w, vv):
     """The CG runs on (Sigma_V + W^{-1}) u = Sigma_V v with u = W x and
     stops on that residual; (Sigma_V^{-1} + W) x - v is Sigma_V^{-1} times

@@ -69,6 +69,21 @@ def test_wendland_taper_properties():
     assert np.linalg.eigvalsh(T).min() > -1e-10
 
 
+def test_wendland_taper_is_wendlands_phi31():
+    """The taper is Wendland's phi_{3,1}: his integral operator
+    (I f)(r) = int_r^1 t f(t) dt applied once to the truncated power
+    (1 - r)^3_+, normalised to 1 at r = 0, evaluated here by numerical
+    quadrature (independent of the closed form); and one interior value by
+    hand, W(1/2) = (1/2)^4 (1 + 2) = 3/16."""
+    from scipy.integrate import quad
+    gamma = 0.7
+    f0 = quad(lambda t: t * (1 - t) ** 3, 0.0, 1.0, epsabs=1e-15, epsrel=1e-14)[0]
+    for r in (0.0, 0.1, 0.25, 0.5, 0.8, 0.95):
+        ref = quad(lambda t: t * (1 - t) ** 3, r, 1.0, epsabs=1e-15, epsrel=1e-14)[0] / f0
+        assert abs(float(O.wendland_taper(r * gamma, gamma)) - ref) < 1e-12, r
+    assert abs(float(O.wendland_taper(0.5 * gamma, gamma)) - 3.0 / 16.0) < 1e-15
+
+
 # ---------------------------------------------------------------- pattern
 
 def test_pattern_equals_bruteforce_random():
