@@ -200,6 +200,14 @@ fsa_status fsa_build_dev(const double* locs_dev, int64_t n, int32_t d, const dou
  * DEVICE. */
 fsa_status fsa_nll_grad(fsa_ctx* ctx, const fsa_theta* theta, double* nll, double* grad, fsa_stats* st);
 
+/* The same with the outputs in device memory of the context's GPU: nll_dev
+ * (1 double) and, if not NULL, grad_dev (3 doubles, order (sigma1^2, rho,
+ * sigma^2)), both written by copies on the context's stream (no host round
+ * trip of the values).  Returns after the stream has drained; nll_dev is
+ * +inf on a BREAKDOWN or NOT_SPD failure.  Errors as fsa_nll_grad. */
+fsa_status fsa_nll_grad_dev(fsa_ctx* ctx, const fsa_theta* theta, double* nll_dev, double* grad_dev,
+                            fsa_stats* st);
+
 /* Gradient of the NLL of the preceding fsa_nll_grad call on this context
  * (eq. NEGLLDNEGLLFSA, trace by stochastic estimation with P^{-1} z,
  * Section 3.3), from the solves that call retained: the backward pass of the
@@ -273,6 +281,26 @@ fsa_status fsa_scores(const double* y, const double* mean, const double* var, in
  * cached pinned host block of the solvers' readbacks.  Blocks held by live
  * contexts are not affected. */
 void fsa_pool_trim(void);
+
+/* Device memory from the caller (the problem statement's inputs and outputs
+ * of Section 2 live in the caller's framework, e.g. torch's caching
+ * allocator).  After this call every device block the library needs comes
+ * from alloc(bytes, stream, user), where stream is the hipStream_t on which
+ * the block is first used (the context's stream, or its side stream); a
+ * null return is FSA_ERR_OOM.  Each block goes back through release(ptr,
+ * user) once every piece of work the library enqueued on it has completed
+ * (tracked by an event recorded at the library's release; the callback runs
+ * on a thread that calls into the library, without library locks held, at
+ * the latest in fsa_destroy of the owning context or fsa_pool_trim).  Blocks
+ * keep their origin: a block from the library's own pool goes back to the
+ * pool, a block from a callback pair to that pair, whatever is registered
+ * later; the callbacks must stay valid until every block they handed out has
+ * been released.  Both NULL: back to the library's own pool (hipMalloc,
+ * cached).  The registration is process-wide; contexts in flight may mix
+ * blocks of both origins.  INVALID_ARG if exactly one callback is NULL. */
+typedef void* (*fsa_alloc_fn)(size_t bytes, void* hip_stream, void* user);
+typedef void (*fsa_release_fn)(void* ptr, void* user);
+fsa_status fsa_set_allocator(fsa_alloc_fn alloc, fsa_release_fn release, void* user);
 
 /* ------------------------------------------------------------------------
  * The FITC preconditioner in iterative methods for Vecchia approximations

@@ -130,11 +130,17 @@ const char* get_error();
 // reused by the next allocation of the same rounded size, so rebuilding a
 // context of the same shape performs no hipMalloc.  A release records an
 // event on the calling thread's current stream (set by PoolStream at each
-// entry point); an allocation from another stream makes that stream wait
-// for the event, so a block is never handed to new work while earlier work
-// that used it can still run.
+// entry point, and around work enqueued on a side stream); an allocation
+// from another stream makes that stream wait for the event, so a block is
+// never handed to new work while earlier work that used it can still run.
+// With a caller's allocator registered (fsa_set_allocator), blocks come from
+// it for the current stream and go back to it once the release event has
+// passed.
 void* pool_alloc(size_t bytes);
 void pool_free(void* p);
+// hand every released block of a registered allocator back to it, waiting
+// for the work that used it
+void pool_flush();
 hipStream_t pool_stream();
 void pool_set_stream(hipStream_t st);
 struct PoolStream {  // scope guard: the current stream of this thread

@@ -32,10 +32,29 @@ struct FreeBlock {
   hipStream_t st;  // stream current when the block was released
   hipEvent_t ev;   // recorded on st at the release
 };
+// A block from the caller's allocator (fsa_set_allocator) and where it goes back.
+struct UserAlloc {
+  fsa_alloc_fn alloc = nullptr;
+  fsa_release_fn release = nullptr;
+  void* user = nullptr;
+};
+struct LiveBlock {
+  size_t bytes;
+  UserAlloc from;  // from.release == nullptr: the library's own pool
+};
+// A released block of the caller's allocator, handed back once the event
+// recorded at its release (after every use the library enqueued) has passed.
+struct Pending {
+  void* p;
+  hipEvent_t ev;
+  UserAlloc to;
+};
 std::mutex g_pool_mu;
 std::multimap<size_t, FreeBlock> g_free;  // rounded size -> block
-std::map<void*, size_t> g_live;           // block -> rounded size
+std::map<void*, LiveBlock> g_live;        // block -> rounded size and origin
 std::vector<hipEvent_t> g_events;         // idle events
+std::vector<Pending> g_pending;
+UserAlloc g_user;                         // the registered allocator (alloc == nullptr: none)
 thread_local hipStream_t t_stream = nullptr;
 size_t pool_round(size_t b) {
   const size_t g = b < (1u << 20) ? 4096 : (size_t(2) << 20);
@@ -50,6 +69,47 @@ void release_cached_locked() {
   }
   g_free.clear();
 }
+hipEvent_t event_get_locked() {
+  if (!g_events.empty()) {
+    hipEvent_t e = g_events.back();
+    g_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+// Hand the caller's blocks whose last use has completed back to their
+// allocator (all of them, waiting, with wait = true).  The callbacks run
+// without the pool lock held.
+void flush_pending(bool wait) {
+  std::vector<Pending> ready;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (size_t i = 0; i < g_pending.size();) {
+      Pending& q = g_pending[i];
+      bool done = true;
+      if (q.ev) {
+        if (wait) (void)hipEventSynchronize(q.ev);
+        const hipError_t e = hipEventQuery(q.ev);
+        done = e == hipSuccess;
+        if (e != hipSuccess && e != hipErrorNotReady) (void)hipGetLastError();
+      }
+      if (done) {
+        if (q.ev) g_events.push_back(q.ev);
+        ready.push_back(q);
+        g_pending[i] = g_pending.back();
+        g_pending.pop_back();
+      } else {
+        ++i;
+      }
+    }
+  }
+  for (auto& q : ready) q.to.release(q.p, q.to.user);
+}
 }  // namespace
 
 hipStream_t pool_stream() { return t_stream; }
@@ -57,6 +117,19 @@ void pool_set_stream(hipStream_t st) { t_stream = st; }
 
 void* pool_alloc(size_t bytes) {
   size_t r = pool_round(bytes);
+  UserAlloc ua;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    ua = g_user;
+  }
+  if (ua.alloc) {
+    flush_pending(false);
+    void* p = ua.alloc(r, reinterpret_cast<void*>(t_stream), ua.user);
+    if (!p) return nullptr;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_live[p] = LiveBlock{r, ua};
+    return p;
+  }
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     auto it = g_free.find(r);
@@ -65,7 +138,7 @@ void* pool_alloc(size_t bytes) {
       g_free.erase(it);
       if (fb.st != t_stream) (void)hipStreamWaitEvent(t_stream, fb.ev, 0);
       g_events.push_back(fb.ev);
-      g_live[fb.p] = r;
+      g_live[fb.p] = LiveBlock{r, UserAlloc{}};
       return fb.p;
     }
   }
@@ -81,35 +154,41 @@ void* pool_alloc(size_t bytes) {
     }
   }
   std::lock_guard<std::mutex> lk(g_pool_mu);
-  g_live[p] = r;
+  g_live[p] = LiveBlock{r, UserAlloc{}};
   return p;
 }
 
 void pool_free(void* p) {
   if (!p) return;
-  std::lock_guard<std::mutex> lk(g_pool_mu);
-  auto it = g_live.find(p);
-  if (it == g_live.end()) return;
-  hipEvent_t ev = nullptr;
-  if (!g_events.empty()) {
-    ev = g_events.back();
-    g_events.pop_back();
-  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    // no event: make the block safe to reuse anywhere by draining its stream
-    (void)hipStreamSynchronize(t_stream);
-    ev = nullptr;
+  bool user = false;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;
+    const LiveBlock lb = it->second;
+    g_live.erase(it);
+    hipEvent_t ev = event_get_locked();
+    if (ev) (void)hipEventRecord(ev, t_stream);
+    if (lb.from.release) {
+      // the caller's block: back to its allocator once this event has passed
+      if (!ev) (void)hipStreamSynchronize(t_stream);
+      g_pending.push_back(Pending{p, ev, lb.from});
+      user = true;
+    } else if (ev) {
+      g_free.emplace(lb.bytes, FreeBlock{p, t_stream, ev});
+    } else {
+      // no event: make the block safe to reuse anywhere by draining its stream
+      (void)hipStreamSynchronize(t_stream);
+      (void)hipFree(p);
+    }
   }
-  if (ev) (void)hipEventRecord(ev, t_stream);
-  if (ev) {
-    g_free.emplace(it->second, FreeBlock{p, t_stream, ev});
-  } else {
-    (void)hipFree(p);
-  }
-  g_live.erase(it);
+  if (user) flush_pending(false);
 }
 
+void pool_flush() { flush_pending(true); }
+
 void pool_trim() {
+  flush_pending(true);
   std::lock_guard<std::mutex> lk(g_pool_mu);
   release_cached_locked();
 }
@@ -864,6 +943,16 @@ fsa_status fsa_scores(const double* y, const double* mean, const double* var, in
   return FSA_OK;
 }
 
+fsa_status fsa_set_allocator(fsa_alloc_fn alloc, fsa_release_fn release, void* user) {
+  if ((alloc == nullptr) != (release == nullptr)) {
+    set_error("fsa_set_allocator needs both callbacks or neither");
+    return FSA_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_user = UserAlloc{alloc, release, user};
+  return FSA_OK;
+}
+
 void fsa_pool_trim(void) {
   pool_trim();
   blas_trim();
@@ -922,6 +1011,7 @@ void fsa_destroy(fsa_ctx* c) {
   pinned_put(c->hstage, c->hstage_bytes);
   blas_release(c->blas);
   delete c;  // Buf members return their blocks to the pool
+  pool_flush();  // and blocks of a registered allocator go back to it now
 }
 
 int64_t fsa_nnz(const fsa_ctx* c) { return c ? c->csr.nnz : -1; }
@@ -1313,7 +1403,13 @@ static fsa_status enqueue_derivative(fsa_ctx* c) {
   FSA_TRY(side_stream(c));
   FSA_HIP(hipEventRecord(c->ev_ready, c->st));
   FSA_HIP(hipStreamWaitEvent(c->st2, c->ev_ready, 0));
-  FSA_TRY(build_derivative(c, c->st2));
+  {
+    // blocks the derivative build takes or gives back are used on st2: the
+    // pool's waits and release events belong there (st2 is behind st's work
+    // at ev_ready, so st's earlier uses are covered)
+    PoolStream ps(c->st2);
+    FSA_TRY(build_derivative(c, c->st2));
+  }
   FSA_HIP(hipEventRecord(c->ev_deriv, c->st2));
   c->deriv_state = 1;
   return FSA_OK;
@@ -1339,7 +1435,7 @@ static void collect_timer(fsa_ctx* c) {
   c->timer_pending = false;
 }
 
-static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
+static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6, double* grad_dev = nullptr) {
   hipStream_t st = c->st;
   const int64_t n = c->n;
   const int tp = c->tp, ld = c->ld;
@@ -1393,6 +1489,7 @@ static fsa_status run_gradient(fsa_ctx* c, double* grad, double* parts6) {
                        c->th.s2, cv, res);
   }
   FSA_HIP(hipGetLastError());
+  if (grad_dev) FSA_HIP(hipMemcpyAsync(grad_dev, res, 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
   collect_timer(c);  // host work while the gradient kernels run
   double g9[15];
   FSA_HIP(hipMemcpyAsync(g9, res, (cv == FSA_CV_NONE ? 9 : 15) * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1661,10 +1758,12 @@ static fsa_status predict_core(fsa_ctx* c, const double* pred_locs_h, int64_t n_
   return ps;
 }
 
-extern "C" {
-
-fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double* grad, fsa_stats* st_out) {
-  if (!c || !nll) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+// The likelihood call behind fsa_nll_grad and fsa_nll_grad_dev: host
+// outputs (nll, grad) and/or device outputs (nll_dev, grad_dev), each may be
+// null except one of nll / nll_dev; a gradient is computed if grad or
+// grad_dev is given.
+static fsa_status nll_grad_core(fsa_ctx* c, const fsa_theta* theta, double* nll, double* grad, double* nll_dev,
+                                double* grad_dev, fsa_stats* st_out) {
   PoolStream ps(c->st);
   double t0 = now_ms();
   hipStream_t st = c->st;
@@ -1678,7 +1777,8 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
     }
   }
   double t_build = now_ms();
-  if (grad && c->deriv_state == 0) mark_derivative(c);
+  const bool want_grad = grad || grad_dev;
+  if (want_grad && c->deriv_state == 0) mark_derivative(c);
   double ms_pcg = 0;
   fsa_status s;
   if (c->opt.precision != FSA_FP64) s = run_pcg<float>(c, &ms_pcg);
@@ -1687,13 +1787,19 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
   if (s != FSA_OK && s != FSA_ERR_NOT_CONVERGED) {
     FSA_TRY(join_slq(c));
     collect_timer(c);
-    *nll = INFINITY;
+    if (nll) *nll = INFINITY;
+    if (nll_dev) {
+      const double inf = INFINITY;
+      FSA_HIP(hipMemcpyAsync(nll_dev, &inf, sizeof(double), hipMemcpyHostToDevice, st));
+      FSA_HIP(hipStreamSynchronize(st));
+    }
     return s;
   }
   double t_b0 = now_ms();
-  if (grad) {
+  if (want_grad) {
     double parts6[6];
-    fsa_status gs = run_gradient(c, grad, parts6);
+    double gh[3];
+    fsa_status gs = run_gradient(c, grad ? grad : gh, parts6, grad_dev);
     if (gs != FSA_OK) {
       FSA_TRY(join_slq(c));
       return gs;
@@ -1706,9 +1812,11 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
   // the likelihood from the side stream (the quadrature ran beside the gradient)
   FSA_TRY(join_slq(c));
   double fin[3];
+  if (nll_dev)
+    FSA_HIP(hipMemcpyAsync(nll_dev, c->results.p + 2 * c->ldw + 2, sizeof(double), hipMemcpyDeviceToDevice, st));
   FSA_HIP(hipMemcpyAsync(fin, c->results.p + 2 * c->ldw, sizeof(fin), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
-  *nll = fin[2];
+  if (nll) *nll = fin[2];
   collect_timer(c);
   double t1 = now_ms();
   c->stats.logdet = fin[0];
@@ -1716,11 +1824,24 @@ fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double*
   c->stats.logdet_P = c->last_logdet_P;
   c->stats.ms_build = t_build - t0;
   c->stats.ms_pcg = ms_pcg;
-  c->stats.ms_backward = grad ? t1 - t_b0 : 0.0;
+  c->stats.ms_backward = want_grad ? t1 - t_b0 : 0.0;
   c->stats.ms_total = t1 - t0;
   c->stats.nnz = c->csr.nnz;
   if (st_out) *st_out = c->stats;
   return s;
+}
+
+extern "C" {
+
+fsa_status fsa_nll_grad(fsa_ctx* c, const fsa_theta* theta, double* nll, double* grad, fsa_stats* st_out) {
+  if (!c || !nll) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  return nll_grad_core(c, theta, nll, grad, nullptr, nullptr, st_out);
+}
+
+fsa_status fsa_nll_grad_dev(fsa_ctx* c, const fsa_theta* theta, double* nll_dev, double* grad_dev,
+                            fsa_stats* st_out) {
+  if (!c || !nll_dev) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  return nll_grad_core(c, theta, nullptr, nullptr, nll_dev, grad_dev, st_out);
 }
 
 fsa_status fsa_grad(fsa_ctx* c, double* grad, fsa_stats* st_out) {

@@ -34,7 +34,7 @@ EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad",
             "fsa_destroy",
             "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_export_lanczos", "fsa_export_solution",
             "fsa_apply",
-            "fsa_pool_trim", "fsa_scores",
+            "fsa_pool_trim", "fsa_scores", "fsa_set_allocator", "fsa_nll_grad_dev",
             "fsa_vecchia_build_dev", "fsa_vecchia_factor_dev", "fsa_vecchia_apply_dev", "fsa_vecchia_solve_logdet_dev",
             "fsa_vecchia_destroy"]
 
@@ -87,6 +87,11 @@ class fsa_vecchia_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+# fsa_set_allocator callbacks: alloc(bytes, hip_stream, user) -> device pointer, release(ptr, user)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2405_14492_amd.build`")
@@ -103,6 +108,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         f.restype = C.c_int
     lib.fsa_nll_grad.argtypes = [vp, P(fsa_theta), dp, dp, P(fsa_stats)]
     lib.fsa_nll_grad.restype = C.c_int
+    lib.fsa_nll_grad_dev.argtypes = [vp, P(fsa_theta), vp, vp, P(fsa_stats)]
+    lib.fsa_nll_grad_dev.restype = C.c_int
+    lib.fsa_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, vp]
+    lib.fsa_set_allocator.restype = C.c_int
     lib.fsa_grad.argtypes = [vp, dp, P(fsa_stats)]
     lib.fsa_grad.restype = C.c_int
     lib.fsa_predict_var.argtypes = [vp, dp, C.c_int64, C.c_int32, dp, dp, P(fsa_stats)]
@@ -229,6 +238,70 @@ def fsa_nll_grad(ctx, theta=None, with_grad=True, allow_not_converged=False):
     return nll.value, (g if with_grad else None), st.as_dict()
 
 
+def fsa_nll_grad_dev(ctx, nll_out, grad_out=None, theta=None, allow_not_converged=False):
+    """Device outputs: nll_out (1 float64 element) and grad_out (3, or None)
+    are torch CUDA tensors written by the library on the context's stream."""
+    st = fsa_stats()
+    th = make_theta(theta) if theta is not None else None
+    s = lib().fsa_nll_grad_dev(ctx, C.byref(th) if th is not None else None, nll_out.data_ptr(),
+                               grad_out.data_ptr() if grad_out is not None else None, C.byref(st))
+    _check(s, allow_not_converged)
+    return st.as_dict()
+
+
+_ALLOCATOR = None  # the registered callbacks (kept alive while registered)
+
+
+def fsa_set_allocator(allocator=None):
+    """Register an object with alloc(nbytes, stream) -> int and
+    release(ptr) (e.g. TorchAllocator) as the library's source of device
+    memory, or None for the library's own pool.  The previous object is
+    kept referenced by its blocks' release path until they are returned."""
+    global _ALLOCATOR
+    if allocator is None:
+        _check(lib().fsa_set_allocator(ALLOC_FN(), RELEASE_FN(), None))
+        _ALLOCATOR = None
+        return
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return allocator.alloc(int(nbytes), int(stream or 0)) or None
+        except Exception:  # an allocation failure is the library's OOM
+            return None
+
+    def _release(ptr, user):
+        allocator.release(int(ptr))
+
+    cbs = (ALLOC_FN(_alloc), RELEASE_FN(_release), allocator)
+    _check(lib().fsa_set_allocator(cbs[0], cbs[1], None))
+    allocator._fsa_callbacks = cbs  # must outlive every block handed out
+    _ALLOCATOR = cbs
+
+
+class TorchAllocator:
+    """Device memory for the library from torch's caching allocator, on the
+    stream the library names; counts what it hands out and gets back."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.live = {}
+        self.allocs = 0
+        self.releases = 0
+
+    def alloc(self, nbytes, stream):
+        torch = self._torch
+        p = torch.cuda.caching_allocator_alloc(nbytes, torch.cuda.current_device(), stream)
+        self.live[p] = nbytes
+        self.allocs += 1
+        return p
+
+    def release(self, ptr):
+        self.live.pop(ptr)
+        self.releases += 1
+        self._torch.cuda.caching_allocator_delete(ptr)
+
+
 def fsa_grad(ctx):
     g = np.zeros(3)
     st = fsa_stats()
@@ -343,6 +416,12 @@ class FSA:
         if theta is not None:
             self.theta = tuple(theta)
         return out
+
+    def nll_grad_dev(self, nll_out, grad_out=None, theta=None, allow_not_converged=False):
+        st = fsa_nll_grad_dev(self.ctx, nll_out, grad_out, theta, allow_not_converged)
+        if theta is not None:
+            self.theta = tuple(theta)
+        return st
 
     def grad(self):
         return fsa_grad(self.ctx)

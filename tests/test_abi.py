@@ -138,3 +138,17 @@ def test_vecchia_null_handle(L):
                                           ctypes.byref(d), None) == 1
     assert L.fsa_vecchia_factor_dev(None, None, None, None) == 1
     assert L.fsa_vecchia_destroy(None) == 0
+
+
+def test_set_allocator_validates_on_host(L):
+    """Both callbacks or neither; neither restores the library's own pool.
+    No device memory is touched."""
+    from paper_2405_14492_amd import fsa
+    alloc = fsa.ALLOC_FN(lambda nbytes, stream, user: None)
+    assert L.fsa_set_allocator(alloc, fsa.RELEASE_FN(), None) == 1
+    assert len(L.fsa_last_error()) > 0
+    assert L.fsa_set_allocator(fsa.ALLOC_FN(), fsa.RELEASE_FN(), None) == 0
+
+
+def test_nll_grad_dev_rejects_null_handle(L):
+    assert L.fsa_nll_grad_dev(None, None, None, None, None) == 1
