@@ -277,6 +277,18 @@ fsa_status fsa_apply(fsa_ctx* ctx, int32_t which, const double* X, double* Y, in
  * variance. */
 fsa_status fsa_scores(const double* y, const double* mean, const double* var, int64_t n, double* out);
 
+/* fsa_scores without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels, default stream and results
+ * as fsa_scores; inputs are staged in a fixed library-owned device array of
+ * 6.32 MB per GPU, held from the first call on that GPU until the process
+ * ends, so n is limited to 262,144 points (INVALID_ARG beyond, with a
+ * message).  All calls on one GPU share that array: they are serialized by
+ * a lock inside the library, each returns after the default stream has
+ * drained, and the array keeps the last call's contents (the counter of bad
+ * variances is cleared by a kernel at every call). */
+fsa_status fsa_scores_noalloc(const double* y, const double* mean, const double* var, int64_t n, double* out);
+
 /* Release every cached device block of the process-wide pool and every
  * cached pinned host block of the solvers' readbacks.  Blocks held by live
  * contexts are not affected. */

@@ -943,6 +943,80 @@ fsa_status fsa_scores(const double* y, const double* mean, const double* var, in
   return FSA_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- scores without allocation
+// fsa_scores_noalloc stages its inputs, its per-workgroup partials, its
+// result and its counter in one file-scope device array.  In host code the
+// array's name is only a host-side stand-in: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is ever passed to kernels or copies.
+namespace {
+constexpr int64_t kScoresNoallocMaxN = int64_t(1) << 18;  // 262,144 points
+constexpr int kScoresMaxGroups = 1024;                      // grid cap of k_score_parts
+constexpr size_t kScoresPartOff = 3 * (size_t)kScoresNoallocMaxN;
+constexpr size_t kScoresOutOff = kScoresPartOff + 3 * (size_t)kScoresMaxGroups;
+constexpr size_t kScoresBadOff = kScoresOutOff + 4;          // an int in the slot of one double
+constexpr size_t kScoresScratchDoubles = kScoresBadOff + 4;  // 6.32 MB in all
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScoresScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu[kMaxDevices];  // one call at a time per device: the array is shared
+double* g_scratch_ptr[kMaxDevices] = {};
+
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+}  // namespace
+
+extern "C" {
+
+fsa_status fsa_scores_noalloc(const double* y, const double* mean, const double* var, int64_t n, double* out) {
+  if (!y || !mean || !var || !out) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (n < 1) { set_error("n must be >= 1"); return FSA_ERR_INVALID_ARG; }
+  if (n > kScoresNoallocMaxN) {
+    set_error("fsa_scores_noalloc: n = %lld exceeds its fixed scratch of %lld points (use fsa_scores)",
+              (long long)n, (long long)kScoresNoallocMaxN);
+    return FSA_ERR_INVALID_ARG;
+  }
+  int dev = 0;
+  FSA_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) { set_error("device %d out of range", dev); return FSA_ERR_INVALID_ARG; }
+  std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    FSA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  double* base = g_scratch_ptr[dev];
+  double* dy = base;
+  double* dmu = base + n;
+  double* dvar = base + 2 * n;
+  double* part = base + kScoresPartOff;
+  double* res_d = base + kScoresOutOff;
+  int* bad = reinterpret_cast<int*>(base + kScoresBadOff);
+  hipStream_t st = nullptr;  // the default stream, as fsa_scores
+  const int G = (int)std::min<int64_t>(ceil_div(n, 256), kScoresMaxGroups);
+  FSA_HIP(hipMemcpyAsync(dy, y, n * sizeof(double), hipMemcpyHostToDevice, st));
+  FSA_HIP(hipMemcpyAsync(dmu, mean, n * sizeof(double), hipMemcpyHostToDevice, st));
+  FSA_HIP(hipMemcpyAsync(dvar, var, n * sizeof(double), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, bad);  // the counter keeps the last call's value
+  hipLaunchKernelGGL(k_score_parts, dim3(G), dim3(256), 0, st, dy, dmu, dvar, n, part, bad);
+  hipLaunchKernelGGL(k_score_final, dim3(1), dim3(64), 0, st, part, G, n, res_d);
+  FSA_HIP(hipGetLastError());
+  double res[3];
+  int hb = 0;
+  FSA_HIP(hipMemcpyAsync(res, res_d, sizeof(res), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (hb) { set_error("%d predictive variances are not finite and positive", hb); return FSA_ERR_INVALID_ARG; }
+  for (int j = 0; j < 3; ++j) out[j] = res[j];
+  return FSA_OK;
+}
+
 fsa_status fsa_set_allocator(fsa_alloc_fn alloc, fsa_release_fn release, void* user) {
   if ((alloc == nullptr) != (release == nullptr)) {
     set_error("fsa_set_allocator needs both callbacks or neither");

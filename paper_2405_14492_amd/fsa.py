@@ -34,7 +34,7 @@ EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad",
             "fsa_destroy",
             "fsa_last_error", "fsa_nnz", "fsa_export_csr", "fsa_export_diag", "fsa_export_lanczos", "fsa_export_solution",
             "fsa_apply",
-            "fsa_pool_trim", "fsa_scores", "fsa_set_allocator", "fsa_nll_grad_dev",
+            "fsa_pool_trim", "fsa_scores", "fsa_scores_noalloc", "fsa_set_allocator", "fsa_nll_grad_dev",
             "fsa_vecchia_build_dev", "fsa_vecchia_factor_dev", "fsa_vecchia_apply_dev", "fsa_vecchia_solve_logdet_dev",
             "fsa_vecchia_destroy"]
 
@@ -136,6 +136,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fsa_pool_trim.restype = None
     lib.fsa_scores.argtypes = [dp, dp, dp, C.c_int64, dp]
     lib.fsa_scores.restype = C.c_int
+    lib.fsa_scores_noalloc.argtypes = [dp, dp, dp, C.c_int64, dp]
+    lib.fsa_scores_noalloc.restype = C.c_int
     lib.fsa_vecchia_build_dev.argtypes = [vp, C.c_int64, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                           vp, vp, P(vp)]
     lib.fsa_vecchia_build_dev.restype = C.c_int
@@ -376,6 +378,20 @@ def fsa_scores(y, mean, var):
         raise ValueError("y, mean and var must have the same length")
     out = np.zeros(3)
     _check(lib().fsa_scores(_dptr(y), _dptr(mean), _dptr(var), y.shape[0], _dptr(out)))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+SCORES_NOALLOC_MAX_N = 1 << 18  # the fixed device scratch of fsa_scores_noalloc
+
+
+def fsa_scores_noalloc(y, mean, var):
+    """fsa_scores through the entry point that allocates no device memory
+    (fixed library scratch; n <= SCORES_NOALLOC_MAX_N)."""
+    y, mean, var = _f64(y).ravel(), _f64(mean).ravel(), _f64(var).ravel()
+    if not (y.shape == mean.shape == var.shape):
+        raise ValueError("y, mean and var must have the same length")
+    out = np.zeros(3)
+    _check(lib().fsa_scores_noalloc(_dptr(y), _dptr(mean), _dptr(var), y.shape[0], _dptr(out)))
     return float(out[0]), float(out[1]), float(out[2])
 
 
