@@ -273,6 +273,78 @@ def run_vecchia(F, torch, n, mv, m, t, steps, warmup, seed=0, cpu_sample_n=0):
     return out
 
 
+def run_serving(F, torch, n_requests, rate, slots, budget_gib, warm=8):
+    """The serving stream: `n_requests` likelihood + gradient (70%) and
+    predictive-variance (30%) requests with Poisson arrivals at `rate` per
+    second, n log-uniform in [5k, 300k], m in {100, 200, 500}, t = 20, through
+    the library's server (mixed precision, `slots` workers, admission against
+    `budget_gib` GiB), and the same trace through a one-at-a-time float64
+    server (one worker).  solves/s = completed requests / (last completion -
+    first arrival); latency = completion - arrival."""
+    from workloads import configs
+    from workloads import generators as G
+    trace = configs.serving_trace(n_requests, rate)
+    t0 = time.perf_counter()
+    resp = G.rff_response_torch(torch)
+    arrays = [r.materialize(256, response=resp) for r in trace]
+    log(f"serving inputs ready in {time.perf_counter() - t0:.1f} s ({n_requests} requests)")
+
+    def submit(srv, r, a, at):
+        locs, y, ind, pred = a
+        kind = F.REQ_NLL_GRAD if r.kind == "nll_grad" else F.REQ_PREDICT_VAR
+        return srv.submit(kind, locs, y, r.theta, ind, r.gamma, pred, r.num_samples, arrival_ms=at)
+
+    def one(label, precision, nslots, tol, graph, paced=True):
+        opts = dict(num_probes=20, seed=4005, tol=tol, max_iter=2000, precision=precision, rr_period=10, graph=graph)
+        with F.Server(slots=nslots, hbm_budget=int(budget_gib * (1 << 30)), **opts) as srv:
+            for r, a in zip(trace[:warm], arrays[:warm]):  # code objects, library handles, pinned blocks
+                srv.wait(submit(srv, r, a, 0.0))
+            start = srv.clock_ms() + 100.0
+            ids = [submit(srv, r, a, start + (1000.0 * r.arrival_s if paced else 0.0)) for r, a in zip(trace, arrays)]
+            res = []
+            for k, i in enumerate(ids):
+                res.append(srv.wait(i)[0])
+                if (k + 1) % 128 == 0:
+                    log(f"serving {label}: {k + 1}/{len(ids)} done")
+            st = srv.stats()
+        bad = [x for x in res if x["status"] not in (0, 4)]
+        lat = np.array([x["done_ms"] - x["arrival_ms"] for x in res])
+        kinds = np.array([r.kind for r in trace])
+        span = max(x["done_ms"] for x in res) - min(x["arrival_ms"] for x in res)
+        out = {"slots": nslots, "precision": label, "tol": tol, "graph": bool(graph),
+               "arrivals": "poisson" if paced else "all at once (capacity)",
+               "completed": len(res) - len(bad), "failed": len(bad),
+               "solves_per_s": (len(res) - len(bad)) / (span / 1000.0), "makespan_s": span / 1000.0,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+               "p50_ms_nll_grad": float(np.percentile(lat[kinds == "nll_grad"], 50)),
+               "p50_ms_predict_var": float(np.percentile(lat[kinds == "predict_var"], 50)),
+               "peak_active": st["peak_active"], "peak_reserved_GiB": st["peak_reserved"] / 2 ** 30,
+               "budget_GiB": st["hbm_budget"] / 2 ** 30,
+               "probe_iters": int(sum(x["probe_iters"] for x in res)),
+               "max_peak_over_footprint": max(x["peak_bytes"] / x["footprint"] for x in res)}
+        if bad:
+            out["first_error"] = bad[0]["message"]
+            for x in bad[:8]:
+                r = trace[ids.index(x["id"])]
+                log(f"  failed: {r.kind} n={r.n} m={r.m} footprint {x['footprint']} peak {x['peak_bytes']}: "
+                    f"{x['message']}")
+        log(f"serving {label}: {out['solves_per_s']:.1f} solves/s, p50 {out['p50_ms']:.1f} ms, "
+            f"p99 {out['p99_ms']:.1f} ms, peak active {out['peak_active']}, failed {len(bad)}")
+        return out
+
+    mixed = one("mixed_fp32", F.MIXED_FP32, slots, 1e-6, True)
+    base = one("fp64_one_at_a_time", F.FP64, 1, 1e-6, False)
+    cap = one("mixed_fp32", F.MIXED_FP32, slots, 1e-6, True, paced=False)
+    return {"workload": f"serving stream: {n_requests} requests, Poisson {rate:g}/s, n log-uniform [5000, 300000], "
+                        f"m in {{100, 200, 500}}, exponential or matern32, t=20, 70% nll+grad / 30% predict_var "
+                        f"(n_p=n/4, s=20), tol=1e-6, budget {budget_gib:g} GiB",
+            "metric": "serving solves/s and p50/p99 latency (ms)",
+            "mixed": mixed, "fp64_one_at_a_time": base, "mixed_capacity": cap,
+            "solves_per_s_ratio": mixed["solves_per_s"] / base["solves_per_s"],
+            "p99_ratio": base["p99_ms"] / mixed["p99_ms"]}
+
+
 def cpu_baseline(w, sample_n, iters):
     """The oracle on a spatial window of the same workload (same density,
     taper range, covariance and all m inducing points), `iters` PCG
@@ -323,6 +395,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-vecchia", action="store_true", help="skip the Vecchia (Section 5) leg")
     ap.add_argument("--vecchia-only", action="store_true", help="run only the Vecchia (Section 5) leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving-stream leg")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for hardware-counter scaling)")
     args = ap.parse_args()
@@ -341,6 +419,10 @@ def main():
         log("vecchia leg")
         print(json.dumps({"vecchia": run_vecchia(F, torch, 100_000, 30, 200, args.probes, args.steps, args.warmup)}),
               flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": run_serving(F, torch, args.serve_requests, args.serve_rate, args.serve_slots,
+                                                 args.serve_budget_gib)}), flush=True)
         return
     log(f"generating inputs n={args.n} m={args.m} t={args.probes}")
     t0 = time.perf_counter()
@@ -405,6 +487,10 @@ def main():
                                      cpu_sample_n=0 if args.no_cpu_baseline else 15_000)
         log(f"vecchia: {out['vecchia']['value']:.1f} probe-iters/s, {out['vecchia']['ms_per_step']:.2f} ms/step, "
             f"{out['vecchia']['nlevels']} levels")
+    if not args.no_serving:
+        log("serving leg")
+        out["serving"] = run_serving(F, torch, args.serve_requests, args.serve_rate, args.serve_slots,
+                                     args.serve_budget_gib)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_n, args.cpu_iters)

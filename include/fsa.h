@@ -128,6 +128,11 @@ typedef struct {
                             a pair of HIP events on the stream (about 3 us each); FSA_PROFILE_ALL times all */
   double sigma_m_jitter; /* adds jitter * sigma1^2 to the diagonal of Sigma_m (default 0) */
   void* hip_stream;      /* hipStream_t to run on, or NULL for the default stream */
+  int32_t graph;         /* nonzero: every PCG iteration after the first is replayed from a HIP graph captured from
+                            the second (one launch per iteration instead of one per kernel; results are bitwise
+                            those of the eager launches); ignored while profile is set and on the null stream,
+                            which cannot be captured */
+  int32_t reserved0;
 } fsa_options;
 
 typedef struct {
@@ -315,6 +320,101 @@ typedef void (*fsa_release_fn)(void* ptr, void* user);
 fsa_status fsa_set_allocator(fsa_alloc_fn alloc, fsa_release_fn release, void* user);
 
 /* ------------------------------------------------------------------------
+ * Serving: likelihood + gradient and prediction requests of uneven size on
+ * one GPU, each computed as fsa_nll_grad / fsa_predict_var compute it
+ * (Section 3.1 with eq. NEGLLDNEGLLFSA, and Algorithm 1).
+ *
+ * A server owns `slots` workers, each with its own stream (default
+ * priority) and host thread, and one block of `hbm_budget` bytes of device
+ * memory taken at creation.  Requests are admitted in arrival order, each
+ * once its arrival time has come, a worker is free and a contiguous range of
+ * the block can hold the request's footprint (fsa_request_footprint); the
+ * request then allocates only inside that range, so the admitted footprints
+ * never sum past the budget and requests in flight never allocate from the
+ * GPU.  Requests on different workers run concurrently on the device.  Every
+ * result is that of the same request computed alone: a request's work uses
+ * its own buffers and fixed-order reductions only.
+ * ------------------------------------------------------------------------ */
+typedef struct fsa_server fsa_server; /* opaque; owned by the library until fsa_server_destroy */
+
+typedef enum { FSA_REQ_NLL_GRAD = 0, FSA_REQ_PREDICT_VAR = 1 } fsa_request_kind;
+
+typedef struct {
+  int32_t kind;             /* fsa_request_kind */
+  int32_t m;                /* inducing points, 1 <= m <= min(n, 512) */
+  int64_t n;                /* training locations, n >= 2 */
+  const double* locs;       /* host, n x 2 row-major */
+  const double* y;          /* host, n responses */
+  const double* inducing;   /* host, m x 2 row-major */
+  fsa_theta theta;          /* covariance parameters */
+  double taper_range;       /* gamma > 0 */
+  int64_t n_p;              /* FSA_REQ_PREDICT_VAR: prediction locations (>= 1), else 0 */
+  const double* pred_locs;  /* host, n_p x 2 row-major (prediction only) */
+  int32_t num_samples;      /* Algorithm 1's s (prediction only) */
+  int32_t reserved0;
+  double arrival_ms;        /* server clock (fsa_server_clock_ms); the request is not admitted before it */
+} fsa_request;
+
+typedef struct {
+  int32_t slots;            /* workers: requests on the device at once, 1..64 */
+  int32_t reserved0;
+  uint64_t hbm_budget;      /* bytes of device memory shared by the admitted requests */
+  fsa_options opt;          /* solver options of every request (hip_stream is ignored: each worker has one) */
+} fsa_server_options;
+
+typedef struct {
+  int64_t id;
+  int32_t status;           /* fsa_status of the request */
+  int32_t kind;
+  double nll;               /* FSA_REQ_NLL_GRAD */
+  double grad[3];           /* FSA_REQ_NLL_GRAD, order (sigma1^2, rho, sigma^2) */
+  double arrival_ms, admit_ms, done_ms; /* server clock */
+  uint64_t footprint;       /* bytes reserved at admission */
+  uint64_t peak_bytes;      /* most device bytes the request held at once */
+  int32_t worker;           /* the worker that ran it (-1: refused) */
+  int32_t iters_max;        /* PCG iterations of the slowest column */
+  int64_t probe_iters;      /* PCG iterations summed over the columns */
+  int64_t n_p;              /* length of the variance output */
+  char message[192];        /* fsa_last_error() of a failed request */
+} fsa_result;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  uint64_t hbm_budget;
+  uint64_t peak_reserved;   /* largest sum of admitted footprints at one time */
+  int32_t slots, peak_active;
+  double first_arrival_ms, last_done_ms;
+} fsa_server_stats;
+
+/* Device bytes a request may use at most: its context (taper pattern,
+ * factors, float32 copies in the mixed modes), the PCG blocks and the
+ * gradient (FSA_REQ_NLL_GRAD) or Algorithm 1's solves (FSA_REQ_PREDICT_VAR),
+ * and the library's scratch.  The pattern's size comes from a host binning of
+ * the locations on the device's grid (cells of side gamma (1 + 2^-20)): every
+ * pair of points in neighbouring cells is counted, an upper bound on the
+ * nonzeros.  INVALID_ARG for a request fsa_build would refuse. */
+fsa_status fsa_request_footprint(const fsa_request* r, const fsa_options* opt, uint64_t* bytes);
+
+/* Create a server on the current device; its clock starts at 0.  OOM if the
+ * budget cannot be allocated; INVALID_ARG for bad options. */
+fsa_status fsa_server_create(const fsa_server_options* o, fsa_server** out);
+double fsa_server_clock_ms(const fsa_server* s);
+/* Queue a request; its host arrays are copied before the call returns.
+ * *id receives its handle.  A request whose footprint exceeds the budget
+ * completes at once with FSA_ERR_OOM.  INVALID_ARG for a malformed request
+ * (as fsa_build would refuse it). */
+fsa_status fsa_server_submit(fsa_server* s, const fsa_request* r, int64_t* id);
+/* Block until request `id` is done, fill *res, copy its predictive
+ * variances (n_p doubles, nugget included) into var_out if not NULL, and
+ * forget the request.  Returns FSA_OK when the wait succeeded (the request's
+ * own status is res->status); INVALID_ARG for an unknown id. */
+fsa_status fsa_server_wait(fsa_server* s, int64_t id, fsa_result* res, double* var_out);
+fsa_status fsa_server_get_stats(fsa_server* s, fsa_server_stats* st);
+/* Finish every queued request, then release the workers, streams and the
+ * device block.  Results not yet collected are dropped. */
+void fsa_server_destroy(fsa_server* s);
+
+/* ------------------------------------------------------------------------
  * The FITC preconditioner in iterative methods for Vecchia approximations
  * (Section 5).
  *
@@ -404,6 +504,45 @@ fsa_status fsa_vecchia_apply_dev(fsa_vecchia* v, int32_t which, const double* X,
 fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, double* x, int32_t num_probes,
                                         uint64_t seed, double tol, int32_t max_iter, int32_t fixed_iter,
                                         double* logdet, fsa_vecchia_stats* stats);
+
+typedef struct {
+  int32_t newton_steps;  /* Newton steps taken */
+  int32_t converged;     /* 1 if the mode met newton_tol (0 with fixed_newton) */
+  int32_t cg_iters_max;  /* most PCG iterations of any column of any solve */
+  int32_t reserved0;
+  int64_t probe_iters;   /* PCG iterations summed over every solve and column */
+  double loglik;         /* log p(y | b) at the mode */
+  double quad;           /* b^T Sigma_V^{-1} b at the mode */
+  double sum_log_d;      /* sum log D_i of the Vecchia factor (log det Sigma_V) */
+  double logdet;         /* SLQ estimate of log det(Sigma_V^{-1} + W) at the mode */
+  double ms;             /* host wall-clock of the call */
+} fsa_vecchia_laplace_stats;
+
+/* Vecchia-Laplace approximation (Section 5.1) of the negative log marginal
+ * likelihood of Bernoulli responses y in {0, 1} with the logistic link,
+ * log p(y | b) = sum_i y_i b_i - log(1 + e^{b_i}), under the Vecchia prior
+ * b ~ N(0, Sigma_V) of this handle.  The mode of log p(y|b) - b^T Sigma_V^{-1} b / 2
+ * by Newton's method from b = 0,
+ *   b <- (Sigma_V^{-1} + W)^{-1} (W b + y - pi),  pi = 1/(1 + e^{-b}),
+ *   W = diag(pi (1 - pi)) (the negative second derivatives of the log-likelihood),
+ * each solve by block PCG with the FITC preconditioner rebuilt for the
+ * current W (as fsa_vecchia_solve_logdet_dev; the W given at build is
+ * replaced), stopping when ||b_new - b|| <= newton_tol ||b_new|| or after
+ * exactly fixed_newton steps (> 0; max_newton and newton_tol then unused).
+ * At the mode, with W there,
+ *   *nll = -log p(y|b) + b^T Sigma_V^{-1} b / 2 + log det(I + Sigma_V W) / 2,
+ *   log det(I + Sigma_V W) = sum log D_i + log det(Sigma_V^{-1} + W),
+ * the last term by SLQ with num_probes probes (1..1023) keyed by seed.
+ * y and mode (n doubles, the caller's order) are device pointers; nll and
+ * stats host.  tol, max_iter and fixed_iter apply to every PCG solve as in
+ * fsa_vecchia_solve_logdet_dev.  INVALID_ARG for a response not 0 or 1 or
+ * bad sizes; NOT_SPD if a weight underflows (|b| beyond about 36);
+ * NOT_CONVERGED (outputs written) if a solve or the Newton iteration did not
+ * converge; BREAKDOWN as the solve. */
+fsa_status fsa_vecchia_laplace_dev(fsa_vecchia* v, const double* y, int32_t num_probes, uint64_t seed, double tol,
+                                   int32_t max_iter, int32_t fixed_iter, double newton_tol, int32_t max_newton,
+                                   int32_t fixed_newton, double* mode, double* nll,
+                                   fsa_vecchia_laplace_stats* stats);
 
 fsa_status fsa_vecchia_destroy(fsa_vecchia* v);
 

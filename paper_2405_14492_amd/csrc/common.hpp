@@ -151,6 +151,51 @@ struct PoolStream {  // scope guard: the current stream of this thread
   PoolStream& operator=(const PoolStream&) = delete;
 };
 
+// A fixed range of device memory that serves every pool allocation of one
+// host thread while it is current (serving: the device memory reserved for
+// one request at its admission).  Blocks are 256-byte aligned and carved
+// first-fit from the free ranges; a released block becomes free again once
+// the event recorded at its release (on the releasing stream) has passed,
+// so a reuse never overlaps earlier work on any stream.  An allocation that
+// no free range can hold waits for pending releases, then fails (OOM).
+class Region {
+ public:
+  Region(void* base, size_t bytes);
+  ~Region();
+  Region(const Region&) = delete;
+  Region& operator=(const Region&) = delete;
+  void* alloc(size_t bytes);
+  bool owns(const void* p) const;
+  void release(void* p, hipStream_t st);
+  // wait for every pending release (the region is then whole if nothing is live)
+  void settle();
+  size_t live_bytes() const { return live_; }
+  size_t peak_bytes() const { return peak_; }
+  size_t size() const { return size_; }
+
+ private:
+  struct Pend {
+    size_t off, len;
+    hipEvent_t ev;
+  };
+  void reclaim(bool wait);
+  void insert_free(size_t off, size_t len);
+  char* base_;
+  size_t size_, live_ = 0, peak_ = 0;
+  std::vector<std::pair<size_t, size_t>> free_;  // (offset, length), sorted by offset, coalesced
+  std::vector<std::pair<size_t, size_t>> used_;  // (offset, length) of live blocks
+  std::vector<Pend> pend_;
+};
+Region* pool_region();
+void pool_set_region(Region* r);
+struct PoolRegion {  // scope guard: the current region of this thread
+  Region* prev;
+  explicit PoolRegion(Region* r) : prev(pool_region()) { pool_set_region(r); }
+  ~PoolRegion() { pool_set_region(prev); }
+  PoolRegion(const PoolRegion&) = delete;
+  PoolRegion& operator=(const PoolRegion&) = delete;
+};
+
 // Device buffer owned by its holder: released to the pool when it is
 // reallocated, released explicitly, or destroyed.
 template <typename T>

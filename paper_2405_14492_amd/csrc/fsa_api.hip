@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <map>
 #include <mutex>
@@ -115,7 +116,114 @@ void flush_pending(bool wait) {
 hipStream_t pool_stream() { return t_stream; }
 void pool_set_stream(hipStream_t st) { t_stream = st; }
 
+// ---- regions
+namespace {
+thread_local Region* t_region = nullptr;
+constexpr size_t kRegionAlign = 256;
+}  // namespace
+Region* pool_region() { return t_region; }
+void pool_set_region(Region* r) { t_region = r; }
+
+Region::Region(void* base, size_t bytes) : base_(static_cast<char*>(base)), size_(bytes / kRegionAlign * kRegionAlign) {
+  if (size_) free_.emplace_back(0, size_);
+}
+
+Region::~Region() { settle(); }
+
+bool Region::owns(const void* p) const {
+  const char* c = static_cast<const char*>(p);
+  return c >= base_ && c < base_ + size_;
+}
+
+void Region::insert_free(size_t off, size_t len) {
+  auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (size_t)0));
+  it = free_.insert(it, {off, len});
+  // coalesce with the successor, then with the predecessor
+  auto nx = it + 1;
+  if (nx != free_.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    free_.erase(nx);
+  }
+  if (it != free_.begin()) {
+    auto pv = it - 1;
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      free_.erase(it);
+    }
+  }
+}
+
+void Region::reclaim(bool wait) {
+  for (size_t i = 0; i < pend_.size();) {
+    Pend& q = pend_[i];
+    bool done = true;
+    if (q.ev) {
+      if (wait) (void)hipEventSynchronize(q.ev);
+      const hipError_t e = hipEventQuery(q.ev);
+      done = e == hipSuccess;
+      if (e != hipSuccess && e != hipErrorNotReady) (void)hipGetLastError();
+    }
+    if (done) {
+      if (q.ev) {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        g_events.push_back(q.ev);
+      }
+      insert_free(q.off, q.len);
+      pend_[i] = pend_.back();
+      pend_.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+void Region::settle() { reclaim(true); }
+
+void* Region::alloc(size_t bytes) {
+  const size_t r = (std::max<size_t>(bytes, 1) + kRegionAlign - 1) / kRegionAlign * kRegionAlign;
+  for (int pass = 0; pass < 2; ++pass) {
+    reclaim(pass == 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < r) continue;
+      const size_t off = it->first;
+      if (it->second == r) free_.erase(it);
+      else {
+        it->first += r;
+        it->second -= r;
+      }
+      used_.insert(std::lower_bound(used_.begin(), used_.end(), std::make_pair(off, (size_t)0)), {off, r});
+      live_ += r;
+      peak_ = std::max(peak_, live_);
+      return base_ + off;
+    }
+  }
+  return nullptr;
+}
+
+void Region::release(void* p, hipStream_t st) {
+  const size_t off = (size_t)(static_cast<char*>(p) - base_);
+  auto it = std::lower_bound(used_.begin(), used_.end(), std::make_pair(off, (size_t)0));
+  if (it == used_.end() || it->first != off) return;
+  const size_t len = it->second;
+  used_.erase(it);
+  live_ -= len;
+  hipEvent_t ev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    ev = event_get_locked();
+  }
+  if (ev && hipEventRecord(ev, st) != hipSuccess) {
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_events.push_back(ev);
+    ev = nullptr;
+  }
+  if (!ev) (void)hipStreamSynchronize(st);
+  pend_.push_back(Pend{off, len, ev});
+}
+
 void* pool_alloc(size_t bytes) {
+  if (t_region) return t_region->alloc(bytes);
   size_t r = pool_round(bytes);
   UserAlloc ua;
   {
@@ -160,6 +268,10 @@ void* pool_alloc(size_t bytes) {
 
 void pool_free(void* p) {
   if (!p) return;
+  if (t_region && t_region->owns(p)) {
+    t_region->release(p, t_stream);
+    return;
+  }
   bool user = false;
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
@@ -605,7 +717,7 @@ struct fsa_ctx {
   Grid grid;
   Csr csr;
   Buf<double> ind, y;
-  Buf<double> Sm, Lm, Lminv, C, LCinv, Cinv;
+  Buf<double> Sm, Lm, Lminv, LminvT, C, LCinv, Cinv;
   Buf<double> A, vals, D, Dinv;
   Buf<float> Af, valsf;
   Buf<int64_t> tile_off;  // the float32 sparse part as MFMA-order tiles (mixed modes)
@@ -651,7 +763,6 @@ struct fsa_ctx {
   // L_C^{-1} A and L_C^{-1} F by rows, and the five trace sums (per theta)
   Buf<double> dD, cvBA, cvBF, cvpart, cvtr;
   Scratch scr;
-  BlasHandle blas;
   KernelTimer timer;
   bool solved = false;
   double last_logdet_P = 0;
@@ -714,9 +825,9 @@ static fsa_status build_values(fsa_ctx* c) {
     set_error("Cholesky of Sigma_m failed at column %d (duplicate inducing points?)", info - 1);
     return FSA_ERR_NOT_SPD;
   }
-  FSA_TRY(blas_acquire(c->blas));
-  FSA_TRY(blas_tri_inverse(c->blas, st, c->Lm.p, c->Lminv.p, mp));
-  FSA_TRY(whiten(c->blas, c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->Lm.p, c->A.p, st));
+  FSA_TRY(tri_inverse(c->Lm.p, c->Lminv.p, mp, st));
+  FSA_TRY(transpose_scale(c->Lminv.p, c->LminvT.p, mp, 1.0, st));
+  FSA_TRY(whiten(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->LminvT.p, c->A.p, st));
   // MIXED_BF16A: the model takes the bfloat16-rounded factor from here on
   // (residual values, D_s, capacitance, probes, gradient and prediction), so
   // the PCG operator read in bfloat16 is the float64 operator of that model
@@ -736,7 +847,7 @@ static fsa_status build_values(fsa_ctx* c) {
   FSA_HIP(hipStreamWaitEvent(c->st2, c->ev_ready, 0));
   FSA_TRY(dense_cholesky(c->C.p, mp, c->info.p, c->st2));
   FSA_TRY(dense_logdet_chol(c->C.p, mp, c->logdet_parts.p, c->st2));
-  FSA_TRY(blas_tri_inverse(c->blas, c->st2, c->C.p, c->LCinv.p, mp));
+  FSA_TRY(tri_inverse(c->C.p, c->LCinv.p, mp, c->st2));
   FSA_TRY(dense_gemm(c->LCinv.p, true, c->LCinv.p, false, c->Cinv.p, mp, 1.0, c->st2));
   FSA_HIP(hipEventRecord(c->ev_fact, c->st2));
   {
@@ -804,6 +915,7 @@ static fsa_status build_core(fsa_ctx* c, const double* locs, const double* y, co
   FSA_TRY(c->y.alloc(n));
   FSA_TRY(permute_rows(y, 1, c->y.p, 1, c->grid.perm.p, n, 1, st));
   FSA_TRY(c->Lminv.alloc(mm));
+  FSA_TRY(c->LminvT.alloc(mm));
   FSA_TRY(c->C.alloc(mm));
   FSA_TRY(c->LCinv.alloc(mm));
   FSA_TRY(c->Cinv.alloc(mm));
@@ -1029,7 +1141,6 @@ fsa_status fsa_set_allocator(fsa_alloc_fn alloc, fsa_release_fn release, void* u
 
 void fsa_pool_trim(void) {
   pool_trim();
-  blas_trim();
   pinned_trim();
 }
 
@@ -1083,7 +1194,6 @@ void fsa_destroy(fsa_ctx* c) {
     (void)hipStreamDestroy(c->st2);
   }
   pinned_put(c->hstage, c->hstage_bytes);
-  blas_release(c->blas);
   delete c;  // Buf members return their blocks to the pool
   pool_flush();  // and blocks of a registered allocator go back to it now
 }
@@ -1150,6 +1260,39 @@ static fsa_status stage_status(fsa_ctx* c, const int* flags, const double* rr, c
   hs->iters = iters ? reinterpret_cast<const int*>(hs->bn + tp) : nullptr;
   return FSA_OK;
 }
+
+// One PCG iteration replayed from a HIP graph: captured on first use, then
+// launched once per iteration.  The iteration's launches and arguments are
+// the same every iteration (its state lives in device memory), and its
+// scratch is sized by the eager first iteration, so the capture allocates
+// nothing and holds no memset.
+template <typename T>
+struct IterGraph {
+  hipStream_t st = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  explicit IterGraph(hipStream_t s) : st(s) {}
+  IterGraph(const IterGraph&) = delete;
+  IterGraph& operator=(const IterGraph&) = delete;
+  ~IterGraph() {
+    if (!x && !g) return;
+    (void)hipStreamSynchronize(st);
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+  }
+  fsa_status run(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, Scratch& s) {
+    if (!x) {
+      FSA_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      const fsa_status cs = pcg_iter<T>(b, op, tol, fixed, s, st);
+      const hipError_t ce = hipStreamEndCapture(st, &g);
+      if (cs != FSA_OK) return cs;
+      FSA_HIP(ce);
+      FSA_HIP(hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
+    }
+    FSA_HIP(hipGraphLaunch(x, st));
+    return FSA_OK;
+  }
+};
 
 template <typename T>
 static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
@@ -1241,8 +1384,11 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   // far from convergence, and no idle iterations once every column is done.
   int next_check = 4, prev_it = 0;
   double prev_res = -1.0;
+  IterGraph<T> ig(st);
+  const bool use_graph = c->opt.graph != 0 && !c->timer.on && st != nullptr;  // the null stream cannot be captured
   for (it = 0; it < max_iter; ++it) {
-    FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
+    if (use_graph && it > 0) FSA_TRY(ig.run(b, op, tol, fixed, c->scr));
+    else FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
     if (it == 0) FSA_TRY(enqueue_derivative(c));  // a derivative build marked before the solve
     bool replaced = false;
     if constexpr (sizeof(T) == 4) {
@@ -1406,11 +1552,9 @@ static fsa_status build_derivative(fsa_ctx* c, hipStream_t st) {
   // symmetric K = E/2 costs 2 n mp^2 (taken here in 128-row blocks: 1.25 n mp^2)
   hipLaunchKernelGGL(k_lower_half, dim3(ceil_div((int64_t)mp * mp, 256)), dim3(256), 0, st, E, mp, T1);
   FSA_HIP(hipGetLastError());
+  FSA_TRY(transpose_scale(T1, E, mp, -1.0, st));  // -Phi(E)^T (E is not needed past here)
   FSA_TRY(c->F.alloc((size_t)c->n * mp));
-  FSA_TRY(blas_acquire(c->blas));
-  FSA_TRY(cov_block(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, true, c->F.p, st));
-  FSA_TRY(blas_solve_lower(c->blas, st, c->Lm.p, mp, c->F.p, c->n));
-  FSA_TRY(blas_lower_mul_acc(c->blas, st, T1, mp, c->A.p, c->F.p, c->n, -1.0));
+  FSA_TRY(derivative_factor(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->LminvT.p, c->A.p, E, c->F.p, st));
   FSA_TRY(c->dvals.alloc(c->csr.nnz));
   FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, c->F.p, c->F.p, mp, c->th, c->gamma, true, true,
                           c->dvals.p, nullptr, st));
@@ -1422,12 +1566,12 @@ static fsa_status build_derivative(fsa_ctx* c, hipStream_t st) {
     FSA_TRY(c->dD.alloc(n));
     hipLaunchKernelGGL(k_csr_diag, dim3(ceil_div(n, 256)), dim3(256), 0, st, c->csr.row_ptr.p, c->csr.col.p,
                        c->dvals.p, n, c->dD.p);
+    // rows of L_C^{-1} A and L_C^{-1} F: A L_C^{-T} and F L_C^{-T}
     FSA_TRY(c->cvBA.alloc((size_t)n * mp));
     FSA_TRY(c->cvBF.alloc((size_t)n * mp));
-    FSA_HIP(hipMemcpyAsync(c->cvBA.p, c->A.p, (size_t)n * mp * sizeof(double), hipMemcpyDeviceToDevice, st));
-    FSA_HIP(hipMemcpyAsync(c->cvBF.p, c->F.p, (size_t)n * mp * sizeof(double), hipMemcpyDeviceToDevice, st));
-    FSA_TRY(blas_solve_lower(c->blas, st, c->C.p, mp, c->cvBA.p, n));
-    FSA_TRY(blas_solve_lower(c->blas, st, c->C.p, mp, c->cvBF.p, n));
+    FSA_TRY(transpose_scale(c->LCinv.p, T1, mp, 1.0, st));  // L_C^{-T}
+    FSA_TRY(rows_times_lower_t(c->A.p, n, mp, T1, c->cvBA.p, st));
+    FSA_TRY(rows_times_lower_t(c->F.p, n, mp, T1, c->cvBF.p, st));
     const int G = 1024;
     FSA_TRY(c->cvpart.alloc((size_t)G * 5));
     FSA_TRY(c->cvtr.alloc(8));
@@ -1645,8 +1789,10 @@ static fsa_status run_sparse_pcg(fsa_ctx* c, const double* B, int ncols, int ld,
   const int fixed = c->opt.fixed_iter > 0 ? 1 : 0;
   FSA_TRY(pcg_init<T>(b, op, B, tol, c->scr, st));
   int flags[2] = {0, 0};
+  IterGraph<T> ig(st);
   for (int it = 0; it < max_iter; ++it) {
-    FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
+    if (c->opt.graph != 0 && st != nullptr && it > 0) FSA_TRY(ig.run(b, op, tol, fixed, c->scr));
+    else FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
     if constexpr (sizeof(T) == 4) {
       if (c->opt.rr_period > 0 && (it + 1) % c->opt.rr_period == 0 && it + 1 < max_iter)
         FSA_TRY(pcg_replace_residual_f32(reinterpret_cast<PcgBlock<float>&>(b), op64,
@@ -1724,8 +1870,7 @@ static fsa_status predict_core(fsa_ctx* c, const double* pred_locs_h, int64_t n_
   FSA_TRY(Ap.alloc((size_t)n_p * mp));
   FSA_TRY(vPT.alloc(cPT.nnz));
   FSA_TRY(vTP.alloc(cTP.nnz));
-  FSA_TRY(blas_acquire(c->blas));
-  FSA_TRY(whiten(c->blas, pg.xs.p, n_p, c->ind.p, c->m, mp, c->th, c->Lm.p, Ap.p, st));
+  FSA_TRY(whiten(pg.xs.p, n_p, c->ind.p, c->m, mp, c->th, c->LminvT.p, Ap.p, st));
   if (c->opt.precision == FSA_MIXED_BF16A) FSA_TRY(to_bf16(Ap.p, nullptr, Ap.p, n_p * (int64_t)mp, st));
   FSA_TRY(residual_values(pg, c->grid, cPT, Ap.p, c->A.p, nullptr, nullptr, mp, c->th, c->gamma, false, false, vPT.p,
                           nullptr, st));
@@ -1764,8 +1909,7 @@ static fsa_status predict_core(fsa_ctx* c, const double* pred_locs_h, int64_t n_
   FSA_HIP(hipMemcpyAsync(&info, c->info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   if (info) { set_error("Cholesky of I + A Sigma~_s^{-1} A^T failed at column %d", info - 1); return FSA_ERR_NOT_SPD; }
-  FSA_TRY(blas_acquire(c->blas));
-  FSA_TRY(blas_tri_inverse(c->blas, st, Mt.p, LMi.p, mp));
+  FSA_TRY(tri_inverse(Mt.p, LMi.p, mp, st));
   FSA_TRY(transpose_scale(LMi.p, G.p, mp, 1.0, st));
   // Y = A_p L_M^{-T}, Z2 = (S_p^T V~) L_M^{-T}, Z_l = S_p^T W_l
   Buf<double> Y, Y2, Z2, Zl;

@@ -199,12 +199,6 @@ fsa_status cov_block(const double* xs, int64_t n, const double* ind, int m, int 
   return FSA_OK;
 }
 
-fsa_status whiten(BlasHandle& b, const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
-                  const double* Lm, double* A_out, hipStream_t st) {
-  FSA_TRY(cov_block(xs, n, ind, m, mp, th, false, A_out, st));
-  return blas_solve_lower(b, st, Lm, mp, A_out, n);
-}
-
 fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const double* Xr, const double* Yc,
                            const double* Fr, const double* Fc, int mp, const Theta& th, double gamma, bool self,
                            bool deriv, double* vals, double* D, hipStream_t st) {

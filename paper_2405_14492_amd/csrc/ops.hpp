@@ -68,33 +68,26 @@ struct KernelTimer {
 };
 enum { KT_SPMM = 0, KT_PASS1 = 1, KT_PASS2 = 2, KT_UPDATE = 3, KT_SMALL = 4 };
 
-// ---- dense float64 library products (rocBLAS, pooled handles) ----
-struct BlasHandle {
-  void* h = nullptr;
-  int dev = -1;
-};
-fsa_status blas_acquire(BlasHandle& b);
-void blas_release(BlasHandle& b);
-void blas_trim();
-// X := L^{-1} X (L row-major lower mp x mp, X point-major n x mp)
-fsa_status blas_solve_lower(BlasHandle& b, hipStream_t st, const double* L, int mp, double* X, int64_t n);
-// Y := Y + alpha K X (K row-major lower-triangular mp x mp; X, Y point-major n x mp)
-fsa_status blas_lower_mul_acc(BlasHandle& b, hipStream_t st, const double* K, int mp, const double* X, double* Y,
-                              int64_t n, double alpha);
-// Linv := L^{-1} (row-major lower-triangular mp x mp)
-fsa_status blas_tri_inverse(BlasHandle& b, hipStream_t st, const double* L, double* Linv, int mp);
-// X := alpha M Y + beta X (M row-major mp x mp; X, Y point-major n x mp)
-fsa_status blas_left_mul(BlasHandle& b, hipStream_t st, const double* M, int mp, const double* Y, double* X, int64_t n,
-                         double alpha, double beta);
+// ---- float64 factor kernels (whiten.hip) ----
+// Linv := L^{-1} for row-major lower-triangular L (mp x mp, mp % 64 == 0, mp <= 512)
+fsa_status tri_inverse(const double* L, double* Linv, int mp, hipStream_t st);
+// Y := X W^T for point-major X (n x mp) and lower-triangular W given as WT = W^T (row-major mp x mp)
+fsa_status rows_times_lower_t(const double* X, int64_t n, int mp, const double* WT, double* Y, hipStream_t st);
+// F := dSigma_nm L_m^{-T} - A Phi(E)^T (point-major n x mp), dSigma_nm generated on the fly;
+// LminvT = (L_m^{-1})^T, PhiT_neg = -Phi(E)^T, both row-major mp x mp
+fsa_status derivative_factor(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
+                             const double* LminvT, const double* A, const double* PhiT_neg, double* F_out,
+                             hipStream_t st);
 
 // ---- build-time contractions (float64) ----
 // out[i][k] = c(x_i, ind_k) (deriv: dc/drho) for k < m, 0 for m <= k < mp
 // (point-major n x mp, Section 2.1)
 fsa_status cov_block(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th, bool deriv,
                      double* out, hipStream_t st);
-// A = L_m^{-1} Sigma_mn (point-major n x mp): whitened low-rank factor
-fsa_status whiten(BlasHandle& b, const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
-                  const double* Lm, double* A_out, hipStream_t st);
+// A = L_m^{-1} Sigma_mn = Sigma_nm L_m^{-T} (point-major n x mp): whitened low-rank factor,
+// Sigma_nm generated on the fly (never stored); LminvT = (L_m^{-1})^T (row-major mp x mp)
+fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
+                  const double* LminvT, double* A_out, hipStream_t st);
 // Residual values of a taper pattern (rows of grid rg, columns of grid cg):
 // v = (c(d) - Xr_p . Yc_q) W(d/gamma) (+ s2 on the self diagonal, D[p] = v_pp).
 // deriv: v = (dc/drho(d) - [F|A]_p . [A|F]_q) W(d/gamma).

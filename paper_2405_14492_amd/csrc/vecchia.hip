@@ -576,14 +576,77 @@ struct fsa_vecchia {
   std::vector<int> lmaxc;  // longest child list among the points of level l
   // FITC preconditioner of Sigma + W^{-1}
   Buf<double> Sm, Lm, A, Ds, C, LCinv, Cinv, parts;  // parts: [0] log det P, [1] sum log w - sum log D
-  BlasHandle blas;
   Scratch scr;
-  double logdet_P = 0.0, offset = 0.0;
+  double logdet_P = 0.0, offset = 0.0, sum_log_dv = 0.0;
   ~fsa_vecchia() {
     if (st) (void)hipStreamSynchronize(st);
-    blas_release(blas);
   }
 };
+
+// ---------------------------------------------------------------- Vecchia-Laplace (Bernoulli-logit)
+// Newton data at latent values b (caller's order) for responses y in {0, 1}:
+// pi = 1/(1 + e^{-b}), W = pi (1 - pi) (the negative second derivative of
+// the log-likelihood), and rhs = W b + y - pi (with_wb) or y - pi.
+__global__ void k_vnewton(int64_t n, const double* __restrict__ b, const double* __restrict__ y, int with_wb,
+                          double* __restrict__ w, double* __restrict__ rhs) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double pi = 0.5 * (1.0 + tanh(0.5 * b[i]));
+  const double wi = pi * (1.0 - pi);
+  w[i] = wi;
+  rhs[i] = (with_wb ? wi * b[i] : 0.0) + y[i] - pi;
+}
+
+// Per-workgroup partial sums, three per group:
+//   mode 0: |x - b|^2, |x|^2, 0;  mode 1: sum y b - log(1 + e^b), 0, 0;  mode 2: x . b, 0, 0
+__global__ __launch_bounds__(256) void k_vlaplace_parts(int64_t n, int mode, const double* __restrict__ x,
+                                                        const double* __restrict__ b, const double* __restrict__ y,
+                                                        double* __restrict__ part) {
+  __shared__ double s[3][256];
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    if (mode == 0) {
+      const double d = x[i] - b[i];
+      a0 += d * d;
+      a1 += x[i] * x[i];
+    } else if (mode == 1) {
+      const double bi = b[i];
+      const double sp = bi > 0.0 ? bi + log1p(exp(-bi)) : log1p(exp(bi));  // log(1 + e^b)
+      a0 += y[i] * bi - sp;
+    } else {
+      a0 += x[i] * b[i];
+    }
+  }
+  s[0][threadIdx.x] = a0;
+  s[1][threadIdx.x] = a1;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + o];
+      s[1][threadIdx.x] += s[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = s[0][0];
+    part[3 * blockIdx.x + 1] = s[1][0];
+    part[3 * blockIdx.x + 2] = 0.0;
+  }
+}
+
+__global__ void k_vsum3(const double* __restrict__ part, int np, double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= 3 || blockIdx.x != 0) return;
+  double a = 0.0;
+  for (int i = 0; i < np; ++i) a += part[3 * i + j];
+  out[j] = a;
+}
+
+// count of responses not in {0, 1}
+__global__ void k_vcount_nonbinary(int64_t n, const double* __restrict__ y, int* bad) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && !(y[i] == 0.0 || y[i] == 1.0)) atomicAdd(bad, 1);
+}
 
 namespace {
 
@@ -655,6 +718,56 @@ fsa_status operator_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, d
   hipLaunchKernelGGL(k_vadd_winv, dim3(grid1(v->n * ncols)), dim3(256), 0, v->st, v->n, ncols, X, ldx, v->wp.p, Y,
                      ldy);
   FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// The FITC preconditioner of Sigma + W^{-1} (Section 5.1) for the weights in
+// v->w (the caller's order), on the factor A built once: W in level order,
+// D_s = sigma1^2 - |A_p|^2 + 1/W, C = I + A D_s^{-1} A^T with its Cholesky
+// factor, inverse and log det, and the log-determinant offset
+// sum log W - sum log D.  The Vecchia factor does not depend on W.
+fsa_status set_weights(fsa_vecchia* v) {
+  hipStream_t st = v->st;
+  const int64_t n = v->n;
+  const int mp = v->mp;
+  int hinfo[2] = {0, 0};
+  FSA_HIP(hipMemsetAsync(v->info.p, 0, 4 * sizeof(int), st));
+  Buf<double> part, part2, part3;
+  FSA_TRY(sum_log(v->w.p, n, v->parts.p + 2, v->info.p + 1, st, part3));
+  hipLaunchKernelGGL(k_vgather, dim3(grid1(n)), dim3(256), 0, st, n, 1, v->w.p, (int64_t)1, v->order.p, v->wp.p,
+                     (int64_t)1);
+  FSA_TRY(v->Ds.alloc(n));
+  hipLaunchKernelGGL(k_vds, dim3(grid1(n, 4)), dim3(256), 0, st, v->A.p, n, mp, v->th.s1, v->wp.p, v->Ds.p);
+  FSA_TRY(v->C.alloc((size_t)mp * mp));
+  FSA_TRY(capacitance(v->A.p, v->Ds.p, n, mp, v->C.p, v->scr, st));
+  FSA_TRY(dense_cholesky(v->C.p, mp, v->info.p, st));
+  FSA_TRY(dense_logdet_chol(v->C.p, mp, v->parts.p, st));
+  FSA_TRY(v->LCinv.alloc((size_t)mp * mp));
+  FSA_TRY(v->Cinv.alloc((size_t)mp * mp));
+  FSA_TRY(tri_inverse(v->C.p, v->LCinv.p, mp, st));
+  FSA_TRY(dense_gemm(v->LCinv.p, true, v->LCinv.p, false, v->Cinv.p, mp, 1.0, st));
+  // sums of logs: [1] log D_s, [2] log W, [3] log D (Vecchia)
+  FSA_TRY(sum_log(v->Ds.p, n, v->parts.p + 1, v->info.p + 1, st, part));
+  FSA_TRY(sum_log(v->Dv.p, n, v->parts.p + 3, v->info.p + 1, st, part2));
+  double hp[4];
+  FSA_HIP(hipMemcpyAsync(hp, v->parts.p, sizeof(hp), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipMemcpyAsync(hinfo, v->info.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  if (hinfo[0]) {
+    set_error("Cholesky of the FITC capacitance failed at column %d", hinfo[0] - 1);
+    return FSA_ERR_NOT_SPD;
+  }
+  if (hinfo[1]) {
+    set_error("a weight W or the FITC diagonal D_s is not finite and positive");
+    return FSA_ERR_NOT_SPD;
+  }
+  v->logdet_P = hp[0] + hp[1];
+  v->offset = hp[2] - hp[3];
+  v->sum_log_dv = hp[3];
+  // parts[0] = log det P, parts[1] = sum log w - sum log D (read by k_vlogdet)
+  const double hp2[2] = {v->logdet_P, v->offset};
+  FSA_HIP(hipMemcpyAsync(v->parts.p, hp2, sizeof(hp2), hipMemcpyHostToDevice, st));
+  FSA_HIP(hipStreamSynchronize(st));
   return FSA_OK;
 }
 
@@ -819,40 +932,162 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
     set_error("Cholesky of Sigma_m failed at column %d (duplicate inducing points?)", hinfo[0] - 1);
     return FSA_ERR_NOT_SPD;
   }
-  FSA_TRY(blas_acquire(v->blas));
   FSA_TRY(v->A.alloc((size_t)n * mp));
-  FSA_TRY(whiten(v->blas, v->xsp.p, n, v->ind.p, v->m, mp, v->th, v->Lm.p, v->A.p, st));
-  FSA_TRY(v->Ds.alloc(n));
-  hipLaunchKernelGGL(k_vds, dim3(grid1(n, 4)), dim3(256), 0, st, v->A.p, n, mp, v->th.s1, v->wp.p, v->Ds.p);
-  FSA_TRY(v->C.alloc((size_t)mp * mp));
-  FSA_TRY(capacitance(v->A.p, v->Ds.p, n, mp, v->C.p, v->scr, st));
-  FSA_TRY(dense_cholesky(v->C.p, mp, v->info.p, st));
-  FSA_TRY(dense_logdet_chol(v->C.p, mp, v->parts.p, st));
-  FSA_TRY(v->LCinv.alloc((size_t)mp * mp));
-  FSA_TRY(v->Cinv.alloc((size_t)mp * mp));
-  FSA_TRY(blas_tri_inverse(v->blas, st, v->C.p, v->LCinv.p, mp));
-  FSA_TRY(dense_gemm(v->LCinv.p, true, v->LCinv.p, false, v->Cinv.p, mp, 1.0, st));
-  // sums of logs: [1] log D_s, [3] log D (Vecchia)
-  FSA_TRY(sum_log(v->Ds.p, n, v->parts.p + 1, v->info.p + 1, st, part));
-  Buf<double> part2;
-  FSA_TRY(sum_log(v->Dv.p, n, v->parts.p + 3, v->info.p + 1, st, part2));
-  double hp[4];
-  FSA_HIP(hipMemcpyAsync(hp, v->parts.p, sizeof(hp), hipMemcpyDeviceToHost, st));
-  FSA_HIP(hipMemcpyAsync(hinfo, v->info.p, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  {
+    Buf<double> Li, LiT;  // L_m^{-1} and its transpose
+    FSA_TRY(Li.alloc((size_t)mp * mp));
+    FSA_TRY(LiT.alloc((size_t)mp * mp));
+    FSA_TRY(tri_inverse(v->Lm.p, Li.p, mp, st));
+    FSA_TRY(transpose_scale(Li.p, LiT.p, mp, 1.0, st));
+    FSA_TRY(whiten(v->xsp.p, n, v->ind.p, v->m, mp, v->th, LiT.p, v->A.p, st));
+  }
+  return set_weights(v);
+}
+
+// One block PCG run on Sigma_V + W^{-1} over [Sigma_V rhs, z_1 .. z_t]
+// (num_probes = t >= 0; with t = 0 the solve alone, logdet unused):
+// x = (Sigma_V^{-1} + W)^{-1} rhs, *logdet = the SLQ estimate of
+// log det(Sigma_V^{-1} + W).  rhs and x in the caller's order.
+fsa_status vsolve(fsa_vecchia* v, const double* rhs, double* x, int32_t num_probes, uint64_t seed, double tol,
+                  int32_t max_iter, int fixed, double* logdet, fsa_vecchia_stats* stats) {
+  hipStream_t st = v->st;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = v->n;
+  const int ncols = num_probes + 1;
+  const int64_t ld = round_up(ncols, 64);
+  const int ldw = (int)round_up(ncols, 64);
+  const size_t blk = (size_t)n * ld;
+  Buf<double> mem, Wm, G, Emat, col, hist;
+  Buf<int> ivec;
+  FSA_TRY(mem.alloc(8 * blk));
+  double* Bk = mem.p;
+  double* R = mem.p + blk;
+  double* H = mem.p + 2 * blk;
+  double* V = mem.p + 3 * blk;
+  double* Z = mem.p + 4 * blk;
+  double* U = mem.p + 5 * blk;
+  double* Q0 = mem.p + 6 * blk;
+  double* T = mem.p + 7 * blk;
+  FSA_TRY(Wm.alloc((size_t)v->mp * ldw));
+  FSA_TRY(G.alloc((size_t)v->mp * ldw));
+  FSA_TRY(Emat.alloc((size_t)v->mp * ldw));
+  // per column: [0] rz [1] bn2 [2] hv [3] alpha [4] beta [5] rzn [6] rr [7] weight [8] slq terms, then 2 results
+  FSA_TRY(col.alloc(9 * (size_t)ncols + 2));
+  double* c_rz = col.p;
+  double* c_bn2 = col.p + ncols;
+  double* c_hv = col.p + 2 * ncols;
+  double* c_alpha = col.p + 3 * ncols;
+  double* c_beta = col.p + 4 * ncols;
+  double* c_rzn = col.p + 5 * ncols;
+  double* c_rr = col.p + 6 * ncols;
+  double* c_w = col.p + 7 * ncols;
+  double* c_slq = col.p + 8 * ncols;
+  double* res = col.p + 9 * ncols;
+  FSA_TRY(hist.alloc(2 * (size_t)max_iter * ncols));
+  double* ah = hist.p;
+  double* bh = hist.p + (size_t)max_iter * ncols;
+  FSA_TRY(ivec.alloc(2 * (size_t)ncols + 2));
+  int* active = ivec.p;
+  int* iters = ivec.p + ncols;
+  int* flags = ivec.p + 2 * ncols;
+  FSA_HIP(hipMemsetAsync(mem.p, 0, 8 * blk * sizeof(double), st));
+  FSA_HIP(hipMemsetAsync(hist.p, 0, hist.bytes(), st));
+  // right-hand sides [Sigma_V v, z_1 .. z_t], z ~ (0, P) (App. F sampling recipe)
+  hipLaunchKernelGGL(k_vgather, dim3(grid1(n)), dim3(256), 0, st, n, 1, rhs, (int64_t)1, v->order.p, Q0, ld);
+  FSA_TRY(sigma_v(v, Q0, ld, 1, T, ld));
+  FSA_HIP(hipMemsetAsync(Q0, 0, blk * sizeof(double), st));
+  {
+    Buf<double> y;
+    FSA_TRY(y.alloc(n));
+    FSA_HIP(hipMemcpy2DAsync(y.p, sizeof(double), T, ld * sizeof(double), sizeof(double), n,
+                             hipMemcpyDeviceToDevice, st));
+    FSA_HIP(hipMemsetAsync(T, 0, blk * sizeof(double), st));
+    // the Rademacher draws are keyed by the caller's point index (order[p])
+    FSA_TRY(make_probes(v->A.p, n, v->m, v->mp, v->Ds.p, y.p, v->order.p, seed, num_probes, Bk, (int)ld, Emat.p, st));
+    FSA_HIP(hipStreamSynchronize(st));  // y leaves scope
+  }
+  // init: R = B, Z = P^{-1} R, H = Q0 = Z
+  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Bk, ld, R, ld);
+  FSA_TRY(precond(v, R, ld, ncols, Z, T, Wm.p, G.p, ldw));
+  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Z, ld, H, ld);
+  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Z, ld, Q0, ld);
+  FSA_TRY((coldot<double, double>(R, Z, n, (int)ld, ncols, c_rzn, v->scr, st)));
+  FSA_TRY((coldot<double, double>(Bk, Bk, n, (int)ld, ncols, c_bn2, v->scr, st)));
+  FSA_TRY((coldot<double, double>(Bk, Q0, n, (int)ld, ncols, c_w, v->scr, st)));
+  hipLaunchKernelGGL(k_vpcg_init, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_rzn, c_bn2, c_rz, active, iters, flags);
+  FSA_HIP(hipGetLastError());
+  const double tol2 = tol * tol;
+  int hflags[2] = {0, 0};
+  int it = 0;
+  bool converged = false;
+  for (; it < max_iter; ++it) {
+    FSA_TRY(operator_v(v, H, ld, ncols, V, ld));
+    FSA_TRY((coldot<double, double>(H, V, n, (int)ld, ncols, c_hv, v->scr, st)));
+    hipLaunchKernelGGL(k_vpcg_alpha, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_hv, c_rz, active, c_alpha, flags);
+    hipLaunchKernelGGL(k_vpcg_update, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, ld, c_alpha, H, V, U, R);
+    FSA_TRY(precond(v, R, ld, ncols, Z, T, Wm.p, G.p, ldw));
+    FSA_TRY((coldot<double, double>(R, Z, n, (int)ld, ncols, c_rzn, v->scr, st)));
+    FSA_TRY((coldot<double, double>(R, R, n, (int)ld, ncols, c_rr, v->scr, st)));
+    FSA_HIP(hipMemsetAsync(flags, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_vpcg_beta, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_rzn, c_rr, c_bn2, c_alpha, c_rz,
+                       c_beta, active, iters, ah, bh, max_iter, tol2, fixed, flags);
+    hipLaunchKernelGGL(k_vpcg_direction, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, ld, c_beta, Z, H);
+    FSA_HIP(hipGetLastError());
+    if (fixed && it + 1 < max_iter) continue;  // breakdowns are read after the last iteration
+    FSA_HIP(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    FSA_HIP(hipStreamSynchronize(st));
+    if (hflags[1]) {
+      set_error("CG breakdown in the Vecchia solve (h^T K h <= 0 or non-finite)");
+      return FSA_ERR_BREAKDOWN;
+    }
+    if (hflags[0] == 0 || fixed) {
+      converged = true;
+      ++it;
+      break;
+    }
+  }
+  // solution and log det
+  hipLaunchKernelGGL(k_vsolution, dim3(grid1(n)), dim3(256), 0, st, n, U, ld, v->wp.p, v->order.p, x);
+  double hres[2] = {0.0, 0.0};
+  if (ncols > 1) {
+    FSA_TRY(slq_terms(ah, bh, iters, ncols, 1, c_w, c_slq, nullptr, max_iter, st));
+    hipLaunchKernelGGL(k_vlogdet, dim3(1), dim3(64), 0, st, c_slq, 1, ncols, v->parts.p, res);
+    FSA_HIP(hipGetLastError());
+  }
+  std::vector<int> hit(ncols);
+  if (ncols > 1) FSA_HIP(hipMemcpyAsync(hres, res, sizeof(hres), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipMemcpyAsync(hit.data(), iters, ncols * sizeof(int), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
-  if (hinfo[0]) {
-    set_error("Cholesky of the FITC capacitance failed at column %d", hinfo[0] - 1);
-    return FSA_ERR_NOT_SPD;
+  if (logdet) *logdet = hres[0];
+  if (stats) {
+    *stats = fsa_vecchia_stats{};
+    stats->nlevels = (int32_t)v->lptr.size() - 1;
+    stats->iters_rhs = hit[0];
+    stats->iters_max = *std::max_element(hit.begin(), hit.end());
+    stats->converged = converged ? 1 : 0;
+    for (int c = 0; c < ncols; ++c) stats->probe_iters += hit[c];
+    stats->logdet_P = v->logdet_P;
+    stats->logdet_offset = v->offset;
+    stats->logdet_sw = hres[1];
+    stats->ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
-  if (hinfo[1]) {
-    set_error("FITC diagonal D_s has a non-positive or non-finite entry");
-    return FSA_ERR_NOT_SPD;
+  if (!converged) {
+    set_error("Vecchia solve: max_iter (%d) reached", max_iter);
+    return FSA_ERR_NOT_CONVERGED;
   }
-  v->logdet_P = hp[0] + hp[1];
-  v->offset = hp[2] - hp[3];
-  // parts[0] = log det P, parts[1] = sum log w - sum log D (read by k_vlogdet)
-  const double hp2[2] = {v->logdet_P, v->offset};
-  FSA_HIP(hipMemcpyAsync(v->parts.p, hp2, sizeof(hp2), hipMemcpyHostToDevice, st));
+  return FSA_OK;
+}
+
+// the three sums of k_vlaplace_parts (fixed order), read back to the host
+fsa_status laplace_sums(fsa_vecchia* v, int mode, const double* x, const double* b, const double* y, double out[3]) {
+  hipStream_t st = v->st;
+  const int G = (int)std::min<int64_t>(grid1(v->n), 256);
+  Buf<double> part;
+  FSA_TRY(part.alloc(3 * (size_t)G + 3));
+  hipLaunchKernelGGL(k_vlaplace_parts, dim3(G), dim3(256), 0, st, v->n, mode, x, b, y, part.p);
+  hipLaunchKernelGGL(k_vsum3, dim3(1), dim3(64), 0, st, part.p, G, part.p + 3 * (size_t)G);
+  FSA_HIP(hipGetLastError());
+  FSA_HIP(hipMemcpyAsync(out, part.p + 3 * (size_t)G, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   return FSA_OK;
 }
@@ -964,127 +1199,105 @@ fsa_status fsa_vecchia_solve_logdet_dev(fsa_vecchia* v, const double* rhs, doubl
   if (!fixed && (!(tol > 0.0) || !std::isfinite(tol))) { set_error("tol must be finite and positive"); return FSA_ERR_INVALID_ARG; }
   if (max_iter < 1 || max_iter > 6000) { set_error("max_iter must be in [1, 6000]"); return FSA_ERR_INVALID_ARG; }
   PoolStream ps(v->st);
+  return vsolve(v, rhs, x, num_probes, seed, tol, max_iter, fixed, logdet, stats);
+}
+
+fsa_status fsa_vecchia_laplace_dev(fsa_vecchia* v, const double* y, int32_t num_probes, uint64_t seed, double tol,
+                                   int32_t max_iter, int32_t fixed_iter, double newton_tol, int32_t max_newton,
+                                   int32_t fixed_newton, double* mode, double* nll,
+                                   fsa_vecchia_laplace_stats* stats) {
+  if (!v || !y || !mode || !nll) { set_error("null argument"); return FSA_ERR_INVALID_ARG; }
+  if (num_probes < 1 || num_probes > 1023) { set_error("num_probes must be in [1, 1023]"); return FSA_ERR_INVALID_ARG; }
+  if (fixed_iter < 0 || fixed_iter > 6000) { set_error("fixed_iter must be in [0, 6000]"); return FSA_ERR_INVALID_ARG; }
+  const int fixed = fixed_iter > 0 ? 1 : 0;
+  if (fixed) max_iter = fixed_iter;
+  if (!fixed && (!(tol > 0.0) || !std::isfinite(tol))) { set_error("tol must be finite and positive"); return FSA_ERR_INVALID_ARG; }
+  if (max_iter < 1 || max_iter > 6000) { set_error("max_iter must be in [1, 6000]"); return FSA_ERR_INVALID_ARG; }
+  if (fixed_newton < 0 || fixed_newton > 200) { set_error("fixed_newton must be in [0, 200]"); return FSA_ERR_INVALID_ARG; }
+  if (fixed_newton == 0 && (max_newton < 1 || max_newton > 200 || !(newton_tol > 0.0) || !std::isfinite(newton_tol))) {
+    set_error("need 1 <= max_newton <= 200 and a finite positive newton_tol");
+    return FSA_ERR_INVALID_ARG;
+  }
+  PoolStream ps(v->st);
   hipStream_t st = v->st;
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t n = v->n;
-  const int ncols = num_probes + 1;
-  const int64_t ld = round_up(ncols, 64);
-  const int ldw = (int)round_up(ncols, 64);
-  const size_t blk = (size_t)n * ld;
-  Buf<double> mem, Wm, G, Emat, col, hist;
-  Buf<int> ivec;
-  FSA_TRY(mem.alloc(8 * blk));
-  double* Bk = mem.p;
-  double* R = mem.p + blk;
-  double* H = mem.p + 2 * blk;
-  double* V = mem.p + 3 * blk;
-  double* Z = mem.p + 4 * blk;
-  double* U = mem.p + 5 * blk;
-  double* Q0 = mem.p + 6 * blk;
-  double* T = mem.p + 7 * blk;
-  FSA_TRY(Wm.alloc((size_t)v->mp * ldw));
-  FSA_TRY(G.alloc((size_t)v->mp * ldw));
-  FSA_TRY(Emat.alloc((size_t)v->mp * ldw));
-  // per column: [0] rz [1] bn2 [2] hv [3] alpha [4] beta [5] rzn [6] rr [7] weight [8] slq terms, then 2 results
-  FSA_TRY(col.alloc(9 * (size_t)ncols + 2));
-  double* c_rz = col.p;
-  double* c_bn2 = col.p + ncols;
-  double* c_hv = col.p + 2 * ncols;
-  double* c_alpha = col.p + 3 * ncols;
-  double* c_beta = col.p + 4 * ncols;
-  double* c_rzn = col.p + 5 * ncols;
-  double* c_rr = col.p + 6 * ncols;
-  double* c_w = col.p + 7 * ncols;
-  double* c_slq = col.p + 8 * ncols;
-  double* res = col.p + 9 * ncols;
-  FSA_TRY(hist.alloc(2 * (size_t)max_iter * ncols));
-  double* ah = hist.p;
-  double* bh = hist.p + (size_t)max_iter * ncols;
-  FSA_TRY(ivec.alloc(2 * (size_t)ncols + 2));
-  int* active = ivec.p;
-  int* iters = ivec.p + ncols;
-  int* flags = ivec.p + 2 * ncols;
-  FSA_HIP(hipMemsetAsync(mem.p, 0, 8 * blk * sizeof(double), st));
-  FSA_HIP(hipMemsetAsync(hist.p, 0, hist.bytes(), st));
-  // right-hand sides [Sigma_V v, z_1 .. z_t], z ~ (0, P) (App. F sampling recipe)
-  hipLaunchKernelGGL(k_vgather, dim3(grid1(n)), dim3(256), 0, st, n, 1, rhs, (int64_t)1, v->order.p, Q0, ld);
-  FSA_TRY(sigma_v(v, Q0, ld, 1, T, ld));
-  FSA_HIP(hipMemsetAsync(Q0, 0, blk * sizeof(double), st));
   {
-    Buf<double> y;
-    FSA_TRY(y.alloc(n));
-    FSA_HIP(hipMemcpy2DAsync(y.p, sizeof(double), T, ld * sizeof(double), sizeof(double), n,
-                             hipMemcpyDeviceToDevice, st));
-    FSA_HIP(hipMemsetAsync(T, 0, blk * sizeof(double), st));
-    // the Rademacher draws are keyed by the caller's point index (order[p])
-    FSA_TRY(make_probes(v->A.p, n, v->m, v->mp, v->Ds.p, y.p, v->order.p, seed, num_probes, Bk, (int)ld, Emat.p, st));
-    FSA_HIP(hipStreamSynchronize(st));  // y leaves scope
-  }
-  // init: R = B, Z = P^{-1} R, H = Q0 = Z
-  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Bk, ld, R, ld);
-  FSA_TRY(precond(v, R, ld, ncols, Z, T, Wm.p, G.p, ldw));
-  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Z, ld, H, ld);
-  hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Z, ld, Q0, ld);
-  FSA_TRY((coldot<double, double>(R, Z, n, (int)ld, ncols, c_rzn, v->scr, st)));
-  FSA_TRY((coldot<double, double>(Bk, Bk, n, (int)ld, ncols, c_bn2, v->scr, st)));
-  FSA_TRY((coldot<double, double>(Bk, Q0, n, (int)ld, ncols, c_w, v->scr, st)));
-  hipLaunchKernelGGL(k_vpcg_init, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_rzn, c_bn2, c_rz, active, iters, flags);
-  FSA_HIP(hipGetLastError());
-  const double tol2 = tol * tol;
-  int hflags[2] = {0, 0};
-  int it = 0;
-  bool converged = false;
-  for (; it < max_iter; ++it) {
-    FSA_TRY(operator_v(v, H, ld, ncols, V, ld));
-    FSA_TRY((coldot<double, double>(H, V, n, (int)ld, ncols, c_hv, v->scr, st)));
-    hipLaunchKernelGGL(k_vpcg_alpha, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_hv, c_rz, active, c_alpha, flags);
-    hipLaunchKernelGGL(k_vpcg_update, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, ld, c_alpha, H, V, U, R);
-    FSA_TRY(precond(v, R, ld, ncols, Z, T, Wm.p, G.p, ldw));
-    FSA_TRY((coldot<double, double>(R, Z, n, (int)ld, ncols, c_rzn, v->scr, st)));
-    FSA_TRY((coldot<double, double>(R, R, n, (int)ld, ncols, c_rr, v->scr, st)));
-    FSA_HIP(hipMemsetAsync(flags, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_vpcg_beta, dim3(grid1(ncols)), dim3(256), 0, st, ncols, c_rzn, c_rr, c_bn2, c_alpha, c_rz,
-                       c_beta, active, iters, ah, bh, max_iter, tol2, fixed, flags);
-    hipLaunchKernelGGL(k_vpcg_direction, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, ld, c_beta, Z, H);
+    int bad = 0;
+    FSA_HIP(hipMemsetAsync(v->info.p + 2, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_vcount_nonbinary, dim3(grid1(n)), dim3(256), 0, st, n, y, v->info.p + 2);
     FSA_HIP(hipGetLastError());
-    if (fixed && it + 1 < max_iter) continue;  // breakdowns are read after the last iteration
-    FSA_HIP(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    FSA_HIP(hipMemcpyAsync(&bad, v->info.p + 2, sizeof(int), hipMemcpyDeviceToHost, st));
     FSA_HIP(hipStreamSynchronize(st));
-    if (hflags[1]) {
-      set_error("CG breakdown in the Vecchia solve (h^T K h <= 0 or non-finite)");
-      return FSA_ERR_BREAKDOWN;
-    }
-    if (hflags[0] == 0 || fixed) {
-      converged = true;
-      ++it;
+    if (bad) { set_error("%d responses are not 0 or 1", bad); return FSA_ERR_INVALID_ARG; }
+  }
+  Buf<double> b, rhs, xn;
+  FSA_TRY(b.alloc(n));
+  FSA_TRY(rhs.alloc(n));
+  FSA_TRY(xn.alloc(n));
+  FSA_HIP(hipMemsetAsync(b.p, 0, n * sizeof(double), st));
+  fsa_vecchia_laplace_stats ls{};
+  bool soft_fail = false;
+  const int limit = fixed_newton > 0 ? fixed_newton : max_newton;
+  for (int k = 0; k < limit; ++k) {
+    // b <- (Sigma_V^{-1} + W)^{-1} (W b + y - pi), W and the preconditioner at the current b
+    hipLaunchKernelGGL(k_vnewton, dim3(grid1(n)), dim3(256), 0, st, n, b.p, y, 1, v->w.p, rhs.p);
+    FSA_HIP(hipGetLastError());
+    FSA_TRY(set_weights(v));
+    fsa_vecchia_stats vs{};
+    const fsa_status rc = vsolve(v, rhs.p, xn.p, 0, seed, tol, max_iter, fixed, nullptr, &vs);
+    if (rc == FSA_ERR_NOT_CONVERGED) soft_fail = true;
+    else FSA_TRY(rc);
+    ls.cg_iters_max = std::max(ls.cg_iters_max, vs.iters_max);
+    ls.probe_iters += vs.probe_iters;
+    double nrm[3];
+    FSA_TRY(laplace_sums(v, 0, xn.p, b.p, y, nrm));
+    FSA_HIP(hipMemcpyAsync(b.p, xn.p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    ++ls.newton_steps;
+    if (fixed_newton == 0 && std::sqrt(nrm[0]) <= newton_tol * std::sqrt(nrm[1])) {
+      ls.converged = 1;
       break;
     }
   }
-  // solution and log det
-  hipLaunchKernelGGL(k_vsolution, dim3(grid1(n)), dim3(256), 0, st, n, U, ld, v->wp.p, v->order.p, x);
-  FSA_TRY(slq_terms(ah, bh, iters, ncols, 1, c_w, c_slq, nullptr, max_iter, st));
-  hipLaunchKernelGGL(k_vlogdet, dim3(1), dim3(64), 0, st, c_slq, 1, ncols, v->parts.p, res);
+  // at the mode: W there, log det(Sigma_V^{-1} + W) by SLQ, the log-likelihood and b^T Sigma_V^{-1} b
+  hipLaunchKernelGGL(k_vnewton, dim3(grid1(n)), dim3(256), 0, st, n, b.p, y, 0, v->w.p, rhs.p);
   FSA_HIP(hipGetLastError());
-  double hres[2];
-  std::vector<int> hit(ncols);
-  FSA_HIP(hipMemcpyAsync(hres, res, sizeof(hres), hipMemcpyDeviceToHost, st));
-  FSA_HIP(hipMemcpyAsync(hit.data(), iters, ncols * sizeof(int), hipMemcpyDeviceToHost, st));
-  FSA_HIP(hipStreamSynchronize(st));
-  *logdet = hres[0];
-  if (stats) {
-    *stats = fsa_vecchia_stats{};
-    stats->nlevels = (int32_t)v->lptr.size() - 1;
-    stats->iters_rhs = hit[0];
-    stats->iters_max = *std::max_element(hit.begin(), hit.end());
-    stats->converged = converged ? 1 : 0;
-    for (int c = 0; c < ncols; ++c) stats->probe_iters += hit[c];
-    stats->logdet_P = v->logdet_P;
-    stats->logdet_offset = v->offset;
-    stats->logdet_sw = hres[1];
-    stats->ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  FSA_TRY(set_weights(v));
+  fsa_vecchia_stats vs{};
+  double ld = 0.0;
+  {
+    const fsa_status rc = vsolve(v, rhs.p, xn.p, num_probes, seed, tol, max_iter, fixed, &ld, &vs);
+    if (rc == FSA_ERR_NOT_CONVERGED) soft_fail = true;
+    else FSA_TRY(rc);
   }
-  if (!converged) {
-    set_error("Vecchia solve: max_iter (%d) reached", max_iter);
+  ls.cg_iters_max = std::max(ls.cg_iters_max, vs.iters_max);
+  ls.probe_iters += vs.probe_iters;
+  double ll[3], qd[3];
+  FSA_TRY(laplace_sums(v, 1, nullptr, b.p, y, ll));
+  {
+    Buf<double> bp, qb;
+    FSA_TRY(bp.alloc(n));
+    FSA_TRY(qb.alloc(n));
+    hipLaunchKernelGGL(k_vgather, dim3(grid1(n)), dim3(256), 0, st, n, 1, b.p, (int64_t)1, v->order.p, bp.p,
+                       (int64_t)1);
+    FSA_TRY(precision_v(v, bp.p, 1, 1, qb.p, 1));
+    FSA_TRY(laplace_sums(v, 2, qb.p, bp.p, nullptr, qd));
+  }
+  FSA_HIP(hipMemcpyAsync(mode, b.p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  FSA_HIP(hipStreamSynchronize(st));
+  ls.loglik = ll[0];
+  ls.quad = qd[0];
+  ls.sum_log_d = v->sum_log_dv;
+  ls.logdet = ld;
+  *nll = -ls.loglik + 0.5 * ls.quad + 0.5 * (ls.sum_log_d + ls.logdet);
+  ls.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = ls;
+  if (soft_fail) {
+    set_error("Vecchia-Laplace: a PCG solve reached max_iter (%d)", max_iter);
+    return FSA_ERR_NOT_CONVERGED;
+  }
+  if (fixed_newton == 0 && !ls.converged) {
+    set_error("Vecchia-Laplace: the mode did not converge in %d Newton steps", max_newton);
     return FSA_ERR_NOT_CONVERGED;
   }
   return FSA_OK;

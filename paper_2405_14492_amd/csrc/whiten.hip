@@ -1,0 +1,334 @@
+// Hand-written float64 kernels of the low-rank factor (Section 2.1) and its
+// derivative (eq. NEGLLDNEGLLFSA):
+//  - the inverse of a lower-triangular mp x mp factor (L_m, L_C, the
+//    prediction factor of Algorithm 1), blocked by 64;
+//  - products Y = X W^T of a tall point-major block X (n x K) with the
+//    transpose of a lower-triangular mp x K matrix W, on the float64 MFMA,
+//    with X either read from memory or generated on the fly as the
+//    covariance (or its rho-derivative) between the points and the inducing
+//    points.  The whitened factor A = L_m^{-1} Sigma_mn is Sigma_nm L_m^{-T}
+//    with Sigma_nm never stored; the derivative factor
+//    F = L_m^{-1} dSigma_mn - Phi(E) A is one product over [dSigma_nm | A]
+//    against [L_m^{-T} ; -Phi(E)^T].
+#include "common.hpp"
+#include "kernels.hpp"
+#include "ops.hpp"
+
+namespace fsa {
+
+// ---------------------------------------------------------------- triangular inverse
+// Inverse of each 64 x 64 diagonal block of a lower-triangular L (row-major,
+// mp x mp): forward substitution, one thread per column of the block.
+__global__ __launch_bounds__(64) void k_trinv_diag(const double* __restrict__ L, int mp, double* __restrict__ Linv) {
+  __shared__ double Lb[64][65];
+  __shared__ double Xb[64][65];
+  const int c = threadIdx.x;
+  const int64_t o = (int64_t)blockIdx.x * 64;
+  for (int r = 0; r < 64; ++r) Lb[r][c] = L[(o + r) * mp + o + c];
+  __syncthreads();
+  for (int r = 0; r < 64; ++r) {
+    double s = 0.0;
+    if (r >= c) {
+      s = r == c ? 1.0 : 0.0;
+      for (int k = c; k < r; ++k) s -= Lb[r][k] * Xb[k][c];
+      s /= Lb[r][r];
+    }
+    Xb[r][c] = s;
+  }
+  __syncthreads();
+  for (int r = 0; r < 64; ++r) Linv[(o + r) * mp + o + c] = Xb[r][c];
+}
+
+// Block column j of L^{-1} below the diagonal block, in order i = j+1..nb-1:
+// X_ij = -inv(L_ii) sum_{k=j}^{i-1} L_ik X_kj (X_jj from k_trinv_diag); the
+// blocks above the diagonal are cleared.  256 threads, a 4 x 4 register tile
+// each.  X_kj is read back after this workgroup wrote it (workgroup scope).
+__global__ __launch_bounds__(256) void k_trinv_off(const double* __restrict__ L, int mp, double* __restrict__ Linv) {
+  __shared__ double As[64][65];
+  __shared__ double Bs[64][65];
+  const int j = blockIdx.x, nb = mp / 64, tid = threadIdx.x;
+  const int tr = tid / 16, tc = tid % 16;
+  for (int i = 0; i < j; ++i)
+    for (int e = tid; e < 64 * 64; e += 256)
+      Linv[(int64_t)(i * 64 + e / 64) * mp + j * 64 + e % 64] = 0.0;
+  for (int i = j + 1; i < nb; ++i) {
+    double acc[4][4] = {};
+    for (int k = j; k < i; ++k) {
+      for (int e = tid; e < 64 * 64; e += 256) {
+        const int r = e / 64, q = e % 64;
+        As[r][q] = L[(int64_t)(i * 64 + r) * mp + k * 64 + q];
+        Bs[r][q] = Linv[(int64_t)(k * 64 + r) * mp + j * 64 + q];
+      }
+      __syncthreads();
+      for (int q = 0; q < 64; ++q) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = As[tr * 4 + u][q];
+          b[u] = Bs[q][tc * 4 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+      }
+      __syncthreads();
+    }
+    // X_ij = -inv(L_ii) T
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int r = e / 64, q = e % 64;
+      As[r][q] = Linv[(int64_t)(i * 64 + r) * mp + i * 64 + q];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Bs[tr * 4 + u][tc * 4 + v] = acc[u][v];
+    __syncthreads();
+    double out[4][4] = {};
+    for (int q = 0; q < 64; ++q) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = As[tr * 4 + u][q];
+        b[u] = Bs[q][tc * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[u][v] -= a[u] * b[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Linv[(int64_t)(i * 64 + tr * 4 + u) * mp + j * 64 + tc * 4 + v] = out[u][v];
+    __syncthreads();
+  }
+}
+
+fsa_status tri_inverse(const double* L, double* Linv, int mp, hipStream_t st) {
+  if (mp % 64 || mp <= 0 || mp > 512) {
+    set_error("tri_inverse: mp must be a multiple of 64 in [64, 512]");
+    return FSA_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_trinv_diag, dim3(mp / 64), dim3(64), 0, st, L, mp, Linv);
+  hipLaunchKernelGGL(k_trinv_off, dim3(mp / 64), dim3(256), 0, st, L, mp, Linv);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// ---------------------------------------------------------------- Y = X W^T, W lower triangular
+// Workgroup: 64 points x 256 output columns, 8 waves.  Wave w takes point
+// half ph = w / 4 (32 points, two 16-row MFMA tiles) and column quarter
+// cq = w % 4 for w < 4, 3 - w % 4 for w >= 4 (64 columns, four 16-column
+// tiles), so the two waves on one SIMD (w and w + 4) together cover
+// quarters q and 3 - q: with W lower triangular, the column quarter
+// [c0, c0 + 64) needs k < c0 + 64 only, and the pair's work is the same on
+// every SIMD.  K runs in chunks of 16 through double-buffered LDS: X as
+// Xs[k][point], W^T as Ws[k][column], both read by the MFMA 16x16x4 lanes
+// (lane l: A[l % 16][l / 16], B[l / 16][l % 16]).
+constexpr int WG_PTS = 64;
+constexpr int WG_COLS = 256;
+constexpr int WG_KC = 16;
+constexpr int XS_LD = WG_PTS + 2;
+constexpr int WS_LD = WG_COLS + 4;
+
+enum { XSRC_MEM = 0, XSRC_COV = 1, XSRC_DCOV = 2 };
+
+struct WgemmSeg {
+  int src;             // XSRC_*
+  const double* X;     // XSRC_MEM: point-major n x ldx
+  int64_t ldx;
+  const double* Wt;    // K x mp row-major (Wt[k][j] = W[j][k]), zero for k > j
+};
+
+struct WgemmArgs {
+  int64_t n;
+  int mp, m, nseg;
+  WgemmSeg seg[2];
+  const double* xs;    // point coordinates (covariance sources)
+  const double* ind;   // inducing coordinates (padded to mp)
+  Theta th;
+  double* Y;           // n x mp point-major
+};
+
+__global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
+  __shared__ double Xs[2][WG_KC][XS_LD];
+  __shared__ double Ws[2][WG_KC][WS_LD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ph = w >> 2, cq = w < 4 ? (w & 3) : 3 - (w & 3);
+  const int64_t p0 = (int64_t)blockIdx.x * WG_PTS;
+  const int jb = blockIdx.y * WG_COLS;
+  const int ncolw = min(WG_COLS, a.mp - jb);  // 64, 128, 192 or 256
+  const int jw = jb + cq * 64;                // this wave's first column
+  const bool wave_on = cq * 64 < ncolw;
+  // the chunks each segment needs: k < jb + ncolw (W lower triangular)
+  const int kneed = min(a.mp, jb + ncolw);
+  const int nch_seg = kneed / WG_KC;
+  const int nch = nch_seg * a.nseg;
+
+  // staging of one chunk: X (64 x 16) and W^T (16 x ncolw)
+  // X: thread t < 512 takes point t / 8 and k pair 2 (t % 8)
+  const int xp = tid >> 3, xk = (tid & 7) * 2;
+  double px = 0.0, py = 0.0;
+  const bool xrow_ok = p0 + xp < a.n;
+  if (xrow_ok) {
+    px = a.xs ? a.xs[2 * (p0 + xp)] : 0.0;
+    py = a.xs ? a.xs[2 * (p0 + xp) + 1] : 0.0;
+  }
+  // W: thread t takes k row t / 32 and columns 8 (t % 32) .. + 8
+  const int wk = tid >> 5, wc = (tid & 31) * 8;
+  double xr[2], wr[8];
+  auto load = [&](int c) {
+    const int s = c / nch_seg, k0 = (c % nch_seg) * WG_KC;
+    const WgemmSeg& sg = a.seg[s];
+    if (sg.src == XSRC_MEM) {
+      xr[0] = xr[1] = 0.0;
+      if (xrow_ok) {
+        const d2 v = *reinterpret_cast<const d2*>(sg.X + (p0 + xp) * sg.ldx + k0 + xk);
+        xr[0] = v[0];
+        xr[1] = v[1];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = k0 + xk + u;
+        double v = 0.0;
+        if (xrow_ok && k < a.m) {
+          const double dx = px - a.ind[2 * k], dy = py - a.ind[2 * k + 1];
+          const double d = sqrt(dx * dx + dy * dy);
+          v = sg.src == XSRC_COV ? cov_d(d, a.th) : dcov_drho(d, a.th);
+        }
+        xr[u] = v;
+      }
+    }
+    if (wc < ncolw) {
+      const d2* src = reinterpret_cast<const d2*>(sg.Wt + (int64_t)(k0 + wk) * a.mp + jb + wc);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const d2 v = src[u];
+        wr[2 * u] = v[0];
+        wr[2 * u + 1] = v[1];
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    Xs[buf][xk][xp] = xr[0];
+    Xs[buf][xk + 1][xp] = xr[1];
+    if (wc < ncolw) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Ws[buf][wk][wc + u] = wr[u];
+    }
+  };
+
+  typedef Mfma<double>::acc acc_t;
+  acc_t acc[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = acc_t{0.0, 0.0, 0.0, 0.0};
+
+  if (nch > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) load(c + 1);
+    const int k0 = (c % nch_seg) * WG_KC;
+    // W lower triangular: columns [jw, jw + 64) need k < jw + 64
+    if (wave_on && k0 < jw + 64) {
+#pragma unroll
+      for (int ks = 0; ks < WG_KC / 4; ++ks) {
+        const int kk = ks * 4 + (lane >> 4);
+        double av[2], bv[4];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) av[r] = Xs[buf][kk][ph * 32 + r * 16 + (lane & 15)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bv[q] = Ws[buf][kk][cq * 64 + q * 16 + (lane & 15)];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[r][q] = Mfma<double>::op(av[r], bv[q], acc[r][q]);
+      }
+    }
+    if (c + 1 < nch) store(buf ^ 1);
+    __syncthreads();
+  }
+  if (!wave_on) return;
+  // lane l, register e holds row (l / 16) + 4 e, column l % 16 of each tile
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t p = p0 + ph * 32 + r * 16 + Mfma<double>::orow(lane >> 4, e);
+      if (p >= a.n) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a.Y[p * a.mp + jw + q * 16 + (lane & 15)] = acc[r][q][e];
+    }
+}
+
+static fsa_status launch_wgemm(const WgemmArgs& a, hipStream_t st) {
+  if (a.n <= 0) return FSA_OK;
+  if (a.mp % 64 || a.mp <= 0 || a.mp > 512) {
+    set_error("wgemm: mp must be a multiple of 64 in [64, 512]");
+    return FSA_ERR_INVALID_ARG;
+  }
+  for (int s = 0; s < a.nseg; ++s)
+    if (a.seg[s].src == XSRC_MEM && ((a.seg[s].ldx & 1) || (reinterpret_cast<uintptr_t>(a.seg[s].X) & 15))) {
+      set_error("wgemm: X rows must be 16-byte aligned");
+      return FSA_ERR_INVALID_ARG;
+    }
+  dim3 grid((unsigned)ceil_div(a.n, WG_PTS), (unsigned)ceil_div(a.mp, WG_COLS));
+  hipLaunchKernelGGL(k_wgemm, grid, dim3(512), 0, st, a);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
+// A = Sigma_nm L_m^{-T} (point-major n x mp): LminvT = (L_m^{-1})^T, mp x mp row-major.
+fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
+                  const double* LminvT, double* A_out, hipStream_t st) {
+  WgemmArgs a{};
+  a.n = n;
+  a.mp = mp;
+  a.m = m;
+  a.nseg = 1;
+  a.seg[0] = WgemmSeg{XSRC_COV, nullptr, 0, LminvT};
+  a.xs = xs;
+  a.ind = ind;
+  a.th = th;
+  a.Y = A_out;
+  return launch_wgemm(a, st);
+}
+
+// F = dSigma_nm L_m^{-T} - A Phi(E)^T: LminvT as above, PhiT_neg = -Phi(E)^T (mp x mp row-major).
+fsa_status derivative_factor(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
+                             const double* LminvT, const double* A, const double* PhiT_neg, double* F_out,
+                             hipStream_t st) {
+  WgemmArgs a{};
+  a.n = n;
+  a.mp = mp;
+  a.m = m;
+  a.nseg = 2;
+  a.seg[0] = WgemmSeg{XSRC_DCOV, nullptr, 0, LminvT};
+  a.seg[1] = WgemmSeg{XSRC_MEM, A, mp, PhiT_neg};
+  a.xs = xs;
+  a.ind = ind;
+  a.th = th;
+  a.Y = F_out;
+  return launch_wgemm(a, st);
+}
+
+// Y = X W^T for point-major X (n x mp) and lower-triangular W given as WT = W^T.
+fsa_status rows_times_lower_t(const double* X, int64_t n, int mp, const double* WT, double* Y, hipStream_t st) {
+  WgemmArgs a{};
+  a.n = n;
+  a.mp = mp;
+  a.m = mp;
+  a.nseg = 1;
+  a.seg[0] = WgemmSeg{XSRC_MEM, X, mp, WT};
+  a.Y = Y;
+  return launch_wgemm(a, st);
+}
+
+}  // namespace fsa

@@ -36,7 +36,9 @@ EXPORTED = ["fsa_default_options", "fsa_build", "fsa_build_dev", "fsa_nll_grad",
             "fsa_apply",
             "fsa_pool_trim", "fsa_scores", "fsa_scores_noalloc", "fsa_set_allocator", "fsa_nll_grad_dev",
             "fsa_vecchia_build_dev", "fsa_vecchia_factor_dev", "fsa_vecchia_apply_dev", "fsa_vecchia_solve_logdet_dev",
-            "fsa_vecchia_destroy"]
+            "fsa_vecchia_destroy", "fsa_vecchia_laplace_dev",
+            "fsa_request_footprint", "fsa_server_create", "fsa_server_clock_ms", "fsa_server_submit",
+            "fsa_server_wait", "fsa_server_get_stats", "fsa_server_destroy"]
 
 
 class FsaError(RuntimeError):
@@ -59,7 +61,7 @@ class fsa_options(C.Structure):
                 ("max_iter", C.c_int32), ("fixed_iter", C.c_int32), ("precision", C.c_int32),
                 ("rr_period", C.c_int32), ("slq_weight_n", C.c_int32), ("profile", C.c_int32),
                 ("sigma_m_jitter", C.c_double),
-                ("hip_stream", C.c_void_p)]
+                ("hip_stream", C.c_void_p), ("graph", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class fsa_stats(C.Structure):
@@ -82,6 +84,15 @@ class fsa_vecchia_stats(C.Structure):
     _fields_ = [("nlevels", C.c_int32), ("iters_max", C.c_int32), ("iters_rhs", C.c_int32), ("converged", C.c_int32),
                 ("probe_iters", C.c_int64), ("logdet_P", C.c_double), ("logdet_offset", C.c_double), ("logdet_sw", C.c_double),
                 ("ms_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fsa_vecchia_laplace_stats(C.Structure):
+    _fields_ = [("newton_steps", C.c_int32), ("converged", C.c_int32), ("cg_iters_max", C.c_int32),
+                ("reserved0", C.c_int32), ("probe_iters", C.c_int64), ("loglik", C.c_double), ("quad", C.c_double),
+                ("sum_log_d", C.c_double), ("logdet", C.c_double), ("ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -150,6 +161,23 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.fsa_vecchia_solve_logdet_dev.restype = C.c_int
     lib.fsa_vecchia_destroy.argtypes = [vp]
     lib.fsa_vecchia_destroy.restype = C.c_int
+    lib.fsa_vecchia_laplace_dev.argtypes = [vp, vp, C.c_int32, C.c_uint64, C.c_double, C.c_int32, C.c_int32,
+                                            C.c_double, C.c_int32, C.c_int32, vp, dp, P(fsa_vecchia_laplace_stats)]
+    lib.fsa_vecchia_laplace_dev.restype = C.c_int
+    lib.fsa_request_footprint.argtypes = [P(fsa_request), P(fsa_options), P(C.c_uint64)]
+    lib.fsa_request_footprint.restype = C.c_int
+    lib.fsa_server_create.argtypes = [P(fsa_server_options), P(vp)]
+    lib.fsa_server_create.restype = C.c_int
+    lib.fsa_server_clock_ms.argtypes = [vp]
+    lib.fsa_server_clock_ms.restype = C.c_double
+    lib.fsa_server_submit.argtypes = [vp, P(fsa_request), P(C.c_int64)]
+    lib.fsa_server_submit.restype = C.c_int
+    lib.fsa_server_wait.argtypes = [vp, C.c_int64, P(fsa_result), dp]
+    lib.fsa_server_wait.restype = C.c_int
+    lib.fsa_server_get_stats.argtypes = [vp, P(fsa_server_stats)]
+    lib.fsa_server_get_stats.restype = C.c_int
+    lib.fsa_server_destroy.argtypes = [vp]
+    lib.fsa_server_destroy.restype = None
     return lib
 
 
@@ -188,7 +216,8 @@ def make_theta(theta) -> fsa_theta:
 
 
 def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, precision=FP64, rr_period=10,
-                 slq_weight_n=False, jitter=0.0, stream=None, profile=False, control_variate=CV_NONE) -> fsa_options:
+                 slq_weight_n=False, jitter=0.0, stream=None, profile=False, control_variate=CV_NONE,
+                 graph=False) -> fsa_options:
     o = fsa_options()
     lib().fsa_default_options(C.byref(o))
     o.num_probes = int(num_probes)
@@ -204,6 +233,7 @@ def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, p
     # True: every kernel class; an int: the class bit mask itself
     o.profile = PROFILE_ALL if profile is True else int(profile)
     o.control_variate = int(control_variate)
+    o.graph = int(bool(graph))
     return o
 
 
@@ -419,9 +449,9 @@ class FSA:
 
     def __init__(self, locs, y, theta, inducing, taper_range, num_probes=50, seed=0, tol=1e-8, max_iter=1000,
                  fixed_iter=0, precision=FP64, rr_period=10, slq_weight_n=False, jitter=0.0, stream=None,
-                 device=False, profile=False, control_variate=CV_NONE):
+                 device=False, profile=False, control_variate=CV_NONE, graph=False):
         self.opt = make_options(num_probes, seed, tol, max_iter, fixed_iter, precision, rr_period, slq_weight_n,
-                                jitter, stream, profile, control_variate)
+                                jitter, stream, profile, control_variate, graph)
         self.n = int(locs.shape[0])
         self.theta = tuple(theta)
         build = fsa_build_dev if device else fsa_build
@@ -561,3 +591,142 @@ class Vecchia:
                                                   C.byref(st)),
                allow_not_converged)
         return x, ld.value, st.as_dict()
+
+    def laplace(self, y, num_probes, seed, tol=1e-8, max_iter=1000, fixed_iter=0, newton_tol=1e-8, max_newton=50,
+                fixed_newton=0, allow_not_converged=False):
+        """Vecchia-Laplace NLL of Bernoulli responses y (float64 0/1 device
+        tensor): (mode, nll, stats).  The handle's weights become those at
+        the mode."""
+        yy = y.contiguous()
+        mode = self._torch.empty_like(yy)
+        nll = C.c_double()
+        st = fsa_vecchia_laplace_stats()
+        self._order_after_caller()
+        _check(lib().fsa_vecchia_laplace_dev(self._h, yy.data_ptr(), int(num_probes), int(seed), float(tol),
+                                             int(max_iter), int(fixed_iter), float(newton_tol), int(max_newton),
+                                             int(fixed_newton), mode.data_ptr(), C.byref(nll), C.byref(st)),
+               allow_not_converged)
+        return mode, nll.value, st.as_dict()
+
+
+# ---------------------------------------------------------------- serving
+REQ_NLL_GRAD, REQ_PREDICT_VAR = 0, 1
+
+
+class fsa_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("m", C.c_int32), ("n", C.c_int64), ("locs", C.c_void_p), ("y", C.c_void_p),
+                ("inducing", C.c_void_p), ("theta", fsa_theta), ("taper_range", C.c_double), ("n_p", C.c_int64),
+                ("pred_locs", C.c_void_p), ("num_samples", C.c_int32), ("reserved0", C.c_int32),
+                ("arrival_ms", C.c_double)]
+
+
+class fsa_server_options(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("reserved0", C.c_int32), ("hbm_budget", C.c_uint64), ("opt", fsa_options)]
+
+
+class fsa_result(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("kind", C.c_int32), ("nll", C.c_double),
+                ("grad", C.c_double * 3), ("arrival_ms", C.c_double), ("admit_ms", C.c_double),
+                ("done_ms", C.c_double), ("footprint", C.c_uint64), ("peak_bytes", C.c_uint64),
+                ("worker", C.c_int32), ("iters_max", C.c_int32), ("probe_iters", C.c_int64), ("n_p", C.c_int64),
+                ("message", C.c_char * 192)]
+
+
+class fsa_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("hbm_budget", C.c_uint64), ("peak_reserved", C.c_uint64), ("slots", C.c_int32),
+                ("peak_active", C.c_int32), ("first_arrival_ms", C.c_double), ("last_done_ms", C.c_double)]
+
+
+def _request(kind, locs, y, theta, inducing, taper_range, pred_locs=None, num_samples=0, arrival_ms=0.0):
+    locs, y, inducing = _f64(locs), _f64(y).ravel(), _f64(inducing)
+    r = fsa_request()
+    r.kind = kind
+    r.n = locs.shape[0]
+    r.m = inducing.shape[0]
+    r.locs, r.y, r.inducing = locs.ctypes.data, y.ctypes.data, inducing.ctypes.data
+    r.theta = make_theta(theta)
+    r.taper_range = float(taper_range)
+    keep = [locs, y, inducing]
+    if kind == REQ_PREDICT_VAR:
+        pred = _f64(pred_locs)
+        r.n_p = pred.shape[0]
+        r.pred_locs = pred.ctypes.data
+        r.num_samples = int(num_samples)
+        keep.append(pred)
+    r.arrival_ms = float(arrival_ms)
+    return r, keep
+
+
+def request_footprint(kind, locs, y, theta, inducing, taper_range, pred_locs=None, num_samples=0, **opts):
+    """Device bytes fsa_request_footprint reserves for a request."""
+    r, keep = _request(kind, locs, y, theta, inducing, taper_range, pred_locs, num_samples)
+    o = make_options(**opts)
+    b = C.c_uint64()
+    _check(lib().fsa_request_footprint(C.byref(r), C.byref(o), C.byref(b)))
+    del keep
+    return int(b.value)
+
+
+class Server:
+    """A serving loop on the current GPU (fsa_server_*): `slots` workers with
+    a stream each, admission by footprint against `hbm_budget` bytes of device
+    memory reserved at creation.  Solver options as for FSA (precision,
+    num_probes, seed, tol, ...)."""
+
+    def __init__(self, slots=4, hbm_budget=64 << 30, **opts):
+        o = fsa_server_options()
+        o.slots = int(slots)
+        o.hbm_budget = int(hbm_budget)
+        o.opt = make_options(**opts)
+        h = C.c_void_p()
+        _check(lib().fsa_server_create(C.byref(o), C.byref(h)))
+        self.h = h
+        self._np = {}
+
+    def clock_ms(self):
+        return lib().fsa_server_clock_ms(self.h)
+
+    def submit(self, kind, locs, y, theta, inducing, taper_range, pred_locs=None, num_samples=0, arrival_ms=None):
+        """Queue a request (its arrays are copied); returns its id."""
+        r, keep = _request(kind, locs, y, theta, inducing, taper_range, pred_locs, num_samples,
+                           self.clock_ms() if arrival_ms is None else arrival_ms)
+        i = C.c_int64()
+        _check(lib().fsa_server_submit(self.h, C.byref(r), C.byref(i)))
+        del keep
+        self._np[i.value] = r.n_p
+        return i.value
+
+    def wait(self, rid):
+        """Block until request `rid` is done: (result dict, variances or None)."""
+        res = fsa_result()
+        n_p = self._np.pop(rid, 0)
+        var = np.zeros(max(n_p, 1))
+        _check(lib().fsa_server_wait(self.h, rid, C.byref(res), _dptr(var)))
+        d = {k: getattr(res, k) for k, _ in fsa_result._fields_}
+        d["grad"] = np.array(res.grad[:])
+        d["message"] = res.message.decode(errors="replace")
+        d["status_name"] = STATUS.get(res.status, res.status)
+        return d, (var[:n_p] if n_p else None)
+
+    def stats(self):
+        st = fsa_server_stats()
+        _check(lib().fsa_server_get_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in fsa_server_stats._fields_}
+
+    def close(self):
+        if self.h:
+            lib().fsa_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

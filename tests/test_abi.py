@@ -21,7 +21,7 @@ def L():
 
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "fsa.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:fsa_status|void|int64_t|const char\*)\s*(fsa_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:fsa_status|void|int64_t|double|const char\*)\s*(fsa_\w+)\s*\(", src, re.M)))
 
 
 def test_every_declared_symbol_is_exported(L):
@@ -51,12 +51,13 @@ def test_header_constants_match_binding(L):
 
 def test_struct_layouts(L):
     from paper_2405_14492_amd import fsa
-    # fsa_options: 2 x int32, uint64, double, 6 x int32, double, void*
-    assert ctypes.sizeof(fsa.fsa_options) == 64
+    # fsa_options: 2 x int32, uint64, double, 6 x int32, double, void*, 2 x int32
+    assert ctypes.sizeof(fsa.fsa_options) == 72
     assert ctypes.sizeof(fsa.fsa_theta) == 32
     o = fsa.fsa_options()
     L.fsa_default_options(ctypes.byref(o))
     assert o.num_probes == 50 and o.cg_rel_tol == 1e-8 and o.max_iter == 1000 and o.precision == 0
+    assert o.graph == 0
     assert o.control_variate == 0
 
 

@@ -157,3 +157,104 @@ def test_slq_estimate_near_dense_logdet():
     out = V.solve_logdet(M, np.ones(300), 200, seed=9, tol=1e-10, max_iter=300)
     se = np.std(out["slq_terms"]) / np.sqrt(200)
     assert abs(out["logdet"] - exact) < 4 * se + 1e-8
+
+
+# ---------------------------------------------------------------- Vecchia-Laplace (Bernoulli-logit)
+def bernoulli_case(n=180, mv=8, m=20, seed=3, theta=TH):
+    locs = G.uniform_locations(n, seed)
+    ind = G.random_subset_inducing(locs, m, seed + 1)
+    M = V.Vecchia(locs, ind, theta, mv, np.full(n, 0.25))
+    rng = np.random.default_rng(seed + 2)
+    # responses from a smooth latent field, so the mode is not trivial
+    field = np.sin(6 * locs[:, 0]) + np.cos(5 * locs[:, 1])
+    y = (rng.uniform(size=n) < 1.0 / (1.0 + np.exp(-2.0 * field))).astype(np.float64)
+    return M, y
+
+
+def test_laplace_mode_matches_a_general_optimizer():
+    """The Newton/CG mode equals the minimiser of -log p(y|b) + b^T Q b / 2
+    (Q = B^T D^{-1} B) found by scipy's trust-region method on the dense
+    objective."""
+    from scipy.optimize import minimize
+    M, y = bernoulli_case()
+    Q = (M.B.T @ sp_diag(1.0 / M.Dv) @ M.B).toarray()
+
+    def f(b):
+        return -V.bernoulli_loglik(y, b) + 0.5 * b @ Q @ b
+
+    def g(b):
+        return -(y - V.logistic(b)) + Q @ b
+
+    def h(b):
+        p = V.logistic(b)
+        return Q + np.diag(p * (1 - p))
+
+    opt = minimize(f, np.zeros(M.n), jac=g, hess=h, method="trust-exact", options={"gtol": 1e-12})
+    out = V.laplace(M, y, 4, seed=1, tol=1e-13, max_iter=500, newton_tol=1e-12)
+    assert out["converged"]
+    assert np.linalg.norm(out["mode"] - opt.x) <= 1e-8 * np.linalg.norm(opt.x)
+
+
+def sp_diag(v):
+    import scipy.sparse as sp
+    return sp.diags(v)
+
+
+def test_laplace_mode_is_stationary():
+    """At the mode, Sigma_V^{-1} b = y - pi(b) (checked with the sparse
+    factor, no solve)."""
+    M, y = bernoulli_case(seed=5, theta=(F.EXPONENTIAL, 1.5, 0.2))
+    out = V.laplace(M, y, 4, seed=2, tol=1e-13, max_iter=500, newton_tol=1e-12)
+    b = out["mode"]
+    r = M.prec_matvec(b) - (y - V.logistic(b))
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(y - V.logistic(b))
+
+
+def test_laplace_nll_matches_dense_laplace():
+    """NLL = -log p(y|b) + b^T Sigma_V^{-1} b / 2 + log det(I + Sigma_V W) / 2:
+    its deterministic part equals the dense evaluation, and the SLQ term lands
+    within a few standard errors of the dense log-determinant."""
+    M, y = bernoulli_case(n=240, seed=7)
+    t = 400
+    out = V.laplace(M, y, t, seed=3, tol=1e-12, max_iter=500, newton_tol=1e-12)
+    b = out["mode"]
+    B = M.B.toarray()
+    SV = np.linalg.inv(B.T @ np.diag(1.0 / M.Dv) @ B)
+    p = V.logistic(b)
+    W = p * (1 - p)
+    exact_ld = np.linalg.slogdet(np.eye(M.n) + SV * W[None, :])[1]
+    quad = b @ np.linalg.solve(SV, b)
+    det_part = -V.bernoulli_loglik(y, b) + 0.5 * quad
+    assert abs(out["quad"] - quad) <= 1e-8 * abs(quad)
+    assert abs(-out["loglik"] + 0.5 * out["quad"] - det_part) <= 1e-10 * abs(det_part)
+    # log det(I + Sigma_V W) = sum log D + log det(Sigma_V^{-1} + W)
+    se = np.std(out["slq_terms"]) / np.sqrt(t)
+    assert abs(out["sum_log_d"] + out["logdet"] - exact_ld) < 4 * se + 1e-8
+    exact_nll = det_part + 0.5 * exact_ld
+    assert abs(out["nll"] - exact_nll) < 2 * se + 1e-8
+
+
+def test_laplace_one_point_is_the_textbook_formula():
+    """n = 1: the Laplace approximation of int p(y|b) N(b; 0, s) db is
+    p(y|b*) N(b*; 0, s) sqrt(2 pi / H), H = 1/s + pi (1 - pi) at the mode b*,
+    which solves b/s = y - pi(b) (found here by bisection)."""
+    s = 1.7
+    locs = np.array([[0.3, 0.6]])
+    M = V.Vecchia(locs, locs, (F.EXPONENTIAL, s, 0.2), 0, np.array([0.25]))
+    for yv in (0.0, 1.0):
+        y = np.array([yv])
+        lo, hi = -20.0, 20.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if mid / s - (yv - V.logistic(mid)) > 0:
+                hi = mid
+            else:
+                lo = mid
+        bs = 0.5 * (lo + hi)
+        p = V.logistic(bs)
+        H = 1.0 / s + p * (1 - p)
+        log_lp = yv * bs - np.logaddexp(0.0, bs) - 0.5 * np.log(2 * np.pi * s) - bs * bs / (2 * s)
+        textbook = -(log_lp + 0.5 * np.log(2 * np.pi / H))
+        out = V.laplace(M, y, 1, seed=0, tol=1e-14, max_iter=5, newton_tol=1e-14)
+        assert abs(out["mode"][0] - bs) < 1e-10
+        assert abs(out["nll"] - textbook) < 1e-10 * abs(textbook)

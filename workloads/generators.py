@@ -99,11 +99,7 @@ def rff_response(locs: np.ndarray, kind: int, sigma1_sq: float, rho: float, sigm
     Student-t with 2 nu degrees of freedom scaled by 1/rho, i.e.
     w = g sqrt(2 nu / u) / rho with g ~ N(0, I_2) and u ~ chi^2_{2 nu}."""
     rng = np.random.default_rng(seed)
-    nu = 0.5 if kind == EXPONENTIAL else 1.5
-    g = rng.standard_normal((n_features, 2))
-    u = rng.chisquare(2 * nu, size=n_features)
-    w = g * (np.sqrt(2 * nu / u) / rho)[:, None]
-    b = rng.uniform(0, 2 * np.pi, n_features)
+    w, b = _rff_frequencies(rng, kind, rho, n_features)
     y = np.empty(locs.shape[0])
     amp = math.sqrt(2 * sigma1_sq / n_features)
 
@@ -114,6 +110,29 @@ def rff_response(locs: np.ndarray, kind: int, sigma1_sq: float, rho: float, sigm
     _parallel(chunk, range(0, locs.shape[0], 8192))
     y += math.sqrt(sigma_sq) * rng.standard_normal(locs.shape[0])
     return y
+
+
+def _rff_frequencies(rng, kind, rho, n_features):
+    nu = 0.5 if kind == EXPONENTIAL else 1.5
+    g = rng.standard_normal((n_features, 2))
+    u = rng.chisquare(2 * nu, size=n_features)
+    w = g * (np.sqrt(2 * nu / u) / rho)[:, None]
+    b = rng.uniform(0, 2 * np.pi, n_features)
+    return w, b
+
+
+def rff_response_torch(torch):
+    """rff_response with the feature sum on torch's current CUDA device (the
+    same draws; equal up to rounding): for generating many large inputs fast."""
+    def response(locs, kind, sigma1_sq, rho, sigma_sq, n_features, seed):
+        rng = np.random.default_rng(seed)
+        w, b = _rff_frequencies(rng, kind, rho, n_features)
+        L = torch.from_numpy(np.ascontiguousarray(locs)).cuda()
+        W = torch.from_numpy(w).cuda()
+        B = torch.from_numpy(b).cuda()
+        y = (math.sqrt(2 * sigma1_sq / n_features) * torch.cos(L @ W.T + B).sum(1)).cpu().numpy()
+        return y + math.sqrt(sigma_sq) * rng.standard_normal(locs.shape[0])
+    return response
 
 
 def _parallel(fn, items):
@@ -175,3 +194,14 @@ def laplace_weights(n: int, seed: int, lo: float = 0.05, hi: float = 0.25) -> np
     values |b| <= 3 (its maximum is 1/4)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(lo, hi, n)
+
+
+def bernoulli_responses(locs: np.ndarray, kind: int, sigma1_sq: float, rho: float, n_features: int,
+                        seed: int) -> np.ndarray:
+    """Binary responses y_i ~ Bernoulli(1 / (1 + e^{-b_i})) of a latent
+    Gaussian process b drawn by random Fourier features (rff_response with a
+    negligible nugget): the setting of the Vecchia-Laplace experiments
+    (binary likelihood, Section 5)."""
+    b = rff_response(locs, kind, sigma1_sq, rho, 1e-12, n_features, seed)
+    u = np.random.default_rng(seed + 1).uniform(size=locs.shape[0])
+    return (u < 1.0 / (1.0 + np.exp(-b))).astype(np.float64)
