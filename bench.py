@@ -73,14 +73,14 @@ def kernel_work(k, n, m, tp, nnz, b, ba=None):
 
 
 def source_fingerprint():
-    """sha256 over the sources of the kernels the hardware counters measure
-    (every source of the library but the Vecchia module, whose kernels are not
-    among them) and the ABI header: traffic is reported only for the sources
-    it was measured on."""
+    """sha256 over the sources that define the PCG kernels the hardware
+    counters measure (their code, launch shapes and the grid layout they
+    read) and the ABI header: traffic is reported only for the sources it was
+    measured on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2405_14492_amd", "csrc")
-    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")) and f != "vecchia.hip")
+    files = ["common.hpp", "gemm.hpp", "geom.hip", "kernels.hpp", "ops.hip", "ops.hpp"]
     for f in files:
         h.update(f.encode())
         with open(os.path.join(csrc, f), "rb") as fh:
@@ -295,7 +295,7 @@ def run_serving(F, torch, n_requests, rate, slots, budget_gib, warm=8):
         return srv.submit(kind, locs, y, r.theta, ind, r.gamma, pred, r.num_samples, arrival_ms=at)
 
     def one(label, precision, nslots, tol, graph, paced=True):
-        opts = dict(num_probes=20, seed=4005, tol=tol, max_iter=2000, precision=precision, rr_period=10, graph=graph)
+        opts = dict(num_probes=20, seed=4005, tol=tol, max_iter=2000, precision=precision, rr_period=20, graph=graph)
         with F.Server(slots=nslots, hbm_budget=int(budget_gib * (1 << 30)), **opts) as srv:
             for r, a in zip(trace[:warm], arrays[:warm]):  # code objects, library handles, pinned blocks
                 srv.wait(submit(srv, r, a, 0.0))

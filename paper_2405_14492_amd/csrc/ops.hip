@@ -250,7 +250,7 @@ static ReduceShape reduce_shape(int64_t n, int kdim, int ncols, int wg_target = 
   r.threads = 64 * (r.nmb < 8 ? r.nmb : 8);
   int64_t target = wg_target / (r.ncb * r.zb);
   if (target < 16) target = 16;
-  int64_t nch = ceil_div(n, 1024);
+  int64_t nch = ceil_div(n, 256);  // chunks of at least 256 points: enough workgroups at small n too
   if (nch > target) nch = target;
   if (nch < 1) nch = 1;
   r.ppc = (int)round_up(ceil_div(n, nch), 64);

@@ -117,8 +117,8 @@ fsa_status tri_inverse(const double* L, double* Linv, int mp, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- Y = X W^T, W lower triangular
-// Workgroup: 64 points x 256 output columns, 8 waves.  Wave w takes point
-// half ph = w / 4 (32 points, two 16-row MFMA tiles) and column quarter
+// Workgroup: 128 points x 256 output columns, 8 waves.  Wave w takes point
+// half ph = w / 4 (64 points, four 16-row MFMA tiles) and column quarter
 // cq = w % 4 for w < 4, 3 - w % 4 for w >= 4 (64 columns, four 16-column
 // tiles), so the two waves on one SIMD (w and w + 4) together cover
 // quarters q and 3 - q: with W lower triangular, the column quarter
@@ -126,7 +126,8 @@ fsa_status tri_inverse(const double* L, double* Linv, int mp, hipStream_t st) {
 // every SIMD.  K runs in chunks of 16 through double-buffered LDS: X as
 // Xs[k][point], W^T as Ws[k][column], both read by the MFMA 16x16x4 lanes
 // (lane l: A[l % 16][l / 16], B[l / 16][l % 16]).
-constexpr int WG_PTS = 64;
+constexpr int WG_PTS = 128;
+constexpr int WG_RT = WG_PTS / 32;  // 16-row MFMA tiles per wave
 constexpr int WG_COLS = 256;
 constexpr int WG_KC = 16;
 constexpr int XS_LD = WG_PTS + 2;
@@ -151,6 +152,8 @@ struct WgemmArgs {
   double* Y;           // n x mp point-major
 };
 
+// SRC0: the source of segment 0 (XSRC_*); segment 1, if TWO, is read from memory.
+template <int SRC0, bool TWO>
 __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
   __shared__ double Xs[2][WG_KC][XS_LD];
   __shared__ double Ws[2][WG_KC][WS_LD];
@@ -164,41 +167,49 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
   // the chunks each segment needs: k < jb + ncolw (W lower triangular)
   const int kneed = min(a.mp, jb + ncolw);
   const int nch_seg = kneed / WG_KC;
-  const int nch = nch_seg * a.nseg;
+  const int nch = nch_seg * (TWO ? 2 : 1);
 
-  // staging of one chunk: X (64 x 16) and W^T (16 x ncolw)
-  // X: thread t < 512 takes point t / 8 and k pair 2 (t % 8)
+  // staging of one chunk: X (128 x 16) and W^T (16 x ncolw)
+  // X: thread t < 512 takes points t / 8 and t / 8 + 64, k pair 2 (t % 8)
   const int xp = tid >> 3, xk = (tid & 7) * 2;
-  double px = 0.0, py = 0.0;
-  const bool xrow_ok = p0 + xp < a.n;
-  if (xrow_ok) {
-    px = a.xs ? a.xs[2 * (p0 + xp)] : 0.0;
-    py = a.xs ? a.xs[2 * (p0 + xp) + 1] : 0.0;
+  double px[2] = {0.0, 0.0}, py[2] = {0.0, 0.0};
+  bool xrow_ok[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    xrow_ok[h] = p0 + xp + 64 * h < a.n;
+    if (xrow_ok[h] && a.xs) {
+      px[h] = a.xs[2 * (p0 + xp + 64 * h)];
+      py[h] = a.xs[2 * (p0 + xp + 64 * h) + 1];
+    }
   }
   // W: thread t takes k row t / 32 and columns 8 (t % 32) .. + 8
   const int wk = tid >> 5, wc = (tid & 31) * 8;
-  double xr[2], wr[8];
+  double xr[2][2], wr[8];
   auto load = [&](int c) {
-    const int s = c / nch_seg, k0 = (c % nch_seg) * WG_KC;
+    const int s = TWO ? c / nch_seg : 0, k0 = (c % nch_seg) * WG_KC;
     const WgemmSeg& sg = a.seg[s];
-    if (sg.src == XSRC_MEM) {
-      xr[0] = xr[1] = 0.0;
-      if (xrow_ok) {
-        const d2 v = *reinterpret_cast<const d2*>(sg.X + (p0 + xp) * sg.ldx + k0 + xk);
-        xr[0] = v[0];
-        xr[1] = v[1];
-      }
-    } else {
+    const bool mem = SRC0 == XSRC_MEM || s == 1;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int k = k0 + xk + u;
-        double v = 0.0;
-        if (xrow_ok && k < a.m) {
-          const double dx = px - a.ind[2 * k], dy = py - a.ind[2 * k + 1];
-          const double d = sqrt(dx * dx + dy * dy);
-          v = sg.src == XSRC_COV ? cov_d(d, a.th) : dcov_drho(d, a.th);
+    for (int h = 0; h < 2; ++h) {
+      if (mem) {
+        xr[h][0] = xr[h][1] = 0.0;
+        if (xrow_ok[h]) {
+          const d2 v = *reinterpret_cast<const d2*>(sg.X + (p0 + xp + 64 * h) * sg.ldx + k0 + xk);
+          xr[h][0] = v[0];
+          xr[h][1] = v[1];
         }
-        xr[u] = v;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int k = k0 + xk + u;
+          double v = 0.0;
+          if (xrow_ok[h] && k < a.m) {
+            const double dx = px[h] - a.ind[2 * k], dy = py[h] - a.ind[2 * k + 1];
+            const double d = sqrt(dx * dx + dy * dy);
+            v = SRC0 == XSRC_COV ? cov_d(d, a.th) : dcov_drho(d, a.th);
+          }
+          xr[h][u] = v;
+        }
       }
     }
     if (wc < ncolw) {
@@ -212,8 +223,11 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
     }
   };
   auto store = [&](int buf) {
-    Xs[buf][xk][xp] = xr[0];
-    Xs[buf][xk + 1][xp] = xr[1];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      Xs[buf][xk][xp + 64 * h] = xr[h][0];
+      Xs[buf][xk + 1][xp + 64 * h] = xr[h][1];
+    }
     if (wc < ncolw) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) Ws[buf][wk][wc + u] = wr[u];
@@ -221,9 +235,9 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
   };
 
   typedef Mfma<double>::acc acc_t;
-  acc_t acc[2][4];
+  acc_t acc[WG_RT][4];
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < WG_RT; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[r][c] = acc_t{0.0, 0.0, 0.0, 0.0};
 
@@ -241,13 +255,13 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
 #pragma unroll
       for (int ks = 0; ks < WG_KC / 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
-        double av[2], bv[4];
+        double av[WG_RT], bv[4];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) av[r] = Xs[buf][kk][ph * 32 + r * 16 + (lane & 15)];
+        for (int r = 0; r < WG_RT; ++r) av[r] = Xs[buf][kk][ph * (WG_PTS / 2) + r * 16 + (lane & 15)];
 #pragma unroll
         for (int q = 0; q < 4; ++q) bv[q] = Ws[buf][kk][cq * 64 + q * 16 + (lane & 15)];
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < WG_RT; ++r)
 #pragma unroll
           for (int q = 0; q < 4; ++q) acc[r][q] = Mfma<double>::op(av[r], bv[q], acc[r][q]);
       }
@@ -258,10 +272,10 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
   if (!wave_on) return;
   // lane l, register e holds row (l / 16) + 4 e, column l % 16 of each tile
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < WG_RT; ++r)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t p = p0 + ph * 32 + r * 16 + Mfma<double>::orow(lane >> 4, e);
+      const int64_t p = p0 + ph * (WG_PTS / 2) + r * 16 + Mfma<double>::orow(lane >> 4, e);
       if (p >= a.n) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) a.Y[p * a.mp + jw + q * 16 + (lane & 15)] = acc[r][q][e];
@@ -280,7 +294,20 @@ static fsa_status launch_wgemm(const WgemmArgs& a, hipStream_t st) {
       return FSA_ERR_INVALID_ARG;
     }
   dim3 grid((unsigned)ceil_div(a.n, WG_PTS), (unsigned)ceil_div(a.mp, WG_COLS));
-  hipLaunchKernelGGL(k_wgemm, grid, dim3(512), 0, st, a);
+  const int src0 = a.seg[0].src;
+  if (a.nseg == 2) {
+    if (src0 != XSRC_DCOV || a.seg[1].src != XSRC_MEM) {
+      set_error("wgemm: two segments are [dSigma_nm | X]");
+      return FSA_ERR_INVALID_ARG;
+    }
+    hipLaunchKernelGGL((k_wgemm<XSRC_DCOV, true>), grid, dim3(512), 0, st, a);
+  } else if (src0 == XSRC_COV) {
+    hipLaunchKernelGGL((k_wgemm<XSRC_COV, false>), grid, dim3(512), 0, st, a);
+  } else if (src0 == XSRC_DCOV) {
+    hipLaunchKernelGGL((k_wgemm<XSRC_DCOV, false>), grid, dim3(512), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_wgemm<XSRC_MEM, false>), grid, dim3(512), 0, st, a);
+  }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
