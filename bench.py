@@ -80,7 +80,7 @@ def source_fingerprint():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2405_14492_amd", "csrc")
-    files = ["common.hpp", "gemm.hpp", "geom.hip", "kernels.hpp", "ops.hip", "ops.hpp"]
+    files = ["common.hpp", "gemm.hpp", "geom.hip", "kernels.hpp", "ops.hip"]
     for f in files:
         h.update(f.encode())
         with open(os.path.join(csrc, f), "rb") as fh:

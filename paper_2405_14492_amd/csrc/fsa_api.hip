@@ -805,6 +805,10 @@ static fsa_status launch_sigma_m(fsa_ctx* c) {
   FSA_TRY(dense_sigma_m(c->ind.p, c->m, mp, c->th, c->opt.sigma_m_jitter, false, c->Sm.p, c->st2));
   FSA_HIP(hipMemcpyAsync(c->Lm.p, c->Sm.p, (size_t)mp * mp * sizeof(double), hipMemcpyDeviceToDevice, c->st2));
   FSA_TRY(dense_cholesky(c->Lm.p, mp, c->info.p, c->st2));
+  // L_m^{-1} and its transpose for the whitening, still beside the main stream
+  // (meaningless if the factorization failed; the build then stops on info)
+  FSA_TRY(tri_inverse(c->Lm.p, c->Lminv.p, mp, c->st2));
+  FSA_TRY(transpose_scale(c->Lminv.p, c->LminvT.p, mp, 1.0, c->st2));
   FSA_HIP(hipEventRecord(c->ev_fact, c->st2));
   c->lm_pending = true;
   return FSA_OK;
@@ -825,9 +829,8 @@ static fsa_status build_values(fsa_ctx* c) {
     set_error("Cholesky of Sigma_m failed at column %d (duplicate inducing points?)", info - 1);
     return FSA_ERR_NOT_SPD;
   }
-  FSA_TRY(tri_inverse(c->Lm.p, c->Lminv.p, mp, st));
-  FSA_TRY(transpose_scale(c->Lminv.p, c->LminvT.p, mp, 1.0, st));
-  FSA_TRY(whiten(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->LminvT.p, c->A.p, st));
+  FSA_TRY(whiten(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->LminvT.p, c->A.p, st,
+                 c->opt.precision == FSA_MIXED_FP32 ? c->Af.p : nullptr));  // the float32 copy in the same pass
   // MIXED_BF16A: the model takes the bfloat16-rounded factor from here on
   // (residual values, D_s, capacitance, probes, gradient and prediction), so
   // the PCG operator read in bfloat16 is the float64 operator of that model
@@ -856,7 +859,6 @@ static fsa_status build_values(fsa_ctx* c) {
     hipLaunchKernelGGL(k_sum_log_part, dim3(nb), dim3(256), 0, st, c->D.p, c->n, c->scr.dot1.p, c->info.p + 1);
     hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, c->scr.dot1.p, nb, c->logdet_parts.p + 1);
   }
-  if (c->opt.precision == FSA_MIXED_FP32) FSA_TRY(to_float(c->A.p, c->Af.p, c->n * (int64_t)mp, st));
   if (c->opt.precision != FSA_FP64) {
     FSA_TRY(to_float(c->vals.p, c->valsf.p, c->csr.nnz, st));
     FSA_TRY(build_spmm_tiles(c->csr, c->grid, c->valsf.p, c->tile_off, c->tiles, c->tile_mask, st));
@@ -909,13 +911,13 @@ static fsa_status build_core(fsa_ctx* c, const double* locs, const double* y, co
   size_t mm = (size_t)mp * mp;
   FSA_TRY(c->Sm.alloc(mm));
   FSA_TRY(c->Lm.alloc(mm));
+  FSA_TRY(c->Lminv.alloc(mm));
+  FSA_TRY(c->LminvT.alloc(mm));
   FSA_TRY(launch_sigma_m(c));  // beside the grid and pattern build
   FSA_TRY(build_grid(c->grid, locs, n, c->gamma, st, nullptr, nullptr));
   FSA_TRY(build_pattern(c->grid, c->grid, c->csr, st));
   FSA_TRY(c->y.alloc(n));
   FSA_TRY(permute_rows(y, 1, c->y.p, 1, c->grid.perm.p, n, 1, st));
-  FSA_TRY(c->Lminv.alloc(mm));
-  FSA_TRY(c->LminvT.alloc(mm));
   FSA_TRY(c->C.alloc(mm));
   FSA_TRY(c->LCinv.alloc(mm));
   FSA_TRY(c->Cinv.alloc(mm));

@@ -86,8 +86,9 @@ fsa_status cov_block(const double* xs, int64_t n, const double* ind, int m, int 
                      double* out, hipStream_t st);
 // A = L_m^{-1} Sigma_mn = Sigma_nm L_m^{-T} (point-major n x mp): whitened low-rank factor,
 // Sigma_nm generated on the fly (never stored); LminvT = (L_m^{-1})^T (row-major mp x mp)
+// (Af_out: optionally the same factor rounded to float32, written by the same kernel)
 fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
-                  const double* LminvT, double* A_out, hipStream_t st);
+                  const double* LminvT, double* A_out, hipStream_t st, float* Af_out = nullptr);
 // Residual values of a taper pattern (rows of grid rg, columns of grid cg):
 // v = (c(d) - Xr_p . Yc_q) W(d/gamma) (+ s2 on the self diagonal, D[p] = v_pp).
 // deriv: v = (dc/drho(d) - [F|A]_p . [A|F]_q) W(d/gamma).

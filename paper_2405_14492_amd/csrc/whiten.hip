@@ -150,6 +150,7 @@ struct WgemmArgs {
   const double* ind;   // inducing coordinates (padded to mp)
   Theta th;
   double* Y;           // n x mp point-major
+  float* Yf;           // optional: the same, rounded to float32 (nearest)
 };
 
 // SRC0: the source of segment 0 (XSRC_*); segment 1, if TWO, is read from memory.
@@ -278,7 +279,11 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
       const int64_t p = p0 + ph * (WG_PTS / 2) + r * 16 + Mfma<double>::orow(lane >> 4, e);
       if (p >= a.n) continue;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a.Y[p * a.mp + jw + q * 16 + (lane & 15)] = acc[r][q][e];
+      for (int q = 0; q < 4; ++q) {
+        const int64_t o = p * a.mp + jw + q * 16 + (lane & 15);
+        a.Y[o] = acc[r][q][e];
+        if (a.Yf) a.Yf[o] = (float)acc[r][q][e];
+      }
     }
 }
 
@@ -314,7 +319,7 @@ static fsa_status launch_wgemm(const WgemmArgs& a, hipStream_t st) {
 
 // A = Sigma_nm L_m^{-T} (point-major n x mp): LminvT = (L_m^{-1})^T, mp x mp row-major.
 fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
-                  const double* LminvT, double* A_out, hipStream_t st) {
+                  const double* LminvT, double* A_out, hipStream_t st, float* Af_out) {
   WgemmArgs a{};
   a.n = n;
   a.mp = mp;
@@ -325,6 +330,7 @@ fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp,
   a.ind = ind;
   a.th = th;
   a.Y = A_out;
+  a.Yf = Af_out;
   return launch_wgemm(a, st);
 }
 
