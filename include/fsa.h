@@ -82,6 +82,18 @@ typedef enum { FSA_COV_EXPONENTIAL = 0, FSA_COV_MATERN32 = 1 } fsa_cov;
  *     dSigma_m/drho with the rounded A. */
 typedef enum { FSA_FP64 = 0, FSA_MIXED_FP32 = 1, FSA_MIXED_BF16A = 2 } fsa_precision;
 
+/* fsa_options.fp32_products: the float32 products of MIXED_FP32's low-rank
+ * PCG passes (A^T D^{-1} r and A C^{-1} w over the n x m factor).
+ *   FSA_F32P_SPLIT (default): on the bfloat16 matrix cores, every float32
+ *     operand split exactly into three bfloat16 parts and the six partial
+ *     products above 2^-23 of the result summed in float32; the dropped ones
+ *     amount to about one float32 rounding per product.  Same arithmetic
+ *     contract as float32 (float32 operands, float32 accumulation), at 6/16
+ *     of the matrix-core time, so the passes are bound by reading A.
+ *     Blocks of more than 52 columns take the float32 matrix cores.
+ *   FSA_F32P_MFMA: on the float32 matrix cores (16x16x4). */
+typedef enum { FSA_F32P_SPLIT = 0, FSA_F32P_MFMA = 1 } fsa_fp32_products;
+
 /* fsa_options.profile: all five kernel classes of fsa_stats.kernel_ms */
 #define FSA_PROFILE_ALL 0x1f
 
@@ -132,7 +144,7 @@ typedef struct {
                             the second (one launch per iteration instead of one per kernel; results are bitwise
                             those of the eager launches); ignored while profile is set and on the null stream,
                             which cannot be captured */
-  int32_t reserved0;
+  int32_t fp32_products; /* fsa_fp32_products: how MIXED_FP32 multiplies the n x m low-rank factor in the PCG passes */
 } fsa_options;
 
 typedef struct {

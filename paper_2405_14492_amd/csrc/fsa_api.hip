@@ -950,6 +950,7 @@ static fsa_status validate_build(int64_t n, int32_t d, const fsa_theta* theta, i
     if (!(opt->cg_rel_tol >= 0)) { set_error("cg_rel_tol must be >= 0"); return FSA_ERR_INVALID_ARG; }
     if (opt->precision != FSA_FP64 && opt->precision != FSA_MIXED_FP32 && opt->precision != FSA_MIXED_BF16A) { set_error("unknown precision"); return FSA_ERR_INVALID_ARG; }
     if (opt->control_variate < FSA_CV_NONE || opt->control_variate > FSA_CV_OPT_PRINTED) { set_error("unknown control_variate"); return FSA_ERR_INVALID_ARG; }
+    if (opt->fp32_products != FSA_F32P_SPLIT && opt->fp32_products != FSA_F32P_MFMA) { set_error("unknown fp32_products"); return FSA_ERR_INVALID_ARG; }
     if (!(opt->sigma_m_jitter >= 0)) { set_error("sigma_m_jitter must be >= 0"); return FSA_ERR_INVALID_ARG; }
   }
   return FSA_OK;
@@ -989,6 +990,7 @@ void fsa_default_options(fsa_options* o) {
   o->slq_weight_n = 0;
   o->sigma_m_jitter = 0.0;
   o->hip_stream = nullptr;
+  o->fp32_products = FSA_F32P_SPLIT;
 }
 
 const char* fsa_last_error(void) { return get_error(); }
@@ -1366,6 +1368,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
     op.A = reinterpret_cast<const T*>(c->Af.p);  // null in MIXED_BF16A
     op.Abf = c->Abf.p;                            // null unless MIXED_BF16A
     op.Abf8 = c->Abf8.p;
+    op.split = c->opt.precision == FSA_MIXED_FP32 && c->opt.fp32_products == FSA_F32P_SPLIT;
   }
   const double tol = c->opt.cg_rel_tol;
   const int fixed = c->opt.fixed_iter > 0 ? 1 : 0;

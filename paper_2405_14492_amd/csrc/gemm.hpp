@@ -1918,4 +1918,396 @@ __global__ __launch_bounds__(1024) void k_rows_bf16(int64_t nrows, int kdim, con
   }
 }
 
+
+// ------------------------------------------------------------------ float32 passes on the bfloat16 MFMA
+// The float32 PCG passes (MIXED_FP32) are bound by the float32 matrix cores
+// (16x16x4, 2048 flop per 32 cycles) at the 500k x 512 shape.  The bfloat16
+// 16x16x32 instruction does sixteen times the flops per cycle, so the passes
+// run there with every float32 operand split into three bfloat16 parts:
+// h = bf16(x), m = bf16(x - h), l = bf16(x - h - m), each to nearest even.
+// For a normal float32 x the split is exact, x = h + m + l (x - h is a
+// multiple of x's last place below 2^-8 |x|, so x - h - m has at most eight
+// significant bits).  Each partial product a_i x_j is exact in float32.  Of
+// the nine, the six with i + j <= 2 are taken (smallest first); the three
+// dropped ones (m l, l m, l l) are below 2^-23 |a x| together, about one
+// float32 rounding.  The result is a float32-accurate product (in another
+// summation order than the float32 MFMA's) at 6/16 of the matrix-core
+// time, so the passes become bound by the HBM stream of A.
+typedef float split_f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 split_b2 __attribute__((ext_vector_type(2)));
+// two floats rounded to bfloat16 (nearest even, one v_cvt_pk_bf16_f32), a in the low half
+__device__ __forceinline__ unsigned bf16_pk2(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((split_f2){a, b}, split_b2));
+}
+// the three bfloat16 parts of two floats (h, m, l: one packed pair each)
+__device__ __forceinline__ void bf16_split_pair(float a, float b, unsigned& h, unsigned& m, unsigned& l) {
+  h = bf16_pk2(a, b);
+  const float ra = a - __uint_as_float(h << 16), rb = b - __uint_as_float(h & 0xffff0000u);
+  m = bf16_pk2(ra, rb);
+  const float sa = ra - __uint_as_float(m << 16), sb = rb - __uint_as_float(m & 0xffff0000u);
+  l = bf16_pk2(sa, sb);
+}
+
+// Residual pass with split operands: same contract, prologue modes and
+// partial layout as k_reduce_gemm_f32, grid (ncb, nchunks), 512 threads.
+// Wave w owns kdim rows 64 w .. 64 w + 63 as four 16-row tiles interleaved by
+// four (tile a, row i: kdim row 64 w + 4 i + a), so a lane reads its four
+// rows of one point with one 16-byte load from the point-major float32 A and
+// splits them in registers; a step takes 32 points (one MFMA k extent).  The
+// prologue writes the three parts of X to a double-buffered LDS block as
+// [part][column][point].  A loads run one step ahead of their use, the
+// prologue inputs one step ahead of the prologue that writes them to LDS.
+template <bool UPD, int SC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_reduce_split(
+    int64_t npts, int pts_per_chunk, int kdim, int ncols, const float* __restrict__ A, F32Pro pro,
+    float* __restrict__ part, double* __restrict__ dot_part, int ld_dot) {
+  constexpr int SP = 32;       // points per step (one MFMA k extent)
+  constexpr int NP = SP / 8;   // prologue elements per thread per step
+  constexpr int XST = 40;      // LDS stride (bfloat16) of one column's points
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][3][64 * XST];
+  __shared__ double red[512];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.x * 64;
+  const int ncb = gridDim.x;
+  const int chunk = blockIdx.y;
+  const int kb = w * 64;
+  const bool mactive = kb < kdim;
+  const int64_t pbeg = (int64_t)chunk * pts_per_chunk;
+  const int64_t pend = min(npts, pbeg + pts_per_chunk);
+  const int np = pend > pbeg ? (int)(pend - pbeg) : 0;
+  const int nsteps = (np + SP - 1) / SP;
+  const int tc = tid & 63, tp = tid >> 6;
+  const int c = c0 + tc;
+  const bool cval = c < ncols;
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+  double dacc = 0.0;
+  const __amdgpu_buffer_rsrc_t arsrc = rsrc_of(A + pbeg * kdim, (int64_t)np * kdim * 4);
+  const __amdgpu_buffer_rsrc_t srsrc = rsrc_of(pro.S + pbeg * pro.ld, (int64_t)np * pro.ld * 4);
+  const __amdgpu_buffer_rsrc_t vrsrc = rsrc_of(UPD ? pro.V + pbeg * pro.ld : pro.S, UPD ? (int64_t)np * pro.ld * 4 : 0);
+  const __amdgpu_buffer_rsrc_t drsrc = rsrc_of(SC ? pro.sc + pbeg : (const double*)pro.S, SC ? (int64_t)np * 8 : 0);
+  const double a_c = (UPD && cval) ? pro.alpha[c] : 0.0;
+  // lane's A: points 8 q + j of the step, kdim rows kb + 4 r16 .. + 3 (one 16-byte load per point)
+  const unsigned a_off = mactive ? (unsigned)((8 * q) * kdim + kb + 4 * r16) * 4u : (unsigned)BUF_OOR;
+  const unsigned a_pt = (unsigned)kdim * 4u;
+  const unsigned a_step = (unsigned)(SP * kdim) * 4u;
+  const unsigned s_off = cval ? (unsigned)(tp * (int)pro.ld + c) * 4u : (unsigned)BUF_OOR;
+  const unsigned s_step = 8u * (unsigned)pro.ld * 4u;
+  float sv[2][NP], vv[2][NP];
+  double dv[2][NP];
+  auto load_a = [&](int s, f4* ab) {
+    const unsigned so = a_off + (unsigned)s * a_step;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ab[j] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(arsrc, so + a_pt * j, 0, 0));
+  };
+  auto pro_load = [&](int s, int set) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int pr = s * SP + tp + 8 * u;
+      const unsigned o = s_off + (unsigned)(s * NP + u) * s_step;
+      sv[set][u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(srsrc, o, 0, 0));
+      vv[set][u] = UPD ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(vrsrc, o, 0, 0)) : 0.f;
+      dv[set][u] = SC ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(drsrc, (unsigned)pr * 8u, 0, 0)) : 1.0;
+    }
+  };
+  auto pro_apply = [&](int s, int set, int buf) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int pl = tp + 8 * u;
+      const int pr = s * SP + pl;
+      double x = (double)sv[set][u];
+      if constexpr (UPD) {
+        const float rt = (float)(x - a_c * (double)vv[set][u]);
+        const unsigned o = s_off + (unsigned)(s * NP + u) * s_step;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, rt), srsrc, o, 0, 0);
+        x = (double)rt;
+        dacc += x * x;
+      }
+      const double y = SC == 0 ? x : (SC == 1 ? x * dv[set][u] : x / dv[set][u]);
+      const float yf = (pr < np && cval) ? (float)y : 0.f;
+      const unsigned h = bf16_pk2(yf, 0.f);
+      const float r1 = yf - __uint_as_float(h << 16);
+      const unsigned m = bf16_pk2(r1, 0.f);
+      const float r2 = r1 - __uint_as_float(m << 16);
+      const unsigned l = bf16_pk2(r2, 0.f);
+      Xs[buf][0][tc * XST + pl] = (uint16_t)h;
+      Xs[buf][1][tc * XST + pl] = (uint16_t)m;
+      Xs[buf][2][tc * XST + pl] = (uint16_t)l;
+    }
+  };
+  // the three parts of the lane's A operand for tile a (kdim row kb + 4 r16 + a, points 8 q .. 8 q + 7)
+  u4v sa[4][3];
+  auto split_a = [&](const f4* ab) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        unsigned h, m, l;
+        bf16_split_pair(ab[2 * i][a], ab[2 * i + 1][a], h, m, l);
+        sa[a][0][i] = h;
+        sa[a][1][i] = m;
+        sa[a][2][i] = l;
+      }
+  };
+  auto mma = [&](int buf) {
+    if (!mactive) return;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      u4v xo[3];
+#pragma unroll
+      for (int P = 0; P < 3; ++P) xo[P] = *reinterpret_cast<const u4v*>(&Xs[buf][P][(16 * b + r16) * XST + 8 * q]);
+      // the six partial products above 2^-24: (h,h) (h,m) (m,h) (h,l) (m,m) (l,h)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(sa[a][2], xo[0], acc[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(sa[a][1], xo[1], acc[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(sa[a][0], xo[2], acc[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(sa[a][1], xo[0], acc[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(sa[a][0], xo[1], acc[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(sa[a][0], xo[0], acc[a][b]);
+    }
+  };
+  // step s (parity par = s & 1): A(s) is split, its registers then take
+  // A(s + 1); the prologue inputs of step s + 2 load; the matrix cores take
+  // step s; the prologue of step s + 1 (inputs loaded a step ago) fills the
+  // other LDS half
+  f4 ab[8];
+  auto step = [&](int s, int par) {
+    split_a(ab);
+    load_a(s + 1, ab);
+    pro_load(s + 2, par);
+    mma(par);
+    pro_apply(s + 1, par ^ 1, par ^ 1);
+    __syncthreads();
+  };
+  if (nsteps > 0) {
+    pro_load(0, 0);
+    load_a(0, ab);
+    pro_load(1, 1);
+    pro_apply(0, 0, 0);
+    __syncthreads();
+    int s = 0;
+    for (; s + 1 < nsteps; s += 2) {
+      step(s, 0);
+      step(s + 1, 1);
+    }
+    if (s < nsteps) step(s, 0);
+  }
+  if (mactive) {
+    // tile (a, b) element r: kdim row kb + 4 (4 q + r) + a, column 16 b + r16
+    float* dst = part + (((int64_t)chunk * ncb + blockIdx.x) * kdim + kb) * 64 + r16;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) dst[(4 * (4 * q + r) + a) * 64 + 16 * b] = acc[a][b][r];
+  }
+  if constexpr (UPD) {
+    red[tid] = dacc;
+    __syncthreads();
+    if (tid < 64) {
+      double sum = 0.0;
+      for (int k = 0; k < 8; ++k) sum += red[k * 64 + tid];
+      dot_part[(int64_t)chunk * ld_dot + c0 + tid] = sum;
+    }
+  }
+}
+
+// Woodbury expansion with split operands: the ROWS_PCG / ROWS_PCG_INIT
+// epilogues of k_rows_gemm_f32 for a column block of at most SPLIT_ROWS_NC
+// columns.  The three parts of G live in LDS as [part][column][k] (row
+// stride kdim + 8), a zero row standing in for the padding columns (160 KB at
+// kdim = 512, one workgroup of NW waves per CU).  Each wave is persistent over
+// 16-row tiles and walks k in steps of 64: a lane loads 64 contiguous bytes
+// of its row (k = 64 kb + 16 q' + 8 t + j for MFMA t, j) two steps ahead and
+// splits them when the step starts; the epilogue's residual and D^{-1} rows
+// load two steps before the tile ends.
+constexpr int SPLIT_ROWS_NC = 52;
+inline size_t split_rows_lds(int kdim) { return (size_t)(3 * SPLIT_ROWS_NC + 1) * (kdim + 8) * 2; }
+
+template <int EM, int NW>
+__global__ __launch_bounds__(64 * NW) void k_rows_split(int64_t nrows, int kdim, const float* __restrict__ A,
+                                                     int64_t lda, const float* __restrict__ G, int ldg, int ncols,
+                                                     F32RowsEpi epi, double* __restrict__ dot_part, int ld_dot) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t gsh[];
+  constexpr int NT = 64 * NW;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane >> 4, r16 = lane & 15;
+  const int c0 = blockIdx.y * 64;
+  const int gst = kdim + 8;
+  for (int e = tid; e < kdim * SPLIT_ROWS_NC; e += NT) {
+    const int k = e / SPLIT_ROWS_NC, cc = e - k * SPLIT_ROWS_NC;
+    const float v = (c0 + cc < ncols) ? G[(int64_t)k * ldg + c0 + cc] : 0.f;
+    unsigned h, m, l;
+    bf16_split_pair(v, 0.f, h, m, l);
+    gsh[(0 * SPLIT_ROWS_NC + cc) * gst + k] = (uint16_t)h;
+    gsh[(1 * SPLIT_ROWS_NC + cc) * gst + k] = (uint16_t)m;
+    gsh[(2 * SPLIT_ROWS_NC + cc) * gst + k] = (uint16_t)l;
+  }
+  for (int e = tid; e < gst; e += NT) gsh[3 * SPLIT_ROWS_NC * gst + e] = 0;
+  __syncthreads();
+  int brow[4][3];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int P = 0; P < 3; ++P) {
+      const int cc = 16 * b + r16;
+      brow[b][P] = (cc < SPLIT_ROWS_NC ? (P * SPLIT_ROWS_NC + cc) : 3 * SPLIT_ROWS_NC) * gst + 16 * q;
+    }
+  const int nkb = kdim / 64;
+  const int64_t ntile = (nrows + 15) / 16;
+  const int64_t gw = (int64_t)blockIdx.x * NW + w, GW = (int64_t)gridDim.x * NW;
+  const int64_t ntw = gw < ntile ? (ntile - gw + GW - 1) / GW : 0;
+  const unsigned lane_off = (unsigned)(r16 * lda + 16 * q) * 4u;
+  double dsum[4] = {0, 0, 0, 0};
+  int64_t lj = 0;
+  int lkb = 0;
+  auto load_next = [&](f4* ab) {
+    const int64_t row0 = (gw + lj * GW) * 16;
+    const int64_t nr = lj < ntw ? min((int64_t)16, nrows - row0) : 0;
+    const __amdgpu_buffer_rsrc_t rs = rsrc_of(A + (lj < ntw ? row0 * lda : 0), nr * lda * 4);
+    const unsigned o = lane_off + (unsigned)lkb * 256u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ab[i] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u * i, 0, 0));
+    if (++lkb == nkb) {
+      lkb = 0;
+      ++lj;
+    }
+  };
+  f4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = f4{0, 0, 0, 0};
+  int64_t cj = 0;
+  int ckb = 0;
+  // epilogue inputs of the current tile, loaded two steps before its end
+  float xin[4][4];
+  double di[4];
+  auto epi_load = [&]() {
+    const int64_t row0 = (gw + cj * GW) * 16;
+    const int64_t nr = min((int64_t)16, nrows - row0);
+    const __amdgpu_buffer_rsrc_t rr = rsrc_of(epi.R + row0 * epi.ld, nr * epi.ld * 4);
+    const __amdgpu_buffer_rsrc_t rd = rsrc_of(epi.Dinv + row0, nr * 8);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      di[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rd, (unsigned)(4 * q + r) * 8u, 0, 0));
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int cc = c0 + b * 16 + r16;
+        const unsigned o = cc < ncols ? (unsigned)((4 * q + r) * (int)epi.ld + cc) * 4u : (unsigned)BUF_OOR;
+        xin[r][b] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rr, o, 0, 0));
+      }
+    }
+  };
+  auto epilogue = [&]() {
+    const int64_t row0 = (gw + cj * GW) * 16;
+    const int64_t nr = min((int64_t)16, nrows - row0);
+    const __amdgpu_buffer_rsrc_t ry = rsrc_of(epi.Y ? epi.Y + row0 * epi.ld : (const void*)A, epi.Y ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rh = rsrc_of(EM == ROWS_PCG_INIT ? epi.H + row0 * epi.ld : (const void*)A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rp = rsrc_of(EM == ROWS_PCG_INIT ? epi.P + row0 * epi.ld : (const void*)A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rq = rsrc_of(EM == ROWS_PCG_INIT ? epi.Q0 + row0 * epi.ld : (const void*)A, EM == ROWS_PCG_INIT ? nr * epi.ld * 4 : 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int cc = c0 + b * 16 + r16;
+        const unsigned o = cc < ncols ? (unsigned)((4 * q + r) * (int)epi.ld + cc) * 4u : (unsigned)BUF_OOR;
+        const float v = acc[b][r];
+        const double rv = (double)xin[r][b];
+        const double qv = (rv - (double)v) * di[r];
+        dsum[b] += rv * qv;
+        if constexpr (EM == ROWS_PCG) {
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), ry, o, 0, 0);
+        } else {
+          const unsigned qb = __builtin_bit_cast(unsigned, (float)qv);
+          __builtin_amdgcn_raw_buffer_store_b32(qb, rh, o, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rp, o, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(qb, rq, o, 0, 0);
+        }
+      }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = f4{0, 0, 0, 0};
+  };
+  auto step = [&](f4* cur) {
+    // the lane's 16 k (64 kb + 16 q + 8 t + j): parts of the two MFMA operands
+    u4v sa[2][3];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = 8 * t + 2 * i;
+        unsigned h, m, l;
+        bf16_split_pair(cur[e >> 2][e & 3], cur[e >> 2][(e & 3) + 1], h, m, l);
+        sa[t][0][i] = h;
+        sa[t][1][i] = m;
+        sa[t][2][i] = l;
+      }
+    load_next(cur);
+    if (ckb == nkb - 2 || (nkb == 1 && ckb == 0)) epi_load();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      u4v g[4][3];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int P = 0; P < 3; ++P) g[b][P] = *reinterpret_cast<const u4v*>(&gsh[brow[b][P] + ckb * 64 + 8 * t]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][2], g[b][0], acc[b]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][1], g[b][1], acc[b]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][0], g[b][2], acc[b]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][1], g[b][0], acc[b]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][0], g[b][1], acc[b]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][0], g[b][0], acc[b]);
+    }
+    if (++ckb == nkb) {
+      epilogue();
+      ckb = 0;
+      ++cj;
+    }
+  };
+  const int64_t nflat = ntw * nkb;
+  f4 b0[4], b1[4];
+  load_next(b0);
+  load_next(b1);
+  int64_t f = 0;
+  for (; f + 1 < nflat; f += 2) {
+    step(b0);
+    step(b1);
+  }
+  if (f < nflat) step(b0);
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(gsh);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double v = dsum[b];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (q == 0) red[w * 64 + b * 16 + r16] = v;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double sacc = 0.0;
+    for (int k = 0; k < NW; ++k) sacc += red[k * 64 + tid];
+    dot_part[(int64_t)blockIdx.x * ld_dot + c0 + tid] = sacc;
+  }
+}
+
 }  // namespace fsa

@@ -275,7 +275,7 @@ static fsa_status ensure_part(Scratch& s, const ReduceShape& r) {
 template <typename T, bool DOT, class Pro>
 static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int ncols, const T* A, const Pro& pro,
                                 T* part, double* dot_part, int ld_dot, hipStream_t st, int lower_only = 0,
-                                const uint16_t* Abf = nullptr, const uint16_t* Abf8 = nullptr) {
+                                const uint16_t* Abf = nullptr, const uint16_t* Abf8 = nullptr, bool split = false) {
   if (DOT && r.zb != 1) {
     set_error("reduce GEMM with a dot prologue needs kdim <= 512 (got %d)", kdim);
     return FSA_ERR_INVALID_ARG;
@@ -304,6 +304,9 @@ static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int n
     } else if (Abf) {
       hipLaunchKernelGGL((k_reduce_gemm_f32<bf16_t, Pro::kUpd, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim,
                          ncols, Abf, fp, part, dot_part, ld_dot);
+    } else if (split && r.zb == 1) {
+      hipLaunchKernelGGL((k_reduce_split<Pro::kUpd, Pro::kSc>), dim3(r.ncb, r.nchunks), dim3(512), 0, st, n, r.ppc,
+                         kdim, ncols, (const float*)A, fp, part, dot_part, ld_dot);
     } else {
       hipLaunchKernelGGL((k_reduce_gemm_f32<float, Pro::kUpd, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim,
                          ncols, (const float*)A, fp, part, dot_part, ld_dot);
@@ -977,6 +980,17 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
       else
         hipLaunchKernelGGL((k_rows_bf16<ROWS_PCG>), grid2, dim3(1024), smem16, st, b.n, op.kdim, op.Abf,
                            (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p, ncb * 64);
+    } else if (op.split && b.ncols <= SPLIT_ROWS_NC && op.kdim <= 512) {
+      // float32 operands split in three bfloat16 parts, one 8-wave workgroup per CU
+      const size_t smem16 = split_rows_lds(op.kdim);
+      if (init)
+        hipLaunchKernelGGL((k_rows_split<ROWS_PCG_INIT, 8>), grid2, dim3(512), smem16, st, b.n, op.kdim,
+                           (const float*)op.A, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p,
+                           ncb * 64);
+      else
+        hipLaunchKernelGGL((k_rows_split<ROWS_PCG, 8>), grid2, dim3(512), smem16, st, b.n, op.kdim,
+                           (const float*)op.A, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p,
+                           ncb * 64);
     } else if (op.Abf) {
       if (init)
         hipLaunchKernelGGL((k_rows_gemm_f32<bf16_t, true, ROWS_PCG_INIT>), grid2, dim3(1024), smem, st, b.n, op.kdim,
@@ -1033,7 +1047,7 @@ fsa_status pcg_init(PcgBlock<T>& b, const OpDesc<T>& op, const double* B, double
     FSA_TRY(ensure_part<T>(s, r));
     MulDinvPro<T> pro{b.R, b.ld, op.Dinv};
     FSA_TRY((launch_reduce<T, false>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, nullptr, 0, st, 0, op.Abf,
-                                     op.Abf8)));
+                                     op.Abf8, op.split)));
     FSA_TRY(reduce_finish<T>(s, r, s.w.p, b.ldw, 0, st));
     FSA_TRY(pcg_precond_and_dots<T>(b, op, 1, s, nparts_rq, st));
     // |b|^2 partials
@@ -1107,7 +1121,7 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     {
       KT_BEGIN(b, KT_PASS1);
       FSA_TRY((launch_reduce<T, true>(r, b.n, op.kdim, b.ncols, op.A, pro, (T*)s.part.p, s.dot2.p, ldd, st, 0,
-                                      op.Abf, op.Abf8)));
+                                      op.Abf, op.Abf8, op.split)));
       KT_END(b, KT_PASS1);
     }
     nparts_rr = r.nchunks;

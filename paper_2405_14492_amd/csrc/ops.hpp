@@ -170,6 +170,10 @@ struct OpDesc {
   // with Abf: the same values point-interleaved, [ceil(n/8)][kdim][8] (zero
   // past n), for the bfloat16-MFMA residual pass (null: widen Abf instead)
   const uint16_t* Abf8 = nullptr;
+  // float32 operator with A in float32: the low-rank passes on the bfloat16
+  // matrix cores with operands split in three parts (k_reduce_split,
+  // k_rows_split) instead of the float32 matrix cores
+  bool split = false;
   int kdim = 0;
   const double* Cinv = nullptr;
   // float32 operator only (may be null): the sparse part pre-scattered into

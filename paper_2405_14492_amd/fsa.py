@@ -22,6 +22,7 @@ MIXED_FP32 = 1
 MIXED_BF16A = 2
 PROFILE_ALL = 0x1f  # fsa_options.profile: all five kernel classes
 CV_NONE, CV_ONE, CV_OPT, CV_OPT_PRINTED = range(4)  # fsa_options.control_variate
+F32P_SPLIT, F32P_MFMA = range(2)  # fsa_options.fp32_products
 
 OP_SIGMA_DAGGER, OP_SIGMA_S, OP_P_INV, OP_D_SIGMA1, OP_D_RHO, OP_PROBES = range(6)
 V_SIGMA, V_PRECISION, V_OPERATOR, V_P_INV = range(4)
@@ -61,7 +62,7 @@ class fsa_options(C.Structure):
                 ("max_iter", C.c_int32), ("fixed_iter", C.c_int32), ("precision", C.c_int32),
                 ("rr_period", C.c_int32), ("slq_weight_n", C.c_int32), ("profile", C.c_int32),
                 ("sigma_m_jitter", C.c_double),
-                ("hip_stream", C.c_void_p), ("graph", C.c_int32), ("reserved0", C.c_int32)]
+                ("hip_stream", C.c_void_p), ("graph", C.c_int32), ("fp32_products", C.c_int32)]
 
 
 class fsa_stats(C.Structure):
@@ -217,7 +218,7 @@ def make_theta(theta) -> fsa_theta:
 
 def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, precision=FP64, rr_period=10,
                  slq_weight_n=False, jitter=0.0, stream=None, profile=False, control_variate=CV_NONE,
-                 graph=False) -> fsa_options:
+                 graph=False, fp32_products=F32P_SPLIT) -> fsa_options:
     o = fsa_options()
     lib().fsa_default_options(C.byref(o))
     o.num_probes = int(num_probes)
@@ -234,6 +235,7 @@ def make_options(num_probes=50, seed=0, tol=1e-8, max_iter=1000, fixed_iter=0, p
     o.profile = PROFILE_ALL if profile is True else int(profile)
     o.control_variate = int(control_variate)
     o.graph = int(bool(graph))
+    o.fp32_products = int(fp32_products)
     return o
 
 
@@ -449,9 +451,9 @@ class FSA:
 
     def __init__(self, locs, y, theta, inducing, taper_range, num_probes=50, seed=0, tol=1e-8, max_iter=1000,
                  fixed_iter=0, precision=FP64, rr_period=10, slq_weight_n=False, jitter=0.0, stream=None,
-                 device=False, profile=False, control_variate=CV_NONE, graph=False):
+                 device=False, profile=False, control_variate=CV_NONE, graph=False, fp32_products=F32P_SPLIT):
         self.opt = make_options(num_probes, seed, tol, max_iter, fixed_iter, precision, rr_period, slq_weight_n,
-                                jitter, stream, profile, control_variate, graph)
+                                jitter, stream, profile, control_variate, graph, fp32_products)
         self.n = int(locs.shape[0])
         self.theta = tuple(theta)
         build = fsa_build_dev if device else fsa_build

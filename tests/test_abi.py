@@ -59,10 +59,11 @@ def test_struct_layouts(L):
     assert o.num_probes == 50 and o.cg_rel_tol == 1e-8 and o.max_iter == 1000 and o.precision == 0
     assert o.graph == 0
     assert o.control_variate == 0
+    assert o.fp32_products == fsa.F32P_SPLIT
 
 
 @pytest.mark.parametrize("case", ["n1", "d3", "m0", "m_gt_n", "gamma0", "sigma2_0", "rho_neg", "cov_bad", "probes0",
-                                  "cv_bad"])
+                                  "cv_bad", "f32p_bad"])
 def test_invalid_arguments_rejected_on_host(L, case):
     from paper_2405_14492_amd import fsa
     n, d, m, gamma = 10, 2, 3, 0.1
@@ -89,6 +90,8 @@ def test_invalid_arguments_rejected_on_host(L, case):
         opt.num_probes = 0
     elif case == "cv_bad":
         opt.control_variate = 4
+    elif case == "f32p_bad":
+        opt.fp32_products = 2
     locs = np.zeros((max(n, 1), d))
     y = np.zeros(max(n, 1))
     ind = np.zeros((max(m, 1), d))

@@ -89,23 +89,52 @@ def test_fp64_fixed_iterations_at_bench_shape(F, name):
     assert st["iters_min"] == k and st["iters_max"] == k
 
 
+@pytest.mark.parametrize("products", ["split", "mfma"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_mixed_fixed_iterations_at_bench_shape(F, name):
+def test_mixed_fixed_iterations_at_bench_shape(F, name, products):
     """The float32 kernels of the timed shape (tiled sparse product, the
-    pipelined residual pass, the expansion with its 128 KiB G tile) with the
-    float64 residual replacement every 5 iterations, against the oracle with
-    the same probes and iteration count: 1e-4."""
-    say("case", name)
+    residual pass and the expansion, their float32 products either split into
+    bfloat16 parts or on the float32 matrix cores with the 128 KiB G tile)
+    with the float64 residual replacement every 5 iterations, against the
+    oracle with the same probes and iteration count: 1e-4."""
+    say("case", name, products)
     locs, y, theta, ind, gamma = case(**CASES[name])
     k = 12
     ref = O.nll_grad(O.FSA(locs, ind, theta, gamma), y, T, 92, fixed_iter=k)
+    fp = {"split": F.F32P_SPLIT, "mfma": F.F32P_MFMA}[products]
     with F.FSA(locs, y, theta, ind, gamma, num_probes=T, seed=92, fixed_iter=k, precision=F.MIXED_FP32,
-               rr_period=5) as f:
+               rr_period=5, fp32_products=fp) as f:
         nll, grad, st = f.nll_grad()
     err = np.abs(grad - ref["grad"]) / gscale(ref)
     say("nll rel", abs(nll - ref["nll"]) / abs(ref["nll"]), "grad err / scale", err)
     assert abs(nll - ref["nll"]) <= 1e-4 * abs(ref["nll"])
     assert np.all(err <= 1e-4)
+
+
+@pytest.mark.parametrize("name", ["m500_uniform", "m500_clustered"])
+def test_split_products_agree_with_fp32_mfma(F, name):
+    """The two ways of taking MIXED_FP32's low-rank products (bfloat16 parts,
+    float32 matrix cores) are both float32 products: with the same probes and
+    a fixed iteration count the likelihood, gradient and every column's
+    Lanczos coefficients agree to float32 rounding propagated through the
+    iterations (gradient components against the gradient's scale: the
+    larger of the component and a hundredth of the largest one, since the
+    sigma1^2 component can be a small difference of large terms)."""
+    say("case", name)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    out = {}
+    for fp in (F.F32P_SPLIT, F.F32P_MFMA):
+        with F.FSA(locs, y, theta, ind, gamma, num_probes=T, seed=95, fixed_iter=15, precision=F.MIXED_FP32,
+                   rr_period=5, fp32_products=fp) as f:
+            nll, grad, st = f.nll_grad()
+            out[fp] = (nll, grad, f.export_lanczos())
+    (n1, g1, l1), (n2, g2, l2) = out[F.F32P_SPLIT], out[F.F32P_MFMA]
+    a1, a2 = np.asarray(l1["alpha"]), np.asarray(l2["alpha"])
+    say("nll rel", abs(n1 - n2) / abs(n2), "grad rel", np.abs(g1 - g2) / np.abs(g2),
+        "alpha rel max", (np.abs(a1 - a2) / np.abs(a2)).max())
+    assert abs(n1 - n2) <= 1e-6 * abs(n2)
+    assert np.all(np.abs(g1 - g2) <= 1e-5 * np.maximum(np.abs(g2), 0.01 * np.abs(g2).max()))
+    assert (np.abs(a1 - a2) / np.abs(a2)).max() <= 1e-4
 
 
 @pytest.mark.parametrize("name", list(CASES))
