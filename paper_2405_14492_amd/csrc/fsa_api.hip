@@ -1388,7 +1388,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   // reaches the tolerance (between 1 and 8 iterations on): few drains while
   // far from convergence, and no idle iterations once every column is done.
   int next_check = 4, prev_it = 0;
-  double prev_res = -1.0;
+  double prev_res = -1.0, rate = 0.0;
   IterGraph<T> ig(st);
   const bool use_graph = c->opt.graph != 0 && !c->timer.on && st != nullptr;  // the null stream cannot be captured
   for (it = 0; it < max_iter; ++it) {
@@ -1428,9 +1428,18 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
           ++it;
           break;
         }
-        prev_res = -1.0;
+        // the columns above the tolerance continue from the float64
+        // residual; the next check comes where the slowest of them is
+        // predicted to reach it at the last rate seen
+        double worst = 0.0;
+        for (int k = 0; k < tp; ++k)
+          if (hs.bn[k] > 0.0) worst = std::max(worst, std::sqrt(std::max(hs.rr[k], 0.0) / hs.bn[k]));
+        int step = 2;
+        if (rate < 0.0 && worst > tol && tol > 0.0)
+          step = (int)std::min(8.0, std::max(1.0, std::ceil(std::log(tol / worst) / rate)));
+        prev_res = worst;
         prev_it = it + 1;
-        next_check = it + 2;
+        next_check = it + 1 + step;
         continue;
       }
       double worst = 0.0;
@@ -1438,7 +1447,7 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
         if (hs.bn[k] > 0.0) worst = std::max(worst, std::sqrt(std::max(hs.rr[k], 0.0) / hs.bn[k]));
       int step = 4;
       if (prev_res > 0.0 && worst > 0.0 && worst < prev_res && tol > 0.0) {
-        const double rate = std::log(worst / prev_res) / (double)(it + 1 - prev_it);  // < 0
+        rate = std::log(worst / prev_res) / (double)(it + 1 - prev_it);  // < 0
         const double remain = std::log(tol / worst) / rate;
         step = (int)std::min(8.0, std::max(1.0, std::floor(remain)));
       }

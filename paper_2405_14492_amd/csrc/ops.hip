@@ -809,29 +809,72 @@ __global__ __launch_bounds__(256) void k_pcg_sparse_update(int64_t n, int ncols,
 
 // u += alpha h (the direction of this iteration), then h = q + beta h with
 // q = (r - t)/D (t = 0 when there is no low-rank part) and p = t + beta p.
+// A thread takes the E = 16 / sizeof(T) consecutive entries of one 16-byte
+// group of the row-major n x ld blocks (ld a multiple of E): group e holds
+// entries E e .. E e + E - 1, in row e / (ld / E), so every access is 16
+// bytes wide and a row's groups are contiguous.  Entries of padding columns
+// (c >= ncols) are written back unchanged, and so are those of a frozen
+// column (alpha 0): it keeps its direction, so that if a float64 residual
+// check reactivates it, its Krylov sequence continues where it stopped.
+template <typename T>
+struct Vec16 {
+  static constexpr int E = 16 / sizeof(T);
+  T v[E];
+};
+template <typename T>
+__device__ __forceinline__ Vec16<T> ld16(const T* p) {
+  Vec16<T> q;
+  if constexpr (sizeof(T) == 4) {
+    const f4 a = *reinterpret_cast<const f4*>(p);
+    q.v[0] = a[0]; q.v[1] = a[1]; q.v[2] = a[2]; q.v[3] = a[3];
+  } else {
+    const d2 a = *reinterpret_cast<const d2*>(p);
+    q.v[0] = a[0]; q.v[1] = a[1];
+  }
+  return q;
+}
+template <typename T>
+__device__ __forceinline__ void st16(T* p, const Vec16<T>& q) {
+  if constexpr (sizeof(T) == 4) *reinterpret_cast<f4*>(p) = f4{q.v[0], q.v[1], q.v[2], q.v[3]};
+  else *reinterpret_cast<d2*>(p) = d2{q.v[0], q.v[1]};
+}
 template <typename T, typename TU>
-__global__ void k_pcg_hupdate(int64_t n, int ncols, int64_t ld, const T* __restrict__ R, const T* __restrict__ Tt,
-                              const double* __restrict__ Dinv, const double* __restrict__ alpha,
-                              const double* __restrict__ beta, T* __restrict__ H, T* __restrict__ P,
-                              TU* __restrict__ U, int has_lr) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t p = e / ncols;
-  int c = (int)(e % ncols);
-  if (p >= n) return;
-  int64_t o = p * ld + c;
-  const double b = beta[c], a = alpha[c];
-  // a frozen column (alpha 0) keeps its direction: if a float64 residual
-  // check reactivates it, its Krylov sequence continues where it stopped
-  if (a == 0.0) return;
-  const double h = (double)H[o];
-  const double t = has_lr ? (double)Tt[o] : 0.0;
-  const double r = (double)R[o];
+__global__ __launch_bounds__(256) void k_pcg_hupdate(int64_t ngroups, int64_t gpr, int ncols, const T* __restrict__ R,
+                                                     const T* __restrict__ Tt, const double* __restrict__ Dinv,
+                                                     const double* __restrict__ alpha, const double* __restrict__ beta,
+                                                     T* __restrict__ H, T* __restrict__ P, TU* __restrict__ U,
+                                                     int has_lr) {
+  static_assert(sizeof(T) == sizeof(TU), "U has the block's element size");
+  constexpr int E = Vec16<T>::E;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= ngroups) return;
+  // row of group e (32-bit division while the group count allows)
+  const int64_t p = ngroups <= 0xffffffffll ? (int64_t)((unsigned)e / (unsigned)gpr) : e / gpr;
+  const int c0 = E * (int)(e - p * gpr);
+  const int64_t o = E * e;
   const double di = Dinv[p];
-  const double u = (double)U[o];
-  const double pv = has_lr ? (double)P[o] : 0.0;
-  U[o] = (TU)(u + a * h);
-  H[o] = (T)((r - t) * di + b * h);
-  if (has_lr) P[o] = (T)(t + b * pv);
+  Vec16<T> h = ld16(H + o), r = ld16(R + o);
+  Vec16<T> t{}, pv{};
+  if (has_lr) {
+    t = ld16(Tt + o);
+    pv = ld16(P + o);
+  }
+  Vec16<TU> u = ld16(U + o);
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int c = c0 + j;
+    const double a = c < ncols ? alpha[c] : 0.0;
+    if (a == 0.0) continue;
+    const double b = beta[c];
+    const double hj = (double)h.v[j];
+    const double tj = has_lr ? (double)t.v[j] : 0.0;
+    u.v[j] = (TU)((double)u.v[j] + a * hj);
+    h.v[j] = (T)(((double)r.v[j] - tj) * di + b * hj);
+    if (has_lr) pv.v[j] = (T)(tj + b * (double)pv.v[j]);
+  }
+  st16(U + o, u);
+  st16(H + o, h);
+  if (has_lr) st16(P + o, pv);
 }
 
 // One workgroup per column c (flags zeroed beforehand): |b|^2, r^T q and the
@@ -1148,21 +1191,28 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
     KT_END(b, KT_SMALL);
   }
   // 5. h = q + beta h, p = t + beta p
-  int64_t tot = b.n * b.ncols;
-  KT_BEGIN(b, KT_UPDATE);
-  bool u32 = false;
-  if constexpr (sizeof(T) == 4) {
-    if (b.U32) {
-      hipLaunchKernelGGL((k_pcg_hupdate<T, float>), dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols,
-                         (int64_t)b.ld, (const T*)b.R, (const T*)b.Tt, op.Dinv, b.alpha, b.beta, b.H, b.P, b.U32,
-                         lr ? 1 : 0);
-      u32 = true;
-    }
+  constexpr int E = Vec16<T>::E;
+  const uintptr_t al = reinterpret_cast<uintptr_t>(b.R) | reinterpret_cast<uintptr_t>(b.H) |
+                       reinterpret_cast<uintptr_t>(b.P) | reinterpret_cast<uintptr_t>(b.Tt) |
+                       reinterpret_cast<uintptr_t>(b.U) | reinterpret_cast<uintptr_t>(b.U32);
+  if ((b.ld % E) || (al & 15)) {
+    set_error("PCG blocks must be 16-byte aligned with a stride that is a multiple of %d (ld %d)", E, b.ld);
+    return FSA_ERR_INVALID_ARG;
   }
-  if (!u32)
-    hipLaunchKernelGGL((k_pcg_hupdate<T, double>), dim3(ceil_div(tot, 256)), dim3(256), 0, st, b.n, b.ncols,
-                       (int64_t)b.ld, (const T*)b.R, (const T*)b.Tt, op.Dinv, b.alpha, b.beta, b.H, b.P, b.U,
+  const int64_t gpr = b.ld / E, ngroups = b.n * gpr;
+  KT_BEGIN(b, KT_UPDATE);
+  if constexpr (sizeof(T) == 4) {
+    if (!b.U32) {
+      set_error("float32 PCG block without its float32 solution increment");
+      return FSA_ERR_INVALID_ARG;
+    }
+    hipLaunchKernelGGL((k_pcg_hupdate<T, float>), dim3(ceil_div(ngroups, 256)), dim3(256), 0, st, ngroups, gpr,
+                       b.ncols, (const T*)b.R, (const T*)b.Tt, op.Dinv, b.alpha, b.beta, b.H, b.P, b.U32,
                        lr ? 1 : 0);
+  } else {
+    hipLaunchKernelGGL((k_pcg_hupdate<T, double>), dim3(ceil_div(ngroups, 256)), dim3(256), 0, st, ngroups, gpr,
+                       b.ncols, (const T*)b.R, (const T*)b.Tt, op.Dinv, b.alpha, b.beta, b.H, b.P, b.U, lr ? 1 : 0);
+  }
   KT_END(b, KT_UPDATE);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
