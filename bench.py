@@ -41,8 +41,9 @@ def log(*a):
 
 # rocprofv3 kernel names of the four PCG kernel classes, per element type
 KERNEL_NAMES = {
-    "f32": ["k_spmm_tiled<2>", "k_reduce_gemm_f32<float, true, 1>", "k_rows_gemm_f32<float, true, 2>",
-            "k_pcg_hupdate<float, float>"],
+    "f32": ["k_spmm_tiled<2>", "k_reduce_split<true, 1>", "k_rows_split<2, 8>", "k_pcg_hupdate<float, float>"],
+    "f32mfma": ["k_spmm_tiled<2>", "k_reduce_gemm_f32<float, true, 1>", "k_rows_gemm_f32<float, true, 2>",
+                "k_pcg_hupdate<float, float>"],
     "bf16a": ["k_spmm_tiled<2>", "k_reduce_bf16<true, 1>", "k_rows_bf16<2>", "k_pcg_hupdate<float, float>"],
     "f64": ["k_spmm_dense<double, 2>", "k_reduce_gemm_f64<true, 1>",
             "k_rows_gemm_f64<true, 2, 3>", "k_pcg_hupdate<double, double>"],
@@ -110,14 +111,14 @@ def measured_traffic(kernel_name):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
-def run_mode(F, dev, w, precision, steps, warmup, tol, torch, rr_period=20):
+def run_mode(F, dev, w, precision, steps, warmup, tol, torch, rr_period=20, fp32_products=0):
     """Warmup, then one untimed step with every kernel class timed by HIP
     events (per-class launch averages; the dominant class), then the timed
     steps with only the dominant class timed (each timed launch adds two event
     records to the stream, about 3 us each)."""
     def options(profile):
         return F.make_options(num_probes=w.num_probes, seed=w.seed, tol=tol, max_iter=1000, precision=precision,
-                              rr_period=rr_period, profile=profile)
+                              rr_period=rr_period, profile=profile, fp32_products=fp32_products)
     theta = w.theta
 
     def step(opt):
@@ -386,8 +387,11 @@ def main():
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--m", type=int, default=500)
     ap.add_argument("--probes", type=int, default=50)
-    ap.add_argument("--modes", default="fp64,mixed,bf16a",
-                    help="comma list of fp64, mixed (float32 operator), bf16a (float32 operator, bfloat16 A)")
+    ap.add_argument("--modes", default="fp64,fp64_tol6,mixed,mixed_mfma,bf16a",
+                    help="comma list of fp64 (tolerance 1e-8, the accuracy reference), fp64_tol6 (float64 at the "
+                         "mixed modes' tolerance 1e-6), mixed (float32 operator, float32 products of A split into "
+                         "bfloat16 parts), mixed_mfma (the same on the float32 matrix cores), bf16a (float32 "
+                         "operator, bfloat16 A)")
     ap.add_argument("--rr-period", type=int, default=20,
                     help="mixed modes: float64 residual replacement every this many iterations (0 = never)")
     ap.add_argument("--cpu-sample-n", type=int, default=80_000)
@@ -439,17 +443,19 @@ def main():
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
     results = {}
     for mode in args.modes.split(","):
-        prec = {"mixed": F.MIXED_FP32, "bf16a": F.MIXED_BF16A, "fp64": F.FP64}[mode]
+        prec = {"mixed": F.MIXED_FP32, "mixed_mfma": F.MIXED_FP32, "bf16a": F.MIXED_BF16A, "fp64": F.FP64,
+                "fp64_tol6": F.FP64}[mode]
         tol = 1e-8 if mode == "fp64" else 1e-6
+        fp32p = F.F32P_MFMA if mode == "mixed_mfma" else F.F32P_SPLIT
         log(f"mode {mode}: warmup {args.warmup}, steps {args.steps}")
-        results[mode] = run_mode(F, dev, w, prec, args.steps, args.warmup, tol, torch, args.rr_period)
+        results[mode] = run_mode(F, dev, w, prec, args.steps, args.warmup, tol, torch, args.rr_period, fp32p)
         log(f"mode {mode}: {results[mode]['value']:.1f} probe-iters/s, {results[mode]['ms_per_step']:.2f} ms/step, "
             f"iters {results[mode]['iters']}, kernel ms/launch "
             f"{[round(a / max(b, 1), 4) for a, b in zip(results[mode]['profiled_step_kernel_ms'], results[mode]['profiled_step_kernel_launches'])]}")
     main_mode = "mixed" if "mixed" in results else list(results)[0]
     r = results[main_mode]
-    dtype = "f64" if main_mode == "fp64" else "f32"
-    rkey = {"mixed": "f32", "bf16a": "bf16a", "fp64": "f64"}[main_mode]
+    dtype = "f64" if main_mode in ("fp64", "fp64_tol6") else "f32"
+    rkey = {"mixed": "f32", "mixed_mfma": "f32mfma", "bf16a": "bf16a", "fp64": "f64", "fp64_tol6": "f64"}[main_mode]
     out = {
         "metric": "PCG probe-iters/s at n=500k,m=500,t=50 (mixed precision; fp64 beside it)",
         "value": r["value"],
@@ -471,10 +477,23 @@ def main():
         "pcg_only_probe_iters_per_s": r["pcg_only_probe_iters_per_s"],
         "modes": results,
     }
+    if "fp64_tol6" in results and "mixed" in results:
+        # the same PCG tolerance (1e-6) in both precisions: probe-iterations/s and time per likelihood step
+        out["mixed_over_fp64_same_tol"] = results["mixed"]["value"] / results["fp64_tol6"]["value"]
+        out["mixed_step_speedup_same_tol"] = results["fp64_tol6"]["ms_per_step"] / results["mixed"]["ms_per_step"]
+        out["mixed_vs_fp64_same_tol_rel_nll"] = (abs(results["mixed"]["nll"] - results["fp64_tol6"]["nll"])
+                                                 / abs(results["fp64_tol6"]["nll"]))
     if "fp64" in results and "mixed" in results:
         out["mixed_over_fp64"] = results["mixed"]["value"] / results["fp64"]["value"]
+        out["mixed_step_speedup"] = results["fp64"]["ms_per_step"] / results["mixed"]["ms_per_step"]
         out["mixed_vs_fp64_rel_nll"] = abs(results["mixed"]["nll"] - results["fp64"]["nll"]) / abs(results["fp64"]["nll"])
+        out["mixed_vs_fp64_rel_grad"] = [abs(a - c) / max(abs(c), 1e-300)
+                                         for a, c in zip(results["mixed"]["grad"], results["fp64"]["grad"])]
         out["roofline_fp64"] = roofline(results["fp64"], args.n, args.m, args.probes + 1, "f64")
+    if "mixed_mfma" in results:
+        out["roofline_mixed_mfma"] = roofline(results["mixed_mfma"], args.n, args.m, args.probes + 1, "f32mfma")
+        if "mixed" in results:
+            out["split_over_mfma"] = results["mixed"]["value"] / results["mixed_mfma"]["value"]
     if "fp64" in results and "bf16a" in results:
         f, g = results["fp64"], results["bf16a"]
         out["bf16a_over_fp64"] = g["value"] / f["value"]

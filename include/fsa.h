@@ -66,7 +66,13 @@ typedef enum { FSA_COV_EXPONENTIAL = 0, FSA_COV_MATERN32 = 1 } fsa_cov;
  *     operator every rr_period iterations.  A column stops once its float32
  *     recurrence residual is below the tolerance and the float64 residual
  *     b - Sigma~ u, recomputed then, confirms it; a column it does not
- *     confirm continues its CG sequence from the float64 residual.
+ *     confirm continues its CG sequence from the float64 residual.  Where
+ *     the low-rank part dominates (|A A^T| / D around 10^5 and more), the
+ *     float32 Woodbury application q = (r - A C^{-1} A^T D^{-1} r) / D
+ *     cancels most of its digits; a likelihood solve whose float32 iteration
+ *     breaks down, or whose slowest column's residual does not halve over
+ *     three replacement periods, is repeated in float64
+ *     (fsa_stats.fp64_fallback).
  *   MIXED_BF16A: MIXED_FP32 on a model whose whitened low-rank factor A is
  *     rounded to bfloat16 (to nearest even, once, right after whitening).
  *     The rounded factor is used everywhere, in float64 where the method is
@@ -85,11 +91,10 @@ typedef enum { FSA_FP64 = 0, FSA_MIXED_FP32 = 1, FSA_MIXED_BF16A = 2 } fsa_preci
 /* fsa_options.fp32_products: the float32 products of MIXED_FP32's low-rank
  * PCG passes (A^T D^{-1} r and A C^{-1} w over the n x m factor).
  *   FSA_F32P_SPLIT (default): on the bfloat16 matrix cores, every float32
- *     operand split exactly into three bfloat16 parts and the six partial
- *     products above 2^-23 of the result summed in float32; the dropped ones
- *     amount to about one float32 rounding per product.  Same arithmetic
- *     contract as float32 (float32 operands, float32 accumulation), at 6/16
- *     of the matrix-core time, so the passes are bound by reading A.
+ *     operand split exactly into three bfloat16 parts and all partial
+ *     products but the smallest (below 2^-32 of the result) summed in
+ *     float32: the float32 product up to accumulation order, at half of the
+ *     float32 matrix-core time, so the passes are bound by reading A.
  *     Blocks of more than 52 columns take the float32 matrix cores.
  *   FSA_F32P_MFMA: on the float32 matrix cores (16x16x4). */
 typedef enum { FSA_F32P_SPLIT = 0, FSA_F32P_MFMA = 1 } fsa_fp32_products;
@@ -176,6 +181,13 @@ typedef struct {
    * estimate */
   double cv_c[3];
   double trace_P[3];
+  /* MIXED_FP32 / MIXED_BF16A: 1 if the float32 solve broke down or stalled and
+   * the likelihood solve was repeated in float64 (the results are then the
+   * float64 ones); fallback_probe_iters counts the abandoned float32
+   * iterations (summed over columns) */
+  int32_t fp64_fallback;
+  int32_t reserved1;
+  int64_t fallback_probe_iters;
 } fsa_stats;
 
 /* Default options: 50 probes, seed 0, tol 1e-8, max_iter 1000, FP64. */

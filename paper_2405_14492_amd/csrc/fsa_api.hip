@@ -707,6 +707,7 @@ __global__ void k_fill_weight_n(double* w, int ncols, double n) {
 using namespace fsa;
 
 struct fsa_ctx {
+  bool mixed_stalled = false;  // the last float32 solve made no progress (see run_pcg)
   int64_t n = 0;
   int m = 0, mp = 0;
   int t = 0, tp = 0, ld = 0, ldw = 0;
@@ -1389,6 +1390,14 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   // far from convergence, and no idle iterations once every column is done.
   int next_check = 4, prev_it = 0;
   double prev_res = -1.0, rate = 0.0;
+  // Float32 stall: the slowest column's residual (the float64 one right after
+  // a replacement) has not halved over three replacement periods.  Where
+  // |A A^T| exceeds D by ~10^5 the float32 Woodbury application cancels
+  // most of its digits, and the float32 iteration can stall or break down.
+  double stall_best = INFINITY;
+  int stall_it = 0;
+  const int stall_span = 3 * std::max(c->opt.rr_period, 10);
+  c->mixed_stalled = false;
   IterGraph<T> ig(st);
   const bool use_graph = c->opt.graph != 0 && !c->timer.on && st != nullptr;  // the null stream cannot be captured
   for (it = 0; it < max_iter; ++it) {
@@ -1445,6 +1454,16 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
       double worst = 0.0;
       for (int k = 0; k < tp; ++k)
         if (hs.bn[k] > 0.0) worst = std::max(worst, std::sqrt(std::max(hs.rr[k], 0.0) / hs.bn[k]));
+      if constexpr (sizeof(T) == 4) {
+        if (worst < 0.5 * stall_best) {
+          stall_best = worst;
+          stall_it = it + 1;
+        } else if (it + 1 - stall_it >= stall_span) {
+          c->mixed_stalled = true;
+          ++it;
+          break;
+        }
+      }
       int step = 4;
       if (prev_res > 0.0 && worst > 0.0 && worst < prev_res && tol > 0.0) {
         rate = std::log(worst / prev_res) / (double)(it + 1 - prev_it);  // < 0
@@ -1518,6 +1537,10 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
     return FSA_ERR_BREAKDOWN;
   }
   c->solved = true;
+  if (c->mixed_stalled) {
+    set_error("float32 PCG stalled at relative residual %.3g after %d iterations", rmax, imax);
+    return FSA_ERR_NOT_CONVERGED;
+  }
   if (!fixed && flags[0] > 0) {
     set_error("PCG did not converge in %d iterations (%d columns active)", max_iter, flags[0]);
     return FSA_ERR_NOT_CONVERGED;
@@ -2013,8 +2036,21 @@ static fsa_status nll_grad_core(fsa_ctx* c, const fsa_theta* theta, double* nll,
   if (want_grad && c->deriv_state == 0) mark_derivative(c);
   double ms_pcg = 0;
   fsa_status s;
-  if (c->opt.precision != FSA_FP64) s = run_pcg<float>(c, &ms_pcg);
-  else s = run_pcg<double>(c, &ms_pcg);
+  if (c->opt.precision != FSA_FP64) {
+    s = run_pcg<float>(c, &ms_pcg);
+    if (s == FSA_ERR_BREAKDOWN || (s == FSA_ERR_NOT_CONVERGED && c->mixed_stalled)) {
+      // the float32 iteration cannot resolve this system: the solve is
+      // repeated in float64 on the float64 operator the replacements use
+      const int64_t wasted = c->stats.probe_iters;
+      double ms64 = 0;
+      s = run_pcg<double>(c, &ms64);
+      ms_pcg += ms64;
+      c->stats.fp64_fallback = 1;
+      c->stats.fallback_probe_iters = wasted;
+    }
+  } else {
+    s = run_pcg<double>(c, &ms_pcg);
+  }
   if (c->deriv_marked) FSA_TRY(enqueue_derivative(c));  // the solve ended before its first iteration
   if (s != FSA_OK && s != FSA_ERR_NOT_CONVERGED) {
     FSA_TRY(join_slq(c));

@@ -72,7 +72,8 @@ class fsa_stats(C.Structure):
                 ("ms_backward", C.c_double), ("ms_total", C.c_double), ("nnz", C.c_int64),
                 ("kernel_ms", C.c_double * 5), ("kernel_launches", C.c_int32 * 5),
                 ("grad_trace", C.c_double * 3), ("grad_quad", C.c_double * 3),
-                ("cv_c", C.c_double * 3), ("trace_P", C.c_double * 3)]
+                ("cv_c", C.c_double * 3), ("trace_P", C.c_double * 3), ("fp64_fallback", C.c_int32),
+                ("reserved1", C.c_int32), ("fallback_probe_iters", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

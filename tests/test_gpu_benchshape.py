@@ -278,3 +278,30 @@ def test_predictive_variances_against_dense_subproblem(F):
     assert np.abs(z).max() < 5.0
     assert abs(np.mean(var - exact)) <= 4 * np.sqrt(np.sum(se * se)) / len(var)
     assert 0.7 < np.mean(z * z) < 1.3
+
+
+def test_mixed_falls_back_to_fp64_where_float32_cannot_resolve(F):
+    """A strongly low-rank problem (n = 6,313, m = 500, Matern-3/2 with rho =
+    0.153: |A A^T| exceeds the nugget by ~10^4): the float32 Woodbury
+    application loses most of its digits, the float32 iteration stalls, and
+    MIXED_FP32 repeats the solve in float64 (its result is then the float64
+    one, bit for bit, and the stats say so).  A well-conditioned request of
+    the same stream stays in float32."""
+    trace = configs.serving_trace()
+    hard = next(r for r in trace if r.index == 5)
+    locs, y, ind, _ = hard.materialize()
+    with F.FSA(locs, y, hard.theta, ind, hard.gamma, num_probes=20, seed=4005, tol=1e-6, max_iter=2000) as f:
+        nll64, grad64, st64 = f.nll_grad()
+    with F.FSA(locs, y, hard.theta, ind, hard.gamma, num_probes=20, seed=4005, tol=1e-6, max_iter=2000,
+               precision=F.MIXED_FP32, rr_period=20) as f:
+        nll, grad, st = f.nll_grad()
+    say("hard: fallback", st["fp64_fallback"], "abandoned probe-iterations", st["fallback_probe_iters"],
+        "iters", st["iters_max"], st64["iters_max"])
+    assert st["fp64_fallback"] == 1 and st["fallback_probe_iters"] > 0
+    assert nll == nll64 and np.array_equal(grad, grad64)
+    easy = next(r for r in trace if r.index == 0)
+    locs, y, ind, _ = easy.materialize()
+    with F.FSA(locs, y, easy.theta, ind, easy.gamma, num_probes=20, seed=4005, tol=1e-6, max_iter=2000,
+               precision=F.MIXED_FP32, rr_period=20) as f:
+        nll, grad, st = f.nll_grad()
+    assert st["fp64_fallback"] == 0 and st["fallback_probe_iters"] == 0
