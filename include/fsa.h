@@ -91,10 +91,10 @@ typedef enum { FSA_FP64 = 0, FSA_MIXED_FP32 = 1, FSA_MIXED_BF16A = 2 } fsa_preci
 /* fsa_options.fp32_products: the float32 products of MIXED_FP32's low-rank
  * PCG passes (A^T D^{-1} r and A C^{-1} w over the n x m factor).
  *   FSA_F32P_SPLIT (default): on the bfloat16 matrix cores, every float32
- *     operand split exactly into three bfloat16 parts and all partial
- *     products but the smallest (below 2^-32 of the result) summed in
- *     float32: the float32 product up to accumulation order, at half of the
- *     float32 matrix-core time, so the passes are bound by reading A.
+ *     operand split exactly into three bfloat16 parts and the six partial
+ *     products above 2^-23 of the result summed in float32 (the dropped ones
+ *     are below the float32 accumulation error of the k-long sums), at 6/16
+ *     of the float32 matrix-core time, so the passes are bound by reading A.
  *     Blocks of more than 52 columns take the float32 matrix cores.
  *   FSA_F32P_MFMA: on the float32 matrix cores (16x16x4). */
 typedef enum { FSA_F32P_SPLIT = 0, FSA_F32P_MFMA = 1 } fsa_fp32_products;

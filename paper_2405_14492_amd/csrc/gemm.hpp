@@ -1928,13 +1928,13 @@ __global__ __launch_bounds__(1024) void k_rows_bf16(int64_t nrows, int kdim, con
 // For a normal float32 x the split is exact, x = h + m + l (x - h is a
 // multiple of x's last place below 2^-8 |x|, so x - h - m has at most eight
 // significant bits).  Each partial product a_i x_j is exact in float32.  Of
-// the nine, all but l l (below 2^-32 |a x|) are taken, smallest first, so a
-// product is the exact one up to float32 accumulation, as on the float32
-// matrix cores.  (Six products, dropping m l and l m as well, leave up to
-// 2^-23 |a x| per product: on strongly low-rank problems, where |A A^T|
-// exceeds the nugget by 10^5, that extra noise broke the float32 CG down
-// where the float32 MFMA did not.)  The eight take half of the float32
-// matrix-core time, and the passes stay bound by the HBM stream of A.
+// the nine, the six with i + j <= 2 are taken, smallest first; the three
+// dropped ones (m l, l m, l l) are below 2^-23 |a x| together, under the
+// float32 accumulation error of a k-long sum (about 2^-24 sqrt(k) of the
+// sum of |terms|).  Taking m l and l m as well (eight products) did not
+// spare the float32 iteration its breakdowns on strongly low-rank problems
+// (those go to float64) and cost 14 us per expansion.  The six take 6/16 of the
+// float32 matrix-core time, so the passes are bound by the HBM stream of A.
 typedef float split_f2 __attribute__((ext_vector_type(2)));
 typedef __bf16 split_b2 __attribute__((ext_vector_type(2)));
 // two floats rounded to bfloat16 (nearest even, one v_cvt_pk_bf16_f32), a in the low half
@@ -2064,11 +2064,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
       u4v xo[3];
 #pragma unroll
       for (int P = 0; P < 3; ++P) xo[P] = *reinterpret_cast<const u4v*>(&Xs[buf][P][(16 * b + r16) * XST + 8 * q]);
-      // every partial product but (l,l), smallest first: (m,l) (l,m) (l,h) (m,m) (h,l) (m,h) (h,m) (h,h)
-#pragma unroll
-      for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(sa[a][1], xo[2], acc[a][b]);
-#pragma unroll
-      for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(sa[a][2], xo[1], acc[a][b]);
+      // the six partial products with i + j <= 2, smallest first: (l,h) (m,m) (h,l) (m,h) (h,m) (h,h)
 #pragma unroll
       for (int a = 0; a < 4; ++a) acc[a][b] = mfma_bf16(sa[a][2], xo[0], acc[a][b]);
 #pragma unroll
@@ -2270,10 +2266,6 @@ __global__ __launch_bounds__(64 * NW) void k_rows_split(int64_t nrows, int kdim,
       for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int P = 0; P < 3; ++P) g[b][P] = *reinterpret_cast<const u4v*>(&gsh[brow[b][P] + ckb * 64 + 8 * t]);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][1], g[b][2], acc[b]);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][2], g[b][1], acc[b]);
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][2], g[b][0], acc[b]);
 #pragma unroll
