@@ -72,7 +72,9 @@ typedef enum { FSA_COV_EXPONENTIAL = 0, FSA_COV_MATERN32 = 1 } fsa_cov;
  *     cancels most of its digits; a likelihood solve whose float32 iteration
  *     breaks down, or whose slowest column's residual does not halve over
  *     three replacement periods, is repeated in float64
- *     (fsa_stats.fp64_fallback).
+ *     (fsa_stats.fp64_fallback).  The derivative factor F of the gradient
+ *     (which enters the gradient only) is a float32 product from the float32
+ *     copy of A.
  *   MIXED_BF16A: MIXED_FP32 on a model whose whitened low-rank factor A is
  *     rounded to bfloat16 (to nearest even, once, right after whitening).
  *     The rounded factor is used everywhere, in float64 where the method is
@@ -182,8 +184,9 @@ typedef struct {
   double cv_c[3];
   double trace_P[3];
   /* MIXED_FP32 / MIXED_BF16A: 1 if the float32 solve broke down or stalled and
-   * the likelihood solve was repeated in float64 (the results are then the
-   * float64 ones); fallback_probe_iters counts the abandoned float32
+   * the likelihood solve was repeated in float64 (the likelihood is then the
+   * float64 one; the gradient keeps the mode's float32 derivative factor);
+   * fallback_probe_iters counts the abandoned float32
    * iterations (summed over columns) */
   int32_t fp64_fallback;
   int32_t reserved1;

@@ -1591,10 +1591,21 @@ static fsa_status build_derivative(fsa_ctx* c, hipStream_t st) {
   FSA_HIP(hipGetLastError());
   FSA_TRY(transpose_scale(T1, E, mp, -1.0, st));  // -Phi(E)^T (E is not needed past here)
   FSA_TRY(c->F.alloc((size_t)c->n * mp));
-  FSA_TRY(derivative_factor(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->LminvT.p, c->A.p, E, c->F.p, st));
+  // MIXED_FP32: F and the derivative values only enter the gradient (its 1e-4
+  // bar), so both run in float32 arithmetic from the float32 copy of A, at
+  // twice the float64 MFMA rate (F is kept in float64 too, widened, for the
+  // gradient's float64 passes)
+  const bool f32 = c->opt.precision == FSA_MIXED_FP32;
+  Buf<float> Ff;
+  if (f32) FSA_TRY(Ff.alloc((size_t)c->n * mp));
+  FSA_TRY(derivative_factor(c->grid.xs.p, c->n, c->ind.p, c->m, mp, c->th, c->LminvT.p, c->A.p, E, c->F.p, st,
+                            f32 ? c->Af.p : nullptr, f32 ? Ff.p : nullptr));
   FSA_TRY(c->dvals.alloc(c->csr.nnz));
-  FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, c->F.p, c->F.p, mp, c->th, c->gamma, true, true,
-                          c->dvals.p, nullptr, st));
+  if (f32)
+    FSA_TRY(derivative_values_f32(c->grid, c->csr, c->Af.p, Ff.p, mp, c->th, c->gamma, c->dvals.p, st));
+  else
+    FSA_TRY(residual_values(c->grid, c->grid, c->csr, c->A.p, c->A.p, c->F.p, c->F.p, mp, c->th, c->gamma, true,
+                            true, c->dvals.p, nullptr, st));
   if (c->opt.control_variate != FSA_CV_NONE) {
     // Tr(P^{-1} dP/dtheta) by Woodbury (App. E, F): with C = L_C L_C^T,
     // Tr P^{-1} = sum 1/D - sum |L_C^{-1} A_p|^2 / D^2, Tr(P^{-1} dD) likewise

@@ -29,6 +29,7 @@ constexpr int XS_LD = 68;  // LDS row stride of the X chunk
 // ------------------------------------------------------------------ operand loaders
 template <typename T>
 struct RowsOp {  // row i of a point-major matrix
+  typedef T value_type;
   const T* a;
   int64_t lda;
   __device__ __forceinline__ V4<T> operator()(int64_t i, int k) const { return load4(a + i * lda + k); }
@@ -36,6 +37,7 @@ struct RowsOp {  // row i of a point-major matrix
 
 template <typename T>
 struct Rows2Op {  // row i of [a1 | a2] (two point-major matrices, kseg each)
+  typedef T value_type;
   const T* a1;
   const T* a2;
   int64_t lda;
@@ -1455,9 +1457,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   // the dense block Dv reuses the row-operand tile once the products are
   // done (66 KB of LDS: two workgroups per CU)
   static_assert(DLD == XLD, "Dv aliases Xs");
-  __shared__ __attribute__((aligned(16))) double Xs[32 * XLD];
-  double* const Dv = Xs;
-  typedef Mfma<double>::acc acc_t;
+  // operand arithmetic: the rows' element type (float64, or float32 with
+  // float32 MFMA); the dense block is float64 either way
+  typedef typename XOp::value_type T;
+  __shared__ __attribute__((aligned(16))) double Sm[32 * XLD];
+  T* const Xs = reinterpret_cast<T*>(Sm);
+  double* const Dv = Sm;
+  typedef typename Mfma<T>::acc acc_t;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1503,30 +1509,35 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int u = tid; u < 32 * (kn / 4); u += 512) {
           const int r = u / (kn / 4), k4 = (u - r * (kn / 4)) * 4;
           const int64_t p = g0 + min(r, nrg - 1);
-          const V4<double> x = xop(p, kc0 + k4);
-          double* dst = &Xs[r * XLD + k4];
-          *reinterpret_cast<d2*>(dst) = d2{x.v[0], x.v[1]};
-          *reinterpret_cast<d2*>(dst + 2) = d2{x.v[2], x.v[3]};
+          const V4<T> x = xop(p, kc0 + k4);
+          T* dst = &Xs[r * XLD + k4];
+          if constexpr (sizeof(T) == 8) {
+            *reinterpret_cast<d2*>(dst) = d2{x.v[0], x.v[1]};
+            *reinterpret_cast<d2*>(dst + 2) = d2{x.v[2], x.v[3]};
+          } else {  // float rows of XLD = 258 are 8-byte aligned
+            *reinterpret_cast<float2*>(dst) = float2{x.v[0], x.v[1]};
+            *reinterpret_cast<float2*>(dst + 2) = float2{x.v[2], x.v[3]};
+          }
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           if (!tile_on[t]) continue;
-          V4<double> b0 = yop(qcol[t], kc0 + 4 * q), b1;
+          V4<T> b0 = yop(qcol[t], kc0 + 4 * q), b1;
           for (int ks = 0; ks < kn; ks += 32) {
             b1 = yop(qcol[t], kc0 + min(ks + 16, kn - 16) + 4 * q);
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-              const double* xa = &Xs[(a * 16 + r16) * XLD + ks + 4 * q];
+              const T* xa = &Xs[(a * 16 + r16) * XLD + ks + 4 * q];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) acc[t][a] = Mfma<double>::op(xa[j], b0.v[j], acc[t][a]);
+              for (int j = 0; j < 4; ++j) acc[t][a] = Mfma<T>::op(xa[j], b0.v[j], acc[t][a]);
             }
             b0 = yop(qcol[t], kc0 + min(ks + 32, kn - 16) + 4 * q);
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-              const double* xa = &Xs[(a * 16 + r16) * XLD + ks + 16 + 4 * q];
+              const T* xa = &Xs[(a * 16 + r16) * XLD + ks + 16 + 4 * q];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) acc[t][a] = Mfma<double>::op(xa[j], b1.v[j], acc[t][a]);
+              for (int j = 0; j < 4; ++j) acc[t][a] = Mfma<T>::op(xa[j], b1.v[j], acc[t][a]);
             }
           }
         }
@@ -1538,7 +1549,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) Dv[(a * 16 + Mfma<double>::orow(q, r)) * DLD + 16 * (w + 8 * t) + r16] = acc[t][a][r];
+          for (int r = 0; r < 4; ++r)
+            Dv[(a * 16 + Mfma<T>::orow(q, r)) * DLD + 16 * (w + 8 * t) + r16] = (double)acc[t][a][r];
       }
       __syncthreads();
       // (a) this group's nonzeros with a forward column

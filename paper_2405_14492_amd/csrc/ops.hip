@@ -237,6 +237,23 @@ fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const
   return FSA_OK;
 }
 
+// The derivative values of one point set from float32 rows: [Ff | Af]_p .
+// [Af | Ff]_q on the float32 MFMA, the rest of DValFn in float64.
+fsa_status derivative_values_f32(const Grid& g, const Csr& csr, const float* Af, const float* Ff, int mp,
+                                 const Theta& th, double gamma, double* vals, hipStream_t st) {
+  if (g.ncell == 0 || csr.nnz == 0) return FSA_OK;
+  GridDesc gd = g.desc;
+  gd.gamma = gamma;
+  dim3 grid(8 * ceil_div(g.ncell, 8));
+  const int sw = 16;
+  Rows2Op<float> xo{Ff, Af, mp, mp}, yo{Af, Ff, mp, mp};
+  DValFn fn{th, gamma};
+  hipLaunchKernelGGL((k_sddmm_sym<Rows2Op<float>, Rows2Op<float>, DValFn>), grid, dim3(512), 0, st, g.cstart.p,
+                     g.ncell, g.xs.p, gd, csr.row_ptr.p, csr.col.p, csr.key.p, 2 * mp, xo, yo, fn, vals, sw);
+  FSA_HIP(hipGetLastError());
+  return FSA_OK;
+}
+
 struct ReduceShape {
   int nchunks, ppc, ncb, nmb, zb, threads;
 };

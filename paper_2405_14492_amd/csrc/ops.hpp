@@ -75,9 +75,11 @@ fsa_status tri_inverse(const double* L, double* Linv, int mp, hipStream_t st);
 fsa_status rows_times_lower_t(const double* X, int64_t n, int mp, const double* WT, double* Y, hipStream_t st);
 // F := dSigma_nm L_m^{-T} - A Phi(E)^T (point-major n x mp), dSigma_nm generated on the fly;
 // LminvT = (L_m^{-1})^T, PhiT_neg = -Phi(E)^T, both row-major mp x mp
+// Af non-null: in float32 arithmetic from the float32 copy of A (F_out gets the
+// float32 result widened; Ff_out, if non-null, the float32 one)
 fsa_status derivative_factor(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
                              const double* LminvT, const double* A, const double* PhiT_neg, double* F_out,
-                             hipStream_t st);
+                             hipStream_t st, const float* Af = nullptr, float* Ff_out = nullptr);
 
 // ---- build-time contractions (float64) ----
 // out[i][k] = c(x_i, ind_k) (deriv: dc/drho) for k < m, 0 for m <= k < mp
@@ -95,6 +97,10 @@ fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp,
 fsa_status residual_values(const Grid& rg, const Grid& cg, const Csr& csr, const double* Xr, const double* Yc,
                            const double* Fr, const double* Fc, int mp, const Theta& th, double gamma, bool self,
                            bool deriv, double* vals, double* D, hipStream_t st);
+// deriv values of one point set (grid g against itself) from float32 rows:
+// v = (dc/drho(d) - [Ff|Af]_p . [Af|Ff]_q) W(d/gamma), the dot on the float32 MFMA
+fsa_status derivative_values_f32(const Grid& g, const Csr& csr, const float* Af, const float* Ff, int mp,
+                                 const Theta& th, double gamma, double* vals, hipStream_t st);
 // C = I + A D^{-1} A^T (mp x mp float64)
 fsa_status capacitance(const double* A, const double* D, int64_t n, int mp, double* C, Scratch& s, hipStream_t st);
 

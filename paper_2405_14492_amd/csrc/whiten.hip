@@ -12,6 +12,7 @@
 //    against [L_m^{-T} ; -Phi(E)^T].
 #include "common.hpp"
 #include "kernels.hpp"
+#include <type_traits>
 #include "ops.hpp"
 
 namespace fsa {
@@ -135,11 +136,26 @@ constexpr int WS_LD = WG_COLS + 4;
 
 enum { XSRC_MEM = 0, XSRC_COV = 1, XSRC_DCOV = 2 };
 
+// float32 versions of cov_d and dcov_drho (the float32 derivative factor)
+__device__ __forceinline__ float cov_f(float d, const Theta& th) {
+  const float s1 = (float)th.s1, rho = (float)th.rho;
+  if (th.kind == FSA_COV_EXPONENTIAL) return s1 * expf(-d / rho);
+  const float x = 1.7320508f * d / rho;
+  return s1 * (1.0f + x) * expf(-x);
+}
+__device__ __forceinline__ float dcov_drho_f(float d, const Theta& th) {
+  const float s1 = (float)th.s1, rho = (float)th.rho;
+  if (th.kind == FSA_COV_EXPONENTIAL) return s1 * (d / (rho * rho)) * expf(-d / rho);
+  const float x = 1.7320508f * d / rho;
+  return s1 * (x * x / rho) * expf(-x);
+}
+
 struct WgemmSeg {
   int src;             // XSRC_*
   const double* X;     // XSRC_MEM: point-major n x ldx
   int64_t ldx;
   const double* Wt;    // K x mp row-major (Wt[k][j] = W[j][k]), zero for k > j
+  const float* Xf;     // float32 products only: X in float32 (null: X rounded when staged)
 };
 
 struct WgemmArgs {
@@ -154,10 +170,13 @@ struct WgemmArgs {
 };
 
 // SRC0: the source of segment 0 (XSRC_*); segment 1, if TWO, is read from memory.
-template <int SRC0, bool TWO>
+// T: the arithmetic of the product (double: float64 MFMA with the covariance
+// generated in float64; float: float32 MFMA, the covariance generated in
+// float32 and W rounded to float32 when staged).
+template <int SRC0, bool TWO, typename T>
 __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
-  __shared__ double Xs[2][WG_KC][XS_LD];
-  __shared__ double Ws[2][WG_KC][WS_LD];
+  __shared__ T Xs[2][WG_KC][XS_LD];
+  __shared__ T Ws[2][WG_KC][WS_LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int ph = w >> 2, cq = w < 4 ? (w & 3) : 3 - (w & 3);
   const int64_t p0 = (int64_t)blockIdx.x * WG_PTS;
@@ -185,7 +204,7 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
   }
   // W: thread t takes k row t / 32 and columns 8 (t % 32) .. + 8
   const int wk = tid >> 5, wc = (tid & 31) * 8;
-  double xr[2][2], wr[8];
+  T xr[2][2], wr[8];
   auto load = [&](int c) {
     const int s = TWO ? c / nch_seg : 0, k0 = (c % nch_seg) * WG_KC;
     const WgemmSeg& sg = a.seg[s];
@@ -193,21 +212,34 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (mem) {
-        xr[h][0] = xr[h][1] = 0.0;
+        xr[h][0] = xr[h][1] = T(0);
         if (xrow_ok[h]) {
-          const d2 v = *reinterpret_cast<const d2*>(sg.X + (p0 + xp + 64 * h) * sg.ldx + k0 + xk);
-          xr[h][0] = v[0];
-          xr[h][1] = v[1];
+          const int64_t o = (p0 + xp + 64 * h) * sg.ldx + k0 + xk;
+          if (std::is_same<T, float>::value && sg.Xf) {
+            const float2 v = *reinterpret_cast<const float2*>(sg.Xf + o);
+            xr[h][0] = (T)v.x;
+            xr[h][1] = (T)v.y;
+          } else {
+            const d2 v = *reinterpret_cast<const d2*>(sg.X + o);
+            xr[h][0] = (T)v[0];
+            xr[h][1] = (T)v[1];
+          }
         }
       } else {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           const int k = k0 + xk + u;
-          double v = 0.0;
+          T v = T(0);
           if (xrow_ok[h] && k < a.m) {
-            const double dx = px[h] - a.ind[2 * k], dy = py[h] - a.ind[2 * k + 1];
-            const double d = sqrt(dx * dx + dy * dy);
-            v = SRC0 == XSRC_COV ? cov_d(d, a.th) : dcov_drho(d, a.th);
+            if constexpr (std::is_same<T, double>::value) {
+              const double dx = px[h] - a.ind[2 * k], dy = py[h] - a.ind[2 * k + 1];
+              const double d = sqrt(dx * dx + dy * dy);
+              v = SRC0 == XSRC_COV ? cov_d(d, a.th) : dcov_drho(d, a.th);
+            } else {
+              const float dx = (float)(px[h] - a.ind[2 * k]), dy = (float)(py[h] - a.ind[2 * k + 1]);
+              const float d = sqrtf(dx * dx + dy * dy);
+              v = SRC0 == XSRC_COV ? cov_f(d, a.th) : dcov_drho_f(d, a.th);
+            }
           }
           xr[h][u] = v;
         }
@@ -218,8 +250,8 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const d2 v = src[u];
-        wr[2 * u] = v[0];
-        wr[2 * u + 1] = v[1];
+        wr[2 * u] = (T)v[0];
+        wr[2 * u + 1] = (T)v[1];
       }
     }
   };
@@ -235,12 +267,12 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
     }
   };
 
-  typedef Mfma<double>::acc acc_t;
+  typedef typename Mfma<T>::acc acc_t;
   acc_t acc[WG_RT][4];
 #pragma unroll
   for (int r = 0; r < WG_RT; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = acc_t{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < 4; ++c) acc[r][c] = acc_t{T(0), T(0), T(0), T(0)};
 
   if (nch > 0) {
     load(0);
@@ -256,7 +288,7 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
 #pragma unroll
       for (int ks = 0; ks < WG_KC / 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
-        double av[WG_RT], bv[4];
+        T av[WG_RT], bv[4];
 #pragma unroll
         for (int r = 0; r < WG_RT; ++r) av[r] = Xs[buf][kk][ph * (WG_PTS / 2) + r * 16 + (lane & 15)];
 #pragma unroll
@@ -264,29 +296,30 @@ __global__ __launch_bounds__(512) void k_wgemm(WgemmArgs a) {
 #pragma unroll
         for (int r = 0; r < WG_RT; ++r)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[r][q] = Mfma<double>::op(av[r], bv[q], acc[r][q]);
+          for (int q = 0; q < 4; ++q) acc[r][q] = Mfma<T>::op(av[r], bv[q], acc[r][q]);
       }
     }
     if (c + 1 < nch) store(buf ^ 1);
     __syncthreads();
   }
   if (!wave_on) return;
-  // lane l, register e holds row (l / 16) + 4 e, column l % 16 of each tile
+  // lane l, register e holds row orow(l / 16, e), column l % 16 of each tile
 #pragma unroll
   for (int r = 0; r < WG_RT; ++r)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t p = p0 + ph * (WG_PTS / 2) + r * 16 + Mfma<double>::orow(lane >> 4, e);
+      const int64_t p = p0 + ph * (WG_PTS / 2) + r * 16 + Mfma<T>::orow(lane >> 4, e);
       if (p >= a.n) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t o = p * a.mp + jw + q * 16 + (lane & 15);
-        a.Y[o] = acc[r][q][e];
+        if (a.Y) a.Y[o] = (double)acc[r][q][e];
         if (a.Yf) a.Yf[o] = (float)acc[r][q][e];
       }
     }
 }
 
+template <typename T>
 static fsa_status launch_wgemm(const WgemmArgs& a, hipStream_t st) {
   if (a.n <= 0) return FSA_OK;
   if (a.mp % 64 || a.mp <= 0 || a.mp > 512) {
@@ -305,13 +338,13 @@ static fsa_status launch_wgemm(const WgemmArgs& a, hipStream_t st) {
       set_error("wgemm: two segments are [dSigma_nm | X]");
       return FSA_ERR_INVALID_ARG;
     }
-    hipLaunchKernelGGL((k_wgemm<XSRC_DCOV, true>), grid, dim3(512), 0, st, a);
+    hipLaunchKernelGGL((k_wgemm<XSRC_DCOV, true, T>), grid, dim3(512), 0, st, a);
   } else if (src0 == XSRC_COV) {
-    hipLaunchKernelGGL((k_wgemm<XSRC_COV, false>), grid, dim3(512), 0, st, a);
+    hipLaunchKernelGGL((k_wgemm<XSRC_COV, false, T>), grid, dim3(512), 0, st, a);
   } else if (src0 == XSRC_DCOV) {
-    hipLaunchKernelGGL((k_wgemm<XSRC_DCOV, false>), grid, dim3(512), 0, st, a);
+    hipLaunchKernelGGL((k_wgemm<XSRC_DCOV, false, T>), grid, dim3(512), 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_wgemm<XSRC_MEM, false>), grid, dim3(512), 0, st, a);
+    hipLaunchKernelGGL((k_wgemm<XSRC_MEM, false, T>), grid, dim3(512), 0, st, a);
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -325,31 +358,34 @@ fsa_status whiten(const double* xs, int64_t n, const double* ind, int m, int mp,
   a.mp = mp;
   a.m = m;
   a.nseg = 1;
-  a.seg[0] = WgemmSeg{XSRC_COV, nullptr, 0, LminvT};
+  a.seg[0] = WgemmSeg{XSRC_COV, nullptr, 0, LminvT, nullptr};
   a.xs = xs;
   a.ind = ind;
   a.th = th;
   a.Y = A_out;
   a.Yf = Af_out;
-  return launch_wgemm(a, st);
+  return launch_wgemm<double>(a, st);
 }
 
 // F = dSigma_nm L_m^{-T} - A Phi(E)^T: LminvT as above, PhiT_neg = -Phi(E)^T (mp x mp row-major).
+// Af non-null: the product in float32 arithmetic from the float32 copy of A
+// (F_out gets the float32 result widened, Ff_out, if non-null, the float32 one).
 fsa_status derivative_factor(const double* xs, int64_t n, const double* ind, int m, int mp, const Theta& th,
                              const double* LminvT, const double* A, const double* PhiT_neg, double* F_out,
-                             hipStream_t st) {
+                             hipStream_t st, const float* Af, float* Ff_out) {
   WgemmArgs a{};
   a.n = n;
   a.mp = mp;
   a.m = m;
   a.nseg = 2;
-  a.seg[0] = WgemmSeg{XSRC_DCOV, nullptr, 0, LminvT};
-  a.seg[1] = WgemmSeg{XSRC_MEM, A, mp, PhiT_neg};
+  a.seg[0] = WgemmSeg{XSRC_DCOV, nullptr, 0, LminvT, nullptr};
+  a.seg[1] = WgemmSeg{XSRC_MEM, A, mp, PhiT_neg, Af};
   a.xs = xs;
   a.ind = ind;
   a.th = th;
   a.Y = F_out;
-  return launch_wgemm(a, st);
+  a.Yf = Ff_out;
+  return Af ? launch_wgemm<float>(a, st) : launch_wgemm<double>(a, st);
 }
 
 // Y = X W^T for point-major X (n x mp) and lower-triangular W given as WT = W^T.
@@ -359,9 +395,9 @@ fsa_status rows_times_lower_t(const double* X, int64_t n, int mp, const double* 
   a.mp = mp;
   a.m = mp;
   a.nseg = 1;
-  a.seg[0] = WgemmSeg{XSRC_MEM, X, mp, WT};
+  a.seg[0] = WgemmSeg{XSRC_MEM, X, mp, WT, nullptr};
   a.Y = Y;
-  return launch_wgemm(a, st);
+  return launch_wgemm<double>(a, st);
 }
 
 }  // namespace fsa

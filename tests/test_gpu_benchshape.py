@@ -284,9 +284,11 @@ def test_mixed_falls_back_to_fp64_where_float32_cannot_resolve(F):
     """A strongly low-rank problem (n = 6,313, m = 500, Matern-3/2 with rho =
     0.153: |A A^T| exceeds the nugget by ~10^4): the float32 Woodbury
     application loses most of its digits, the float32 iteration stalls, and
-    MIXED_FP32 repeats the solve in float64 (its result is then the float64
-    one, bit for bit, and the stats say so).  A well-conditioned request of
-    the same stream stays in float32."""
+    MIXED_FP32 repeats the solve in float64 (the likelihood is then the
+    float64 one bit for bit, and the stats say so; the gradient's derivative
+    factor stays the float32 one of the mixed mode, so the gradient agrees to
+    the mixed-precision bar).  A well-conditioned request of the same stream
+    stays in float32."""
     trace = configs.serving_trace()
     hard = next(r for r in trace if r.index == 5)
     locs, y, ind, _ = hard.materialize()
@@ -298,7 +300,9 @@ def test_mixed_falls_back_to_fp64_where_float32_cannot_resolve(F):
     say("hard: fallback", st["fp64_fallback"], "abandoned probe-iterations", st["fallback_probe_iters"],
         "iters", st["iters_max"], st64["iters_max"])
     assert st["fp64_fallback"] == 1 and st["fallback_probe_iters"] > 0
-    assert nll == nll64 and np.array_equal(grad, grad64)
+    assert nll == nll64
+    scale = np.maximum(np.abs(grad64), 0.01 * np.abs(grad64).max())
+    assert np.all(np.abs(grad - grad64) <= 1e-4 * scale)
     easy = next(r for r in trace if r.index == 0)
     locs, y, ind, _ = easy.materialize()
     with F.FSA(locs, y, easy.theta, ind, easy.gamma, num_probes=20, seed=4005, tol=1e-6, max_iter=2000,

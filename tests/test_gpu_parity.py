@@ -430,7 +430,9 @@ def test_gradient_control_variate_mixed_and_bf16a(F):
     """The control variate on the float32 solves: MIXED_FP32 against the
     float64 oracle, MIXED_BF16A against the oracle of its rounded model
     (whose sigma1^2 derivative, of Sigma~ and of P, scales with sigma1^2), at
-    the mixed-precision bar."""
+    the mixed-precision bar.  The exact Tr(P^{-1} dP/dtheta) is float64 work
+    on the derivative factor F, which MIXED_FP32 forms as a float32 product
+    (float32 accuracy, 1e-6) and MIXED_BF16A in float64 (1e-9)."""
     locs, y, theta, ind, gamma = case(**CASES["m32_n1500_m100"])
     for prec, mdl in ((F.MIXED_FP32, O.FSA(locs, ind, theta, gamma)),
                       (F.MIXED_BF16A, DF.RoundedFSA(locs, ind, theta, gamma,
@@ -441,7 +443,7 @@ def test_gradient_control_variate_mixed_and_bf16a(F):
             nll, grad, st = f.nll_grad()
         gscale = np.maximum(np.abs(ref["grad"]), 0.5 * np.abs(ref["trace_terms"]).mean(1))
         say(prec, "grad err / scale", np.abs(grad - ref["grad"]) / gscale, "trace_P", st["trace_P"], ref["trace_P"])
-        np.testing.assert_allclose(st["trace_P"], ref["trace_P"], rtol=1e-9)
+        np.testing.assert_allclose(st["trace_P"], ref["trace_P"], rtol=1e-6 if prec == F.MIXED_FP32 else 1e-9)
         assert np.all(np.abs(grad - ref["grad"]) <= 1e-4 * gscale), (prec, grad, ref["grad"])
 
 
