@@ -480,11 +480,15 @@ def main():
     if "fp64_tol6" in results and "mixed" in results:
         # the same PCG tolerance (1e-6) in both precisions: probe-iterations/s and time per likelihood step
         out["mixed_over_fp64_same_tol"] = results["mixed"]["value"] / results["fp64_tol6"]["value"]
+        out["mixed_over_fp64_same_tol_pcg_only"] = (results["mixed"]["pcg_only_probe_iters_per_s"]
+                                                    / results["fp64_tol6"]["pcg_only_probe_iters_per_s"])
         out["mixed_step_speedup_same_tol"] = results["fp64_tol6"]["ms_per_step"] / results["mixed"]["ms_per_step"]
         out["mixed_vs_fp64_same_tol_rel_nll"] = (abs(results["mixed"]["nll"] - results["fp64_tol6"]["nll"])
                                                  / abs(results["fp64_tol6"]["nll"]))
     if "fp64" in results and "mixed" in results:
         out["mixed_over_fp64"] = results["mixed"]["value"] / results["fp64"]["value"]
+        out["mixed_over_fp64_pcg_only"] = (results["mixed"]["pcg_only_probe_iters_per_s"]
+                                           / results["fp64"]["pcg_only_probe_iters_per_s"])
         out["mixed_step_speedup"] = results["fp64"]["ms_per_step"] / results["mixed"]["ms_per_step"]
         out["mixed_vs_fp64_rel_nll"] = abs(results["mixed"]["nll"] - results["fp64"]["nll"]) / abs(results["fp64"]["nll"])
         out["mixed_vs_fp64_rel_grad"] = [abs(a - c) / max(abs(c), 1e-300)

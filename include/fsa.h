@@ -165,7 +165,7 @@ typedef struct {
   double quad;                  /* y^T Sigma~_dagger^{-1} y */
   double ms_build;              /* host wall time of a rebuild for a new theta inside the call (0 if none) */
   double ms_pcg;                /* the block PCG solve with its SLQ quadrature and quadratic term */
-  double ms_backward;           /* the gradient after the solve (the derivative build overlaps the solve) */
+  double ms_backward;           /* the gradient after the solve, with the derivative build */
   double ms_total;
   int64_t nnz;                  /* nonzeros of the tapered residual */
   /* with options.profile: summed device time and launch count of the PCG

@@ -736,12 +736,10 @@ struct fsa_ctx {
   Buf<double> hist;
   Buf<double> slq_scratch, results;
   const double* lanczos_weight = nullptr;  // quadrature weights of the last solve (in colbuf)
-  // The derivative factor and values (backward) depend on theta only, so
-  // fsa_nll_grad builds them on a second, non-blocking stream (default
-  // priority) while the solve runs: deriv_state 0 = not built for this
-  // theta, 1 = enqueued on st2 (ev_deriv marks its end), 2 = ready on st.
+  // A second, non-blocking stream (default priority) for build and
+  // quadrature work beside the main stream; ev_ready orders it behind st
   hipStream_t st2 = nullptr;
-  hipEvent_t ev_ready = nullptr, ev_deriv = nullptr;
+  hipEvent_t ev_ready = nullptr;
   // the quadrature of a solve also runs on st2, beside the gradient: ev_solve
   // marks the solve's end on st, ev_slq the quadrature's end on st2
   hipEvent_t ev_solve = nullptr, ev_slq = nullptr;
@@ -755,8 +753,10 @@ struct fsa_ctx {
   Buf<char> dstage;
   char* hstage = nullptr;
   size_t hstage_bytes = 0;
-  int deriv_state = 0;
-  bool deriv_marked = false;  // derivative build requested, not yet enqueued
+  // the derivative factor and values (backward) depend on theta only: built
+  // once per theta, after the solve, on st (beside the solve they only
+  // shared the CUs with its kernels, each of which fills the chip)
+  bool deriv_ready = false;
   bool timer_pending = false;  // the last solve's kernel events are not yet summed
   // gradient
   Buf<double> F, dvals, Xb, tmp, dSm, Ework;
@@ -792,7 +792,6 @@ static fsa_status check_theta(const fsa_theta* th) {
 }
 
 // Sigma_m, L_m, whitened factor, residual values, D_s, FITC capacitance.
-static fsa_status settle_derivative(fsa_ctx* c);
 static fsa_status side_stream(fsa_ctx* c);
 
 // Sigma_m and its Cholesky factor L_m on the side stream, behind everything
@@ -816,8 +815,7 @@ static fsa_status launch_sigma_m(fsa_ctx* c) {
 }
 
 static fsa_status build_values(fsa_ctx* c) {
-  FSA_TRY(settle_derivative(c));  // nothing may still read A, L_m or F
-  c->deriv_state = 0;
+  c->deriv_ready = false;
   hipStream_t st = c->st;
   const int mp = c->mp;
   if (!c->lm_pending) FSA_TRY(launch_sigma_m(c));
@@ -1192,7 +1190,6 @@ void fsa_destroy(fsa_ctx* c) {
   if (c->st2) {
     (void)hipStreamSynchronize(c->st2);
     (void)hipEventDestroy(c->ev_ready);
-    (void)hipEventDestroy(c->ev_deriv);
     (void)hipEventDestroy(c->ev_solve);
     (void)hipEventDestroy(c->ev_slq);
     (void)hipEventDestroy(c->ev_fact);
@@ -1208,14 +1205,11 @@ int64_t fsa_nnz(const fsa_ctx* c) { return c ? c->csr.nnz : -1; }
 }  // extern "C"
 
 // ---------------------------------------------------------------- PCG driver
-static fsa_status enqueue_derivative(fsa_ctx* c);
-
 // The side stream (non-blocking, default priority) and its events.
 static fsa_status side_stream(fsa_ctx* c) {
   if (!c->st2) {
     FSA_HIP(hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking));
     FSA_HIP(hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming));
-    FSA_HIP(hipEventCreateWithFlags(&c->ev_deriv, hipEventDisableTiming));
     FSA_HIP(hipEventCreateWithFlags(&c->ev_solve, hipEventDisableTiming));
     FSA_HIP(hipEventCreateWithFlags(&c->ev_slq, hipEventDisableTiming));
     FSA_HIP(hipEventCreateWithFlags(&c->ev_fact, hipEventDisableTiming));
@@ -1403,7 +1397,6 @@ static fsa_status run_pcg(fsa_ctx* c, double* ms_pcg) {
   for (it = 0; it < max_iter; ++it) {
     if (use_graph && it > 0) FSA_TRY(ig.run(b, op, tol, fixed, c->scr));
     else FSA_TRY(pcg_iter<T>(b, op, tol, fixed, c->scr, st));
-    if (it == 0) FSA_TRY(enqueue_derivative(c));  // a derivative build marked before the solve
     bool replaced = false;
     if constexpr (sizeof(T) == 4) {
       if (c->opt.rr_period > 0 && (it + 1) % c->opt.rr_period == 0 && it + 1 < max_iter) {
@@ -1647,48 +1640,11 @@ static fsa_status apply_drho(fsa_ctx* c, const double* X, double* Y, int ncols, 
   return FSA_OK;
 }
 
-// Wait (on the host) for derivative work still enqueued on the side stream.
-static fsa_status settle_derivative(fsa_ctx* c) {
-  if (c->deriv_state == 1) {
-    FSA_HIP(hipEventSynchronize(c->ev_deriv));
-    c->deriv_state = 2;
-  }
-  return FSA_OK;
-}
-
-// A requested derivative build (mark_derivative) is enqueued on the side
-// stream by the solve once its first iteration is queued, so that the device
-// works while the host enqueues the derivative's ~20 launches; it runs
-// behind everything on st at that point (ev_ready), which also orders any
-// block the pool hands it after earlier users on st.
-static void mark_derivative(fsa_ctx* c) { c->deriv_marked = true; }
-
-static fsa_status enqueue_derivative(fsa_ctx* c) {
-  if (!c->deriv_marked) return FSA_OK;
-  c->deriv_marked = false;
-  FSA_TRY(side_stream(c));
-  FSA_HIP(hipEventRecord(c->ev_ready, c->st));
-  FSA_HIP(hipStreamWaitEvent(c->st2, c->ev_ready, 0));
-  {
-    // blocks the derivative build takes or gives back are used on st2: the
-    // pool's waits and release events belong there (st2 is behind st's work
-    // at ev_ready, so st's earlier uses are covered)
-    PoolStream ps(c->st2);
-    FSA_TRY(build_derivative(c, c->st2));
-  }
-  FSA_HIP(hipEventRecord(c->ev_deriv, c->st2));
-  c->deriv_state = 1;
-  return FSA_OK;
-}
-
 // Make the derivative factor and values available to work on st.
 static fsa_status ensure_derivative(fsa_ctx* c) {
-  if (c->deriv_state == 1) {
-    FSA_HIP(hipStreamWaitEvent(c->st, c->ev_deriv, 0));
-    c->deriv_state = 2;
-  } else if (c->deriv_state == 0) {
+  if (!c->deriv_ready) {
     FSA_TRY(build_derivative(c, c->st));
-    c->deriv_state = 2;
+    c->deriv_ready = true;
   }
   return FSA_OK;
 }
@@ -2044,7 +2000,6 @@ static fsa_status nll_grad_core(fsa_ctx* c, const fsa_theta* theta, double* nll,
   }
   double t_build = now_ms();
   const bool want_grad = grad || grad_dev;
-  if (want_grad && c->deriv_state == 0) mark_derivative(c);
   double ms_pcg = 0;
   fsa_status s;
   if (c->opt.precision != FSA_FP64) {
@@ -2062,7 +2017,6 @@ static fsa_status nll_grad_core(fsa_ctx* c, const fsa_theta* theta, double* nll,
   } else {
     s = run_pcg<double>(c, &ms_pcg);
   }
-  if (c->deriv_marked) FSA_TRY(enqueue_derivative(c));  // the solve ended before its first iteration
   if (s != FSA_OK && s != FSA_ERR_NOT_CONVERGED) {
     FSA_TRY(join_slq(c));
     collect_timer(c);
