@@ -121,8 +121,9 @@ typedef enum { FSA_F32P_SPLIT = 0, FSA_F32P_MFMA = 1 } fsa_fp32_products;
  *                       c_opt read with a centred denominator);
  *   FSA_CV_OPT_PRINTED  c = sum_i (a_i - mean a) b_i / sum_i b_i^2, as printed.
  * The gradient's costs two m x m-triangular solves over n x m blocks per
- * theta (beside the solve, on the side stream) and one pass over the probe
- * block per gradient; the diagonal's two sparse products per prediction. */
+ * theta (with the derivative build, after the solve) and one pass over the
+ * probe block per gradient; the diagonal's two sparse products per
+ * prediction. */
 typedef enum { FSA_CV_NONE = 0, FSA_CV_ONE = 1, FSA_CV_OPT = 2, FSA_CV_OPT_PRINTED = 3 } fsa_control_variate;
 
 typedef struct {

@@ -50,8 +50,8 @@ def run_all(F, prec, locs, y, theta, ind, gamma, pred):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_caller_allocator_receives_every_block(F, prec):
-    """Build, likelihood + gradient, revaluation at a new theta (derivative
-    built on the side stream), prediction and destroy with torch's caching
+    """Build, likelihood + gradient, revaluation at a new theta (the
+    derivative rebuilt), prediction and destroy with torch's caching
     allocator registered: every block handed out comes back, torch's
     allocated bytes return to where they were, and every result is
     bitwise that of the library's own pool."""

@@ -3,7 +3,7 @@
 With options.graph every iteration after the first is one launch of a graph
 captured from the second.  The replays run between the solver's own eager
 work (convergence checkpoints that drain the stream, float64 residual
-replacements in mixed precision, the derivative build on the side stream),
+replacements in mixed precision, the derivative build after the solve),
 and every result must be bitwise that of the eager launches: likelihood,
 gradient, the Lanczos record of every column, predictive variances."""
 import sys
