@@ -1143,7 +1143,7 @@ struct SpmmTile {
   }
 };
 
-template <int EM>
+template <int EM, bool NARROW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_spmm_tiled(
     const int64_t* __restrict__ rcs, int64_t ncell, const int64_t* __restrict__ ccs, GridDesc gd,
     const int64_t* __restrict__ toff, const float* __restrict__ tiles, const unsigned* __restrict__ tmask,
@@ -1209,15 +1209,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       for (int k = 0; k < XU; ++k)
         *reinterpret_cast<f4*>(&xs[((tid >> 4) + 16 * k) * XLD + sc4]) = f4{xr[k].v[0], xr[k].v[1], xr[k].v[2], xr[k].v[3]};
     };
+    // this wave's column tiles that hold a column (uniform): in a block of at
+    // most 32 columns (NARROW) the second, or both, have no work
+    const bool on0 = !NARROW || c0 + ct0 * 16 < ncols, on1 = !NARROW || c0 + ct0 * 16 + 16 < ncols;
     auto mma = [&](const float* xs, const f4* a, unsigned mk, acc_t& acc0, acc_t& acc1) {
+      if (!on0) return;
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         if (!((mk >> ks) & 1u)) continue;  // uniform over the wave
         const float* xb = &xs[(ks * 16 + 4 * q) * XLD + ct0 * 16 + r16];
+        if (on1) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc0 = Mfma<float>::op(a[ks][j], xb[j * XLD], acc0);
-          acc1 = Mfma<float>::op(a[ks][j], xb[j * XLD + 16], acc1);
+          for (int j = 0; j < 4; ++j) {
+            acc0 = Mfma<float>::op(a[ks][j], xb[j * XLD], acc0);
+            acc1 = Mfma<float>::op(a[ks][j], xb[j * XLD + 16], acc1);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc0 = Mfma<float>::op(a[ks][j], xb[j * XLD], acc0);
         }
       }
     };
@@ -1964,6 +1973,8 @@ __device__ __forceinline__ void bf16_split_pair(float a, float b, unsigned& h, u
 
 // Residual pass with split operands: same contract, prologue modes and
 // partial layout as k_reduce_gemm_f32, grid (ncb, nchunks), 512 threads.
+// Only the first NB 16-column tiles of a column block are multiplied (a
+// single block of at most 16 NB columns; the others stay zero).
 // Wave w owns kdim rows 64 w .. 64 w + 63 as four 16-row tiles interleaved by
 // four (tile a, row i: kdim row 64 w + 4 i + a), so a lane reads its four
 // rows of one point with one 16-byte load from the point-major float32 A and
@@ -1971,7 +1982,7 @@ __device__ __forceinline__ void bf16_split_pair(float a, float b, unsigned& h, u
 // prologue writes the three parts of X to a double-buffered LDS block as
 // [part][column][point].  A loads run one step ahead of their use, the
 // prologue inputs one step ahead of the prologue that writes them to LDS.
-template <bool UPD, int SC>
+template <bool UPD, int SC, int NB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_reduce_split(
     int64_t npts, int pts_per_chunk, int kdim, int ncols, const float* __restrict__ A, F32Pro pro,
     float* __restrict__ part, double* __restrict__ dot_part, int ld_dot) {
@@ -2072,7 +2083,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
   auto mma = [&](int buf) {
     if (!mactive) return;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < NB; ++b) {
       u4v xo[3];
 #pragma unroll
       for (int P = 0; P < 3; ++P) xo[P] = *reinterpret_cast<const u4v*>(&Xs[buf][P][(16 * b + r16) * XST + 8 * q]);
@@ -2146,11 +2157,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 // 16-row tiles and walks k in steps of 64: a lane loads 64 contiguous bytes
 // of its row (k = 64 kb + 16 q' + 8 t + j for MFMA t, j) two steps ahead and
 // splits them when the step starts; the epilogue's residual and D^{-1} rows
-// load two steps before the tile ends.
+// load two steps before the tile ends.  Only the first NB 16-column tiles
+// of the block are multiplied (the launch takes NB = ceil(ncols / 16), 3
+// rounded up to 4); the others stay zero.
 constexpr int SPLIT_ROWS_NC = 52;
 inline size_t split_rows_lds(int kdim) { return (size_t)(3 * SPLIT_ROWS_NC + 1) * (kdim + 8) * 2; }
 
-template <int EM, int NW>
+template <int EM, int NW, int NB>
 __global__ __launch_bounds__(64 * NW) void k_rows_split(int64_t nrows, int kdim, const float* __restrict__ A,
                                                      int64_t lda, const float* __restrict__ G, int ldg, int ncols,
                                                      F32RowsEpi epi, double* __restrict__ dot_part, int ld_dot) {
@@ -2273,23 +2286,23 @@ __global__ __launch_bounds__(64 * NW) void k_rows_split(int64_t nrows, int kdim,
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      u4v g[4][3];
+      u4v g[NB][3];
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int P = 0; P < 3; ++P) g[b][P] = *reinterpret_cast<const u4v*>(&gsh[brow[b][P] + ckb * 64 + 8 * t]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][2], g[b][0], acc[b]);
+      for (int b = 0; b < NB; ++b) acc[b] = mfma_bf16(sa[t][2], g[b][0], acc[b]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][1], g[b][1], acc[b]);
+      for (int b = 0; b < NB; ++b) acc[b] = mfma_bf16(sa[t][1], g[b][1], acc[b]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][0], g[b][2], acc[b]);
+      for (int b = 0; b < NB; ++b) acc[b] = mfma_bf16(sa[t][0], g[b][2], acc[b]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][1], g[b][0], acc[b]);
+      for (int b = 0; b < NB; ++b) acc[b] = mfma_bf16(sa[t][1], g[b][0], acc[b]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][0], g[b][1], acc[b]);
+      for (int b = 0; b < NB; ++b) acc[b] = mfma_bf16(sa[t][0], g[b][1], acc[b]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = mfma_bf16(sa[t][0], g[b][0], acc[b]);
+      for (int b = 0; b < NB; ++b) acc[b] = mfma_bf16(sa[t][0], g[b][0], acc[b]);
     }
     if (++ckb == nkb) {
       epilogue();

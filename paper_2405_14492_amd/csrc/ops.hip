@@ -322,8 +322,14 @@ static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int n
       hipLaunchKernelGGL((k_reduce_gemm_f32<bf16_t, Pro::kUpd, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim,
                          ncols, Abf, fp, part, dot_part, ld_dot);
     } else if (split && r.zb == 1) {
-      hipLaunchKernelGGL((k_reduce_split<Pro::kUpd, Pro::kSc>), dim3(r.ncb, r.nchunks), dim3(512), 0, st, n, r.ppc,
-                         kdim, ncols, (const float*)A, fp, part, dot_part, ld_dot);
+      auto go = [&](auto nb) {
+        hipLaunchKernelGGL((k_reduce_split<Pro::kUpd, Pro::kSc, decltype(nb)::value>), dim3(r.ncb, r.nchunks),
+                           dim3(512), 0, st, n, r.ppc, kdim, ncols, (const float*)A, fp, part, dot_part, ld_dot);
+      };
+      // a single column block multiplies only the column tiles that hold a column
+      if (r.ncb == 1 && ncols <= 16) go(std::integral_constant<int, 1>{});
+      else if (r.ncb == 1 && ncols <= 32) go(std::integral_constant<int, 2>{});
+      else go(std::integral_constant<int, 4>{});
     } else {
       hipLaunchKernelGGL((k_reduce_gemm_f32<float, Pro::kUpd, Pro::kSc>), grid, dim3(512), 0, st, n, r.ppc, kdim,
                          ncols, (const float*)A, fp, part, dot_part, ld_dot);
@@ -578,8 +584,12 @@ static fsa_status launch_spmm_tiled(const Grid& g, const int64_t* toff, const fl
   }
   dim3 grid(8 * ceil_div(g.ncell, 8), ceil_div(ncols, 64));
   const int sw = 32;  // cell columns per strip of the workgroup walk
-  hipLaunchKernelGGL(k_spmm_tiled<SP_PCG>, grid, dim3(256), 0, st, g.cstart.p, g.ncell, g.cstart.p, g.desc, toff,
-                     tiles, tmask, X, ldx, ncols, epi, dot_part, ld_dot, sw);
+  if (ncols <= 32)  // one block whose last two column tiles are empty
+    hipLaunchKernelGGL((k_spmm_tiled<SP_PCG, true>), grid, dim3(256), 0, st, g.cstart.p, g.ncell, g.cstart.p, g.desc,
+                       toff, tiles, tmask, X, ldx, ncols, epi, dot_part, ld_dot, sw);
+  else
+    hipLaunchKernelGGL((k_spmm_tiled<SP_PCG, false>), grid, dim3(256), 0, st, g.cstart.p, g.ncell, g.cstart.p, g.desc,
+                       toff, tiles, tmask, X, ldx, ncols, epi, dot_part, ld_dot, sw);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -1043,14 +1053,19 @@ static fsa_status pcg_precond_and_dots(PcgBlock<T>& b, const OpDesc<T>& op, int 
     } else if (op.split && b.ncols <= SPLIT_ROWS_NC && op.kdim <= 512) {
       // float32 operands split in three bfloat16 parts, one 8-wave workgroup per CU
       const size_t smem16 = split_rows_lds(op.kdim);
-      if (init)
-        hipLaunchKernelGGL((k_rows_split<ROWS_PCG_INIT, 8>), grid2, dim3(512), smem16, st, b.n, op.kdim,
-                           (const float*)op.A, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p,
-                           ncb * 64);
-      else
-        hipLaunchKernelGGL((k_rows_split<ROWS_PCG, 8>), grid2, dim3(512), smem16, st, b.n, op.kdim,
-                           (const float*)op.A, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe, s.dot.p,
-                           ncb * 64);
+      auto go = [&](auto em, auto nb) {
+        hipLaunchKernelGGL((k_rows_split<decltype(em)::value, 8, decltype(nb)::value>), grid2, dim3(512), smem16, st,
+                           b.n, op.kdim, (const float*)op.A, (int64_t)op.kdim, (const float*)b.g, b.ldw, b.ncols, fe,
+                           s.dot.p, ncb * 64);
+      };
+      // the column tiles that hold a column
+      auto go_nb = [&](auto em) {
+        if (b.ncols <= 16) go(em, std::integral_constant<int, 1>{});
+        else if (b.ncols <= 32) go(em, std::integral_constant<int, 2>{});
+        else go(em, std::integral_constant<int, 4>{});
+      };
+      if (init) go_nb(std::integral_constant<int, ROWS_PCG_INIT>{});
+      else go_nb(std::integral_constant<int, ROWS_PCG>{});
     } else if (op.Abf) {
       if (init)
         hipLaunchKernelGGL((k_rows_gemm_f32<bf16_t, true, ROWS_PCG_INIT>), grid2, dim3(1024), smem, st, b.n, op.kdim,
