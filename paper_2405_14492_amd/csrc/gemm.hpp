@@ -814,31 +814,39 @@ __global__ __launch_bounds__(1024) void k_reduce_gemm_f64(int64_t npts, int pts_
   }
 }
 
-// Sum the row-major per-chunk partials of k_reduce_gemm_f32 (fixed order,
-// eight interleaved partial sums) into W (float64, row-major kdim x ldw, all
-// 64 ncb columns); optionally add the identity.
+// Sum the row-major per-chunk partials of the reduce GEMMs into W (float64,
+// row-major kdim x ldw, all 64 ncb columns); optionally add the identity.
+// One workgroup per 64-element row (column block cb, kdim row k): wave w
+// sums the w-th quarter of the chunks (eight interleaved running sums), and
+// the four quarters are added in LDS, all in a fixed order.  With
+// lower_only, rows k < 64 cb (above the diagonal block) are left alone.
 template <typename TP>
-__global__ void k_reduce_parts_rm(const TP* __restrict__ part, int nchunks, int ncb, int kdim,
-                                  double* __restrict__ W, int ldw, int add_identity, int lower_only) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_reduce_parts_rm(const TP* __restrict__ part, int nchunks, int ncb, int kdim,
+                                                         double* __restrict__ W, int ldw, int add_identity,
+                                                         int lower_only) {
+  __shared__ double red[4][64];
+  const int64_t row = blockIdx.x;
+  const int k = (int)(row % kdim), cb = (int)(row / kdim);
+  if (lower_only && k < 64 * cb) return;  // uniform over the workgroup
+  const int cl = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t per = (int64_t)ncb * kdim * 64;
-  if (e >= per) return;
-  if (lower_only && (int)((e >> 6) % kdim) < 64 * (int)((e >> 6) / kdim)) return;
+  const int64_t e = row * 64 + cl;
+  const int q0 = (int)((int64_t)nchunks * wv / 4), q1 = (int)((int64_t)nchunks * (wv + 1) / 4);
   double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int ch = 0;
-  for (; ch + 8 <= nchunks; ch += 8) {
+  int ch = q0;
+  for (; ch + 8 <= q1; ch += 8) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) s8[u] += (double)part[(int64_t)(ch + u) * per + e];
   }
-  for (int u = 0; ch < nchunks; ++ch, ++u) s8[u] += (double)part[(int64_t)ch * per + e];
-  double sum = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
-  const int cl = (int)(e & 63);
-  const int64_t rest = e >> 6;
-  const int k = (int)(rest % kdim);
-  const int cb = (int)(rest / kdim);
-  const int cc = cb * 64 + cl;
-  if (add_identity && k == cc) sum += 1.0;
-  W[(int64_t)k * ldw + cc] = sum;
+  for (int u = 0; ch < q1; ++ch, ++u) s8[u] += (double)part[(int64_t)ch * per + e];
+  red[wv][cl] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+  __syncthreads();
+  if (wv == 0) {
+    double sum = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+    const int cc = cb * 64 + cl;
+    if (add_identity && k == cc) sum += 1.0;
+    W[(int64_t)k * ldw + cc] = sum;
+  }
 }
 
 // Column sums of per-workgroup partials: out[c] = sum_k part[k*ldp + c],

@@ -344,10 +344,10 @@ static fsa_status launch_reduce(const ReduceShape& r, int64_t n, int kdim, int n
 template <typename T>
 static fsa_status reduce_finish(Scratch& s, const ReduceShape& r, double* W, int ldw, int add_id, hipStream_t st,
                                 int lower_only = 0) {
-  int64_t per = (int64_t)r.ncb * r.nmb * 4096;
-  // row-major partials of the pipelined kernels (all of kdim)
-  hipLaunchKernelGGL(k_reduce_parts_rm<T>, dim3(ceil_div(per, 256)), dim3(256), 0, st, (const T*)s.part.p, r.nchunks,
-                     r.ncb, r.nmb * 64, W, ldw, add_id, lower_only);
+  // row-major partials of the pipelined kernels (all of kdim): a workgroup per 64-column row
+  const int64_t rows = (int64_t)r.ncb * r.nmb * 64;
+  hipLaunchKernelGGL(k_reduce_parts_rm<T>, dim3(rows), dim3(256), 0, st, (const T*)s.part.p, r.nchunks, r.ncb,
+                     r.nmb * 64, W, ldw, add_id, lower_only);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -685,23 +685,26 @@ fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double
 
 // ---------------------------------------------------------------- m-space
 // G (kdim x ldg, type T) = M (kdim x kdim) W (kdim x ldw, columns < ncols),
-// float64 MFMA 16x16x4: one workgroup per 16 x 16 output tile, the four waves
-// split k into quarters and their partial tiles are summed in LDS (fixed
-// order).  Lane (q, r) of a wave reads four consecutive k of row r of M.
+// float64 MFMA 16x16x4: one workgroup per 16 x 16 output tile; its sixteen
+// waves take the 16-wide k blocks round robin (a few steps each, so the
+// loads of a wave are few and in flight together) and their partial tiles
+// are summed in LDS in a fixed order.  Lane (q, r) of a wave reads four
+// consecutive k of row r of M.
+constexpr int MSPACE_WAVES = 16;
 template <typename T>
-__global__ __launch_bounds__(256) void k_mspace(const double* __restrict__ M, const double* __restrict__ W, int ldw,
-                                                int kdim, int ncols, T* __restrict__ G, int ldg) {
-  __shared__ double red[4][4][64];
+__global__ __launch_bounds__(64 * MSPACE_WAVES) void k_mspace(const double* __restrict__ M,
+                                                              const double* __restrict__ W, int ldw, int kdim,
+                                                              int ncols, T* __restrict__ G, int ldg) {
+  __shared__ double red[MSPACE_WAVES][4][64];
   typedef Mfma<double>::acc acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int q = lane >> 4, r16 = lane & 15;
   const int k0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
-  const int kq = kdim / 4;  // kdim is a multiple of 64
   const int cc = c0 + r16;
   const bool cok = cc < ncols;
   const double* mrow = M + (int64_t)(k0 + r16) * kdim;
   acc_t acc = acc_t{0, 0, 0, 0};
-  for (int kb = w * kq; kb < (w + 1) * kq; kb += 16) {
+  for (int kb = 16 * w; kb < kdim; kb += 16 * MSPACE_WAVES) {
     const V4<double> a = load4(mrow + kb + 4 * q);
     double bv[4];
 #pragma unroll
@@ -715,9 +718,15 @@ __global__ __launch_bounds__(256) void k_mspace(const double* __restrict__ M, co
   if (w == 0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const double v = (red[0][r][lane] + red[1][r][lane]) + (red[2][r][lane] + red[3][r][lane]);
+      double p[MSPACE_WAVES / 2];
+#pragma unroll
+      for (int i = 0; i < MSPACE_WAVES / 2; ++i) p[i] = red[2 * i][r][lane] + red[2 * i + 1][r][lane];
+#pragma unroll
+      for (int h = MSPACE_WAVES / 4; h >= 1; h /= 2)
+#pragma unroll
+        for (int i = 0; i < h; ++i) p[i] = p[2 * i] + p[2 * i + 1];
       const int k = k0 + Mfma<double>::orow(q, r);
-      if (cc < ldg) G[(int64_t)k * ldg + cc] = (T)(cok ? v : 0.0);
+      if (cc < ldg) G[(int64_t)k * ldg + cc] = (T)(cok ? p[0] : 0.0);
     }
   }
 }
@@ -730,7 +739,7 @@ fsa_status mspace_apply(const double* M, const double* W, int ldw, int kdim, int
     return FSA_ERR_INVALID_ARG;
   }
   dim3 grid(ceil_div(ldg, 16), kdim / 16);
-  hipLaunchKernelGGL(k_mspace<T>, grid, dim3(256), 0, st, M, W, ldw, kdim, ncols, G, ldg);
+  hipLaunchKernelGGL(k_mspace<T>, grid, dim3(64 * MSPACE_WAVES), 0, st, M, W, ldw, kdim, ncols, G, ldg);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
