@@ -685,12 +685,13 @@ fsa_status coldot(const TX* X, const TY* Y, int64_t n, int ld, int ncols, double
 
 // ---------------------------------------------------------------- m-space
 // G (kdim x ldg, type T) = M (kdim x kdim) W (kdim x ldw, columns < ncols),
-// float64 MFMA 16x16x4: one workgroup per 16 x 16 output tile; its sixteen
+// float64 MFMA 16x16x4: one workgroup per 16 x 16 output tile; its eight
 // waves take the 16-wide k blocks round robin (a few steps each, so the
 // loads of a wave are few and in flight together) and their partial tiles
-// are summed in LDS in a fixed order.  Lane (q, r) of a wave reads four
+// are summed in LDS in a fixed order.  (Sixteen waves were no faster alone
+// and waited longer for a free CU beside other work.)  Lane (q, r) of a wave reads four
 // consecutive k of row r of M.
-constexpr int MSPACE_WAVES = 16;
+constexpr int MSPACE_WAVES = 8;
 template <typename T>
 __global__ __launch_bounds__(64 * MSPACE_WAVES) void k_mspace(const double* __restrict__ M,
                                                               const double* __restrict__ W, int ldw, int kdim,
