@@ -274,7 +274,8 @@ def run_vecchia(F, torch, n, mv, m, t, steps, warmup, seed=0, cpu_sample_n=0):
     return out
 
 
-def run_serving(F, torch, n_requests, rate, slots, budget_gib, warm=8):
+def run_serving(F, torch, n_requests, rate, slots, budget_gib, warm=8, legs=("mixed", "fp64", "capacity"),
+                graph=True):
     """The serving stream: `n_requests` likelihood + gradient (70%) and
     predictive-variance (30%) requests with Poisson arrivals at `rate` per
     second, n log-uniform in [5k, 300k], m in {100, 200, 500}, t = 20, through
@@ -334,9 +335,19 @@ def run_serving(F, torch, n_requests, rate, slots, budget_gib, warm=8):
             f"p99 {out['p99_ms']:.1f} ms, peak active {out['peak_active']}, failed {len(bad)}")
         return out
 
-    mixed = one("mixed_fp32", F.MIXED_FP32, slots, 1e-6, True)
+    if tuple(legs) != ("mixed", "fp64", "capacity"):
+        # a subset of the legs (a profile of one of them): the legs' records only
+        out = {"workload": f"serving stream: {n_requests} requests, legs {','.join(legs)}, graph {int(graph)}"}
+        if "mixed" in legs:
+            out["mixed"] = one("mixed_fp32", F.MIXED_FP32, slots, 1e-6, graph)
+        if "fp64" in legs:
+            out["fp64_one_at_a_time"] = one("fp64_one_at_a_time", F.FP64, 1, 1e-6, False)
+        if "capacity" in legs:
+            out["mixed_capacity"] = one("mixed_fp32", F.MIXED_FP32, slots, 1e-6, graph, paced=False)
+        return out
+    mixed = one("mixed_fp32", F.MIXED_FP32, slots, 1e-6, graph)
     base = one("fp64_one_at_a_time", F.FP64, 1, 1e-6, False)
-    cap = one("mixed_fp32", F.MIXED_FP32, slots, 1e-6, True, paced=False)
+    cap = one("mixed_fp32", F.MIXED_FP32, slots, 1e-6, graph, paced=False)
     return {"workload": f"serving stream: {n_requests} requests, Poisson {rate:g}/s, n log-uniform [5000, 300000], "
                         f"m in {{100, 200, 500}}, exponential or matern32, t=20, 70% nll+grad / 30% predict_var "
                         f"(n_p=n/4, s=20), tol=1e-6, budget {budget_gib:g} GiB",
@@ -405,6 +416,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-legs", default="mixed,fp64,capacity",
+                    help="serving legs to run: mixed (paced), fp64 (one-at-a-time float64 loop), capacity (all queued)")
+    ap.add_argument("--serve-graph", type=int, default=1,
+                    help="mixed legs replay PCG iterations from HIP graphs (0: plain launches)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for hardware-counter scaling)")
     args = ap.parse_args()
@@ -426,7 +441,8 @@ def main():
         return
     if args.serving_only:
         print(json.dumps({"serving": run_serving(F, torch, args.serve_requests, args.serve_rate, args.serve_slots,
-                                                 args.serve_budget_gib)}), flush=True)
+                                                 args.serve_budget_gib, legs=args.serve_legs.split(","),
+                                                 graph=bool(args.serve_graph))}), flush=True)
         return
     log(f"generating inputs n={args.n} m={args.m} t={args.probes}")
     t0 = time.perf_counter()
@@ -513,7 +529,8 @@ def main():
     if not args.no_serving:
         log("serving leg")
         out["serving"] = run_serving(F, torch, args.serve_requests, args.serve_rate, args.serve_slots,
-                                     args.serve_budget_gib)
+                                     args.serve_budget_gib, legs=args.serve_legs.split(","),
+                                     graph=bool(args.serve_graph))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_n, args.cpu_iters)
