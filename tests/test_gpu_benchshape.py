@@ -111,6 +111,28 @@ def test_mixed_fixed_iterations_at_bench_shape(F, name, products):
     assert np.all(err <= 1e-4)
 
 
+@pytest.mark.parametrize("t", [12, 20])
+@pytest.mark.parametrize("name", ["m500_uniform", "m500_clustered"])
+def test_mixed_narrow_blocks_against_oracle(F, name, t):
+    """Blocks of at most 16 and 32 columns (t' = 13 and 21, the serving
+    stream's width): the split residual pass and expansion multiply one or
+    two of their four 16-column tiles and the tiled sparse product leaves its
+    empty column tiles out.  Against the oracle with the same probes and
+    iteration count: 1e-4."""
+    say("case", name, "t", t)
+    locs, y, theta, ind, gamma = case(**CASES[name])
+    k = 12
+    ref = O.nll_grad(O.FSA(locs, ind, theta, gamma), y, t, 96, fixed_iter=k)
+    with F.FSA(locs, y, theta, ind, gamma, num_probes=t, seed=96, fixed_iter=k, precision=F.MIXED_FP32,
+               rr_period=5) as f:
+        nll, grad, st = f.nll_grad()
+    err = np.abs(grad - ref["grad"]) / gscale(ref)
+    say("nll rel", abs(nll - ref["nll"]) / abs(ref["nll"]), "grad err / scale", err)
+    assert abs(nll - ref["nll"]) <= 1e-4 * abs(ref["nll"])
+    assert np.all(err <= 1e-4)
+    assert st["iters_min"] == k and st["iters_max"] == k
+
+
 @pytest.mark.parametrize("name", ["m500_uniform", "m500_clustered"])
 def test_split_products_agree_with_fp32_mfma(F, name):
     """The two ways of taking MIXED_FP32's low-rank products (bfloat16 parts,
