@@ -173,22 +173,25 @@ def roofline(res, n, m, tp, precision):
     dom = res["dominant_class"]
     avg = [res["profiled_step_kernel_ms"][k] / max(res["profiled_step_kernel_launches"][k], 1) for k in range(5)]
     avg[dom] = res["kernel_ms"][dom] / max(res["kernel_launches"][dom], 1)  # over the timed steps
-    byt, flop = kernel_work(dom, n, m, tp, res["nnz"], b, ba)
-    t_s = avg[dom] / 1000.0
-    gbs = byt / t_s / 1e9
-    tfl = flop / t_s / 1e12
-    peak_t = PEAK_TFLOPS["f64" if precision == "f64" else ("bf16" if precision == "bf16a" and dom in (1, 2) else "f32")]
-    t_hbm = byt / (HBM_PEAK_GBS * 1e9)
-    t_cmp = flop / (peak_t * 1e12)
-    if t_cmp > t_hbm:
-        r = {"bound": "mfma", "achieved": tfl, "peak": peak_t, "unit": "TFLOP/s", "frac": tfl / peak_t}
-    else:
-        r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+
+    def bound(k):
+        """(bound, achieved, peak, unit, frac, bytes, flops, GB/s, TFLOP/s) of class k at its average launch"""
+        byt, flop = kernel_work(k, n, m, tp, res["nnz"], b, ba)
+        t_s = max(avg[k], 1e-9) / 1000.0
+        gbs, tfl = byt / t_s / 1e9, flop / t_s / 1e12
+        peak_t = PEAK_TFLOPS["f64" if precision == "f64" else ("bf16" if precision == "bf16a" and k in (1, 2) else "f32")]
+        if flop / (peak_t * 1e12) > byt / (HBM_PEAK_GBS * 1e9):
+            return "mfma", tfl, peak_t, "TFLOP/s", tfl / peak_t, byt, flop, gbs, tfl
+        return "hbm", gbs, HBM_PEAK_GBS, "GB/s", gbs / HBM_PEAK_GBS, byt, flop, gbs, tfl
+
+    bnd, ach, peak, unit, frac, byt, flop, gbs, tfl = bound(dom)
+    r = {"bound": bnd, "achieved": ach, "peak": peak, "unit": unit, "frac": frac}
     name = KERNEL_NAMES[precision][dom]
     r.update({"traffic": measured_traffic(name), "kernel": KERNELS[dom], "rocprof_kernel": name,
               "avg_launch_ms": avg[dom], "algorithmic_bytes": byt, "algorithmic_flops": flop, "achieved_GBps": gbs,
               "achieved_TFLOPs": tfl, "source_fingerprint": source_fingerprint(),
               "per_kernel_avg_ms": dict(zip(KERNELS, avg)),
+              "per_kernel_frac": {KERNELS[k]: {"bound": bound(k)[0], "frac": bound(k)[4]} for k in range(4)},
               "timing": "the dominant kernel class timed with HIP events over the timed steps; the other classes "
                         "from one untimed step with every class timed"})
     return r
