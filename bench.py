@@ -427,8 +427,8 @@ def main():
                     help="also run a plain device copy of this size (for hardware-counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path does not shard "
-              f"across GPUs in this build)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the library runs on one GPU "
+              f"and does not shard the path across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
