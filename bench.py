@@ -41,10 +41,10 @@ def log(*a):
 
 # rocprofv3 kernel names of the four PCG kernel classes, per element type
 KERNEL_NAMES = {
-    "f32": ["k_spmm_tiled<2, false>", "k_reduce_split<true, 1, 4>", "k_rows_split<2, 8, 4>", "k_pcg_hupdate<float, float>"],
-    "f32mfma": ["k_spmm_tiled<2, false>", "k_reduce_gemm_f32<float, true, 1>", "k_rows_gemm_f32<float, true, 2>",
+    "f32": ["k_spmm_tiled<2, 4>", "k_reduce_split<true, 1, 4>", "k_rows_split<2, 8, 4>", "k_pcg_hupdate<float, float>"],
+    "f32mfma": ["k_spmm_tiled<2, 4>", "k_reduce_gemm_f32<float, true, 1>", "k_rows_gemm_f32<float, true, 2>",
                 "k_pcg_hupdate<float, float>"],
-    "bf16a": ["k_spmm_tiled<2, false>", "k_reduce_bf16<true, 1>", "k_rows_bf16<2>", "k_pcg_hupdate<float, float>"],
+    "bf16a": ["k_spmm_tiled<2, 4>", "k_reduce_bf16<true, 1>", "k_rows_bf16<2>", "k_pcg_hupdate<float, float>"],
     "f64": ["k_spmm_dense<double, 2>", "k_reduce_gemm_f64<true, 1>",
             "k_rows_gemm_f64<true, 2, 3>", "k_pcg_hupdate<double, double>"],
 }

@@ -1128,52 +1128,99 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 
 // ------------------------------------------------------------------ SpMM on pre-scattered tiles
 // The float32 operator's pattern and values are fixed for a whole solve, so
-// the build scatters each 32-row group's nonzeros once into dense 32 x 64
-// tiles, one per 64-position chunk of the cell's 3x3 neighbourhood (in
-// Csr::key positions), tiles of a cell in (group, chunk) order.  Inside a
-// tile the values sit in the order the MFMA 16x16x4 reads them: for row
-// tile rt, 16-position step ks and lane (q, r16), the four positions
+// the build scatters them once into dense 64 x 64 tiles.  The rows are taken
+// by cell pairs: cells 2 sx and 2 sx + 1 of a cell row (one cell at an odd
+// grid's right edge), whose rows are contiguous.  The pair's neighbourhood
+// is cell rows sy - 1 .. sy + 1 by cell columns 2 sx - 1 .. 2 sx + 2
+// (clipped): three contiguous column ranges, 12 cells against 18 for the
+// two cells' own neighbourhoods, so a staged chunk of X serves twice the
+// rows of a single cell.  A pair has a tile per (64-row group, 64-position
+// chunk of its neighbourhood), tiles in (group, chunk) order.  Inside a tile
+// the values sit in the order the MFMA 16x16x4 reads them: for row tile rt
+// (0..3), 16-position step ks and lane (q, r16), the four positions
 // 16 ks + 4 q + j (j = 0..3) of row 16 rt + r16 are one 16-byte word.  The
 // product then loads its sparse operand straight into registers (no
 // scatter, no tile clearing, no keys); the chunk's block rows of X go
 // through LDS, double-buffered, so a chunk costs one workgroup barrier.
-// The stored zeros make a tile about twice the bytes of the key/value
-// entries it replaces; a per-tile mask marks the 16 x 16 blocks (row tile,
-// 16-position step) that hold a nonzero, and a wave neither loads nor
-// multiplies the others (padding rows and positions, and neighbour points
-// beyond the taper range of all 16 rows: about a quarter of the blocks
-// with the points of each cell in ascending y).
+// A per-tile mask marks the 16 x 16 blocks (row tile, 16-position step)
+// that hold a nonzero, and a wave neither loads nor multiplies the others
+// (padding rows and positions, and neighbour points beyond the taper range
+// of all 16 rows; the points of each cell are in ascending y).
 struct SpmmTile {
-  static constexpr int ROWS = 32, CH = 64, FLOATS = ROWS * CH;
+  static constexpr int ROWS = 64, CH = 64, FLOATS = ROWS * CH;
   __host__ __device__ static int offset(int r, int v) {
     const int rt = r >> 4, r16 = r & 15, ks = v >> 4, q = (v >> 2) & 3, j = v & 3;
     return (((rt * 4 + ks) * 64 + q * 16 + r16) << 2) + j;
   }
 };
 
-template <int EM, bool NARROW>
+// Cell pairs of a gx-wide grid: gxs = ceil(gx / 2) pairs per cell row.
+__host__ __device__ __forceinline__ int64_t pair_cols(int64_t gx) { return (gx + 1) >> 1; }
+
+// Rows [rb, re) of pair `pair` (cs: the row grid's cell starts).
+__device__ __forceinline__ void pair_rows(int64_t pair, const GridDesc& gd, const int64_t* __restrict__ cs,
+                                          int64_t& rb, int64_t& re) {
+  const int64_t gxs = pair_cols(gd.gx), sx = pair % gxs, sy = pair / gxs;
+  const int64_t c0 = sy * gd.gx + 2 * sx;
+  const int64_t c1 = sy * gd.gx + (2 * sx + 2 < gd.gx ? 2 * sx + 2 : gd.gx);
+  rb = cs[c0];
+  re = cs[c1];
+}
+
+// The column points that can neighbour a row of pair `pair`, as cell_ranges
+// for a cell: range t is [qb[t], qe[t]) (cell row sy - 1 + t, cell columns
+// 2 sx - 1 .. 2 sx + 2, clipped) and starts at position off[t] of the
+// concatenation; the return value is the total length.
+__device__ __forceinline__ int pair_ranges(int64_t pair, const GridDesc& gd, const int64_t* __restrict__ ccs, int* qb,
+                                           int* qe, int* off) {
+  const int64_t gxs = pair_cols(gd.gx), sx = pair % gxs, sy = pair / gxs;
+  const int64_t xlo = 2 * sx - 1 < 0 ? 0 : 2 * sx - 1;
+  const int64_t xhi = 2 * sx + 2 >= gd.gx ? gd.gx - 1 : 2 * sx + 2;
+  int tot = 0;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int64_t yy = sy - 1 + t;
+    qb[t] = qe[t] = 0;
+    if (yy >= 0 && yy < gd.gy) {
+      qb[t] = (int)ccs[yy * gd.gx + xlo];
+      qe[t] = (int)ccs[yy * gd.gx + xhi + 1];
+    }
+    off[t] = tot;
+    tot += qe[t] - qb[t];
+  }
+  return tot;
+}
+
+// One workgroup (4 waves) per cell pair and 64-column block; wave w owns row
+// tile w of every 64-row group and the block's first NCT 16-column tiles
+// (NCT < 4: a single block of at most 16 NCT columns).
+template <int EM, int NCT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_spmm_tiled(
-    const int64_t* __restrict__ rcs, int64_t ncell, const int64_t* __restrict__ ccs, GridDesc gd,
+    const int64_t* __restrict__ rcs, int64_t npair, const int64_t* __restrict__ ccs, GridDesc gd,
     const int64_t* __restrict__ toff, const float* __restrict__ tiles, const unsigned* __restrict__ tmask,
     const float* __restrict__ X, int ldx, int ncols, SpmmEpi<float> epi, double* __restrict__ dot_part, int ld_dot,
     int sw) {
   constexpr int CH = SpmmTile::CH, XLD = 68, XU = CH * 16 / 256;
   constexpr unsigned TB = SpmmTile::FLOATS * 4;  // bytes per tile
+  constexpr bool HD = EM == SP_PCG || EM == SP_DOT;
   __shared__ __attribute__((aligned(16))) float Xs[2][CH * XLD];
   typedef Mfma<float>::acc acc_t;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q = lane >> 4, r16 = lane & 15;
-  const int64_t cell = xcd_cell(blockIdx.x, ncell, gd.gx, sw);
-  if (cell >= ncell) return;
+  const int64_t pair = xcd_cell(blockIdx.x, npair, pair_cols(gd.gx), sw);
+  if (pair >= npair) return;
   const int c0 = blockIdx.y * 64;
-  const int64_t rb = rcs[cell], re = rcs[cell + 1];
-  const int rt = w >> 1, ct0 = (w & 1) * 2;  // this wave's tiles: rows rt*16.., columns (ct0, ct0+1)*16..
-  double dsum0 = 0.0, dsum1 = 0.0;
+  int64_t rb, re;
+  pair_rows(pair, gd, rcs, rb, re);
+  const int rt = w;  // this wave's row tile
+  double dsum[NCT];
+#pragma unroll
+  for (int t = 0; t < NCT; ++t) dsum[t] = 0.0;
   if (rb < re) {
     int qb[3], qe[3], off[3];
-    const int V = cell_ranges(cell, gd, ccs, qb, qe, off);
+    const int V = pair_ranges(pair, gd, ccs, qb, qe, off);
     int qlo = 0x7fffffff, qhi = 0;
 #pragma unroll
     for (int t = 0; t < 3; ++t)
@@ -1185,8 +1232,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const __amdgpu_buffer_rsrc_t xrs = rsrc_of(X + (int64_t)qlo * ldx, (int64_t)(qhi - qlo) * ldx * 4);
     const int nk = (V + CH - 1) / CH;
     const int ng = (int)((re - rb + SpmmTile::ROWS - 1) / SpmmTile::ROWS);
-    const int nt = ng * nk;  // this cell's tiles, (group, chunk) order
-    const int64_t t0 = toff[cell];
+    const int nt = ng * nk;  // this pair's tiles, (group, chunk) order
+    const int64_t t0 = toff[pair];
     const __amdgpu_buffer_rsrc_t trs = rsrc_of(tiles + t0 * SpmmTile::FLOATS, (int64_t)nt * TB);
     // staging unit u = tid + 256 k: chunk row (tid >> 4) + 16 k, columns 4 (tid & 15)..+3
     const int sc4 = (tid & 15) * 4;
@@ -1217,32 +1264,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       for (int k = 0; k < XU; ++k)
         *reinterpret_cast<f4*>(&xs[((tid >> 4) + 16 * k) * XLD + sc4]) = f4{xr[k].v[0], xr[k].v[1], xr[k].v[2], xr[k].v[3]};
     };
-    // this wave's column tiles that hold a column (uniform): in a block of at
-    // most 32 columns (NARROW) the second, or both, have no work
-    const bool on0 = !NARROW || c0 + ct0 * 16 < ncols, on1 = !NARROW || c0 + ct0 * 16 + 16 < ncols;
-    auto mma = [&](const float* xs, const f4* a, unsigned mk, acc_t& acc0, acc_t& acc1) {
-      if (!on0) return;
+    auto mma = [&](const float* xs, const f4* a, unsigned mk, acc_t* acc) {
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         if (!((mk >> ks) & 1u)) continue;  // uniform over the wave
-        const float* xb = &xs[(ks * 16 + 4 * q) * XLD + ct0 * 16 + r16];
-        if (on1) {
+        const float* xb = &xs[(ks * 16 + 4 * q) * XLD + r16];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            acc0 = Mfma<float>::op(a[ks][j], xb[j * XLD], acc0);
-            acc1 = Mfma<float>::op(a[ks][j], xb[j * XLD + 16], acc1);
-          }
-        } else {
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc0 = Mfma<float>::op(a[ks][j], xb[j * XLD], acc0);
-        }
+          for (int t = 0; t < NCT; ++t) acc[t] = Mfma<float>::op(a[ks][j], xb[j * XLD + 16 * t], acc[t]);
       }
+    };
+    // epilogue offset of this lane's element r of column tile t (past the block's columns: out of range)
+    auto eoff = [&](int t, int r) -> unsigned {
+      const int c = c0 + 16 * t + r16;
+      return c < ncols ? (unsigned)((rt * 16 + Mfma<float>::orow(q, r)) * (int)epi.ld + c) * 4u : (unsigned)BUF_OOR;
     };
     V4<float> xr[XU];
     f4 ar[4], ac[4];
     load_chunk(0, xr);
     unsigned mnext = load_a(0, ar);
-    acc_t acc0 = acc_t{0, 0, 0, 0}, acc1 = acc_t{0, 0, 0, 0};
+    acc_t acc[NCT];
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) acc[t] = acc_t{0, 0, 0, 0};
     for (int i = 0; i < nt; ++i) {
       const int g = i / nk, k = i - g * nk;
       // chunk buffers alternate over the whole (group, chunk) sequence: the
@@ -1261,71 +1305,64 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int64_t g0 = rb + (int64_t)g * SpmmTile::ROWS;
       const int nrg = (int)min((int64_t)SpmmTile::ROWS, re - g0);
       const __amdgpu_buffer_rsrc_t yrs = rsrc_of(epi.Y + g0 * epi.ld, (int64_t)nrg * epi.ld * 4);
-      constexpr bool HD = EM == SP_PCG || EM == SP_DOT;
       const __amdgpu_buffer_rsrc_t hrs = rsrc_of(HD ? epi.H + g0 * epi.ld : epi.Y, HD ? (int64_t)nrg * epi.ld * 4 : 0);
       const __amdgpu_buffer_rsrc_t prs = rsrc_of(EM == SP_PCG && epi.P ? epi.P + g0 * epi.ld : epi.Y,
                                                  EM == SP_PCG && epi.P ? (int64_t)nrg * epi.ld * 4 : 0);
-      unsigned eo[2][4];
-      float in0[2][4], in1[2][4];
       const bool last = k == nk - 1;
+      mma(xs, ac, mcur, acc);
       if (last) {
-        // epilogue inputs of this wave's two tiles, in flight during the products
+        // epilogue inputs of this wave's tiles (loaded after the products:
+        // with four column tiles in flight they would not fit the registers)
+        float in0[NCT][4], in1[NCT][4];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int c = c0 + (ct0 + t) * 16 + r16;
+        for (int t = 0; t < NCT; ++t)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            eo[t][r] = c < ncols ? (unsigned)((rt * 16 + Mfma<float>::orow(q, r)) * (int)epi.ld + c) * 4u : (unsigned)BUF_OOR;
-            if constexpr (EM == SP_ACC) in0[t][r] = bload<float>(yrs, eo[t][r]);
-            if constexpr (HD) in0[t][r] = bload<float>(hrs, eo[t][r]);
-            if constexpr (EM == SP_PCG) in1[t][r] = bload<float>(prs, eo[t][r]);
+            const unsigned o = eoff(t, r);
+            if constexpr (EM == SP_ACC) in0[t][r] = bload<float>(yrs, o);
+            if constexpr (HD) in0[t][r] = bload<float>(hrs, o);
+            if constexpr (EM == SP_PCG) in1[t][r] = bload<float>(prs, o);
           }
-        }
-      }
-      mma(xs, ac, mcur, acc0, acc1);
-      if (last) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NCT; ++t) {
           double d = 0.0;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float a = t == 0 ? acc0[r] : acc1[r];
+            const unsigned o = eoff(t, r);
+            const float a = acc[t][r];
             if constexpr (EM == SP_STORE) {
-              bstore<float>(a, yrs, eo[t][r]);
+              bstore<float>(a, yrs, o);
             } else if constexpr (EM == SP_ACC) {
-              bstore<float>(a + in0[t][r], yrs, eo[t][r]);
+              bstore<float>(a + in0[t][r], yrs, o);
             } else if constexpr (EM == SP_DOT) {
               d += (double)in0[t][r] * (double)a;  // zero past the group's rows and columns
             } else {
               const float v = (float)((double)a + (double)in1[t][r]);
-              bstore<float>(v, yrs, eo[t][r]);
+              bstore<float>(v, yrs, o);
               d += (double)in0[t][r] * (double)v;  // zero past the group's rows and columns
             }
           }
-          if (t == 0) dsum0 += d;
-          else dsum1 += d;
+          dsum[t] += d;
+          acc[t] = acc_t{0, 0, 0, 0};
         }
-        acc0 = acc_t{0, 0, 0, 0};
-        acc1 = acc_t{0, 0, 0, 0};
       }
     }
   }
-  if constexpr (EM >= SP_PCG) {
-    dsum0 += __shfl_xor(dsum0, 16, 64);
-    dsum0 += __shfl_xor(dsum0, 32, 64);
-    dsum1 += __shfl_xor(dsum1, 16, 64);
-    dsum1 += __shfl_xor(dsum1, 32, 64);
-    double* red = reinterpret_cast<double*>(&Xs[0][0]);
+  if constexpr (HD) {
+    // column c0 + 16 t + r16 gathers the q groups of the wave, then the four waves (row tiles)
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) {
+      dsum[t] += __shfl_xor(dsum[t], 16, 64);
+      dsum[t] += __shfl_xor(dsum[t], 32, 64);
+    }
+    double* red = reinterpret_cast<double*>(&Xs[0][0]);  // [wave][64 columns]
     __syncthreads();
     if (q == 0) {
-      red[w * 32 + r16] = dsum0;
-      red[w * 32 + 16 + r16] = dsum1;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) red[w * 64 + 16 * t + r16] = t < NCT ? dsum[t < NCT ? t : 0] : 0.0;
     }
     __syncthreads();
-    if (tid < 64) {
-      const int half = tid >> 5, o = tid & 31;
-      dot_part[cell * ld_dot + c0 + tid] = red[half * 32 + o] + red[(half + 2) * 32 + o];
-    }
+    if (tid < 64) dot_part[pair * ld_dot + c0 + tid] = (red[tid] + red[64 + tid]) + (red[128 + tid] + red[192 + tid]);
   }
 }
 

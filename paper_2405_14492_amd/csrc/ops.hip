@@ -490,44 +490,48 @@ static fsa_status launch_spmm_cell(const Csr& S, const Grid& rg, const Grid& cg,
 }
 
 // ---------------------------------------------------------------- pre-scattered tiles
-// tiles of cell c: ceil(rows / 32) groups x ceil(V / 64) neighbourhood chunks
-__global__ void k_tile_counts(const int64_t* __restrict__ cs, int64_t ncell, GridDesc gd, int* __restrict__ cnt) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const int64_t nr = cs[c + 1] - cs[c];
+// tiles of cell pair p: ceil(rows / 64) groups x ceil(V / 64) neighbourhood chunks
+__global__ void k_tile_counts(const int64_t* __restrict__ cs, int64_t npair, GridDesc gd, int* __restrict__ cnt) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= npair) return;
+  int64_t rb, re;
+  pair_rows(p, gd, cs, rb, re);
   int qb[3], qe[3], off[3];
-  const int V = nr > 0 ? cell_ranges(c, gd, cs, qb, qe, off) : 0;
-  cnt[c] = nr > 0 ? (int)((nr + SpmmTile::ROWS - 1) / SpmmTile::ROWS) * ((V + SpmmTile::CH - 1) / SpmmTile::CH) : 0;
+  const int V = re > rb ? pair_ranges(p, gd, cs, qb, qe, off) : 0;
+  cnt[p] = re > rb ? (int)((re - rb + SpmmTile::ROWS - 1) / SpmmTile::ROWS) * ((V + SpmmTile::CH - 1) / SpmmTile::CH)
+                   : 0;
 }
 
-// one workgroup per cell: the cell's tiles are cleared, then, one wave per
-// row at a time, every nonzero of the cell's rows goes to its (group, chunk)
-// tile at its MFMA-order slot, and the
-// tile's mask gets the bit of the 16 x 16 block (row tile, step) it lands in
-// (bit rt * 4 + ks; a nonzero value, so a block with only zeros stays off).
-// The masks of the cell's first TILE_MASK_LDS tiles gather in LDS, the rest
-// (cells of very many points) in global memory.
+// one workgroup per cell pair: the pair's tiles are cleared, then, one wave
+// per row at a time, every nonzero of the pair's rows goes to its (group,
+// chunk) tile at its MFMA-order slot (its column's position in the pair's
+// neighbourhood ranges), and the tile's mask gets the bit of the 16 x 16
+// block (row tile, step) it lands in (bit rt * 4 + ks; a nonzero value, so
+// a block with only zeros stays off).  The masks of the pair's first
+// TILE_MASK_LDS tiles gather in LDS, the rest (pairs of very many points) in
+// global memory.
 constexpr int TILE_MASK_LDS = 512;
-__global__ __launch_bounds__(256) void k_tile_fill(const int64_t* __restrict__ cs, int64_t ncell, GridDesc gd,
+__global__ __launch_bounds__(256) void k_tile_fill(const int64_t* __restrict__ cs, int64_t npair, GridDesc gd,
                                                    const int64_t* __restrict__ toff, const int64_t* __restrict__ rp,
-                                                   const int* __restrict__ key, const float* __restrict__ val,
+                                                   const int* __restrict__ col, const float* __restrict__ val,
                                                    float* __restrict__ tiles, unsigned* __restrict__ mask) {
   __shared__ unsigned msk[TILE_MASK_LDS];
-  const int64_t c = blockIdx.x;
-  if (c >= ncell) return;
-  const int64_t rb = cs[c], re = cs[c + 1];
+  const int64_t pr = blockIdx.x;
+  if (pr >= npair) return;
+  int64_t rb, re;
+  pair_rows(pr, gd, cs, rb, re);
   if (rb >= re) return;
   int qb[3], qe[3], off[3];
-  const int V = cell_ranges(c, gd, cs, qb, qe, off);
+  const int V = pair_ranges(pr, gd, cs, qb, qe, off);
   const int nk = (V + SpmmTile::CH - 1) / SpmmTile::CH;
   const int nt = (int)((re - rb + SpmmTile::ROWS - 1) / SpmmTile::ROWS) * nk;
-  float* base = tiles + toff[c] * SpmmTile::FLOATS;
-  unsigned* gmask = mask + toff[c];
+  float* base = tiles + toff[pr] * SpmmTile::FLOATS;
+  unsigned* gmask = mask + toff[pr];
   for (int i = threadIdx.x; i < nt; i += 256) {
     if (i < TILE_MASK_LDS) msk[i] = 0u;
     else gmask[i] = 0u;
   }
-  // the cell's tiles start from zero (written here, so the scattered
+  // the pair's tiles start from zero (written here, so the scattered
   // entries below update lines this workgroup has just written)
   f4* base4 = reinterpret_cast<f4*>(base);
   for (int64_t i = threadIdx.x; i < (int64_t)nt * (SpmmTile::FLOATS / 4); i += 256) base4[i] = f4{0.f, 0.f, 0.f, 0.f};
@@ -536,7 +540,12 @@ __global__ __launch_bounds__(256) void k_tile_fill(const int64_t* __restrict__ c
   for (int64_t p = rb + w; p < re; p += 4) {
     const int g = (int)((p - rb) / SpmmTile::ROWS), r = (int)((p - rb) % SpmmTile::ROWS);
     for (int64_t e = rp[p] + lane; e < rp[p + 1]; e += 64) {
-      const int slot = key[e] & KEY_SLOT_MASK;
+      // the column's range in the pair's neighbourhood (it lies in one: a
+      // row's own cell neighbourhood is inside its pair's)
+      const int qc = col[e];
+      const int rg = (qc >= qb[2] && qc < qe[2]) ? 2 : ((qc >= qb[1] && qc < qe[1]) ? 1 : 0);
+      if (qc < qb[rg] || qc >= qe[rg]) continue;
+      const int slot = qc - qb[rg] + off[rg];
       const int t = g * nk + slot / SpmmTile::CH, v = slot % SpmmTile::CH;
       const float x = val[e];
       base[(int64_t)t * SpmmTile::FLOATS + SpmmTile::offset(r, v)] = x;
@@ -551,24 +560,26 @@ __global__ __launch_bounds__(256) void k_tile_fill(const int64_t* __restrict__ c
   for (int i = threadIdx.x; i < nt && i < TILE_MASK_LDS; i += 256) gmask[i] = msk[i];
 }
 
+int64_t spmm_tile_pairs(const Grid& g) { return pair_cols(g.desc.gx) * g.desc.gy; }
+
 fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<int64_t>& toff, Buf<float>& tiles,
                             Buf<unsigned>& tmask, hipStream_t st) {
-  const int64_t nc = g.ncell;
-  FSA_TRY(toff.alloc(nc + 1));
+  const int64_t np = g.ncell > 0 ? spmm_tile_pairs(g) : 0;
+  FSA_TRY(toff.alloc(np + 1));
   Buf<int> cnt;
   Buf<int64_t> scr;
-  FSA_TRY(cnt.alloc(nc > 0 ? nc : 1));
-  hipLaunchKernelGGL(k_tile_counts, dim3(ceil_div(nc > 0 ? nc : 1, 256)), dim3(256), 0, st, g.cstart.p, nc, g.desc,
+  FSA_TRY(cnt.alloc(np > 0 ? np : 1));
+  hipLaunchKernelGGL(k_tile_counts, dim3(ceil_div(np > 0 ? np : 1, 256)), dim3(256), 0, st, g.cstart.p, np, g.desc,
                      cnt.p);
-  FSA_TRY(scan_counts(cnt.p, nc, toff.p, scr, st));
+  FSA_TRY(scan_counts(cnt.p, np, toff.p, scr, st));
   int64_t ntile = 0;
-  FSA_HIP(hipMemcpyAsync(&ntile, toff.p + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  FSA_HIP(hipMemcpyAsync(&ntile, toff.p + np, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   FSA_HIP(hipStreamSynchronize(st));
   const size_t nf = (size_t)(ntile > 0 ? ntile : 1) * SpmmTile::FLOATS;
-  FSA_TRY(tiles.alloc(nf));  // cleared cell by cell by the fill
+  FSA_TRY(tiles.alloc(nf));  // cleared pair by pair by the fill
   FSA_TRY(tmask.alloc(ntile > 0 ? ntile : 1));
-  if (nc > 0)
-    hipLaunchKernelGGL(k_tile_fill, dim3(nc), dim3(256), 0, st, g.cstart.p, nc, g.desc, toff.p, S.row_ptr.p, S.key.p,
+  if (np > 0)
+    hipLaunchKernelGGL(k_tile_fill, dim3(np), dim3(256), 0, st, g.cstart.p, np, g.desc, toff.p, S.row_ptr.p, S.col.p,
                        val, tiles.p, tmask.p);
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -582,14 +593,17 @@ static fsa_status launch_spmm_tiled(const Grid& g, const int64_t* toff, const fl
     set_error("spmm: block rows must be 16-byte aligned (ld multiple of 4)");
     return FSA_ERR_INVALID_ARG;
   }
-  dim3 grid(8 * ceil_div(g.ncell, 8), ceil_div(ncols, 64));
-  const int sw = 32;  // cell columns per strip of the workgroup walk
-  if (ncols <= 32)  // one block whose last two column tiles are empty
-    hipLaunchKernelGGL((k_spmm_tiled<SP_PCG, true>), grid, dim3(256), 0, st, g.cstart.p, g.ncell, g.cstart.p, g.desc,
-                       toff, tiles, tmask, X, ldx, ncols, epi, dot_part, ld_dot, sw);
-  else
-    hipLaunchKernelGGL((k_spmm_tiled<SP_PCG, false>), grid, dim3(256), 0, st, g.cstart.p, g.ncell, g.cstart.p, g.desc,
-                       toff, tiles, tmask, X, ldx, ncols, epi, dot_part, ld_dot, sw);
+  const int64_t np = spmm_tile_pairs(g);
+  dim3 grid(8 * ceil_div(np, 8), ceil_div(ncols, 64));
+  const int sw = 16;  // pair columns per strip of the workgroup walk
+  auto go = [&](auto nct) {
+    hipLaunchKernelGGL((k_spmm_tiled<SP_PCG, decltype(nct)::value>), grid, dim3(256), 0, st, g.cstart.p, np,
+                       g.cstart.p, g.desc, toff, tiles, tmask, X, ldx, ncols, epi, dot_part, ld_dot, sw);
+  };
+  // a single block multiplies only the column tiles that hold a column
+  if (ncols <= 16) go(std::integral_constant<int, 1>{});
+  else if (ncols <= 32) go(std::integral_constant<int, 2>{});
+  else go(std::integral_constant<int, 4>{});
   FSA_HIP(hipGetLastError());
   return FSA_OK;
 }
@@ -1170,13 +1184,15 @@ fsa_status pcg_iter(PcgBlock<T>& b, const OpDesc<T>& op, double tol, int fixed, 
   // 1. V = S H + P, h^T v
   {
     SpmmEpi<T> epi{b.V, b.H, lr ? b.P : nullptr, b.ld};
-    int64_t g = op.grid->ncell;
+    // partial dot rows: one per cell, or one per cell pair of the tiled product
+    const bool tiled = sizeof(T) == 4 && op.tiles;
+    int64_t g = tiled ? spmm_tile_pairs(*op.grid) : op.grid->ncell;
     size_t need = (size_t)g * ldd;
     if (s.dot.count < need) FSA_TRY(s.dot.alloc(need));
     {
       KT_BEGIN(b, KT_SPMM);
       if constexpr (sizeof(T) == 4) {
-        if (op.tiles)
+        if (tiled)
           FSA_TRY(launch_spmm_tiled(*op.grid, op.tile_off, op.tiles, op.tile_mask, (const float*)b.H, b.ld, b.ncols,
                                     reinterpret_cast<const SpmmEpi<float>&>(epi), s.dot.p, ldd, st));
         else

@@ -118,12 +118,15 @@ fsa_status lowrank_expand(const T* A, const T* A2, int64_t n, int kdim, const T*
 template <typename T>
 fsa_status spmm(const Csr& S, const Grid& rg, const Grid& cg, const T* val, const T* X, int ldx, int ncols, T* Y,
                 int ldy, bool accumulate, hipStream_t st);
-// The float32 sparse part as dense 32 x 64 tiles in MFMA order, one per
-// (32-row group, 64-position neighbourhood chunk) of each cell; toff (ncell
-// + 1) gives each cell's first tile.  The pattern's rows and columns are
-// both the grid g.
+// The float32 sparse part as dense 64 x 64 tiles in MFMA order, one per
+// (64-row group, 64-position neighbourhood chunk) of each cell pair (cells
+// 2 sx, 2 sx + 1 of a cell row); toff (spmm_tile_pairs(g) + 1) gives each
+// pair's first tile.  The pattern's rows and columns are both the grid g.
 fsa_status build_spmm_tiles(const Csr& S, const Grid& g, const float* val, Buf<int64_t>& toff, Buf<float>& tiles,
                             Buf<unsigned>& tmask, hipStream_t st);
+// Cell pairs of grid g (ceil(gx / 2) per cell row); also the number of
+// partial dot rows the tiled product writes.
+int64_t spmm_tile_pairs(const Grid& g);
 // out[c] = sum_p H[p][c] (S X)[p][c] for c < ncols (float64 result; S X is
 // not stored), S with the pattern of grid g on both sides
 template <typename T>

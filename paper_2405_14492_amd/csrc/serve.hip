@@ -134,10 +134,19 @@ fsa_status footprint(const fsa_request* r, const fsa_options* opt, uint64_t* out
   double cand = 0, tiles = 0;
   for (size_t c = 0; c < g.cnt.size(); ++c) {
     const double k = g.cnt[c];
-    if (k <= 0) continue;
-    cand += k * (double)nb[c];
-    tiles += std::ceil(k / 32.0) * std::ceil((double)nb[c] / 64.0);
+    if (k > 0) cand += k * (double)nb[c];
   }
+  // the sparse product's 64 x 64 tiles per cell pair (cells 2 sx, 2 sx + 1
+  // of a row); the pair's neighbourhood holds at most its cells' two
+  for (int64_t y = 0; y < g.gy; ++y)
+    for (int64_t x = 0; x < g.gx; x += 2) {
+      const size_t cl = (size_t)(y * g.gx + x), cr = cl + 1;
+      const bool right = x + 1 < g.gx;
+      const double k = (double)g.cnt[cl] + (right ? (double)g.cnt[cr] : 0.0);
+      if (k <= 0) continue;
+      const double v = (double)nb[cl] + (right ? (double)nb[cr] : 0.0);
+      tiles += std::ceil(k / 64.0) * std::ceil(v / 64.0);
+    }
   const double n = (double)r->n, ncell = (double)(g.gx * g.gy);
   const double mp = (double)round_up(r->m, 64);
   const double tp = opt->num_probes + 1.0, ld = (double)round_up((int64_t)tp, 4), ldw = (double)round_up((int64_t)tp, 64);
@@ -159,7 +168,7 @@ fsa_status footprint(const fsa_request* r, const fsa_options* opt, uint64_t* out
   if (prec == FSA_MIXED_FP32) T.add(4 * n * mp);
   if (prec == FSA_MIXED_BF16A) { T.add(2 * n * mp); T.add(2 * (n + 8) * mp); }
   T.add(8 * nnz);
-  if (mixed) { T.add(4 * nnz); T.add(8192.0 * tiles); T.add(4 * tiles); T.add(8 * (ncell + 1)); T.add(4 * ncell); }
+  if (mixed) { T.add(4 * nnz); T.add(16384.0 * tiles); T.add(4 * tiles); T.add(8 * (ncell + 1)); T.add(4 * ncell); }
   T.add(8 * n * ld); T.add(8 * mp * ldw);          // probe block, E
   // the library's reduction scratch: column partials and reduce-GEMM tiles
   const double ncb_max = std::max({std::ceil(ldw / 64.0), mp / 64.0,
