@@ -242,12 +242,33 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 // range of positions [base, base + cnt) and a list holds positions.
 // One workgroup (NW waves) per point of a level, one lane per column
 // (64-column passes).  The point's list (neighbours or children, with
-// coefficients) is loaded across the lanes 64 entries at a time and
-// broadcast entry by entry (readlane reads a lane whatever the exec mask);
-// wave q takes the groups of four entries q, q + NW, q + 2 NW, ... so that
-// up to 4 NW row gathers per point are in flight, and the NW partial sums
-// are added in a fixed order.
-template <bool CHILDREN, int NW>
+// coefficients) is cut into NW contiguous segments, one per wave; a wave loads
+// its segment across its lanes (64 entries at a time) and broadcasts it entry
+// by entry (readlane reads a lane whatever the exec mask), U row gathers at a
+// time with no branch: past the segment's end the last valid entry's row is
+// read again and its term dropped, so all U gathers of a round are in flight
+// together.  The NW partial sums are added in a fixed order.  No point of a
+// level is on the list of another point of the same level, and only the
+// point's own workgroup writes its row, so wave 0 reads that row together
+// with the list: the read is off the dependent chain (row pointer, list,
+// gathers, store).
+template <bool CHILDREN, int NW, int U>
+__device__ __forceinline__ void vtri_chunk(int iq, double vq, int nq, const double* X, int64_t ld, int c,
+                                           double (&acc)[U]) {
+  for (int q = 0; q < nq; q += U) {
+    double xr[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int l = q + k < nq ? q + k : nq - 1;
+      xr[k] = X[(int64_t)__builtin_amdgcn_readlane(iq, l) * ld + c];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (q + k < nq) acc[k] += readlane_d(vq, q + k) * xr[k];
+  }
+}
+
+template <bool CHILDREN, int NW, int U>
 __global__ __launch_bounds__(NW * 64) void k_vtri(int base, int cnt, const int64_t* __restrict__ cptr,
                                               const int* __restrict__ idx, const double* __restrict__ val, int mv,
                                               double* X, int64_t ld, int ncols) {
@@ -259,31 +280,42 @@ __global__ __launch_bounds__(NW * 64) void k_vtri(int base, int cnt, const int64
   // forward: the neighbours of i (a prefix of its mv slots); backward: its children
   const int64_t b = CHILDREN ? cptr[i] : i * mv;
   const int64_t e = CHILDREN ? cptr[i + 1] : i * mv + mv;
+  const int64_t seg = (e - b + NW - 1) / NW;
+  const int64_t sb = b + wq * seg < e ? b + wq * seg : e;
+  const int64_t se = sb + seg < e ? sb + seg : e;
+  // the segment's first 64 entries serve every 64-column pass; neighbour
+  // lists end in -1 slots, so their valid entries are a prefix
+  const int m0 = (int)(se - sb < 64 ? se - sb : 64);
+  const int iq0 = lane < m0 ? idx[sb + lane] : -1;
+  const double vq0 = lane < m0 ? val[sb + lane] : 0.0;
+  // the point's own row for the first pass, issued with the list
+  double own = (wq == 0 && lane < ncols) ? X[i * ld + lane] : 0.0;
   for (int c0 = 0; c0 < ncols; c0 += 64) {
     const int c = c0 + lane;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (int64_t p0 = b; p0 < e; p0 += 64) {
-      const int64_t rem = e - p0;
+    const bool live = c < ncols;
+    const int nq0 = CHILDREN ? m0 : __popcll(__ballot(iq0 >= 0));
+    double acc[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) acc[k] = 0.0;
+    if (live) vtri_chunk<CHILDREN, NW, U>(iq0, vq0, nq0, X, ld, c, acc);
+    for (int64_t p0 = sb + 64; p0 < se; p0 += 64) {  // segments over 64 entries (lists over 64 NW)
+      const int64_t rem = se - p0;
       const int m64 = (int)(rem < 64 ? rem : 64);
       const int iq = lane < m64 ? idx[p0 + lane] : -1;
       const double vq = lane < m64 ? val[p0 + lane] : 0.0;
       const int nq = CHILDREN ? m64 : __popcll(__ballot(iq >= 0));
-      if (c < ncols) {
-        for (int q = 4 * wq; q < nq; q += 4 * NW) {
-          const int i0 = __builtin_amdgcn_readlane(iq, q);
-          a0 += readlane_d(vq, q) * X[(int64_t)i0 * ld + c];
-          if (q + 1 < nq) a1 += readlane_d(vq, q + 1) * X[(int64_t)__builtin_amdgcn_readlane(iq, q + 1) * ld + c];
-          if (q + 2 < nq) a2 += readlane_d(vq, q + 2) * X[(int64_t)__builtin_amdgcn_readlane(iq, q + 2) * ld + c];
-          if (q + 3 < nq) a3 += readlane_d(vq, q + 3) * X[(int64_t)__builtin_amdgcn_readlane(iq, q + 3) * ld + c];
-        }
-      }
+      if (live) vtri_chunk<CHILDREN, NW, U>(iq, vq, nq, X, ld, c, acc);
     }
-    part[wq][lane] = (a0 + a1) + (a2 + a3);
+    double a = acc[0];
+#pragma unroll
+    for (int k = 1; k < U; ++k) a += acc[k];
+    part[wq][lane] = a;
     __syncthreads();
-    if (wq == 0 && c < ncols) {
+    if (wq == 0 && live) {
       double t = part[0][lane];
       for (int u = 1; u < NW; ++u) t += part[u][lane];
-      X[i * ld + c] += t;
+      X[i * ld + c] = own + t;
+      own = c + 64 < ncols ? X[i * ld + c + 64] : 0.0;  // the next pass's
     }
     __syncthreads();
   }
@@ -667,19 +699,20 @@ fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, doub
   const int nlev = (int)v->lptr.size() - 1;
   for (int l = nlev - 1; l >= 0; --l) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
-    // levels with long child lists (the early points) take 16 waves per point
-    if (v->lmaxc[l] > 96)
-      hipLaunchKernelGGL((k_vtri<true, 16>), dim3((unsigned)cnt), dim3(1024), 0, st, b, cnt, v->cptr.p,
+    // 16 waves per point where some list of the level exceeds 32 entries,
+    // else 4; a wave has 8 row gathers in flight per round
+    if (v->lmaxc[l] > 32)
+      hipLaunchKernelGGL((k_vtri<true, 16, 8>), dim3((unsigned)cnt), dim3(1024), 0, st, b, cnt, v->cptr.p,
                          v->ci.p, v->cv.p, 0, Y, ldy, ncols);
     else
-      hipLaunchKernelGGL((k_vtri<true, 4>), dim3((unsigned)cnt), dim3(256), 0, st, b, cnt, v->cptr.p,
+      hipLaunchKernelGGL((k_vtri<true, 4, 8>), dim3((unsigned)cnt), dim3(256), 0, st, b, cnt, v->cptr.p,
                          v->ci.p, v->cv.p, 0, Y, ldy, ncols);
   }
   hipLaunchKernelGGL(k_vscale_rows, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Y, ldy, v->Dvp.p);
   for (int l = 0; l < nlev; ++l) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
     // at most 32 neighbours: 8 waves take four each, all gathers in one round
-    hipLaunchKernelGGL((k_vtri<false, 8>), dim3((unsigned)cnt), dim3(512), 0, st, b, cnt, (const int64_t*)nullptr,
+    hipLaunchKernelGGL((k_vtri<false, 8, 4>), dim3((unsigned)cnt), dim3(512), 0, st, b, cnt, (const int64_t*)nullptr,
                        v->fnbr.p, v->fcoef.p, v->mv, Y, ldy, ncols);
   }
   FSA_HIP(hipGetLastError());
