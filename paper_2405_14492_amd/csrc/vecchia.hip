@@ -245,9 +245,9 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 // coefficients) is cut into NW contiguous segments, one per wave; a wave loads
 // its segment across its lanes (64 entries at a time) and broadcasts it entry
 // by entry (readlane reads a lane whatever the exec mask), U row gathers at a
-// time with no branch: past the segment's end the last valid entry's row is
-// read again and its term dropped, so all U gathers of a round are in flight
-// together.  The NW partial sums are added in a fixed order.  No point of a
+// time: the round issues the loads of its entries that exist before it uses
+// any, so they are in flight together.  The NW partial sums are added in a
+// fixed order.  No point of a
 // level is on the list of another point of the same level, and only the
 // point's own workgroup writes its row, so wave 0 reads that row together
 // with the list: the read is off the dependent chain (row pointer, list,
@@ -258,10 +258,8 @@ __device__ __forceinline__ void vtri_chunk(int iq, double vq, int nq, const doub
   for (int q = 0; q < nq; q += U) {
     double xr[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const int l = q + k < nq ? q + k : nq - 1;
-      xr[k] = X[(int64_t)__builtin_amdgcn_readlane(iq, l) * ld + c];
-    }
+    for (int k = 0; k < U; ++k)
+      xr[k] = q + k < nq ? X[(int64_t)__builtin_amdgcn_readlane(iq, q + k) * ld + c] : 0.0;
 #pragma unroll
     for (int k = 0; k < U; ++k)
       if (q + k < nq) acc[k] += readlane_d(vq, q + k) * xr[k];
