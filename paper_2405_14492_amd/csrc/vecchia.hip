@@ -232,6 +232,23 @@ __global__ void k_vchild_sort(const int64_t* __restrict__ cptr, int64_t n, int* 
   }
 }
 
+// Child lists padded per level: every point of level l gets stride_l slots
+// (the level's longest list), its children first and -1 after, at poff[p],
+// so a product finds a list from the launch's level base and the position
+// alone.  stride_l >= the list's length by construction.
+__global__ void k_vchild_pad(const int64_t* __restrict__ cptr, int64_t n, const int* __restrict__ ci,
+                             const double* __restrict__ cv, const int64_t* __restrict__ poff, int* __restrict__ pci,
+                             double* __restrict__ pcv) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t b = cptr[p], len = cptr[p + 1] - b;
+  const int64_t o = poff[p], w = poff[p + 1] - o;
+  for (int64_t j = 0; j < w; ++j) {
+    pci[o + j] = j < len ? ci[b + j] : -1;
+    pcv[o + j] = j < len ? cv[b + j] : 0.0;
+  }
+}
+
 // ---------------------------------------------------------------- B products
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const int2 u = __builtin_bit_cast(int2, v);
@@ -239,20 +256,20 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 }
 
 // Points, lists and block rows are stored in level order, so level l is the
-// range of positions [base, base + cnt) and a list holds positions.
+// range of positions [base, base + cnt) and a list holds positions.  The
+// k-th point's list (neighbours, or children in the padded layout) is the
+// stride slots at lbase + k * stride, valid entries first and -1 after.
 // One workgroup (NW waves) per point of a level, one lane per column
-// (64-column passes).  The point's list (neighbours or children, with
-// coefficients) is cut into NW contiguous segments, one per wave; a wave loads
-// its segment across its lanes (64 entries at a time) and broadcasts it entry
-// by entry (readlane reads a lane whatever the exec mask), U row gathers at a
-// time: the round issues the loads of its entries that exist before it uses
-// any, so they are in flight together.  The NW partial sums are added in a
-// fixed order.  No point of a
-// level is on the list of another point of the same level, and only the
-// point's own workgroup writes its row, so wave 0 reads that row together
-// with the list: the read is off the dependent chain (row pointer, list,
-// gathers, store).
-template <bool CHILDREN, int NW, int U>
+// (64-column passes).  The list is cut into NW contiguous segments, one per
+// wave; a wave loads its segment across its lanes (64 entries at a time) and
+// broadcasts it entry by entry (readlane reads a lane whatever the exec
+// mask), U row gathers at a time: the round issues the loads of its entries
+// that exist before it uses any, so they are in flight together.  The NW
+// partial sums are added in a fixed order.  No point of a level is on the
+// list of another point of the same level, and only the point's own
+// workgroup writes its row, so wave 0 reads that row together with the list:
+// the read is off the dependent chain (list, gathers, store).
+template <int NW, int U>
 __device__ __forceinline__ void vtri_chunk(int iq, double vq, int nq, const double* X, int64_t ld, int c,
                                            double (&acc)[U]) {
   for (int q = 0; q < nq; q += U) {
@@ -266,23 +283,22 @@ __device__ __forceinline__ void vtri_chunk(int iq, double vq, int nq, const doub
   }
 }
 
-template <bool CHILDREN, int NW, int U>
-__global__ __launch_bounds__(NW * 64) void k_vtri(int base, int cnt, const int64_t* __restrict__ cptr,
-                                              const int* __restrict__ idx, const double* __restrict__ val, int mv,
-                                              double* X, int64_t ld, int ncols) {
+template <int NW, int U>
+__global__ __launch_bounds__(NW * 64) void k_vtri(int base, int cnt, int64_t lbase, int stride,
+                                              const int* __restrict__ idx, const double* __restrict__ val, double* X,
+                                              int64_t ld, int ncols) {
   __shared__ double part[NW][64];
   if ((int)blockIdx.x >= cnt) return;  // uniform per workgroup
   const int wq = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t i = base + (int64_t)blockIdx.x;
-  // forward: the neighbours of i (a prefix of its mv slots); backward: its children
-  const int64_t b = CHILDREN ? cptr[i] : i * mv;
-  const int64_t e = CHILDREN ? cptr[i + 1] : i * mv + mv;
+  const int64_t b = lbase + (int64_t)blockIdx.x * stride;
+  const int64_t e = b + stride;
   const int64_t seg = (e - b + NW - 1) / NW;
   const int64_t sb = b + wq * seg < e ? b + wq * seg : e;
   const int64_t se = sb + seg < e ? sb + seg : e;
-  // the segment's first 64 entries serve every 64-column pass; neighbour
-  // lists end in -1 slots, so their valid entries are a prefix
+  // the segment's first 64 entries serve every 64-column pass; the valid
+  // entries of a list, and so of each segment, are a prefix
   const int m0 = (int)(se - sb < 64 ? se - sb : 64);
   const int iq0 = lane < m0 ? idx[sb + lane] : -1;
   const double vq0 = lane < m0 ? val[sb + lane] : 0.0;
@@ -291,18 +307,18 @@ __global__ __launch_bounds__(NW * 64) void k_vtri(int base, int cnt, const int64
   for (int c0 = 0; c0 < ncols; c0 += 64) {
     const int c = c0 + lane;
     const bool live = c < ncols;
-    const int nq0 = CHILDREN ? m0 : __popcll(__ballot(iq0 >= 0));
+    const int nq0 = __popcll(__ballot(iq0 >= 0));
     double acc[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) acc[k] = 0.0;
-    if (live) vtri_chunk<CHILDREN, NW, U>(iq0, vq0, nq0, X, ld, c, acc);
+    if (live) vtri_chunk<NW, U>(iq0, vq0, nq0, X, ld, c, acc);
     for (int64_t p0 = sb + 64; p0 < se; p0 += 64) {  // segments over 64 entries (lists over 64 NW)
       const int64_t rem = se - p0;
       const int m64 = (int)(rem < 64 ? rem : 64);
       const int iq = lane < m64 ? idx[p0 + lane] : -1;
       const double vq = lane < m64 ? val[p0 + lane] : 0.0;
-      const int nq = CHILDREN ? m64 : __popcll(__ballot(iq >= 0));
-      if (live) vtri_chunk<CHILDREN, NW, U>(iq, vq, nq, X, ld, c, acc);
+      const int nq = __popcll(__ballot(iq >= 0));
+      if (live) vtri_chunk<NW, U>(iq, vq, nq, X, ld, c, acc);
     }
     double a = acc[0];
 #pragma unroll
@@ -600,10 +616,11 @@ struct fsa_vecchia {
   Buf<int> posof, fnbr;
   Buf<double> fcoef, Dvp, wp, xsp;
   Buf<int64_t> cptr, scan_scratch;
-  Buf<int> ci;
-  Buf<double> cv;
+  Buf<int> ci, pci;
+  Buf<double> cv, pcv;     // pci, pcv: the child lists padded per level
   std::vector<int> lptr;   // level l holds order[lptr[l] .. lptr[l+1])
   std::vector<int> lmaxc;  // longest child list among the points of level l
+  std::vector<int64_t> lpoff;  // level l's padded child lists start at lpoff[l]
   // FITC preconditioner of Sigma + W^{-1}
   Buf<double> Sm, Lm, A, Ds, C, LCinv, Cinv, parts;  // parts: [0] log det P, [1] sum log w - sum log D
   Scratch scr;
@@ -698,20 +715,22 @@ fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, doub
   for (int l = nlev - 1; l >= 0; --l) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
     // 16 waves per point where some list of the level exceeds 32 entries,
-    // else 4; a wave has 8 row gathers in flight per round
-    if (v->lmaxc[l] > 32)
-      hipLaunchKernelGGL((k_vtri<true, 16, 8>), dim3((unsigned)cnt), dim3(1024), 0, st, b, cnt, v->cptr.p,
-                         v->ci.p, v->cv.p, 0, Y, ldy, ncols);
-    else
-      hipLaunchKernelGGL((k_vtri<true, 4, 8>), dim3((unsigned)cnt), dim3(256), 0, st, b, cnt, v->cptr.p,
-                         v->ci.p, v->cv.p, 0, Y, ldy, ncols);
+    // else 4; a wave has 8 row gathers in flight per round.  A level without
+    // children (the last) leaves its rows as they are.
+    const int w = v->lmaxc[l];
+    if (w > 32)
+      hipLaunchKernelGGL((k_vtri<16, 8>), dim3((unsigned)cnt), dim3(1024), 0, st, b, cnt, v->lpoff[l], w, v->pci.p,
+                         v->pcv.p, Y, ldy, ncols);
+    else if (w > 0)
+      hipLaunchKernelGGL((k_vtri<4, 8>), dim3((unsigned)cnt), dim3(256), 0, st, b, cnt, v->lpoff[l], w, v->pci.p,
+                         v->pcv.p, Y, ldy, ncols);
   }
   hipLaunchKernelGGL(k_vscale_rows, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Y, ldy, v->Dvp.p);
   for (int l = 0; l < nlev; ++l) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
     // at most 32 neighbours: 8 waves take four each, all gathers in one round
-    hipLaunchKernelGGL((k_vtri<false, 8, 4>), dim3((unsigned)cnt), dim3(512), 0, st, b, cnt, (const int64_t*)nullptr,
-                       v->fnbr.p, v->fcoef.p, v->mv, Y, ldy, ncols);
+    hipLaunchKernelGGL((k_vtri<8, 4>), dim3((unsigned)cnt), dim3(512), 0, st, b, cnt, (int64_t)b * v->mv, v->mv,
+                       v->fnbr.p, v->fcoef.p, Y, ldy, ncols);
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -948,8 +967,27 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
                          cur.p, v->ci.p, v->cv.p);
       hipLaunchKernelGGL(k_vchild_sort, dim3(grid1(n)), dim3(256), 0, st, v->cptr.p, n, v->ci.p, v->cv.p);
     }
-    FSA_HIP(hipGetLastError());
-    FSA_HIP(hipStreamSynchronize(st));
+    // the padded copy: position p of level l at lpoff[l] + (p - lptr[l]) lmaxc[l]
+    {
+      const int nl = (int)v->lptr.size() - 1;
+      std::vector<int64_t> hpo(n + 1);
+      v->lpoff.assign(nl, 0);
+      int64_t at = 0;
+      for (int l = 0; l < nl; ++l) {
+        v->lpoff[l] = at;
+        for (int q = v->lptr[l]; q < v->lptr[l + 1]; ++q, at += v->lmaxc[l]) hpo[q] = at;
+      }
+      hpo[n] = at;
+      Buf<int64_t> poff;
+      FSA_TRY(poff.alloc(n + 1));
+      FSA_TRY(v->pci.alloc(std::max<int64_t>(at, 1)));
+      FSA_TRY(v->pcv.alloc(std::max<int64_t>(at, 1)));
+      FSA_HIP(hipMemcpyAsync(poff.p, hpo.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_vchild_pad, dim3(grid1(n)), dim3(256), 0, st, v->cptr.p, n, v->ci.p, v->cv.p, poff.p,
+                         v->pci.p, v->pcv.p);
+      FSA_HIP(hipGetLastError());
+      FSA_HIP(hipStreamSynchronize(st));  // hpo and poff leave scope
+    }
   }
   // FITC preconditioner of Sigma + W^{-1}: A = L_m^{-1} Sigma_mn, D_s, C = I + A D_s^{-1} A^T
   FSA_TRY(v->Sm.alloc((size_t)mp * mp));
