@@ -283,17 +283,14 @@ __device__ __forceinline__ void vtri_chunk(int iq, double vq, int nq, const doub
   }
 }
 
+// Row i of X plus the list [b, e) of entries applied to X's rows; ends with
+// a workgroup barrier after the row's store.
 template <int NW, int U>
-__global__ __launch_bounds__(NW * 64) void k_vtri(int base, int cnt, int64_t lbase, int stride,
-                                              const int* __restrict__ idx, const double* __restrict__ val, double* X,
-                                              int64_t ld, int ncols) {
-  __shared__ double part[NW][64];
-  if ((int)blockIdx.x >= cnt) return;  // uniform per workgroup
+__device__ __forceinline__ void vtri_point(int64_t i, int64_t b, int64_t e, const int* __restrict__ idx,
+                                           const double* __restrict__ val, double* X, int64_t ld, int ncols,
+                                           double (&part)[NW][64]) {
   const int wq = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int64_t i = base + (int64_t)blockIdx.x;
-  const int64_t b = lbase + (int64_t)blockIdx.x * stride;
-  const int64_t e = b + stride;
   const int64_t seg = (e - b + NW - 1) / NW;
   const int64_t sb = b + wq * seg < e ? b + wq * seg : e;
   const int64_t se = sb + seg < e ? sb + seg : e;
@@ -332,6 +329,35 @@ __global__ __launch_bounds__(NW * 64) void k_vtri(int base, int cnt, int64_t lba
       own = c + 64 < ncols ? X[i * ld + c + 64] : 0.0;  // the next pass's
     }
     __syncthreads();
+  }
+}
+
+template <int NW, int U>
+__global__ __launch_bounds__(NW * 64) void k_vtri(int base, int cnt, int64_t lbase, int stride,
+                                              const int* __restrict__ idx, const double* __restrict__ val, double* X,
+                                              int64_t ld, int ncols) {
+  __shared__ double part[NW][64];
+  if ((int)blockIdx.x >= cnt) return;  // uniform per workgroup
+  const int64_t b = lbase + (int64_t)blockIdx.x * stride;
+  vtri_point<NW, U>(base + (int64_t)blockIdx.x, b, b + stride, idx, val, X, ld, ncols, part);
+}
+
+// A run of consecutive levels of one point each (positions [base, base +
+// cnt)) in one workgroup, point after point: ascending over the neighbour
+// lists (mv slots at position * mv), descending over the padded child lists
+// ([poff[i], poff[i + 1])).  A point's row is stored before the barrier that
+// ends its turn, so the later points of the run, whose lists may hold it,
+// read it from the same compute unit after that barrier.
+template <int NW, int U>
+__global__ __launch_bounds__(NW * 64) void k_vtri_run(int base, int cnt, const int64_t* __restrict__ poff, int mv,
+                                                  const int* __restrict__ idx, const double* __restrict__ val,
+                                                  double* X, int64_t ld, int ncols) {
+  __shared__ double part[NW][64];
+  for (int k = 0; k < cnt; ++k) {
+    const int64_t i = poff ? base + cnt - 1 - k : base + k;
+    const int64_t b = poff ? poff[i] : i * mv;
+    const int64_t e = poff ? poff[i + 1] : b + mv;
+    vtri_point<NW, U>(i, b, e, idx, val, X, ld, ncols, part);
   }
 }
 
@@ -618,6 +644,7 @@ struct fsa_vecchia {
   Buf<int64_t> cptr, scan_scratch;
   Buf<int> ci, pci;
   Buf<double> cv, pcv;     // pci, pcv: the child lists padded per level
+  Buf<int64_t> ppos;       // position p's padded child list: [ppos[p], ppos[p + 1])
   std::vector<int> lptr;   // level l holds order[lptr[l] .. lptr[l+1])
   std::vector<int> lmaxc;  // longest child list among the points of level l
   std::vector<int64_t> lpoff;  // level l's padded child lists start at lpoff[l]
@@ -712,8 +739,18 @@ fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, doub
   const int64_t n = v->n;
   hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, X, ldx, Y, ldy);
   const int nlev = (int)v->lptr.size() - 1;
-  for (int l = nlev - 1; l >= 0; --l) {
+  const auto single = [&](int l) { return v->lptr[l + 1] - v->lptr[l] == 1; };
+  for (int l = nlev - 1; l >= 0;) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
+    if (l > 0 && single(l) && single(l - 1)) {
+      // levels l0 .. l hold one point each: one workgroup, point after point
+      int l0 = l - 1;
+      while (l0 > 0 && single(l0 - 1)) --l0;
+      hipLaunchKernelGGL((k_vtri_run<16, 8>), dim3(1), dim3(1024), 0, st, v->lptr[l0], l - l0 + 1, v->ppos.p, 0,
+                         v->pci.p, v->pcv.p, Y, ldy, ncols);
+      l = l0 - 1;
+      continue;
+    }
     // 16 waves per point where some list of the level exceeds 32 entries,
     // else 4; a wave has 8 row gathers in flight per round.  A level without
     // children (the last) leaves its rows as they are.
@@ -724,13 +761,23 @@ fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, doub
     else if (w > 0)
       hipLaunchKernelGGL((k_vtri<4, 8>), dim3((unsigned)cnt), dim3(256), 0, st, b, cnt, v->lpoff[l], w, v->pci.p,
                          v->pcv.p, Y, ldy, ncols);
+    --l;
   }
   hipLaunchKernelGGL(k_vscale_rows, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Y, ldy, v->Dvp.p);
-  for (int l = 0; l < nlev; ++l) {
+  for (int l = 0; l < nlev;) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
+    if (l + 1 < nlev && single(l) && single(l + 1)) {
+      int l1 = l + 1;
+      while (l1 + 1 < nlev && single(l1 + 1)) ++l1;
+      hipLaunchKernelGGL((k_vtri_run<8, 4>), dim3(1), dim3(512), 0, st, b, l1 - l + 1, (const int64_t*)nullptr,
+                         v->mv, v->fnbr.p, v->fcoef.p, Y, ldy, ncols);
+      l = l1 + 1;
+      continue;
+    }
     // at most 32 neighbours: 8 waves take four each, all gathers in one round
     hipLaunchKernelGGL((k_vtri<8, 4>), dim3((unsigned)cnt), dim3(512), 0, st, b, cnt, (int64_t)b * v->mv, v->mv,
                        v->fnbr.p, v->fcoef.p, Y, ldy, ncols);
+    ++l;
   }
   FSA_HIP(hipGetLastError());
   return FSA_OK;
@@ -978,15 +1025,14 @@ fsa_status build(fsa_vecchia* v, const double* locs, const double* inducing, con
         for (int q = v->lptr[l]; q < v->lptr[l + 1]; ++q, at += v->lmaxc[l]) hpo[q] = at;
       }
       hpo[n] = at;
-      Buf<int64_t> poff;
-      FSA_TRY(poff.alloc(n + 1));
+      FSA_TRY(v->ppos.alloc(n + 1));
       FSA_TRY(v->pci.alloc(std::max<int64_t>(at, 1)));
       FSA_TRY(v->pcv.alloc(std::max<int64_t>(at, 1)));
-      FSA_HIP(hipMemcpyAsync(poff.p, hpo.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_vchild_pad, dim3(grid1(n)), dim3(256), 0, st, v->cptr.p, n, v->ci.p, v->cv.p, poff.p,
+      FSA_HIP(hipMemcpyAsync(v->ppos.p, hpo.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_vchild_pad, dim3(grid1(n)), dim3(256), 0, st, v->cptr.p, n, v->ci.p, v->cv.p, v->ppos.p,
                          v->pci.p, v->pcv.p);
       FSA_HIP(hipGetLastError());
-      FSA_HIP(hipStreamSynchronize(st));  // hpo and poff leave scope
+      FSA_HIP(hipStreamSynchronize(st));  // hpo leaves scope
     }
   }
   // FITC preconditioner of Sigma + W^{-1}: A = L_m^{-1} Sigma_mn, D_s, C = I + A D_s^{-1} A^T
