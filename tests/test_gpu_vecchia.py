@@ -81,6 +81,23 @@ def test_products_match_oracle(which):
     assert err < 1e-9, err
 
 
+@pytest.mark.parametrize("ncols", [64, 65, 130])
+def test_sigma_product_over_64_columns(ncols):
+    """Blocks wider than one 64-lane pass of the triangular solves: each pass
+    reads its own slice of the point's row and reuses the list, on the
+    one-point levels (one workgroup, point after point) and on the others."""
+    from paper_2405_14492_amd import fsa
+    n, mv, m = 1200, 30, 32
+    locs, ind, w, th = _case(n, mv, m, seed=17, clustered=True)
+    M = VO.Vecchia(locs, ind, th, mv, w)
+    X = np.random.default_rng(8).standard_normal((n, ncols))
+    ref = M.cov_matvec(X)
+    with _gpu(locs, ind, w, th, mv) as v:
+        Y = v.apply(fsa.V_SIGMA, _dev(X)).cpu().numpy()
+    err = np.abs(Y - ref).max() / np.abs(ref).max()
+    assert err < 1e-9, err
+
+
 def test_products_are_inverse_of_each_other():
     from paper_2405_14492_amd import fsa
     n, mv, m = 1500, 20, 30
