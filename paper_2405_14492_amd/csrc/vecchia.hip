@@ -740,6 +740,7 @@ fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, doub
   hipLaunchKernelGGL(k_vcopy, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, X, ldx, Y, ldy);
   const int nlev = (int)v->lptr.size() - 1;
   const auto single = [&](int l) { return v->lptr[l + 1] - v->lptr[l] == 1; };
+  // B^{-T}: levels in descending order, each point adding its children's rows
   for (int l = nlev - 1; l >= 0;) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
     if (l > 0 && single(l) && single(l - 1)) {
@@ -764,9 +765,11 @@ fsa_status sigma_v(fsa_vecchia* v, const double* X, int64_t ldx, int ncols, doub
     --l;
   }
   hipLaunchKernelGGL(k_vscale_rows, dim3(grid1(n * ncols)), dim3(256), 0, st, n, ncols, Y, ldy, v->Dvp.p);
+  // B^{-1}: levels in ascending order, each point adding its neighbours' rows
   for (int l = 0; l < nlev;) {
     const int b = v->lptr[l], cnt = v->lptr[l + 1] - b;
     if (l + 1 < nlev && single(l) && single(l + 1)) {
+      // levels l .. l1 hold one point each
       int l1 = l + 1;
       while (l1 + 1 < nlev && single(l1 + 1)) ++l1;
       hipLaunchKernelGGL((k_vtri_run<8, 4>), dim3(1), dim3(512), 0, st, b, l1 - l + 1, (const int64_t*)nullptr,
