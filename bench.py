@@ -273,7 +273,8 @@ def run_vecchia(F, torch, n, mv, m, t, steps, warmup, seed=0, cpu_sample_n=0):
             "value": rate * ns / n, "unit": "probe-iters/s", "cores": int(cores), "kind": "oracle",
             "sample": (f"oracle solve + SLQ log det on the first {ns} points of the same ordered workload (a Vecchia "
                        f"model of its own), {int(o['iters'].sum())} probe-iterations; rate {rate:.1f} probe-iters/s "
-                       f"at n={ns} scaled by {ns}/{n}; oracle build {ts - tb:.1f} s not included")}
+                       f"at n={ns} scaled by {ns}/{n}; oracle build {ts - tb:.1f} s not included; its dense "
+                       f"products run on {int(cores)} BLAS threads, its triangular solves (scipy) on one")}
     return out
 
 
@@ -389,7 +390,8 @@ def cpu_baseline(w, sample_n, iters):
             "sample": (f"oracle PCG, {iters} iterations x {B.shape[1]} columns on the {ns}-point window "
                        f"[0,{a:.4f}]^2 of the same workload (all {w.m} inducing points, same gamma); rate "
                        f"{rate:.2f} probe-iters/s at n={ns} scaled by {ns}/{w.n}; oracle build "
-                       f"{t1 - t0:.1f} s not included"),
+                       f"{t1 - t0:.1f} s not included; its dense products run on {blas_threads} BLAS threads, "
+                       f"its sparse products (scipy) on one"),
             "host_cores_visible": len(os.sched_getaffinity(0))}
 
 
