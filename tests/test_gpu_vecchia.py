@@ -98,6 +98,29 @@ def test_sigma_product_over_64_columns(ncols):
     assert err < 1e-9, err
 
 
+def test_chain_of_one_point_levels():
+    """Points in order along a line: each point's nearest earlier points are
+    the ones just before it, so every level holds one point (n levels) and
+    each pass of the triangular solves is one stretch, one workgroup walking
+    all n points."""
+    from paper_2405_14492_amd import fsa
+    n, mv = 400, 5
+    x = np.linspace(0.0, 1.0, n)
+    locs = np.column_stack([x, np.full(n, 0.5)])
+    ind = locs[::25][:16].copy()
+    w = G.laplace_weights(n, 4)
+    th = (F.MATERN32, 1.0, 0.01)
+    M = VO.Vecchia(locs, ind, th, mv, w)
+    X = np.random.default_rng(6).standard_normal((n, 3))
+    ref = M.cov_matvec(X)
+    with _gpu(locs, ind, w, th, mv) as v:
+        Y = v.apply(fsa.V_SIGMA, _dev(X)).cpu().numpy()
+        _, _, st = v.solve_logdet(_dev(X[:, 0]), 2, seed=1, fixed_iter=3)
+    assert st["nlevels"] == n
+    err = np.abs(Y - ref).max() / np.abs(ref).max()
+    assert err < 1e-9, err
+
+
 def test_products_are_inverse_of_each_other():
     from paper_2405_14492_amd import fsa
     n, mv, m = 1500, 20, 30
