@@ -73,21 +73,45 @@ def kernel_work(k, n, m, tp, nnz, b, ba=None):
     return 0, 0
 
 
+def _code_text(src):
+    """C/C++ source without its comments, whitespace runs collapsed to one
+    space (string and character literals kept as written)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_fingerprint():
-    """sha256 over the sources that define the PCG kernels the hardware
-    counters measure (their code, launch shapes and the grid layout they
-    read) and the ABI header: traffic is reported only for the sources it was
-    measured on."""
+    """sha256 over the code (comments and layout ignored) of the sources that
+    define the PCG kernels the hardware counters measure (their code, launch
+    shapes and the grid layout they read) and of the ABI header: traffic is
+    reported only for the code it was measured on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2405_14492_amd", "csrc")
-    files = ["common.hpp", "gemm.hpp", "geom.hip", "kernels.hpp", "ops.hip"]
-    for f in files:
-        h.update(f.encode())
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    with open(os.path.join(ROOT, "include", "fsa.h"), "rb") as fh:
-        h.update(fh.read())
+    paths = [os.path.join(csrc, f) for f in ("common.hpp", "gemm.hpp", "geom.hip", "kernels.hpp", "ops.hip")]
+    paths.append(os.path.join(ROOT, "include", "fsa.h"))
+    for path in paths:
+        h.update(os.path.basename(path).encode())
+        with open(path, encoding="utf-8") as fh:
+            h.update(_code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -496,7 +496,8 @@ typedef enum {
  * search is an exact scan of the earlier points (n^2/2 distance tests, about
  * 30 ms at n = 100,000); the triangular solves take one launch per level of
  * the neighbour graph (about 400 levels at n = 100,000, m_v = 30 in random
- * order).  The level schedule is built once per context.
+ * order), one per stretch of consecutive levels of a single point.  The
+ * level schedule is built once per context.
  *   locs: n x 2 row-major; inducing: m x 2 row-major; w: n weights W_ii > 0;
  *   covariance kind (fsa_cov) with sigma1^2 > 0 and rho > 0 (no nugget:
  *   the process is latent); 0 <= m_v <= 32; 1 <= m <= 512.
